@@ -1,0 +1,233 @@
+/*
+ * ect.h -- C ABI of the MI355X (gfx950) library for topological integral
+ * transforms of weighted cubical complexes built from 2D images and 3D volumes.
+ *
+ * The library follows the method's problem statement:
+ *   input    an n-dimensional array turned into a weighted cubical complex
+ *            (Sec. 4.1: one top cell per pixel, lower cells take the min of
+ *            their cofaces; Sec. 5: the dual rule, pixels on vertices and higher
+ *            cells take the min of their vertices);
+ *   queries  directions xi (Sec. 2.2, Sec. 4.3) and thresholds t (Sec. 4.3,
+ *            vectorization);
+ *   outputs  ECT(xi, t) = chi(phi restricted to {xi <= t}) and the hybrid
+ *            transform HT(xi) = integral kappa(t) R(xi, t) dt (Sec. 2.2),
+ *            computed from per-sign-vector critical points (Sec. 3, Lemma 3.1
+ *            and Lemma 3.2).
+ *
+ * Conventions shared by every call:
+ *   - Pointers marked DEVICE are HIP device pointers, HOST pointers are plain
+ *     host memory.  The caller owns every buffer; the library allocates no
+ *     device memory.  Work memory is passed as a workspace: calling with
+ *     ws == NULL writes the number of bytes needed to *ws_bytes and returns
+ *     ECT_OK without doing anything else.
+ *   - Every call that takes a stream only enqueues work on it and returns;
+ *     results are valid once the stream has been synchronised.  The calls
+ *     that say "synchronises" block until their stream is idle.
+ *   - Embedding axis 0 is the fastest-varying memory axis of an image.  A
+ *     vertex with integer index k_a along axis a sits at
+ *     x_a = fma(spacing_a, k_a, origin_a); the default origin centres the
+ *     complex (origin_a = -N_a/2, N_a = number of top cells along a) and the
+ *     default spacing is 1 (pixel units).
+ *   - The projection of vertex x on xi is the canonical FP64 expression
+ *     u = fma(xi_{n-1}, x_{n-1}, ... fma(xi_1, x_1, xi_0 * x_0)), the same on
+ *     every code path, which makes the integer ECT exact: it equals the
+ *     definition evaluated over all cells with this projection.
+ *   - The sign vector of xi has eps_a = +1 when xi_a >= 0 (including -0.0)
+ *     and -1 otherwise.  Sign-vector index e: bit a set means eps_a = -1.
+ *   - Kernels with scale s != 0: kappa_s(t) = kappa(s t) and its primitive
+ *     kbar_s(t) = kbar(s t) / s, with
+ *         ECT_FOURIER  kappa = exp(-i t), kbar = i exp(-i t) = sin t + i cos t
+ *         ECT_LAPLACE  kappa = exp(-t),   kbar = -exp(-t)
+ *         ECT_BESSEL   kappa = J0,        kbar = Ji0(t) = integral_0^t J0
+ *     so that HT(xi) = sum over ordinary critical points x of
+ *     Delta^ord(eps, x) * kbar_s(<xi, x>) (the sign that the definition of HT
+ *     gives; see the readings of the method).
+ *   - No C++ exception crosses this boundary.  Errors found on the host are
+ *     returned before anything is enqueued and leave outputs untouched;
+ *     errors that depend on device data set bits of the plan's device error
+ *     word (ECT_DEVERR_*), read with ect_plan_check().
+ */
+#ifndef ECT_H
+#define ECT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#pragma GCC visibility push(default)
+
+typedef enum {
+    ECT_OK = 0,
+    ECT_E_INVALID = 1,      /* bad argument (null pointer, bad enum, size, non-finite scalar) */
+    ECT_E_NOMEM = 2,        /* workspace smaller than required, or host allocation failed */
+    ECT_E_DEVICE = 3,       /* a HIP runtime call failed */
+    ECT_E_UNSUPPORTED = 4,  /* valid request outside what this build implements */
+    ECT_E_RANGE = 5         /* a value does not fit the output type */
+} ect_status;
+
+typedef enum { ECT_PRIMAL = 0, ECT_DUAL = 1 } ect_construction;
+typedef enum { ECT_U8 = 0, ECT_I16 = 1, ECT_I32 = 2 } ect_dtype;
+typedef enum { ECT_FOURIER = 0, ECT_LAPLACE = 1, ECT_BESSEL = 2 } ect_kernel;
+
+/* ECT_FP32: FP64 phases and argument reduction, FP32 kernel values, FP64
+ * accumulation and FP64 fixed-order reduction.  ECT_FP64: everything in FP64. */
+typedef enum { ECT_FP32 = 0, ECT_FP64 = 1 } ect_precision;
+
+/* Device error word bits (ect_plan_check). */
+#define ECT_DEVERR_THRESHOLDS    0x2u  /* thresholds not non-decreasing: that image's ECT rows are zero */
+#define ECT_DEVERR_NONFINITE     0x4u  /* a non-finite direction: its outputs are NaN / zero */
+#define ECT_DEVERR_LOOKBACK      0x8u  /* ordered compaction gave up waiting (never expected) */
+#define ECT_DEVERR_OVERFLOW      0x10u /* a Laplace output overflowed without a log-scale output */
+#define ECT_DEVERR_CAPACITY      0x20u /* hybrid work list larger than its workspace */
+
+/* A batch of images.  Every image of a batch has the same ndim, dtype and
+ * construction; sizes may differ (ragged batch). */
+typedef struct {
+    int32_t ndim;                  /* 2 or 3 */
+    int32_t num_images;            /* >= 1 */
+    const int32_t* dims;           /* HOST [num_images][ndim]: pixels along axis a (>= 1; dual needs >= 1) */
+    const int64_t* pixel_offsets;  /* HOST [num_images]: element offset of image i in `pixels` */
+    const void* pixels;            /* DEVICE: element type `dtype`, each image contiguous, axis 0 fastest;
+                                      read by ect_precompute / ect_plan_rerun only */
+    int32_t dtype;                 /* ect_dtype; int32 values must lie in [-2^26, 2^26] */
+    int32_t construction;          /* ect_construction */
+    const double* origin;          /* HOST [num_images][ndim] or NULL (centred) */
+    const double* spacing;         /* HOST [num_images][ndim] or NULL (1.0) */
+} ect_image_batch;
+
+/* A set of query vectors (ECT directions or hybrid xi), FP64.
+ * Shared set (offsets == NULL): `count` vectors used by every image; row of
+ * query k of image i is i*count + k.  Ragged set: image i owns rows
+ * offsets[i] .. offsets[i+1]-1 and `count` is the total number of rows
+ * (offsets[num_images]). */
+typedef struct {
+    const double* vecs;            /* DEVICE [rows][ndim] */
+    const int64_t* offsets;        /* DEVICE [num_images+1], non-decreasing, or NULL */
+    int64_t count;
+} ect_query_set;
+
+typedef struct ect_plan_s* ect_plan;  /* host handle; the critical-point lists live in the workspace */
+
+/* ect_precompute -- per-vertex critical values for every sign vector and
+ * their ordered compaction into lists (Sec. 3 definitions of Delta^- and
+ * Delta^ord, Sec. 4.2 preprocessing, Lemma 3.2 for why 2^n sign vectors
+ * suffice).  For each image and each eps it builds the classical list
+ * {(x, Delta^-(eps,x)) : Delta^- != 0}; for each eps with eps_{n-1} = +1 it
+ * builds the ordinary list {(x, Delta^ord(eps,x)) : Delta^ord != 0}; the
+ * lists of eps_{n-1} = -1 are the same points with negated values, because
+ * the upper star for eps is the lower star for -eps.  Lists are ordered by
+ * linear vertex index.
+ *   batch     HOST descriptor (copied; `pixels` must stay valid while the
+ *             plan may rerun)
+ *   ws        DEVICE workspace of *ws_bytes bytes, 256-byte aligned; it holds
+ *             the lists and must outlive the plan
+ *   stream    HIP stream for the work
+ *   out       receives the plan handle (only when ws != NULL)
+ * Synchronises once at the end to read the list sizes back to the host.
+ * Returns ECT_E_INVALID for a malformed batch, ECT_E_NOMEM when *ws_bytes is
+ * too small. */
+ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_bytes,
+                          hipStream_t stream, ect_plan* out);
+
+/* Re-run the precompute kernels of an existing plan on its pixel buffer (same
+ * shapes, new contents).  Enqueues kernels only (no copies, no allocation, no
+ * synchronisation), so it can be captured into a HIP graph.  List sizes held
+ * on the host are NOT refreshed; device-side consumers read the new sizes. */
+ect_status ect_plan_rerun(ect_plan plan, hipStream_t stream);
+
+/* ect_eval -- ECT(xi, t_j) at every direction xi of `dirs` and every
+ * threshold t_j (Sec. 2.2 definition; Lemma 3.1: ECT(xi, .) is the sum of
+ * Delta^-(eps, x) 1[<xi,x>, inf) over classical points; Sec. 4.3
+ * vectorization at explicit thresholds).  Exact int32 result.
+ *   dirs            query set (DEVICE vectors)
+ *   thresholds      DEVICE [M] (thresholds_per_image == 0) or [num_images][M];
+ *                   non-decreasing per image, closed sublevel sets (u <= t)
+ *   out             DEVICE int32 [rows][M], row-major
+ *   ws, ws_bytes    DEVICE workspace (ws == NULL: size query)
+ * Unsorted thresholds or non-finite directions are detected on the device
+ * (error word). */
+ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds, int32_t M,
+                    int32_t thresholds_per_image, int32_t* out, void* ws, size_t* ws_bytes,
+                    hipStream_t stream);
+
+/* hybrid_eval -- HT(xi) = integral kappa_s(t) R(xi,t) dt (Sec. 2.2), evaluated
+ * as the sum over ordinary critical points of Delta^ord(eps,x) kbar_s(<xi,x>)
+ * (Lemma 3.1 with the sign that the definition gives).
+ *   kernel, s       ect_kernel and scale (s finite; s != 0)
+ *   precision       ect_precision
+ *   xi              query set (DEVICE vectors)
+ *   out             DEVICE double [rows] (Laplace, Bessel) or [rows][2]
+ *                   (Fourier: real, imaginary)
+ *   log_scale       DEVICE double [rows] or NULL.  Laplace only: when given,
+ *                   out holds HT * exp(-log_scale) with log_scale an upper
+ *                   bound of max(-s <xi,x>) over the image's vertices, so
+ *                   that no term overflows; when NULL out holds HT and an
+ *                   overflow sets ECT_DEVERR_OVERFLOW.  Other kernels: if
+ *                   given it is filled with 0.
+ * Deterministic: repeated calls give bitwise identical outputs. */
+ect_status hybrid_eval(ect_plan plan, int32_t kernel, double s, int32_t precision,
+                       ect_query_set xi, double* out, double* log_scale,
+                       void* ws, size_t* ws_bytes, hipStream_t stream);
+
+/* hybrid_eval_backward -- vector-Jacobian product of hybrid_eval (without
+ * log_scale) with respect to xi and to the scale s.  With kappa the kernel,
+ * dHT/dxi_a = sum Delta^ord x_a kappa(s <xi,x>) and
+ * dHT/ds = (1/s) [sum Delta^ord <xi,x> kappa(s <xi,x>) - HT].
+ *   out         DEVICE: the forward output of the same call (needed for d/ds)
+ *   grad_out    DEVICE, layout of out
+ *   grad_xi     DEVICE double [rows][ndim] for a ragged set; for a shared set
+ *               [count][ndim], summed over images in image order
+ *   grad_s      DEVICE double scalar (sum over all rows) or NULL
+ * Valid away from directions with a zero coordinate (the transform has kinks
+ * there). */
+ect_status hybrid_eval_backward(ect_plan plan, int32_t kernel, double s, int32_t precision,
+                                ect_query_set xi, const double* out, const double* grad_out,
+                                double* grad_xi, double* grad_s,
+                                void* ws, size_t* ws_bytes, hipStream_t stream);
+
+/* Number of list entries per image, read from the host copy made at the end
+ * of ect_precompute.  classical: HOST int64 [num_images][2^ndim];
+ * ordinary: HOST int64 [num_images][2^(ndim-1)] (lists of eps with
+ * eps_{n-1} = +1, index e < 2^(ndim-1)).  Either may be NULL. */
+ect_status ect_plan_counts(ect_plan plan, int64_t* classical, int64_t* ordinary);
+
+/* Copy one list of one image to the host (tests, caching).  kind 0 =
+ * classical (list = e in [0, 2^ndim)), kind 1 = ordinary (list = e in
+ * [0, 2^(ndim-1))).  coords: HOST int32 [capacity][ndim] vertex indices k;
+ * values: HOST int32 [capacity].  *count receives the list length; at most
+ * `capacity` entries are written.  Synchronises the plan's stream. */
+ect_status ect_plan_export(ect_plan plan, int32_t image, int32_t kind, int32_t list,
+                           int32_t* coords, int32_t* values, int64_t capacity, int64_t* count,
+                           hipStream_t stream);
+
+/* Read and clear the device error word (ECT_DEVERR_* bits).  Synchronises. */
+ect_status ect_plan_check(ect_plan plan, uint32_t* device_error_flags, hipStream_t stream);
+
+/* Free the host handle (the workspace stays with the caller). */
+ect_status ect_plan_destroy(ect_plan plan);
+
+/* Tuning knobs (process-wide; used by the autotuner): hybrid point-chunk
+ * length per work item (0 = automatic), target number of hybrid work items
+ * when automatic, directions per ECT workgroup (1..8).  Values only change
+ * the schedule: results are exact (ECT) or equal to within rounding of the
+ * chunked sums (hybrid), and identical for identical settings. */
+ect_status ect_set_tuning(int64_t hybrid_chunk, int64_t hybrid_target_items, int32_t ect_dirs_per_group);
+
+/* Static description of a status code. */
+const char* ect_status_string(ect_status status);
+
+/* Library version, "major.minor.patch". */
+const char* ect_version(void);
+
+#pragma GCC visibility pop
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ECT_H */

@@ -570,3 +570,10 @@ void oracle_set_threads(int t) {
     (void)t;
 #endif
 }
+
+/* Ji0 at many arguments (one shared memo table). */
+void oracle_ji0_array(long long n, const double* z, double* out) {
+    ji0_table tb = {NULL, 0};
+    for (long long i = 0; i < n; ++i) out[i] = ji0_eval(&tb, z[i]);
+    free(tb.cum);
+}

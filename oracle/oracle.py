@@ -80,6 +80,7 @@ def lib():
         L.oracle_critical_values.argtypes = [ctypes.c_int, i32p, i32p, ctypes.c_int, i32p, i32p]
         L.oracle_ji0.argtypes = [ctypes.c_double]
         L.oracle_ji0.restype = ctypes.c_double
+        L.oracle_ji0_array.argtypes = [ctypes.c_longlong, f64p, f64p]
         L.oracle_max_threads.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -250,6 +251,13 @@ def critical_lists(img, construction=PRIMAL):
 
 def ji0(z: float) -> float:
     return float(lib().oracle_ji0(float(z)))
+
+
+def ji0_array(z) -> np.ndarray:
+    z, zp = _f64(np.asarray(z, dtype=np.float64).reshape(-1))
+    out = np.zeros_like(z)
+    lib().oracle_ji0_array(z.size, zp, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
 
 
 # ---------------------------------------------------------------------------

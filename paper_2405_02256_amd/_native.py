@@ -1,0 +1,142 @@
+"""ctypes binding of libect.so (argument marshalling only).
+
+Every compute step runs in the HIP kernels of libect.so.  If the library is
+missing this module raises: there is no CPU fallback on the product path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libect.so")
+
+c_i32, c_i64, c_f64, c_u32, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32, ctypes.c_void_p
+P = ctypes.POINTER
+
+ECT_OK, ECT_E_INVALID, ECT_E_NOMEM, ECT_E_DEVICE, ECT_E_UNSUPPORTED, ECT_E_RANGE = range(6)
+PRIMAL, DUAL = 0, 1
+U8, I16, I32 = 0, 1, 2
+FOURIER, LAPLACE, BESSEL = 0, 1, 2
+FP32, FP64 = 0, 1
+KERNELS = {"fourier": FOURIER, "laplace": LAPLACE, "bessel": BESSEL}
+PRECISIONS = {"fp32": FP32, "fp64": FP64}
+
+DEVERR_THRESHOLDS = 0x2
+DEVERR_NONFINITE = 0x4
+DEVERR_LOOKBACK = 0x8
+DEVERR_OVERFLOW = 0x10
+DEVERR_CAPACITY = 0x20
+
+
+class ImageBatch(ctypes.Structure):
+    _fields_ = [("ndim", c_i32), ("num_images", c_i32), ("dims", P(c_i32)), ("pixel_offsets", P(c_i64)),
+                ("pixels", c_vp), ("dtype", c_i32), ("construction", c_i32), ("origin", P(c_f64)),
+                ("spacing", P(c_f64))]
+
+
+class QuerySet(ctypes.Structure):
+    _fields_ = [("vecs", c_vp), ("offsets", c_vp), ("count", c_i64)]
+
+
+class EctError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} (status {status})")
+
+
+_lib = None
+
+
+def lib():
+    """Load libect.so once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2405_02256_amd.build` "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    L.ect_version.restype = ctypes.c_char_p
+    L.ect_status_string.restype = ctypes.c_char_p
+    L.ect_status_string.argtypes = [c_i32]
+    L.ect_precompute.argtypes = [P(ImageBatch), c_vp, P(ctypes.c_size_t), c_vp, P(c_vp)]
+    L.ect_plan_rerun.argtypes = [c_vp, c_vp]
+    L.ect_eval.argtypes = [c_vp, QuerySet, c_vp, c_i32, c_i32, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
+    L.hybrid_eval.argtypes = [c_vp, c_i32, c_f64, c_i32, QuerySet, c_vp, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
+    L.hybrid_eval_backward.argtypes = [c_vp, c_i32, c_f64, c_i32, QuerySet, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                       P(ctypes.c_size_t), c_vp]
+    L.ect_plan_counts.argtypes = [c_vp, P(c_i64), P(c_i64)]
+    L.ect_plan_export.argtypes = [c_vp, c_i32, c_i32, c_i32, P(c_i32), P(c_i32), c_i64, P(c_i64), c_vp]
+    L.ect_plan_check.argtypes = [c_vp, P(c_u32), c_vp]
+    L.ect_plan_destroy.argtypes = [c_vp]
+    L.ect_set_tuning.argtypes = [c_i64, c_i64, c_i32]
+    for name in ("ect_precompute", "ect_plan_rerun", "ect_eval", "hybrid_eval", "hybrid_eval_backward",
+                 "ect_plan_counts", "ect_plan_export", "ect_plan_check", "ect_plan_destroy", "ect_set_tuning"):
+        getattr(L, name).restype = c_i32
+    _lib = L
+    return L
+
+
+def status_string(status: int) -> str:
+    return lib().ect_status_string(int(status)).decode()
+
+
+def check(status: int, where: str) -> None:
+    if status != ECT_OK:
+        raise EctError(status, where)
+
+
+def version() -> str:
+    return lib().ect_version().decode()
+
+
+# Thin same-name wrappers around the C entry points (raw pointers as ints).
+
+def ect_precompute(batch: ImageBatch, ws, ws_bytes: ctypes.c_size_t, stream: int) -> int:
+    plan = c_vp()
+    st = lib().ect_precompute(ctypes.byref(batch), ws, ctypes.byref(ws_bytes), c_vp(stream), ctypes.byref(plan))
+    return st, plan.value
+
+
+def ect_plan_rerun(plan: int, stream: int) -> int:
+    return lib().ect_plan_rerun(c_vp(plan), c_vp(stream))
+
+
+def ect_eval(plan, dirs: QuerySet, thresholds, M, per_image, out, ws, ws_bytes: ctypes.c_size_t, stream) -> int:
+    return lib().ect_eval(c_vp(plan), dirs, c_vp(thresholds), int(M), int(per_image), c_vp(out), ws,
+                          ctypes.byref(ws_bytes), c_vp(stream))
+
+
+def hybrid_eval(plan, kernel, s, precision, xi: QuerySet, out, log_scale, ws, ws_bytes: ctypes.c_size_t,
+                stream) -> int:
+    return lib().hybrid_eval(c_vp(plan), int(kernel), float(s), int(precision), xi, c_vp(out),
+                             c_vp(log_scale) if log_scale else None, ws, ctypes.byref(ws_bytes), c_vp(stream))
+
+
+def hybrid_eval_backward(plan, kernel, s, precision, xi: QuerySet, out, grad_out, grad_xi, grad_s, ws,
+                         ws_bytes: ctypes.c_size_t, stream) -> int:
+    return lib().hybrid_eval_backward(c_vp(plan), int(kernel), float(s), int(precision), xi, c_vp(out),
+                                      c_vp(grad_out), c_vp(grad_xi), c_vp(grad_s) if grad_s else None, ws,
+                                      ctypes.byref(ws_bytes), c_vp(stream))
+
+
+def ect_plan_counts(plan, classical, ordinary) -> int:
+    return lib().ect_plan_counts(c_vp(plan), classical, ordinary)
+
+
+def ect_plan_export(plan, image, kind, lst, coords, values, capacity, count, stream) -> int:
+    return lib().ect_plan_export(c_vp(plan), int(image), int(kind), int(lst), coords, values, int(capacity),
+                                 count, c_vp(stream))
+
+
+def ect_plan_check(plan, flags, stream) -> int:
+    return lib().ect_plan_check(c_vp(plan), flags, c_vp(stream))
+
+
+def ect_plan_destroy(plan) -> int:
+    return lib().ect_plan_destroy(c_vp(plan))
+
+
+def ect_set_tuning(hybrid_chunk: int, hybrid_target_items: int, ect_dirs_per_group: int) -> int:
+    return lib().ect_set_tuning(int(hybrid_chunk), int(hybrid_target_items), int(ect_dirs_per_group))

@@ -1,0 +1,247 @@
+"""PyTorch-facing layer over the C ABI: device memory and streams only.
+
+``Plan`` owns the workspace tensors of one precomputed batch and exposes the
+evaluation calls; ``HybridTransform`` is the autograd Function whose backward
+is the library's hand-written vector-Jacobian product.  Every numeric step
+runs in libect.so on the GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+_DTYPES = {torch.uint8: N.U8, torch.int16: N.I16, torch.int32: N.I32}
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class QuerySet:
+    """FP64 query vectors on the device: shared (one set for every image) or ragged."""
+
+    def __init__(self, vecs: torch.Tensor, offsets: torch.Tensor | None = None):
+        if vecs.dtype != torch.float64 or not vecs.is_cuda or vecs.dim() != 2:
+            raise ValueError("query vectors must be a CUDA float64 tensor [rows][ndim]")
+        self.vecs = vecs.contiguous()
+        self.offsets = None if offsets is None else offsets.to(device=vecs.device, dtype=torch.int64).contiguous()
+
+    def validate(self, num_images: int, ndim: int) -> None:
+        if self.vecs.shape[1] != ndim:
+            raise ValueError(f"query vectors have {self.vecs.shape[1]} columns, expected {ndim}")
+        if self.offsets is not None:
+            o = self.offsets.cpu().numpy()
+            if o.shape != (num_images + 1,) or o[0] != 0 or o[-1] != self.vecs.shape[0] or (np.diff(o) < 0).any():
+                raise ValueError("ragged offsets must be [num_images+1], start at 0, be non-decreasing and "
+                                 "end at the number of rows")
+
+    def rows(self, num_images: int) -> int:
+        return self.vecs.shape[0] if self.offsets is not None else self.vecs.shape[0] * num_images
+
+    def c(self) -> N.QuerySet:
+        return N.QuerySet(_dptr(self.vecs), _dptr(self.offsets), self.vecs.shape[0])
+
+
+class Plan:
+    """Critical-point lists of a batch of images (ect_precompute).
+
+    images: list of integer tensors on one CUDA device (numpy axis order: the
+    last index is embedding axis 0), or one tensor for a single image.
+    """
+
+    def __init__(self, images, construction: int = N.PRIMAL, origin=None, spacing=None, stream=None):
+        if isinstance(images, torch.Tensor):
+            images = [images]
+        if not images:
+            raise ValueError("empty batch")
+        dev = images[0].device
+        dt = images[0].dtype
+        if dt not in _DTYPES or not images[0].is_cuda:
+            raise ValueError("images must be CUDA uint8/int16/int32 tensors")
+        ndim = images[0].dim()
+        if ndim not in (2, 3) or any(im.dim() != ndim or im.dtype != dt or im.device != dev for im in images):
+            raise ValueError("every image must have the same ndim (2 or 3), dtype and device")
+        self.ndim = ndim
+        self.num_images = len(images)
+        self.device = dev
+        flat = [im.reshape(-1) for im in images]
+        self.pixels = torch.cat(flat) if len(flat) > 1 else flat[0].contiguous()
+        self.dims = np.array([list(reversed(im.shape)) for im in images], dtype=np.int32)
+        offs = np.zeros(len(images), dtype=np.int64)
+        if len(images) > 1:
+            offs[1:] = np.cumsum([f.numel() for f in flat[:-1]])
+        self.pixel_offsets = offs
+        self.origin = None if origin is None else np.ascontiguousarray(np.asarray(origin, np.float64).reshape(-1, ndim))
+        self.spacing = None if spacing is None else np.ascontiguousarray(np.asarray(spacing, np.float64).reshape(-1, ndim))
+        if self.origin is not None and self.origin.shape[0] == 1 and self.num_images > 1:
+            self.origin = np.ascontiguousarray(np.repeat(self.origin, self.num_images, 0))
+        if self.spacing is not None and self.spacing.shape[0] == 1 and self.num_images > 1:
+            self.spacing = np.ascontiguousarray(np.repeat(self.spacing, self.num_images, 0))
+        self._batch = N.ImageBatch(
+            ndim, len(images), self.dims.ctypes.data_as(N.P(N.c_i32)),
+            self.pixel_offsets.ctypes.data_as(N.P(N.c_i64)), _dptr(self.pixels), _DTYPES[dt], construction,
+            None if self.origin is None else self.origin.ctypes.data_as(N.P(N.c_f64)),
+            None if self.spacing is None else self.spacing.ctypes.data_as(N.P(N.c_f64)))
+        st = _stream(stream)
+        need = ctypes.c_size_t(0)
+        status, _ = N.ect_precompute(self._batch, None, need, st)
+        N.check(status, "ect_precompute(size)")
+        self.ws = _workspace(need.value, dev)
+        have = ctypes.c_size_t(self.ws.numel())
+        status, handle = N.ect_precompute(self._batch, ctypes.c_void_p(_dptr(self.ws)), have, st)
+        N.check(status, "ect_precompute")
+        self.handle = handle
+        self._eval_ws = None
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "handle", None):
+            N.ect_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ------------------------------------------------------------
+    def _ws(self, nbytes: int) -> torch.Tensor:
+        if self._eval_ws is None or self._eval_ws.numel() < nbytes:
+            self._eval_ws = _workspace(nbytes, self.device)
+        return self._eval_ws
+
+    def rerun(self, stream=None):
+        N.check(N.ect_plan_rerun(self.handle, _stream(stream)), "ect_plan_rerun")
+
+    def counts(self):
+        nc, no = 1 << self.ndim, 1 << (self.ndim - 1)
+        c = np.zeros((self.num_images, nc), np.int64)
+        o = np.zeros((self.num_images, no), np.int64)
+        N.check(N.ect_plan_counts(self.handle, c.ctypes.data_as(N.P(N.c_i64)), o.ctypes.data_as(N.P(N.c_i64))),
+                "ect_plan_counts")
+        return c, o
+
+    def export(self, image: int, kind: int, lst: int, stream=None):
+        """(coords [count][ndim] vertex indices, values [count]) of one list (kind 0 classical, 1 ordinary)."""
+        cnt = ctypes.c_int64(0)
+        st = _stream(stream)
+        N.check(N.ect_plan_export(self.handle, image, kind, lst, None, None, 0, ctypes.byref(cnt), st),
+                "ect_plan_export(count)")
+        n = cnt.value
+        coords = np.zeros((max(n, 1), self.ndim), np.int32)
+        vals = np.zeros(max(n, 1), np.int32)
+        N.check(N.ect_plan_export(self.handle, image, kind, lst, coords.ctypes.data_as(N.P(N.c_i32)),
+                                  vals.ctypes.data_as(N.P(N.c_i32)), n, ctypes.byref(cnt), st), "ect_plan_export")
+        return coords[:n], vals[:n]
+
+    def check(self, stream=None) -> int:
+        f = ctypes.c_uint32(0)
+        N.check(N.ect_plan_check(self.handle, ctypes.byref(f), _stream(stream)), "ect_plan_check")
+        return f.value
+
+    # -- evaluation ---------------------------------------------------------
+    def ect(self, dirs, thresholds: torch.Tensor, offsets=None, out=None, stream=None) -> torch.Tensor:
+        """int32 [rows][M]: ECT at every direction and threshold (thresholds [M] or [num_images][M])."""
+        q = dirs if isinstance(dirs, QuerySet) else QuerySet(dirs, offsets)
+        q.validate(self.num_images, self.ndim)
+        thr = thresholds.to(device=self.device, dtype=torch.float64).contiguous()
+        per_image = 1 if thr.dim() == 2 else 0
+        if thr.dim() not in (1, 2) or (per_image and thr.shape[0] != self.num_images):
+            raise ValueError("thresholds must be [M] or [num_images][M]")
+        M = thr.shape[-1]
+        rows = q.rows(self.num_images)
+        if out is None:
+            out = torch.empty((rows, M), dtype=torch.int32, device=self.device)
+        st = _stream(stream)
+        need = ctypes.c_size_t(0)
+        N.check(N.ect_eval(self.handle, q.c(), _dptr(thr), M, per_image, _dptr(out), None, need, st), "ect_eval(size)")
+        ws = self._ws(need.value)
+        have = ctypes.c_size_t(ws.numel())
+        N.check(N.ect_eval(self.handle, q.c(), _dptr(thr), M, per_image, _dptr(out),
+                           ctypes.c_void_p(_dptr(ws)), have, st), "ect_eval")
+        return out
+
+    def hybrid(self, xi, kernel: str = "fourier", s: float = 1.0, precision: str = "fp32", offsets=None,
+               log_scale: bool = False, out=None, stream=None):
+        """float64 [rows] (Fourier: [rows][2]); with log_scale (Laplace) returns (out, log_scale)."""
+        q = xi if isinstance(xi, QuerySet) else QuerySet(xi, offsets)
+        q.validate(self.num_images, self.ndim)
+        k = N.KERNELS[kernel]
+        rows = q.rows(self.num_images)
+        if out is None:
+            out = torch.empty((rows, 2) if k == N.FOURIER else (rows,), dtype=torch.float64, device=self.device)
+        ls = torch.empty(rows, dtype=torch.float64, device=self.device) if log_scale else None
+        st = _stream(stream)
+        need = ctypes.c_size_t(0)
+        N.check(N.hybrid_eval(self.handle, k, s, N.PRECISIONS[precision], q.c(), _dptr(out), _dptr(ls), None,
+                              need, st), "hybrid_eval(size)")
+        ws = self._ws(need.value)
+        have = ctypes.c_size_t(ws.numel())
+        N.check(N.hybrid_eval(self.handle, k, s, N.PRECISIONS[precision], q.c(), _dptr(out), _dptr(ls),
+                              ctypes.c_void_p(_dptr(ws)), have, st), "hybrid_eval")
+        return (out, ls) if log_scale else out
+
+    def hybrid_backward(self, xi, out: torch.Tensor, grad_out: torch.Tensor, kernel: str = "fourier", s: float = 1.0,
+                        precision: str = "fp32", offsets=None, stream=None):
+        """(grad_xi, grad_s): VJP of hybrid() (shared sets sum grad_xi over images)."""
+        q = xi if isinstance(xi, QuerySet) else QuerySet(xi, offsets)
+        q.validate(self.num_images, self.ndim)
+        k = N.KERNELS[kernel]
+        rows = q.rows(self.num_images)
+        if out.shape[0] != rows or grad_out.shape != out.shape:
+            raise ValueError("out and grad_out must have the forward output's shape")
+        gxi = torch.empty((q.vecs.shape[0], self.ndim), dtype=torch.float64, device=self.device)
+        gs = torch.empty((), dtype=torch.float64, device=self.device)
+        out = out.to(torch.float64).contiguous()
+        go = grad_out.to(torch.float64).contiguous()
+        st = _stream(stream)
+        need = ctypes.c_size_t(0)
+        N.check(N.hybrid_eval_backward(self.handle, k, s, N.PRECISIONS[precision], q.c(), _dptr(out), _dptr(go),
+                                       _dptr(gxi), _dptr(gs), None, need, st), "hybrid_eval_backward(size)")
+        ws = self._ws(need.value)
+        have = ctypes.c_size_t(ws.numel())
+        N.check(N.hybrid_eval_backward(self.handle, k, s, N.PRECISIONS[precision], q.c(), _dptr(out), _dptr(go),
+                                       _dptr(gxi), _dptr(gs), ctypes.c_void_p(_dptr(ws)), have, st),
+                "hybrid_eval_backward")
+        return gxi, gs
+
+
+class HybridTransform(torch.autograd.Function):
+    """y = HT_s(xi) for every image of a plan, differentiable in xi and in the scale s.
+
+    xi: [count][ndim] shared by every image (float32 or float64; converted to
+    float64 losslessly at the boundary).  s: 0-dim tensor.  Returns float64
+    [num_images*count] (Fourier: [num_images*count][2]); the backward pass
+    calls the library's vector-Jacobian product kernel.
+    """
+
+    @staticmethod
+    def forward(ctx, xi, s, plan: Plan, kernel: str = "fourier", precision: str = "fp32"):
+        xi64 = xi.detach().to(torch.float64).contiguous()
+        sval = float(s.detach().item()) if torch.is_tensor(s) else float(s)
+        y = plan.hybrid(xi64, kernel, sval, precision)
+        ctx.plan, ctx.kernel, ctx.precision, ctx.sval = plan, kernel, precision, sval
+        ctx.xi_dtype = xi.dtype
+        ctx.s_is_tensor = torch.is_tensor(s)
+        ctx.save_for_backward(xi64, y)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        xi64, y = ctx.saved_tensors
+        gxi, gs = ctx.plan.hybrid_backward(xi64, y, gy.contiguous(), ctx.kernel, ctx.sval, ctx.precision)
+        return gxi.to(ctx.xi_dtype), (gs if ctx.s_is_tensor else None), None, None, None

@@ -1,0 +1,484 @@
+// Host side of the C ABI: argument validation, workspace layouts, plan
+// bookkeeping and kernel launches.  No exception crosses the boundary and no
+// device memory is allocated here.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "eval_internal.h"
+
+using namespace ect;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct EvalLayout {
+    size_t perm, bstart, bcnt, item_off, tile_off, params, counters, partials, gpart, gspart, total;
+    int64_t groups, entries, grid, capacity, tiles;
+};
+
+bool valid_query_set(const ect_query_set& q, int num_images) {
+    if (!q.vecs || q.count < 0) return false;
+    (void)num_images;
+    return true;
+}
+
+int64_t query_rows(const ect_query_set& q, int num_images) {
+    return q.offsets ? q.count : q.count * (int64_t)num_images;
+}
+
+// Workspace shared by the evaluation calls: bucketing and work list.
+void layout_common(const Plan& p, const ect_query_set& q, int B, EvalLayout* L, size_t* off) {
+    const bool shared = q.offsets == nullptr;
+    const int64_t groups = shared ? 1 : p.num_images;
+    const int64_t perm_rows = shared ? q.count : q.count;
+    L->groups = groups;
+    L->entries = (int64_t)p.num_images * B;
+    size_t o = *off;
+    L->perm = o; o = align_up(o + sizeof(int64_t) * std::max<int64_t>(perm_rows, 1), kAlign);
+    L->bstart = o; o = align_up(o + sizeof(int64_t) * groups * B, kAlign);
+    L->bcnt = o; o = align_up(o + sizeof(int32_t) * groups * B, kAlign);
+    L->item_off = o; o = align_up(o + sizeof(int64_t) * (L->entries + 1), kAlign);
+    L->tile_off = o; o = align_up(o + sizeof(int64_t) * (L->entries + 1), kAlign);
+    L->params = o; o = align_up(o + sizeof(int64_t) * 4, kAlign);
+    *off = o;
+}
+
+// Largest list of each ordinary (or classical) kind, from the host copy of
+// the list offsets made by ect_precompute.
+int64_t max_list(const Plan& p, int base, int count) {
+    const int NL = num_lists(p.ndim);
+    int64_t m = 0;
+    for (int i = 0; i < p.num_images; ++i)
+        for (int b = 0; b < count; ++b) {
+            int64_t n = p.h_list_off[(int64_t)(i + 1) * NL + base + b] - p.h_list_off[(int64_t)i * NL + base + b];
+            m = std::max(m, n);
+        }
+    return m;
+}
+
+double mean_list(const Plan& p, int base, int count) {
+    const int NL = num_lists(p.ndim);
+    double s = 0;
+    for (int b = 0; b < count; ++b)
+        s += (double)(p.h_list_off[(int64_t)p.num_images * NL + base + b] - p.h_list_off[base + b]);
+    return s / std::max(1, p.num_images * count);
+}
+
+// Tunables (defaults; an autotuner may override them through ect_set_tuning).
+struct Tuning {
+    int64_t hybrid_chunk = 0;        // 0: automatic
+    int64_t hybrid_target_items = 4096;
+    int ect_dirs_per_group = kEctMaxDirs;
+} g_tuning;
+
+int64_t hybrid_chunk_for(const Plan& p, int64_t rows) {
+    if (g_tuning.hybrid_chunk > 0) return g_tuning.hybrid_chunk;
+    const int P = num_ordinary(p.ndim);
+    const double avg = mean_list(p, num_classical(p.ndim), P);
+    const double pairs = (double)rows * avg;
+    double c = pairs / ((double)kHybridLanes * (double)g_tuning.hybrid_target_items);
+    int64_t ci = (int64_t)std::ceil(std::max(64.0, c) / 16.0) * 16;
+    return ci;
+}
+
+void layout_hybrid(const Plan& p, const ect_query_set& q, bool backward, EvalLayout* L, int64_t* chunk) {
+    const int P = num_ordinary(p.ndim);
+    size_t o = 0;
+    layout_common(p, q, P, L, &o);
+    const bool shared = q.offsets == nullptr;
+    const int64_t rows = query_rows(q, p.num_images);
+    // query tiles: sum over (image, pair) of ceil(count / 64) <= rows/64 + images*P
+    const int64_t tiles = shared ? (int64_t)p.num_images * ((q.count + kHybridLanes - 1) / kHybridLanes + P)
+                                 : (rows + kHybridLanes - 1) / kHybridLanes + (int64_t)p.num_images * P;
+    *chunk = hybrid_chunk_for(p, rows);
+    const int64_t maxn = max_list(p, num_classical(p.ndim), P);
+    const int64_t maxch = std::max<int64_t>(1, (maxn + *chunk - 1) / *chunk);
+    L->tiles = tiles;
+    L->grid = tiles * maxch;
+    L->capacity = L->grid;
+    L->counters = o; o = align_up(o + sizeof(uint32_t) * std::max<int64_t>(tiles, 1), kAlign);
+    L->partials = o; o = align_up(o + sizeof(double) * 4 * kHybridLanes * std::max<int64_t>(L->capacity, 1), kAlign);
+    L->gpart = L->gspart = 0;
+    if (backward) {
+        L->gpart = o; o = align_up(o + sizeof(double) * p.ndim * std::max<int64_t>(rows, 1), kAlign);
+        L->gspart = o; o = align_up(o + sizeof(double) * std::max<int64_t>(rows, 1), kAlign);
+    }
+    L->total = o;
+}
+
+void layout_ect(const Plan& p, const ect_query_set& q, int td, EvalLayout* L) {
+    const int B = num_classical(p.ndim);
+    size_t o = 0;
+    layout_common(p, q, B, L, &o);
+    const bool shared = q.offsets == nullptr;
+    const int64_t rows = query_rows(q, p.num_images);
+    L->grid = shared ? (int64_t)p.num_images * ((q.count + td - 1) / td + B)
+                     : (rows + td - 1) / td + (int64_t)p.num_images * B;
+    L->total = o;
+}
+
+ect_status from_hip(hipError_t e) { return e == hipSuccess ? ECT_OK : ECT_E_DEVICE; }
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+extern "C" {
+
+const char* ect_version(void) { return "0.1.0"; }
+
+const char* ect_status_string(ect_status s) {
+    switch (s) {
+        case ECT_OK: return "ok";
+        case ECT_E_INVALID: return "invalid argument";
+        case ECT_E_NOMEM: return "workspace too small or host allocation failed";
+        case ECT_E_DEVICE: return "HIP runtime error";
+        case ECT_E_UNSUPPORTED: return "unsupported request";
+        case ECT_E_RANGE: return "value out of range";
+    }
+    return "unknown status";
+}
+
+ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_bytes, hipStream_t stream,
+                          ect_plan* out) {
+    if (!batch || !ws_bytes) return ECT_E_INVALID;
+    const int n = batch->ndim;
+    if (n != 2 && n != 3) return ECT_E_INVALID;
+    if (batch->num_images < 1 || !batch->dims || !batch->pixel_offsets || !batch->pixels) return ECT_E_INVALID;
+    if (batch->dtype < ECT_U8 || batch->dtype > ECT_I32) return ECT_E_INVALID;
+    if (batch->construction != ECT_PRIMAL && batch->construction != ECT_DUAL) return ECT_E_INVALID;
+    const int NL = num_lists(n);
+    const int ni = batch->num_images;
+
+    std::vector<ImageDesc> desc(ni);
+    std::vector<int64_t> tstart(ni + 1);
+    int64_t tiles = 0, verts = 0, maxv = 0;
+    for (int i = 0; i < ni; ++i) {
+        ImageDesc& d = desc[i];
+        std::memset(&d, 0, sizeof(d));
+        if (batch->pixel_offsets[i] < 0) return ECT_E_INVALID;
+        d.pixel_offset = batch->pixel_offsets[i];
+        int64_t nv = 1;
+        for (int a = 0; a < 3; ++a) {
+            if (a < n) {
+                const int32_t dim = batch->dims[(int64_t)i * n + a];
+                if (dim < 1 || dim > (1 << 20)) return ECT_E_INVALID;
+                d.dims[a] = dim;
+                d.N[a] = batch->construction == ECT_PRIMAL ? dim : dim - 1;
+                d.V[a] = d.N[a] + 1;
+                d.origin[a] = batch->origin ? batch->origin[(int64_t)i * n + a] : -0.5 * (double)d.N[a];
+                d.spacing[a] = batch->spacing ? batch->spacing[(int64_t)i * n + a] : 1.0;
+                if (!is_finite(d.origin[a]) || !is_finite(d.spacing[a])) return ECT_E_INVALID;
+            } else {
+                d.dims[a] = 1; d.N[a] = 0; d.V[a] = 1; d.origin[a] = 0.0; d.spacing[a] = 1.0;
+            }
+            nv *= d.V[a];
+            const double x0 = d.origin[a];
+            const double x1 = std::fma(d.spacing[a], (double)d.N[a], d.origin[a]);
+            d.lo[a] = std::min(x0, x1);
+            d.hi[a] = std::max(x0, x1);
+        }
+        if (nv >= (int64_t)1 << 31) return ECT_E_UNSUPPORTED;
+        d.nvert = nv;
+        d.tile_start = tiles;
+        tstart[i] = tiles;
+        tiles += (nv + kTileVerts - 1) / kTileVerts;
+        verts += nv;
+        maxv = std::max(maxv, nv);
+    }
+    tstart[ni] = tiles;
+    if (tiles >= (int64_t)1 << 31) return ECT_E_UNSUPPORTED;
+
+    PlanLayout L{};
+    size_t o = 0;
+    L.err = o; o = align_up(o + 16, kAlign);
+    L.desc = o; o = align_up(o + sizeof(ImageDesc) * ni, kAlign);
+    L.tile_start = o; o = align_up(o + sizeof(int64_t) * (ni + 1), kAlign);
+    L.list_off = o; o = align_up(o + sizeof(int64_t) * (int64_t)(ni + 1) * NL, kAlign);
+    L.status = o; o = align_up(o + sizeof(uint64_t) * tiles * NL, kAlign);
+    L.points = o; o = align_up(o + sizeof(Point) * verts * NL, kAlign);
+    L.total = o;
+    L.num_tiles = tiles;
+    L.capacity = verts;
+    if (!ws) {
+        *ws_bytes = L.total;
+        return ECT_OK;
+    }
+    if (*ws_bytes < L.total) return ECT_E_NOMEM;
+    if (((uintptr_t)ws) % kAlign) return ECT_E_INVALID;
+    if (!out) return ECT_E_INVALID;
+
+    Plan* p = new (std::nothrow) Plan();
+    if (!p) return ECT_E_NOMEM;
+    p->ndim = n;
+    p->num_images = ni;
+    p->dtype = batch->dtype;
+    p->construction = batch->construction;
+    p->pixels = batch->pixels;
+    p->ws = (char*)ws;
+    p->lay = L;
+    p->total_verts = verts;
+    p->max_image_verts = maxv;
+    p->h_desc = new (std::nothrow) ImageDesc[ni];
+    p->h_list_off = new (std::nothrow) int64_t[(int64_t)(ni + 1) * NL];
+    if (!p->h_desc || !p->h_list_off) {
+        ect_plan_destroy(p);
+        return ECT_E_NOMEM;
+    }
+    std::memcpy(p->h_desc, desc.data(), sizeof(ImageDesc) * ni);
+
+    hipError_t e = hipMemcpyAsync(p->ws + L.desc, desc.data(), sizeof(ImageDesc) * ni, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->ws + L.tile_start, tstart.data(), sizeof(int64_t) * (ni + 1), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = launch_precompute(*p, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->h_list_off, p->ws + L.list_off, sizeof(int64_t) * (int64_t)(ni + 1) * NL,
+                           hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        ect_plan_destroy(p);
+        return ECT_E_DEVICE;
+    }
+    *out = p;
+    return ECT_OK;
+}
+
+ect_status ect_plan_rerun(ect_plan plan, hipStream_t stream) {
+    if (!plan) return ECT_E_INVALID;
+    return from_hip(launch_precompute(*plan, stream));
+}
+
+ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds, int32_t M,
+                    int32_t thresholds_per_image, int32_t* out, void* ws, size_t* ws_bytes, hipStream_t stream) {
+    if (!plan || !ws_bytes) return ECT_E_INVALID;
+    if (!valid_query_set(dirs, plan->num_images) || !thresholds || !out) return ECT_E_INVALID;
+    if (M < 1) return ECT_E_INVALID;
+    if (M > kEctMaxThresholds) return ECT_E_UNSUPPORTED;
+    const Plan& p = *plan;
+    int td = g_tuning.ect_dirs_per_group;
+    const int64_t lds_budget = 60 * 1024;
+    td = (int)std::min<int64_t>(td, (lds_budget - 8 * (int64_t)M) / (4 * (int64_t)M));
+    td = std::max(1, std::min(td, kEctMaxDirs));
+    EvalLayout L{};
+    layout_ect(p, dirs, td, &L);
+    if (!ws) {
+        *ws_bytes = L.total;
+        return ECT_OK;
+    }
+    if (*ws_bytes < L.total) return ECT_E_NOMEM;
+    const int64_t rows = query_rows(dirs, p.num_images);
+    if (rows == 0) return ECT_OK;
+    char* w = (char*)ws;
+    const int B = num_classical(p.ndim);
+    const int NL = num_lists(p.ndim);
+    uint32_t* err = (uint32_t*)(p.ws + p.lay.err);
+    hipError_t e = launch_bucket(p.ndim, dirs, p.num_images, false, err, (int64_t*)(w + L.perm),
+                                 (int64_t*)(w + L.bstart), (int32_t*)(w + L.bcnt), stream);
+    if (e == hipSuccess)
+        e = launch_worklist(p.num_images, B, 0, NL, dirs.offsets == nullptr, (const int32_t*)(w + L.bcnt),
+                            (const int64_t*)(p.ws + p.lay.list_off), td, 0, 0, err, (int64_t*)(w + L.item_off),
+                            (int64_t*)(w + L.tile_off), (int64_t*)(w + L.params), stream);
+    if (e == hipSuccess) {
+        EctArgs a{};
+        a.points = (const Point*)(p.ws + p.lay.points);
+        a.list_off = (const int64_t*)(p.ws + p.lay.list_off);
+        a.desc = (const ImageDesc*)(p.ws + p.lay.desc);
+        a.capacity = p.lay.capacity;
+        a.num_images = p.num_images;
+        a.NL = NL;
+        a.vecs = dirs.vecs;
+        a.offsets = dirs.offsets;
+        a.count = dirs.count;
+        a.thresholds = thresholds;
+        a.M = M;
+        a.thr_per_image = thresholds_per_image ? 1 : 0;
+        a.out = out;
+        a.perm = (const int64_t*)(w + L.perm);
+        a.bstart = (const int64_t*)(w + L.bstart);
+        a.bcnt = (const int32_t*)(w + L.bcnt);
+        a.item_off = (const int64_t*)(w + L.item_off);
+        a.err = err;
+        a.dirs_per_group = td;
+        e = launch_ect(p.ndim, a, L.grid, stream);
+    }
+    return from_hip(e);
+}
+
+static ect_status hybrid_common(ect_plan plan, int32_t kernel, double s, int32_t precision, ect_query_set xi,
+                                double* out, double* log_scale, const double* fwd_out, const double* grad_out,
+                                double* grad_xi, double* grad_s, void* ws, size_t* ws_bytes, hipStream_t stream,
+                                bool backward) {
+    if (!plan || !ws_bytes) return ECT_E_INVALID;
+    if (kernel < ECT_FOURIER || kernel > ECT_BESSEL) return ECT_E_INVALID;
+    if (precision != ECT_FP32 && precision != ECT_FP64) return ECT_E_INVALID;
+    if (!std::isfinite(s) || s == 0.0) return ECT_E_INVALID;
+    if (!valid_query_set(xi, plan->num_images)) return ECT_E_INVALID;
+    if (!backward && !out) return ECT_E_INVALID;
+    if (backward && (!fwd_out || !grad_out || !grad_xi)) return ECT_E_INVALID;
+    const Plan& p = *plan;
+    EvalLayout L{};
+    int64_t chunk = 0;
+    layout_hybrid(p, xi, backward, &L, &chunk);
+    if (!ws) {
+        *ws_bytes = L.total;
+        return ECT_OK;
+    }
+    if (*ws_bytes < L.total) return ECT_E_NOMEM;
+    const int64_t rows = query_rows(xi, p.num_images);
+    if (rows == 0) return ECT_OK;
+    char* w = (char*)ws;
+    const int P = num_ordinary(p.ndim);
+    const int NL = num_lists(p.ndim);
+    uint32_t* err = (uint32_t*)(p.ws + p.lay.err);
+    const bool shared = xi.offsets == nullptr;
+    hipError_t e = launch_bucket(p.ndim, xi, p.num_images, true, err, (int64_t*)(w + L.perm),
+                                 (int64_t*)(w + L.bstart), (int32_t*)(w + L.bcnt), stream);
+    if (e == hipSuccess)
+        e = launch_worklist(p.num_images, P, num_classical(p.ndim), NL, shared, (const int32_t*)(w + L.bcnt),
+                            (const int64_t*)(p.ws + p.lay.list_off), kHybridLanes, chunk, L.capacity, err,
+                            (int64_t*)(w + L.item_off), (int64_t*)(w + L.tile_off), (int64_t*)(w + L.params),
+                            stream);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)(w + L.counters), L.tiles, 0u, stream);
+    if (e != hipSuccess) return ECT_E_DEVICE;
+    HybridArgs a{};
+    a.points = (const Point*)(p.ws + p.lay.points);
+    a.list_off = (const int64_t*)(p.ws + p.lay.list_off);
+    a.desc = (const ImageDesc*)(p.ws + p.lay.desc);
+    a.capacity = p.lay.capacity;
+    a.num_images = p.num_images;
+    a.NL = NL;
+    a.list_base = num_classical(p.ndim);
+    a.vecs = xi.vecs;
+    a.offsets = xi.offsets;
+    a.count = xi.count;
+    a.s = s;
+    a.out = out;
+    a.log_scale = log_scale;
+    a.fwd_out = fwd_out;
+    a.grad_out = grad_out;
+    a.perm = (const int64_t*)(w + L.perm);
+    a.bstart = (const int64_t*)(w + L.bstart);
+    a.bcnt = (const int32_t*)(w + L.bcnt);
+    a.item_off = (const int64_t*)(w + L.item_off);
+    a.tile_off = (const int64_t*)(w + L.tile_off);
+    a.params = (const int64_t*)(w + L.params);
+    a.partials = (double*)(w + L.partials);
+    a.counters = (uint32_t*)(w + L.counters);
+    a.err = err;
+    if (!backward) return from_hip(launch_hybrid_fwd(p.ndim, kernel, precision, a, L.grid, stream));
+    double* gpart = (double*)(w + L.gpart);
+    a.grad_xi = shared ? gpart : grad_xi;
+    a.grad_s_part = (double*)(w + L.gspart);
+    e = launch_hybrid_bwd(p.ndim, kernel, precision, a, L.grid, stream);
+    if (e == hipSuccess)
+        e = launch_grad_reduce(p.ndim, gpart, p.num_images, xi.count, shared, grad_xi, a.grad_s_part, rows,
+                               grad_s, stream);
+    return from_hip(e);
+}
+
+ect_status hybrid_eval(ect_plan plan, int32_t kernel, double s, int32_t precision, ect_query_set xi, double* out,
+                       double* log_scale, void* ws, size_t* ws_bytes, hipStream_t stream) {
+    return hybrid_common(plan, kernel, s, precision, xi, out, log_scale, nullptr, nullptr, nullptr, nullptr, ws,
+                         ws_bytes, stream, false);
+}
+
+ect_status hybrid_eval_backward(ect_plan plan, int32_t kernel, double s, int32_t precision, ect_query_set xi,
+                                const double* out, const double* grad_out, double* grad_xi, double* grad_s,
+                                void* ws, size_t* ws_bytes, hipStream_t stream) {
+    return hybrid_common(plan, kernel, s, precision, xi, nullptr, nullptr, out, grad_out, grad_xi, grad_s, ws,
+                         ws_bytes, stream, true);
+}
+
+ect_status ect_plan_counts(ect_plan plan, int64_t* classical, int64_t* ordinary) {
+    if (!plan) return ECT_E_INVALID;
+    const int n = plan->ndim, NL = num_lists(n), NC = num_classical(n), NO = num_ordinary(n);
+    for (int i = 0; i < plan->num_images; ++i) {
+        const int64_t* a = plan->h_list_off + (int64_t)i * NL;
+        const int64_t* b = a + NL;
+        for (int l = 0; l < NC; ++l)
+            if (classical) classical[(int64_t)i * NC + l] = b[l] - a[l];
+        for (int l = 0; l < NO; ++l)
+            if (ordinary) ordinary[(int64_t)i * NO + l] = b[NC + l] - a[NC + l];
+    }
+    return ECT_OK;
+}
+
+ect_status ect_plan_export(ect_plan plan, int32_t image, int32_t kind, int32_t list, int32_t* coords,
+                           int32_t* values, int64_t capacity, int64_t* count, hipStream_t stream) {
+    if (!plan || !count || capacity < 0) return ECT_E_INVALID;
+    const Plan& p = *plan;
+    const int n = p.ndim, NL = num_lists(n);
+    if (image < 0 || image >= p.num_images) return ECT_E_INVALID;
+    if (kind != 0 && kind != 1) return ECT_E_INVALID;
+    const int nlist = kind == 0 ? num_classical(n) : num_ordinary(n);
+    if (list < 0 || list >= nlist) return ECT_E_INVALID;
+    if (capacity > 0 && (!coords || !values)) return ECT_E_INVALID;
+    const int l = (kind == 0 ? 0 : num_classical(n)) + list;
+    int64_t off[2];
+    hipError_t e = hipMemcpyAsync(&off[0], p.ws + p.lay.list_off + sizeof(int64_t) * ((int64_t)image * NL + l),
+                                  sizeof(int64_t), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&off[1], p.ws + p.lay.list_off + sizeof(int64_t) * ((int64_t)(image + 1) * NL + l),
+                           sizeof(int64_t), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return ECT_E_DEVICE;
+    const int64_t cnt = off[1] - off[0];
+    *count = cnt;
+    const int64_t take = std::min(cnt, capacity);
+    if (take <= 0) return ECT_OK;
+    std::vector<Point> buf;
+    try {
+        buf.resize(take);
+    } catch (...) {
+        return ECT_E_NOMEM;
+    }
+    e = hipMemcpyAsync(buf.data(), p.ws + p.lay.points + sizeof(Point) * ((int64_t)l * p.lay.capacity + off[0]),
+                       sizeof(Point) * take, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return ECT_E_DEVICE;
+    const ImageDesc& d = p.h_desc[image];
+    for (int64_t k = 0; k < take; ++k) {
+        for (int a = 0; a < n; ++a)
+            coords[k * n + a] = (int32_t)std::lrint((buf[k].x[a] - d.origin[a]) / d.spacing[a]);
+        values[k] = (int32_t)buf[k].val;
+    }
+    return ECT_OK;
+}
+
+ect_status ect_plan_check(ect_plan plan, uint32_t* flags, hipStream_t stream) {
+    if (!plan || !flags) return ECT_E_INVALID;
+    uint32_t v = 0;
+    hipError_t e = hipMemcpyAsync(&v, plan->ws + plan->lay.err, sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    const uint32_t zero = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(plan->ws + plan->lay.err, &zero, sizeof(uint32_t), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return ECT_E_DEVICE;
+    *flags = v;
+    return ECT_OK;
+}
+
+ect_status ect_plan_destroy(ect_plan plan) {
+    if (!plan) return ECT_E_INVALID;
+    delete[] plan->h_desc;
+    delete[] plan->h_list_off;
+    delete plan;
+    return ECT_OK;
+}
+
+// Tuning knobs for the autotuner: hybrid point-chunk length (0 = automatic),
+// target number of hybrid work items, directions per ECT workgroup.
+ect_status ect_set_tuning(int64_t hybrid_chunk, int64_t hybrid_target_items, int32_t ect_dirs_per_group) {
+    if (hybrid_chunk < 0 || hybrid_target_items < 1 || ect_dirs_per_group < 1 || ect_dirs_per_group > kEctMaxDirs)
+        return ECT_E_INVALID;
+    g_tuning.hybrid_chunk = hybrid_chunk;
+    g_tuning.hybrid_target_items = hybrid_target_items;
+    g_tuning.ect_dirs_per_group = ect_dirs_per_group;
+    return ECT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Internal definitions shared by the host plan code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ect.h"
+
+namespace ect {
+
+constexpr int kMaxDim = 3;
+constexpr int kPrecomputeThreads = 256;              // threads per precompute workgroup
+constexpr int kVertsPerThread = 4;                   // vertices per thread per tile
+constexpr int kTileVerts = kPrecomputeThreads * kVertsPerThread;
+constexpr int kMaxLists = 12;                        // 2^n classical + 2^(n-1) ordinary, n = 3
+
+__host__ __device__ constexpr int num_classical(int n) { return 1 << n; }
+__host__ __device__ constexpr int num_ordinary(int n) { return 1 << (n - 1); }
+__host__ __device__ constexpr int num_lists(int n) { return num_classical(n) + num_ordinary(n); }
+
+// One critical point as the evaluation kernels read it: canonical FP64
+// vertex coordinates (x_a = fma(h_a, k_a, o_a); unused axes 0) and its
+// critical value.  32 bytes, so a wave reads one point with one scalar load.
+struct alignas(32) Point {
+    double x[3];
+    double val;
+};
+
+// Per-image constants, uploaded once per plan.
+struct alignas(16) ImageDesc {
+    int64_t pixel_offset;   // element offset of the image in the pixel buffer
+    int64_t nvert;          // number of vertices
+    int64_t tile_start;     // first precompute tile of this image
+    int32_t dims[3];        // pixels per axis (1 for unused axes)
+    int32_t N[3];           // top cells per axis
+    int32_t V[3];           // vertices per axis (N + 1)
+    int32_t pad;
+    double origin[3];
+    double spacing[3];
+    double lo[3], hi[3];    // vertex coordinate range per axis (lo <= hi)
+};
+
+// Layout of the precompute workspace (byte offsets from its base).
+struct PlanLayout {
+    size_t err;             // uint32 device error word (+ uint32 tile counter right after)
+    size_t desc;            // ImageDesc[num_images]
+    size_t tile_start;      // int64[num_images + 1]
+    size_t list_off;        // int64[(num_images + 1) * NL]: start of image i in list l
+    size_t status;          // uint64[num_tiles * NL]: ordered-compaction look-back words
+    size_t points;          // Point[NL * capacity]
+    size_t total;
+    int64_t num_tiles;
+    int64_t capacity;       // entries per list region (= total vertices)
+};
+
+}  // namespace ect
+
+// Host handle behind ect_plan.
+struct ect_plan_s {
+    int32_t ndim = 0;
+    int32_t num_images = 0;
+    int32_t dtype = 0;
+    int32_t construction = 0;
+    const void* pixels = nullptr;
+    char* ws = nullptr;
+    ect::PlanLayout lay{};
+    ect::ImageDesc* h_desc = nullptr;   // host copy
+    int64_t* h_list_off = nullptr;      // host copy [(num_images+1) * NL], as of the last ect_precompute
+    int64_t total_verts = 0;
+    int64_t max_image_verts = 0;
+};
+
+namespace ect {
+
+using Plan = ::ect_plan_s;
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Device error word helpers.
+__device__ inline void raise_error(uint32_t* err, uint32_t bits) {
+    __hip_atomic_fetch_or(err, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sign-vector index of a direction: bit a set iff !(xi_a >= 0).
+template <int N>
+__device__ __forceinline__ int sign_index(const double* xi) {
+    int e = 0;
+#pragma unroll
+    for (int a = 0; a < N; ++a) e |= (xi[a] >= 0.0) ? 0 : (1 << a);
+    return e;
+}
+
+// Canonical FP64 projection u = fma(xi_{n-1}, x_{n-1}, ... fma(xi_1, x_1, xi_0*x_0)).
+template <int N>
+__device__ __forceinline__ double project(const double* xi, const double* x) {
+    double u = __dmul_rn(xi[0], x[0]);
+#pragma unroll
+    for (int a = 1; a < N; ++a) u = __fma_rn(xi[a], x[a], u);
+    return u;
+}
+
+// Kernel launch helpers (host side, defined in the .hip files).
+hipError_t launch_precompute(const Plan& p, hipStream_t stream);
+
+}  // namespace ect

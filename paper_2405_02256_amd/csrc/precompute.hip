@@ -1,0 +1,346 @@
+// Per-vertex classification of lower-star critical values and their ordered
+// compaction into per-sign-vector lists (gfx950).
+//
+// For a vertex k and sign vector eps, the lower star is the set of cells of
+// the vertex's star on which k is the highest vertex for any xi of sign eps:
+// along every axis where such a cell extends, it extends towards -eps_a.  So
+//   L(eps, k) = sum over delta in {0,1}^n of (-1)^|delta| phi(cell(k, -delta*eps))
+// over existing cells (Delta^- of Sec. 3, enumerated as in Sec. 4.2 and
+// Appendix A), and Delta^ord(eps, k) = L(-eps, k) - L(eps, k) because the upper
+// star for eps is the lower star for -eps.
+//
+// Cell values come straight from the pixels (nothing is materialised):
+//   primal  a cell takes the min over its coface pixels (Sec. 4.1);
+//   dual    a cell takes the min over its vertex pixels (Sec. 5).
+// Pixel coordinates are clamped into the image: a clamped duplicate never
+// changes a min over existing cofaces, and cells that do not exist are masked
+// by the existence test on the vertex index.
+//
+// Compaction is single pass and ordered: every workgroup takes the next tile
+// id from a counter, counts its nonzero values per list with wave ballots,
+// publishes the counts and resolves its global offset by decoupled look-back
+// over the preceding tiles (one lane per list), then writes its entries in
+// vertex order.  Lists therefore come out sorted by linear vertex index, and
+// identically on every run.
+#include "ect_internal.h"
+
+namespace ect {
+
+namespace {
+
+constexpr uint64_t kFlagAggregate = 1ull << 62;
+constexpr uint64_t kFlagInclusive = 2ull << 62;
+constexpr uint64_t kValueMask = (1ull << 62) - 1;
+constexpr int kLookbackSpinLimit = 1 << 22;
+
+__device__ __forceinline__ uint32_t udiv(uint32_t v, uint32_t d, double inv_d, uint32_t* rem) {
+    uint32_t q = (uint32_t)((double)v * inv_d);
+    int64_t r = (int64_t)v - (int64_t)q * d;
+    if (r < 0) { q -= 1; r += d; }
+    else if (r >= (int64_t)d) { q += 1; r -= d; }
+    *rem = (uint32_t)r;
+    return q;
+}
+
+template <int N>
+__host__ __device__ constexpr int pow3() { return N == 1 ? 3 : (N == 2 ? 9 : 27); }
+
+// Star cell index: sigma_a in {-1, 0, +1} -> digit sigma_a + 1 in base 3.
+template <int N>
+__device__ __forceinline__ constexpr int star_index(const int* sigma) {
+    int s = 0, m = 1;
+    for (int a = 0; a < N; ++a) { s += (sigma[a] + 1) * m; m *= 3; }
+    return s;
+}
+
+template <typename T>
+__device__ __forceinline__ int32_t px_load(const T* __restrict__ img, int64_t i) {
+    return (int32_t)__builtin_nontemporal_load(img + i);
+}
+
+// Critical values of one vertex: L[e] for the 2^N sign vectors, D[e] for the
+// 2^(N-1) sign vectors with eps_{N-1} = +1.
+template <int N, int CONS, typename T>
+__device__ __forceinline__ void vertex_values(const T* __restrict__ img, const ImageDesc& d,
+                                              const int* k, int32_t* L, int32_t* D) {
+    constexpr int S = pow3<N>();
+    int32_t val[S];
+    if constexpr (CONS == ECT_PRIMAL) {
+        // pixels k_a - 1 + d_a, d in {0,1}^N
+        int32_t p[1 << N];
+#pragma unroll
+        for (int c = 0; c < (1 << N); ++c) {
+            int64_t idx = 0, stride = 1;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                int q = k[a] - 1 + ((c >> a) & 1);
+                q = q < 0 ? 0 : (q > d.dims[a] - 1 ? d.dims[a] - 1 : q);
+                idx += (int64_t)q * stride;
+                stride *= d.dims[a];
+            }
+            p[c] = px_load(img, idx);
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            // sigma digits: 0 -> -1 (pixel d=0 only), 1 -> 0 (both), 2 -> +1 (pixel d=1 only)
+            int32_t m = 0x7fffffff;
+#pragma unroll
+            for (int c = 0; c < (1 << N); ++c) {
+                bool ok = true;
+                int r = s;
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    int dig = r % 3;
+                    r /= 3;
+                    int bit = (c >> a) & 1;
+                    if ((dig == 0 && bit != 0) || (dig == 2 && bit != 1)) ok = false;
+                }
+                if (ok) m = min(m, p[c]);
+            }
+            val[s] = m;
+        }
+    } else {
+        // pixels k + t, t in {-1,0,1}^N; a cell extending by sigma takes the min
+        // over the pixels k + t with t_a in {0, sigma_a}
+        int32_t q[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            int64_t idx = 0, stride = 1;
+            int r = c;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                int t = r % 3 - 1;
+                r /= 3;
+                int x = k[a] + t;
+                x = x < 0 ? 0 : (x > d.dims[a] - 1 ? d.dims[a] - 1 : x);
+                idx += (int64_t)x * stride;
+                stride *= d.dims[a];
+            }
+            q[c] = px_load(img, idx);
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            int32_t m = 0x7fffffff;
+#pragma unroll
+            for (int c = 0; c < S; ++c) {
+                bool ok = true;
+                int rs = s, rc = c;
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    int sg = rs % 3 - 1, t = rc % 3 - 1;
+                    rs /= 3;
+                    rc /= 3;
+                    if (!(t == 0 || t == sg)) ok = false;
+                }
+                if (ok) m = min(m, q[c]);
+            }
+            val[s] = m;
+        }
+    }
+    // existence: a cell extending towards -1 (+1) along a needs k_a >= 1 (k_a <= N_a - 1)
+    bool hm[N], hp[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) { hm[a] = k[a] >= 1; hp[a] = k[a] <= d.N[a] - 1; }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        bool ex = true;
+        int r = s;
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            int dig = r % 3;
+            r /= 3;
+            if (dig == 0 && !hm[a]) ex = false;
+            if (dig == 2 && !hp[a]) ex = false;
+        }
+        if (!ex) val[s] = 0;
+    }
+#pragma unroll
+    for (int e = 0; e < (1 << N); ++e) {
+        int32_t acc = 0;
+#pragma unroll
+        for (int del = 0; del < (1 << N); ++del) {
+            int sigma[N];
+            int par = 0;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                int eps = ((e >> a) & 1) ? -1 : 1;
+                int dl = (del >> a) & 1;
+                sigma[a] = dl ? -eps : 0;
+                par += dl;
+            }
+            int32_t v = val[star_index<N>(sigma)];
+            acc += (par & 1) ? -v : v;
+        }
+        L[e] = acc;
+    }
+    constexpr int full = (1 << N) - 1;
+#pragma unroll
+    for (int e = 0; e < (1 << (N - 1)); ++e) D[e] = L[e ^ full] - L[e];
+}
+
+__global__ void reset_kernel(uint32_t* __restrict__ err, uint64_t* __restrict__ status, int64_t nstatus) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (i == 0) { err[0] = 0u; err[1] = 0u; }
+    for (; i < nstatus; i += stride) status[i] = 0ull;
+}
+
+template <int N, int CONS, typename T>
+__global__ void __launch_bounds__(kPrecomputeThreads)
+classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
+                 const int64_t* __restrict__ tile_start, int32_t num_images, int64_t num_tiles,
+                 uint32_t* __restrict__ err, uint64_t* __restrict__ status,
+                 int64_t* __restrict__ list_off, Point* __restrict__ points, int64_t capacity) {
+    constexpr int NC = 1 << N;
+    constexpr int NO = 1 << (N - 1);
+    constexpr int NL = NC + NO;
+    constexpr int W = kPrecomputeThreads / 64;
+    constexpr int J = kVertsPerThread;
+
+    __shared__ uint32_t s_tile;
+    __shared__ int32_t s_cnt[J][W][NL];   // per (round, wave, list) counts, then exclusive offsets
+    __shared__ int64_t s_base[NL];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    if (tid == 0) s_tile = __hip_atomic_fetch_add(err + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    if (tile >= num_tiles) return;  // never expected: the grid has exactly num_tiles workgroups
+
+    // image owning this tile: last i with tile_start[i] <= tile
+    int lo = 0, hi = num_images - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (tile_start[mid] <= tile) lo = mid; else hi = mid - 1;
+    }
+    const ImageDesc d = descs[lo];
+    const int img_id = lo;
+    const T* __restrict__ img = pixels + d.pixel_offset;
+    const int64_t vbase = (tile - d.tile_start) * kTileVerts;
+    const double inv0 = 1.0 / (double)d.V[0];
+    const double inv1 = 1.0 / (double)d.V[1];
+
+    int32_t vals[J][NL];
+    int kk[J][3];
+    bool valid[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        int64_t v = vbase + j * kPrecomputeThreads + tid;
+        valid[j] = v < d.nvert;
+        uint32_t r0, r1;
+        uint32_t q0 = udiv((uint32_t)(valid[j] ? v : 0), (uint32_t)d.V[0], inv0, &r0);
+        uint32_t q1 = N == 3 ? udiv(q0, (uint32_t)d.V[1], inv1, &r1) : 0u;
+        kk[j][0] = (int)r0;
+        kk[j][1] = N == 3 ? (int)r1 : (int)q0;
+        kk[j][2] = N == 3 ? (int)q1 : 0;
+        int32_t L[NC], D[NO];
+        vertex_values<N, CONS, T>(img, d, kk[j], L, D);
+#pragma unroll
+        for (int l = 0; l < NC; ++l) vals[j][l] = valid[j] ? L[l] : 0;
+#pragma unroll
+        for (int l = 0; l < NO; ++l) vals[j][NC + l] = valid[j] ? D[l] : 0;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            uint64_t b = __ballot(vals[j][l] != 0);
+            if (lane == 0) s_cnt[j][wave][l] = __popcll(b);
+        }
+    }
+    __syncthreads();
+
+    if (tid < NL) {
+        const int l = tid;
+        int32_t run = 0;
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                int32_t c = s_cnt[j][w][l];
+                s_cnt[j][w][l] = run;
+                run += c;
+            }
+        const uint64_t agg = (uint64_t)run;
+        uint64_t* st = status + tile * NL + l;
+        uint64_t excl = 0;
+        if (tile > 0) {
+            __hip_atomic_store(st, kFlagAggregate | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            int64_t j = tile - 1;
+            int spins = 0;
+            while (true) {
+                uint64_t w = __hip_atomic_load(status + j * NL + l, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                uint64_t f = w & ~kValueMask;
+                if (f == 0) {
+                    if (++spins > kLookbackSpinLimit) { raise_error(err, ECT_DEVERR_LOOKBACK); break; }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += w & kValueMask;
+                if (f == kFlagInclusive) break;
+                --j;
+            }
+        }
+        __hip_atomic_store(st, kFlagInclusive | (excl + agg), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        s_base[l] = (int64_t)excl;
+        if (tile == d.tile_start) list_off[(int64_t)img_id * NL + l] = (int64_t)excl;
+        if (tile == num_tiles - 1) list_off[(int64_t)num_images * NL + l] = (int64_t)(excl + agg);
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        Point pt;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            pt.x[a] = a < N ? __fma_rn(d.spacing[a], (double)kk[j][a], d.origin[a]) : 0.0;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const bool nz = vals[j][l] != 0;
+            const uint64_t b = __ballot(nz);
+            if (nz) {
+                const int rank = __popcll(b & ((1ull << lane) - 1ull));
+                const int64_t pos = s_base[l] + s_cnt[j][wave][l] + rank;
+                pt.val = (double)vals[j][l];
+                points[(int64_t)l * capacity + pos] = pt;
+            }
+        }
+    }
+}
+
+template <int N, int CONS, typename T>
+hipError_t launch_typed(const Plan& p, hipStream_t stream) {
+    const PlanLayout& L = p.lay;
+    uint32_t* err = (uint32_t*)(p.ws + L.err);
+    uint64_t* status = (uint64_t*)(p.ws + L.status);
+    const int64_t nstatus = L.num_tiles * num_lists(N);
+    int rblocks = (int)std::min<int64_t>((nstatus + 255) / 256 + 1, 4096);
+    hipLaunchKernelGGL(reset_kernel, dim3(rblocks), dim3(256), 0, stream, err, status, nstatus);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((classify_compact<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads),
+                       0, stream, (const T*)p.pixels, (const ImageDesc*)(p.ws + L.desc),
+                       (const int64_t*)(p.ws + L.tile_start), p.num_images, L.num_tiles, err, status,
+                       (int64_t*)(p.ws + L.list_off), (Point*)(p.ws + L.points), L.capacity);
+    return hipGetLastError();
+}
+
+template <int N, int CONS>
+hipError_t launch_dtype(const Plan& p, hipStream_t s) {
+    switch (p.dtype) {
+        case ECT_U8: return launch_typed<N, CONS, uint8_t>(p, s);
+        case ECT_I16: return launch_typed<N, CONS, int16_t>(p, s);
+        default: return launch_typed<N, CONS, int32_t>(p, s);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_precompute(const Plan& p, hipStream_t stream) {
+    if (p.ndim == 2)
+        return p.construction == ECT_PRIMAL ? launch_dtype<2, ECT_PRIMAL>(p, stream)
+                                            : launch_dtype<2, ECT_DUAL>(p, stream);
+    return p.construction == ECT_PRIMAL ? launch_dtype<3, ECT_PRIMAL>(p, stream)
+                                        : launch_dtype<3, ECT_DUAL>(p, stream);
+}
+
+}  // namespace ect

@@ -1,0 +1,379 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Bar: critical lists and the ECT bit-exact; hybrid transforms within the gates
+of tests/gates.py; gradients within the same gates.  Inputs are seeded; sizes
+span several tiles with ragged tails, plus the degenerate cases.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2405_02256_amd import workloads as W
+
+from gates import fp32_gate, fp64_gate, term_scales
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_02256_amd import api as A
+    return A
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev())
+
+
+def _oracle_lists(img, construction):
+    lw, od = O.critical_values(img, construction)
+    n = img.ndim
+    V = list(reversed(O.vertex_shape(img, construction)))
+    ks = np.array(np.meshgrid(*[np.arange(v) for v in V], indexing="ij")).reshape(n, -1).T
+    ks = ks[np.lexsort(ks.T)]
+    out = []
+    for e in range(1 << n):
+        nz = np.nonzero(lw[:, e])[0]
+        out.append(("c", e, ks[nz], lw[nz, e]))
+    for e in range(1 << (n - 1)):
+        nz = np.nonzero(od[:, e])[0]
+        out.append(("o", e, ks[nz], od[nz, e]))
+    return out
+
+
+def _check_lists(plan, imgs, construction):
+    for i, img in enumerate(imgs):
+        for kind, e, ks, vals in _oracle_lists(img, construction):
+            coords, v = plan.export(i, 0 if kind == "c" else 1, e)
+            assert coords.shape[0] == ks.shape[0], (i, kind, e)
+            assert np.array_equal(coords, ks), (i, kind, e)
+            assert np.array_equal(v, vals), (i, kind, e)
+
+
+# ---------------------------------------------------------------------------
+# a1-a3: classification and ordered compaction
+# ---------------------------------------------------------------------------
+
+def test_running_example_table2(api):
+    img = W.RUNNING_EXAMPLE
+    plan = api.Plan(T(img), construction=1)
+    _check_lists(plan, [img], O.DUAL)
+    assert plan.check() == 0
+
+
+@pytest.mark.parametrize("construction", [O.PRIMAL, O.DUAL])
+def test_lists_random_2d_3d_ragged_batch(api, construction):
+    rng = np.random.default_rng(101)
+    shapes2 = [(1, 1), (1, 7), (5, 3), (33, 70), (64, 64), (40, 129)]
+    imgs = [W.random_image(rng, s, 4) for s in shapes2]
+    plan = api.Plan([T(im) for im in imgs], construction=construction)
+    _check_lists(plan, imgs, construction)
+    shapes3 = [(1, 1, 1), (3, 4, 5), (17, 9, 30), (2, 33, 16)]
+    imgs3 = [W.random_image(rng, s, 3) for s in shapes3]
+    plan3 = api.Plan([T(im) for im in imgs3], construction=construction)
+    _check_lists(plan3, imgs3, construction)
+
+
+def test_lists_exhaustive_binary_3x3_and_2x2x2(api):
+    imgs = list(W.all_binary_images((3, 3)))
+    plan = api.Plan([T(im) for im in imgs], construction=O.PRIMAL)
+    _check_lists(plan, imgs, O.PRIMAL)
+    imgs3 = list(W.all_binary_images((2, 2, 2)))
+    for cons in (O.PRIMAL, O.DUAL):
+        plan = api.Plan([T(im) for im in imgs3], construction=cons)
+        _check_lists(plan, imgs3, cons)
+
+
+def test_lists_small_binary_and_int_dtypes(api):
+    w = W.small_binary(1)
+    img = w.images[0]
+    plan = api.Plan(T(img))
+    _check_lists(plan, [img], O.PRIMAL)
+    rng = np.random.default_rng(7)
+    big = rng.integers(-300, 300, size=(37, 41)).astype(np.int16)
+    plan16 = api.Plan(T(big))
+    _check_lists(plan16, [big.astype(np.int32)], O.PRIMAL)
+    big32 = rng.integers(-100000, 100000, size=(12, 9, 10)).astype(np.int32)
+    plan32 = api.Plan(T(big32), construction=O.DUAL)
+    _check_lists(plan32, [big32], O.DUAL)
+
+
+def test_list_counts_and_invariants_grf(api):
+    w = W.grf_512(2, n_xi=8)
+    img = w.images[0]
+    plan = api.Plan(T(img))
+    c, o = plan.counts()
+    lw, od = O.critical_values(img, O.PRIMAL)
+    assert c[0].tolist() == [int(np.count_nonzero(lw[:, e])) for e in range(4)]
+    assert o[0].tolist() == [int(np.count_nonzero(od[:, e])) for e in range(2)]
+    chi = O.euler_characteristic(img, O.PRIMAL)
+    for e in range(4):
+        _, v = plan.export(0, 0, e)
+        assert v.sum() == chi
+    for e in range(2):
+        _, v = plan.export(0, 1, e)
+        assert v.sum() == 0
+
+
+# ---------------------------------------------------------------------------
+# a4-a5: ECT, bit-exact
+# ---------------------------------------------------------------------------
+
+def test_ect_running_example_paper_values(api):
+    img = W.RUNNING_EXAMPLE
+    plan = api.Plan(T(img), construction=O.DUAL, origin=[-0.5, -0.5], spacing=[1 / 3, 1 / 3])
+    out = plan.ect(T(np.array([[2.0, 2.0]])), T(np.array([-2.0, -1.0, 0.0, 1.0, 2.0])))
+    assert out.cpu().numpy()[0].tolist() == [1, 1, 2, 2, 2]
+
+
+def test_ect_small_binary_full(api):
+    w = W.small_binary(1)
+    img = w.images[0]
+    plan = api.Plan(T(img))
+    got = plan.ect(T(w.ect_dirs), T(w.ect_thresholds)).cpu().numpy()
+    assert np.array_equal(got, O.ect(img, w.ect_dirs, w.ect_thresholds))
+
+
+@pytest.mark.parametrize("construction", [O.PRIMAL, O.DUAL])
+def test_ect_random_with_axis_and_signed_zero_dirs(api, construction):
+    rng = np.random.default_rng(202)
+    for shape in [(20, 31), (9, 12, 7)]:
+        img = W.random_image(rng, shape, 5)
+        n = img.ndim
+        dirs = rng.standard_normal((37, n))
+        dirs[0] = 0.0
+        dirs[1, 0] = -0.0
+        dirs[2, :] = 0.0
+        dirs[2, 0] = 1.0
+        dirs[3, :] = -0.0
+        dirs[3, -1] = -1.0
+        R = float(np.linalg.norm(shape))
+        thr = np.sort(np.concatenate([rng.uniform(-R, R, 50), [0.0, 0.0, 0.5, -0.5]]))
+        plan = api.Plan(T(img), construction=construction)
+        got = plan.ect(T(dirs), T(thr)).cpu().numpy()
+        assert np.array_equal(got, O.ect(img, dirs, thr, construction))
+
+
+def test_ect_ragged_batch_per_image_thresholds_and_dirs(api):
+    rng = np.random.default_rng(303)
+    sides = [28, 64, 5, 128, 1, 64]
+    imgs = [W.binary_field(rng, (s, s), 3.0) if s > 4 else W.random_image(rng, (s, s), 2) for s in sides]
+    plan = api.Plan([T(im) for im in imgs])
+    M = 47
+    thr = np.stack([W.even_thresholds(s / np.sqrt(2), M) for s in sides])
+    counts = [5, 0, 17, 9, 3, 40]
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    dirs = rng.standard_normal((offs[-1], 2))
+    got = plan.ect(T(dirs), T(thr), offsets=T(offs)).cpu().numpy()
+    for i, im in enumerate(imgs):
+        ref = O.ect(im, dirs[offs[i]:offs[i + 1]], thr[i]) if counts[i] else np.zeros((0, M), np.int32)
+        assert np.array_equal(got[offs[i]:offs[i + 1]], ref), i
+    # shared set for every image
+    sd = W.circle_dirs(12)
+    got = plan.ect(T(sd), T(thr)).cpu().numpy().reshape(len(imgs), 12, M)
+    for i, im in enumerate(imgs):
+        assert np.array_equal(got[i], O.ect(im, sd, thr[i])), i
+
+
+def test_ect_grf512_full_config(api):
+    w = W.grf_512(2, n_xi=8)
+    img = w.images[0]
+    plan = api.Plan(T(img))
+    got = plan.ect(T(w.ect_dirs), T(w.ect_thresholds)).cpu().numpy()
+    sel = np.arange(0, 360, 9)
+    assert np.array_equal(got[sel], O.ect(img, w.ect_dirs[sel], w.ect_thresholds))
+
+
+def test_ect_large_threshold_count(api):
+    rng = np.random.default_rng(404)
+    img = W.random_image(rng, (30, 30), 3)
+    thr = np.linspace(-25, 25, 4096)
+    dirs = rng.standard_normal((10, 2))
+    plan = api.Plan(T(img))
+    got = plan.ect(T(dirs), T(thr)).cpu().numpy()
+    assert np.array_equal(got, O.ect(img, dirs, thr))
+
+
+def test_ect_unsorted_thresholds_flag(api):
+    img = W.small_binary(1).images[0]
+    plan = api.Plan(T(img))
+    thr = np.array([0.0, 1.0, 0.5, 2.0])
+    out = plan.ect(T(W.circle_dirs(4)), T(thr)).cpu().numpy()
+    assert (out == 0).all()
+    assert plan.check() & 0x2
+    assert plan.check() == 0
+
+
+# ---------------------------------------------------------------------------
+# a6: hybrid transforms
+# ---------------------------------------------------------------------------
+
+def _cplx(y, kernel):
+    y = np.asarray(y)
+    return y[:, 0] + 1j * y[:, 1] if kernel == "fourier" else y
+
+
+@pytest.mark.parametrize("kernel", ["fourier", "laplace", "bessel"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_hybrid_small_binary(api, kernel, precision):
+    w = W.small_binary(1)
+    img = w.images[0]
+    plan = api.Plan(T(img))
+    y = _cplx(plan.hybrid(T(w.hybrid_xi), kernel, 1.0, precision).cpu().numpy(), kernel)
+    ref = O.hybrid(img, w.hybrid_xi, kernel, 1.0)
+    S1, S2 = term_scales(img, w.hybrid_xi, kernel, 1.0)
+    if precision == "fp32":
+        ok, ratio, norm, strict = fp32_gate(y, ref, S2)
+        assert ok, (ratio, norm, strict)
+    else:
+        ok, ratio = fp64_gate(y, ref, S1)
+        assert ok, ratio
+
+
+@pytest.mark.parametrize("kernel", ["fourier", "laplace", "bessel"])
+def test_hybrid_grf512_sampled(api, kernel):
+    w = W.grf_512(2)
+    img = w.images[0]
+    plan = api.Plan(T(img))
+    y = _cplx(plan.hybrid(T(w.hybrid_xi), kernel, 1.0, "fp32").cpu().numpy(), kernel)
+    sel = np.random.default_rng(9).choice(len(w.hybrid_xi), 48, replace=False)
+    ref = O.hybrid(img, w.hybrid_xi[sel], kernel, 1.0, with_shift=False)
+    S1, S2 = term_scales(img, w.hybrid_xi[sel], kernel, 1.0)
+    ok, ratio, norm, strict = fp32_gate(y[sel], ref, S2)
+    assert ok, (ratio, norm, strict)
+
+
+@pytest.mark.parametrize("construction", [O.PRIMAL, O.DUAL])
+@pytest.mark.parametrize("kernel", ["fourier", "laplace", "bessel"])
+def test_hybrid_3d_and_dual(api, kernel, construction):
+    rng = np.random.default_rng(505)
+    img = W.quantised_volume(rng, 20, 2.0)
+    xi = W.sphere_vectors(rng, 100, 0.01, 2.0)
+    plan = api.Plan(T(img), construction=construction, origin=[0.0, 0.0, 0.0])
+    org = np.zeros(3)
+    for precision in ("fp32", "fp64"):
+        y = _cplx(plan.hybrid(T(xi), kernel, 0.8, precision).cpu().numpy(), kernel)
+        ref = O.hybrid(img, xi, kernel, 0.8, construction, origin=org)
+        S1, S2 = term_scales(img, xi, kernel, 0.8, construction, origin=org)
+        if precision == "fp32":
+            ok, ratio, norm, strict = fp32_gate(y, ref, S2)
+            assert ok, (precision, ratio, norm, strict)
+        else:
+            ok, ratio = fp64_gate(y, ref, S1)
+            assert ok, (precision, ratio)
+
+
+def test_laplace_log_scale_large_phases(api):
+    rng = np.random.default_rng(606)
+    img = W.quantised_volume(rng, 24, 2.0)
+    xi = W.sphere_vectors(rng, 64, 0.5, 20.0)    # phases up to ~800: exp overflows FP64 unshifted
+    plan = api.Plan(T(img), origin=[0.0, 0.0, 0.0])
+    out, ls = plan.hybrid(T(xi), "laplace", 1.0, "fp32", log_scale=True)
+    out, ls = out.cpu().numpy(), ls.cpu().numpy()
+    ref, m = O.hybrid(img, xi, "laplace", 1.0, origin=np.zeros(3), with_shift=True)
+    y = out * np.exp(ls - m)
+    S1, S2 = term_scales(img, xi, "laplace", 1.0, origin=np.zeros(3), shift=m)
+    ok, ratio, norm, strict = fp32_gate(y, ref, S2)
+    assert ok, (ratio, norm, strict)
+
+
+def test_hybrid_ragged_batch_and_signs(api):
+    rng = np.random.default_rng(707)
+    sides = [28, 64, 1, 100]
+    imgs = [W.binary_field(rng, (s, s), 4.0) if s > 1 else np.ones((1, 1), np.uint8) for s in sides]
+    plan = api.Plan([T(im) for im in imgs])
+    counts = [70, 3, 5, 130]
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    xi = W.polar_vectors(rng, int(offs[-1]), 0.01, 1.0)
+    xi[0] = [0.3, 0.0]
+    xi[1] = [-0.0, -0.2]
+    for kernel in ("fourier", "laplace"):
+        y = _cplx(plan.hybrid(T(xi), kernel, 1.0, "fp32", offsets=T(offs)).cpu().numpy(), kernel)
+        for i, im in enumerate(imgs):
+            sl = slice(offs[i], offs[i + 1])
+            ref = O.hybrid(im, xi[sl], kernel, 1.0)
+            S1, S2 = term_scales(im, xi[sl], kernel, 1.0)
+            ok, ratio, norm, strict = fp32_gate(y[sl], ref, S2)
+            assert ok, (kernel, i, ratio, norm)
+
+
+def test_hybrid_deterministic(api):
+    w = W.grf_512(2, n_xi=1024)
+    plan = api.Plan(T(w.images[0]))
+    for kernel in ("fourier", "laplace", "bessel"):
+        a = plan.hybrid(T(w.hybrid_xi), kernel, 1.0, "fp32").cpu().numpy()
+        b = plan.hybrid(T(w.hybrid_xi), kernel, 1.0, "fp32").cpu().numpy()
+        assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
+def test_empty_lists_and_tiny(api):
+    z = np.zeros((16, 16), np.uint8)
+    plan = api.Plan(T(z))
+    c, o = plan.counts()
+    assert c.sum() == 0 and o.sum() == 0
+    xi = W.circle_dirs(70) * 0.5
+    y = plan.hybrid(T(xi), "fourier", 1.0).cpu().numpy()
+    assert (y == 0).all()
+    e = plan.ect(T(xi), T(np.linspace(-5, 5, 9))).cpu().numpy()
+    assert (e == 0).all()
+
+
+# ---------------------------------------------------------------------------
+# a7: backward
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kernel", ["fourier", "laplace", "bessel"])
+def test_backward_against_oracle_gradient(api, kernel):
+    rng = np.random.default_rng(808)
+    imgs = [W.binary_field(rng, (48, 48), 3.0) for _ in range(3)]
+    plan = api.Plan([T(im) for im in imgs])
+    xi = W.polar_vectors(rng, 40, 0.01, 0.5, axis_gap=0.02)
+    y = plan.hybrid(T(xi), kernel, 1.0, "fp32")
+    g = rng.standard_normal(tuple(y.shape))
+    gxi, gs = plan.hybrid_backward(T(xi), y, T(g), kernel, 1.0, "fp32")
+    gxi, gs = gxi.cpu().numpy(), float(gs.cpu())
+    rows = g.reshape(len(imgs), 40, *g.shape[1:])
+    rgx = np.zeros((40, 2))
+    rgs = 0.0
+    for i, im in enumerate(imgs):
+        a, b = O.hybrid_grad(im, xi, kernel, 1.0, rows[i])
+        rgx += a
+        rgs += b
+    err = np.abs(gxi - rgx).max() / max(np.abs(rgx).max(), 1e-300)
+    assert err < 1e-5, err
+    assert abs(gs - rgs) <= 1e-5 * max(abs(rgs), np.abs(rgx).max()), (gs, rgs)
+
+
+def test_autograd_function_matches_finite_differences(api):
+    rng = np.random.default_rng(909)
+    imgs = [W.binary_field(rng, (32, 32), 3.0) for _ in range(2)]
+    plan = api.Plan([T(im) for im in imgs])
+    xi0 = W.polar_vectors(rng, 8, 0.05, 0.5, axis_gap=0.05)
+    xi = T(xi0).clone().requires_grad_(True)
+    s = torch.tensor(1.0, dtype=torch.float64, device=dev(), requires_grad=True)
+    y = api.HybridTransform.apply(xi, s, plan, "laplace", "fp64")
+    wts = T(rng.standard_normal(tuple(y.shape)))
+    (y * wts).sum().backward()
+    wnp = wts.cpu().numpy().reshape(2, 8)
+
+    def loss(xv, sv):
+        return sum(float((O.hybrid(im, xv, "laplace", sv) * wnp[i]).sum()) for i, im in enumerate(imgs))
+
+    h = 1e-3
+    for q in range(8):
+        for a in range(2):
+            xp, xm = xi0.copy(), xi0.copy()
+            xp[q, a] += h
+            xm[q, a] -= h
+            fd = (loss(xp, 1.0) - loss(xm, 1.0)) / (2 * h)
+            assert abs(fd - float(xi.grad[q, a])) <= 1e-2 * max(1.0, abs(fd))
+    fds = (loss(xi0, 1.0 + h) - loss(xi0, 1.0 - h)) / (2 * h)
+    assert abs(fds - float(s.grad)) <= 1e-2 * max(1.0, abs(fds))
