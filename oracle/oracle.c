@@ -307,6 +307,44 @@ int oracle_ect(int n, const int32_t* dims, const int32_t* px, int construction,
     return err;
 }
 
+
+/* ---- compensated accumulation ----
+ * The cell form sums, per cell, kbar at its top vertex minus kbar at its
+ * bottom vertex.  At a vertex that is not critical these contributions cancel
+ * exactly in exact arithmetic, but in plain FP64 they leave rounding residues
+ * of the size of the largest term, which can exceed the value of the
+ * transform itself (Laplace kernel at large phases).  Every product is split
+ * with TwoProduct (fma) and every addition with TwoSum (Knuth), so that the
+ * sum is evaluated as in doubled precision (Ogita, Rump, Oishi, "Accurate sum
+ * and dot product", SIAM J. Sci. Comput. 2005, algorithms Sum2 / Dot2). */
+typedef struct { double hi, lo; } csum;
+
+static void csum_add(csum* a, double x) {
+    double t = a->hi + x;
+    double bp = t - a->hi;
+    double err = (a->hi - (t - bp)) + (x - bp);
+    a->hi = t;
+    a->lo += err;
+}
+
+/* a += w * v with w an integer weight (exactly representable) */
+static void csum_axpy(csum* a, double w, double v) {
+    double p = w * v;
+    double e = fma(w, v, -p);
+    csum_add(a, p);
+    csum_add(a, e);
+}
+
+/* a += w * x * v */
+static void csum_axpy3(csum* a, double w, double x, double v) {
+    double p = x * v;
+    double e = fma(x, v, -p);
+    csum_axpy(a, w, p);
+    csum_axpy(a, w, e);
+}
+
+static double csum_value(const csum* a) { return a->hi + a->lo; }
+
 /* ---- kernels ---- */
 
 /* Ji0(z) = integral_0^z J0(t) dt by composite 10-point Gauss-Legendre over unit
@@ -402,7 +440,7 @@ int oracle_hybrid(int n, const int32_t* dims, const int32_t* px, int constructio
                     else if (kernel == OR_LAPLACE) { kr[v] = -exp(-z - m) / s; ki[v] = 0.0; }
                     else { kr[v] = ji0_eval(&tb, z) / s; ki[v] = 0.0; }
                 }
-                double ar = 0.0, ai = 0.0;
+                csum ar = {0.0, 0.0}, ai = {0.0, 0.0};
                 for (long long i = 0; i < cs.count; ++i) {
                     long long top = cs.verts[i * 8], bot = top;
                     for (int q = 1; q < cs.nv[i]; ++q) {
@@ -411,11 +449,13 @@ int oracle_hybrid(int n, const int32_t* dims, const int32_t* px, int constructio
                         if (u[w] < u[bot]) bot = w;
                     }
                     double sg = (cs.dim[i] & 1) ? (double)cs.value[i] : -(double)cs.value[i];
-                    ar += sg * (kr[top] - kr[bot]);
-                    ai += sg * (ki[top] - ki[bot]);
+                    csum_axpy(&ar, sg, kr[top]);
+                    csum_axpy(&ar, -sg, kr[bot]);
+                    csum_axpy(&ai, sg, ki[top]);
+                    csum_axpy(&ai, -sg, ki[bot]);
                 }
-                if (kernel == OR_FOURIER) { out[2LL * qi] = ar; out[2LL * qi + 1] = ai; }
-                else out[qi] = ar;
+                if (kernel == OR_FOURIER) { out[2LL * qi] = csum_value(&ar); out[2LL * qi + 1] = csum_value(&ai); }
+                else out[qi] = csum_value(&ar);
                 if (shift) shift[qi] = m;
             }
         }
@@ -477,8 +517,8 @@ int oracle_hybrid_grad(int n, const int32_t* dims, const int32_t* px, int constr
                         kp[v] = gr * j0(z);
                     }
                 }
-                double acc[MAXD] = {0.0, 0.0, 0.0};
-                double du = 0.0, y = 0.0;
+                csum acc[MAXD] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+                csum du = {0.0, 0.0}, y = {0.0, 0.0};
                 for (long long i = 0; i < cs.count; ++i) {
                     long long top = cs.verts[i * 8], bot = top;
                     for (int q = 1; q < cs.nv[i]; ++q) {
@@ -487,13 +527,17 @@ int oracle_hybrid_grad(int n, const int32_t* dims, const int32_t* px, int constr
                         if (u[w] < u[bot]) bot = w;
                     }
                     double sg = (cs.dim[i] & 1) ? (double)cs.value[i] : -(double)cs.value[i];
-                    for (int a = 0; a < n; ++a)
-                        acc[a] += sg * (x[top * MAXD + a] * kp[top] - x[bot * MAXD + a] * kp[bot]);
-                    du += sg * (u[top] * kp[top] - u[bot] * kp[bot]);
-                    y += sg * (kb[top] - kb[bot]);
+                    for (int a = 0; a < n; ++a) {
+                        csum_axpy3(&acc[a], sg, x[top * MAXD + a], kp[top]);
+                        csum_axpy3(&acc[a], -sg, x[bot * MAXD + a], kp[bot]);
+                    }
+                    csum_axpy3(&du, sg, u[top], kp[top]);
+                    csum_axpy3(&du, -sg, u[bot], kp[bot]);
+                    csum_axpy(&y, sg, kb[top]);
+                    csum_axpy(&y, -sg, kb[bot]);
                 }
-                for (int a = 0; a < n; ++a) gxi[(long long)qi * n + a] = acc[a];
-                gs_part[qi] = (du - y) / s;
+                for (int a = 0; a < n; ++a) gxi[(long long)qi * n + a] = csum_value(&acc[a]);
+                gs_part[qi] = (csum_value(&du) - csum_value(&y)) / s;
             }
         }
         free(u); free(kb); free(kp); free(tb.cum);

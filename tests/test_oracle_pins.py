@@ -450,3 +450,25 @@ def test_gradient_matches_central_differences(kernel):
             assert abs(fd - gxi[q, a]) <= 1e-6 * max(1.0, abs(fd))
     fd_s = (loss(xi, s + h) - loss(xi, s - h)) / (2 * h)
     assert abs(fd_s - gs) <= 1e-6 * max(1.0, abs(fd_s))
+
+
+def test_lemma31_laplace_large_phases_cancellation():
+    """At phases ~10^3 every critical point can sit far below the maximal vertex; the cell
+    form must still equal the critical-point sum (here summed with correctly rounded fsum)."""
+    rng = np.random.default_rng(606)
+    img = W.quantised_volume(rng, 16, 2.0)
+    xi = W.sphere_vectors(rng, 24, 0.5, 20.0)
+    org = np.zeros(3)
+    out, m = O.hybrid(img, xi, "laplace", 1.0, origin=org, with_shift=True)
+    _, od = O.critical_values(img, O.PRIMAL)
+    x = _vertex_coords(img, O.PRIMAL, org)
+    for q in range(len(xi)):
+        D = od[:, _sign_index(xi[q])]
+        nz = np.nonzero(D)[0]
+        u = x[nz] @ xi[q]
+        terms = [-float(d) * math.exp(-uu - m[q]) for d, uu in zip(D[nz], u)]
+        ref = math.fsum(terms)
+        scale = math.fsum(abs(t) for t in terms)
+        # Sum2 bound: a relative 1e-12 of the critical-point terms plus a doubled-precision
+        # residue (~2^-106) of the O(1) cell terms that cancel at non-critical vertices
+        assert abs(out[q] - ref) <= 1e-12 * scale + 1e-28, (q, out[q], ref, scale)
