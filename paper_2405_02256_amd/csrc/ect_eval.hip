@@ -57,12 +57,13 @@ __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
         int ok = 0;
         int64_t row = -1;
         if (tid < nd) {
-            int64_t code = a.perm[a.bstart[bidx] + q0 + tid];
-            row = row_base + (code >> 1);
+            const int64_t rel = a.perm[a.bstart[bidx] + q0 + tid] >> 1;
+            row = row_base + rel;                         // output row
+            const int64_t vrow = shared_q ? rel : row;    // row of the direction vector
             ok = 1;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                double v = c < N ? a.vecs[row * N + c] : 0.0;
+                double v = c < N ? a.vecs[vrow * N + c] : 0.0;
                 s_xi[tid][c] = v;
                 ok &= isfinite(v) ? 1 : 0;
             }

@@ -50,9 +50,10 @@ __device__ __forceinline__ float ji0_f32(double z) {
     const double az = fabs(z);
     float r;
     if (az < JI0_Z0) {
-        const float zf = (float)az;
-        const float v = zf * zf * (float)(1.0 / (JI0_Z0 * JI0_Z0));
-        r = zf * horner<JI0_F32_SMALL_DEG + 1, float>(JI0_F32_SMALL, v);
+        // the monomial coefficients alternate in sign up to ~16 in size, so the
+        // polynomial is evaluated in FP64 (same issue rate as FP32 on this chip)
+        const double v = az * az * (1.0 / (JI0_Z0 * JI0_Z0));
+        r = (float)(az * horner<JI0_F32_SMALL_DEG + 1, double>(JI0_F32_SMALL, v));
     } else {
         const float zf = (float)az;
         const float rz = __builtin_amdgcn_rcpf(zf);
@@ -208,10 +209,11 @@ __global__ void __launch_bounds__(kHybridLanes) hybrid_kernel(HybridArgs a) {
     const double s = a.s;
     if (active) {
         const int64_t code = a.perm[a.bstart[bidx] + qi];
-        row = row_base + (code >> 1);
+        row = row_base + (code >> 1);                       // output row
+        const int64_t vrow = shared_q ? (code >> 1) : row;  // row of the query vector
         q.sigma = (code & 1) ? -1.0 : 1.0;
 #pragma unroll
-        for (int k = 0; k < N; ++k) q.xi[k] = a.vecs[row * N + k];
+        for (int k = 0; k < N; ++k) q.xi[k] = a.vecs[vrow * N + k];
     } else {
 #pragma unroll
         for (int k = 0; k < N; ++k) q.xi[k] = 0.0;
