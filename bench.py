@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""Throughput of the whole hot path on one MI355X.
+
+Workload (synthetic, seeded): one 512x512 binary image, a Gaussian random field
+(sigma 8 px) thresholded at its median; ECT at 360 directions x 256 thresholds;
+Euler-Fourier, Euler-Laplace and Euler-Bessel transforms at 4096 vectors xi
+with |xi| ~ U[0.01, 1] and uniform angle; one Euler-Fourier backward pass.
+
+One step = one pass of every stage on that batch: per-vertex classification
+and ordered compaction, sign-vector bucketing, the exact ECT, the three
+hybrid transforms (FP32 kernel values, FP64 phases and accumulation) and the
+backward pass, replayed as one HIP graph.  value = (query, critical point)
+hybrid evaluations (three forward kernels + the backward) per second of step
+time.  Inputs are resident in HBM before the timed region.
+
+Roofline: the dominant kernel's average duration comes from HIP events that
+the library records around that kernel alone (ect_set_stage_events), over K
+profiled eager steps that follow the timed graph replays.  The CPU baseline
+times the FP64 oracle on a bounded sample of the same step on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ξ·crit-pt evals/s (hybrid), ECT dirs/s; batched FP32 vs plain FP64 @1e-5"
+KERNELS = ("fourier", "laplace", "bessel")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-graph", action="store_true", help="time eager steps instead of graph replays")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")
+    ap.add_argument("--cpu-budget", type=float, default=1.0, help="scale of the oracle sample")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_digest(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2405_02256_amd import _native as N
+    from paper_2405_02256_amd import api, hipevents, pipeline, roofline
+    from paper_2405_02256_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    w = W.grf_512(2)
+    img = w.images[0]
+    rng = np.random.default_rng(12)
+    gout = rng.standard_normal((len(w.hybrid_xi), 2))
+    img_t = torch.from_numpy(img).to(dev)
+    dirs = torch.from_numpy(w.ect_dirs).to(dev)
+    thr = torch.from_numpy(w.ect_thresholds).to(dev)
+    xi = torch.from_numpy(w.hybrid_xi).to(dev)
+    g_t = torch.from_numpy(gout).to(dev)
+    log("building plan")
+    plan = api.Plan(img_t)
+    step = pipeline.Step(plan, dirs, thr, xi, kernels=KERNELS, s=1.0, precision="fp32",
+                         backward_kernel="fourier", grad_out=g_t)
+
+    # work per step: sum over xi of the ordinary list length of its orthant pair
+    n = 2
+    lists = [plan.export(0, 1, b)[0] for b in range(2)]
+    counts = np.array([len(L) for L in lists])
+    e = ((w.hybrid_xi[:, 0] < 0) * 1 + (w.hybrid_xi[:, 1] < 0) * 2)
+    pair = np.where(e >= 2, e ^ 3, e)
+    per_kernel_pairs = float(counts[pair].sum())
+    evals_per_step = per_kernel_pairs * (len(KERNELS) + 1)
+    cls_counts, _ = plan.counts()
+    ect_pairs = float(sum(cls_counts[0][((d[0] < 0) * 1 + (d[1] < 0) * 2)] for d in w.ect_dirs))
+    # fraction of Bessel pairs on the small-argument branch
+    x_of = [(L.astype(np.float64) - 256.0) for L in lists]
+    small = 0.0
+    for b in range(2):
+        sel = w.hybrid_xi[pair == b]
+        if len(sel):
+            z = np.abs(sel @ x_of[b].T)
+            small += float((z < 8.0).sum())
+    small_frac = small / max(per_kernel_pairs, 1.0)
+
+    log("warm-up and graph capture")
+    step.run()
+    torch.cuda.synchronize()
+    use_graph = not args.no_graph
+    if use_graph:
+        step.capture()
+        run = step.replay
+    else:
+        run = step.run
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    if plan.check() != 0:
+        raise RuntimeError("device error flags set during warm-up")
+
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = (t1 - t0) / args.steps
+    value = evals_per_step / sec
+    log(f"{sec * 1e3:.4f} ms/step, {value:.4e} evals/s")
+
+    # ---- live per-stage kernel timing (library-recorded HIP events) ----
+    st = int(torch.cuda.current_stream().cuda_stream)
+    names = ["precompute", "ect"] + [f"hybrid_{k}" for k in KERNELS] + ["hybrid_bwd_fourier"]
+    evs = {nm: [(hipevents.Event(), hipevents.Event()) for _ in range(args.steps)] for nm in names}
+
+    def arm(stage, pair_):
+        N.check(N.ect_set_stage_events(stage, pair_[0].handle, pair_[1].handle), "stage events")
+
+    for i in range(args.steps):
+        arm(N.STAGE_PRECOMPUTE, evs["precompute"][i])
+        plan.rerun()
+        arm(N.STAGE_ECT, evs["ect"][i])
+        plan.ect(step.ect_q, step.ect_thr, out=step.ect_out)
+        for k in KERNELS:
+            arm(N.STAGE_HYBRID, evs[f"hybrid_{k}"][i])
+            plan.hybrid(step.hy_q, k, 1.0, "fp32", out=step.hy_out[k])
+        arm(N.STAGE_HYBRID_BWD, evs["hybrid_bwd_fourier"][i])
+        plan.hybrid_backward(step.hy_q, step.hy_out["fourier"], step.grad_out, "fourier", 1.0, "fp32",
+                             grad_xi=step.grad_xi, grad_s=step.grad_s)
+    torch.cuda.synchronize()
+    for stg in range(4):
+        N.ect_set_stage_events(stg, None, None)
+    stage_ms = {nm: float(np.mean([a.elapsed_ms(b) for a, b in evs[nm]])) for nm in names}
+    log("stage kernel ms: " + ", ".join(f"{k}={v:.4f}" for k, v in stage_ms.items()))
+    dom = max(stage_ms, key=stage_ms.get)
+    dsec = stage_ms[dom] * 1e-3
+    if dom == "precompute":
+        nbytes = img.size + 32.0 * float(cls_counts.sum() + counts.sum()) + 8 * 2 * 6
+        roof = roofline.hbm_roofline(nbytes, dsec)
+    elif dom == "ect":
+        roof = roofline.alu_roofline("ect", n, ect_pairs, dsec)
+    elif dom == "hybrid_bwd_fourier":
+        roof = roofline.alu_roofline("fourier_bwd", n, per_kernel_pairs, dsec)
+    else:
+        kind = dom.split("_", 1)[1]
+        roof = roofline.alu_roofline(kind, n, per_kernel_pairs, dsec, small_frac)
+    roof["kernel"] = dom
+    roof["kernel_ms"] = stage_ms[dom]
+    roof["traffic"] = None
+    # HBM traffic of the dominant kernel from committed rocprofv3 counter runs, if taken on this source
+    src_hash = source_digest(sorted(os.path.join(ROOT, "paper_2405_02256_amd", "csrc", f)
+                                    for f in os.listdir(os.path.join(ROOT, "paper_2405_02256_amd", "csrc"))))
+    tpath = os.path.join(ROOT, "profiles", "traffic_grf_512.json")
+    if os.path.exists(tpath):
+        try:
+            tr = json.load(open(tpath))
+            if tr.get("source_digest") == src_hash and dom in tr.get("bytes_per_launch", {}):
+                roof["traffic"] = tr["bytes_per_launch"][dom]
+        except (OSError, ValueError):
+            pass
+
+    # ---- FP64 path on the same step, for the FP32-vs-FP64 comparison ----
+    fp64 = None
+    if not args.no_fp64:
+        step64 = pipeline.Step(plan, dirs, thr, xi, kernels=KERNELS, s=1.0, precision="fp64",
+                               backward_kernel="fourier", grad_out=g_t)
+        step64.run()
+        torch.cuda.synchronize()
+        reps = max(3, args.steps // 5)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step64.run()
+        torch.cuda.synchronize()
+        fp64 = (time.perf_counter() - t0) / reps
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample of the same step ----
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        b = args.cpu_budget
+        samp = {"ect": max(4, int(72 * b)), "fourier": max(8, int(256 * b)), "laplace": max(8, int(256 * b)),
+                "bessel": max(4, int(32 * b)), "grad": max(8, int(128 * b))}
+        full = {"ect": len(w.ect_dirs), "fourier": len(w.hybrid_xi), "laplace": len(w.hybrid_xi),
+                "bessel": len(w.hybrid_xi), "grad": len(w.hybrid_xi)}
+        tcpu = {}
+        sel_d = np.linspace(0, len(w.ect_dirs) - 1, samp["ect"]).astype(int)
+        t0 = time.perf_counter()
+        O.ect(img, w.ect_dirs[sel_d], w.ect_thresholds)
+        tcpu["ect"] = time.perf_counter() - t0
+        for k in KERNELS:
+            sel = np.linspace(0, len(w.hybrid_xi) - 1, samp[k]).astype(int)
+            t0 = time.perf_counter()
+            O.hybrid(img, w.hybrid_xi[sel], k, 1.0)
+            tcpu[k] = time.perf_counter() - t0
+        sel = np.linspace(0, len(w.hybrid_xi) - 1, samp["grad"]).astype(int)
+        t0 = time.perf_counter()
+        O.hybrid_grad(img, w.hybrid_xi[sel], "fourier", 1.0, gout[sel])
+        tcpu["grad"] = time.perf_counter() - t0
+        t_step = sum(tcpu[k] * full[k] / samp[k] for k in tcpu)
+        cpu = {"value": evals_per_step / t_step, "unit": "ξ·crit-pt evals/s", "cores": O.max_threads(),
+               "kind": "oracle",
+               "sample": (f"FP64 oracle (cell forms over all cells) on {samp['ect']} of 360 ECT directions, "
+                          f"{samp['fourier']}/{samp['laplace']}/{samp['bessel']} of 4096 xi for "
+                          f"Fourier/Laplace/Bessel and {samp['grad']} xi of the Fourier gradient; "
+                          f"{sum(tcpu.values()):.1f} s of wall time scaled to one full step "
+                          f"({t_step:.1f} s)")}
+
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "ξ·crit-pt evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "grf_512: 512x512 binary Gaussian random field (sigma 8 px, median "
+                               "threshold), primal cubical complex; ECT 360 dirs x 256 thresholds; "
+                               "Euler-Fourier/Laplace/Bessel at 4096 xi, |xi|~U[0.01,1]; Fourier backward",
+                   "graph": use_graph, "precision": "FP32 kernel values, FP64 phases and accumulation"},
+        "ect_dirs_per_s": len(w.ect_dirs) / sec,
+        "evals_per_step": evals_per_step,
+        "stage_kernel_ms": stage_ms,
+        "bessel_small_branch_fraction": small_frac,
+        "roofline": roof,
+        "fp64_path_ms_per_step": None if fp64 is None else fp64 * 1e3,
+        "fp32_vs_fp64_speedup": None if fp64 is None else fp64 / sec,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -218,6 +218,17 @@ ect_status ect_plan_destroy(ect_plan plan);
  * chunked sums (hybrid), and identical for identical settings. */
 ect_status ect_set_tuning(int64_t hybrid_chunk, int64_t hybrid_target_items, int32_t ect_dirs_per_group);
 
+/* Profiling hook (process-wide): when set, the library records `before` on
+ * the call's stream right before it launches the main kernel of `stage` and
+ * `after` right after it, so that hipEventElapsedTime measures that kernel
+ * alone (the small bucketing and work-list kernels of the call fall outside).
+ * stage: ECT_STAGE_*.  Pass NULL events to disable.  Not thread-safe. */
+#define ECT_STAGE_PRECOMPUTE   0
+#define ECT_STAGE_ECT          1
+#define ECT_STAGE_HYBRID       2
+#define ECT_STAGE_HYBRID_BWD   3
+ect_status ect_set_stage_events(int32_t stage, hipEvent_t before, hipEvent_t after);
+
 /* Static description of a status code. */
 const char* ect_status_string(ect_status status);
 

@@ -176,7 +176,7 @@ class Plan:
         return out
 
     def hybrid(self, xi, kernel: str = "fourier", s: float = 1.0, precision: str = "fp32", offsets=None,
-               log_scale: bool = False, out=None, stream=None):
+               log_scale: bool = False, out=None, stream=None, log_scale_out=None):
         """float64 [rows] (Fourier: [rows][2]); with log_scale (Laplace) returns (out, log_scale)."""
         q = xi if isinstance(xi, QuerySet) else QuerySet(xi, offsets)
         q.validate(self.num_images, self.ndim)
@@ -184,7 +184,10 @@ class Plan:
         rows = q.rows(self.num_images)
         if out is None:
             out = torch.empty((rows, 2) if k == N.FOURIER else (rows,), dtype=torch.float64, device=self.device)
-        ls = torch.empty(rows, dtype=torch.float64, device=self.device) if log_scale else None
+        if log_scale_out is not None:
+            log_scale = True
+        ls = log_scale_out if log_scale_out is not None else (
+            torch.empty(rows, dtype=torch.float64, device=self.device) if log_scale else None)
         st = _stream(stream)
         need = ctypes.c_size_t(0)
         N.check(N.hybrid_eval(self.handle, k, s, N.PRECISIONS[precision], q.c(), _dptr(out), _dptr(ls), None,
@@ -196,7 +199,7 @@ class Plan:
         return (out, ls) if log_scale else out
 
     def hybrid_backward(self, xi, out: torch.Tensor, grad_out: torch.Tensor, kernel: str = "fourier", s: float = 1.0,
-                        precision: str = "fp32", offsets=None, stream=None):
+                        precision: str = "fp32", offsets=None, stream=None, grad_xi=None, grad_s=None):
         """(grad_xi, grad_s): VJP of hybrid() (shared sets sum grad_xi over images)."""
         q = xi if isinstance(xi, QuerySet) else QuerySet(xi, offsets)
         q.validate(self.num_images, self.ndim)
@@ -204,8 +207,9 @@ class Plan:
         rows = q.rows(self.num_images)
         if out.shape[0] != rows or grad_out.shape != out.shape:
             raise ValueError("out and grad_out must have the forward output's shape")
-        gxi = torch.empty((q.vecs.shape[0], self.ndim), dtype=torch.float64, device=self.device)
-        gs = torch.empty((), dtype=torch.float64, device=self.device)
+        gxi = grad_xi if grad_xi is not None else torch.empty((q.vecs.shape[0], self.ndim), dtype=torch.float64,
+                                                              device=self.device)
+        gs = grad_s if grad_s is not None else torch.empty((), dtype=torch.float64, device=self.device)
         out = out.to(torch.float64).contiguous()
         go = grad_out.to(torch.float64).contiguous()
         st = _stream(stream)

@@ -11,6 +11,10 @@
 
 using namespace ect;
 
+namespace ect {
+StageEvents g_stage_events[4];
+}
+
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -478,6 +482,13 @@ ect_status ect_set_tuning(int64_t hybrid_chunk, int64_t hybrid_target_items, int
     g_tuning.hybrid_chunk = hybrid_chunk;
     g_tuning.hybrid_target_items = hybrid_target_items;
     g_tuning.ect_dirs_per_group = ect_dirs_per_group;
+    return ECT_OK;
+}
+
+ect_status ect_set_stage_events(int32_t stage, hipEvent_t before, hipEvent_t after) {
+    if (stage < 0 || stage > 3) return ECT_E_INVALID;
+    g_stage_events[stage].before = before;
+    g_stage_events[stage].after = after;
     return ECT_OK;
 }
 

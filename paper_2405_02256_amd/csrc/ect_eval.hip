@@ -144,11 +144,15 @@ __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
 hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, hipStream_t stream) {
     if (grid <= 0) return hipSuccess;
     size_t shmem = sizeof(double) * a.M + sizeof(int32_t) * a.dirs_per_group * a.M;
+    hipError_t e = stage_mark(ECT_STAGE_ECT, false, stream);
+    if (e != hipSuccess) return e;
     if (ndim == 2)
         hipLaunchKernelGGL(ect_kernel<2>, dim3((unsigned)grid), dim3(kEctThreads), shmem, stream, a);
     else
         hipLaunchKernelGGL(ect_kernel<3>, dim3((unsigned)grid), dim3(kEctThreads), shmem, stream, a);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return stage_mark(ECT_STAGE_ECT, true, stream);
 }
 
 }  // namespace ect

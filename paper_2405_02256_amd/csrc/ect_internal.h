@@ -99,6 +99,16 @@ __device__ __forceinline__ double project(const double* xi, const double* x) {
     return u;
 }
 
+// Optional profiling events around the main kernel of each stage.
+struct StageEvents {
+    hipEvent_t before = nullptr, after = nullptr;
+};
+extern StageEvents g_stage_events[4];
+inline hipError_t stage_mark(int stage, bool after, hipStream_t s) {
+    hipEvent_t e = after ? g_stage_events[stage].after : g_stage_events[stage].before;
+    return e ? hipEventRecord(e, s) : hipSuccess;
+}
+
 // Kernel launch helpers (host side, defined in the .hip files).
 hipError_t launch_precompute(const Plan& p, hipStream_t stream);
 

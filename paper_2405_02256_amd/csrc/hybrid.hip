@@ -370,15 +370,23 @@ hipError_t launch_n(int kernel, int precision, const HybridArgs& a, int64_t grid
 hipError_t launch_hybrid_fwd(int ndim, int kernel, int precision, const HybridArgs& a, int64_t grid,
                              hipStream_t stream) {
     if (grid <= 0) return hipSuccess;
-    return ndim == 2 ? launch_n<2, false>(kernel, precision, a, grid, stream)
-                     : launch_n<3, false>(kernel, precision, a, grid, stream);
+    hipError_t e = stage_mark(ECT_STAGE_HYBRID, false, stream);
+    if (e != hipSuccess) return e;
+    e = ndim == 2 ? launch_n<2, false>(kernel, precision, a, grid, stream)
+                  : launch_n<3, false>(kernel, precision, a, grid, stream);
+    if (e != hipSuccess) return e;
+    return stage_mark(ECT_STAGE_HYBRID, true, stream);
 }
 
 hipError_t launch_hybrid_bwd(int ndim, int kernel, int precision, const HybridArgs& a, int64_t grid,
                              hipStream_t stream) {
     if (grid <= 0) return hipSuccess;
-    return ndim == 2 ? launch_n<2, true>(kernel, precision, a, grid, stream)
-                     : launch_n<3, true>(kernel, precision, a, grid, stream);
+    hipError_t e = stage_mark(ECT_STAGE_HYBRID_BWD, false, stream);
+    if (e != hipSuccess) return e;
+    e = ndim == 2 ? launch_n<2, true>(kernel, precision, a, grid, stream)
+                  : launch_n<3, true>(kernel, precision, a, grid, stream);
+    if (e != hipSuccess) return e;
+    return stage_mark(ECT_STAGE_HYBRID_BWD, true, stream);
 }
 
 hipError_t launch_grad_reduce(int ndim, const double* part, int num_images, int64_t count, bool shared,

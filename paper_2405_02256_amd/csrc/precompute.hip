@@ -55,7 +55,7 @@ __device__ __forceinline__ constexpr int star_index(const int* sigma) {
 
 template <typename T>
 __device__ __forceinline__ int32_t px_load(const T* __restrict__ img, int64_t i) {
-    return (int32_t)__builtin_nontemporal_load(img + i);
+    return (int32_t)img[i];
 }
 
 // Critical values of one vertex: L[e] for the 2^N sign vectors, D[e] for the
@@ -317,11 +317,15 @@ hipError_t launch_typed(const Plan& p, hipStream_t stream) {
     hipLaunchKernelGGL(reset_kernel, dim3(rblocks), dim3(256), 0, stream, err, status, nstatus);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    e = stage_mark(ECT_STAGE_PRECOMPUTE, false, stream);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((classify_compact<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads),
                        0, stream, (const T*)p.pixels, (const ImageDesc*)(p.ws + L.desc),
                        (const int64_t*)(p.ws + L.tile_start), p.num_images, L.num_tiles, err, status,
                        (int64_t*)(p.ws + L.list_off), (Point*)(p.ws + L.points), L.capacity);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return stage_mark(ECT_STAGE_PRECOMPUTE, true, stream);
 }
 
 template <int N, int CONS>

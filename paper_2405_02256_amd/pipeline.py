@@ -1,0 +1,88 @@
+"""Whole-path orchestration: one pass over a batch with every buffer preallocated.
+
+``Step`` binds a ``Plan`` to its query sets and output buffers so that one
+call to ``run()`` enqueues the complete hot path on the current stream --
+precompute kernels (classification and ordered compaction), sign-vector
+bucketing, the exact ECT, the hybrid transforms for every requested kernel
+and, optionally, one backward pass -- without allocating, copying or
+synchronising.  ``capture()`` records that sequence once into a HIP graph
+(through torch.cuda.CUDAGraph) so that a replay costs one launch.
+"""
+from __future__ import annotations
+
+import torch
+
+from .api import Plan, QuerySet
+
+
+class Step:
+    def __init__(self, plan: Plan, ect_dirs=None, ect_thresholds=None, hybrid_xi=None, kernels=("fourier",),
+                 s: float = 1.0, precision: str = "fp32", ect_offsets=None, hybrid_offsets=None,
+                 backward_kernel: str | None = None, grad_out: torch.Tensor | None = None,
+                 log_scale_laplace: bool = False, rerun_precompute: bool = True):
+        self.plan = plan
+        dev = plan.device
+        self.rerun_precompute = rerun_precompute
+        self.ect_q = None if ect_dirs is None else QuerySet(ect_dirs, ect_offsets)
+        self.ect_thr = None if ect_thresholds is None else ect_thresholds.to(device=dev, dtype=torch.float64).contiguous()
+        self.hy_q = None if hybrid_xi is None else QuerySet(hybrid_xi, hybrid_offsets)
+        self.kernels = tuple(kernels) if self.hy_q is not None else ()
+        self.s = float(s)
+        self.precision = precision
+        self.log_scale_laplace = log_scale_laplace
+        if self.ect_q is not None:
+            self.ect_q.validate(plan.num_images, plan.ndim)
+            rows = self.ect_q.rows(plan.num_images)
+            self.ect_out = torch.empty((rows, self.ect_thr.shape[-1]), dtype=torch.int32, device=dev)
+        self.hy_out = {}
+        self.hy_ls = {}
+        if self.hy_q is not None:
+            self.hy_q.validate(plan.num_images, plan.ndim)
+            rows = self.hy_q.rows(plan.num_images)
+            for k in self.kernels:
+                shape = (rows, 2) if k == "fourier" else (rows,)
+                self.hy_out[k] = torch.empty(shape, dtype=torch.float64, device=dev)
+                if k == "laplace" and log_scale_laplace:
+                    self.hy_ls[k] = torch.empty(rows, dtype=torch.float64, device=dev)
+        self.backward_kernel = backward_kernel
+        if backward_kernel is not None:
+            if backward_kernel not in self.kernels:
+                raise ValueError("backward kernel must be one of the forward kernels")
+            self.grad_out = grad_out.to(device=dev, dtype=torch.float64).contiguous()
+            self.grad_xi = torch.empty((self.hy_q.vecs.shape[0], plan.ndim), dtype=torch.float64, device=dev)
+            self.grad_s = torch.empty((), dtype=torch.float64, device=dev)
+        self.graph = None
+
+    def run(self, stream=None) -> None:
+        p = self.plan
+        if self.rerun_precompute:
+            p.rerun(stream)
+        if self.ect_q is not None:
+            p.ect(self.ect_q, self.ect_thr, out=self.ect_out, stream=stream)
+        for k in self.kernels:
+            if k in self.hy_ls:
+                p.hybrid(self.hy_q, k, self.s, self.precision, out=self.hy_out[k], log_scale_out=self.hy_ls[k],
+                         stream=stream)
+            else:
+                p.hybrid(self.hy_q, k, self.s, self.precision, out=self.hy_out[k], stream=stream)
+        if self.backward_kernel is not None:
+            p.hybrid_backward(self.hy_q, self.hy_out[self.backward_kernel], self.grad_out, self.backward_kernel,
+                              self.s, self.precision, stream=stream, grad_xi=self.grad_xi, grad_s=self.grad_s)
+
+    def capture(self) -> "torch.cuda.CUDAGraph":
+        """Record run() into a graph (after one eager run sized every workspace)."""
+        self.run()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                self.run()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = g
+        return g
+
+    def replay(self) -> None:
+        self.graph.replay()

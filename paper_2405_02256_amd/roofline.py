@@ -1,0 +1,60 @@
+"""Algorithmic work models of the kernels (for roofline fractions).
+
+Peaks are MI355X's published figures; the VALU issue peak follows from the unit
+counts: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-instructions/s.
+Expressed as FP32-FMA-equivalent FLOP (2 per lane-instruction) that is the
+78.6 TFLOP/s non-packed vector rate, which equals the published FP64 vector
+peak; packed FP32 is not used (disabled at build time).
+
+Work per (query, critical point) pair is counted in VALU issue slots of the
+minimal arithmetic the method needs on this path, with a quarter-rate
+transcendental (sin, cos, exp2, rcp, rsq) counted as 4 slots:
+
+  Fourier forward   phase 2n-1 (mul + fmas), reduction to [0,1) 2 (floor, sub),
+                    cvt 1, sin 4, cos 4, 2 x (cvt + fma) 4          -> 2n + 14
+  Laplace forward   exponent n (fmas incl. shift), split 2 (floor, sub), cvt 1,
+                    exp2 4, cvt 1, cvt-to-int 1, ldexp 1, fma 1     -> n + 11
+  Bessel forward    |z| < 8: phase 2n-1, v 2, degree-9 Horner 10, scale 1,
+                    cvt 2, sign 1, fma 1                            -> 2n + 16
+                    |z| >= 8: phase 2n-1, cvt 1, rcp 4, w 2, two degree-5
+                    Horner 12, phase reduction 4, sin 4, cos 4, rsq 4,
+                    combine 5, sign 1, cvt + fma 2                  -> 2n + 46
+  Fourier backward  phase 2n-1, reduction 2, cvt 1, sin 4, cos 4, cvt 2,
+                    cotangent combine 3, n fmas                     -> 3n + 15
+  ECT               projection 2n-1, bin guess 6 (sub, mul, ceil, max, min,
+                    cvt), fix-up compares 2, LDS add 1              -> 2n + 8
+Precompute is bounded by HBM: bytes = pixels read once + 32 B per list entry
+written + list offsets.
+"""
+from __future__ import annotations
+
+HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TFLOPS = 78.6          # 256 CU * 64 lanes * 2 FLOP * 2.4 GHz
+VALU_SLOT_RATE = 256 * 64 * 2.4e9  # lane-instruction slots per second
+
+
+def slots_per_pair(kind: str, n: int, small_fraction: float = 1.0) -> float:
+    if kind == "fourier":
+        return 2 * n + 14
+    if kind == "laplace":
+        return n + 11
+    if kind == "bessel":
+        return small_fraction * (2 * n + 16) + (1.0 - small_fraction) * (2 * n + 46)
+    if kind == "fourier_bwd":
+        return 3 * n + 15
+    if kind == "ect":
+        return 2 * n + 8
+    raise ValueError(kind)
+
+
+def alu_roofline(kind: str, n: int, pairs: float, seconds: float, small_fraction: float = 1.0) -> dict:
+    flop = 2.0 * slots_per_pair(kind, n, small_fraction) * pairs
+    achieved = flop / seconds / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / VALU_PEAK_TFLOPS}
+
+
+def hbm_roofline(nbytes: float, seconds: float) -> dict:
+    achieved = nbytes / seconds / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS}
