@@ -8,8 +8,9 @@ with |xi| ~ U[0.01, 1] and uniform angle; one Euler-Fourier backward pass.
 
 One step = one pass of every stage on that batch: per-vertex classification
 and ordered compaction, sign-vector bucketing, the exact ECT, the three
-hybrid transforms (FP32 kernel values, FP64 phases and accumulation) and the
-backward pass, replayed as one HIP graph.  value = (query, critical point)
+hybrid transforms (one fused pass over the (xi, point) pairs; FP32 kernel
+values, FP64 phases and accumulation) and the backward pass, replayed as one
+HIP graph.  value = (query, critical point)
 hybrid evaluations (three forward kernels + the backward) per second of step
 time.  Inputs are resident in HBM before the timed region.
 
@@ -91,7 +92,7 @@ def main():
     log("building plan")
     plan = api.Plan(img_t)
     step = pipeline.Step(plan, dirs, thr, xi, kernels=KERNELS, s=1.0, precision="fp32",
-                         backward_kernel="fourier", grad_out=g_t)
+                         backward_kernel="fourier", grad_out=g_t, fused=True)
 
     # work per step: sum over xi of the ordinary list length of its orthant pair
     n = 2
@@ -141,7 +142,7 @@ def main():
 
     # ---- live per-stage kernel timing (library-recorded HIP events) ----
     st = int(torch.cuda.current_stream().cuda_stream)
-    names = ["precompute", "ect"] + [f"hybrid_{k}" for k in KERNELS] + ["hybrid_bwd_fourier"]
+    names = ["precompute", "ect", "hybrid_fused", "hybrid_bwd_fourier"]
     evs = {nm: [(hipevents.Event(), hipevents.Event()) for _ in range(args.steps)] for nm in names}
 
     def arm(stage, pair_):
@@ -152,9 +153,8 @@ def main():
         plan.rerun()
         arm(N.STAGE_ECT, evs["ect"][i])
         plan.ect(step.ect_q, step.ect_thr, out=step.ect_out)
-        for k in KERNELS:
-            arm(N.STAGE_HYBRID, evs[f"hybrid_{k}"][i])
-            plan.hybrid(step.hy_q, k, 1.0, "fp32", out=step.hy_out[k])
+        arm(N.STAGE_HYBRID, evs["hybrid_fused"][i])
+        plan.hybrid_multi(step.hy_q, KERNELS, 1.0, "fp32", outs=step.hy_out)
         arm(N.STAGE_HYBRID_BWD, evs["hybrid_bwd_fourier"][i])
         plan.hybrid_backward(step.hy_q, step.hy_out["fourier"], step.grad_out, "fourier", 1.0, "fp32",
                              grad_xi=step.grad_xi, grad_s=step.grad_s)
@@ -173,8 +173,7 @@ def main():
     elif dom == "hybrid_bwd_fourier":
         roof = roofline.alu_roofline("fourier_bwd", n, per_kernel_pairs, dsec)
     else:
-        kind = dom.split("_", 1)[1]
-        roof = roofline.alu_roofline(kind, n, per_kernel_pairs, dsec, small_frac)
+        roof = roofline.alu_roofline("+".join(KERNELS), n, per_kernel_pairs, dsec, small_frac)
     roof["kernel"] = dom
     roof["kernel_ms"] = stage_ms[dom]
     roof["traffic"] = None
@@ -194,7 +193,7 @@ def main():
     fp64 = None
     if not args.no_fp64:
         step64 = pipeline.Step(plan, dirs, thr, xi, kernels=KERNELS, s=1.0, precision="fp64",
-                               backward_kernel="fourier", grad_out=g_t)
+                               backward_kernel="fourier", grad_out=g_t, fused=True)
         step64.run()
         torch.cuda.synchronize()
         reps = max(3, args.steps // 5)

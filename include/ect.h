@@ -167,12 +167,22 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
  *                   out holds HT * exp(-log_scale) with log_scale an upper
  *                   bound of max(-s <xi,x>) over the image's vertices, so
  *                   that no term overflows; when NULL out holds HT and an
- *                   overflow sets ECT_DEVERR_OVERFLOW.  Other kernels: if
- *                   given it is filled with 0.
+ *                   overflow sets ECT_DEVERR_OVERFLOW.  Other kernels: must
+ *                   be NULL.
  * Deterministic: repeated calls give bitwise identical outputs. */
 ect_status hybrid_eval(ect_plan plan, int32_t kernel, double s, int32_t precision,
                        ect_query_set xi, double* out, double* log_scale,
                        void* ws, size_t* ws_bytes, hipStream_t stream);
+
+/* hybrid_eval_multi -- several hybrid transforms in one pass over the same
+ * (query, critical point) pairs, sharing the projection <xi, x> and the staged
+ * points.  kernel_mask: bit k set evaluates ect_kernel k (1..7).  Each output
+ * has the layout hybrid_eval gives for its kernel and must be non-NULL when
+ * its bit is set; log_scale_laplace as hybrid_eval's log_scale (Laplace only).
+ * Results equal those of separate hybrid_eval calls bit for bit. */
+ect_status hybrid_eval_multi(ect_plan plan, uint32_t kernel_mask, double s, int32_t precision,
+                             ect_query_set xi, double* out_fourier, double* out_laplace, double* out_bessel,
+                             double* log_scale_laplace, void* ws, size_t* ws_bytes, hipStream_t stream);
 
 /* hybrid_eval_backward -- vector-Jacobian product of hybrid_eval (without
  * log_scale) with respect to xi and to the scale s.  With kappa the kernel,
@@ -213,7 +223,7 @@ ect_status ect_plan_destroy(ect_plan plan);
 
 /* Tuning knobs (process-wide; used by the autotuner): hybrid point-chunk
  * length per work item (0 = automatic), target number of hybrid work items
- * when automatic, directions per ECT workgroup (1..8).  Values only change
+ * when automatic, directions per ECT workgroup (1..8, 0 = automatic).  Values only change
  * the schedule: results are exact (ECT) or equal to within rounding of the
  * chunked sums (hybrid), and identical for identical settings. */
 ect_status ect_set_tuning(int64_t hybrid_chunk, int64_t hybrid_target_items, int32_t ect_dirs_per_group);

@@ -198,6 +198,30 @@ class Plan:
                               ctypes.c_void_p(_dptr(ws)), have, st), "hybrid_eval")
         return (out, ls) if log_scale else out
 
+    def hybrid_multi(self, xi, kernels=("fourier", "laplace", "bessel"), s: float = 1.0, precision: str = "fp32",
+                     offsets=None, outs=None, log_scale_out=None, stream=None) -> dict:
+        """Several kernels in one pass: {kernel: output} (outputs as hybrid())."""
+        q = xi if isinstance(xi, QuerySet) else QuerySet(xi, offsets)
+        q.validate(self.num_images, self.ndim)
+        rows = q.rows(self.num_images)
+        outs = dict(outs or {})
+        mask = 0
+        for k in kernels:
+            mask |= 1 << N.KERNELS[k]
+            if k not in outs:
+                outs[k] = torch.empty((rows, 2) if k == "fourier" else (rows,), dtype=torch.float64,
+                                      device=self.device)
+        st = _stream(stream)
+        ptrs = [_dptr(outs.get(k)) for k in ("fourier", "laplace", "bessel")]
+        need = ctypes.c_size_t(0)
+        N.check(N.hybrid_eval_multi(self.handle, mask, s, N.PRECISIONS[precision], q.c(), *ptrs,
+                                    _dptr(log_scale_out), None, need, st), "hybrid_eval_multi(size)")
+        ws = self._ws(need.value)
+        have = ctypes.c_size_t(ws.numel())
+        N.check(N.hybrid_eval_multi(self.handle, mask, s, N.PRECISIONS[precision], q.c(), *ptrs,
+                                    _dptr(log_scale_out), ctypes.c_void_p(_dptr(ws)), have, st), "hybrid_eval_multi")
+        return {k: outs[k] for k in kernels}
+
     def hybrid_backward(self, xi, out: torch.Tensor, grad_out: torch.Tensor, kernel: str = "fourier", s: float = 1.0,
                         precision: str = "fp32", offsets=None, stream=None, grad_xi=None, grad_s=None):
         """(grad_xi, grad_s): VJP of hybrid() (shared sets sum grad_xi over images)."""

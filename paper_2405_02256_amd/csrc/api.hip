@@ -18,9 +18,10 @@ StageEvents g_stage_events[4];
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kAccSlotsHost = 4;  // doubles per query in a partial record
 
 struct EvalLayout {
-    size_t perm, bstart, bcnt, item_off, tile_off, params, counters, partials, gpart, gspart, total;
+    size_t recs, bcnt, item_off, tile_off, params, partials, gpart, gspart, total;
     int64_t groups, entries, grid, capacity, tiles;
 };
 
@@ -34,16 +35,15 @@ int64_t query_rows(const ect_query_set& q, int num_images) {
     return q.offsets ? q.count : q.count * (int64_t)num_images;
 }
 
-// Workspace shared by the evaluation calls: bucketing and work list.
+// Workspace shared by the evaluation calls: bucketing and work list.  Bucket
+// b of image i owns B * Q_i record slots (see queries.hip).
 void layout_common(const Plan& p, const ect_query_set& q, int B, EvalLayout* L, size_t* off) {
     const bool shared = q.offsets == nullptr;
     const int64_t groups = shared ? 1 : p.num_images;
-    const int64_t perm_rows = shared ? q.count : q.count;
     L->groups = groups;
     L->entries = (int64_t)p.num_images * B;
     size_t o = *off;
-    L->perm = o; o = align_up(o + sizeof(int64_t) * std::max<int64_t>(perm_rows, 1), kAlign);
-    L->bstart = o; o = align_up(o + sizeof(int64_t) * groups * B, kAlign);
+    L->recs = o; o = align_up(o + sizeof(QRec) * (size_t)B * std::max<int64_t>(q.count, 1), kAlign);
     L->bcnt = o; o = align_up(o + sizeof(int32_t) * groups * B, kAlign);
     L->item_off = o; o = align_up(o + sizeof(int64_t) * (L->entries + 1), kAlign);
     L->tile_off = o; o = align_up(o + sizeof(int64_t) * (L->entries + 1), kAlign);
@@ -75,8 +75,8 @@ double mean_list(const Plan& p, int base, int count) {
 // Tunables (defaults; an autotuner may override them through ect_set_tuning).
 struct Tuning {
     int64_t hybrid_chunk = 0;        // 0: automatic
-    int64_t hybrid_target_items = 4096;
-    int ect_dirs_per_group = kEctMaxDirs;
+    int64_t hybrid_target_items = 2048;
+    int ect_dirs_per_group = 0;      // 0: automatic
 } g_tuning;
 
 int64_t hybrid_chunk_for(const Plan& p, int64_t rows) {
@@ -84,8 +84,8 @@ int64_t hybrid_chunk_for(const Plan& p, int64_t rows) {
     const int P = num_ordinary(p.ndim);
     const double avg = mean_list(p, num_classical(p.ndim), P);
     const double pairs = (double)rows * avg;
-    double c = pairs / ((double)kHybridLanes * (double)g_tuning.hybrid_target_items);
-    int64_t ci = (int64_t)std::ceil(std::max(64.0, c) / 16.0) * 16;
+    double c = pairs / ((double)kHybridThreads * (double)g_tuning.hybrid_target_items);
+    int64_t ci = (int64_t)std::ceil(std::max(32.0, c) / 16.0) * 16;
     return ci;
 }
 
@@ -96,16 +96,15 @@ void layout_hybrid(const Plan& p, const ect_query_set& q, bool backward, EvalLay
     const bool shared = q.offsets == nullptr;
     const int64_t rows = query_rows(q, p.num_images);
     // query tiles: sum over (image, pair) of ceil(count / 64) <= rows/64 + images*P
-    const int64_t tiles = shared ? (int64_t)p.num_images * ((q.count + kHybridLanes - 1) / kHybridLanes + P)
-                                 : (rows + kHybridLanes - 1) / kHybridLanes + (int64_t)p.num_images * P;
+    const int64_t tiles = shared ? (int64_t)p.num_images * ((q.count + kHybridThreads - 1) / kHybridThreads + P)
+                                 : (rows + kHybridThreads - 1) / kHybridThreads + (int64_t)p.num_images * P;
     *chunk = hybrid_chunk_for(p, rows);
     const int64_t maxn = max_list(p, num_classical(p.ndim), P);
     const int64_t maxch = std::max<int64_t>(1, (maxn + *chunk - 1) / *chunk);
     L->tiles = tiles;
     L->grid = tiles * maxch;
     L->capacity = L->grid;
-    L->counters = o; o = align_up(o + sizeof(uint32_t) * std::max<int64_t>(tiles, 1), kAlign);
-    L->partials = o; o = align_up(o + sizeof(double) * 4 * kHybridLanes * std::max<int64_t>(L->capacity, 1), kAlign);
+    L->partials = o; o = align_up(o + sizeof(double) * kAccSlotsHost * kHybridThreads * std::max<int64_t>(L->capacity, 1), kAlign);
     L->gpart = L->gspart = 0;
     if (backward) {
         L->gpart = o; o = align_up(o + sizeof(double) * p.ndim * std::max<int64_t>(rows, 1), kAlign);
@@ -263,7 +262,11 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
     if (M < 1) return ECT_E_INVALID;
     if (M > kEctMaxThresholds) return ECT_E_UNSUPPORTED;
     const Plan& p = *plan;
-    int td = g_tuning.ect_dirs_per_group;
+    // directions per workgroup: enough workgroups to fill the chip first, then
+    // more directions per streamed point
+    const int64_t nrows = query_rows(dirs, plan->num_images);
+    int td = g_tuning.ect_dirs_per_group > 0 ? g_tuning.ect_dirs_per_group
+                                             : (int)std::min<int64_t>(kEctMaxDirs, std::max<int64_t>(1, nrows / 1024));
     const int64_t lds_budget = 60 * 1024;
     td = (int)std::min<int64_t>(td, (lds_budget - 8 * (int64_t)M) / (4 * (int64_t)M));
     td = std::max(1, std::min(td, kEctMaxDirs));
@@ -280,12 +283,9 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
     const int B = num_classical(p.ndim);
     const int NL = num_lists(p.ndim);
     uint32_t* err = (uint32_t*)(p.ws + p.lay.err);
-    hipError_t e = launch_bucket(p.ndim, dirs, p.num_images, false, err, (int64_t*)(w + L.perm),
-                                 (int64_t*)(w + L.bstart), (int32_t*)(w + L.bcnt), stream);
-    if (e == hipSuccess)
-        e = launch_worklist(p.num_images, B, 0, NL, dirs.offsets == nullptr, (const int32_t*)(w + L.bcnt),
-                            (const int64_t*)(p.ws + p.lay.list_off), td, 0, 0, err, (int64_t*)(w + L.item_off),
-                            (int64_t*)(w + L.tile_off), (int64_t*)(w + L.params), stream);
+    hipError_t e = launch_prepare(p.ndim, dirs, p.num_images, false, err, (QRec*)(w + L.recs), (int32_t*)(w + L.bcnt),
+                                  (const int64_t*)(p.ws + p.lay.list_off), 0, NL, td, 0, 0, (int64_t*)(w + L.item_off),
+                                  (int64_t*)(w + L.tile_off), (int64_t*)(w + L.params), stream);
     if (e == hipSuccess) {
         EctArgs a{};
         a.points = (const Point*)(p.ws + p.lay.points);
@@ -301,8 +301,7 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
         a.M = M;
         a.thr_per_image = thresholds_per_image ? 1 : 0;
         a.out = out;
-        a.perm = (const int64_t*)(w + L.perm);
-        a.bstart = (const int64_t*)(w + L.bstart);
+        a.recs = (const QRec*)(w + L.recs);
         a.bcnt = (const int32_t*)(w + L.bcnt);
         a.item_off = (const int64_t*)(w + L.item_off);
         a.err = err;
@@ -312,17 +311,22 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
     return from_hip(e);
 }
 
-static ect_status hybrid_common(ect_plan plan, int32_t kernel, double s, int32_t precision, ect_query_set xi,
-                                double* out, double* log_scale, const double* fwd_out, const double* grad_out,
-                                double* grad_xi, double* grad_s, void* ws, size_t* ws_bytes, hipStream_t stream,
-                                bool backward) {
+static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t precision, ect_query_set xi,
+                                double* out_f, double* out_l, double* out_b, double* log_scale,
+                                const double* fwd_out, const double* grad_out, double* grad_xi, double* grad_s,
+                                void* ws, size_t* ws_bytes, hipStream_t stream, bool backward) {
     if (!plan || !ws_bytes) return ECT_E_INVALID;
-    if (kernel < ECT_FOURIER || kernel > ECT_BESSEL) return ECT_E_INVALID;
+    if (mask == 0 || mask > 7) return ECT_E_INVALID;
+    if (backward && (mask & (mask - 1))) return ECT_E_INVALID;
     if (precision != ECT_FP32 && precision != ECT_FP64) return ECT_E_INVALID;
     if (!std::isfinite(s) || s == 0.0) return ECT_E_INVALID;
     if (!valid_query_set(xi, plan->num_images)) return ECT_E_INVALID;
-    if (!backward && !out) return ECT_E_INVALID;
-    if (backward && (!fwd_out || !grad_out || !grad_xi)) return ECT_E_INVALID;
+    if (!backward) {
+        if (((mask & 1) && !out_f) || ((mask & 2) && !out_l) || ((mask & 4) && !out_b)) return ECT_E_INVALID;
+        if (log_scale && !(mask & 2)) return ECT_E_INVALID;
+    } else if (!fwd_out || !grad_out || !grad_xi) {
+        return ECT_E_INVALID;
+    }
     const Plan& p = *plan;
     EvalLayout L{};
     int64_t chunk = 0;
@@ -335,18 +339,13 @@ static ect_status hybrid_common(ect_plan plan, int32_t kernel, double s, int32_t
     const int64_t rows = query_rows(xi, p.num_images);
     if (rows == 0) return ECT_OK;
     char* w = (char*)ws;
-    const int P = num_ordinary(p.ndim);
     const int NL = num_lists(p.ndim);
     uint32_t* err = (uint32_t*)(p.ws + p.lay.err);
     const bool shared = xi.offsets == nullptr;
-    hipError_t e = launch_bucket(p.ndim, xi, p.num_images, true, err, (int64_t*)(w + L.perm),
-                                 (int64_t*)(w + L.bstart), (int32_t*)(w + L.bcnt), stream);
-    if (e == hipSuccess)
-        e = launch_worklist(p.num_images, P, num_classical(p.ndim), NL, shared, (const int32_t*)(w + L.bcnt),
-                            (const int64_t*)(p.ws + p.lay.list_off), kHybridLanes, chunk, L.capacity, err,
-                            (int64_t*)(w + L.item_off), (int64_t*)(w + L.tile_off), (int64_t*)(w + L.params),
-                            stream);
-    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)(w + L.counters), L.tiles, 0u, stream);
+    hipError_t e = launch_prepare(p.ndim, xi, p.num_images, true, err, (QRec*)(w + L.recs), (int32_t*)(w + L.bcnt),
+                                  (const int64_t*)(p.ws + p.lay.list_off), num_classical(p.ndim), NL,
+                                  kHybridThreads, chunk, L.capacity, (int64_t*)(w + L.item_off),
+                                  (int64_t*)(w + L.tile_off), (int64_t*)(w + L.params), stream);
     if (e != hipSuccess) return ECT_E_DEVICE;
     HybridArgs a{};
     a.points = (const Point*)(p.ws + p.lay.points);
@@ -360,41 +359,53 @@ static ect_status hybrid_common(ect_plan plan, int32_t kernel, double s, int32_t
     a.offsets = xi.offsets;
     a.count = xi.count;
     a.s = s;
-    a.out = out;
+    a.out_f = out_f;
+    a.out_l = out_l;
+    a.out_b = out_b;
     a.log_scale = log_scale;
     a.fwd_out = fwd_out;
     a.grad_out = grad_out;
-    a.perm = (const int64_t*)(w + L.perm);
-    a.bstart = (const int64_t*)(w + L.bstart);
+    a.recs = (const QRec*)(w + L.recs);
     a.bcnt = (const int32_t*)(w + L.bcnt);
     a.item_off = (const int64_t*)(w + L.item_off);
     a.tile_off = (const int64_t*)(w + L.tile_off);
     a.params = (const int64_t*)(w + L.params);
     a.partials = (double*)(w + L.partials);
-    a.counters = (uint32_t*)(w + L.counters);
     a.err = err;
-    if (!backward) return from_hip(launch_hybrid_fwd(p.ndim, kernel, precision, a, L.grid, stream));
+    if (!backward) return from_hip(launch_hybrid(p.ndim, mask, precision, false, a, L.grid, L.tiles, stream));
     double* gpart = (double*)(w + L.gpart);
     a.grad_xi = shared ? gpart : grad_xi;
     a.grad_s_part = (double*)(w + L.gspart);
-    e = launch_hybrid_bwd(p.ndim, kernel, precision, a, L.grid, stream);
+    e = launch_hybrid(p.ndim, mask, precision, true, a, L.grid, L.tiles, stream);
     if (e == hipSuccess)
         e = launch_grad_reduce(p.ndim, gpart, p.num_images, xi.count, shared, grad_xi, a.grad_s_part, rows,
                                grad_s, stream);
     return from_hip(e);
 }
 
+static double* kernel_out(int32_t kernel, int32_t which, double* out) { return kernel == which ? out : nullptr; }
+
 ect_status hybrid_eval(ect_plan plan, int32_t kernel, double s, int32_t precision, ect_query_set xi, double* out,
                        double* log_scale, void* ws, size_t* ws_bytes, hipStream_t stream) {
-    return hybrid_common(plan, kernel, s, precision, xi, out, log_scale, nullptr, nullptr, nullptr, nullptr, ws,
-                         ws_bytes, stream, false);
+    if (kernel < ECT_FOURIER || kernel > ECT_BESSEL || !out) return ECT_E_INVALID;
+    return hybrid_common(plan, 1u << kernel, s, precision, xi, kernel_out(kernel, ECT_FOURIER, out),
+                         kernel_out(kernel, ECT_LAPLACE, out), kernel_out(kernel, ECT_BESSEL, out), log_scale,
+                         nullptr, nullptr, nullptr, nullptr, ws, ws_bytes, stream, false);
+}
+
+ect_status hybrid_eval_multi(ect_plan plan, uint32_t kernel_mask, double s, int32_t precision, ect_query_set xi,
+                             double* out_fourier, double* out_laplace, double* out_bessel, double* log_scale_laplace,
+                             void* ws, size_t* ws_bytes, hipStream_t stream) {
+    return hybrid_common(plan, kernel_mask, s, precision, xi, out_fourier, out_laplace, out_bessel,
+                         log_scale_laplace, nullptr, nullptr, nullptr, nullptr, ws, ws_bytes, stream, false);
 }
 
 ect_status hybrid_eval_backward(ect_plan plan, int32_t kernel, double s, int32_t precision, ect_query_set xi,
                                 const double* out, const double* grad_out, double* grad_xi, double* grad_s,
                                 void* ws, size_t* ws_bytes, hipStream_t stream) {
-    return hybrid_common(plan, kernel, s, precision, xi, nullptr, nullptr, out, grad_out, grad_xi, grad_s, ws,
-                         ws_bytes, stream, true);
+    if (kernel < ECT_FOURIER || kernel > ECT_BESSEL) return ECT_E_INVALID;
+    return hybrid_common(plan, 1u << kernel, s, precision, xi, nullptr, nullptr, nullptr, nullptr, out, grad_out,
+                         grad_xi, grad_s, ws, ws_bytes, stream, true);
 }
 
 ect_status ect_plan_counts(ect_plan plan, int64_t* classical, int64_t* ordinary) {
@@ -477,7 +488,7 @@ ect_status ect_plan_destroy(ect_plan plan) {
 // Tuning knobs for the autotuner: hybrid point-chunk length (0 = automatic),
 // target number of hybrid work items, directions per ECT workgroup.
 ect_status ect_set_tuning(int64_t hybrid_chunk, int64_t hybrid_target_items, int32_t ect_dirs_per_group) {
-    if (hybrid_chunk < 0 || hybrid_target_items < 1 || ect_dirs_per_group < 1 || ect_dirs_per_group > kEctMaxDirs)
+    if (hybrid_chunk < 0 || hybrid_target_items < 1 || ect_dirs_per_group < 0 || ect_dirs_per_group > kEctMaxDirs)
         return ECT_E_INVALID;
     g_tuning.hybrid_chunk = hybrid_chunk;
     g_tuning.hybrid_target_items = hybrid_target_items;

@@ -57,13 +57,12 @@ __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
         int ok = 0;
         int64_t row = -1;
         if (tid < nd) {
-            const int64_t rel = a.perm[a.bstart[bidx] + q0 + tid] >> 1;
-            row = row_base + rel;                         // output row
-            const int64_t vrow = shared_q ? rel : row;    // row of the direction vector
+            const QRec r = a.recs[bucket_start(a.offsets, a.count, img, B, b) + q0 + tid];
+            row = row_base + (r.code >> 1);               // output row
             ok = 1;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                double v = c < N ? a.vecs[vrow * N + c] : 0.0;
+                const double v = r.v[c];
                 s_xi[tid][c] = v;
                 ok &= isfinite(v) ? 1 : 0;
             }
@@ -101,19 +100,31 @@ __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
 
     const Point* __restrict__ pts = a.points + (int64_t)b * a.capacity;
     const int64_t p0 = a.list_off[img * a.NL + b], p1 = a.list_off[(img + 1) * a.NL + b];
-    for (int64_t p = p0 + tid; p < p1; p += kEctThreads) {
-        const Point pt = pts[p];
-        const int32_t val = (int32_t)pt.val;
+    // U points per thread are loaded before any is processed, so that their
+    // memory latencies overlap
+    constexpr int U = 4;
+    for (int64_t p = p0 + tid; p < p1; p += (int64_t)kEctThreads * U) {
+        Point pt[U];
 #pragma unroll
-        for (int dd = 0; dd < TD; ++dd) {
-            if (!use[dd]) continue;
-            const double u = project<N>(xi[dd], pt.x);
-            double g = ceil((u - t0) * inv);
-            g = fmin(fmax(g, 0.0), (double)M);
-            int j = (int)g;
-            while (j > 0 && s_thr[j - 1] >= u) --j;
-            while (j < M && s_thr[j] < u) ++j;
-            if (j < M) atomicAdd(&s_hist[dd * M + j], val);
+        for (int u = 0; u < U; ++u) {
+            const int64_t pp = p + (int64_t)u * kEctThreads;
+            if (pp < p1) pt[u] = pts[pp];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (p + (int64_t)u * kEctThreads >= p1) break;
+            const int32_t val = (int32_t)pt[u].val;
+#pragma unroll
+            for (int dd = 0; dd < TD; ++dd) {
+                if (!use[dd]) continue;
+                const double uu = project<N>(xi[dd], pt[u].x);
+                double g = ceil((uu - t0) * inv);
+                g = fmin(fmax(g, 0.0), (double)M);
+                int j = (int)g;
+                while (j > 0 && s_thr[j - 1] >= uu) --j;
+                while (j < M && s_thr[j] < uu) ++j;
+                if (j < M) atomicAdd(&s_hist[dd * M + j], val);
+            }
         }
     }
     __syncthreads();

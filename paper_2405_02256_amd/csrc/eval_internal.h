@@ -7,18 +7,36 @@
 namespace ect {
 
 constexpr int kBucketThreads = 256;
+
+// A query in bucket order: its vector (unused axes 0) and code = 2 * row + negated,
+// where row is relative to the image's first query row and `negated` marks a
+// query evaluated on the mirrored list of its orthant pair.
+struct alignas(32) QRec {
+    double v[3];
+    int64_t code;
+};
 constexpr int kEctThreads = 256;      // ECT workgroup: points stream across its lanes
 constexpr int kEctMaxDirs = 8;        // directions per ECT workgroup
 constexpr int kEctMaxThresholds = 4096;
-constexpr int kHybridLanes = 64;      // one wave per hybrid work item, one query per lane and slot
+constexpr int kHybridThreads = 256;  // one query per thread; the workgroup shares a staged chunk of points
+constexpr int kHybridStage = 256;    // points staged in LDS at a time
 
-hipError_t launch_bucket(int ndim, const ect_query_set& qs, int num_images, bool hybrid, uint32_t* err,
-                         int64_t* perm, int64_t* bstart, int32_t* bcnt, hipStream_t stream);
+constexpr int64_t kSmallMaxRows = 65536;   // query sets bucketed by a single workgroup
+constexpr int kSmallMaxEntries = 4096;     // (image, bucket) entries counted in LDS there
 
-hipError_t launch_worklist(int num_images, int B, int list_base, int NL, bool shared_queries,
-                           const int32_t* bcnt, const int64_t* list_off, int qtile, int64_t chunk,
-                           int64_t capacity, uint32_t* err, int64_t* item_off, int64_t* tile_off,
-                           int64_t* params, hipStream_t stream);
+// Bucket the queries by sign vector and build the work list (one launch for
+// small sets; fill + bucket + work list otherwise).
+hipError_t launch_prepare(int ndim, const ect_query_set& qs, int num_images, bool hybrid, uint32_t* err,
+                          QRec* recs, int32_t* bcnt, const int64_t* list_off, int list_base, int NL, int qtile,
+                          int64_t chunk, int64_t capacity, int64_t* item_off, int64_t* tile_off, int64_t* params,
+                          hipStream_t stream);
+
+// First record slot of bucket b of image img (see queries.hip).
+__device__ __forceinline__ int64_t bucket_start(const int64_t* offsets, int64_t count, int64_t img, int B, int b) {
+    if (!offsets) return (int64_t)b * count;
+    const int64_t r0 = offsets[img];
+    return (int64_t)B * r0 + (int64_t)b * (offsets[img + 1] - r0);
+}
 
 struct EctArgs {
     const Point* points;
@@ -34,8 +52,7 @@ struct EctArgs {
     int M;
     int thr_per_image;
     int32_t* out;
-    const int64_t* perm;
-    const int64_t* bstart;
+    const QRec* recs;
     const int32_t* bcnt;
     const int64_t* item_off;
     uint32_t* err;
@@ -56,27 +73,27 @@ struct HybridArgs {
     const int64_t* offsets;
     int64_t count;
     double s;
-    double* out;
-    double* log_scale;
-    const double* fwd_out;    // backward: forward output
+    double* out_f;            // Fourier [rows][2]
+    double* out_l;            // Laplace [rows]
+    double* out_b;            // Bessel [rows]
+    double* log_scale;        // Laplace log-scale [rows] or null
+    const double* fwd_out;    // backward: forward output of the kernel
     const double* grad_out;   // backward
     double* grad_xi;          // backward: [rows][n] (ragged) or per-image partial [images][count][n]
     double* grad_s_part;      // backward: per-row contribution to d/ds
-    const int64_t* perm;
-    const int64_t* bstart;
+    const QRec* recs;
     const int32_t* bcnt;
     const int64_t* item_off;
     const int64_t* tile_off;
     const int64_t* params;    // [0] items, [1] tiles, [2] chunk
     double* partials;
-    uint32_t* counters;
     uint32_t* err;
 };
 
-hipError_t launch_hybrid_fwd(int ndim, int kernel, int precision, const HybridArgs& a, int64_t grid,
-                             hipStream_t stream);
-hipError_t launch_hybrid_bwd(int ndim, int kernel, int precision, const HybridArgs& a, int64_t grid,
-                             hipStream_t stream);
+// Main kernel (grid work items) then, for multi-chunk tiles, the in-order
+// reduction (tiles work groups).  mask: bit k = ect_kernel k (backward: one bit).
+hipError_t launch_hybrid(int ndim, unsigned mask, int precision, bool backward, const HybridArgs& a,
+                         int64_t grid, int64_t tiles, hipStream_t stream);
 hipError_t launch_grad_reduce(int ndim, const double* part, int num_images, int64_t count, bool shared,
                               double* grad_xi, const double* gs_part, int64_t rows, double* grad_s,
                               hipStream_t stream);

@@ -7,19 +7,23 @@
 // here is the one the definition gives (a closed square yields
 // kbar(max) - kbar(min)).
 //
+// Several kernels can be evaluated in one pass (a bit mask of Fourier,
+// Laplace, Bessel): they share the staged points and the projection <xi, x>.
+//
 // Work decomposition: queries are bucketed by orthant pair; a work item is
-// (image, pair, tile of 64 queries, chunk of points).  One wave runs an item:
-// every lane owns one query held in registers, and the wave walks the chunk's
-// points in lockstep, so each point is fetched once per wave with a scalar
-// load.  Per pair of (query, point):
+// (image, pair, tile of 256 queries, chunk of points).  One workgroup runs an
+// item: every thread owns one query held in registers, and the chunk's points
+// are staged through LDS and read by all threads in lockstep.  Per pair of
+// (query, point):
 //   FP32 precision: FP64 phase, FP64 argument reduction to [0, 1) revolutions
 //                   (or to a split exponent for Laplace), FP32 kernel value
 //                   (hardware sin/cos/exp2 on reduced arguments, polynomial
 //                   Ji0), FP64 accumulation;
 //   FP64 precision: every step in FP64.
-// Items of one query tile write per-lane partial sums; the last item of the
-// tile to finish (counted with an atomic) adds the partials in chunk order, so
-// results are bitwise reproducible.
+// Items of a tile split over several chunks write per-query partial sums,
+// which a second kernel adds in chunk order, so results are bitwise
+// reproducible (a kernel boundary is the cheap synchronisation point between
+// the chip's non-coherent L2 slices).
 #include "eval_internal.h"
 #include "ji0_coeffs.h"
 
@@ -99,145 +103,116 @@ __device__ __forceinline__ double exp2_split(double a) {
     return ldexp(e, (int)fmax(n, -2000.0));
 }
 
-// Per-lane query state.
+// Per-thread query state.
 template <int N>
 struct Query {
-    double xi[N];     // raw direction
-    double w[N];      // scaled direction used for the phase
-    double m;         // Laplace shift (natural log units)
+    double xi[N];     // direction
+    double cF;        // Fourier: revolutions per unit of <xi,x>, s / (2 pi)
+    double cL, mL;    // Laplace: exponent = cL <xi,x> - mL (FP32: log2 units)
+    double cB;        // Bessel: z = s <xi,x>
     double gr, gi;    // backward: output cotangent
     double sigma;     // +1, or -1 when the query's list is the pair's mirror
 };
 
-// Accumulate the contributions of points [c0, c1) of `pts`.
-//   forward: acc[0] (Fourier: acc[0], acc[1] = sums of D sin, D cos)
-//   backward: acc[a] = sum of D x_a kappa-part (weighted by the cotangent)
-template <int N, int KER, int PREC, bool BWD>
-__device__ __forceinline__ void accumulate(const Point* __restrict__ pts, int64_t c0, int64_t c1,
-                                           const Query<N>& q, double* acc) {
-#pragma unroll 2
-    for (int64_t p = c0; p < c1; ++p) {
-        const Point pt = pts[p];
-        if constexpr (KER == ECT_FOURIER) {
-            // phase in revolutions: s <xi, x> / (2 pi)
-            double ph = q.w[0] * pt.x[0];
+constexpr int kF = 1 << ECT_FOURIER, kL = 1 << ECT_LAPLACE, kB = 1 << ECT_BESSEL;
+// accumulator slots: Fourier 0-1, Laplace 2, Bessel 3; backward: 0..n-1
+constexpr int kSlotF = 0, kSlotL = 2, kSlotB = 3;
+
+// Contribution of one point.  Forward: per requested kernel, sum of D kbar(s u)
+// (without the 1/s); backward (one kernel): acc[a] = sum of D x_a g(kappa).
+template <int N, int MASK, int PREC, bool BWD>
+__device__ __forceinline__ void accumulate_point(const Point& pt, const Query<N>& q, double* acc) {
+    double u = q.xi[0] * pt.x[0];
 #pragma unroll
-            for (int a = 1; a < N; ++a) ph = fma(q.w[a], pt.x[a], ph);
-            double sn, cs;
-            if constexpr (PREC == ECT_FP32) {
-                float s32, c32;
-                sincos_rev_f32((float)(ph - floor(ph)), &s32, &c32);
-                sn = (double)s32;
-                cs = (double)c32;
-            } else {
-                sincospi(2.0 * (ph - rint(ph)), &sn, &cs);
-            }
-            if constexpr (!BWD) {
-                acc[0] = fma(pt.val, sn, acc[0]);
-                acc[1] = fma(pt.val, cs, acc[1]);
-            } else {
-                // kappa(s u) = exp(-i s u): d Re/d xi_a = x cos, d Im/d xi_a = -x sin
-                const double g = pt.val * (q.gr * cs - q.gi * sn);
-#pragma unroll
-                for (int a = 0; a < N; ++a) acc[a] = fma(g, pt.x[a], acc[a]);
-            }
-        } else if constexpr (KER == ECT_LAPLACE) {
-            // exponent -s u - m <= 0 (FP32: in log2 units)
-            double ex = fma(q.w[0], pt.x[0], -q.m);
-#pragma unroll
-            for (int a = 1; a < N; ++a) ex = fma(q.w[a], pt.x[a], ex);
-            const double term = (PREC == ECT_FP32) ? exp2_split(ex) : exp(ex);
-            if constexpr (!BWD) {
-                acc[0] = fma(pt.val, term, acc[0]);
-            } else {
-                const double g = pt.val * term;
-#pragma unroll
-                for (int a = 0; a < N; ++a) acc[a] = fma(g, pt.x[a], acc[a]);
-            }
+    for (int a = 1; a < N; ++a) u = fma(q.xi[a], pt.x[a], u);
+    if constexpr ((MASK & kF) != 0) {
+        const double ph = u * q.cF;
+        double sn, cs;
+        if constexpr (PREC == ECT_FP32) {
+            float s32, c32;
+            sincos_rev_f32((float)(ph - floor(ph)), &s32, &c32);
+            sn = (double)s32;
+            cs = (double)c32;
         } else {
-            double z = q.w[0] * pt.x[0];
+            sincospi(2.0 * (ph - rint(ph)), &sn, &cs);
+        }
+        if constexpr (!BWD) {
+            acc[kSlotF] = fma(pt.val, sn, acc[kSlotF]);
+            acc[kSlotF + 1] = fma(pt.val, cs, acc[kSlotF + 1]);
+        } else {
+            // kappa(s u) = exp(-i s u): d Re/d xi_a = x cos, d Im/d xi_a = -x sin
+            const double g = pt.val * (q.gr * cs - q.gi * sn);
 #pragma unroll
-            for (int a = 1; a < N; ++a) z = fma(q.w[a], pt.x[a], z);
-            if constexpr (!BWD) {
-                const double ji = (PREC == ECT_FP32) ? (double)ji0_f32(z) : ji0_f64(z);
-                acc[0] = fma(pt.val, ji, acc[0]);
-            } else {
-                const double j = (PREC == ECT_FP32) ? (double)j0f((float)z) : j0(z);
-                const double g = pt.val * j;
+            for (int a = 0; a < N; ++a) acc[a] = fma(g, pt.x[a], acc[a]);
+        }
+    }
+    if constexpr ((MASK & kL) != 0) {
+        const double ex = fma(u, q.cL, -q.mL);   // <= 0
+        const double term = (PREC == ECT_FP32) ? exp2_split(ex) : exp(ex);
+        if constexpr (!BWD) {
+            acc[kSlotL] = fma(pt.val, term, acc[kSlotL]);
+        } else {
+            const double g = pt.val * term;
 #pragma unroll
-                for (int a = 0; a < N; ++a) acc[a] = fma(g, pt.x[a], acc[a]);
-            }
+            for (int a = 0; a < N; ++a) acc[a] = fma(g, pt.x[a], acc[a]);
+        }
+    }
+    if constexpr ((MASK & kB) != 0) {
+        const double z = u * q.cB;
+        if constexpr (!BWD) {
+            const double ji = (PREC == ECT_FP32) ? (double)ji0_f32(z) : ji0_f64(z);
+            acc[kSlotB] = fma(pt.val, ji, acc[kSlotB]);
+        } else {
+            const double j = (PREC == ECT_FP32) ? (double)j0f((float)z) : j0(z);
+            const double g = pt.val * j;
+#pragma unroll
+            for (int a = 0; a < N; ++a) acc[a] = fma(g, pt.x[a], acc[a]);
         }
     }
 }
 
-template <int N, int KER, int PREC, bool BWD>
-__global__ void __launch_bounds__(kHybridLanes) hybrid_kernel(HybridArgs a) {
+template <int MASK, bool BWD, int N>
+__host__ __device__ constexpr bool slot_used(int k) {
+    if (BWD) return k < N;
+    return ((MASK & kF) && (k == 0 || k == 1)) || ((MASK & kL) && k == 2) || ((MASK & kB) && k == 3);
+}
+
+// Per-query set-up shared by the evaluation and reduction kernels.
+template <int N, int MASK, int PREC, bool BWD>
+__device__ __forceinline__ void setup_query(const HybridArgs& a, int64_t img, int b, int64_t qi, bool active,
+                                            Query<N>& q, int64_t& row) {
     constexpr int P = 1 << (N - 1);
-    constexpr int NACC = BWD ? N : (KER == ECT_FOURIER ? 2 : 1);
-    const int lane = threadIdx.x;
-    const int64_t item = blockIdx.x;
-    const int64_t total = a.params[0];
-    if (item >= total) return;
-    const int64_t C = a.params[2];
-    const int64_t E = (int64_t)a.num_images * P;
-    int64_t lo = 0, hi = E - 1;
-    while (lo < hi) {
-        int64_t mid = (lo + hi + 1) >> 1;
-        if (a.item_off[mid] <= item) lo = mid; else hi = mid - 1;
-    }
-    const int64_t e = lo;
-    const int64_t img = e / P;
-    const int b = (int)(e % P);
-    const int64_t local = item - a.item_off[e];
-    const int l = a.list_base + b;
-    const int64_t p0 = a.list_off[img * a.NL + l], p1 = a.list_off[(img + 1) * a.NL + l];
-    const int64_t np = p1 - p0;
-    const int64_t chunks = np > 0 ? (np + C - 1) / C : 1;
-    const int64_t t = local / chunks, c = local % chunks;
     const bool shared_q = a.offsets == nullptr;
-    const int64_t bidx = shared_q ? b : e;
-    const int64_t qn = a.bcnt[bidx];
-    const int64_t qi = t * kHybridLanes + lane;
-    const bool active = qi < qn;
     const int64_t row_base = shared_q ? img * a.count : a.offsets[img];
-    int64_t row = 0;
-    Query<N> q;
+    row = 0;
     q.sigma = 1.0;
-    q.m = 0.0;
     q.gr = q.gi = 0.0;
     const double s = a.s;
     if (active) {
-        const int64_t code = a.perm[a.bstart[bidx] + qi];
-        row = row_base + (code >> 1);                       // output row
-        const int64_t vrow = shared_q ? (code >> 1) : row;  // row of the query vector
-        q.sigma = (code & 1) ? -1.0 : 1.0;
+        const QRec r = a.recs[bucket_start(a.offsets, a.count, img, P, b) + qi];
+        row = row_base + (r.code >> 1);
+        q.sigma = (r.code & 1) ? -1.0 : 1.0;
 #pragma unroll
-        for (int k = 0; k < N; ++k) q.xi[k] = a.vecs[vrow * N + k];
+        for (int k = 0; k < N; ++k) q.xi[k] = r.v[k];
     } else {
 #pragma unroll
         for (int k = 0; k < N; ++k) q.xi[k] = 0.0;
     }
-    const ImageDesc& dsc = a.desc[img];
-    if constexpr (KER == ECT_FOURIER) {
-#pragma unroll
-        for (int k = 0; k < N; ++k) q.w[k] = q.xi[k] * (s * kInv2Pi);
-    } else if constexpr (KER == ECT_LAPLACE) {
+    q.cF = s * kInv2Pi;
+    q.cB = s;
+    q.cL = (PREC == ECT_FP32) ? -s * kLog2E : -s;
+    q.mL = 0.0;
+    if constexpr ((MASK & kL) != 0) {
         // m = max over the image's vertex box of -s <xi, x> (an upper bound of every exponent)
+        const ImageDesc& dsc = a.desc[img];
         double m = 0.0;
 #pragma unroll
         for (int k = 0; k < N; ++k) m += fmax(-s * q.xi[k] * dsc.lo[k], -s * q.xi[k] * dsc.hi[k]);
-        q.m = (PREC == ECT_FP32) ? m * kLog2E : m;
-#pragma unroll
-        for (int k = 0; k < N; ++k) q.w[k] = (PREC == ECT_FP32) ? -s * kLog2E * q.xi[k] : -s * q.xi[k];
-        q.m = active ? q.m : 0.0;
-    } else {
-#pragma unroll
-        for (int k = 0; k < N; ++k) q.w[k] = s * q.xi[k];
+        q.mL = active ? ((PREC == ECT_FP32) ? m * kLog2E : m) : 0.0;
     }
     if constexpr (BWD) {
         if (active) {
-            if (KER == ECT_FOURIER) {
+            if (MASK == kF) {
                 q.gr = a.grad_out[row * 2];
                 q.gi = a.grad_out[row * 2 + 1];
             } else {
@@ -245,61 +220,35 @@ __global__ void __launch_bounds__(kHybridLanes) hybrid_kernel(HybridArgs a) {
             }
         }
     }
+}
 
-    double acc[kAccSlots] = {0.0, 0.0, 0.0, 0.0};
-    const Point* __restrict__ pts = a.points + (int64_t)l * a.capacity;
-    const int64_t c0 = p0 + c * C, c1 = min(p1, c0 + C);
-    if (np > 0) accumulate<N, KER, PREC, BWD>(pts, c0, c1, q, acc);
-
-    if (chunks > 1) {
-        double* part = a.partials + (item * kHybridLanes + lane) * kAccSlots;
-#pragma unroll
-        for (int k = 0; k < NACC; ++k) part[k] = acc[k];
-        __threadfence();
-        uint32_t old = 0;
-        if (lane == 0)
-            old = __hip_atomic_fetch_add(a.counters + a.tile_off[e] + t, 1u, __ATOMIC_ACQ_REL,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-        old = __shfl(old, 0, 64);
-        if (old != (uint32_t)(chunks - 1)) return;
-        __threadfence();
-#pragma unroll
-        for (int k = 0; k < NACC; ++k) acc[k] = 0.0;
-        const int64_t first = a.item_off[e] + t * chunks;
-        for (int64_t cc = 0; cc < chunks; ++cc) {
-            const double* pp = a.partials + ((first + cc) * kHybridLanes + lane) * kAccSlots;
-#pragma unroll
-            for (int k = 0; k < NACC; ++k) acc[k] += __builtin_nontemporal_load(pp + k);
-        }
-        if (lane == 0) a.counters[a.tile_off[e] + t] = 0u;
-    }
-    if (!active) return;
-
+// Scale the point sums of one query into its outputs.
+template <int N, int MASK, int PREC, bool BWD>
+__device__ __forceinline__ void finalize(const HybridArgs& a, const Query<N>& q, int64_t row, const double* acc) {
+    const double s = a.s;
     if constexpr (!BWD) {
-        if constexpr (KER == ECT_FOURIER) {
-            a.out[row * 2] = q.sigma * acc[0] / s;
-            a.out[row * 2 + 1] = q.sigma * acc[1] / s;
-            if (a.log_scale) a.log_scale[row] = 0.0;
-        } else if constexpr (KER == ECT_LAPLACE) {
-            const double mnat = (PREC == ECT_FP32) ? q.m / kLog2E : q.m;
-            const double shifted = -q.sigma * acc[0] / s;
+        if constexpr ((MASK & kF) != 0) {
+            a.out_f[row * 2] = q.sigma * acc[kSlotF] / s;
+            a.out_f[row * 2 + 1] = q.sigma * acc[kSlotF + 1] / s;
+        }
+        if constexpr ((MASK & kL) != 0) {
+            const double mnat = (PREC == ECT_FP32) ? q.mL / kLog2E : q.mL;
+            const double shifted = -q.sigma * acc[kSlotL] / s;
             if (a.log_scale) {
-                a.out[row] = shifted;
+                a.out_l[row] = shifted;
                 a.log_scale[row] = mnat;
             } else {
                 const double v = shifted * exp(mnat);
                 if (!isfinite(v)) raise_error(a.err, ECT_DEVERR_OVERFLOW);
-                a.out[row] = v;
+                a.out_l[row] = v;
             }
-        } else {
-            a.out[row] = q.sigma * acc[0] / s;
-            if (a.log_scale) a.log_scale[row] = 0.0;
         }
+        if constexpr ((MASK & kB) != 0) a.out_b[row] = q.sigma * acc[kSlotB] / s;
     } else {
         // G_a = sigma * sum D x_a (weighted kappa); Laplace sums carry exp(-m)
         double scale = q.sigma;
-        if constexpr (KER == ECT_LAPLACE) scale *= q.gr * exp((PREC == ECT_FP32) ? q.m / kLog2E : q.m);
-        if constexpr (KER == ECT_BESSEL) scale *= q.gr;
+        if constexpr (MASK == kL) scale *= q.gr * exp((PREC == ECT_FP32) ? q.mL / kLog2E : q.mL);
+        if constexpr (MASK == kB) scale *= q.gr;
         double dots = 0.0;
 #pragma unroll
         for (int k = 0; k < N; ++k) {
@@ -308,10 +257,120 @@ __global__ void __launch_bounds__(kHybridLanes) hybrid_kernel(HybridArgs a) {
             dots = fma(q.xi[k], G, dots);
         }
         double gy;
-        if constexpr (KER == ECT_FOURIER) gy = q.gr * a.fwd_out[row * 2] + q.gi * a.fwd_out[row * 2 + 1];
+        if constexpr (MASK == kF) gy = q.gr * a.fwd_out[row * 2] + q.gi * a.fwd_out[row * 2 + 1];
         else gy = q.gr * a.fwd_out[row];
         a.grad_s_part[row] = (dots - gy) / s;
     }
+}
+
+// Locate the entry (image, pair) of a work item or query tile by binary search
+// over a non-decreasing prefix array (the last entry whose start is <= idx).
+__device__ __forceinline__ int64_t find_entry(const int64_t* __restrict__ off, int64_t E, int64_t idx) {
+    int64_t lo = 0, hi = E - 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= idx) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Partial sums are stored slot-major inside an item so that consecutive
+// threads touch consecutive doubles.
+__device__ __forceinline__ int64_t partial_index(int64_t item, int slot, int tid) {
+    return (item * kAccSlots + slot) * kHybridThreads + tid;
+}
+
+// One workgroup per work item (image, orthant pair, tile of 256 queries, chunk
+// of points).  Each thread owns one query; the chunk's points are staged in LDS
+// kHybridStage at a time with one coalesced load per thread and then read by
+// every thread (same address across the wave: a broadcast).  A tile split into
+// several chunks writes per-query partial sums, which hybrid_reduce adds in
+// chunk order after the kernel; a single-chunk tile writes its outputs here.
+template <int N, int MASK, int PREC, bool BWD>
+__global__ void __launch_bounds__(kHybridThreads) hybrid_kernel(HybridArgs a) {
+    constexpr int P = 1 << (N - 1);
+    __shared__ Point s_pts[kHybridStage];
+    const int tid = threadIdx.x;
+    const int64_t item = blockIdx.x;
+    if (item >= a.params[0]) return;
+    const int64_t C = a.params[2];
+    const int64_t e = find_entry(a.item_off, (int64_t)a.num_images * P, item);
+    const int64_t img = e / P;
+    const int b = (int)(e % P);
+    const int64_t local = item - a.item_off[e];
+    const int l = a.list_base + b;
+    const int64_t p0 = a.list_off[img * a.NL + l], p1 = a.list_off[(img + 1) * a.NL + l];
+    const int64_t np = p1 - p0;
+    const int64_t chunks = np > 0 ? (np + C - 1) / C : 1;
+    const int64_t t = local / chunks, c = local % chunks;
+    const int64_t qn = a.bcnt[a.offsets == nullptr ? b : e];
+    const int64_t qi = t * kHybridThreads + tid;
+    const bool active = qi < qn;
+    const Point* __restrict__ pts = a.points + (int64_t)l * a.capacity;
+    const int64_t c0 = p0 + c * C, c1 = min(p1, c0 + C);
+
+    Query<N> q;
+    int64_t row;
+    setup_query<N, MASK, PREC, BWD>(a, img, b, qi, active, q, row);
+
+    double acc[kAccSlots] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t base = c0; base < c1; base += kHybridStage) {
+        const int cnt = (int)min<int64_t>(kHybridStage, c1 - base);
+        __syncthreads();
+        if (tid < cnt) s_pts[tid] = pts[base + tid];
+        __syncthreads();
+        for (int k = 0; k < cnt; ++k) accumulate_point<N, MASK, PREC, BWD>(s_pts[k], q, acc);
+    }
+
+    if (chunks > 1) {
+#pragma unroll
+        for (int k = 0; k < kAccSlots; ++k)
+            if (slot_used<MASK, BWD, N>(k)) a.partials[partial_index(item, k, tid)] = acc[k];
+        return;
+    }
+    if (active) finalize<N, MASK, PREC, BWD>(a, q, row, acc);
+}
+
+// One workgroup per query tile: add the partial sums of a multi-chunk tile in
+// chunk order and write the outputs (single-chunk tiles were written already).
+template <int N, int MASK, int PREC, bool BWD>
+__global__ void __launch_bounds__(kHybridThreads) hybrid_reduce_kernel(HybridArgs a) {
+    constexpr int P = 1 << (N - 1);
+    const int tid = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    if (tile >= a.params[1]) return;
+    const int64_t C = a.params[2];
+    const int64_t e = find_entry(a.tile_off, (int64_t)a.num_images * P, tile);
+    const int64_t img = e / P;
+    const int b = (int)(e % P);
+    const int64_t t = tile - a.tile_off[e];
+    const int l = a.list_base + b;
+    const int64_t np = a.list_off[(img + 1) * a.NL + l] - a.list_off[img * a.NL + l];
+    const int64_t chunks = np > 0 ? (np + C - 1) / C : 1;
+    if (chunks == 1) return;
+    const int64_t qn = a.bcnt[a.offsets == nullptr ? b : e];
+    const int64_t qi = t * kHybridThreads + tid;
+    if (qi >= qn) return;
+    Query<N> q;
+    int64_t row;
+    setup_query<N, MASK, PREC, BWD>(a, img, b, qi, true, q, row);
+    double acc[kAccSlots] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t first = a.item_off[e] + t * chunks;
+    constexpr int BATCH = 16;
+    for (int64_t cc = 0; cc < chunks; cc += BATCH) {
+        double v[BATCH][kAccSlots];
+#pragma unroll
+        for (int j = 0; j < BATCH; ++j)
+#pragma unroll
+            for (int k = 0; k < kAccSlots; ++k)
+                v[j][k] = (slot_used<MASK, BWD, N>(k) && cc + j < chunks)
+                              ? a.partials[partial_index(first + cc + j, k, tid)] : 0.0;
+#pragma unroll
+        for (int j = 0; j < BATCH; ++j)
+#pragma unroll
+            for (int k = 0; k < kAccSlots; ++k) acc[k] += v[j][k];
+    }
+    finalize<N, MASK, PREC, BWD>(a, q, row, acc);
 }
 
 // Sum per-image gradient rows of a shared query set in image order, and the
@@ -348,45 +407,59 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v)
         p[i] = v;
 }
 
-template <int N, bool BWD>
-hipError_t launch_n(int kernel, int precision, const HybridArgs& a, int64_t grid, hipStream_t stream) {
-    dim3 g((unsigned)grid), blk(kHybridLanes);
-#define ECT_HYB(K, PR) hipLaunchKernelGGL((hybrid_kernel<N, K, PR, BWD>), g, blk, 0, stream, a)
+template <int N, int MASK, bool BWD>
+hipError_t launch_mask(int precision, const HybridArgs& a, int64_t grid, bool reduce, hipStream_t stream) {
+    dim3 g((unsigned)grid), blk(kHybridThreads);
     if (precision == ECT_FP32) {
-        if (kernel == ECT_FOURIER) ECT_HYB(ECT_FOURIER, ECT_FP32);
-        else if (kernel == ECT_LAPLACE) ECT_HYB(ECT_LAPLACE, ECT_FP32);
-        else ECT_HYB(ECT_BESSEL, ECT_FP32);
+        if (reduce) hipLaunchKernelGGL((hybrid_reduce_kernel<N, MASK, ECT_FP32, BWD>), g, blk, 0, stream, a);
+        else hipLaunchKernelGGL((hybrid_kernel<N, MASK, ECT_FP32, BWD>), g, blk, 0, stream, a);
     } else {
-        if (kernel == ECT_FOURIER) ECT_HYB(ECT_FOURIER, ECT_FP64);
-        else if (kernel == ECT_LAPLACE) ECT_HYB(ECT_LAPLACE, ECT_FP64);
-        else ECT_HYB(ECT_BESSEL, ECT_FP64);
+        if (reduce) hipLaunchKernelGGL((hybrid_reduce_kernel<N, MASK, ECT_FP64, BWD>), g, blk, 0, stream, a);
+        else hipLaunchKernelGGL((hybrid_kernel<N, MASK, ECT_FP64, BWD>), g, blk, 0, stream, a);
     }
-#undef ECT_HYB
     return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_dispatch(unsigned mask, int precision, bool backward, const HybridArgs& a, int64_t grid,
+                           bool reduce, hipStream_t stream) {
+    if (backward) {
+        switch (mask) {
+            case kF: return launch_mask<N, kF, true>(precision, a, grid, reduce, stream);
+            case kL: return launch_mask<N, kL, true>(precision, a, grid, reduce, stream);
+            default: return launch_mask<N, kB, true>(precision, a, grid, reduce, stream);
+        }
+    }
+    switch (mask) {
+        case 1: return launch_mask<N, 1, false>(precision, a, grid, reduce, stream);
+        case 2: return launch_mask<N, 2, false>(precision, a, grid, reduce, stream);
+        case 3: return launch_mask<N, 3, false>(precision, a, grid, reduce, stream);
+        case 4: return launch_mask<N, 4, false>(precision, a, grid, reduce, stream);
+        case 5: return launch_mask<N, 5, false>(precision, a, grid, reduce, stream);
+        case 6: return launch_mask<N, 6, false>(precision, a, grid, reduce, stream);
+        default: return launch_mask<N, 7, false>(precision, a, grid, reduce, stream);
+    }
 }
 
 }  // namespace
 
-hipError_t launch_hybrid_fwd(int ndim, int kernel, int precision, const HybridArgs& a, int64_t grid,
-                             hipStream_t stream) {
-    if (grid <= 0) return hipSuccess;
-    hipError_t e = stage_mark(ECT_STAGE_HYBRID, false, stream);
-    if (e != hipSuccess) return e;
-    e = ndim == 2 ? launch_n<2, false>(kernel, precision, a, grid, stream)
-                  : launch_n<3, false>(kernel, precision, a, grid, stream);
-    if (e != hipSuccess) return e;
-    return stage_mark(ECT_STAGE_HYBRID, true, stream);
-}
-
-hipError_t launch_hybrid_bwd(int ndim, int kernel, int precision, const HybridArgs& a, int64_t grid,
-                             hipStream_t stream) {
-    if (grid <= 0) return hipSuccess;
-    hipError_t e = stage_mark(ECT_STAGE_HYBRID_BWD, false, stream);
-    if (e != hipSuccess) return e;
-    e = ndim == 2 ? launch_n<2, true>(kernel, precision, a, grid, stream)
-                  : launch_n<3, true>(kernel, precision, a, grid, stream);
-    if (e != hipSuccess) return e;
-    return stage_mark(ECT_STAGE_HYBRID_BWD, true, stream);
+hipError_t launch_hybrid(int ndim, unsigned mask, int precision, bool backward, const HybridArgs& a,
+                         int64_t grid, int64_t tiles, hipStream_t stream) {
+    const int stage = backward ? ECT_STAGE_HYBRID_BWD : ECT_STAGE_HYBRID;
+    hipError_t e = hipSuccess;
+    if (grid > 0) {
+        e = stage_mark(stage, false, stream);
+        if (e != hipSuccess) return e;
+        e = ndim == 2 ? launch_dispatch<2>(mask, precision, backward, a, grid, false, stream)
+                      : launch_dispatch<3>(mask, precision, backward, a, grid, false, stream);
+        if (e != hipSuccess) return e;
+        e = stage_mark(stage, true, stream);
+        if (e != hipSuccess) return e;
+    }
+    if (tiles > 0)
+        e = ndim == 2 ? launch_dispatch<2>(mask, precision, backward, a, tiles, true, stream)
+                      : launch_dispatch<3>(mask, precision, backward, a, tiles, true, stream);
+    return e;
 }
 
 hipError_t launch_grad_reduce(int ndim, const double* part, int num_images, int64_t count, bool shared,

@@ -19,8 +19,8 @@
 // Compaction is single pass and ordered: every workgroup takes the next tile
 // id from a counter, counts its nonzero values per list with wave ballots,
 // publishes the counts and resolves its global offset by decoupled look-back
-// over the preceding tiles (one lane per list), then writes its entries in
-// vertex order.  Lists therefore come out sorted by linear vertex index, and
+// over the preceding tiles (a wave inspects 64 predecessors per round for every
+// list at once), then writes its entries in vertex order.  Lists therefore come out sorted by linear vertex index, and
 // identically on every run.
 #include "ect_internal.h"
 
@@ -249,41 +249,88 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
     }
     __syncthreads();
 
-    if (tid < NL) {
-        const int l = tid;
-        int32_t run = 0;
+    if (wave == 0) {
+        // tile aggregates (lane l < NL owns list l); per-(round, wave) counts become
+        // exclusive offsets inside the tile
+        uint64_t agg = 0;
+        if (lane < NL) {
+            int32_t run = 0;
 #pragma unroll
-        for (int j = 0; j < J; ++j)
+            for (int j = 0; j < J; ++j)
 #pragma unroll
-            for (int w = 0; w < W; ++w) {
-                int32_t c = s_cnt[j][w][l];
-                s_cnt[j][w][l] = run;
-                run += c;
+                for (int w = 0; w < W; ++w) {
+                    int32_t c = s_cnt[j][w][lane];
+                    s_cnt[j][w][lane] = run;
+                    run += c;
+                }
+            agg = (uint64_t)run;
+            if (tile > 0)
+                __hip_atomic_store(status + tile * NL + lane, kFlagAggregate | agg, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // Decoupled look-back, one window of 64 predecessor tiles per round and
+        // list: lane i inspects tile base - i.  A status word carries both its
+        // flag and its count, so relaxed device-scope atomics suffice (no fence,
+        // hence no L2 write-back between the chip's non-coherent L2 slices);
+        // the list entries are only read by later kernels.  The nearest tile holding an
+        // inclusive prefix ends the walk; every tile in front of it must have
+        // published its aggregate (otherwise the window is read again).
+        uint64_t excl[NL];
+        int64_t wbase[NL];
+        bool done[NL];
+#pragma unroll
+        for (int l = 0; l < NL; ++l) { excl[l] = 0; wbase[l] = tile - 1; done[l] = tile == 0; }
+        int spins = 0;
+        bool all_done = tile == 0;
+        while (!all_done) {
+            uint64_t wv[NL];
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                const int64_t j = wbase[l] - lane;
+                wv[l] = (!done[l] && j >= 0)
+                            ? __hip_atomic_load(status + j * NL + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                            : (kFlagInclusive | 0ull);
             }
-        const uint64_t agg = (uint64_t)run;
-        uint64_t* st = status + tile * NL + l;
-        uint64_t excl = 0;
-        if (tile > 0) {
-            __hip_atomic_store(st, kFlagAggregate | agg, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            int64_t j = tile - 1;
-            int spins = 0;
-            while (true) {
-                uint64_t w = __hip_atomic_load(status + j * NL + l, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                uint64_t f = w & ~kValueMask;
-                if (f == 0) {
-                    if (++spins > kLookbackSpinLimit) { raise_error(err, ECT_DEVERR_LOOKBACK); break; }
-                    __builtin_amdgcn_s_sleep(1);
+            bool waiting = false;
+            all_done = true;
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                if (done[l]) continue;
+                const uint64_t f = wv[l] & ~kValueMask;
+                const uint64_t incl = __ballot(f == kFlagInclusive);
+                const uint64_t notready = __ballot(f == 0);
+                const int first = incl ? (int)__ffsll((unsigned long long)incl) - 1 : 64;
+                const uint64_t upto = first >= 63 ? ~0ull : ((1ull << (first + 1)) - 1ull);
+                if (notready & upto) {
+                    waiting = true;
+                    all_done = false;
                     continue;
                 }
-                excl += w & kValueMask;
-                if (f == kFlagInclusive) break;
-                --j;
+                uint64_t v = (lane <= first) ? (wv[l] & kValueMask) : 0ull;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                excl[l] += v;
+                if (first < 64) done[l] = true;
+                else { wbase[l] -= 64; all_done = false; }
+            }
+            if (waiting) {
+                if (++spins > kLookbackSpinLimit) {
+                    if (lane == 0) raise_error(err, ECT_DEVERR_LOOKBACK);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
             }
         }
-        __hip_atomic_store(st, kFlagInclusive | (excl + agg), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        s_base[l] = (int64_t)excl;
-        if (tile == d.tile_start) list_off[(int64_t)img_id * NL + l] = (int64_t)excl;
-        if (tile == num_tiles - 1) list_off[(int64_t)num_images * NL + l] = (int64_t)(excl + agg);
+        if (lane < NL) {
+            uint64_t mine = 0;
+#pragma unroll
+            for (int l = 0; l < NL; ++l) if (lane == l) mine = excl[l];
+            __hip_atomic_store(status + tile * NL + lane, kFlagInclusive | (mine + agg), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            s_base[lane] = (int64_t)mine;
+            if (tile == d.tile_start) list_off[(int64_t)img_id * NL + lane] = (int64_t)mine;
+            if (tile == num_tiles - 1) list_off[(int64_t)num_images * NL + lane] = (int64_t)(mine + agg);
+        }
     }
     __syncthreads();
 

@@ -9,210 +9,276 @@
 // Hybrid mode: 2^(n-1) buckets, one per pair {eps, -eps}; a query whose
 // eps_{n-1} = -1 is evaluated on the list of -eps with negated values, because
 // Delta^ord(-eps, x) = -Delta^ord(eps, x).  The negation is carried as bit 0 of
-// the permutation entry (entry = 2 * row + negated).
+// the record code (code = 2 * row + negated).
+//
+// Bucket b of image i owns the record slots [B*r0_i + b*Q_i, B*r0_i + (b+1)*Q_i)
+// (r0_i = first query row of the image, Q_i = its number of queries), so every
+// query finds its slot with one atomic increment and no prefix sum.  The order
+// inside a bucket is therefore not fixed, but no result depends on it: every
+// query is evaluated independently and in a fixed order over the points.
 #include "eval_internal.h"
 
 namespace ect {
 
 namespace {
 
-// One workgroup per image (ragged set) or a single workgroup (shared set).
-// Stable: inside a bucket, queries keep their row order.
+// Slot of this lane in counters[key] (global or LDS), with one atomic per
+// distinct key of the wave instead of one per lane.  Every lane of the wave
+// must call it; lanes with !valid get 0.
+template <typename Ctr>
+__device__ __forceinline__ int aggregated_add(Ctr* counters, int key, bool valid) {
+    const int lane = threadIdx.x & 63;
+    uint64_t pending = __ballot(valid);
+    int slot = 0;
+    while (pending) {
+        const int leader = (int)__ffsll((unsigned long long)pending) - 1;
+        const int lkey = __shfl(key, leader, 64);
+        const uint64_t m = __ballot(valid && key == lkey);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(counters + lkey, (int)__popcll(m));
+        base = __shfl(base, leader, 64);
+        if (valid && key == lkey) slot = base + (int)__popcll(m & ((1ull << lane) - 1ull));
+        pending &= ~m;
+    }
+    return slot;
+}
+
+// Bucket key and record of query row r: returns the (image, bucket) entry.
 template <int N>
-__global__ void __launch_bounds__(kBucketThreads)
-bucket_kernel(const double* __restrict__ vecs, const int64_t* __restrict__ offsets, int64_t count,
-              int mode_hybrid, uint32_t* __restrict__ err, int64_t* __restrict__ perm,
-              int64_t* __restrict__ bstart, int32_t* __restrict__ bcnt) {
+__device__ __forceinline__ int64_t classify_query(const double* __restrict__ vecs, const int64_t* __restrict__ offsets,
+                                                  int64_t r, int64_t rows, int num_images, int mode_hybrid,
+                                                  uint32_t* __restrict__ err, QRec* rec, int64_t* slot_base) {
     const int B = mode_hybrid ? (1 << (N - 1)) : (1 << N);
     const int full = (1 << N) - 1;
-    const int img = blockIdx.x;
-    const int64_t r0 = offsets ? offsets[img] : 0;
-    const int64_t r1 = offsets ? offsets[img + 1] : count;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    constexpr int W = kBucketThreads / 64;
-
-    __shared__ int32_t s_wc[W][8];
-    __shared__ int64_t s_run[8];
-    __shared__ int64_t s_start[8];
-
-    auto key_of = [&](int64_t r, int* neg) -> int {
-        double xi[N];
-        bool fin = true;
+    int img = 0;
+    int64_t r0 = 0, q = rows;
+    if (offsets) {
+        int lo = 0, hi = num_images - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (offsets[mid] <= r) lo = mid; else hi = mid - 1;
+        }
+        img = lo;
+        r0 = offsets[img];
+        q = offsets[img + 1] - r0;
+    }
+    bool fin = true;
 #pragma unroll
-        for (int a = 0; a < N; ++a) {
-            xi[a] = vecs[r * N + a];
-            fin = fin && isfinite(xi[a]);
-        }
-        if (!fin) raise_error(err, ECT_DEVERR_NONFINITE);
-        int e = sign_index<N>(xi);
-        *neg = 0;
-        if (mode_hybrid && (e >> (N - 1)) & 1) { e ^= full; *neg = 1; }
-        return e;
-    };
+    for (int a = 0; a < 3; ++a) {
+        rec->v[a] = a < N ? vecs[r * N + a] : 0.0;
+        fin = fin && isfinite(rec->v[a]);
+    }
+    if (!fin) raise_error(err, ECT_DEVERR_NONFINITE);
+    int e = sign_index<N>(rec->v);
+    int neg = 0;
+    if (mode_hybrid && ((e >> (N - 1)) & 1)) { e ^= full; neg = 1; }
+    rec->code = 2 * (r - r0) + neg;
+    *slot_base = B * r0 + e * q;
+    return (int64_t)img * B + e;
+}
 
-    // pass 1: counts
-    if (tid < 8) s_run[tid] = 0;
-    __syncthreads();
-    for (int64_t base = r0; base < r1; base += kBucketThreads) {
-        int64_t r = base + tid;
-        int key = -1, neg = 0;
-        if (r < r1) key = key_of(r, &neg);
-        for (int b = 0; b < B; ++b) {
-            uint64_t m = __ballot(key == b);
-            if (lane == 0) s_wc[wave][b] = __popcll(m);
-        }
-        __syncthreads();
-        if (tid < B) {
-            int64_t c = 0;
-            for (int w = 0; w < W; ++w) c += s_wc[w][tid];
-            s_run[tid] += c;
-        }
-        __syncthreads();
+template <int N>
+__global__ void __launch_bounds__(kBucketThreads)
+bucket_kernel(const double* __restrict__ vecs, const int64_t* __restrict__ offsets, int64_t rows,
+              int num_images, int mode_hybrid, uint32_t* __restrict__ err, QRec* __restrict__ recs,
+              int32_t* __restrict__ bcnt) {
+    const int64_t r = (int64_t)blockIdx.x * kBucketThreads + threadIdx.x;
+    const bool valid = r < rows;
+    QRec rec;
+    int64_t sbase = 0, ent = 0;
+    if (valid) ent = classify_query<N>(vecs, offsets, r, rows, num_images, mode_hybrid, err, &rec, &sbase);
+    const int slot = aggregated_add(bcnt, (int)ent, valid);
+    if (valid) recs[sbase + slot] = rec;
+}
+
+// Exclusive scan of two int64 values per thread over a 1024-thread block.
+__device__ __forceinline__ void block_exclusive_scan2(int64_t& a, int64_t& b, int64_t* tot_a, int64_t* tot_b,
+                                                      int64_t* s_a, int64_t* s_b) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int64_t ia = a, ib = b;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int64_t ta = __shfl_up(ia, off, 64), tb = __shfl_up(ib, off, 64);
+        if (lane >= off) { ia += ta; ib += tb; }
     }
+    if (lane == 63) { s_a[wave] = ia; s_b[wave] = ib; }
+    __syncthreads();
     if (tid == 0) {
-        int64_t acc = r0;
-        for (int b = 0; b < B; ++b) {
-            s_start[b] = acc;
-            bstart[(int64_t)img * B + b] = acc;
-            bcnt[(int64_t)img * B + b] = (int32_t)s_run[b];
-            acc += s_run[b];
-            s_run[b] = 0;
+        int64_t ra = 0, rb = 0;
+        for (int w = 0; w < 16; ++w) {
+            int64_t ca = s_a[w], cb = s_b[w];
+            s_a[w] = ra;
+            s_b[w] = rb;
+            ra += ca;
+            rb += cb;
         }
+        s_a[16] = ra;
+        s_b[16] = rb;
     }
     __syncthreads();
-    // pass 2: stable scatter
-    for (int64_t base = r0; base < r1; base += kBucketThreads) {
-        int64_t r = base + tid;
-        int key = -1, neg = 0;
-        if (r < r1) key = key_of(r, &neg);
-        int rank = 0;
-        for (int b = 0; b < B; ++b) {
-            uint64_t m = __ballot(key == b);
-            if (lane == 0) s_wc[wave][b] = __popcll(m);
-            if (key == b) rank = __popcll(m & ((1ull << lane) - 1ull));
-        }
-        __syncthreads();
-        if (key >= 0) {
-            int64_t pos = s_start[key] + s_run[key] + rank;
-            for (int w = 0; w < wave; ++w) pos += s_wc[w][key];
-            perm[pos] = 2 * (r - r0) + neg;   // row relative to the image's first row
-        }
-        __syncthreads();
-        if (tid < B) {
-            int64_t c = 0;
-            for (int w = 0; w < W; ++w) c += s_wc[w][tid];
-            s_run[tid] += c;
-        }
-        __syncthreads();
-    }
+    a = s_a[wave] + ia - a;
+    b = s_b[wave] + ib - b;
+    *tot_a = s_a[16];
+    *tot_b = s_b[16];
+    __syncthreads();
 }
 
 // Work list: items of entry (i, b) = ceil(bucket count / qtile) query tiles,
 // each split into ceil(points / chunk) point chunks (chunk == 0: no split).
-// Writes the item prefix over entries, the query-tile prefix (for the
-// reduction counters) and the chunk size actually used.  If the item count
-// exceeds `capacity`, the chunk size is doubled until it fits.
+// Writes the item prefix over entries, the query-tile prefix and the chunk
+// size actually used.  If the item count exceeds `capacity`, the chunk size is
+// doubled until it fits.  Runs on one 1024-thread workgroup.
+__device__ void build_worklist(int num_images, int B, int list_base, int NL, int shared_queries,
+                               const int32_t* bcnt, const int64_t* __restrict__ list_off, int qtile,
+                               int64_t chunk0, int64_t capacity, uint32_t* __restrict__ err,
+                               int64_t* __restrict__ item_off, int64_t* __restrict__ tile_off,
+                               int64_t* __restrict__ params) {
+    __shared__ int64_t s_a[17], s_b[17];
+    __shared__ int64_t s_red[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t E = (int64_t)num_images * B;
+    auto entry = [&](int64_t e, int64_t chunk, int64_t* items, int64_t* tiles) {
+        const int64_t i = e / B, b = e % B;
+        const int64_t q = bcnt[shared_queries ? b : e];
+        const int64_t t = (q + qtile - 1) / qtile;
+        const int64_t np = list_off[(i + 1) * NL + list_base + b] - list_off[i * NL + list_base + b];
+        int64_t ch = chunk > 0 ? (np + chunk - 1) / chunk : 1;
+        if (ch < 1) ch = 1;  // an empty list still gets one item per tile, which writes zeros
+        *items = t * ch;
+        *tiles = t;
+    };
+    int64_t chunk = chunk0;
+    if (chunk > 0 && capacity > 0) {
+        for (int attempt = 0; attempt < 40; ++attempt) {
+            int64_t my = 0;
+            for (int64_t e = tid; e < E; e += 1024) {
+                int64_t it, tl;
+                entry(e, chunk, &it, &tl);
+                my += it;
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) my += __shfl_xor(my, off, 64);
+            if (lane == 0) s_red[wave] = my;
+            __syncthreads();
+            int64_t total = 0;
+            for (int w = 0; w < 16; ++w) total += s_red[w];
+            __syncthreads();
+            if (total <= capacity) break;
+            chunk *= 2;
+            if (attempt == 39) {
+                if (tid == 0) {
+                    raise_error(err, ECT_DEVERR_CAPACITY);
+                    params[0] = 0;
+                    params[1] = 0;
+                    params[2] = chunk;
+                    item_off[E] = 0;
+                    tile_off[E] = 0;
+                }
+                return;
+            }
+        }
+    }
+    int64_t carry_i = 0, carry_t = 0;
+    for (int64_t base = 0; base < E; base += 1024) {
+        const int64_t e = base + tid;
+        int64_t it = 0, tl = 0;
+        if (e < E) entry(e, chunk, &it, &tl);
+        int64_t tot_i, tot_t;
+        block_exclusive_scan2(it, tl, &tot_i, &tot_t, s_a, s_b);
+        if (e < E) {
+            item_off[e] = carry_i + it;
+            tile_off[e] = carry_t + tl;
+        }
+        carry_i += tot_i;
+        carry_t += tot_t;
+    }
+    if (tid == 0) {
+        item_off[E] = carry_i;
+        tile_off[E] = carry_t;
+        params[0] = carry_i;
+        params[1] = carry_t;
+        params[2] = chunk;
+    }
+}
+
 __global__ void __launch_bounds__(1024)
 worklist_kernel(int num_images, int B, int list_base, int NL, int shared_queries,
                 const int32_t* __restrict__ bcnt, const int64_t* __restrict__ list_off,
                 int qtile, int64_t chunk0, int64_t capacity, uint32_t* __restrict__ err,
                 int64_t* __restrict__ item_off, int64_t* __restrict__ tile_off,
                 int64_t* __restrict__ params) {
-    __shared__ int64_t s_part[1024];
-    __shared__ int64_t s_tpart[1024];
-    __shared__ int64_t s_total[2];
+    build_worklist(num_images, B, list_base, NL, shared_queries, bcnt, list_off, qtile, chunk0, capacity, err,
+                   item_off, tile_off, params);
+}
+
+// Small query sets: bucketing with LDS counters and the work list in one
+// 1024-thread workgroup (one launch instead of three).
+template <int N>
+__global__ void __launch_bounds__(1024)
+prepare_small_kernel(const double* __restrict__ vecs, const int64_t* __restrict__ offsets, int64_t rows,
+                     int num_images, int mode_hybrid, uint32_t* __restrict__ err, QRec* __restrict__ recs,
+                     int32_t* __restrict__ bcnt, const int64_t* __restrict__ list_off, int list_base, int NL,
+                     int qtile, int64_t chunk0, int64_t capacity, int64_t* __restrict__ item_off,
+                     int64_t* __restrict__ tile_off, int64_t* __restrict__ params) {
+    __shared__ int32_t s_cnt[kSmallMaxEntries];
+    const int B = mode_hybrid ? (1 << (N - 1)) : (1 << N);
+    const int groups = offsets ? num_images : 1;
+    const int E = groups * B;
     const int tid = threadIdx.x;
-    const int64_t E = (int64_t)num_images * B;
-    int64_t chunk = chunk0;
-    for (int attempt = 0; attempt < 40; ++attempt) {
-        // per-thread contiguous range of entries
-        const int64_t per = (E + 1023) / 1024;
-        const int64_t e0 = tid * per, e1 = min(E, e0 + per);
-        int64_t my = 0, myt = 0;
-        for (int64_t e = e0; e < e1; ++e) {
-            int64_t i = e / B, b = e % B;
-            int64_t q = bcnt[shared_queries ? b : e];
-            int64_t tiles = (q + qtile - 1) / qtile;
-            int64_t np = list_off[(i + 1) * NL + list_base + b] - list_off[i * NL + list_base + b];
-            int64_t ch = chunk > 0 ? (np + chunk - 1) / chunk : 1;
-            if (ch < 1) ch = 1;  // an empty list still gets one item per tile, which writes zeros
-            my += tiles * ch;
-            myt += tiles;
-        }
-        s_part[tid] = my;
-        s_tpart[tid] = myt;
-        __syncthreads();
-        if (tid == 0) {
-            int64_t acc = 0, tacc = 0;
-            for (int t = 0; t < 1024; ++t) {
-                int64_t c = s_part[t], ct = s_tpart[t];
-                s_part[t] = acc;
-                s_tpart[t] = tacc;
-                acc += c;
-                tacc += ct;
-            }
-            s_total[0] = acc;
-            s_total[1] = tacc;
-        }
-        __syncthreads();
-        const int64_t total = s_total[0];
-        if (capacity <= 0 || total <= capacity || chunk == 0) {
-            int64_t run = s_part[tid], trun = s_tpart[tid];
-            for (int64_t e = e0; e < e1; ++e) {
-                int64_t i = e / B, b = e % B;
-                int64_t q = bcnt[shared_queries ? b : e];
-                int64_t tiles = (q + qtile - 1) / qtile;
-                int64_t np = list_off[(i + 1) * NL + list_base + b] - list_off[i * NL + list_base + b];
-                int64_t ch = chunk > 0 ? (np + chunk - 1) / chunk : 1;
-                if (ch < 1) ch = 1;
-                item_off[e] = run;
-                tile_off[e] = trun;
-                run += tiles * ch;
-                trun += tiles;
-            }
-            if (tid == 0) {
-                item_off[E] = total;
-                tile_off[E] = s_total[1];
-                params[0] = total;
-                params[1] = s_total[1];
-                params[2] = chunk;
-            }
-            return;
-        }
-        chunk *= 2;
-        __syncthreads();
+    for (int i = tid; i < E; i += 1024) s_cnt[i] = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < rows; base += 1024) {
+        const int64_t r = base + tid;
+        const bool valid = r < rows;
+        QRec rec;
+        int64_t sbase = 0, ent = 0;
+        if (valid) ent = classify_query<N>(vecs, offsets, r, rows, num_images, mode_hybrid, err, &rec, &sbase);
+        const int slot = aggregated_add(s_cnt, (int)ent, valid);
+        if (valid) recs[sbase + slot] = rec;
     }
-    if (tid == 0) {
-        raise_error(err, ECT_DEVERR_CAPACITY);
-        params[0] = 0;
-        params[1] = 0;
-        params[2] = chunk;
-        item_off[E] = 0;
-        tile_off[E] = 0;
-    }
+    __syncthreads();
+    for (int i = tid; i < E; i += 1024) bcnt[i] = s_cnt[i];
+    build_worklist(num_images, B, list_base, NL, offsets == nullptr ? 1 : 0, s_cnt, list_off, qtile, chunk0,
+                   capacity, err, item_off, tile_off, params);
 }
 
 }  // namespace
 
-hipError_t launch_bucket(int ndim, const ect_query_set& qs, int num_images, bool hybrid, uint32_t* err,
-                         int64_t* perm, int64_t* bstart, int32_t* bcnt, hipStream_t stream) {
+hipError_t launch_prepare(int ndim, const ect_query_set& qs, int num_images, bool hybrid, uint32_t* err,
+                          QRec* recs, int32_t* bcnt, const int64_t* list_off, int list_base, int NL, int qtile,
+                          int64_t chunk, int64_t capacity, int64_t* item_off, int64_t* tile_off, int64_t* params,
+                          hipStream_t stream) {
+    const int B = hybrid ? (1 << (ndim - 1)) : (1 << ndim);
+    const int64_t rows = qs.count;  // shared: the set itself; ragged: all rows
     const int groups = qs.offsets ? num_images : 1;
-    if (ndim == 2)
-        hipLaunchKernelGGL(bucket_kernel<2>, dim3(groups), dim3(kBucketThreads), 0, stream, qs.vecs, qs.offsets,
-                           qs.count, hybrid ? 1 : 0, err, perm, bstart, bcnt);
-    else
-        hipLaunchKernelGGL(bucket_kernel<3>, dim3(groups), dim3(kBucketThreads), 0, stream, qs.vecs, qs.offsets,
-                           qs.count, hybrid ? 1 : 0, err, perm, bstart, bcnt);
-    return hipGetLastError();
-}
-
-hipError_t launch_worklist(int num_images, int B, int list_base, int NL, bool shared_queries,
-                           const int32_t* bcnt, const int64_t* list_off, int qtile, int64_t chunk,
-                           int64_t capacity, uint32_t* err, int64_t* item_off, int64_t* tile_off,
-                           int64_t* params, hipStream_t stream) {
+    const bool shared = qs.offsets == nullptr;
+    if (rows <= kSmallMaxRows && (int64_t)groups * B <= kSmallMaxEntries) {
+        if (ndim == 2)
+            hipLaunchKernelGGL(prepare_small_kernel<2>, dim3(1), dim3(1024), 0, stream, qs.vecs, qs.offsets, rows,
+                               num_images, hybrid ? 1 : 0, err, recs, bcnt, list_off, list_base, NL, qtile, chunk,
+                               capacity, item_off, tile_off, params);
+        else
+            hipLaunchKernelGGL(prepare_small_kernel<3>, dim3(1), dim3(1024), 0, stream, qs.vecs, qs.offsets, rows,
+                               num_images, hybrid ? 1 : 0, err, recs, bcnt, list_off, list_base, NL, qtile, chunk,
+                               capacity, item_off, tile_off, params);
+        return hipGetLastError();
+    }
+    hipError_t e = launch_fill_u32((uint32_t*)bcnt, (int64_t)groups * B, 0u, stream);
+    if (e != hipSuccess) return e;
+    if (rows > 0) {
+        const unsigned blocks = (unsigned)((rows + kBucketThreads - 1) / kBucketThreads);
+        const int ni = qs.offsets ? num_images : 1;
+        if (ndim == 2)
+            hipLaunchKernelGGL(bucket_kernel<2>, dim3(blocks), dim3(kBucketThreads), 0, stream, qs.vecs, qs.offsets,
+                               rows, ni, hybrid ? 1 : 0, err, recs, bcnt);
+        else
+            hipLaunchKernelGGL(bucket_kernel<3>, dim3(blocks), dim3(kBucketThreads), 0, stream, qs.vecs, qs.offsets,
+                               rows, ni, hybrid ? 1 : 0, err, recs, bcnt);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(worklist_kernel, dim3(1), dim3(1024), 0, stream, num_images, B, list_base, NL,
-                       shared_queries ? 1 : 0, bcnt, list_off, qtile, chunk, capacity, err, item_off,
-                       tile_off, params);
+                       shared ? 1 : 0, bcnt, list_off, qtile, chunk, capacity, err, item_off, tile_off, params);
     return hipGetLastError();
 }
 

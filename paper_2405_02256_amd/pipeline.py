@@ -4,7 +4,8 @@
 call to ``run()`` enqueues the complete hot path on the current stream --
 precompute kernels (classification and ordered compaction), sign-vector
 bucketing, the exact ECT, the hybrid transforms for every requested kernel
-and, optionally, one backward pass -- without allocating, copying or
+(fused into one pass over the (query, point) pairs by default) and,
+optionally, one backward pass -- without allocating, copying or
 synchronising.  ``capture()`` records that sequence once into a HIP graph
 (through torch.cuda.CUDAGraph) so that a replay costs one launch.
 """
@@ -19,7 +20,7 @@ class Step:
     def __init__(self, plan: Plan, ect_dirs=None, ect_thresholds=None, hybrid_xi=None, kernels=("fourier",),
                  s: float = 1.0, precision: str = "fp32", ect_offsets=None, hybrid_offsets=None,
                  backward_kernel: str | None = None, grad_out: torch.Tensor | None = None,
-                 log_scale_laplace: bool = False, rerun_precompute: bool = True):
+                 log_scale_laplace: bool = False, rerun_precompute: bool = True, fused: bool = True):
         self.plan = plan
         dev = plan.device
         self.rerun_precompute = rerun_precompute
@@ -30,6 +31,7 @@ class Step:
         self.s = float(s)
         self.precision = precision
         self.log_scale_laplace = log_scale_laplace
+        self.fused = fused
         if self.ect_q is not None:
             self.ect_q.validate(plan.num_images, plan.ndim)
             rows = self.ect_q.rows(plan.num_images)
@@ -59,12 +61,16 @@ class Step:
             p.rerun(stream)
         if self.ect_q is not None:
             p.ect(self.ect_q, self.ect_thr, out=self.ect_out, stream=stream)
-        for k in self.kernels:
-            if k in self.hy_ls:
-                p.hybrid(self.hy_q, k, self.s, self.precision, out=self.hy_out[k], log_scale_out=self.hy_ls[k],
-                         stream=stream)
-            else:
-                p.hybrid(self.hy_q, k, self.s, self.precision, out=self.hy_out[k], stream=stream)
+        if self.fused and len(self.kernels) > 1:
+            p.hybrid_multi(self.hy_q, self.kernels, self.s, self.precision, outs=self.hy_out,
+                           log_scale_out=self.hy_ls.get("laplace"), stream=stream)
+        else:
+            for k in self.kernels:
+                if k in self.hy_ls:
+                    p.hybrid(self.hy_q, k, self.s, self.precision, out=self.hy_out[k],
+                             log_scale_out=self.hy_ls[k], stream=stream)
+                else:
+                    p.hybrid(self.hy_q, k, self.s, self.precision, out=self.hy_out[k], stream=stream)
         if self.backward_kernel is not None:
             p.hybrid_backward(self.hy_q, self.hy_out[self.backward_kernel], self.grad_out, self.backward_kernel,
                               self.s, self.precision, stream=stream, grad_xi=self.grad_xi, grad_s=self.grad_s)

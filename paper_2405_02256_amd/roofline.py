@@ -8,21 +8,23 @@ peak; packed FP32 is not used (disabled at build time).
 
 Work per (query, critical point) pair is counted in VALU issue slots of the
 minimal arithmetic the method needs on this path, with a quarter-rate
-transcendental (sin, cos, exp2, rcp, rsq) counted as 4 slots:
+transcendental (sin, cos, exp2, rcp, rsq) counted as 4 slots.  The projection
+u = <xi, x> costs 2n-1 (one mul, n-1 fmas) and is shared by every kernel of a
+fused pass; then per kernel:
 
-  Fourier forward   phase 2n-1 (mul + fmas), reduction to [0,1) 2 (floor, sub),
-                    cvt 1, sin 4, cos 4, 2 x (cvt + fma) 4          -> 2n + 14
-  Laplace forward   exponent n (fmas incl. shift), split 2 (floor, sub), cvt 1,
-                    exp2 4, cvt 1, cvt-to-int 1, ldexp 1, fma 1     -> n + 11
-  Bessel forward    |z| < 8: phase 2n-1, v 2, degree-9 Horner 10, scale 1,
-                    cvt 2, sign 1, fma 1                            -> 2n + 16
-                    |z| >= 8: phase 2n-1, cvt 1, rcp 4, w 2, two degree-5
-                    Horner 12, phase reduction 4, sin 4, cos 4, rsq 4,
-                    combine 5, sign 1, cvt + fma 2                  -> 2n + 46
-  Fourier backward  phase 2n-1, reduction 2, cvt 1, sin 4, cos 4, cvt 2,
-                    cotangent combine 3, n fmas                     -> 3n + 15
-  ECT               projection 2n-1, bin guess 6 (sub, mul, ceil, max, min,
-                    cvt), fix-up compares 2, LDS add 1              -> 2n + 8
+  Fourier   phase u*s/(2 pi) 1, reduction to [0,1) 2 (floor, sub), cvt 1,
+            sin 4, cos 4, two (cvt + fma) 4                          -> 16
+  Laplace   exponent fma 1, split 2 (floor, sub), cvt 1, exp2 4, cvt 1,
+            cvt-to-int 1, ldexp 1, fma 1                              -> 12
+  Bessel    |z| < 8: z 1, v 2, degree-9 FP64 Horner 10, scale 1, cvt 2,
+            sign 1, fma 1                                             -> 18
+            |z| >= 8: z 1, cvt 1, rcp 4, w 2, two degree-5 Horner 12,
+            phase reduction 4, cvt 1, sin 4, cos 4, rsq 4, combine 5,
+            sign 1, cvt + fma 2                                       -> 45
+  Fourier backward: phase and reduction 3, cvt 1, sin 4, cos 4, cvt 2,
+            cotangent combine 3, n fmas                               -> 17 + n
+  ECT       projection 2n-1, bin guess 6 (sub, mul, ceil, max, min, cvt),
+            fix-up compares 2, LDS add 1                              -> 2n + 8
 Precompute is bounded by HBM: bytes = pixels read once + 32 B per list entry
 written + list offsets.
 """
@@ -34,17 +36,17 @@ VALU_SLOT_RATE = 256 * 64 * 2.4e9  # lane-instruction slots per second
 
 
 def slots_per_pair(kind: str, n: int, small_fraction: float = 1.0) -> float:
-    if kind == "fourier":
-        return 2 * n + 14
-    if kind == "laplace":
-        return n + 11
-    if kind == "bessel":
-        return small_fraction * (2 * n + 16) + (1.0 - small_fraction) * (2 * n + 46)
-    if kind == "fourier_bwd":
-        return 3 * n + 15
+    """kind: 'fourier', 'laplace', 'bessel', '+'-joined fused kernels, 'fourier_bwd' or 'ect'."""
     if kind == "ect":
         return 2 * n + 8
-    raise ValueError(kind)
+    if kind == "fourier_bwd":
+        return (2 * n - 1) + 17 + n
+    per = {"fourier": 16.0, "laplace": 12.0,
+           "bessel": small_fraction * 18.0 + (1.0 - small_fraction) * 45.0}
+    parts = kind.split("+")
+    if any(p not in per for p in parts):
+        raise ValueError(kind)
+    return (2 * n - 1) + sum(per[p] for p in parts)
 
 
 def alu_roofline(kind: str, n: int, pairs: float, seconds: float, small_fraction: float = 1.0) -> dict:

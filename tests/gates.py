@@ -61,8 +61,11 @@ def term_scales(img, xi, kernel, s, construction=O.PRIMAL, origin=None, spacing=
     return S1, S2
 
 
-def fp32_gate(y, ref, S2):
-    """Return (ok, worst ratio, normwise error, strict max relative error)."""
+def fp32_gate(y, ref, S2, normwise=True):
+    """Return (ok, worst ratio, normwise error, strict max relative error).
+
+    normwise=False drops the set-wide criterion, for sets of a few queries
+    whose largest value may itself be a cancellation to ~0."""
     y = np.asarray(y)
     ref = np.asarray(ref)
     err = np.abs(y - ref)
@@ -70,7 +73,7 @@ def fp32_gate(y, ref, S2):
     ratio = float((err / np.maximum(tol, 1e-300)).max()) if err.size else 0.0
     norm = float(err.max() / max(np.abs(ref).max(), 1e-300)) if err.size else 0.0
     strict = float((err / np.maximum(np.abs(ref), 1e-300)).max()) if err.size else 0.0
-    return ratio <= 1.0 and norm <= 1e-5, ratio, norm, strict
+    return ratio <= 1.0 and (norm <= 1e-5 or not normwise), ratio, norm, strict
 
 
 def fp64_gate(y, ref, S1):

@@ -326,6 +326,51 @@ def test_empty_lists_and_tiny(api):
     assert (e == 0).all()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_fused_multi_kernel_equals_separate_calls(api, precision):
+    w = W.grf_512(2, n_xi=2048)
+    plan = api.Plan(T(w.images[0]))
+    xi = T(w.hybrid_xi)
+    for kernels in (("fourier", "laplace", "bessel"), ("fourier", "bessel"), ("laplace", "bessel")):
+        multi = plan.hybrid_multi(xi, kernels, 1.0, precision)
+        for k in kernels:
+            one = plan.hybrid(xi, k, 1.0, precision).cpu().numpy()
+            got = multi[k].cpu().numpy()
+            assert np.array_equal(got.view(np.uint64), one.view(np.uint64)), (kernels, k)
+
+
+def test_large_query_sets_use_multi_workgroup_bucketing(api):
+    rng = np.random.default_rng(1001)
+    img = W.binary_field(rng, (40, 40), 3.0)
+    plan = api.Plan(T(img))
+    xi = W.polar_vectors(rng, 70000, 0.01, 1.0)          # > 65536 rows: multi-workgroup path
+    y = plan.hybrid(T(xi), "fourier", 1.0).cpu().numpy()
+    sel = rng.choice(len(xi), 40, replace=False)
+    ref = O.hybrid(img, xi[sel], "fourier", 1.0)
+    S1, S2 = term_scales(img, xi[sel], "fourier", 1.0)
+    ok, ratio, norm, strict = fp32_gate(_cplx(y, "fourier")[sel], ref, S2)
+    assert ok, (ratio, norm)
+    dirs = W.circle_dirs(70000)
+    thr = np.linspace(-30, 30, 16)
+    e = plan.ect(T(dirs), T(thr)).cpu().numpy()
+    assert np.array_equal(e[sel], O.ect(img, dirs[sel], thr))
+    # many (image, bucket) entries: 2100 images x 2 pairs > 4096
+    imgs = [W.random_image(rng, (3, 4), 2) for _ in range(2100)]
+    planb = api.Plan([T(im) for im in imgs])
+    counts = rng.integers(0, 4, size=len(imgs))
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    xib = W.polar_vectors(rng, int(offs[-1]), 0.05, 1.0)
+    yb = planb.hybrid(T(xib), "laplace", 1.0, offsets=T(offs)).cpu().numpy()
+    for i in rng.choice(len(imgs), 25, replace=False):
+        if counts[i] == 0:
+            continue
+        sl = slice(offs[i], offs[i + 1])
+        ref = O.hybrid(imgs[i], xib[sl], "laplace", 1.0)
+        S1, S2 = term_scales(imgs[i], xib[sl], "laplace", 1.0)
+        ok, ratio, norm, strict = fp32_gate(yb[sl], ref, S2, normwise=False)   # 1-3 queries per image
+        assert ok, (i, ratio)
+
+
 # ---------------------------------------------------------------------------
 # a7: backward
 # ---------------------------------------------------------------------------
