@@ -84,7 +84,7 @@ int64_t hybrid_chunk_for(const Plan& p, int64_t rows) {
     const int P = num_ordinary(p.ndim);
     const double avg = mean_list(p, num_classical(p.ndim), P);
     const double pairs = (double)rows * avg;
-    double c = pairs / ((double)kHybridThreads * (double)g_tuning.hybrid_target_items);
+    double c = pairs / ((double)kHybridTile * (double)g_tuning.hybrid_target_items);
     int64_t ci = (int64_t)std::ceil(std::max(32.0, c) / 16.0) * 16;
     return ci;
 }
@@ -96,15 +96,15 @@ void layout_hybrid(const Plan& p, const ect_query_set& q, bool backward, EvalLay
     const bool shared = q.offsets == nullptr;
     const int64_t rows = query_rows(q, p.num_images);
     // query tiles: sum over (image, pair) of ceil(count / 64) <= rows/64 + images*P
-    const int64_t tiles = shared ? (int64_t)p.num_images * ((q.count + kHybridThreads - 1) / kHybridThreads + P)
-                                 : (rows + kHybridThreads - 1) / kHybridThreads + (int64_t)p.num_images * P;
+    const int64_t tiles = shared ? (int64_t)p.num_images * ((q.count + kHybridTile - 1) / kHybridTile + P)
+                                 : (rows + kHybridTile - 1) / kHybridTile + (int64_t)p.num_images * P;
     *chunk = hybrid_chunk_for(p, rows);
     const int64_t maxn = max_list(p, num_classical(p.ndim), P);
     const int64_t maxch = std::max<int64_t>(1, (maxn + *chunk - 1) / *chunk);
     L->tiles = tiles;
     L->grid = tiles * maxch;
     L->capacity = L->grid;
-    L->partials = o; o = align_up(o + sizeof(double) * kAccSlotsHost * kHybridThreads * std::max<int64_t>(L->capacity, 1), kAlign);
+    L->partials = o; o = align_up(o + sizeof(double) * kAccSlotsHost * kHybridTile * std::max<int64_t>(L->capacity, 1), kAlign);
     L->gpart = L->gspart = 0;
     if (backward) {
         L->gpart = o; o = align_up(o + sizeof(double) * p.ndim * std::max<int64_t>(rows, 1), kAlign);
@@ -344,7 +344,7 @@ static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t 
     const bool shared = xi.offsets == nullptr;
     hipError_t e = launch_prepare(p.ndim, xi, p.num_images, true, err, (QRec*)(w + L.recs), (int32_t*)(w + L.bcnt),
                                   (const int64_t*)(p.ws + p.lay.list_off), num_classical(p.ndim), NL,
-                                  kHybridThreads, chunk, L.capacity, (int64_t*)(w + L.item_off),
+                                  kHybridTile, chunk, L.capacity, (int64_t*)(w + L.item_off),
                                   (int64_t*)(w + L.tile_off), (int64_t*)(w + L.params), stream);
     if (e != hipSuccess) return ECT_E_DEVICE;
     HybridArgs a{};

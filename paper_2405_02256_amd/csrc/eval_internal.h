@@ -18,7 +18,9 @@ struct alignas(32) QRec {
 constexpr int kEctThreads = 256;      // ECT workgroup: points stream across its lanes
 constexpr int kEctMaxDirs = 8;        // directions per ECT workgroup
 constexpr int kEctMaxThresholds = 4096;
-constexpr int kHybridThreads = 256;  // one query per thread; the workgroup shares a staged chunk of points
+constexpr int kHybridThreads = 256;  // four waves share one staged chunk of points
+constexpr int kHybridSplit = 4;      // the waves split the chunk's points between them ...
+constexpr int kHybridTile = kHybridThreads / kHybridSplit;  // ... for one tile of 64 queries
 constexpr int kHybridStage = 256;    // points staged in LDS at a time
 
 constexpr int64_t kSmallMaxRows = 65536;   // query sets bucketed by a single workgroup

@@ -11,10 +11,10 @@
 // Laplace, Bessel): they share the staged points and the projection <xi, x>.
 //
 // Work decomposition: queries are bucketed by orthant pair; a work item is
-// (image, pair, tile of 256 queries, chunk of points).  One workgroup runs an
-// item: every thread owns one query held in registers, and the chunk's points
-// are staged through LDS and read by all threads in lockstep.  Per pair of
-// (query, point):
+// (image, pair, tile of 64 queries, chunk of points).  One workgroup of four
+// waves runs an item: every lane owns one query held in registers, the chunk's
+// points are staged through LDS and the four waves take every fourth point.
+// Per pair of (query, point):
 //   FP32 precision: FP64 phase, FP64 argument reduction to [0, 1) revolutions
 //                   (or to a split exponent for Laplace), FP32 kernel value
 //                   (hardware sin/cos/exp2 on reduced arguments, polynomial
@@ -276,21 +276,26 @@ __device__ __forceinline__ int64_t find_entry(const int64_t* __restrict__ off, i
 
 // Partial sums are stored slot-major inside an item so that consecutive
 // threads touch consecutive doubles.
-__device__ __forceinline__ int64_t partial_index(int64_t item, int slot, int tid) {
-    return (item * kAccSlots + slot) * kHybridThreads + tid;
+__device__ __forceinline__ int64_t partial_index(int64_t item, int slot, int q) {
+    return (item * kAccSlots + slot) * kHybridTile + q;
 }
 
-// One workgroup per work item (image, orthant pair, tile of 256 queries, chunk
-// of points).  Each thread owns one query; the chunk's points are staged in LDS
-// kHybridStage at a time with one coalesced load per thread and then read by
-// every thread (same address across the wave: a broadcast).  A tile split into
-// several chunks writes per-query partial sums, which hybrid_reduce adds in
-// chunk order after the kernel; a single-chunk tile writes its outputs here.
+// One workgroup per work item (image, orthant pair, tile of 64 queries, chunk
+// of points).  The chunk's points are staged in LDS kHybridStage at a time with
+// one coalesced load per thread; wave w of the four then reads the staged
+// points w, w+4, ... (the same address across the wave: a broadcast) for the
+// tile's 64 queries, one query per lane.  The four wave sums of a query are
+// added in wave order.  A tile split into several chunks writes per-query
+// partial sums, which hybrid_reduce adds in chunk order after the kernel; a
+// single-chunk tile writes its outputs here.
 template <int N, int MASK, int PREC, bool BWD>
 __global__ void __launch_bounds__(kHybridThreads) hybrid_kernel(HybridArgs a) {
     constexpr int P = 1 << (N - 1);
     __shared__ Point s_pts[kHybridStage];
+    __shared__ double s_acc[kHybridSplit - 1][kAccSlots][kHybridTile];
     const int tid = threadIdx.x;
+    const int lane = tid & (kHybridTile - 1);
+    const int wave = tid / kHybridTile;
     const int64_t item = blockIdx.x;
     if (item >= a.params[0]) return;
     const int64_t C = a.params[2];
@@ -304,7 +309,7 @@ __global__ void __launch_bounds__(kHybridThreads) hybrid_kernel(HybridArgs a) {
     const int64_t chunks = np > 0 ? (np + C - 1) / C : 1;
     const int64_t t = local / chunks, c = local % chunks;
     const int64_t qn = a.bcnt[a.offsets == nullptr ? b : e];
-    const int64_t qi = t * kHybridThreads + tid;
+    const int64_t qi = t * kHybridTile + lane;
     const bool active = qi < qn;
     const Point* __restrict__ pts = a.points + (int64_t)l * a.capacity;
     const int64_t c0 = p0 + c * C, c1 = min(p1, c0 + C);
@@ -319,22 +324,35 @@ __global__ void __launch_bounds__(kHybridThreads) hybrid_kernel(HybridArgs a) {
         __syncthreads();
         if (tid < cnt) s_pts[tid] = pts[base + tid];
         __syncthreads();
-        for (int k = 0; k < cnt; ++k) accumulate_point<N, MASK, PREC, BWD>(s_pts[k], q, acc);
+        for (int k = wave; k < cnt; k += kHybridSplit) accumulate_point<N, MASK, PREC, BWD>(s_pts[k], q, acc);
     }
+    if (wave > 0) {
+#pragma unroll
+        for (int k = 0; k < kAccSlots; ++k)
+            if (slot_used<MASK, BWD, N>(k)) s_acc[wave - 1][k][lane] = acc[k];
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int w = 0; w < kHybridSplit - 1; ++w)
+#pragma unroll
+        for (int k = 0; k < kAccSlots; ++k)
+            if (slot_used<MASK, BWD, N>(k)) acc[k] += s_acc[w][k][lane];
 
     if (chunks > 1) {
 #pragma unroll
         for (int k = 0; k < kAccSlots; ++k)
-            if (slot_used<MASK, BWD, N>(k)) a.partials[partial_index(item, k, tid)] = acc[k];
+            if (slot_used<MASK, BWD, N>(k)) a.partials[partial_index(item, k, lane)] = acc[k];
         return;
     }
     if (active) finalize<N, MASK, PREC, BWD>(a, q, row, acc);
 }
 
-// One workgroup per query tile: add the partial sums of a multi-chunk tile in
-// chunk order and write the outputs (single-chunk tiles were written already).
+// One 64-thread workgroup per query tile: add the partial sums of a
+// multi-chunk tile in chunk order and write the outputs (single-chunk tiles
+// were written already).
 template <int N, int MASK, int PREC, bool BWD>
-__global__ void __launch_bounds__(kHybridThreads) hybrid_reduce_kernel(HybridArgs a) {
+__global__ void __launch_bounds__(kHybridTile) hybrid_reduce_kernel(HybridArgs a) {
     constexpr int P = 1 << (N - 1);
     const int tid = threadIdx.x;
     const int64_t tile = blockIdx.x;
@@ -349,7 +367,7 @@ __global__ void __launch_bounds__(kHybridThreads) hybrid_reduce_kernel(HybridArg
     const int64_t chunks = np > 0 ? (np + C - 1) / C : 1;
     if (chunks == 1) return;
     const int64_t qn = a.bcnt[a.offsets == nullptr ? b : e];
-    const int64_t qi = t * kHybridThreads + tid;
+    const int64_t qi = t * kHybridTile + tid;
     if (qi >= qn) return;
     Query<N> q;
     int64_t row;
@@ -409,12 +427,12 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v)
 
 template <int N, int MASK, bool BWD>
 hipError_t launch_mask(int precision, const HybridArgs& a, int64_t grid, bool reduce, hipStream_t stream) {
-    dim3 g((unsigned)grid), blk(kHybridThreads);
+    dim3 g((unsigned)grid), blk(kHybridThreads), rblk(kHybridTile);
     if (precision == ECT_FP32) {
-        if (reduce) hipLaunchKernelGGL((hybrid_reduce_kernel<N, MASK, ECT_FP32, BWD>), g, blk, 0, stream, a);
+        if (reduce) hipLaunchKernelGGL((hybrid_reduce_kernel<N, MASK, ECT_FP32, BWD>), g, rblk, 0, stream, a);
         else hipLaunchKernelGGL((hybrid_kernel<N, MASK, ECT_FP32, BWD>), g, blk, 0, stream, a);
     } else {
-        if (reduce) hipLaunchKernelGGL((hybrid_reduce_kernel<N, MASK, ECT_FP64, BWD>), g, blk, 0, stream, a);
+        if (reduce) hipLaunchKernelGGL((hybrid_reduce_kernel<N, MASK, ECT_FP64, BWD>), g, rblk, 0, stream, a);
         else hipLaunchKernelGGL((hybrid_kernel<N, MASK, ECT_FP64, BWD>), g, blk, 0, stream, a);
     }
     return hipGetLastError();

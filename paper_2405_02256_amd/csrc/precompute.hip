@@ -58,28 +58,44 @@ __device__ __forceinline__ int32_t px_load(const T* __restrict__ img, int64_t i)
     return (int32_t)img[i];
 }
 
-// Critical values of one vertex: L[e] for the 2^N sign vectors, D[e] for the
-// 2^(N-1) sign vectors with eps_{N-1} = +1.
+// Pixels a vertex's star depends on: primal, the 2^N pixels k_a - 1 + d_a
+// (d in {0,1}^N); dual, the 3^N pixels k + t (t in {-1,0,1}^N).  Coordinates
+// are clamped into the image.
+template <int N, int CONS>
+__host__ __device__ constexpr int nb_count() { return CONS == ECT_PRIMAL ? (1 << N) : pow3<N>(); }
+
 template <int N, int CONS, typename T>
-__device__ __forceinline__ void vertex_values(const T* __restrict__ img, const ImageDesc& d,
-                                              const int* k, int32_t* L, int32_t* D) {
+__device__ __forceinline__ void load_neighbourhood(const T* __restrict__ img, const ImageDesc& d, const int* k,
+                                                   int32_t* p) {
+#pragma unroll
+    for (int c = 0; c < nb_count<N, CONS>(); ++c) {
+        int64_t idx = 0, stride = 1;
+        int r = c;
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            int x;
+            if constexpr (CONS == ECT_PRIMAL) {
+                x = k[a] - 1 + ((c >> a) & 1);
+            } else {
+                x = k[a] + (r % 3) - 1;
+                r /= 3;
+            }
+            x = x < 0 ? 0 : (x > d.dims[a] - 1 ? d.dims[a] - 1 : x);
+            idx += (int64_t)x * stride;
+            stride *= d.dims[a];
+        }
+        p[c] = px_load(img, idx);
+    }
+}
+
+// Critical values of one vertex from its neighbourhood: L[e] for the 2^N sign
+// vectors, D[e] for the 2^(N-1) sign vectors with eps_{N-1} = +1.
+template <int N, int CONS>
+__device__ __forceinline__ void vertex_values(const int32_t* p, const ImageDesc& d, const int* k, int32_t* L,
+                                              int32_t* D) {
     constexpr int S = pow3<N>();
     int32_t val[S];
     if constexpr (CONS == ECT_PRIMAL) {
-        // pixels k_a - 1 + d_a, d in {0,1}^N
-        int32_t p[1 << N];
-#pragma unroll
-        for (int c = 0; c < (1 << N); ++c) {
-            int64_t idx = 0, stride = 1;
-#pragma unroll
-            for (int a = 0; a < N; ++a) {
-                int q = k[a] - 1 + ((c >> a) & 1);
-                q = q < 0 ? 0 : (q > d.dims[a] - 1 ? d.dims[a] - 1 : q);
-                idx += (int64_t)q * stride;
-                stride *= d.dims[a];
-            }
-            p[c] = px_load(img, idx);
-        }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             // sigma digits: 0 -> -1 (pixel d=0 only), 1 -> 0 (both), 2 -> +1 (pixel d=1 only)
@@ -100,24 +116,7 @@ __device__ __forceinline__ void vertex_values(const T* __restrict__ img, const I
             val[s] = m;
         }
     } else {
-        // pixels k + t, t in {-1,0,1}^N; a cell extending by sigma takes the min
-        // over the pixels k + t with t_a in {0, sigma_a}
-        int32_t q[S];
-#pragma unroll
-        for (int c = 0; c < S; ++c) {
-            int64_t idx = 0, stride = 1;
-            int r = c;
-#pragma unroll
-            for (int a = 0; a < N; ++a) {
-                int t = r % 3 - 1;
-                r /= 3;
-                int x = k[a] + t;
-                x = x < 0 ? 0 : (x > d.dims[a] - 1 ? d.dims[a] - 1 : x);
-                idx += (int64_t)x * stride;
-                stride *= d.dims[a];
-            }
-            q[c] = px_load(img, idx);
-        }
+        // a cell extending by sigma takes the min over the pixels k + t with t_a in {0, sigma_a}
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             int32_t m = 0x7fffffff;
@@ -132,7 +131,7 @@ __device__ __forceinline__ void vertex_values(const T* __restrict__ img, const I
                     rc /= 3;
                     if (!(t == 0 || t == sg)) ok = false;
                 }
-                if (ok) m = min(m, q[c]);
+                if (ok) m = min(m, p[c]);
             }
             val[s] = m;
         }
@@ -225,6 +224,8 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
     int32_t vals[J][NL];
     int kk[J][3];
     bool valid[J];
+    // every round's pixel loads are issued before any vertex is classified
+    int32_t nb[J][nb_count<N, CONS>()];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         int64_t v = vbase + j * kPrecomputeThreads + tid;
@@ -235,8 +236,12 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
         kk[j][0] = (int)r0;
         kk[j][1] = N == 3 ? (int)r1 : (int)q0;
         kk[j][2] = N == 3 ? (int)q1 : 0;
+        load_neighbourhood<N, CONS, T>(img, d, kk[j], nb[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
         int32_t L[NC], D[NO];
-        vertex_values<N, CONS, T>(img, d, kk[j], L, D);
+        vertex_values<N, CONS>(nb[j], d, kk[j], L, D);
 #pragma unroll
         for (int l = 0; l < NC; ++l) vals[j][l] = valid[j] ? L[l] : 0;
 #pragma unroll
