@@ -43,7 +43,8 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="time eager steps instead of graph replays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")
-    ap.add_argument("--cpu-budget", type=float, default=1.0, help="scale of the oracle sample")
+    ap.add_argument("--cpu-budget", type=float, default=10.0, help="scale of the oracle sample")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 4096-image batched comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (counter calibration) and exit")
     return ap.parse_args()
@@ -219,10 +220,10 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         b = args.cpu_budget
-        samp = {"ect": max(4, int(72 * b)), "fourier": max(8, int(256 * b)), "laplace": max(8, int(256 * b)),
-                "bessel": max(4, int(32 * b)), "grad": max(8, int(128 * b))}
         full = {"ect": len(w.ect_dirs), "fourier": len(w.hybrid_xi), "laplace": len(w.hybrid_xi),
                 "bessel": len(w.hybrid_xi), "grad": len(w.hybrid_xi)}
+        base = {"ect": 72, "fourier": 256, "laplace": 256, "bessel": 32, "grad": 128}
+        samp = {k: int(min(full[k], max(4, base[k] * b))) for k in base}
         tcpu = {}
         sel_d = np.linspace(0, len(w.ect_dirs) - 1, samp["ect"]).astype(int)
         t0 = time.perf_counter()
@@ -243,8 +244,70 @@ def main():
                "sample": (f"FP64 oracle (cell forms over all cells) on {samp['ect']} of 360 ECT directions, "
                           f"{samp['fourier']}/{samp['laplace']}/{samp['bessel']} of 4096 xi for "
                           f"Fourier/Laplace/Bessel and {samp['grad']} xi of the Fourier gradient; "
-                          f"{sum(tcpu.values()):.1f} s of wall time scaled to one full step "
-                          f"({t_step:.1f} s)")}
+                          f"{sum(tcpu.values()):.1f} s of wall time on {O.max_threads()} OpenMP threads "
+                          f"(" + ", ".join(f"{k} {v:.2f} s" for k, v in tcpu.items()) + ") scaled to one "
+                          f"full step ({t_step:.1f} s)")}
+
+    # ---- batched FP32 (one graph) vs the plain per-image FP64 path, 4096 ragged images ----
+    batch = None
+    if not args.no_batch:
+        log("batched comparison: 4096 ragged images")
+        w4 = W.batch_4096(4)
+        imgs4 = [torch.from_numpy(im).to(dev) for im in w4.images]
+        plan4 = api.Plan(imgs4)
+        dirs4 = torch.from_numpy(w4.ect_dirs).to(dev)
+        thr4 = torch.from_numpy(w4.ect_thresholds).to(dev)
+        xi4 = torch.from_numpy(w4.hybrid_xi).to(dev)
+        nq = len(w4.hybrid_xi) // len(imgs4)
+        offs4 = torch.arange(len(imgs4) + 1, dtype=torch.int64, device=dev) * nq
+        step4 = pipeline.Step(plan4, dirs4, thr4, xi4, kernels=("laplace",), s=1.0, precision="fp32",
+                              hybrid_offsets=offs4)
+        step4.capture()
+        for _ in range(3):
+            step4.replay()
+        torch.cuda.synchronize()
+        reps = 10
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step4.replay()
+        torch.cuda.synchronize()
+        t_batched = (time.perf_counter() - t0) / reps
+        y32 = step4.hy_out["laplace"].cpu().numpy()
+        e32 = step4.ect_out.cpu().numpy()
+        plans = [api.Plan(im) for im in imgs4]
+        outs_e = [torch.empty((len(w4.ect_dirs), thr4.shape[1]), dtype=torch.int32, device=dev) for _ in plans]
+        outs_h = [torch.empty(nq, dtype=torch.float64, device=dev) for _ in plans]
+        xis = [xi4[i * nq:(i + 1) * nq] for i in range(len(plans))]
+
+        def per_image():
+            for i, pl in enumerate(plans):
+                pl.rerun()
+                pl.ect(dirs4, thr4[i], out=outs_e[i])
+                pl.hybrid(xis[i], "laplace", 1.0, "fp64", out=outs_h[i])
+
+        per_image()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        per_image()
+        torch.cuda.synchronize()
+        t_loop = time.perf_counter() - t0
+        y64 = torch.cat(outs_h).cpu().numpy()
+        e64 = torch.cat(outs_e).cpu().numpy()
+        pairs4 = 0.0
+        c4, o4 = plan4.counts()
+        ex4 = w4.hybrid_xi.reshape(len(imgs4), nq, 2)
+        e_idx = (ex4[..., 0] < 0) * 1 + (ex4[..., 1] < 0) * 2
+        pr = np.where(e_idx >= 2, e_idx ^ 3, e_idx)
+        pairs4 = float(np.take_along_axis(o4, pr, axis=1).sum())
+        batch = {"workload": "batch_4096: 4096 binary GRF images, sides U{28,64,128,256}, sigma U[2,8]; "
+                             "ECT 128 dirs x 128 per-image thresholds; Euler-Laplace at 512 xi per image",
+                 "batched_fp32_graph_ms": t_batched * 1e3, "per_image_fp64_loop_ms": t_loop * 1e3,
+                 "speedup": t_loop / t_batched,
+                 "hybrid_evals_per_s_batched": pairs4 / t_batched,
+                 "ect_dirs_per_s_batched": len(imgs4) * len(w4.ect_dirs) / t_batched,
+                 "ect_identical": bool(np.array_equal(e32, e64)),
+                 "fp32_vs_fp64_normwise": float(np.abs(y32 - y64).max() / np.abs(y64).max())}
+        log(f"batched {t_batched * 1e3:.3f} ms vs per-image FP64 loop {t_loop * 1e3:.1f} ms")
 
     res = {
         "metric": METRIC,
@@ -270,6 +333,7 @@ def main():
         "roofline": roof,
         "fp64_path_ms_per_step": None if fp64 is None else fp64 * 1e3,
         "fp32_vs_fp64_speedup": None if fp64 is None else fp64 / sec,
+        "batched_vs_per_image": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

@@ -40,6 +40,10 @@ class QuerySet:
         self.offsets = None if offsets is None else offsets.to(device=vecs.device, dtype=torch.int64).contiguous()
 
     def validate(self, num_images: int, ndim: int) -> None:
+        """Check shapes once per (num_images, ndim); the offsets check reads them back to the host,
+        so a set used inside graph capture must have been validated before."""
+        if getattr(self, "_checked", None) == (num_images, ndim):
+            return
         if self.vecs.shape[1] != ndim:
             raise ValueError(f"query vectors have {self.vecs.shape[1]} columns, expected {ndim}")
         if self.offsets is not None:
@@ -47,6 +51,7 @@ class QuerySet:
             if o.shape != (num_images + 1,) or o[0] != 0 or o[-1] != self.vecs.shape[0] or (np.diff(o) < 0).any():
                 raise ValueError("ragged offsets must be [num_images+1], start at 0, be non-decreasing and "
                                  "end at the number of rows")
+        self._checked = (num_images, ndim)
 
     def rows(self, num_images: int) -> int:
         return self.vecs.shape[0] if self.offsets is not None else self.vecs.shape[0] * num_images
