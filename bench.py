@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="scale of the oracle sample")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-image batched comparison")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule knobs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (counter calibration) and exit")
     return ap.parse_args()
@@ -126,6 +127,12 @@ def main():
             small += float((z < 8.0).sum())
     small_frac = small / max(per_kernel_pairs, 1.0)
 
+    tuning = None
+    if not args.no_autotune:
+        log("autotuning schedule knobs")
+        t = step.autotune()
+        tuning = {"hybrid_target_items": t.hybrid_target_items, "ect_dirs_per_group": t.ect_dirs_per_group}
+        log(f"tuning {tuning}")
     log("warm-up and graph capture")
     step.run()
     torch.cuda.synchronize()
@@ -262,6 +269,8 @@ def main():
         offs4 = torch.arange(len(imgs4) + 1, dtype=torch.int64, device=dev) * nq
         step4 = pipeline.Step(plan4, dirs4, thr4, xi4, kernels=("laplace",), s=1.0, precision="fp32",
                               hybrid_offsets=offs4)
+        if not args.no_autotune:
+            step4.autotune()
         step4.capture()
         for _ in range(3):
             step4.replay()
@@ -325,7 +334,8 @@ def main():
         "config": {"workload": "grf_512: 512x512 binary Gaussian random field (sigma 8 px, median "
                                "threshold), primal cubical complex; ECT 360 dirs x 256 thresholds; "
                                "Euler-Fourier/Laplace/Bessel at 4096 xi, |xi|~U[0.01,1]; Fourier backward",
-                   "graph": use_graph, "precision": "FP32 kernel values, FP64 phases and accumulation"},
+                   "graph": use_graph, "precision": "FP32 kernel values, FP64 phases and accumulation",
+                   "tuning": tuning},
         "ect_dirs_per_s": len(w.ect_dirs) / sec,
         "evals_per_step": evals_per_step,
         "stage_kernel_ms": stage_ms,

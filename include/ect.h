@@ -221,12 +221,16 @@ ect_status ect_plan_check(ect_plan plan, uint32_t* device_error_flags, hipStream
 /* Free the host handle (the workspace stays with the caller). */
 ect_status ect_plan_destroy(ect_plan plan);
 
-/* Tuning knobs (process-wide; used by the autotuner): hybrid point-chunk
- * length per work item (0 = automatic), target number of hybrid work items
- * when automatic, directions per ECT workgroup (1..8, 0 = automatic).  Values only change
- * the schedule: results are exact (ECT) or equal to within rounding of the
- * chunked sums (hybrid), and identical for identical settings. */
-ect_status ect_set_tuning(int64_t hybrid_chunk, int64_t hybrid_target_items, int32_t ect_dirs_per_group);
+/* Tuning knobs of one plan (used by the autotuner): hybrid point-chunk
+ * length per work item (0 = automatic, else 16 .. 2^40), target number of
+ * hybrid work items when automatic (1 .. 2^24), directions per ECT workgroup
+ * (1..8, 0 = automatic).  Out-of-range values return ECT_E_INVALID and leave
+ * the plan unchanged.
+ * They only change the schedule: the ECT is exact whatever they are, hybrid
+ * results differ only by the rounding of the chunked sums, and identical
+ * settings give bitwise identical results. */
+ect_status ect_plan_set_tuning(ect_plan plan, int64_t hybrid_chunk, int64_t hybrid_target_items,
+                               int32_t ect_dirs_per_group);
 
 /* Profiling hook (process-wide): when set, the library records `before` on
  * the call's stream right before it launches the main kernel of `stage` and

@@ -72,11 +72,11 @@ def lib():
     L.ect_plan_export.argtypes = [c_vp, c_i32, c_i32, c_i32, P(c_i32), P(c_i32), c_i64, P(c_i64), c_vp]
     L.ect_plan_check.argtypes = [c_vp, P(c_u32), c_vp]
     L.ect_plan_destroy.argtypes = [c_vp]
-    L.ect_set_tuning.argtypes = [c_i64, c_i64, c_i32]
+    L.ect_plan_set_tuning.argtypes = [c_vp, c_i64, c_i64, c_i32]
     L.ect_set_stage_events.argtypes = [c_i32, c_vp, c_vp]
     for name in ("ect_precompute", "ect_plan_rerun", "ect_eval", "hybrid_eval", "hybrid_eval_multi",
                  "hybrid_eval_backward",
-                 "ect_plan_counts", "ect_plan_export", "ect_plan_check", "ect_plan_destroy", "ect_set_tuning",
+                 "ect_plan_counts", "ect_plan_export", "ect_plan_check", "ect_plan_destroy", "ect_plan_set_tuning",
                  "ect_set_stage_events"):
         getattr(L, name).restype = c_i32
     _lib = L
@@ -151,8 +151,9 @@ def ect_plan_destroy(plan) -> int:
     return lib().ect_plan_destroy(c_vp(plan))
 
 
-def ect_set_tuning(hybrid_chunk: int, hybrid_target_items: int, ect_dirs_per_group: int) -> int:
-    return lib().ect_set_tuning(int(hybrid_chunk), int(hybrid_target_items), int(ect_dirs_per_group))
+def ect_plan_set_tuning(plan, hybrid_chunk: int, hybrid_target_items: int, ect_dirs_per_group: int) -> int:
+    return lib().ect_plan_set_tuning(c_vp(plan), int(hybrid_chunk), int(hybrid_target_items),
+                                     int(ect_dirs_per_group))
 
 
 STAGE_PRECOMPUTE, STAGE_ECT, STAGE_HYBRID, STAGE_HYBRID_BWD = 0, 1, 2, 3

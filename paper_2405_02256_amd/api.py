@@ -80,6 +80,8 @@ class Plan:
         if ndim not in (2, 3) or any(im.dim() != ndim or im.dtype != dt or im.device != dev for im in images):
             raise ValueError("every image must have the same ndim (2 or 3), dtype and device")
         self.ndim = ndim
+        self.construction = int(construction)
+        self.tuning = (0, 2048, 0)
         self.num_images = len(images)
         self.device = dev
         flat = [im.reshape(-1) for im in images]
@@ -128,6 +130,11 @@ class Plan:
         if self._eval_ws is None or self._eval_ws.numel() < nbytes:
             self._eval_ws = _workspace(nbytes, self.device)
         return self._eval_ws
+
+    def set_tuning(self, hybrid_chunk: int = 0, hybrid_target_items: int = 2048, ect_dirs_per_group: int = 0):
+        N.check(N.ect_plan_set_tuning(self.handle, hybrid_chunk, hybrid_target_items, ect_dirs_per_group),
+                "ect_plan_set_tuning")
+        self.tuning = (hybrid_chunk, hybrid_target_items, ect_dirs_per_group)
 
     def rerun(self, stream=None):
         N.check(N.ect_plan_rerun(self.handle, _stream(stream)), "ect_plan_rerun")

@@ -72,19 +72,12 @@ double mean_list(const Plan& p, int base, int count) {
     return s / std::max(1, p.num_images * count);
 }
 
-// Tunables (defaults; an autotuner may override them through ect_set_tuning).
-struct Tuning {
-    int64_t hybrid_chunk = 0;        // 0: automatic
-    int64_t hybrid_target_items = 2048;
-    int ect_dirs_per_group = 0;      // 0: automatic
-} g_tuning;
-
 int64_t hybrid_chunk_for(const Plan& p, int64_t rows) {
-    if (g_tuning.hybrid_chunk > 0) return g_tuning.hybrid_chunk;
+    if (p.tune_hybrid_chunk > 0) return p.tune_hybrid_chunk;
     const int P = num_ordinary(p.ndim);
     const double avg = mean_list(p, num_classical(p.ndim), P);
     const double pairs = (double)rows * avg;
-    double c = pairs / ((double)kHybridTile * (double)g_tuning.hybrid_target_items);
+    double c = pairs / ((double)kHybridTile * (double)p.tune_hybrid_target_items);
     int64_t ci = (int64_t)std::ceil(std::max(32.0, c) / 16.0) * 16;
     return ci;
 }
@@ -265,7 +258,7 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
     // directions per workgroup: enough workgroups to fill the chip first, then
     // more directions per streamed point
     const int64_t nrows = query_rows(dirs, plan->num_images);
-    int td = g_tuning.ect_dirs_per_group > 0 ? g_tuning.ect_dirs_per_group
+    int td = plan->tune_ect_dirs_per_group > 0 ? plan->tune_ect_dirs_per_group
                                              : (int)std::min<int64_t>(kEctMaxDirs, std::max<int64_t>(1, nrows / 1024));
     const int64_t lds_budget = 60 * 1024;
     td = (int)std::min<int64_t>(td, (lds_budget - 8 * (int64_t)M) / (4 * (int64_t)M));
@@ -485,14 +478,16 @@ ect_status ect_plan_destroy(ect_plan plan) {
     return ECT_OK;
 }
 
-// Tuning knobs for the autotuner: hybrid point-chunk length (0 = automatic),
-// target number of hybrid work items, directions per ECT workgroup.
-ect_status ect_set_tuning(int64_t hybrid_chunk, int64_t hybrid_target_items, int32_t ect_dirs_per_group) {
-    if (hybrid_chunk < 0 || hybrid_target_items < 1 || ect_dirs_per_group < 0 || ect_dirs_per_group > kEctMaxDirs)
+ect_status ect_plan_set_tuning(ect_plan plan, int64_t hybrid_chunk, int64_t hybrid_target_items,
+                               int32_t ect_dirs_per_group) {
+    if (!plan) return ECT_E_INVALID;
+    if (hybrid_chunk < 0 || (hybrid_chunk > 0 && hybrid_chunk < 16) || hybrid_chunk > (int64_t(1) << 40) ||
+        hybrid_target_items < 1 || hybrid_target_items > (int64_t(1) << 24) || ect_dirs_per_group < 0 ||
+        ect_dirs_per_group > kEctMaxDirs)
         return ECT_E_INVALID;
-    g_tuning.hybrid_chunk = hybrid_chunk;
-    g_tuning.hybrid_target_items = hybrid_target_items;
-    g_tuning.ect_dirs_per_group = ect_dirs_per_group;
+    plan->tune_hybrid_chunk = hybrid_chunk;
+    plan->tune_hybrid_target_items = hybrid_target_items;
+    plan->tune_ect_dirs_per_group = ect_dirs_per_group;
     return ECT_OK;
 }
 

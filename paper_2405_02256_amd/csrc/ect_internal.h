@@ -68,6 +68,9 @@ struct ect_plan_s {
     int64_t* h_list_off = nullptr;      // host copy [(num_images+1) * NL], as of the last ect_precompute
     int64_t total_verts = 0;
     int64_t max_image_verts = 0;
+    int64_t tune_hybrid_chunk = 0;          // 0: automatic
+    int64_t tune_hybrid_target_items = 2048;
+    int32_t tune_ect_dirs_per_group = 0;    // 0: automatic
 };
 
 namespace ect {

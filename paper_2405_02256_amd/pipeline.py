@@ -75,10 +75,22 @@ class Step:
             p.hybrid_backward(self.hy_q, self.hy_out[self.backward_kernel], self.grad_out, self.backward_kernel,
                               self.s, self.precision, stream=stream, grad_xi=self.grad_xi, grad_s=self.grad_s)
 
+    def autotune(self, cache=None, use_cache: bool = True, reps: int = 10):
+        """Pick the plan's schedule knobs for this step's queries (before capture())."""
+        from . import autotune as AT
+        return AT.tune(self.plan, self.ect_q, self.ect_thr, self.hy_q, self.kernels, self.s, self.precision,
+                       backward_kernel=self.backward_kernel,
+                       grad_out=self.grad_out if self.backward_kernel is not None else None,
+                       cache=cache, use_cache=use_cache, reps=reps)
+
     def capture(self) -> "torch.cuda.CUDAGraph":
-        """Record run() into a graph (after one eager run sized every workspace)."""
+        """Record run() into a graph (after one eager run sized every workspace).
+
+        The graph keeps the evaluation workspace it recorded alive, so later
+        eager calls on the plan that need a larger one cannot free it."""
         self.run()
         torch.cuda.synchronize()
+        self.graph_ws = self.plan._eval_ws
         g = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())

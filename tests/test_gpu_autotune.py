@@ -1,0 +1,128 @@
+"""Schedule knobs and the autotuner on the GPU: any setting keeps the ECT
+bit-exact and the hybrid transforms within the FP32 gate of the oracle;
+identical settings give bitwise identical outputs; a tuned, captured step
+replays to its eager result; the cache answers a repeated workload without
+timing anything."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2405_02256_amd import workloads as W
+
+from gates import fp32_gate, term_scales
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_02256_amd import api as A
+    return A
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(torch.device("cuda:0"))
+
+
+def _cplx(y):
+    return y[:, 0] + 1j * y[:, 1]
+
+
+@pytest.fixture(scope="module")
+def small():
+    rng = np.random.default_rng(77)
+    img = W.binary_field(rng, (96, 80), 3.0)
+    xi = W.polar_vectors(rng, 200, 0.01, 1.0)
+    dirs = W.circle_dirs(40)
+    thr = W.even_thresholds(70.0, 96)
+    return img, xi, dirs, thr
+
+
+# chunk 16 splits every list into many chunks (more than the reduce kernel's
+# batch of 16 per pass); large chunks leave every tile in one chunk
+@pytest.mark.parametrize("chunk,items,td", [(16, 2048, 1), (48, 2048, 3), (0, 1, 8), (0, 1 << 24, 0),
+                                            (1 << 20, 2048, 5)])
+def test_any_tuning_keeps_parity(api, small, chunk, items, td):
+    img, xi, dirs, thr = small
+    plan = api.Plan(T(img))
+    plan.set_tuning(chunk, items, td)
+    assert np.array_equal(plan.ect(T(dirs), T(thr)).cpu().numpy(), O.ect(img, dirs, thr))
+    outs = plan.hybrid_multi(T(xi), ("fourier", "laplace", "bessel"), 1.0, "fp32")
+    for k in ("fourier", "laplace", "bessel"):
+        y = outs[k].cpu().numpy()
+        y = _cplx(y) if k == "fourier" else y
+        ref = O.hybrid(img, xi, k, 1.0)
+        _, S2 = term_scales(img, xi, k, 1.0)
+        ok, ratio, norm, _ = fp32_gate(y, ref, S2)
+        assert ok, (k, ratio, norm)
+    # the backward reduces per-query partials over the same chunks
+    y = plan.hybrid(T(xi), "fourier", 1.0, "fp32")
+    g = np.random.default_rng(8).standard_normal((len(xi), 2))
+    gxi, gs = plan.hybrid_backward(T(xi), y, T(g), "fourier", 1.0, "fp32")
+    ref_xi, ref_s = O.hybrid_grad(img, xi, "fourier", 1.0, g[:, 0] + 1j * g[:, 1])
+    assert np.abs(gxi.cpu().numpy() - ref_xi).max() <= 1e-5 * np.abs(ref_xi).max()
+    assert abs(float(gs.cpu()) - ref_s) <= 1e-5 * max(abs(ref_s), np.abs(ref_xi).max())
+    assert plan.check() == 0
+
+
+def test_same_tuning_bitwise_identical(api, small):
+    img, xi, dirs, thr = small
+    plan = api.Plan(T(img))
+    plan.set_tuning(32, 2048, 2)
+    a = plan.hybrid_multi(T(xi), ("fourier", "laplace"), 1.0, "fp32")
+    plan.set_tuning(0, 64, 0)
+    plan.hybrid_multi(T(xi), ("fourier", "laplace"), 1.0, "fp32")
+    plan.set_tuning(32, 2048, 2)
+    b = plan.hybrid_multi(T(xi), ("fourier", "laplace"), 1.0, "fp32")
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+
+
+def test_rejects_out_of_range(api, small):
+    plan = api.Plan(T(small[0]))
+    for args in [(8, 2048, 0), (-1, 2048, 0), (0, 0, 0), (0, 2048, 9), (0, 2048, -1)]:
+        with pytest.raises(RuntimeError):
+            plan.set_tuning(*args)
+
+
+def test_autotuned_step_replays_and_caches(api, small, tmp_path):
+    from paper_2405_02256_amd import autotune as AT
+    from paper_2405_02256_amd.pipeline import Step
+    img, xi, dirs, thr = small
+    cache = AT.Cache(str(tmp_path / "tuning.json"))
+    plan = api.Plan(T(img))
+    g = T(np.random.default_rng(9).standard_normal((len(xi), 2)))
+    step = Step(plan, T(dirs), T(thr), T(xi), ("fourier", "laplace", "bessel"), backward_kernel="fourier",
+                grad_out=g)
+    t = step.autotune(cache=cache, reps=3)
+    assert t.ect_dirs_per_group in AT.ECT_DIRS_CANDIDATES
+    assert t.hybrid_target_items in AT.HYBRID_ITEM_CANDIDATES
+    assert set(t.timings) == {"ect", "hybrid"}
+    assert plan.tuning == t.as_args()
+    step.run()
+    torch.cuda.synchronize()
+    eager = {k: v.clone() for k, v in step.hy_out.items()}
+    eager_ect, eager_gxi = step.ect_out.clone(), step.grad_xi.clone()
+    assert np.array_equal(eager_ect.cpu().numpy(), O.ect(img, dirs, thr))
+    step.capture()
+    for _ in range(3):
+        for v in step.hy_out.values():
+            v.fill_(float("nan"))
+        step.ect_out.fill_(-1)
+        step.replay()
+        torch.cuda.synchronize()
+        for k in eager:
+            assert torch.equal(step.hy_out[k], eager[k]), k
+        assert torch.equal(step.ect_out, eager_ect)
+        assert torch.equal(step.grad_xi, eager_gxi)
+
+    def no_timing(fn, reps):
+        raise AssertionError("cache hit expected")
+    plan2 = api.Plan(T(img))
+    t2 = AT.tune(plan2, T(dirs), T(thr), T(xi), ("fourier", "laplace", "bessel"), backward_kernel="fourier",
+                 grad_out=g, cache=cache, timer=no_timing)
+    assert t2.as_args() == t.as_args() and plan2.tuning == t.as_args()
