@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="scale of the oracle sample")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-image batched comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule knobs")
+    ap.add_argument("--concurrent", action="store_true", help="run the ECT branch on a side stream")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (counter calibration) and exit")
     return ap.parse_args()
@@ -105,7 +106,7 @@ def main():
     log("building plan")
     plan = api.Plan(img_t)
     step = pipeline.Step(plan, dirs, thr, xi, kernels=KERNELS, s=1.0, precision="fp32",
-                         backward_kernel="fourier", grad_out=g_t, fused=True)
+                         backward_kernel="fourier", grad_out=g_t, fused=True, concurrent=args.concurrent)
 
     # work per step: sum over xi of the ordinary list length of its orthant pair
     n = 2
@@ -212,7 +213,7 @@ def main():
     fp64 = None
     if not args.no_fp64:
         step64 = pipeline.Step(plan, dirs, thr, xi, kernels=KERNELS, s=1.0, precision="fp64",
-                               backward_kernel="fourier", grad_out=g_t, fused=True)
+                               backward_kernel="fourier", grad_out=g_t, fused=True, concurrent=args.concurrent)
         step64.run()
         torch.cuda.synchronize()
         reps = max(3, args.steps // 5)

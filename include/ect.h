@@ -23,6 +23,10 @@
  *   - Every call that takes a stream only enqueues work on it and returns;
  *     results are valid once the stream has been synchronised.  The calls
  *     that say "synchronises" block until their stream is idle.
+ *   - Evaluation calls (ect_eval, hybrid_eval*, ect_plan_export) only read a
+ *     plan's lists: several may run at the same time on different streams as
+ *     long as each has its own workspace.  ect_plan_rerun rewrites the lists,
+ *     so the caller orders it after every evaluation still reading them.
  *   - Embedding axis 0 is the fastest-varying memory axis of an image.  A
  *     vertex with integer index k_a along axis a sits at
  *     x_a = fma(spacing_a, k_a, origin_a); the default origin centres the
@@ -136,8 +140,9 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
 
 /* Re-run the precompute kernels of an existing plan on its pixel buffer (same
  * shapes, new contents).  Enqueues kernels only (no copies, no allocation, no
- * synchronisation), so it can be captured into a HIP graph.  List sizes held
- * on the host are NOT refreshed; device-side consumers read the new sizes. */
+ * synchronisation), so it can be captured into a HIP graph: one kernel launch,
+ * no reset launch before it.  List sizes held on the host are NOT refreshed;
+ * device-side consumers read the new sizes. */
 ect_status ect_plan_rerun(ect_plan plan, hipStream_t stream);
 
 /* ect_eval -- ECT(xi, t_j) at every direction xi of `dirs` and every
@@ -148,7 +153,10 @@ ect_status ect_plan_rerun(ect_plan plan, hipStream_t stream);
  *   thresholds      DEVICE [M] (thresholds_per_image == 0) or [num_images][M];
  *                   non-decreasing per image, closed sublevel sets (u <= t)
  *   out             DEVICE int32 [rows][M], row-major
- *   ws, ws_bytes    DEVICE workspace (ws == NULL: size query)
+ *   ws, ws_bytes    DEVICE workspace (ws == NULL: size query).  A shared
+ *                   set (offsets == NULL) needs none: the size is 0 and any
+ *                   non-NULL ws runs the call.  Ragged sets are bucketed by
+ *                   sign vector in the workspace first.
  * Unsorted thresholds or non-finite directions are detected on the device
  * (error word). */
 ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds, int32_t M,
@@ -193,11 +201,24 @@ ect_status hybrid_eval_multi(ect_plan plan, uint32_t kernel_mask, double s, int3
  *   grad_xi     DEVICE double [rows][ndim] for a ragged set; for a shared set
  *               [count][ndim], summed over images in image order
  *   grad_s      DEVICE double scalar (sum over all rows) or NULL
+ *   flags       0, or ECT_BWD_REUSE_PREPARED: ws still holds the query
+ *               buckets and work list written by the last hybrid_eval /
+ *               hybrid_eval_multi / hybrid_eval_backward call on this plan
+ *               with this ws and this query set (same vector and offset
+ *               pointers, same count, unchanged contents), enqueued earlier
+ *               on the same stream with no use of ws in between; the
+ *               bucketing pass is then skipped.  The host checks what it
+ *               can (workspace and query pointers, count, no ect_plan_rerun or
+ *               ect_plan_set_tuning since) and returns ECT_E_INVALID when the
+ *               last preparation does not match; unchanged contents are the
+ *               caller's promise.  Forward and backward calls need the same
+ *               workspace size.
  * Valid away from directions with a zero coordinate (the transform has kinks
  * there). */
+#define ECT_BWD_REUSE_PREPARED 0x1u
 ect_status hybrid_eval_backward(ect_plan plan, int32_t kernel, double s, int32_t precision,
                                 ect_query_set xi, const double* out, const double* grad_out,
-                                double* grad_xi, double* grad_s,
+                                double* grad_xi, double* grad_s, uint32_t flags,
                                 void* ws, size_t* ws_bytes, hipStream_t stream);
 
 /* Number of list entries per image, read from the host copy made at the end
@@ -215,7 +236,8 @@ ect_status ect_plan_export(ect_plan plan, int32_t image, int32_t kind, int32_t l
                            int32_t* coords, int32_t* values, int64_t capacity, int64_t* count,
                            hipStream_t stream);
 
-/* Read and clear the device error word (ECT_DEVERR_* bits).  Synchronises. */
+/* Read and clear the device error word: the ECT_DEVERR_* bits raised since
+ * the plan was created or last checked.  Synchronises. */
 ect_status ect_plan_check(ect_plan plan, uint32_t* device_error_flags, hipStream_t stream);
 
 /* Free the host handle (the workspace stays with the caller). */

@@ -27,6 +27,7 @@ DEVERR_NONFINITE = 0x4
 DEVERR_LOOKBACK = 0x8
 DEVERR_OVERFLOW = 0x10
 DEVERR_CAPACITY = 0x20
+BWD_REUSE_PREPARED = 0x1
 
 
 class ImageBatch(ctypes.Structure):
@@ -66,8 +67,8 @@ def lib():
     L.hybrid_eval.argtypes = [c_vp, c_i32, c_f64, c_i32, QuerySet, c_vp, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
     L.hybrid_eval_multi.argtypes = [c_vp, c_u32, c_f64, c_i32, QuerySet, c_vp, c_vp, c_vp, c_vp, c_vp,
                                     P(ctypes.c_size_t), c_vp]
-    L.hybrid_eval_backward.argtypes = [c_vp, c_i32, c_f64, c_i32, QuerySet, c_vp, c_vp, c_vp, c_vp, c_vp,
-                                       P(ctypes.c_size_t), c_vp]
+    L.hybrid_eval_backward.argtypes = [c_vp, c_i32, c_f64, c_i32, QuerySet, c_vp, c_vp, c_vp, c_vp, c_u32,
+                                       c_vp, P(ctypes.c_size_t), c_vp]
     L.ect_plan_counts.argtypes = [c_vp, P(c_i64), P(c_i64)]
     L.ect_plan_export.argtypes = [c_vp, c_i32, c_i32, c_i32, P(c_i32), P(c_i32), c_i64, P(c_i64), c_vp]
     L.ect_plan_check.argtypes = [c_vp, P(c_u32), c_vp]
@@ -128,10 +129,10 @@ def hybrid_eval_multi(plan, mask, s, precision, xi: QuerySet, out_f, out_l, out_
 
 
 def hybrid_eval_backward(plan, kernel, s, precision, xi: QuerySet, out, grad_out, grad_xi, grad_s, ws,
-                         ws_bytes: ctypes.c_size_t, stream) -> int:
+                         ws_bytes: ctypes.c_size_t, stream, flags: int = 0) -> int:
     return lib().hybrid_eval_backward(c_vp(plan), int(kernel), float(s), int(precision), xi, c_vp(out),
-                                      c_vp(grad_out), c_vp(grad_xi), c_vp(grad_s) if grad_s else None, ws,
-                                      ctypes.byref(ws_bytes), c_vp(stream))
+                                      c_vp(grad_out), c_vp(grad_xi), c_vp(grad_s) if grad_s else None,
+                                      int(flags), ws, ctypes.byref(ws_bytes), c_vp(stream))
 
 
 def ect_plan_counts(plan, classical, ordinary) -> int:

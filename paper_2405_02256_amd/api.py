@@ -111,7 +111,7 @@ class Plan:
         status, handle = N.ect_precompute(self._batch, ctypes.c_void_p(_dptr(self.ws)), have, st)
         N.check(status, "ect_precompute")
         self.handle = handle
-        self._eval_ws = None
+        self._eval_ws = {}
 
     # -- lifetime ---------------------------------------------------------
     def close(self):
@@ -126,10 +126,13 @@ class Plan:
             pass
 
     # -- helpers ------------------------------------------------------------
-    def _ws(self, nbytes: int) -> torch.Tensor:
-        if self._eval_ws is None or self._eval_ws.numel() < nbytes:
-            self._eval_ws = _workspace(nbytes, self.device)
-        return self._eval_ws
+    def _ws(self, nbytes: int, slot: str = "main") -> torch.Tensor:
+        """Evaluation workspace `slot`: calls that may run at the same time on
+        different streams must use different slots."""
+        ws = self._eval_ws.get(slot)
+        if ws is None or ws.numel() < nbytes:
+            ws = self._eval_ws[slot] = _workspace(nbytes, self.device)
+        return ws
 
     def set_tuning(self, hybrid_chunk: int = 0, hybrid_target_items: int = 2048, ect_dirs_per_group: int = 0):
         N.check(N.ect_plan_set_tuning(self.handle, hybrid_chunk, hybrid_target_items, ect_dirs_per_group),
@@ -166,7 +169,7 @@ class Plan:
         return f.value
 
     # -- evaluation ---------------------------------------------------------
-    def ect(self, dirs, thresholds: torch.Tensor, offsets=None, out=None, stream=None) -> torch.Tensor:
+    def ect(self, dirs, thresholds: torch.Tensor, offsets=None, out=None, stream=None, slot: str = "main") -> torch.Tensor:
         """int32 [rows][M]: ECT at every direction and threshold (thresholds [M] or [num_images][M])."""
         q = dirs if isinstance(dirs, QuerySet) else QuerySet(dirs, offsets)
         q.validate(self.num_images, self.ndim)
@@ -181,14 +184,14 @@ class Plan:
         st = _stream(stream)
         need = ctypes.c_size_t(0)
         N.check(N.ect_eval(self.handle, q.c(), _dptr(thr), M, per_image, _dptr(out), None, need, st), "ect_eval(size)")
-        ws = self._ws(need.value)
+        ws = self._ws(need.value, slot)
         have = ctypes.c_size_t(ws.numel())
         N.check(N.ect_eval(self.handle, q.c(), _dptr(thr), M, per_image, _dptr(out),
                            ctypes.c_void_p(_dptr(ws)), have, st), "ect_eval")
         return out
 
     def hybrid(self, xi, kernel: str = "fourier", s: float = 1.0, precision: str = "fp32", offsets=None,
-               log_scale: bool = False, out=None, stream=None, log_scale_out=None):
+               log_scale: bool = False, out=None, stream=None, log_scale_out=None, slot: str = "main"):
         """float64 [rows] (Fourier: [rows][2]); with log_scale (Laplace) returns (out, log_scale)."""
         q = xi if isinstance(xi, QuerySet) else QuerySet(xi, offsets)
         q.validate(self.num_images, self.ndim)
@@ -204,14 +207,14 @@ class Plan:
         need = ctypes.c_size_t(0)
         N.check(N.hybrid_eval(self.handle, k, s, N.PRECISIONS[precision], q.c(), _dptr(out), _dptr(ls), None,
                               need, st), "hybrid_eval(size)")
-        ws = self._ws(need.value)
+        ws = self._ws(need.value, slot)
         have = ctypes.c_size_t(ws.numel())
         N.check(N.hybrid_eval(self.handle, k, s, N.PRECISIONS[precision], q.c(), _dptr(out), _dptr(ls),
                               ctypes.c_void_p(_dptr(ws)), have, st), "hybrid_eval")
         return (out, ls) if log_scale else out
 
     def hybrid_multi(self, xi, kernels=("fourier", "laplace", "bessel"), s: float = 1.0, precision: str = "fp32",
-                     offsets=None, outs=None, log_scale_out=None, stream=None) -> dict:
+                     offsets=None, outs=None, log_scale_out=None, stream=None, slot: str = "main") -> dict:
         """Several kernels in one pass: {kernel: output} (outputs as hybrid())."""
         q = xi if isinstance(xi, QuerySet) else QuerySet(xi, offsets)
         q.validate(self.num_images, self.ndim)
@@ -228,15 +231,20 @@ class Plan:
         need = ctypes.c_size_t(0)
         N.check(N.hybrid_eval_multi(self.handle, mask, s, N.PRECISIONS[precision], q.c(), *ptrs,
                                     _dptr(log_scale_out), None, need, st), "hybrid_eval_multi(size)")
-        ws = self._ws(need.value)
+        ws = self._ws(need.value, slot)
         have = ctypes.c_size_t(ws.numel())
         N.check(N.hybrid_eval_multi(self.handle, mask, s, N.PRECISIONS[precision], q.c(), *ptrs,
                                     _dptr(log_scale_out), ctypes.c_void_p(_dptr(ws)), have, st), "hybrid_eval_multi")
         return {k: outs[k] for k in kernels}
 
     def hybrid_backward(self, xi, out: torch.Tensor, grad_out: torch.Tensor, kernel: str = "fourier", s: float = 1.0,
-                        precision: str = "fp32", offsets=None, stream=None, grad_xi=None, grad_s=None):
-        """(grad_xi, grad_s): VJP of hybrid() (shared sets sum grad_xi over images)."""
+                        precision: str = "fp32", offsets=None, stream=None, grad_xi=None, grad_s=None,
+                        slot: str = "main", reuse_prepared: bool = False):
+        """(grad_xi, grad_s): VJP of hybrid() (shared sets sum grad_xi over images).
+
+        reuse_prepared: the last forward call on this plan used the same query
+        set (same QuerySet object or tensors, unchanged) and workspace slot,
+        on the same stream, so its bucketing is reused."""
         q = xi if isinstance(xi, QuerySet) else QuerySet(xi, offsets)
         q.validate(self.num_images, self.ndim)
         k = N.KERNELS[kernel]
@@ -252,10 +260,11 @@ class Plan:
         need = ctypes.c_size_t(0)
         N.check(N.hybrid_eval_backward(self.handle, k, s, N.PRECISIONS[precision], q.c(), _dptr(out), _dptr(go),
                                        _dptr(gxi), _dptr(gs), None, need, st), "hybrid_eval_backward(size)")
-        ws = self._ws(need.value)
+        ws = self._ws(need.value, slot)
         have = ctypes.c_size_t(ws.numel())
         N.check(N.hybrid_eval_backward(self.handle, k, s, N.PRECISIONS[precision], q.c(), _dptr(out), _dptr(go),
-                                       _dptr(gxi), _dptr(gs), ctypes.c_void_p(_dptr(ws)), have, st),
+                                       _dptr(gxi), _dptr(gs), ctypes.c_void_p(_dptr(ws)), have, st,
+                                       N.BWD_REUSE_PREPARED if reuse_prepared else 0),
                 "hybrid_eval_backward")
         return gxi, gs
 

@@ -160,10 +160,10 @@ def tune(plan, ect_dirs=None, ect_thresholds=None, hybrid_xi=None, kernels=("fou
         out = None
         for td in ECT_DIRS_CANDIDATES:
             plan.set_tuning(0, best.hybrid_target_items, td)
-            out = plan.ect(eq, ect_thresholds)
+            out = plan.ect(eq, ect_thresholds, slot="ect")
 
             def run(o=out):
-                plan.ect(eq, ect_thresholds, out=o)
+                plan.ect(eq, ect_thresholds, out=o, slot="ect")
             ect_t[td] = timer(run, reps)
         best.ect_dirs_per_group = pick(ect_t)
         timings["ect"] = {str(k): v for k, v in ect_t.items()}

@@ -98,11 +98,12 @@ void layout_hybrid(const Plan& p, const ect_query_set& q, bool backward, EvalLay
     L->grid = tiles * maxch;
     L->capacity = L->grid;
     L->partials = o; o = align_up(o + sizeof(double) * kAccSlotsHost * kHybridTile * std::max<int64_t>(L->capacity, 1), kAlign);
-    L->gpart = L->gspart = 0;
-    if (backward) {
-        L->gpart = o; o = align_up(o + sizeof(double) * p.ndim * std::max<int64_t>(rows, 1), kAlign);
-        L->gspart = o; o = align_up(o + sizeof(double) * std::max<int64_t>(rows, 1), kAlign);
-    }
+    // gradient partials are reserved for forward calls too, so that one
+    // workspace size serves a forward call and the backward call reusing its
+    // buckets and work list
+    (void)backward;
+    L->gpart = o; o = align_up(o + sizeof(double) * p.ndim * std::max<int64_t>(rows, 1), kAlign);
+    L->gspart = o; o = align_up(o + sizeof(double) * std::max<int64_t>(rows, 1), kAlign);
     L->total = o;
 }
 
@@ -191,7 +192,7 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
 
     PlanLayout L{};
     size_t o = 0;
-    L.err = o; o = align_up(o + 16, kAlign);
+    L.err = o; o = align_up(o + 16, kAlign);   // uint32 error word, uint32 spare, uint64 ticket counter
     L.desc = o; o = align_up(o + sizeof(ImageDesc) * ni, kAlign);
     L.tile_start = o; o = align_up(o + sizeof(int64_t) * (ni + 1), kAlign);
     L.list_off = o; o = align_up(o + sizeof(int64_t) * (int64_t)(ni + 1) * NL, kAlign);
@@ -230,7 +231,7 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
     hipError_t e = hipMemcpyAsync(p->ws + L.desc, desc.data(), sizeof(ImageDesc) * ni, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->ws + L.tile_start, tstart.data(), sizeof(int64_t) * (ni + 1), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = launch_precompute(*p, stream);
+    if (e == hipSuccess) e = launch_precompute(*p, true, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->h_list_off, p->ws + L.list_off, sizeof(int64_t) * (int64_t)(ni + 1) * NL,
                            hipMemcpyDeviceToHost, stream);
@@ -245,7 +246,8 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
 
 ect_status ect_plan_rerun(ect_plan plan, hipStream_t stream) {
     if (!plan) return ECT_E_INVALID;
-    return from_hip(launch_precompute(*plan, stream));
+    ++plan->lists_epoch;
+    return from_hip(launch_precompute(*plan, false, stream));
 }
 
 ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds, int32_t M,
@@ -263,8 +265,10 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
     const int64_t lds_budget = 60 * 1024;
     td = (int)std::min<int64_t>(td, (lds_budget - 8 * (int64_t)M) / (4 * (int64_t)M));
     td = std::max(1, std::min(td, kEctMaxDirs));
+    // shared sets go straight to the evaluation kernel (no bucketing, no workspace)
+    const bool direct = dirs.offsets == nullptr;
     EvalLayout L{};
-    layout_ect(p, dirs, td, &L);
+    if (!direct) layout_ect(p, dirs, td, &L);
     if (!ws) {
         *ws_bytes = L.total;
         return ECT_OK;
@@ -273,12 +277,19 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
     const int64_t rows = query_rows(dirs, p.num_images);
     if (rows == 0) return ECT_OK;
     char* w = (char*)ws;
-    const int B = num_classical(p.ndim);
     const int NL = num_lists(p.ndim);
     uint32_t* err = (uint32_t*)(p.ws + p.lay.err);
-    hipError_t e = launch_prepare(p.ndim, dirs, p.num_images, false, err, (QRec*)(w + L.recs), (int32_t*)(w + L.bcnt),
-                                  (const int64_t*)(p.ws + p.lay.list_off), 0, NL, td, 0, 0, (int64_t*)(w + L.item_off),
-                                  (int64_t*)(w + L.tile_off), (int64_t*)(w + L.params), stream);
+    hipError_t e = hipSuccess;
+    int64_t direct_groups = 0;
+    if (direct) {
+        direct_groups = (dirs.count + td - 1) / td;
+        L.grid = direct_groups * p.num_images;
+    } else {
+        if (plan->last_prep.ws == ws) plan->last_prep.valid = false;
+        e = launch_prepare(p.ndim, dirs, p.num_images, false, err, (QRec*)(w + L.recs), (int32_t*)(w + L.bcnt),
+                           (const int64_t*)(p.ws + p.lay.list_off), 0, NL, td, 0, 0, (int64_t*)(w + L.item_off),
+                           (int64_t*)(w + L.tile_off), (int64_t*)(w + L.params), stream);
+    }
     if (e == hipSuccess) {
         EctArgs a{};
         a.points = (const Point*)(p.ws + p.lay.points);
@@ -294,12 +305,12 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
         a.M = M;
         a.thr_per_image = thresholds_per_image ? 1 : 0;
         a.out = out;
-        a.recs = (const QRec*)(w + L.recs);
-        a.bcnt = (const int32_t*)(w + L.bcnt);
-        a.item_off = (const int64_t*)(w + L.item_off);
+        a.recs = direct ? nullptr : (const QRec*)(w + L.recs);
+        a.bcnt = direct ? nullptr : (const int32_t*)(w + L.bcnt);
+        a.item_off = direct ? nullptr : (const int64_t*)(w + L.item_off);
         a.err = err;
         a.dirs_per_group = td;
-        e = launch_ect(p.ndim, a, L.grid, stream);
+        e = launch_ect(p.ndim, a, L.grid, direct_groups, stream);
     }
     return from_hip(e);
 }
@@ -307,7 +318,8 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
 static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t precision, ect_query_set xi,
                                 double* out_f, double* out_l, double* out_b, double* log_scale,
                                 const double* fwd_out, const double* grad_out, double* grad_xi, double* grad_s,
-                                void* ws, size_t* ws_bytes, hipStream_t stream, bool backward) {
+                                void* ws, size_t* ws_bytes, hipStream_t stream, bool backward,
+                                bool reuse = false) {
     if (!plan || !ws_bytes) return ECT_E_INVALID;
     if (mask == 0 || mask > 7) return ECT_E_INVALID;
     if (backward && (mask & (mask - 1))) return ECT_E_INVALID;
@@ -329,17 +341,33 @@ static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t 
         return ECT_OK;
     }
     if (*ws_bytes < L.total) return ECT_E_NOMEM;
+    auto& lp = plan->last_prep;
+    if (reuse && !(lp.valid && lp.ws == ws && lp.vecs == xi.vecs && lp.offsets == xi.offsets &&
+                   lp.count == xi.count && lp.epoch == plan->lists_epoch))
+        return ECT_E_INVALID;
     const int64_t rows = query_rows(xi, p.num_images);
     if (rows == 0) return ECT_OK;
     char* w = (char*)ws;
     const int NL = num_lists(p.ndim);
     uint32_t* err = (uint32_t*)(p.ws + p.lay.err);
     const bool shared = xi.offsets == nullptr;
-    hipError_t e = launch_prepare(p.ndim, xi, p.num_images, true, err, (QRec*)(w + L.recs), (int32_t*)(w + L.bcnt),
-                                  (const int64_t*)(p.ws + p.lay.list_off), num_classical(p.ndim), NL,
-                                  kHybridTile, chunk, L.capacity, (int64_t*)(w + L.item_off),
-                                  (int64_t*)(w + L.tile_off), (int64_t*)(w + L.params), stream);
-    if (e != hipSuccess) return ECT_E_DEVICE;
+    hipError_t e = hipSuccess;
+    if (!reuse) {
+        e = launch_prepare(p.ndim, xi, p.num_images, true, err, (QRec*)(w + L.recs), (int32_t*)(w + L.bcnt),
+                           (const int64_t*)(p.ws + p.lay.list_off), num_classical(p.ndim), NL, kHybridTile, chunk,
+                           L.capacity, (int64_t*)(w + L.item_off), (int64_t*)(w + L.tile_off),
+                           (int64_t*)(w + L.params), stream);
+        if (e != hipSuccess) {
+            lp.valid = false;
+            return ECT_E_DEVICE;
+        }
+        lp.ws = ws;
+        lp.vecs = xi.vecs;
+        lp.offsets = xi.offsets;
+        lp.count = xi.count;
+        lp.epoch = plan->lists_epoch;
+        lp.valid = true;
+    }
     HybridArgs a{};
     a.points = (const Point*)(p.ws + p.lay.points);
     a.list_off = (const int64_t*)(p.ws + p.lay.list_off);
@@ -395,10 +423,11 @@ ect_status hybrid_eval_multi(ect_plan plan, uint32_t kernel_mask, double s, int3
 
 ect_status hybrid_eval_backward(ect_plan plan, int32_t kernel, double s, int32_t precision, ect_query_set xi,
                                 const double* out, const double* grad_out, double* grad_xi, double* grad_s,
-                                void* ws, size_t* ws_bytes, hipStream_t stream) {
+                                uint32_t flags, void* ws, size_t* ws_bytes, hipStream_t stream) {
     if (kernel < ECT_FOURIER || kernel > ECT_BESSEL) return ECT_E_INVALID;
+    if (flags & ~(uint32_t)ECT_BWD_REUSE_PREPARED) return ECT_E_INVALID;
     return hybrid_common(plan, 1u << kernel, s, precision, xi, nullptr, nullptr, nullptr, nullptr, out, grad_out,
-                         grad_xi, grad_s, ws, ws_bytes, stream, true);
+                         grad_xi, grad_s, ws, ws_bytes, stream, true, (flags & ECT_BWD_REUSE_PREPARED) != 0);
 }
 
 ect_status ect_plan_counts(ect_plan plan, int64_t* classical, int64_t* ordinary) {
@@ -485,6 +514,7 @@ ect_status ect_plan_set_tuning(ect_plan plan, int64_t hybrid_chunk, int64_t hybr
         hybrid_target_items < 1 || hybrid_target_items > (int64_t(1) << 24) || ect_dirs_per_group < 0 ||
         ect_dirs_per_group > kEctMaxDirs)
         return ECT_E_INVALID;
+    ++plan->lists_epoch;
     plan->tune_hybrid_chunk = hybrid_chunk;
     plan->tune_hybrid_target_items = hybrid_target_items;
     plan->tune_ect_dirs_per_group = ect_dirs_per_group;

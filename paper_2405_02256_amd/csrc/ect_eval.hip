@@ -10,6 +10,10 @@
 // is the ECT row (the vectorization of Sec. 4.3 and Appendix A, at arbitrary
 // non-decreasing thresholds).
 //
+// Shared query sets (one direction set for every image) are evaluated without
+// a bucketing pass (ect_direct_kernel); ragged sets are bucketed by sign vector
+// first (ect_kernel).
+//
 // The bin search starts from the arithmetic guess for evenly spaced thresholds
 // and corrects it against the stored thresholds, so any non-decreasing array
 // gives the exact answer and an evenly spaced one needs at most a step or two.
@@ -19,12 +23,99 @@ namespace ect {
 
 namespace {
 
+// Stage the thresholds of image img in LDS and clear the histograms; returns
+// nonzero (in every thread) when they are not non-decreasing or not finite.
+__device__ __forceinline__ int stage_thresholds(const EctArgs& a, int64_t img, double* s_thr, int32_t* s_hist) {
+    const int M = a.M;
+    const double* thr = a.thresholds + (a.thr_per_image ? img * M : 0);
+    int bad = 0;
+    for (int j = threadIdx.x; j < M; j += kEctThreads) {
+        const double v = thr[j];
+        s_thr[j] = v;
+        if (j > 0 && !(v >= thr[j - 1])) bad = 1;
+        if (!isfinite(v)) bad = 1;
+    }
+    for (int j = threadIdx.x; j < a.dirs_per_group * M; j += kEctThreads) s_hist[j] = 0;
+    return __syncthreads_or(bad);
+}
+
+// Stream points [p0, p1) of one list and add each point's critical value into
+// the histogram of every direction dd with use[dd].
+template <int N>
+__device__ __forceinline__ void accumulate_list(const Point* __restrict__ pts, int64_t p0, int64_t p1,
+                                                const double (&xi)[kEctMaxDirs][N], const bool (&use)[kEctMaxDirs],
+                                                const double* s_thr, int M, int32_t* s_hist) {
+    const double t0 = s_thr[0], t1 = s_thr[M - 1];
+    const double inv = (M > 1 && t1 > t0) ? (double)(M - 1) / (t1 - t0) : 0.0;
+    // U points per thread are loaded before any is processed, so that their
+    // memory latencies overlap
+    constexpr int U = 4;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += (int64_t)kEctThreads * U) {
+        Point pt[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t pp = p + (int64_t)u * kEctThreads;
+            if (pp < p1) pt[u] = pts[pp];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (p + (int64_t)u * kEctThreads >= p1) break;
+            const int32_t val = (int32_t)pt[u].val;
+#pragma unroll
+            for (int dd = 0; dd < kEctMaxDirs; ++dd) {
+                if (!use[dd]) continue;
+                const double uu = project<N>(xi[dd], pt[u].x);
+                double g = ceil((uu - t0) * inv);
+                g = fmin(fmax(g, 0.0), (double)M);
+                int j = (int)g;
+                while (j > 0 && s_thr[j - 1] >= uu) --j;
+                while (j < M && s_thr[j] < uu) ++j;
+                if (j < M) atomicAdd(&s_hist[dd * M + j], val);
+            }
+        }
+    }
+}
+
+// Inclusive prefix sum of each histogram into its output row (zeros for an
+// invalid direction); one wave per direction.
+__device__ __forceinline__ void write_rows(const EctArgs& a, int nd, const int64_t* s_row, const int* s_valid,
+                                           const int32_t* s_hist) {
+    const int M = a.M;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int W = kEctThreads / 64;
+    for (int dd = wave; dd < nd; dd += W) {
+        int32_t* out = a.out + s_row[dd] * M;
+        if (!s_valid[dd]) {
+            for (int j = lane; j < M; j += 64) out[j] = 0;
+            continue;
+        }
+        int32_t carry = 0;
+        for (int jb = 0; jb < M; jb += 64) {
+            const int j = jb + lane;
+            int32_t v = j < M ? s_hist[dd * M + j] : 0;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                int32_t o = __shfl_up(v, off, 64);
+                if (lane >= off) v += o;
+            }
+            if (j < M) out[j] = carry + v;
+            carry += __shfl(v, 63, 64);
+        }
+    }
+}
+
+__device__ __forceinline__ void zero_rows(const EctArgs& a, int nd, const int64_t* s_row) {
+    for (int dd = 0; dd < nd; ++dd)
+        for (int j = threadIdx.x; j < a.M; j += kEctThreads) a.out[s_row[dd] * a.M + j] = 0;
+}
+
+// Bucketed sets (ragged query sets): one workgroup per group of up to
+// dirs_per_group directions of one (image, sign vector) bucket.
 template <int N>
 __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
     extern __shared__ __align__(16) char smem[];
     constexpr int TD = kEctMaxDirs;
     constexpr int B = 1 << N;
-    constexpr int W = kEctThreads / 64;
     const int M = a.M;
     double* s_thr = (double*)smem;
     int32_t* s_hist = (int32_t*)(smem + sizeof(double) * M);
@@ -32,7 +123,7 @@ __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
     __shared__ int64_t s_row[TD];
     __shared__ int s_valid[TD];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     const int64_t item = blockIdx.x;
     const int64_t E = (int64_t)a.num_images * B;
     if (item >= a.item_off[E]) return;
@@ -70,25 +161,11 @@ __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
         s_row[tid] = row;
         s_valid[tid] = ok;
     }
-    const double* thr = a.thresholds + (a.thr_per_image ? img * M : 0);
-    int bad = 0;
-    for (int j = tid; j < M; j += kEctThreads) {
-        double v = thr[j];
-        s_thr[j] = v;
-        if (j > 0 && !(v >= thr[j - 1])) bad = 1;
-        if (!isfinite(v)) bad = 1;
-    }
-    for (int j = tid; j < a.dirs_per_group * M; j += kEctThreads) s_hist[j] = 0;
-    bad = __syncthreads_or(bad);
-    if (bad) {
+    if (stage_thresholds(a, img, s_thr, s_hist)) {
         if (tid == 0) raise_error(a.err, ECT_DEVERR_THRESHOLDS);
-        for (int dd = 0; dd < nd; ++dd)
-            for (int j = tid; j < M; j += kEctThreads) a.out[s_row[dd] * M + j] = 0;
+        zero_rows(a, nd, s_row);
         return;
     }
-
-    const double t0 = s_thr[0], t1 = s_thr[M - 1];
-    const double inv = (M > 1 && t1 > t0) ? (double)(M - 1) / (t1 - t0) : 0.0;
     double xi[TD][N];
     bool use[TD];
 #pragma unroll
@@ -97,70 +174,112 @@ __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
 #pragma unroll
         for (int c = 0; c < N; ++c) xi[dd][c] = s_xi[dd][c];
     }
-
-    const Point* __restrict__ pts = a.points + (int64_t)b * a.capacity;
     const int64_t p0 = a.list_off[img * a.NL + b], p1 = a.list_off[(img + 1) * a.NL + b];
-    // U points per thread are loaded before any is processed, so that their
-    // memory latencies overlap
-    constexpr int U = 4;
-    for (int64_t p = p0 + tid; p < p1; p += (int64_t)kEctThreads * U) {
-        Point pt[U];
+    accumulate_list<N>(a.points + (int64_t)b * a.capacity, p0, p1, xi, use, s_thr, M, s_hist);
+    __syncthreads();
+    write_rows(a, nd, s_row, s_valid, s_hist);
+}
+
+// Shared query sets: no bucketing pass.  Workgroup (image, g) takes rows
+// [g * dirs_per_group, ...) of the set in input order and streams the list of
+// each distinct sign vector among them once, for the directions that have it
+// (one pass when neighbouring directions share an orthant, as in angle-ordered
+// sets).  A non-finite direction gets a zero row and raises
+// ECT_DEVERR_NONFINITE, as in the bucketed path.
+template <int N>
+__global__ void __launch_bounds__(kEctThreads) ect_direct_kernel(EctArgs a, int64_t groups) {
+    extern __shared__ __align__(16) char smem[];
+    constexpr int TD = kEctMaxDirs;
+    const int M = a.M;
+    double* s_thr = (double*)smem;
+    int32_t* s_hist = (int32_t*)(smem + sizeof(double) * M);
+    __shared__ double s_xi[TD][3];
+    __shared__ int64_t s_row[TD];
+    __shared__ int s_valid[TD];
+    __shared__ int s_sign[TD];
+
+    const int tid = threadIdx.x;
+    const int64_t img = blockIdx.x / groups;
+    const int64_t g = blockIdx.x % groups;
+    const int TDg = a.dirs_per_group;
+    const int64_t q0 = g * TDg;
+    const int nd = (int)min<int64_t>(TDg, a.count - q0);
+    if (tid < TD) {
+        int ok = 0, sg = 0;
+        int64_t row = -1;
+        if (tid < nd) {
+            const int64_t q = q0 + tid;
+            row = img * a.count + q;
+            double v[3] = {0.0, 0.0, 0.0};
+            ok = 1;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t pp = p + (int64_t)u * kEctThreads;
-            if (pp < p1) pt[u] = pts[pp];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (p + (int64_t)u * kEctThreads >= p1) break;
-            const int32_t val = (int32_t)pt[u].val;
-#pragma unroll
-            for (int dd = 0; dd < TD; ++dd) {
-                if (!use[dd]) continue;
-                const double uu = project<N>(xi[dd], pt[u].x);
-                double g = ceil((uu - t0) * inv);
-                g = fmin(fmax(g, 0.0), (double)M);
-                int j = (int)g;
-                while (j > 0 && s_thr[j - 1] >= uu) --j;
-                while (j < M && s_thr[j] < uu) ++j;
-                if (j < M) atomicAdd(&s_hist[dd * M + j], val);
+            for (int c = 0; c < N; ++c) {
+                v[c] = a.vecs[q * N + c];
+                ok &= isfinite(v[c]) ? 1 : 0;
             }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s_xi[tid][c] = v[c];
+            sg = sign_index<N>(v);
+            if (!ok) raise_error(a.err, ECT_DEVERR_NONFINITE);
         }
+        s_row[tid] = row;
+        s_valid[tid] = ok;
+        s_sign[tid] = sg;
+    }
+    if (stage_thresholds(a, img, s_thr, s_hist)) {
+        if (tid == 0) raise_error(a.err, ECT_DEVERR_THRESHOLDS);
+        zero_rows(a, nd, s_row);
+        return;
+    }
+    double xi[TD][N];
+    int sgn[TD];
+    bool pending[TD];
+#pragma unroll
+    for (int dd = 0; dd < TD; ++dd) {
+        pending[dd] = dd < nd && s_valid[dd];
+        sgn[dd] = s_sign[dd];
+#pragma unroll
+        for (int c = 0; c < N; ++c) xi[dd][c] = s_xi[dd][c];
+    }
+    // one pass per distinct sign vector, in order of first appearance
+    for (int pass = 0; pass < TD; ++pass) {
+        int b = -1;
+#pragma unroll
+        for (int dd = TD - 1; dd >= 0; --dd)
+            if (pending[dd]) b = sgn[dd];
+        if (b < 0) break;
+        bool use[TD];
+#pragma unroll
+        for (int dd = 0; dd < TD; ++dd) {
+            use[dd] = pending[dd] && sgn[dd] == b;
+            if (use[dd]) pending[dd] = false;
+        }
+        const int64_t p0 = a.list_off[img * a.NL + b], p1 = a.list_off[(img + 1) * a.NL + b];
+        accumulate_list<N>(a.points + (int64_t)b * a.capacity, p0, p1, xi, use, s_thr, M, s_hist);
     }
     __syncthreads();
-
-    for (int dd = wave; dd < nd; dd += W) {
-        int32_t* out = a.out + s_row[dd] * M;
-        if (!s_valid[dd]) {
-            for (int j = lane; j < M; j += 64) out[j] = 0;
-            continue;
-        }
-        int32_t carry = 0;
-        for (int jb = 0; jb < M; jb += 64) {
-            const int j = jb + lane;
-            int32_t v = j < M ? s_hist[dd * M + j] : 0;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                int32_t o = __shfl_up(v, off, 64);
-                if (lane >= off) v += o;
-            }
-            if (j < M) out[j] = carry + v;
-            carry += __shfl(v, 63, 64);
-        }
-    }
+    write_rows(a, nd, s_row, s_valid, s_hist);
 }
 
 }  // namespace
 
-hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, hipStream_t stream) {
+hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, int64_t direct_groups, hipStream_t stream) {
     if (grid <= 0) return hipSuccess;
     size_t shmem = sizeof(double) * a.M + sizeof(int32_t) * a.dirs_per_group * a.M;
     hipError_t e = stage_mark(ECT_STAGE_ECT, false, stream);
     if (e != hipSuccess) return e;
-    if (ndim == 2)
+    if (direct_groups > 0) {
+        if (ndim == 2)
+            hipLaunchKernelGGL(ect_direct_kernel<2>, dim3((unsigned)grid), dim3(kEctThreads), shmem, stream, a,
+                               direct_groups);
+        else
+            hipLaunchKernelGGL(ect_direct_kernel<3>, dim3((unsigned)grid), dim3(kEctThreads), shmem, stream, a,
+                               direct_groups);
+    } else if (ndim == 2) {
         hipLaunchKernelGGL(ect_kernel<2>, dim3((unsigned)grid), dim3(kEctThreads), shmem, stream, a);
-    else
+    } else {
         hipLaunchKernelGGL(ect_kernel<3>, dim3((unsigned)grid), dim3(kEctThreads), shmem, stream, a);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return stage_mark(ECT_STAGE_ECT, true, stream);

@@ -42,7 +42,7 @@ struct alignas(16) ImageDesc {
 
 // Layout of the precompute workspace (byte offsets from its base).
 struct PlanLayout {
-    size_t err;             // uint32 device error word (+ uint32 tile counter right after)
+    size_t err;             // uint32 device error word, uint32 spare, uint64 look-back ticket counter
     size_t desc;            // ImageDesc[num_images]
     size_t tile_start;      // int64[num_images + 1]
     size_t list_off;        // int64[(num_images + 1) * NL]: start of image i in list l
@@ -68,6 +68,18 @@ struct ect_plan_s {
     int64_t* h_list_off = nullptr;      // host copy [(num_images+1) * NL], as of the last ect_precompute
     int64_t total_verts = 0;
     int64_t max_image_verts = 0;
+    // bumped by every call that can change list sizes or the work-list shape
+    // (ect_plan_rerun, ect_plan_set_tuning)
+    uint64_t lists_epoch = 0;
+    // the hybrid query buckets and work list last written into a workspace
+    struct {
+        const void* ws = nullptr;
+        const double* vecs = nullptr;
+        const int64_t* offsets = nullptr;
+        int64_t count = 0;
+        uint64_t epoch = 0;
+        bool valid = false;
+    } last_prep;
     int64_t tune_hybrid_chunk = 0;          // 0: automatic
     int64_t tune_hybrid_target_items = 2048;
     int32_t tune_ect_dirs_per_group = 0;    // 0: automatic
@@ -113,6 +125,8 @@ inline hipError_t stage_mark(int stage, bool after, hipStream_t s) {
 }
 
 // Kernel launch helpers (host side, defined in the .hip files).
-hipError_t launch_precompute(const Plan& p, hipStream_t stream);
+// first: also clear the plan's error word, ticket counter and look-back words
+// (plan creation); re-runs launch the classification kernel alone.
+hipError_t launch_precompute(const Plan& p, bool first, hipStream_t stream);
 
 }  // namespace ect

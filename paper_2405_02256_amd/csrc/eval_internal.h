@@ -61,7 +61,9 @@ struct EctArgs {
     int dirs_per_group;
 };
 
-hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, hipStream_t stream);
+// direct_groups > 0: shared query set, grid = num_images * direct_groups
+// workgroups of ect_direct_kernel (no bucketing); else the bucketed kernel.
+hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, int64_t direct_groups, hipStream_t stream);
 
 struct HybridArgs {
     const Point* points;

@@ -348,13 +348,20 @@ __global__ void __launch_bounds__(kHybridThreads) hybrid_kernel(HybridArgs a) {
     if (active) finalize<N, MASK, PREC, BWD>(a, q, row, acc);
 }
 
-// One 64-thread workgroup per query tile: add the partial sums of a
-// multi-chunk tile in chunk order and write the outputs (single-chunk tiles
-// were written already).
+// One workgroup of four waves per query tile: add the partial sums of a
+// multi-chunk tile and write the outputs (single-chunk tiles were written
+// already).  Wave w adds the w-th quarter of the chunks in chunk order, with
+// kReduceBatch chunks' loads in flight per lane; the four quarter sums are then
+// added in wave order, so the result is fixed by the chunk count alone.
+constexpr int kReduceBatch = 8;
+
 template <int N, int MASK, int PREC, bool BWD>
-__global__ void __launch_bounds__(kHybridTile) hybrid_reduce_kernel(HybridArgs a) {
+__global__ void __launch_bounds__(kHybridThreads) hybrid_reduce_kernel(HybridArgs a) {
     constexpr int P = 1 << (N - 1);
+    __shared__ double s_acc[kHybridSplit - 1][kAccSlots][kHybridTile];
     const int tid = threadIdx.x;
+    const int lane = tid & (kHybridTile - 1);
+    const int wave = tid / kHybridTile;
     const int64_t tile = blockIdx.x;
     if (tile >= a.params[1]) return;
     const int64_t C = a.params[2];
@@ -367,27 +374,40 @@ __global__ void __launch_bounds__(kHybridTile) hybrid_reduce_kernel(HybridArgs a
     const int64_t chunks = np > 0 ? (np + C - 1) / C : 1;
     if (chunks == 1) return;
     const int64_t qn = a.bcnt[a.offsets == nullptr ? b : e];
-    const int64_t qi = t * kHybridTile + tid;
-    if (qi >= qn) return;
+    const int64_t qi = t * kHybridTile + lane;
+    const bool active = qi < qn;
     Query<N> q;
-    int64_t row;
-    setup_query<N, MASK, PREC, BWD>(a, img, b, qi, true, q, row);
-    double acc[kAccSlots] = {0.0, 0.0, 0.0, 0.0};
+    int64_t row = 0;
+    if (wave == 0) setup_query<N, MASK, PREC, BWD>(a, img, b, qi, active, q, row);
     const int64_t first = a.item_off[e] + t * chunks;
-    constexpr int BATCH = 16;
-    for (int64_t cc = 0; cc < chunks; cc += BATCH) {
-        double v[BATCH][kAccSlots];
+    const int64_t per = (chunks + kHybridSplit - 1) / kHybridSplit;
+    const int64_t lo = min<int64_t>(chunks, wave * per), hi = min<int64_t>(chunks, lo + per);
+    double acc[kAccSlots] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t cc = lo; cc < hi; cc += kReduceBatch) {
+        double v[kReduceBatch][kAccSlots];
 #pragma unroll
-        for (int j = 0; j < BATCH; ++j)
+        for (int j = 0; j < kReduceBatch; ++j)
 #pragma unroll
             for (int k = 0; k < kAccSlots; ++k)
-                v[j][k] = (slot_used<MASK, BWD, N>(k) && cc + j < chunks)
-                              ? a.partials[partial_index(first + cc + j, k, tid)] : 0.0;
+                v[j][k] = (slot_used<MASK, BWD, N>(k) && cc + j < hi)
+                              ? a.partials[partial_index(first + cc + j, k, lane)] : 0.0;
 #pragma unroll
-        for (int j = 0; j < BATCH; ++j)
+        for (int j = 0; j < kReduceBatch; ++j)
 #pragma unroll
             for (int k = 0; k < kAccSlots; ++k) acc[k] += v[j][k];
     }
+    if (wave > 0) {
+#pragma unroll
+        for (int k = 0; k < kAccSlots; ++k)
+            if (slot_used<MASK, BWD, N>(k)) s_acc[wave - 1][k][lane] = acc[k];
+    }
+    __syncthreads();
+    if (wave > 0 || !active) return;
+#pragma unroll
+    for (int w = 0; w < kHybridSplit - 1; ++w)
+#pragma unroll
+        for (int k = 0; k < kAccSlots; ++k)
+            if (slot_used<MASK, BWD, N>(k)) acc[k] += s_acc[w][k][lane];
     finalize<N, MASK, PREC, BWD>(a, q, row, acc);
 }
 
@@ -398,19 +418,35 @@ __global__ void __launch_bounds__(256)
 grad_reduce_kernel(const double* __restrict__ part, int num_images, int64_t count, int shared,
                    double* __restrict__ grad_xi, const double* __restrict__ gs_part, int64_t rows,
                    double* __restrict__ grad_s) {
+    constexpr int R = 8;   // loads in flight per thread
     if (blockIdx.x < gridDim.x - 1) {
         if (!shared) return;
         const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
         if (k >= count * N) return;
         double acc = 0.0;
-        for (int i = 0; i < num_images; ++i) acc += part[(int64_t)i * count * N + k];
+        for (int i0 = 0; i0 < num_images; i0 += R) {
+            double v[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) v[j] = i0 + j < num_images ? part[(int64_t)(i0 + j) * count * N + k] : 0.0;
+#pragma unroll
+            for (int j = 0; j < R; ++j) acc += v[j];
+        }
         grad_xi[k] = acc;
         return;
     }
     if (!grad_s) return;
     __shared__ double s_red[256];
     double acc = 0.0;
-    for (int64_t r = threadIdx.x; r < rows; r += blockDim.x) acc += gs_part[r];
+    for (int64_t r0 = threadIdx.x; r0 < rows; r0 += (int64_t)R * blockDim.x) {
+        double v[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int64_t r = r0 + (int64_t)j * blockDim.x;
+            v[j] = r < rows ? gs_part[r] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) acc += v[j];
+    }
     s_red[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -427,7 +463,7 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v)
 
 template <int N, int MASK, bool BWD>
 hipError_t launch_mask(int precision, const HybridArgs& a, int64_t grid, bool reduce, hipStream_t stream) {
-    dim3 g((unsigned)grid), blk(kHybridThreads), rblk(kHybridTile);
+    dim3 g((unsigned)grid), blk(kHybridThreads), rblk(kHybridThreads);
     if (precision == ECT_FP32) {
         if (reduce) hipLaunchKernelGGL((hybrid_reduce_kernel<N, MASK, ECT_FP32, BWD>), g, rblk, 0, stream, a);
         else hipLaunchKernelGGL((hybrid_kernel<N, MASK, ECT_FP32, BWD>), g, blk, 0, stream, a);

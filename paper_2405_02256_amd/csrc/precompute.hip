@@ -28,9 +28,17 @@ namespace ect {
 
 namespace {
 
+// Look-back status word: flag (bits 63-62), run parity (bit 61), count.
+// Tickets taken from a 64-bit counter that is never reset number the
+// workgroups of successive runs consecutively, so run r = ticket / num_tiles
+// and its tile = ticket % num_tiles.  A word is current when its parity bit
+// matches the run's: every word left by run r-1 reads as "not yet published"
+// in run r, so re-runs need no reset launch.
 constexpr uint64_t kFlagAggregate = 1ull << 62;
 constexpr uint64_t kFlagInclusive = 2ull << 62;
-constexpr uint64_t kValueMask = (1ull << 62) - 1;
+constexpr uint64_t kFlagMask = 3ull << 62;
+constexpr uint64_t kParityBit = 1ull << 61;
+constexpr uint64_t kValueMask = (1ull << 61) - 1;
 constexpr int kLookbackSpinLimit = 1 << 22;
 
 __device__ __forceinline__ uint32_t udiv(uint32_t v, uint32_t d, double inv_d, uint32_t* rem) {
@@ -177,10 +185,12 @@ __device__ __forceinline__ void vertex_values(const int32_t* p, const ImageDesc&
     for (int e = 0; e < (1 << (N - 1)); ++e) D[e] = L[e ^ full] - L[e];
 }
 
-__global__ void reset_kernel(uint32_t* __restrict__ err, uint64_t* __restrict__ status, int64_t nstatus) {
+// Once per plan: clear the error word, the ticket counter and the status words.
+__global__ void reset_kernel(uint32_t* __restrict__ err, uint64_t* __restrict__ ticket, uint64_t* __restrict__ status,
+                             int64_t nstatus) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    if (i == 0) { err[0] = 0u; err[1] = 0u; }
+    if (i == 0) { err[0] = 0u; err[1] = 0u; *ticket = 0ull; }
     for (; i < nstatus; i += stride) status[i] = 0ull;
 }
 
@@ -188,7 +198,7 @@ template <int N, int CONS, typename T>
 __global__ void __launch_bounds__(kPrecomputeThreads)
 classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
                  const int64_t* __restrict__ tile_start, int32_t num_images, int64_t num_tiles,
-                 uint32_t* __restrict__ err, uint64_t* __restrict__ status,
+                 uint32_t* __restrict__ err, uint64_t* __restrict__ ticket, uint64_t* __restrict__ status,
                  int64_t* __restrict__ list_off, Point* __restrict__ points, int64_t capacity) {
     constexpr int NC = 1 << N;
     constexpr int NO = 1 << (N - 1);
@@ -196,17 +206,18 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
     constexpr int W = kPrecomputeThreads / 64;
     constexpr int J = kVertsPerThread;
 
-    __shared__ uint32_t s_tile;
+    __shared__ uint64_t s_ticket;
     __shared__ int32_t s_cnt[J][W][NL];   // per (round, wave, list) counts, then exclusive offsets
     __shared__ int64_t s_base[NL];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    if (tid == 0) s_tile = __hip_atomic_fetch_add(err + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) s_ticket = __hip_atomic_fetch_add(ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    const int64_t tile = s_tile;
-    if (tile >= num_tiles) return;  // never expected: the grid has exactly num_tiles workgroups
+    const uint64_t tk = s_ticket;
+    const int64_t tile = (int64_t)(tk % (uint64_t)num_tiles);
+    const uint64_t parity = ((tk / (uint64_t)num_tiles) & 1ull) ? kParityBit : 0ull;
 
     // image owning this tile: last i with tile_start[i] <= tile
     int lo = 0, hi = num_images - 1;
@@ -270,7 +281,7 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
                 }
             agg = (uint64_t)run;
             if (tile > 0)
-                __hip_atomic_store(status + tile * NL + lane, kFlagAggregate | agg, __ATOMIC_RELAXED,
+                __hip_atomic_store(status + tile * NL + lane, kFlagAggregate | parity | agg, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         }
         // Decoupled look-back, one window of 64 predecessor tiles per round and
@@ -294,16 +305,17 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
                 const int64_t j = wbase[l] - lane;
                 wv[l] = (!done[l] && j >= 0)
                             ? __hip_atomic_load(status + j * NL + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                            : (kFlagInclusive | 0ull);
+                            : (kFlagInclusive | parity);
             }
             bool waiting = false;
             all_done = true;
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
                 if (done[l]) continue;
-                const uint64_t f = wv[l] & ~kValueMask;
-                const uint64_t incl = __ballot(f == kFlagInclusive);
-                const uint64_t notready = __ballot(f == 0);
+                const uint64_t f = wv[l] & kFlagMask;
+                const bool current = (wv[l] & kParityBit) == parity;
+                const uint64_t incl = __ballot(current && f == kFlagInclusive);
+                const uint64_t notready = __ballot(!current || f == 0);
                 const int first = incl ? (int)__ffsll((unsigned long long)incl) - 1 : 64;
                 const uint64_t upto = first >= 63 ? ~0ull : ((1ull << (first + 1)) - 1ull);
                 if (notready & upto) {
@@ -330,7 +342,7 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
             uint64_t mine = 0;
 #pragma unroll
             for (int l = 0; l < NL; ++l) if (lane == l) mine = excl[l];
-            __hip_atomic_store(status + tile * NL + lane, kFlagInclusive | (mine + agg), __ATOMIC_RELAXED,
+            __hip_atomic_store(status + tile * NL + lane, kFlagInclusive | parity | (mine + agg), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
             s_base[lane] = (int64_t)mine;
             if (tile == d.tile_start) list_off[(int64_t)img_id * NL + lane] = (int64_t)mine;
@@ -360,20 +372,24 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
 }
 
 template <int N, int CONS, typename T>
-hipError_t launch_typed(const Plan& p, hipStream_t stream) {
+hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream) {
     const PlanLayout& L = p.lay;
     uint32_t* err = (uint32_t*)(p.ws + L.err);
+    uint64_t* ticket = (uint64_t*)(p.ws + L.err + 8);
     uint64_t* status = (uint64_t*)(p.ws + L.status);
     const int64_t nstatus = L.num_tiles * num_lists(N);
-    int rblocks = (int)std::min<int64_t>((nstatus + 255) / 256 + 1, 4096);
-    hipLaunchKernelGGL(reset_kernel, dim3(rblocks), dim3(256), 0, stream, err, status, nstatus);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    if (first) {
+        int rblocks = (int)std::min<int64_t>((nstatus + 255) / 256 + 1, 4096);
+        hipLaunchKernelGGL(reset_kernel, dim3(rblocks), dim3(256), 0, stream, err, ticket, status, nstatus);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     e = stage_mark(ECT_STAGE_PRECOMPUTE, false, stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((classify_compact<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads),
                        0, stream, (const T*)p.pixels, (const ImageDesc*)(p.ws + L.desc),
-                       (const int64_t*)(p.ws + L.tile_start), p.num_images, L.num_tiles, err, status,
+                       (const int64_t*)(p.ws + L.tile_start), p.num_images, L.num_tiles, err, ticket, status,
                        (int64_t*)(p.ws + L.list_off), (Point*)(p.ws + L.points), L.capacity);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -381,22 +397,22 @@ hipError_t launch_typed(const Plan& p, hipStream_t stream) {
 }
 
 template <int N, int CONS>
-hipError_t launch_dtype(const Plan& p, hipStream_t s) {
+hipError_t launch_dtype(const Plan& p, bool first, hipStream_t s) {
     switch (p.dtype) {
-        case ECT_U8: return launch_typed<N, CONS, uint8_t>(p, s);
-        case ECT_I16: return launch_typed<N, CONS, int16_t>(p, s);
-        default: return launch_typed<N, CONS, int32_t>(p, s);
+        case ECT_U8: return launch_typed<N, CONS, uint8_t>(p, first, s);
+        case ECT_I16: return launch_typed<N, CONS, int16_t>(p, first, s);
+        default: return launch_typed<N, CONS, int32_t>(p, first, s);
     }
 }
 
 }  // namespace
 
-hipError_t launch_precompute(const Plan& p, hipStream_t stream) {
+hipError_t launch_precompute(const Plan& p, bool first, hipStream_t stream) {
     if (p.ndim == 2)
-        return p.construction == ECT_PRIMAL ? launch_dtype<2, ECT_PRIMAL>(p, stream)
-                                            : launch_dtype<2, ECT_DUAL>(p, stream);
-    return p.construction == ECT_PRIMAL ? launch_dtype<3, ECT_PRIMAL>(p, stream)
-                                        : launch_dtype<3, ECT_DUAL>(p, stream);
+        return p.construction == ECT_PRIMAL ? launch_dtype<2, ECT_PRIMAL>(p, first, stream)
+                                            : launch_dtype<2, ECT_DUAL>(p, first, stream);
+    return p.construction == ECT_PRIMAL ? launch_dtype<3, ECT_PRIMAL>(p, first, stream)
+                                        : launch_dtype<3, ECT_DUAL>(p, first, stream);
 }
 
 }  // namespace ect

@@ -43,29 +43,18 @@ __device__ __forceinline__ int aggregated_add(Ctr* counters, int key, bool valid
     return slot;
 }
 
-// Bucket key and record of query row r: returns the (image, bucket) entry.
+// Bucket key and record of query row r with vector v in image img (rows
+// [r0, r0 + q) of the set belong to it): returns the (image, bucket) entry.
 template <int N>
-__device__ __forceinline__ int64_t classify_query(const double* __restrict__ vecs, const int64_t* __restrict__ offsets,
-                                                  int64_t r, int64_t rows, int num_images, int mode_hybrid,
-                                                  uint32_t* __restrict__ err, QRec* rec, int64_t* slot_base) {
+__device__ __forceinline__ int64_t classify_vec(const double (&v)[N], int64_t r, int img, int64_t r0, int64_t q,
+                                                int mode_hybrid, uint32_t* __restrict__ err, QRec* rec,
+                                                int64_t* slot_base) {
     const int B = mode_hybrid ? (1 << (N - 1)) : (1 << N);
     const int full = (1 << N) - 1;
-    int img = 0;
-    int64_t r0 = 0, q = rows;
-    if (offsets) {
-        int lo = 0, hi = num_images - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (offsets[mid] <= r) lo = mid; else hi = mid - 1;
-        }
-        img = lo;
-        r0 = offsets[img];
-        q = offsets[img + 1] - r0;
-    }
     bool fin = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        rec->v[a] = a < N ? vecs[r * N + a] : 0.0;
+        rec->v[a] = a < N ? v[a < N ? a : 0] : 0.0;
         fin = fin && isfinite(rec->v[a]);
     }
     if (!fin) raise_error(err, ECT_DEVERR_NONFINITE);
@@ -75,6 +64,35 @@ __device__ __forceinline__ int64_t classify_query(const double* __restrict__ vec
     rec->code = 2 * (r - r0) + neg;
     *slot_base = B * r0 + e * q;
     return (int64_t)img * B + e;
+}
+
+// Image of row r: the last image whose first row is <= r (offsets in global
+// memory or staged in LDS).
+template <typename O>
+__device__ __forceinline__ int image_of(const O* off, int num_images, int64_t r) {
+    int lo = 0, hi = num_images - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)off[mid] <= r) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int N>
+__device__ __forceinline__ int64_t classify_query(const double* __restrict__ vecs, const int64_t* __restrict__ offsets,
+                                                  int64_t r, int64_t rows, int num_images, int mode_hybrid,
+                                                  uint32_t* __restrict__ err, QRec* rec, int64_t* slot_base) {
+    int img = 0;
+    int64_t r0 = 0, q = rows;
+    if (offsets) {
+        img = image_of(offsets, num_images, r);
+        r0 = offsets[img];
+        q = offsets[img + 1] - r0;
+    }
+    double v[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) v[a] = vecs[r * N + a];
+    return classify_vec<N>(v, r, img, r0, q, mode_hybrid, err, rec, slot_base);
 }
 
 template <int N>
@@ -129,7 +147,8 @@ __device__ __forceinline__ void block_exclusive_scan2(int64_t& a, int64_t& b, in
 // size actually used.  If the item count exceeds `capacity`, the chunk size is
 // doubled until it fits.  Runs on one 1024-thread workgroup.
 __device__ void build_worklist(int num_images, int B, int list_base, int NL, int shared_queries,
-                               const int32_t* bcnt, const int64_t* __restrict__ list_off, int qtile,
+                               const int32_t* bcnt, const int64_t* __restrict__ list_off,
+                               const int32_t* np_lds, int qtile,
                                int64_t chunk0, int64_t capacity, uint32_t* __restrict__ err,
                                int64_t* __restrict__ item_off, int64_t* __restrict__ tile_off,
                                int64_t* __restrict__ params) {
@@ -141,7 +160,8 @@ __device__ void build_worklist(int num_images, int B, int list_base, int NL, int
         const int64_t i = e / B, b = e % B;
         const int64_t q = bcnt[shared_queries ? b : e];
         const int64_t t = (q + qtile - 1) / qtile;
-        const int64_t np = list_off[(i + 1) * NL + list_base + b] - list_off[i * NL + list_base + b];
+        const int64_t np = np_lds ? (int64_t)np_lds[e]
+                                  : list_off[(i + 1) * NL + list_base + b] - list_off[i * NL + list_base + b];
         int64_t ch = chunk > 0 ? (np + chunk - 1) / chunk : 1;
         if (ch < 1) ch = 1;  // an empty list still gets one item per tile, which writes zeros
         *items = t * ch;
@@ -207,12 +227,19 @@ worklist_kernel(int num_images, int B, int list_base, int NL, int shared_queries
                 int qtile, int64_t chunk0, int64_t capacity, uint32_t* __restrict__ err,
                 int64_t* __restrict__ item_off, int64_t* __restrict__ tile_off,
                 int64_t* __restrict__ params) {
-    build_worklist(num_images, B, list_base, NL, shared_queries, bcnt, list_off, qtile, chunk0, capacity, err,
-                   item_off, tile_off, params);
+    build_worklist(num_images, B, list_base, NL, shared_queries, bcnt, list_off, nullptr, qtile, chunk0, capacity,
+                   err, item_off, tile_off, params);
 }
 
 // Small query sets: bucketing with LDS counters and the work list in one
-// 1024-thread workgroup (one launch instead of three).
+// 1024-thread workgroup (one launch instead of three).  Everything the
+// bucketing and the work list read is fetched up front with independent
+// loads (list sizes and ragged offsets staged in LDS, kPrepRows query rows in
+// flight per thread), so the kernel waits on memory a few times, not once per
+// row and per entry.
+constexpr int kPrepRows = 8;
+constexpr int kSmallMaxOffsets = kSmallMaxEntries / 2 + 1;   // ragged: images <= entries / 2
+
 template <int N>
 __global__ void __launch_bounds__(1024)
 prepare_small_kernel(const double* __restrict__ vecs, const int64_t* __restrict__ offsets, int64_t rows,
@@ -221,25 +248,61 @@ prepare_small_kernel(const double* __restrict__ vecs, const int64_t* __restrict_
                      int qtile, int64_t chunk0, int64_t capacity, int64_t* __restrict__ item_off,
                      int64_t* __restrict__ tile_off, int64_t* __restrict__ params) {
     __shared__ int32_t s_cnt[kSmallMaxEntries];
+    __shared__ int32_t s_np[kSmallMaxEntries];
+    __shared__ int32_t s_off[kSmallMaxOffsets];
     const int B = mode_hybrid ? (1 << (N - 1)) : (1 << N);
     const int groups = offsets ? num_images : 1;
     const int E = groups * B;
+    const int64_t EW = (int64_t)num_images * B;     // work-list entries
+    const bool stage_np = EW <= kSmallMaxEntries;
     const int tid = threadIdx.x;
+    // the first batch of query rows is requested before anything else
+    double v[kPrepRows][N];
+    auto load_rows = [&](int64_t base) {
+#pragma unroll
+        for (int j = 0; j < kPrepRows; ++j) {
+            const int64_t r = base + (int64_t)j * 1024 + tid;
+#pragma unroll
+            for (int a = 0; a < N; ++a) v[j][a] = r < rows ? vecs[r * N + a] : 0.0;
+        }
+    };
+    load_rows(0);
     for (int i = tid; i < E; i += 1024) s_cnt[i] = 0;
+    if (stage_np)
+        for (int i = tid; i < (int)EW; i += 1024) {
+            const int img = i / B, b = i % B;
+            s_np[i] = (int32_t)(list_off[(int64_t)(img + 1) * NL + list_base + b] -
+                                list_off[(int64_t)img * NL + list_base + b]);
+        }
+    if (offsets)
+        for (int i = tid; i <= num_images; i += 1024) s_off[i] = (int32_t)offsets[i];
     __syncthreads();
-    for (int64_t base = 0; base < rows; base += 1024) {
-        const int64_t r = base + tid;
-        const bool valid = r < rows;
-        QRec rec;
-        int64_t sbase = 0, ent = 0;
-        if (valid) ent = classify_query<N>(vecs, offsets, r, rows, num_images, mode_hybrid, err, &rec, &sbase);
-        const int slot = aggregated_add(s_cnt, (int)ent, valid);
-        if (valid) recs[sbase + slot] = rec;
+    for (int64_t base = 0; base < rows; base += 1024 * kPrepRows) {
+        if (base > 0) load_rows(base);
+#pragma unroll
+        for (int j = 0; j < kPrepRows; ++j) {
+            const int64_t r = base + (int64_t)j * 1024 + tid;
+            const bool valid = r < rows;
+            QRec rec;
+            int64_t sbase = 0, ent = 0;
+            if (valid) {
+                int img = 0;
+                int64_t r0 = 0, q = rows;
+                if (offsets) {
+                    img = image_of(s_off, num_images, r);
+                    r0 = s_off[img];
+                    q = (int64_t)s_off[img + 1] - r0;
+                }
+                ent = classify_vec<N>(v[j], r, img, r0, q, mode_hybrid, err, &rec, &sbase);
+            }
+            const int slot = aggregated_add(s_cnt, (int)ent, valid);
+            if (valid) recs[sbase + slot] = rec;
+        }
     }
     __syncthreads();
     for (int i = tid; i < E; i += 1024) bcnt[i] = s_cnt[i];
-    build_worklist(num_images, B, list_base, NL, offsets == nullptr ? 1 : 0, s_cnt, list_off, qtile, chunk0,
-                   capacity, err, item_off, tile_off, params);
+    build_worklist(num_images, B, list_base, NL, offsets == nullptr ? 1 : 0, s_cnt, list_off,
+                   stage_np ? s_np : nullptr, qtile, chunk0, capacity, err, item_off, tile_off, params);
 }
 
 }  // namespace

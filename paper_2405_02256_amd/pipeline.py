@@ -8,6 +8,12 @@ bucketing, the exact ECT, the hybrid transforms for every requested kernel
 optionally, one backward pass -- without allocating, copying or
 synchronising.  ``capture()`` records that sequence once into a HIP graph
 (through torch.cuda.CUDAGraph) so that a replay costs one launch.
+
+The ECT and the hybrid transforms only read the precomputed lists, so with
+``concurrent=True`` the ECT branch runs on a side stream (its own workspace)
+between an event after the precompute and a join before the step ends; its
+small, latency-bound kernels then overlap the hybrid chain instead of
+adding to it.  In a captured graph the fork and join become graph edges.
 """
 from __future__ import annotations
 
@@ -20,8 +26,10 @@ class Step:
     def __init__(self, plan: Plan, ect_dirs=None, ect_thresholds=None, hybrid_xi=None, kernels=("fourier",),
                  s: float = 1.0, precision: str = "fp32", ect_offsets=None, hybrid_offsets=None,
                  backward_kernel: str | None = None, grad_out: torch.Tensor | None = None,
-                 log_scale_laplace: bool = False, rerun_precompute: bool = True, fused: bool = True):
+                 log_scale_laplace: bool = False, rerun_precompute: bool = True, fused: bool = True,
+                 concurrent: bool = False, reuse_prepared: bool = True):
         self.plan = plan
+        self.reuse_prepared = reuse_prepared
         dev = plan.device
         self.rerun_precompute = rerun_precompute
         self.ect_q = None if ect_dirs is None else QuerySet(ect_dirs, ect_offsets)
@@ -54,13 +62,26 @@ class Step:
             self.grad_xi = torch.empty((self.hy_q.vecs.shape[0], plan.ndim), dtype=torch.float64, device=dev)
             self.grad_s = torch.empty((), dtype=torch.float64, device=dev)
         self.graph = None
+        self.concurrent = concurrent and self.ect_q is not None and self.hy_q is not None
+        if self.concurrent:
+            self.side = torch.cuda.Stream(device=dev)
+            self._fork = torch.cuda.Event()
+            self._join = torch.cuda.Event()
 
     def run(self, stream=None) -> None:
         p = self.plan
+        main = stream if stream is not None else torch.cuda.current_stream()
         if self.rerun_precompute:
-            p.rerun(stream)
+            p.rerun(main)
         if self.ect_q is not None:
-            p.ect(self.ect_q, self.ect_thr, out=self.ect_out, stream=stream)
+            if self.concurrent:
+                self._fork.record(main)
+                self.side.wait_event(self._fork)
+                p.ect(self.ect_q, self.ect_thr, out=self.ect_out, stream=self.side, slot="ect")
+                self._join.record(self.side)
+            else:
+                p.ect(self.ect_q, self.ect_thr, out=self.ect_out, stream=main)
+        stream = main
         if self.fused and len(self.kernels) > 1:
             p.hybrid_multi(self.hy_q, self.kernels, self.s, self.precision, outs=self.hy_out,
                            log_scale_out=self.hy_ls.get("laplace"), stream=stream)
@@ -72,8 +93,12 @@ class Step:
                 else:
                     p.hybrid(self.hy_q, k, self.s, self.precision, out=self.hy_out[k], stream=stream)
         if self.backward_kernel is not None:
+            # the forward calls just bucketed this query set into the same workspace
             p.hybrid_backward(self.hy_q, self.hy_out[self.backward_kernel], self.grad_out, self.backward_kernel,
-                              self.s, self.precision, stream=stream, grad_xi=self.grad_xi, grad_s=self.grad_s)
+                              self.s, self.precision, stream=stream, grad_xi=self.grad_xi, grad_s=self.grad_s,
+                              reuse_prepared=self.reuse_prepared)
+        if self.concurrent:
+            main.wait_event(self._join)
 
     def autotune(self, cache=None, use_cache: bool = True, reps: int = 10):
         """Pick the plan's schedule knobs for this step's queries (before capture())."""
@@ -90,7 +115,7 @@ class Step:
         eager calls on the plan that need a larger one cannot free it."""
         self.run()
         torch.cuda.synchronize()
-        self.graph_ws = self.plan._eval_ws
+        self.graph_ws = dict(self.plan._eval_ws)
         g = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())

@@ -37,7 +37,8 @@ def small():
     rng = np.random.default_rng(77)
     img = W.binary_field(rng, (96, 80), 3.0)
     xi = W.polar_vectors(rng, 200, 0.01, 1.0)
-    dirs = W.circle_dirs(40)
+    # shuffled: neighbouring directions in a group fall in different orthants
+    dirs = W.circle_dirs(40)[rng.permutation(40)]
     thr = W.even_thresholds(70.0, 96)
     return img, xi, dirs, thr
 
@@ -126,3 +127,64 @@ def test_autotuned_step_replays_and_caches(api, small, tmp_path):
     t2 = AT.tune(plan2, T(dirs), T(thr), T(xi), ("fourier", "laplace", "bessel"), backward_kernel="fourier",
                  grad_out=g, cache=cache, timer=no_timing)
     assert t2.as_args() == t.as_args() and plan2.tuning == t.as_args()
+
+
+def test_concurrent_ect_branch_matches_serial_step(api, small):
+    """The ECT branch on its own stream (and graph branch) gives the serial step's outputs bitwise."""
+    from paper_2405_02256_amd.pipeline import Step
+    img, xi, dirs, thr = small
+    g = T(np.random.default_rng(10).standard_normal((len(xi), 2)))
+    outs = []
+    for concurrent in (False, True):
+        plan = api.Plan(T(img))
+        st = Step(plan, T(dirs), T(thr), T(xi), ("fourier", "laplace"), backward_kernel="fourier", grad_out=g,
+                  concurrent=concurrent)
+        st.run()
+        torch.cuda.synchronize()
+        eager = (st.ect_out.clone(), {k: v.clone() for k, v in st.hy_out.items()}, st.grad_xi.clone())
+        st.capture()
+        for _ in range(2):
+            st.ect_out.fill_(-7)
+            st.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(st.ect_out, eager[0])
+            assert all(torch.equal(st.hy_out[k], eager[1][k]) for k in eager[1])
+            assert torch.equal(st.grad_xi, eager[2])
+        outs.append(eager)
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert all(torch.equal(outs[0][1][k], outs[1][1][k]) for k in outs[0][1])
+    assert torch.equal(outs[0][2], outs[1][2])
+
+
+def test_backward_reuses_forward_buckets(api, small):
+    """The backward call with the reuse flag gives the same gradients as a
+    backward call that buckets again, and is refused when the last
+    preparation does not match (other query set, re-run, retuning)."""
+    from paper_2405_02256_amd import _native as N
+    img, xi, dirs, thr = small
+    plan = api.Plan(T(img))
+    q = api.QuerySet(T(xi))
+    g = T(np.random.default_rng(11).standard_normal((len(xi), 2)))
+    y = plan.hybrid_multi(q, ("fourier", "bessel"), 1.0, "fp32")["fourier"]
+    a = plan.hybrid_backward(q, y, g, "fourier", 1.0, "fp32", reuse_prepared=True)
+    b = plan.hybrid_backward(q, y, g, "fourier", 1.0, "fp32")
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    # the plain backward call above prepared again, so reuse still matches
+    c = plan.hybrid_backward(q, y, g, "fourier", 1.0, "fp32", reuse_prepared=True)
+    assert torch.equal(a[0], c[0])
+    other = api.QuerySet(T(xi[:50]))
+    plan.hybrid(other, "laplace", 1.0, "fp32")
+    with pytest.raises(N.EctError):
+        plan.hybrid_backward(q, y, g, "fourier", 1.0, "fp32", reuse_prepared=True)
+    plan.hybrid(q, "fourier", 1.0, "fp32")
+    plan.rerun()
+    with pytest.raises(N.EctError):
+        plan.hybrid_backward(q, y, g, "fourier", 1.0, "fp32", reuse_prepared=True)
+    plan.hybrid(q, "fourier", 1.0, "fp32")
+    plan.set_tuning(64, 2048, 0)
+    with pytest.raises(N.EctError):
+        plan.hybrid_backward(q, y, g, "fourier", 1.0, "fp32", reuse_prepared=True)
+    plan.hybrid(q, "fourier", 1.0, "fp32", slot="other")
+    with pytest.raises(N.EctError):
+        plan.hybrid_backward(q, y, g, "fourier", 1.0, "fp32", reuse_prepared=True)
+    torch.cuda.synchronize()

@@ -142,6 +142,63 @@ def test_ect_small_binary_full(api):
     assert np.array_equal(got, O.ect(img, w.ect_dirs, w.ect_thresholds))
 
 
+@pytest.mark.parametrize("ragged", [False, True])
+def test_ect_non_finite_directions(api, ragged):
+    """A NaN or infinite direction gets a zero row and raises the non-finite
+    flag; every other row stays exact (shared sets skip bucketing, ragged sets
+    are bucketed: both paths)."""
+    rng = np.random.default_rng(31)
+    imgs = [W.random_image(rng, (21, 17), 4), W.random_image(rng, (9, 30), 4)]
+    dirs = W.circle_dirs(12)
+    dirs[3] = [np.nan, 1.0]
+    dirs[7] = [np.inf, -0.5]
+    thr = W.even_thresholds(25.0, 30)
+    plan = api.Plan([T(im) for im in imgs])
+    if ragged:
+        d = np.concatenate([dirs, dirs[:5]])
+        offs = np.array([0, 12, 17], np.int64)
+        got = plan.ect(T(d), T(thr), offsets=T(offs)).cpu().numpy()
+        parts = [(0, dirs, got[:12]), (1, dirs[:5], got[12:])]
+    else:
+        got = plan.ect(T(dirs), T(thr)).cpu().numpy().reshape(2, 12, -1)
+        parts = [(0, dirs, got[0]), (1, dirs, got[1])]
+    for i, dd, g in parts:
+        fin = np.isfinite(dd).all(axis=1)
+        assert (g[~fin] == 0).all()
+        assert np.array_equal(g[fin], O.ect(imgs[i], dd[fin], thr)), i
+    assert plan.check() & 0x4
+
+
+def test_rerun_on_new_contents_many_times(api):
+    """Re-runs reuse the look-back words of the previous run (no reset launch):
+    alternate three images of one shape through one plan, a ragged batch of
+    several tiles per image, and check the ECT and a hybrid transform after
+    every re-run."""
+    rng = np.random.default_rng(4242)
+    shapes = [(70, 90), (33, 47), (64, 64)]
+    sets = [[W.binary_field(rng, sh, 2.5) if k % 2 else W.random_image(rng, sh, 5).astype(np.uint8)
+             for sh in shapes] for k in range(3)]
+    dirs = W.circle_dirs(24)
+    thr = W.even_thresholds(60.0, 40)
+    xi = W.polar_vectors(rng, 40, 0.02, 1.0)
+    plan = api.Plan([T(im) for im in sets[0]])
+    for it in range(7):
+        cur = sets[it % 3]
+        for off, im in zip(plan.pixel_offsets, cur):
+            plan.pixels[int(off):int(off) + im.size].copy_(T(im).reshape(-1))
+        plan.rerun()
+        got = plan.ect(T(dirs), T(thr)).cpu().numpy().reshape(len(cur), len(dirs), -1)
+        for i, im in enumerate(cur):
+            assert np.array_equal(got[i], O.ect(im, dirs, thr)), (it, i)
+        y = plan.hybrid(T(xi), "fourier", 1.0, "fp64").cpu().numpy().reshape(len(cur), len(xi), 2)
+        for i, im in enumerate(cur):
+            ref = O.hybrid(im, xi, "fourier", 1.0)
+            S1, _ = term_scales(im, xi, "fourier", 1.0)
+            ok, ratio = fp64_gate(y[i, :, 0] + 1j * y[i, :, 1], ref, S1)
+            assert ok, (it, i, ratio)
+    assert plan.check() == 0
+
+
 @pytest.mark.parametrize("construction", [O.PRIMAL, O.DUAL])
 def test_ect_random_with_axis_and_signed_zero_dirs(api, construction):
     rng = np.random.default_rng(202)
