@@ -65,6 +65,8 @@ struct EctArgs {
 // workgroups of ect_direct_kernel (no bucketing); else the bucketed kernel.
 hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, int64_t direct_groups, hipStream_t stream);
 
+constexpr int kJi0SmallCoeffs = 10;   // FP32-path small-argument Ji0 polynomial
+
 struct HybridArgs {
     const Point* points;
     const int64_t* list_off;
@@ -92,6 +94,7 @@ struct HybridArgs {
     const int64_t* params;    // [0] items, [1] tiles, [2] chunk
     double* partials;
     uint32_t* err;
+    double ji0c[kJi0SmallCoeffs];   // filled at launch (kernel arguments live in scalar registers)
 };
 
 // Main kernel (grid work items) then, for multi-chunk tiles, the in-order

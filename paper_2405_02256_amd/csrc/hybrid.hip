@@ -49,26 +49,39 @@ __device__ __forceinline__ void sincos_rev_f32(float r, float* sn, float* cs) {
     *cs = __builtin_amdgcn_cosf(r);
 }
 
+static_assert(JI0_F32_SMALL_DEG + 1 == kJi0SmallCoeffs, "kernel-argument copy of the Ji0 coefficients");
+
+// Horner on coefficients held in scalar registers (the kernel-argument copy):
+// FP64 FMAs take them directly as their addend, where literal coefficients
+// would be copied into a vector register before every FMA.
+template <int D>
+__device__ __forceinline__ double horner_sgpr(const double* c, double x) {
+    double r = c[D - 1];
+#pragma unroll
+    for (int k = D - 2; k >= 0; --k) r = fma(r, x, c[k]);
+    return r;
+}
+
 // Ji0(z) = integral_0^z J0 in FP32 (coefficients fitted against mpmath).
-__device__ __forceinline__ float ji0_f32(double z) {
+__device__ __forceinline__ float ji0_f32(double z, const double* small_coeffs) {
     const double az = fabs(z);
     float r;
     if (az < JI0_Z0) {
         // the monomial coefficients alternate in sign up to ~16 in size, so the
         // polynomial is evaluated in FP64 (same issue rate as FP32 on this chip)
         const double v = az * az * (1.0 / (JI0_Z0 * JI0_Z0));
-        r = (float)(az * horner<JI0_F32_SMALL_DEG + 1, double>(JI0_F32_SMALL, v));
+        r = (float)(az * horner_sgpr<JI0_F32_SMALL_DEG + 1>(small_coeffs, v));
     } else {
         const float zf = (float)az;
-        const float rz = __builtin_amdgcn_rcpf(zf);
+        const float rs = __builtin_amdgcn_rsqf(zf);   // z^-1/2; z^-1 = rs^2
+        const float rz = rs * rs;
         const float w = (float)(JI0_Z0 * JI0_Z0) * rz * rz;
         const float A = horner<JI0_F32_TAILA_DEG + 1, float>(JI0_F32_TAILA, w);
         const float Bv = horner<JI0_F32_TAILB_DEG + 1, float>(JI0_F32_TAILB, w);
-        const double rev = az * kInv2Pi - 0.125;
-        const float rf = (float)(rev - floor(rev));
+        const float rf = (float)__builtin_amdgcn_fract(fma(az, kInv2Pi, -0.125));
         float sn, cs;
         sincos_rev_f32(rf, &sn, &cs);
-        const float amp = 0.79788456080286536f * __builtin_amdgcn_rsqf(zf);
+        const float amp = 0.79788456080286536f * rs;
         r = 1.0f - amp * (A * rz * cs + Bv * sn);
     }
     return z < 0.0 ? -r : r;
@@ -121,7 +134,8 @@ constexpr int kSlotF = 0, kSlotL = 2, kSlotB = 3;
 // Contribution of one point.  Forward: per requested kernel, sum of D kbar(s u)
 // (without the 1/s); backward (one kernel): acc[a] = sum of D x_a g(kappa).
 template <int N, int MASK, int PREC, bool BWD>
-__device__ __forceinline__ void accumulate_point(const Point& pt, const Query<N>& q, double* acc) {
+__device__ __forceinline__ void accumulate_point(const Point& pt, const Query<N>& q, double* acc,
+                                                 const double* ji0c) {
     double u = q.xi[0] * pt.x[0];
 #pragma unroll
     for (int a = 1; a < N; ++a) u = fma(q.xi[a], pt.x[a], u);
@@ -130,7 +144,7 @@ __device__ __forceinline__ void accumulate_point(const Point& pt, const Query<N>
         double sn, cs;
         if constexpr (PREC == ECT_FP32) {
             float s32, c32;
-            sincos_rev_f32((float)(ph - floor(ph)), &s32, &c32);
+            sincos_rev_f32((float)__builtin_amdgcn_fract(ph), &s32, &c32);   // fract is exact
             sn = (double)s32;
             cs = (double)c32;
         } else {
@@ -160,7 +174,7 @@ __device__ __forceinline__ void accumulate_point(const Point& pt, const Query<N>
     if constexpr ((MASK & kB) != 0) {
         const double z = u * q.cB;
         if constexpr (!BWD) {
-            const double ji = (PREC == ECT_FP32) ? (double)ji0_f32(z) : ji0_f64(z);
+            const double ji = (PREC == ECT_FP32) ? (double)ji0_f32(z, ji0c) : ji0_f64(z);
             acc[kSlotB] = fma(pt.val, ji, acc[kSlotB]);
         } else {
             const double j = (PREC == ECT_FP32) ? (double)j0f((float)z) : j0(z);
@@ -324,7 +338,9 @@ __global__ void __launch_bounds__(kHybridThreads) hybrid_kernel(HybridArgs a) {
         __syncthreads();
         if (tid < cnt) s_pts[tid] = pts[base + tid];
         __syncthreads();
-        for (int k = wave; k < cnt; k += kHybridSplit) accumulate_point<N, MASK, PREC, BWD>(s_pts[k], q, acc);
+        // wave-uniform loop bounds (scalar counter)
+        const int k0 = __builtin_amdgcn_readfirstlane(wave);
+        for (int k = k0; k < cnt; k += kHybridSplit) accumulate_point<N, MASK, PREC, BWD>(s_pts[k], q, acc, a.ji0c);
     }
     if (wave > 0) {
 #pragma unroll
@@ -462,7 +478,9 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v)
 }
 
 template <int N, int MASK, bool BWD>
-hipError_t launch_mask(int precision, const HybridArgs& a, int64_t grid, bool reduce, hipStream_t stream) {
+hipError_t launch_mask(int precision, const HybridArgs& a0, int64_t grid, bool reduce, hipStream_t stream) {
+    HybridArgs a = a0;
+    for (int k = 0; k < kJi0SmallCoeffs; ++k) a.ji0c[k] = JI0_F32_SMALL[k];
     dim3 g((unsigned)grid), blk(kHybridThreads), rblk(kHybridThreads);
     if (precision == ECT_FP32) {
         if (reduce) hipLaunchKernelGGL((hybrid_reduce_kernel<N, MASK, ECT_FP32, BWD>), g, rblk, 0, stream, a);
