@@ -196,7 +196,7 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
     L.desc = o; o = align_up(o + sizeof(ImageDesc) * ni, kAlign);
     L.tile_start = o; o = align_up(o + sizeof(int64_t) * (ni + 1), kAlign);
     L.list_off = o; o = align_up(o + sizeof(int64_t) * (int64_t)(ni + 1) * NL, kAlign);
-    L.status = o; o = align_up(o + sizeof(uint64_t) * tiles * NL, kAlign);
+    L.status = o; o = align_up(o + sizeof(uint64_t) * (tiles + (tiles + 63) / 64) * NL, kAlign);
     L.points = o; o = align_up(o + sizeof(Point) * verts * NL, kAlign);
     L.total = o;
     L.num_tiles = tiles;
@@ -227,8 +227,15 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
         return ECT_E_NOMEM;
     }
     std::memcpy(p->h_desc, desc.data(), sizeof(ImageDesc) * ni);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) {
+        ect_plan_destroy(p);
+        return ECT_E_DEVICE;
+    }
 
-    hipError_t e = hipMemcpyAsync(p->ws + L.desc, desc.data(), sizeof(ImageDesc) * ni, hipMemcpyHostToDevice, stream);
+    e = hipMemcpyAsync(p->ws + L.desc, desc.data(), sizeof(ImageDesc) * ni, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->ws + L.tile_start, tstart.data(), sizeof(int64_t) * (ni + 1), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = launch_precompute(*p, true, stream);

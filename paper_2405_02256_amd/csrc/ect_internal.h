@@ -46,7 +46,7 @@ struct PlanLayout {
     size_t desc;            // ImageDesc[num_images]
     size_t tile_start;      // int64[num_images + 1]
     size_t list_off;        // int64[(num_images + 1) * NL]: start of image i in list l
-    size_t status;          // uint64[num_tiles * NL]: ordered-compaction look-back words
+    size_t status;          // uint64[(num_tiles + groups of 64 tiles) * NL]: ordered-compaction status words
     size_t points;          // Point[NL * capacity]
     size_t total;
     int64_t num_tiles;
@@ -61,6 +61,10 @@ struct ect_plan_s {
     int32_t num_images = 0;
     int32_t dtype = 0;
     int32_t construction = 0;
+    int32_t num_cus = 0;                    // compute units of the plan's device
+    // 1: the precompute grid fits on the chip at once (tile = workgroup id),
+    // 0: tiles by ticket, -1: not decided yet (first launch)
+    mutable int32_t precompute_resident = -1;
     const void* pixels = nullptr;
     char* ws = nullptr;
     ect::PlanLayout lay{};

@@ -19,8 +19,9 @@
 // Compaction is single pass and ordered: every workgroup takes the next tile
 // id from a counter, counts its nonzero values per list with wave ballots,
 // publishes the counts and resolves its global offset by decoupled look-back
-// over the preceding tiles (a wave inspects 64 predecessors per round for every
-// list at once), then writes its entries in vertex order.  Lists therefore come out sorted by linear vertex index, and
+// over the preceding tiles (the workgroup's waves inspect 64 predecessors each
+// per round, for every list at once), then writes its entries in vertex
+// order.  Lists therefore come out sorted by linear vertex index, and
 // identically on every run.
 #include "ect_internal.h"
 
@@ -28,12 +29,18 @@ namespace ect {
 
 namespace {
 
-// Look-back status word: flag (bits 63-62), run parity (bit 61), count.
-// Tickets taken from a 64-bit counter that is never reset number the
-// workgroups of successive runs consecutively, so run r = ticket / num_tiles
-// and its tile = ticket % num_tiles.  A word is current when its parity bit
-// matches the run's: every word left by run r-1 reads as "not yet published"
-// in run r, so re-runs need no reset launch.
+// Look-back status word: flag (bits 63-62), run parity (bit 61), count.  A
+// word is current when its parity bit matches the run's: every word left by
+// run r-1 reads as "not yet published" in run r, so re-runs need no reset
+// launch.  The run number comes from a 64-bit counter in the plan's workspace
+// that is never reset:
+//   resident grids (every workgroup fits on the chip at once): tile =
+//     blockIdx.x, the counter holds the run number; every workgroup reads it
+//     first, and the last tile increments it once its look-back is complete,
+//     which implies that every tile has published a word, so has read it;
+//   larger grids: the counter hands out tickets in start order (tile =
+//     ticket % num_tiles, run = ticket / num_tiles), so a workgroup only
+//     waits on tiles whose workgroups have started.
 constexpr uint64_t kFlagAggregate = 1ull << 62;
 constexpr uint64_t kFlagInclusive = 2ull << 62;
 constexpr uint64_t kFlagMask = 3ull << 62;
@@ -194,12 +201,51 @@ __global__ void reset_kernel(uint32_t* __restrict__ err, uint64_t* __restrict__ 
     for (; i < nstatus; i += stride) status[i] = 0ull;
 }
 
+// Sum over lanes i < count of the values of words[i * stride] (wave 0, every
+// lane gets the sum), waiting until each of those words is current (run
+// parity) and published.  Returns false if the spin limit was reached.
+template <int NL>
+__device__ __forceinline__ bool sum_published(const uint64_t* words, int64_t count, uint64_t parity, uint64_t* sums,
+                                              uint32_t* err) {
+    const int lane = threadIdx.x & 63;
+    for (int spins = 0;; ++spins) {
+        uint64_t wv[NL];
+#pragma unroll
+        for (int l = 0; l < NL; ++l)
+            wv[l] = lane < count ? __hip_atomic_load(words + (int64_t)lane * NL + l, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)
+                                 : (kFlagAggregate | parity);
+        bool ready = true;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const bool ok = (wv[l] & kParityBit) == parity && (wv[l] & kFlagMask) != 0;
+            ready = ready && __ballot(!ok) == 0;
+        }
+        if (ready) {
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                uint64_t v = lane < count ? (wv[l] & kValueMask) : 0ull;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                sums[l] = v;
+            }
+            return true;
+        }
+        if (spins > kLookbackSpinLimit) {
+            if (lane == 0) raise_error(err, ECT_DEVERR_LOOKBACK);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 template <int N, int CONS, typename T>
 __global__ void __launch_bounds__(kPrecomputeThreads)
 classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
                  const int64_t* __restrict__ tile_start, int32_t num_images, int64_t num_tiles,
                  uint32_t* __restrict__ err, uint64_t* __restrict__ ticket, uint64_t* __restrict__ status,
-                 int64_t* __restrict__ list_off, Point* __restrict__ points, int64_t capacity) {
+                 uint64_t* __restrict__ gstatus, int64_t* __restrict__ list_off, Point* __restrict__ points,
+                 int64_t capacity, int resident) {
     constexpr int NC = 1 << N;
     constexpr int NO = 1 << (N - 1);
     constexpr int NL = NC + NO;
@@ -209,15 +255,20 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
     __shared__ uint64_t s_ticket;
     __shared__ int32_t s_cnt[J][W][NL];   // per (round, wave, list) counts, then exclusive offsets
     __shared__ int64_t s_base[NL];
+    __shared__ uint64_t s_lb_sum[W][NL];
+    __shared__ int s_lb_state[W][NL];   // 0: no inclusive prefix in the part, 1: found one, 2: a word not ready
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    if (tid == 0) s_ticket = __hip_atomic_fetch_add(ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0)
+        s_ticket = resident ? __hip_atomic_load(ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                            : __hip_atomic_fetch_add(ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const uint64_t tk = s_ticket;
-    const int64_t tile = (int64_t)(tk % (uint64_t)num_tiles);
-    const uint64_t parity = ((tk / (uint64_t)num_tiles) & 1ull) ? kParityBit : 0ull;
+    const int64_t tile = resident ? (int64_t)blockIdx.x : (int64_t)(tk % (uint64_t)num_tiles);
+    const uint64_t run = resident ? tk : tk / (uint64_t)num_tiles;
+    const uint64_t parity = (run & 1ull) ? kParityBit : 0ull;
 
     // image owning this tile: last i with tile_start[i] <= tile
     int lo = 0, hi = num_images - 1;
@@ -265,32 +316,66 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
     }
     __syncthreads();
 
-    if (wave == 0) {
-        // tile aggregates (lane l < NL owns list l); per-(round, wave) counts become
-        // exclusive offsets inside the tile
-        uint64_t agg = 0;
-        if (lane < NL) {
-            int32_t run = 0;
+    // tile aggregates (wave 0, lane l < NL owns list l); per-(round, wave)
+    // counts become exclusive offsets inside the tile
+    uint64_t agg = 0;
+    if (wave == 0 && lane < NL) {
+        int32_t run = 0;
 #pragma unroll
-            for (int j = 0; j < J; ++j)
+        for (int j = 0; j < J; ++j)
 #pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    int32_t c = s_cnt[j][w][lane];
-                    s_cnt[j][w][lane] = run;
-                    run += c;
-                }
-            agg = (uint64_t)run;
-            if (tile > 0)
-                __hip_atomic_store(status + tile * NL + lane, kFlagAggregate | parity | agg, __ATOMIC_RELAXED,
+            for (int w = 0; w < W; ++w) {
+                int32_t c = s_cnt[j][w][lane];
+                s_cnt[j][w][lane] = run;
+                run += c;
+            }
+        agg = (uint64_t)run;
+        if (tile > 0 || resident)   // the two-level scan also reads tile 0's aggregate
+            __hip_atomic_store(status + tile * NL + lane, kFlagAggregate | parity | agg, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (resident) {
+        // Two-level scan (every tile is running, so none waits on an unstarted
+        // one): tiles form groups of 64; wave 0 sums the aggregates of the
+        // tile's predecessors in its group, the group's last tile publishes
+        // the group total, and the totals of the preceding groups complete the
+        // prefix.  Each tile reads at most 63 + groups words per list, where a
+        // window look-back over simultaneously finishing tiles reads hundreds.
+        if (wave == 0) {
+            const int64_t g = tile >> 6, k = tile & 63;
+            uint64_t loc[NL], grp[NL];
+            bool ok = sum_published<NL>(status + (g << 6) * NL, k, parity, loc, err);
+            if (ok && (k == 63 || tile == num_tiles - 1) && lane < NL) {
+                uint64_t mine = 0;
+#pragma unroll
+                for (int l = 0; l < NL; ++l) if (lane == l) mine = loc[l];
+                __hip_atomic_store(gstatus + g * NL + lane, kFlagAggregate | parity | (mine + agg), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (ok) ok = sum_published<NL>(gstatus, g, parity, grp, err);
+            // every group total is in, so every tile has read the run number
+            if (tile == num_tiles - 1 && lane == 0)
+                __hip_atomic_store(ticket, tk + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane < NL) {
+                uint64_t mine = 0;
+#pragma unroll
+                for (int l = 0; l < NL; ++l) if (lane == l) mine = ok ? loc[l] + grp[l] : 0;
+                s_base[lane] = (int64_t)mine;
+                if (tile == d.tile_start) list_off[(int64_t)img_id * NL + lane] = (int64_t)mine;
+                if (tile == num_tiles - 1) list_off[(int64_t)num_images * NL + lane] = (int64_t)(mine + agg);
+            }
         }
-        // Decoupled look-back, one window of 64 predecessor tiles per round and
-        // list: lane i inspects tile base - i.  A status word carries both its
-        // flag and its count, so relaxed device-scope atomics suffice (no fence,
-        // hence no L2 write-back between the chip's non-coherent L2 slices);
-        // the list entries are only read by later kernels.  The nearest tile holding an
-        // inclusive prefix ends the walk; every tile in front of it must have
-        // published its aggregate (otherwise the window is read again).
+    } else {
+    // Decoupled look-back over windows of 64 * W predecessor tiles: lane i of
+    // wave w inspects tile base - 64 w - i for every list at once.  A status
+    // word carries both its flag and its count, so relaxed device-scope
+    // atomics suffice (no fence, hence no L2 write-back between the chip's
+    // non-coherent L2 slices); the list entries are only read by later
+    // kernels.  Per list, the nearest tile holding an inclusive prefix ends
+    // the walk; every tile in front of it must have published its aggregate,
+    // otherwise the window is read again.  The waves' window parts are
+    // combined in order through LDS.
+    {
         uint64_t excl[NL];
         int64_t wbase[NL];
         bool done[NL];
@@ -299,46 +384,64 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
         int spins = 0;
         bool all_done = tile == 0;
         while (!all_done) {
-            uint64_t wv[NL];
+            // every list's word is requested before any is examined, so the
+            // loads are in flight together
+            uint64_t wvs[NL];
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
-                const int64_t j = wbase[l] - lane;
-                wv[l] = (!done[l] && j >= 0)
-                            ? __hip_atomic_load(status + j * NL + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                            : (kFlagInclusive | parity);
+                const int64_t j = wbase[l] - 64 * wave - lane;
+                wvs[l] = (!done[l] && j >= 0)
+                             ? __hip_atomic_load(status + j * NL + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                             : (kFlagInclusive | parity);
             }
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                if (done[l]) continue;
+                const uint64_t wv = wvs[l];
+                const uint64_t f = wv & kFlagMask;
+                const bool current = (wv & kParityBit) == parity;
+                const uint64_t incl = __ballot(current && f == kFlagInclusive);
+                const uint64_t notready = __ballot(!current || f == 0);
+                const int first = incl ? (int)__ffsll((unsigned long long)incl) - 1 : 64;
+                const uint64_t upto = first >= 63 ? ~0ull : ((1ull << (first + 1)) - 1ull);
+                uint64_t v = (lane <= first) ? (wv & kValueMask) : 0ull;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                if (lane == 0) {
+                    s_lb_sum[wave][l] = v;
+                    s_lb_state[wave][l] = (notready & upto) ? 2 : (first < 64 ? 1 : 0);
+                }
+            }
+            __syncthreads();
+            // every thread combines the W parts in order (same result everywhere)
             bool waiting = false;
             all_done = true;
 #pragma unroll
             for (int l = 0; l < NL; ++l) {
                 if (done[l]) continue;
-                const uint64_t f = wv[l] & kFlagMask;
-                const bool current = (wv[l] & kParityBit) == parity;
-                const uint64_t incl = __ballot(current && f == kFlagInclusive);
-                const uint64_t notready = __ballot(!current || f == 0);
-                const int first = incl ? (int)__ffsll((unsigned long long)incl) - 1 : 64;
-                const uint64_t upto = first >= 63 ? ~0ull : ((1ull << (first + 1)) - 1ull);
-                if (notready & upto) {
-                    waiting = true;
-                    all_done = false;
-                    continue;
+                uint64_t total = 0;
+                int state = 0;
+                for (int w = 0; w < W; ++w) {
+                    const int st = s_lb_state[w][l];
+                    if (st == 2) { state = 2; break; }
+                    total += s_lb_sum[w][l];
+                    if (st == 1) { state = 1; break; }
                 }
-                uint64_t v = (lane <= first) ? (wv[l] & kValueMask) : 0ull;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-                excl[l] += v;
-                if (first < 64) done[l] = true;
-                else { wbase[l] -= 64; all_done = false; }
+                if (state == 2) { waiting = true; all_done = false; continue; }
+                excl[l] += total;
+                if (state == 1) done[l] = true;
+                else { wbase[l] -= 64 * W; all_done = false; }
             }
+            __syncthreads();   // the parts are rewritten by the next round
             if (waiting) {
                 if (++spins > kLookbackSpinLimit) {
-                    if (lane == 0) raise_error(err, ECT_DEVERR_LOOKBACK);
+                    if (tid == 0) raise_error(err, ECT_DEVERR_LOOKBACK);
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
         }
-        if (lane < NL) {
+        if (wave == 0 && lane < NL) {
             uint64_t mine = 0;
 #pragma unroll
             for (int l = 0; l < NL; ++l) if (lane == l) mine = excl[l];
@@ -348,6 +451,7 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
             if (tile == d.tile_start) list_off[(int64_t)img_id * NL + lane] = (int64_t)mine;
             if (tile == num_tiles - 1) list_off[(int64_t)num_images * NL + lane] = (int64_t)(mine + agg);
         }
+    }
     }
     __syncthreads();
 
@@ -377,7 +481,8 @@ hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream) {
     uint32_t* err = (uint32_t*)(p.ws + L.err);
     uint64_t* ticket = (uint64_t*)(p.ws + L.err + 8);
     uint64_t* status = (uint64_t*)(p.ws + L.status);
-    const int64_t nstatus = L.num_tiles * num_lists(N);
+    uint64_t* gstatus = status + L.num_tiles * num_lists(N);   // group totals of the two-level scan
+    const int64_t nstatus = (L.num_tiles + (L.num_tiles + 63) / 64) * num_lists(N);
     hipError_t e = hipSuccess;
     if (first) {
         int rblocks = (int)std::min<int64_t>((nstatus + 255) / 256 + 1, 4096);
@@ -387,10 +492,19 @@ hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream) {
     }
     e = stage_mark(ECT_STAGE_PRECOMPUTE, false, stream);
     if (e != hipSuccess) return e;
+    if (p.precompute_resident < 0) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, classify_compact<N, CONS, T>, kPrecomputeThreads,
+                                                         0) != hipSuccess)
+            per_cu = 0;
+        // the two-level scan covers 64 groups of 64 tiles
+        p.precompute_resident = ((int64_t)per_cu * p.num_cus >= L.num_tiles && L.num_tiles <= 64 * 64) ? 1 : 0;
+    }
     hipLaunchKernelGGL((classify_compact<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads),
                        0, stream, (const T*)p.pixels, (const ImageDesc*)(p.ws + L.desc),
-                       (const int64_t*)(p.ws + L.tile_start), p.num_images, L.num_tiles, err, ticket, status,
-                       (int64_t*)(p.ws + L.list_off), (Point*)(p.ws + L.points), L.capacity);
+                       (const int64_t*)(p.ws + L.tile_start), p.num_images, L.num_tiles, err, ticket, status, gstatus,
+                       (int64_t*)(p.ws + L.list_off), (Point*)(p.ws + L.points), L.capacity,
+                       (int)p.precompute_resident);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return stage_mark(ECT_STAGE_PRECOMPUTE, true, stream);
