@@ -12,10 +12,12 @@
 // the record code (code = 2 * row + negated).
 //
 // Bucket b of image i owns the record slots [B*r0_i + b*Q_i, B*r0_i + (b+1)*Q_i)
-// (r0_i = first query row of the image, Q_i = its number of queries), so every
-// query finds its slot with one atomic increment and no prefix sum.  The order
-// inside a bucket is therefore not fixed, but no result depends on it: every
-// query is evaluated independently and in a fixed order over the points.
+// (r0_i = first query row of the image, Q_i = its number of queries).  Small
+// shared sets are partitioned stably (row order kept inside a bucket) by one
+// workgroup with a counting scan; other sets find their slots with one atomic
+// increment per bucket and wave, so the order inside a bucket is not fixed.
+// No result depends on that order: every query is evaluated independently and
+// in a fixed order over the points.
 #include "eval_internal.h"
 
 namespace ect {
@@ -57,7 +59,7 @@ __device__ __forceinline__ int64_t classify_vec(const double (&v)[N], int64_t r,
         rec->v[a] = a < N ? v[a < N ? a : 0] : 0.0;
         fin = fin && isfinite(rec->v[a]);
     }
-    if (!fin) raise_error(err, ECT_DEVERR_NONFINITE);
+    if (!fin && err) raise_error(err, ECT_DEVERR_NONFINITE);
     int e = sign_index<N>(rec->v);
     int neg = 0;
     if (mode_hybrid && ((e >> (N - 1)) & 1)) { e ^= full; neg = 1; }
@@ -221,6 +223,61 @@ __device__ void build_worklist(int num_images, int B, int list_base, int NL, int
     }
 }
 
+// Work list of at most 64 entries by one wave, lane = entry (no barrier):
+// q = the entry's query count, np = its list size.  Same items, prefixes,
+// chunk doubling and outputs as build_worklist.
+__device__ void worklist_wave(int64_t E, int64_t q, int64_t np, int qtile, int64_t chunk0, int64_t capacity,
+                              uint32_t* __restrict__ err, int64_t* __restrict__ item_off,
+                              int64_t* __restrict__ tile_off, int64_t* __restrict__ params) {
+    const int lane = threadIdx.x & 63;
+    const bool valid = lane < E;
+    const int64_t t = valid ? (q + qtile - 1) / qtile : 0;
+    auto items_for = [&](int64_t chunk) {
+        int64_t ch = chunk > 0 ? (np + chunk - 1) / chunk : 1;
+        if (ch < 1) ch = 1;  // an empty list still gets one item per tile, which writes zeros
+        return t * ch;
+    };
+    int64_t chunk = chunk0;
+    if (chunk > 0 && capacity > 0) {
+        for (int attempt = 0;; ++attempt) {
+            int64_t total = items_for(chunk);
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) total += __shfl_xor(total, off, 64);
+            if (total <= capacity) break;
+            chunk *= 2;
+            if (attempt == 39) {
+                if (lane == 0) {
+                    raise_error(err, ECT_DEVERR_CAPACITY);
+                    params[0] = 0;
+                    params[1] = 0;
+                    params[2] = chunk;
+                    item_off[E] = 0;
+                    tile_off[E] = 0;
+                }
+                return;
+            }
+        }
+    }
+    int64_t it = items_for(chunk), tl = t, ii = it, ti = tl;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t a = __shfl_up(ii, off, 64), b = __shfl_up(ti, off, 64);
+        if (lane >= off) { ii += a; ti += b; }
+    }
+    if (valid) {
+        item_off[lane] = ii - it;
+        tile_off[lane] = ti - tl;
+    }
+    const int64_t tot_i = __shfl(ii, 63, 64), tot_t = __shfl(ti, 63, 64);
+    if (lane == 0) {
+        item_off[E] = tot_i;
+        tile_off[E] = tot_t;
+        params[0] = tot_i;
+        params[1] = tot_t;
+        params[2] = chunk;
+    }
+}
+
 __global__ void __launch_bounds__(1024)
 worklist_kernel(int num_images, int B, int list_base, int NL, int shared_queries,
                 const int32_t* __restrict__ bcnt, const int64_t* __restrict__ list_off,
@@ -231,13 +288,116 @@ worklist_kernel(int num_images, int B, int list_base, int NL, int shared_queries
                    err, item_off, tile_off, params);
 }
 
+// Small shared sets (<= kSharedMaxRows rows): one 1024-thread workgroup.
+// Wave w takes a contiguous block of rows and walks it 64 rows at a time
+// (lane l takes the l-th row of a batch, so loads and stores coalesce).
+// Pass 1 counts the block's rows per bucket with ballots; an exclusive prefix
+// of the per-wave counts in LDS gives each wave its first slot in every
+// bucket; pass 2 re-reads the rows and writes each record at that base plus
+// its rank among the block's earlier rows of the bucket (ballot popcounts), so
+// the partition is stable (row order kept inside a bucket).  A work list of
+// at most 64 entries is then built by one wave.
+constexpr int kPrepRows = 8;   // query rows in flight per thread (ragged small sets)
+constexpr int64_t kSharedMaxRows = 65536;
+
+template <int N>
+__global__ void __launch_bounds__(1024)
+prepare_shared_kernel(const double* __restrict__ vecs, int64_t rows, int num_images, int mode_hybrid,
+                      uint32_t* __restrict__ err, QRec* __restrict__ recs, int32_t* __restrict__ bcnt,
+                      const int64_t* __restrict__ list_off, int list_base, int NL, int qtile, int64_t chunk0,
+                      int64_t capacity, int64_t* __restrict__ item_off, int64_t* __restrict__ tile_off,
+                      int64_t* __restrict__ params) {
+    constexpr int W = 16;
+    constexpr int U = 4;   // batches whose loads are in flight together
+    __shared__ int32_t s_wc[W][8];
+    __shared__ int32_t s_tot[8];
+    const int B = mode_hybrid ? (1 << (N - 1)) : (1 << N);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int64_t EW = (int64_t)num_images * B;
+    // list sizes of a small work list, requested first
+    int64_t np_lane = 0;
+    if (EW <= 64 && wave == 0 && lane < EW) {
+        const int i = lane / B, b = lane % B;
+        np_lane = list_off[(int64_t)(i + 1) * NL + list_base + b] - list_off[(int64_t)i * NL + list_base + b];
+    }
+    const int64_t per = ((rows + W - 1) / W + 63) / 64 * 64;   // rows per wave, whole batches
+    const int64_t w0 = min(rows, (int64_t)wave * per), w1 = min(rows, w0 + per);
+    auto load = [&](int64_t rb, double (&v)[U][N]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                const int64_t r = rb + 64 * u + lane;
+                v[u][a] = r < w1 ? vecs[r * N + a] : 0.0;
+            }
+    };
+    // pass 1: per-wave bucket counts
+    int32_t cnt = 0;   // lane b < B: count of bucket b in this wave's block
+    for (int64_t rb = w0; rb < w1; rb += 64 * U) {
+        double v[U][N];
+        load(rb, v);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t r = rb + 64 * u + lane;
+            QRec rec;
+            int64_t sb;
+            const int key = r < w1 ? (int)classify_vec<N>(v[u], r, 0, 0, rows, mode_hybrid, err, &rec, &sb) : -1;
+            for (int c = 0; c < B; ++c) {
+                const int n = (int)__popcll(__ballot(key == c));
+                if (lane == c) cnt += n;
+            }
+        }
+    }
+    if (lane < B) s_wc[wave][lane] = cnt;
+    __syncthreads();
+    // exclusive prefix over waves: base of this wave in each bucket (lane b)
+    int32_t base = 0;
+    if (lane < B) {
+        for (int w = 0; w < wave; ++w) base += s_wc[w][lane];
+        if (wave == W - 1) {
+            const int32_t tot = base + s_wc[W - 1][lane];
+            s_tot[lane] = tot;
+            bcnt[lane] = tot;
+        }
+    }
+    // pass 2: records at base + rank, in row order inside each bucket
+    for (int64_t rb = w0; rb < w1; rb += 64 * U) {
+        double v[U][N];
+        load(rb, v);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t r = rb + 64 * u + lane;
+            QRec rec;
+            int64_t sb = 0;
+            const int key = r < w1 ? (int)classify_vec<N>(v[u], r, 0, 0, rows, mode_hybrid, nullptr, &rec, &sb) : -1;
+            int slot = 0;
+            for (int c = 0; c < B; ++c) {
+                const uint64_t m = __ballot(key == c);
+                const int bc = __shfl(base, c, 64);
+                if (key == c) slot = bc + (int)__popcll(m & lt);
+                if (lane == c) base += (int)__popcll(m);
+            }
+            if (key >= 0) recs[sb + slot] = rec;
+        }
+    }
+    __syncthreads();
+    if (EW <= 64) {
+        if (wave == 0)
+            worklist_wave(EW, lane < EW ? s_tot[lane % B] : 0, np_lane, qtile, chunk0, capacity, err, item_off,
+                          tile_off, params);
+    } else {
+        build_worklist(num_images, B, list_base, NL, 1, s_tot, list_off, nullptr, qtile, chunk0, capacity, err,
+                       item_off, tile_off, params);
+    }
+}
+
 // Small query sets: bucketing with LDS counters and the work list in one
 // 1024-thread workgroup (one launch instead of three).  Everything the
 // bucketing and the work list read is fetched up front with independent
 // loads (list sizes and ragged offsets staged in LDS, kPrepRows query rows in
 // flight per thread), so the kernel waits on memory a few times, not once per
 // row and per entry.
-constexpr int kPrepRows = 8;
 constexpr int kSmallMaxOffsets = kSmallMaxEntries / 2 + 1;   // ragged: images <= entries / 2
 
 template <int N>
@@ -315,6 +475,17 @@ hipError_t launch_prepare(int ndim, const ect_query_set& qs, int num_images, boo
     const int64_t rows = qs.count;  // shared: the set itself; ragged: all rows
     const int groups = qs.offsets ? num_images : 1;
     const bool shared = qs.offsets == nullptr;
+    if (shared && rows <= kSharedMaxRows) {
+        if (ndim == 2)
+            hipLaunchKernelGGL(prepare_shared_kernel<2>, dim3(1), dim3(1024), 0, stream, qs.vecs, rows, num_images,
+                               hybrid ? 1 : 0, err, recs, bcnt, list_off, list_base, NL, qtile, chunk, capacity,
+                               item_off, tile_off, params);
+        else
+            hipLaunchKernelGGL(prepare_shared_kernel<3>, dim3(1), dim3(1024), 0, stream, qs.vecs, rows, num_images,
+                               hybrid ? 1 : 0, err, recs, bcnt, list_off, list_base, NL, qtile, chunk, capacity,
+                               item_off, tile_off, params);
+        return hipGetLastError();
+    }
     if (rows <= kSmallMaxRows && (int64_t)groups * B <= kSmallMaxEntries) {
         if (ndim == 2)
             hipLaunchKernelGGL(prepare_small_kernel<2>, dim3(1), dim3(1024), 0, stream, qs.vecs, qs.offsets, rows,
