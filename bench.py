@@ -132,7 +132,8 @@ def main():
     if not args.no_autotune:
         log("autotuning schedule knobs")
         t = step.autotune()
-        tuning = {"hybrid_target_items": t.hybrid_target_items, "ect_dirs_per_group": t.ect_dirs_per_group}
+        tuning = {"hybrid_target_items": t.hybrid_target_items, "ect_dirs_per_group": t.ect_dirs_per_group,
+                  "ect_chunks": t.ect_chunks}
         log(f"tuning {tuning}")
     log("warm-up and graph capture")
     step.run()

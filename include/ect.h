@@ -246,13 +246,15 @@ ect_status ect_plan_destroy(ect_plan plan);
 /* Tuning knobs of one plan (used by the autotuner): hybrid point-chunk
  * length per work item (0 = automatic, else 16 .. 2^40), target number of
  * hybrid work items when automatic (1 .. 2^24), directions per ECT workgroup
- * (1..8, 0 = automatic).  Out-of-range values return ECT_E_INVALID and leave
- * the plan unchanged.
+ * (1..8, 0 = automatic) and, for shared direction sets, the number of parts
+ * each list is split into for one group of directions (0 = automatic, else
+ * 1 .. 4096; 1 = no split).  Out-of-range values return ECT_E_INVALID and
+ * leave the plan unchanged.
  * They only change the schedule: the ECT is exact whatever they are, hybrid
  * results differ only by the rounding of the chunked sums, and identical
  * settings give bitwise identical results. */
 ect_status ect_plan_set_tuning(ect_plan plan, int64_t hybrid_chunk, int64_t hybrid_target_items,
-                               int32_t ect_dirs_per_group);
+                               int32_t ect_dirs_per_group, int32_t ect_chunks);
 
 /* Profiling hook (process-wide): when set, the library records `before` on
  * the call's stream right before it launches the main kernel of `stage` and

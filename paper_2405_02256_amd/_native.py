@@ -73,7 +73,7 @@ def lib():
     L.ect_plan_export.argtypes = [c_vp, c_i32, c_i32, c_i32, P(c_i32), P(c_i32), c_i64, P(c_i64), c_vp]
     L.ect_plan_check.argtypes = [c_vp, P(c_u32), c_vp]
     L.ect_plan_destroy.argtypes = [c_vp]
-    L.ect_plan_set_tuning.argtypes = [c_vp, c_i64, c_i64, c_i32]
+    L.ect_plan_set_tuning.argtypes = [c_vp, c_i64, c_i64, c_i32, c_i32]
     L.ect_set_stage_events.argtypes = [c_i32, c_vp, c_vp]
     for name in ("ect_precompute", "ect_plan_rerun", "ect_eval", "hybrid_eval", "hybrid_eval_multi",
                  "hybrid_eval_backward",
@@ -152,9 +152,10 @@ def ect_plan_destroy(plan) -> int:
     return lib().ect_plan_destroy(c_vp(plan))
 
 
-def ect_plan_set_tuning(plan, hybrid_chunk: int, hybrid_target_items: int, ect_dirs_per_group: int) -> int:
+def ect_plan_set_tuning(plan, hybrid_chunk: int, hybrid_target_items: int, ect_dirs_per_group: int,
+                        ect_chunks: int = 0) -> int:
     return lib().ect_plan_set_tuning(c_vp(plan), int(hybrid_chunk), int(hybrid_target_items),
-                                     int(ect_dirs_per_group))
+                                     int(ect_dirs_per_group), int(ect_chunks))
 
 
 STAGE_PRECOMPUTE, STAGE_ECT, STAGE_HYBRID, STAGE_HYBRID_BWD = 0, 1, 2, 3

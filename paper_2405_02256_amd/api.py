@@ -81,7 +81,7 @@ class Plan:
             raise ValueError("every image must have the same ndim (2 or 3), dtype and device")
         self.ndim = ndim
         self.construction = int(construction)
-        self.tuning = (0, 2048, 0)
+        self.tuning = (0, 2048, 0, 0)
         self.num_images = len(images)
         self.device = dev
         flat = [im.reshape(-1) for im in images]
@@ -134,10 +134,13 @@ class Plan:
             ws = self._eval_ws[slot] = _workspace(nbytes, self.device)
         return ws
 
-    def set_tuning(self, hybrid_chunk: int = 0, hybrid_target_items: int = 2048, ect_dirs_per_group: int = 0):
-        N.check(N.ect_plan_set_tuning(self.handle, hybrid_chunk, hybrid_target_items, ect_dirs_per_group),
-                "ect_plan_set_tuning")
-        self.tuning = (hybrid_chunk, hybrid_target_items, ect_dirs_per_group)
+    def set_tuning(self, hybrid_chunk: int = 0, hybrid_target_items: int = 2048, ect_dirs_per_group: int = 0,
+                   ect_chunks: int = 0):
+        """Schedule knobs (0 = automatic): hybrid point chunk, hybrid work items,
+        directions per ECT workgroup, parts per list for shared ECT sets."""
+        N.check(N.ect_plan_set_tuning(self.handle, hybrid_chunk, hybrid_target_items, ect_dirs_per_group,
+                                      ect_chunks), "ect_plan_set_tuning")
+        self.tuning = (hybrid_chunk, hybrid_target_items, ect_dirs_per_group, ect_chunks)
 
     def rerun(self, stream=None):
         N.check(N.ect_plan_rerun(self.handle, _stream(stream)), "ect_plan_rerun")

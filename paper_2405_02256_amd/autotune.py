@@ -7,7 +7,9 @@ chunked partial sums):
 * the point-chunk length of a hybrid work item (image, orthant pair, 64-query
   tile, chunk of list entries) -- short chunks give many small work items that
   fill the 256 compute units but cost more partial sums, long ones the reverse;
-* the number of directions one ECT workgroup evaluates per streamed point.
+* the number of directions one ECT workgroup evaluates per streamed point and,
+  for shared direction sets, the number of parts each list is split into so
+  that several workgroups share one group of directions.
 
 The tuner times each candidate on the device with events around a few
 repetitions of the real calls, keeps the fastest and stores it in a JSON cache
@@ -26,7 +28,8 @@ from dataclasses import dataclass, field
 from . import _native as N
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2405_02256_amd", "tuning.json")
-ECT_DIRS_CANDIDATES = (1, 2, 4, 8)
+# (directions per workgroup, list parts; 0 = automatic)
+ECT_CANDIDATES = ((1, 1), (2, 1), (4, 1), (8, 1), (1, 0), (2, 0), (4, 0), (8, 0))
 HYBRID_ITEM_CANDIDATES = (512, 1024, 2048, 4096, 8192, 16384)
 
 
@@ -35,19 +38,22 @@ class Tuning:
     hybrid_chunk: int = 0
     hybrid_target_items: int = 2048
     ect_dirs_per_group: int = 0
+    ect_chunks: int = 0
     timings: dict = field(default_factory=dict)
 
     def as_args(self):
-        return (int(self.hybrid_chunk), int(self.hybrid_target_items), int(self.ect_dirs_per_group))
+        return (int(self.hybrid_chunk), int(self.hybrid_target_items), int(self.ect_dirs_per_group),
+                int(self.ect_chunks))
 
     def to_json(self):
         return {"hybrid_chunk": int(self.hybrid_chunk), "hybrid_target_items": int(self.hybrid_target_items),
-                "ect_dirs_per_group": int(self.ect_dirs_per_group), "timings": self.timings}
+                "ect_dirs_per_group": int(self.ect_dirs_per_group), "ect_chunks": int(self.ect_chunks),
+                "timings": self.timings}
 
     @staticmethod
     def from_json(d):
         return Tuning(int(d["hybrid_chunk"]), int(d["hybrid_target_items"]), int(d["ect_dirs_per_group"]),
-                      dict(d.get("timings", {})))
+                      int(d.get("ect_chunks", 0)), dict(d.get("timings", {})))
 
 
 def signature(plan, ect_rows=0, ect_thresholds=0, hybrid_rows=0, kernels=(), precision="fp32",
@@ -158,20 +164,20 @@ def tune(plan, ect_dirs=None, ect_thresholds=None, hybrid_xi=None, kernels=("fou
     if eq is not None and e_rows > 0:
         ect_t = {}
         out = None
-        for td in ECT_DIRS_CANDIDATES:
-            plan.set_tuning(0, best.hybrid_target_items, td)
+        for td, ch in ECT_CANDIDATES:
+            plan.set_tuning(0, best.hybrid_target_items, td, ch)
             out = plan.ect(eq, ect_thresholds, slot="ect")
 
             def run(o=out):
                 plan.ect(eq, ect_thresholds, out=o, slot="ect")
-            ect_t[td] = timer(run, reps)
-        best.ect_dirs_per_group = pick(ect_t)
-        timings["ect"] = {str(k): v for k, v in ect_t.items()}
+            ect_t[(td, ch)] = timer(run, reps)
+        best.ect_dirs_per_group, best.ect_chunks = pick(ect_t)
+        timings["ect"] = {f"{k[0]}/{k[1]}": v for k, v in ect_t.items()}
     if hq is not None and h_rows > 0:
         hy_t = {}
         kernels = tuple(kernels)
         for items in HYBRID_ITEM_CANDIDATES:
-            plan.set_tuning(0, items, best.ect_dirs_per_group)
+            plan.set_tuning(0, items, best.ect_dirs_per_group, best.ect_chunks)
             if len(kernels) > 1:
                 outs = plan.hybrid_multi(hq, kernels, s, precision)
             else:

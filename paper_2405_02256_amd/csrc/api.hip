@@ -267,15 +267,30 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
     // directions per workgroup: enough workgroups to fill the chip first, then
     // more directions per streamed point
     const int64_t nrows = query_rows(dirs, plan->num_images);
-    int td = plan->tune_ect_dirs_per_group > 0 ? plan->tune_ect_dirs_per_group
-                                             : (int)std::min<int64_t>(kEctMaxDirs, std::max<int64_t>(1, nrows / 1024));
+    int td = plan->tune_ect_dirs_per_group > 0
+                 ? plan->tune_ect_dirs_per_group
+                 : (dirs.offsets == nullptr ? kEctMaxDirs
+                                            : (int)std::min<int64_t>(kEctMaxDirs, std::max<int64_t>(1, nrows / 1024)));
     const int64_t lds_budget = 60 * 1024;
     td = (int)std::min<int64_t>(td, (lds_budget - 8 * (int64_t)M) / (4 * (int64_t)M));
     td = std::max(1, std::min(td, kEctMaxDirs));
-    // shared sets go straight to the evaluation kernel (no bucketing, no workspace)
+    // shared sets go straight to the evaluation kernel (no bucketing); long
+    // lists are split into chunks so that enough workgroups share each group
+    // of directions (about two per compute unit, at least 16384 points each:
+    // below that a workgroup's fixed cost outweighs streaming its list)
     const bool direct = dirs.offsets == nullptr;
     EvalLayout L{};
-    if (!direct) layout_ect(p, dirs, td, &L);
+    int64_t chunks = 1;
+    if (direct) {
+        const int64_t groups = (int64_t)p.num_images * ((dirs.count + td - 1) / td);
+        const double avg = mean_list(p, 0, num_classical(p.ndim));
+        const int64_t want = (2 * (int64_t)std::max(p.num_cus, 1) + groups - 1) / std::max<int64_t>(groups, 1);
+        chunks = p.tune_ect_chunks > 0 ? p.tune_ect_chunks
+                                       : std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)(avg / 16384.0)));
+        if (chunks > 1) L.total = sizeof(int32_t) * (size_t)(groups * chunks * td * (int64_t)M);
+    } else {
+        layout_ect(p, dirs, td, &L);
+    }
     if (!ws) {
         *ws_bytes = L.total;
         return ECT_OK;
@@ -290,7 +305,7 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
     int64_t direct_groups = 0;
     if (direct) {
         direct_groups = (dirs.count + td - 1) / td;
-        L.grid = direct_groups * p.num_images;
+        L.grid = direct_groups * p.num_images * chunks;
     } else {
         if (plan->last_prep.ws == ws) plan->last_prep.valid = false;
         e = launch_prepare(p.ndim, dirs, p.num_images, false, err, (QRec*)(w + L.recs), (int32_t*)(w + L.bcnt),
@@ -317,6 +332,8 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
         a.item_off = direct ? nullptr : (const int64_t*)(w + L.item_off);
         a.err = err;
         a.dirs_per_group = td;
+        a.chunks = chunks;
+        a.part = chunks > 1 ? (int32_t*)w : nullptr;
         e = launch_ect(p.ndim, a, L.grid, direct_groups, stream);
     }
     return from_hip(e);
@@ -515,16 +532,17 @@ ect_status ect_plan_destroy(ect_plan plan) {
 }
 
 ect_status ect_plan_set_tuning(ect_plan plan, int64_t hybrid_chunk, int64_t hybrid_target_items,
-                               int32_t ect_dirs_per_group) {
+                               int32_t ect_dirs_per_group, int32_t ect_chunks) {
     if (!plan) return ECT_E_INVALID;
     if (hybrid_chunk < 0 || (hybrid_chunk > 0 && hybrid_chunk < 16) || hybrid_chunk > (int64_t(1) << 40) ||
         hybrid_target_items < 1 || hybrid_target_items > (int64_t(1) << 24) || ect_dirs_per_group < 0 ||
-        ect_dirs_per_group > kEctMaxDirs)
+        ect_dirs_per_group > kEctMaxDirs || ect_chunks < 0 || ect_chunks > 4096)
         return ECT_E_INVALID;
     ++plan->lists_epoch;
     plan->tune_hybrid_chunk = hybrid_chunk;
     plan->tune_hybrid_target_items = hybrid_target_items;
     plan->tune_ect_dirs_per_group = ect_dirs_per_group;
+    plan->tune_ect_chunks = ect_chunks;
     return ECT_OK;
 }
 

@@ -180,11 +180,16 @@ __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
     write_rows(a, nd, s_row, s_valid, s_hist);
 }
 
-// Shared query sets: no bucketing pass.  Workgroup (image, g) takes rows
-// [g * dirs_per_group, ...) of the set in input order and streams the list of
-// each distinct sign vector among them once, for the directions that have it
-// (one pass when neighbouring directions share an orthant, as in angle-ordered
-// sets).  A non-finite direction gets a zero row and raises
+// Shared query sets: no bucketing pass.  Workgroup (image, g, c) takes rows
+// [g * dirs_per_group, ...) of the set in input order and, for each distinct
+// sign vector among them (one pass when neighbouring directions share an
+// orthant, as in angle-ordered sets), streams the c-th of `chunks` equal parts
+// of that list once for the directions that have it.  Splitting the lists
+// lets many workgroups share one group of directions, so each streamed point
+// serves up to eight directions while the chip stays full.  One chunk writes
+// the ECT rows itself; several write their histograms, which
+// ect_chunk_sum_kernel adds (integers, so the order cannot matter) before the
+// prefix sum.  A non-finite direction gets a zero row and raises
 // ECT_DEVERR_NONFINITE, as in the bucketed path.
 template <int N>
 __global__ void __launch_bounds__(kEctThreads) ect_direct_kernel(EctArgs a, int64_t groups) {
@@ -197,10 +202,14 @@ __global__ void __launch_bounds__(kEctThreads) ect_direct_kernel(EctArgs a, int6
     __shared__ int64_t s_row[TD];
     __shared__ int s_valid[TD];
     __shared__ int s_sign[TD];
+    __shared__ int64_t s_loff[2][1 << N];
 
     const int tid = threadIdx.x;
-    const int64_t img = blockIdx.x / groups;
-    const int64_t g = blockIdx.x % groups;
+    const int64_t chunks = a.chunks;
+    const int64_t c = blockIdx.x % chunks;
+    const int64_t rest = blockIdx.x / chunks;
+    const int64_t img = rest / groups;
+    const int64_t g = rest % groups;
     const int TDg = a.dirs_per_group;
     const int64_t q0 = g * TDg;
     const int nd = (int)min<int64_t>(TDg, a.count - q0);
@@ -213,52 +222,97 @@ __global__ void __launch_bounds__(kEctThreads) ect_direct_kernel(EctArgs a, int6
             double v[3] = {0.0, 0.0, 0.0};
             ok = 1;
 #pragma unroll
-            for (int c = 0; c < N; ++c) {
-                v[c] = a.vecs[q * N + c];
-                ok &= isfinite(v[c]) ? 1 : 0;
+            for (int cc = 0; cc < N; ++cc) {
+                v[cc] = a.vecs[q * N + cc];
+                ok &= isfinite(v[cc]) ? 1 : 0;
             }
 #pragma unroll
-            for (int c = 0; c < 3; ++c) s_xi[tid][c] = v[c];
+            for (int cc = 0; cc < 3; ++cc) s_xi[tid][cc] = v[cc];
             sg = sign_index<N>(v);
-            if (!ok) raise_error(a.err, ECT_DEVERR_NONFINITE);
+            if (!ok && c == 0) raise_error(a.err, ECT_DEVERR_NONFINITE);
         }
         s_row[tid] = row;
         s_valid[tid] = ok;
         s_sign[tid] = sg;
     }
-    if (stage_thresholds(a, img, s_thr, s_hist)) {
-        if (tid == 0) raise_error(a.err, ECT_DEVERR_THRESHOLDS);
-        zero_rows(a, nd, s_row);
-        return;
+    // every classical list's bounds are requested now, with the directions and
+    // thresholds, instead of after the barrier
+    if (tid >= 64 && tid < 64 + (2 << N)) {
+        const int k = tid - 64, b = k & ((1 << N) - 1), hi = k >> N;
+        s_loff[hi][b] = a.list_off[(img + hi) * a.NL + b];
     }
-    double xi[TD][N];
-    int sgn[TD];
-    bool pending[TD];
-#pragma unroll
-    for (int dd = 0; dd < TD; ++dd) {
-        pending[dd] = dd < nd && s_valid[dd];
-        sgn[dd] = s_sign[dd];
-#pragma unroll
-        for (int c = 0; c < N; ++c) xi[dd][c] = s_xi[dd][c];
-    }
-    // one pass per distinct sign vector, in order of first appearance
-    for (int pass = 0; pass < TD; ++pass) {
-        int b = -1;
-#pragma unroll
-        for (int dd = TD - 1; dd >= 0; --dd)
-            if (pending[dd]) b = sgn[dd];
-        if (b < 0) break;
-        bool use[TD];
+    const int bad = stage_thresholds(a, img, s_thr, s_hist);
+    if (bad) {
+        if (tid == 0 && c == 0) raise_error(a.err, ECT_DEVERR_THRESHOLDS);
+    } else {
+        double xi[TD][N];
+        int sgn[TD];
+        bool pending[TD];
 #pragma unroll
         for (int dd = 0; dd < TD; ++dd) {
-            use[dd] = pending[dd] && sgn[dd] == b;
-            if (use[dd]) pending[dd] = false;
+            pending[dd] = dd < nd && s_valid[dd];
+            sgn[dd] = s_sign[dd];
+#pragma unroll
+            for (int cc = 0; cc < N; ++cc) xi[dd][cc] = s_xi[dd][cc];
         }
-        const int64_t p0 = a.list_off[img * a.NL + b], p1 = a.list_off[(img + 1) * a.NL + b];
-        accumulate_list<N>(a.points + (int64_t)b * a.capacity, p0, p1, xi, use, s_thr, M, s_hist);
+        // one pass per distinct sign vector, in order of first appearance
+        for (int pass = 0; pass < TD; ++pass) {
+            int b = -1;
+#pragma unroll
+            for (int dd = TD - 1; dd >= 0; --dd)
+                if (pending[dd]) b = sgn[dd];
+            if (b < 0) break;
+            bool use[TD];
+#pragma unroll
+            for (int dd = 0; dd < TD; ++dd) {
+                use[dd] = pending[dd] && sgn[dd] == b;
+                if (use[dd]) pending[dd] = false;
+            }
+            const int64_t p0 = s_loff[0][b], p1 = s_loff[1][b];
+            const int64_t len = p1 - p0;
+            accumulate_list<N>(a.points + (int64_t)b * a.capacity, p0 + len * c / chunks,
+                               p0 + len * (c + 1) / chunks, xi, use, s_thr, M, s_hist);
+        }
     }
     __syncthreads();
-    write_rows(a, nd, s_row, s_valid, s_hist);
+    if (chunks == 1) {
+        if (bad) zero_rows(a, nd, s_row);
+        else write_rows(a, nd, s_row, s_valid, s_hist);
+        return;
+    }
+    // chunk histograms (zeros for invalid directions or bad thresholds)
+    int32_t* part = a.part + (rest * chunks + c) * (int64_t)TDg * M;
+    for (int j = tid; j < nd * M; j += kEctThreads) part[j] = s_hist[j];
+}
+
+// Sum of the chunk histograms of one direction (one wave per output row) and
+// the inclusive prefix over thresholds.
+__global__ void __launch_bounds__(64) ect_chunk_sum_kernel(EctArgs a, int64_t groups) {
+    const int lane = threadIdx.x;
+    const int TDg = a.dirs_per_group;
+    const int M = a.M;
+    const int64_t chunks = a.chunks;
+    const int64_t dd = blockIdx.x % TDg;
+    const int64_t rest = blockIdx.x / TDg;   // image * groups + g
+    const int64_t q = (rest % groups) * TDg + dd;
+    if (q >= a.count) return;
+    const int64_t img = rest / groups;
+    int32_t* out = a.out + (img * a.count + q) * M;
+    const int32_t* part = a.part + rest * chunks * (int64_t)TDg * M + dd * M;
+    int32_t carry = 0;
+    for (int jb = 0; jb < M; jb += 64) {
+        const int j = jb + lane;
+        int32_t v = 0;
+        if (j < M)
+            for (int64_t c = 0; c < chunks; ++c) v += part[c * TDg * M + j];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t o = __shfl_up(v, off, 64);
+            if (lane >= off) v += o;
+        }
+        if (j < M) out[j] = carry + v;
+        carry += __shfl(v, 63, 64);
+    }
 }
 
 }  // namespace
@@ -275,6 +329,12 @@ hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, int64_t direct_g
         else
             hipLaunchKernelGGL(ect_direct_kernel<3>, dim3((unsigned)grid), dim3(kEctThreads), shmem, stream, a,
                                direct_groups);
+        if (a.chunks > 1) {
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            const int64_t rows = (grid / a.chunks) * a.dirs_per_group;
+            hipLaunchKernelGGL(ect_chunk_sum_kernel, dim3((unsigned)rows), dim3(64), 0, stream, a, direct_groups);
+        }
     } else if (ndim == 2) {
         hipLaunchKernelGGL(ect_kernel<2>, dim3((unsigned)grid), dim3(kEctThreads), shmem, stream, a);
     } else {

@@ -87,6 +87,7 @@ struct ect_plan_s {
     int64_t tune_hybrid_chunk = 0;          // 0: automatic
     int64_t tune_hybrid_target_items = 2048;
     int32_t tune_ect_dirs_per_group = 0;    // 0: automatic
+    int32_t tune_ect_chunks = 0;            // 0: automatic
 };
 
 namespace ect {

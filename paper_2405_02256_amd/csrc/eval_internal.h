@@ -59,10 +59,13 @@ struct EctArgs {
     const int64_t* item_off;
     uint32_t* err;
     int dirs_per_group;
+    int64_t chunks;           // shared sets: point chunks per direction group (1: no split)
+    int32_t* part;            // shared sets with chunks > 1: per-chunk histograms
 };
 
-// direct_groups > 0: shared query set, grid = num_images * direct_groups
-// workgroups of ect_direct_kernel (no bucketing); else the bucketed kernel.
+// direct_groups > 0: shared query set, num_images * direct_groups * a.chunks
+// workgroups of ect_direct_kernel (no bucketing), then, with a.chunks > 1, the
+// in-order sum of the chunk histograms; else the bucketed kernel.
 hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, int64_t direct_groups, hipStream_t stream);
 
 constexpr int kJi0SmallCoeffs = 10;   // FP32-path small-argument Ji0 polynomial

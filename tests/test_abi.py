@@ -91,7 +91,7 @@ def test_eval_calls_reject_null_plan(N):
 
 
 def test_tuning_validation(N):
-    assert N.ect_plan_set_tuning(None, 0, 2048, 0) == N.ECT_E_INVALID
+    assert N.ect_plan_set_tuning(None, 0, 2048, 0, 0) == N.ECT_E_INVALID
 
 
 def test_product_path_refuses_without_library(tmp_path, monkeypatch):

@@ -30,14 +30,14 @@ def test_pick_fastest_and_ties_keep_first():
 def test_cache_round_trip(tmp_path):
     c = AT.Cache(str(tmp_path / "sub" / "t.json"))
     assert c.get("dev", "sig") is None
-    t = AT.Tuning(0, 4096, 2, {"ect": {"1": 0.1}})
+    t = AT.Tuning(0, 4096, 2, 3, {"ect": {"1/0": 0.1}})
     c.put("dev", "sig", t)
     c.put("dev", "sig2", AT.Tuning(64, 2048, 0))
-    c.put("dev2", "sig", AT.Tuning(0, 512, 8))
+    c.put("dev2", "sig", AT.Tuning(0, 512, 8, 1))
     got = c.get("dev", "sig")
-    assert got.as_args() == (0, 4096, 2) and got.timings == {"ect": {"1": 0.1}}
-    assert c.get("dev", "sig2").as_args() == (64, 2048, 0)
-    assert c.get("dev2", "sig").as_args() == (0, 512, 8)
+    assert got.as_args() == (0, 4096, 2, 3) and got.timings == {"ect": {"1/0": 0.1}}
+    assert c.get("dev", "sig2").as_args() == (64, 2048, 0, 0)
+    assert c.get("dev2", "sig").as_args() == (0, 512, 8, 1)
     assert set(json.load(open(c.path))) == {"dev", "dev2"}
 
 
@@ -47,7 +47,7 @@ def test_cache_tolerates_garbage(tmp_path):
     c = AT.Cache(str(p))
     assert c.get("dev", "sig") is None
     c.put("dev", "sig", AT.Tuning())
-    assert c.get("dev", "sig").as_args() == (0, 2048, 0)
+    assert c.get("dev", "sig").as_args() == (0, 2048, 0, 0)
     p.write_text(json.dumps({"dev": {"sig": {"hybrid_chunk": "x"}}}))
     assert c.get("dev", "sig") is None
 

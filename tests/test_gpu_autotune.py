@@ -45,12 +45,12 @@ def small():
 
 # chunk 16 splits every list into many chunks (more than the reduce kernel's
 # batch of 16 per pass); large chunks leave every tile in one chunk
-@pytest.mark.parametrize("chunk,items,td", [(16, 2048, 1), (48, 2048, 3), (0, 1, 8), (0, 1 << 24, 0),
-                                            (1 << 20, 2048, 5)])
-def test_any_tuning_keeps_parity(api, small, chunk, items, td):
+@pytest.mark.parametrize("chunk,items,td,ech", [(16, 2048, 1, 1), (48, 2048, 3, 0), (0, 1, 8, 7), (0, 1 << 24, 0, 64),
+                                                (1 << 20, 2048, 5, 4096)])
+def test_any_tuning_keeps_parity(api, small, chunk, items, td, ech):
     img, xi, dirs, thr = small
     plan = api.Plan(T(img))
-    plan.set_tuning(chunk, items, td)
+    plan.set_tuning(chunk, items, td, ech)
     assert np.array_equal(plan.ect(T(dirs), T(thr)).cpu().numpy(), O.ect(img, dirs, thr))
     outs = plan.hybrid_multi(T(xi), ("fourier", "laplace", "bessel"), 1.0, "fp32")
     for k in ("fourier", "laplace", "bessel"):
@@ -85,7 +85,8 @@ def test_same_tuning_bitwise_identical(api, small):
 
 def test_rejects_out_of_range(api, small):
     plan = api.Plan(T(small[0]))
-    for args in [(8, 2048, 0), (-1, 2048, 0), (0, 0, 0), (0, 2048, 9), (0, 2048, -1)]:
+    for args in [(8, 2048, 0), (-1, 2048, 0), (0, 0, 0), (0, 2048, 9), (0, 2048, -1), (0, 2048, 0, -1),
+                 (0, 2048, 0, 4097)]:
         with pytest.raises(RuntimeError):
             plan.set_tuning(*args)
 
@@ -100,7 +101,7 @@ def test_autotuned_step_replays_and_caches(api, small, tmp_path):
     step = Step(plan, T(dirs), T(thr), T(xi), ("fourier", "laplace", "bessel"), backward_kernel="fourier",
                 grad_out=g)
     t = step.autotune(cache=cache, reps=3)
-    assert t.ect_dirs_per_group in AT.ECT_DIRS_CANDIDATES
+    assert (t.ect_dirs_per_group, t.ect_chunks) in AT.ECT_CANDIDATES
     assert t.hybrid_target_items in AT.HYBRID_ITEM_CANDIDATES
     assert set(t.timings) == {"ect", "hybrid"}
     assert plan.tuning == t.as_args()
