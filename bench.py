@@ -231,7 +231,7 @@ def main():
         b = args.cpu_budget
         full = {"ect": len(w.ect_dirs), "fourier": len(w.hybrid_xi), "laplace": len(w.hybrid_xi),
                 "bessel": len(w.hybrid_xi), "grad": len(w.hybrid_xi)}
-        base = {"ect": 72, "fourier": 256, "laplace": 256, "bessel": 32, "grad": 128}
+        base = {"ect": 72, "fourier": 512, "laplace": 512, "bessel": 96, "grad": 384}
         samp = {k: int(min(full[k], max(4, base[k] * b))) for k in base}
         tcpu = {}
         sel_d = np.linspace(0, len(w.ect_dirs) - 1, samp["ect"]).astype(int)

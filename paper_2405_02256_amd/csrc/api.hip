@@ -192,11 +192,14 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
 
     PlanLayout L{};
     size_t o = 0;
-    L.err = o; o = align_up(o + 16, kAlign);   // uint32 error word, uint32 spare, uint64 ticket counter
+    L.err = o; o = align_up(o + 16, kAlign);   // uint32 error word, uint32 spare, uint64 run counter
     L.desc = o; o = align_up(o + sizeof(ImageDesc) * ni, kAlign);
     L.tile_start = o; o = align_up(o + sizeof(int64_t) * (ni + 1), kAlign);
     L.list_off = o; o = align_up(o + sizeof(int64_t) * (int64_t)(ni + 1) * NL, kAlign);
-    L.status = o; o = align_up(o + sizeof(uint64_t) * (tiles + (tiles + 63) / 64) * NL, kAlign);
+    // single pass: tile aggregates and totals of 64-tile groups; three passes:
+    // tile counts (int32) and their prefixes (int64).  The size does not
+    // depend on the device.
+    L.status = o; o = align_up(o + sizeof(uint64_t) * (2 * tiles + (tiles + 63) / 64 + 1) * NL, kAlign);
     L.points = o; o = align_up(o + sizeof(Point) * verts * NL, kAlign);
     L.total = o;
     L.num_tiles = tiles;
@@ -227,13 +230,17 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
         return ECT_E_NOMEM;
     }
     std::memcpy(p->h_desc, desc.data(), sizeof(ImageDesc) * ni);
+    // compaction workgroups the chip holds at once: plans with at most that
+    // many tiles (and at most 64 groups of 64) use the single pass
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) {
+    const int64_t per_cu = e == hipSuccess ? precompute_slots_per_cu(n, batch->construction, batch->dtype) : 0;
+    if (per_cu <= 0) {
         ect_plan_destroy(p);
         return ECT_E_DEVICE;
     }
+    p->precompute_grid = std::min<int64_t>(per_cu * p->num_cus, 64 * 64);
 
     e = hipMemcpyAsync(p->ws + L.desc, desc.data(), sizeof(ImageDesc) * ni, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)

@@ -42,11 +42,11 @@ struct alignas(16) ImageDesc {
 
 // Layout of the precompute workspace (byte offsets from its base).
 struct PlanLayout {
-    size_t err;             // uint32 device error word, uint32 spare, uint64 look-back ticket counter
+    size_t err;             // uint32 device error word, uint32 spare, uint64 run counter
     size_t desc;            // ImageDesc[num_images]
     size_t tile_start;      // int64[num_images + 1]
     size_t list_off;        // int64[(num_images + 1) * NL]: start of image i in list l
-    size_t status;          // uint64[(num_tiles + groups of 64 tiles) * NL]: ordered-compaction status words
+    size_t status;          // uint64 ordered-compaction status words: tiles, group totals, carries (x NL)
     size_t points;          // Point[NL * capacity]
     size_t total;
     int64_t num_tiles;
@@ -62,9 +62,7 @@ struct ect_plan_s {
     int32_t dtype = 0;
     int32_t construction = 0;
     int32_t num_cus = 0;                    // compute units of the plan's device
-    // 1: the precompute grid fits on the chip at once (tile = workgroup id),
-    // 0: tiles by ticket, -1: not decided yet (first launch)
-    mutable int32_t precompute_resident = -1;
+    int64_t precompute_grid = 1;            // tiles the single-pass compaction handles (all resident)
     const void* pixels = nullptr;
     char* ws = nullptr;
     ect::PlanLayout lay{};
@@ -133,5 +131,7 @@ inline hipError_t stage_mark(int stage, bool after, hipStream_t s) {
 // first: also clear the plan's error word, ticket counter and look-back words
 // (plan creation); re-runs launch the classification kernel alone.
 hipError_t launch_precompute(const Plan& p, bool first, hipStream_t stream);
+// Compaction workgroups one compute unit holds at once (0 if unknown).
+int64_t precompute_slots_per_cu(int ndim, int construction, int dtype);
 
 }  // namespace ect

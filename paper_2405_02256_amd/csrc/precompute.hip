@@ -16,33 +16,30 @@
 // changes a min over existing cofaces, and cells that do not exist are masked
 // by the existence test on the vertex index.
 //
-// Compaction is single pass and ordered: every workgroup takes the next tile
-// id from a counter, counts its nonzero values per list with wave ballots,
-// publishes the counts and resolves its global offset by decoupled look-back
-// over the preceding tiles (the workgroup's waves inspect 64 predecessors each
-// per round, for every list at once), then writes its entries in vertex
-// order.  Lists therefore come out sorted by linear vertex index, and
-// identically on every run.
+// Compaction is ordered: every tile counts its nonzero values per list with
+// wave ballots and needs the counts of all earlier tiles.  When every tile's
+// workgroup fits on the chip at once, one pass does it: a tile publishes its
+// counts and resolves its offset by a two-level scan (its group of 64 tiles,
+// then the group totals) before writing its entries in vertex order.  Larger
+// plans count, scan the counts in one workgroup, and classify again to write
+// (three launches, no workgroup ever waits on another).  Lists come out
+// sorted by linear vertex index, and identically on every run.
+#include <type_traits>
+
 #include "ect_internal.h"
 
 namespace ect {
 
 namespace {
 
-// Look-back status word: flag (bits 63-62), run parity (bit 61), count.  A
-// word is current when its parity bit matches the run's: every word left by
-// run r-1 reads as "not yet published" in run r, so re-runs need no reset
-// launch.  The run number comes from a 64-bit counter in the plan's workspace
-// that is never reset:
-//   resident grids (every workgroup fits on the chip at once): tile =
-//     blockIdx.x, the counter holds the run number; every workgroup reads it
-//     first, and the last tile increments it once its look-back is complete,
-//     which implies that every tile has published a word, so has read it;
-//   larger grids: the counter hands out tickets in start order (tile =
-//     ticket % num_tiles, run = ticket / num_tiles), so a workgroup only
-//     waits on tiles whose workgroups have started.
+// Status word of the single pass: flag (bits 63-62), run parity (bit 61),
+// count.  A word is current when its parity bit matches the run's: every word
+// left by run r-1 reads as "not yet published" in run r, so re-runs need no
+// reset launch.  The run number is a 64-bit counter in the plan's workspace
+// that every workgroup reads first; the last tile advances it once every group
+// total is in, which implies that every tile has published a word, hence has
+// read it.
 constexpr uint64_t kFlagAggregate = 1ull << 62;
-constexpr uint64_t kFlagInclusive = 2ull << 62;
 constexpr uint64_t kFlagMask = 3ull << 62;
 constexpr uint64_t kParityBit = 1ull << 61;
 constexpr uint64_t kValueMask = (1ull << 61) - 1;
@@ -192,12 +189,12 @@ __device__ __forceinline__ void vertex_values(const int32_t* p, const ImageDesc&
     for (int e = 0; e < (1 << (N - 1)); ++e) D[e] = L[e ^ full] - L[e];
 }
 
-// Once per plan: clear the error word, the ticket counter and the status words.
-__global__ void reset_kernel(uint32_t* __restrict__ err, uint64_t* __restrict__ ticket, uint64_t* __restrict__ status,
+// Once per plan: clear the error word, the run counter and the status words.
+__global__ void reset_kernel(uint32_t* __restrict__ err, uint64_t* __restrict__ run_ctr, uint64_t* __restrict__ status,
                              int64_t nstatus) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    if (i == 0) { err[0] = 0u; err[1] = 0u; *ticket = 0ull; }
+    if (i == 0) { err[0] = 0u; err[1] = 0u; *run_ctr = 0ull; }
     for (; i < nstatus; i += stride) status[i] = 0ull;
 }
 
@@ -235,56 +232,47 @@ __device__ __forceinline__ bool sum_published(const uint64_t* words, int64_t cou
             if (lane == 0) raise_error(err, ECT_DEVERR_LOOKBACK);
             return false;
         }
-        __builtin_amdgcn_s_sleep(1);
+        // back off: the polls are uncached loads, and thousands of waiting
+        // waves polling at full rate slow down the stores they wait for
+        const int naps = spins < 16 ? spins + 1 : 16;
+        for (int i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(2);
     }
 }
 
+// Critical values of one tile's vertices (thread tid holds vertices
+// vbase + j * kPrecomputeThreads + tid) and the per-(round, wave, list)
+// counts of nonzero values in s_cnt; the caller synchronises before reading
+// s_cnt.
+template <int N>
+struct TileValues {
+    static constexpr int NC = 1 << N, NO = 1 << (N - 1), NL = NC + NO;
+    ImageDesc d;
+    int img_id;
+    int32_t vals[kVertsPerThread][NL];
+    int kk[kVertsPerThread][3];
+};
+
 template <int N, int CONS, typename T>
-__global__ void __launch_bounds__(kPrecomputeThreads)
-classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
-                 const int64_t* __restrict__ tile_start, int32_t num_images, int64_t num_tiles,
-                 uint32_t* __restrict__ err, uint64_t* __restrict__ ticket, uint64_t* __restrict__ status,
-                 uint64_t* __restrict__ gstatus, int64_t* __restrict__ list_off, Point* __restrict__ points,
-                 int64_t capacity, int resident) {
-    constexpr int NC = 1 << N;
-    constexpr int NO = 1 << (N - 1);
-    constexpr int NL = NC + NO;
-    constexpr int W = kPrecomputeThreads / 64;
+__device__ __forceinline__ void tile_values(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
+                                            const int64_t* __restrict__ tile_start, int32_t num_images,
+                                            int64_t tile, TileValues<N>& tv,
+                                            int32_t (*s_cnt)[kPrecomputeThreads / 64][TileValues<N>::NL]) {
+    constexpr int NC = TileValues<N>::NC, NO = TileValues<N>::NO, NL = TileValues<N>::NL;
     constexpr int J = kVertsPerThread;
-
-    __shared__ uint64_t s_ticket;
-    __shared__ int32_t s_cnt[J][W][NL];   // per (round, wave, list) counts, then exclusive offsets
-    __shared__ int64_t s_base[NL];
-    __shared__ uint64_t s_lb_sum[W][NL];
-    __shared__ int s_lb_state[W][NL];   // 0: no inclusive prefix in the part, 1: found one, 2: a word not ready
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    if (tid == 0)
-        s_ticket = resident ? __hip_atomic_load(ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                            : __hip_atomic_fetch_add(ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const uint64_t tk = s_ticket;
-    const int64_t tile = resident ? (int64_t)blockIdx.x : (int64_t)(tk % (uint64_t)num_tiles);
-    const uint64_t run = resident ? tk : tk / (uint64_t)num_tiles;
-    const uint64_t parity = (run & 1ull) ? kParityBit : 0ull;
-
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // image owning this tile: last i with tile_start[i] <= tile
     int lo = 0, hi = num_images - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
         if (tile_start[mid] <= tile) lo = mid; else hi = mid - 1;
     }
-    const ImageDesc d = descs[lo];
-    const int img_id = lo;
+    tv.d = descs[lo];
+    tv.img_id = lo;
+    const ImageDesc& d = tv.d;
     const T* __restrict__ img = pixels + d.pixel_offset;
     const int64_t vbase = (tile - d.tile_start) * kTileVerts;
     const double inv0 = 1.0 / (double)d.V[0];
     const double inv1 = 1.0 / (double)d.V[1];
-
-    int32_t vals[J][NL];
-    int kk[J][3];
     bool valid[J];
     // every round's pixel loads are issued before any vertex is classified
     int32_t nb[J][nb_count<N, CONS>()];
@@ -295,219 +283,358 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
         uint32_t r0, r1;
         uint32_t q0 = udiv((uint32_t)(valid[j] ? v : 0), (uint32_t)d.V[0], inv0, &r0);
         uint32_t q1 = N == 3 ? udiv(q0, (uint32_t)d.V[1], inv1, &r1) : 0u;
-        kk[j][0] = (int)r0;
-        kk[j][1] = N == 3 ? (int)r1 : (int)q0;
-        kk[j][2] = N == 3 ? (int)q1 : 0;
-        load_neighbourhood<N, CONS, T>(img, d, kk[j], nb[j]);
+        tv.kk[j][0] = (int)r0;
+        tv.kk[j][1] = N == 3 ? (int)r1 : (int)q0;
+        tv.kk[j][2] = N == 3 ? (int)q1 : 0;
+        load_neighbourhood<N, CONS, T>(img, d, tv.kk[j], nb[j]);
     }
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         int32_t L[NC], D[NO];
-        vertex_values<N, CONS>(nb[j], d, kk[j], L, D);
+        vertex_values<N, CONS>(nb[j], d, tv.kk[j], L, D);
 #pragma unroll
-        for (int l = 0; l < NC; ++l) vals[j][l] = valid[j] ? L[l] : 0;
+        for (int l = 0; l < NC; ++l) tv.vals[j][l] = valid[j] ? L[l] : 0;
 #pragma unroll
-        for (int l = 0; l < NO; ++l) vals[j][NC + l] = valid[j] ? D[l] : 0;
+        for (int l = 0; l < NO; ++l) tv.vals[j][NC + l] = valid[j] ? D[l] : 0;
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
-            uint64_t b = __ballot(vals[j][l] != 0);
+            uint64_t b = __ballot(tv.vals[j][l] != 0);
             if (lane == 0) s_cnt[j][wave][l] = __popcll(b);
         }
     }
-    __syncthreads();
+}
 
-    // tile aggregates (wave 0, lane l < NL owns list l); per-(round, wave)
-    // counts become exclusive offsets inside the tile
-    uint64_t agg = 0;
-    if (wave == 0 && lane < NL) {
-        int32_t run = 0;
+// Wave 0, lane l < NL: turn list l's counts into exclusive offsets inside the
+// tile and return the tile's total for list l (0 elsewhere).
+template <int NL>
+__device__ __forceinline__ uint64_t tile_offsets(int32_t (*s_cnt)[kPrecomputeThreads / 64][NL]) {
+    const int lane = threadIdx.x & 63;
+    if (lane >= NL) return 0;
+    int32_t cnt = 0;
 #pragma unroll
-        for (int j = 0; j < J; ++j)
+    for (int j = 0; j < kVertsPerThread; ++j)
 #pragma unroll
-            for (int w = 0; w < W; ++w) {
-                int32_t c = s_cnt[j][w][lane];
-                s_cnt[j][w][lane] = run;
-                run += c;
-            }
-        agg = (uint64_t)run;
-        if (tile > 0 || resident)   // the two-level scan also reads tile 0's aggregate
-            __hip_atomic_store(status + tile * NL + lane, kFlagAggregate | parity | agg, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (resident) {
-        // Two-level scan (every tile is running, so none waits on an unstarted
-        // one): tiles form groups of 64; wave 0 sums the aggregates of the
-        // tile's predecessors in its group, the group's last tile publishes
-        // the group total, and the totals of the preceding groups complete the
-        // prefix.  Each tile reads at most 63 + groups words per list, where a
-        // window look-back over simultaneously finishing tiles reads hundreds.
-        if (wave == 0) {
-            const int64_t g = tile >> 6, k = tile & 63;
-            uint64_t loc[NL], grp[NL];
-            bool ok = sum_published<NL>(status + (g << 6) * NL, k, parity, loc, err);
-            if (ok && (k == 63 || tile == num_tiles - 1) && lane < NL) {
-                uint64_t mine = 0;
-#pragma unroll
-                for (int l = 0; l < NL; ++l) if (lane == l) mine = loc[l];
-                __hip_atomic_store(gstatus + g * NL + lane, kFlagAggregate | parity | (mine + agg), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (ok) ok = sum_published<NL>(gstatus, g, parity, grp, err);
-            // every group total is in, so every tile has read the run number
-            if (tile == num_tiles - 1 && lane == 0)
-                __hip_atomic_store(ticket, tk + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (lane < NL) {
-                uint64_t mine = 0;
-#pragma unroll
-                for (int l = 0; l < NL; ++l) if (lane == l) mine = ok ? loc[l] + grp[l] : 0;
-                s_base[lane] = (int64_t)mine;
-                if (tile == d.tile_start) list_off[(int64_t)img_id * NL + lane] = (int64_t)mine;
-                if (tile == num_tiles - 1) list_off[(int64_t)num_images * NL + lane] = (int64_t)(mine + agg);
-            }
+        for (int w = 0; w < kPrecomputeThreads / 64; ++w) {
+            int32_t c = s_cnt[j][w][lane];
+            s_cnt[j][w][lane] = cnt;
+            cnt += c;
         }
-    } else {
-    // Decoupled look-back over windows of 64 * W predecessor tiles: lane i of
-    // wave w inspects tile base - 64 w - i for every list at once.  A status
-    // word carries both its flag and its count, so relaxed device-scope
-    // atomics suffice (no fence, hence no L2 write-back between the chip's
-    // non-coherent L2 slices); the list entries are only read by later
-    // kernels.  Per list, the nearest tile holding an inclusive prefix ends
-    // the walk; every tile in front of it must have published its aggregate,
-    // otherwise the window is read again.  The waves' window parts are
-    // combined in order through LDS.
-    {
-        uint64_t excl[NL];
-        int64_t wbase[NL];
-        bool done[NL];
-#pragma unroll
-        for (int l = 0; l < NL; ++l) { excl[l] = 0; wbase[l] = tile - 1; done[l] = tile == 0; }
-        int spins = 0;
-        bool all_done = tile == 0;
-        while (!all_done) {
-            // every list's word is requested before any is examined, so the
-            // loads are in flight together
-            uint64_t wvs[NL];
-#pragma unroll
-            for (int l = 0; l < NL; ++l) {
-                const int64_t j = wbase[l] - 64 * wave - lane;
-                wvs[l] = (!done[l] && j >= 0)
-                             ? __hip_atomic_load(status + j * NL + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                             : (kFlagInclusive | parity);
-            }
-#pragma unroll
-            for (int l = 0; l < NL; ++l) {
-                if (done[l]) continue;
-                const uint64_t wv = wvs[l];
-                const uint64_t f = wv & kFlagMask;
-                const bool current = (wv & kParityBit) == parity;
-                const uint64_t incl = __ballot(current && f == kFlagInclusive);
-                const uint64_t notready = __ballot(!current || f == 0);
-                const int first = incl ? (int)__ffsll((unsigned long long)incl) - 1 : 64;
-                const uint64_t upto = first >= 63 ? ~0ull : ((1ull << (first + 1)) - 1ull);
-                uint64_t v = (lane <= first) ? (wv & kValueMask) : 0ull;
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-                if (lane == 0) {
-                    s_lb_sum[wave][l] = v;
-                    s_lb_state[wave][l] = (notready & upto) ? 2 : (first < 64 ? 1 : 0);
-                }
-            }
-            __syncthreads();
-            // every thread combines the W parts in order (same result everywhere)
-            bool waiting = false;
-            all_done = true;
-#pragma unroll
-            for (int l = 0; l < NL; ++l) {
-                if (done[l]) continue;
-                uint64_t total = 0;
-                int state = 0;
-                for (int w = 0; w < W; ++w) {
-                    const int st = s_lb_state[w][l];
-                    if (st == 2) { state = 2; break; }
-                    total += s_lb_sum[w][l];
-                    if (st == 1) { state = 1; break; }
-                }
-                if (state == 2) { waiting = true; all_done = false; continue; }
-                excl[l] += total;
-                if (state == 1) done[l] = true;
-                else { wbase[l] -= 64 * W; all_done = false; }
-            }
-            __syncthreads();   // the parts are rewritten by the next round
-            if (waiting) {
-                if (++spins > kLookbackSpinLimit) {
-                    if (tid == 0) raise_error(err, ECT_DEVERR_LOOKBACK);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        if (wave == 0 && lane < NL) {
-            uint64_t mine = 0;
-#pragma unroll
-            for (int l = 0; l < NL; ++l) if (lane == l) mine = excl[l];
-            __hip_atomic_store(status + tile * NL + lane, kFlagInclusive | parity | (mine + agg), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            s_base[lane] = (int64_t)mine;
-            if (tile == d.tile_start) list_off[(int64_t)img_id * NL + lane] = (int64_t)mine;
-            if (tile == num_tiles - 1) list_off[(int64_t)num_images * NL + lane] = (int64_t)(mine + agg);
-        }
-    }
-    }
-    __syncthreads();
+    return (uint64_t)cnt;
+}
 
+// Write the tile's list entries in vertex order from the list bases s_base
+// and the in-tile offsets.
+template <int N>
+__device__ __forceinline__ void emit_points(const TileValues<N>& tv,
+                                            int32_t (*s_cnt)[kPrecomputeThreads / 64][TileValues<N>::NL],
+                                            const int64_t* s_base, Point* __restrict__ points, int64_t capacity) {
+    constexpr int NL = TileValues<N>::NL;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
+    for (int j = 0; j < kVertsPerThread; ++j) {
         Point pt;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-            pt.x[a] = a < N ? __fma_rn(d.spacing[a], (double)kk[j][a], d.origin[a]) : 0.0;
+            pt.x[a] = a < N ? __fma_rn(tv.d.spacing[a], (double)tv.kk[j][a], tv.d.origin[a]) : 0.0;
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
-            const bool nz = vals[j][l] != 0;
+            const bool nz = tv.vals[j][l] != 0;
             const uint64_t b = __ballot(nz);
             if (nz) {
                 const int rank = __popcll(b & ((1ull << lane) - 1ull));
-                const int64_t pos = s_base[l] + s_cnt[j][wave][l] + rank;
-                pt.val = (double)vals[j][l];
-                points[(int64_t)l * capacity + pos] = pt;
+                const int64_t pos_l = s_base[l] + s_cnt[j][wave][l] + rank;
+                pt.val = (double)tv.vals[j][l];
+                points[(int64_t)l * capacity + pos_l] = pt;
             }
         }
     }
 }
 
+// Single pass, for plans whose tiles all fit on the chip at once (one
+// workgroup per tile, all resident): wave 0 of a tile sums the aggregates of
+// its predecessors in its group of 64 (level 1), the group's last tile
+// publishes the group total, and the totals of the preceding groups complete
+// the prefix (level 2).  Every word a tile waits on belongs to a running or
+// finished workgroup, so the waits end.
+template <int N, int CONS, typename T>
+__global__ void __launch_bounds__(kPrecomputeThreads)
+classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
+                 const int64_t* __restrict__ tile_start, int32_t num_images, int64_t num_tiles,
+                 uint32_t* __restrict__ err, uint64_t* __restrict__ run_ctr, uint64_t* __restrict__ status,
+                 uint64_t* __restrict__ gstatus, int64_t* __restrict__ list_off, Point* __restrict__ points,
+                 int64_t capacity) {
+    constexpr int NL = TileValues<N>::NL;
+    constexpr int W = kPrecomputeThreads / 64;
+    __shared__ uint64_t s_run;
+    __shared__ int32_t s_cnt[kVertsPerThread][W][NL];   // per (round, wave, list) counts, then offsets
+    __shared__ int64_t s_base[NL];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t tile = blockIdx.x;
+    if (tid == 0) s_run = __hip_atomic_load(run_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    TileValues<N> tv;
+    tile_values<N, CONS, T>(pixels, descs, tile_start, num_images, tile, tv, s_cnt);
+    __syncthreads();
+    const uint64_t run = s_run;
+    const uint64_t parity = (run & 1ull) ? kParityBit : 0ull;
+    if (wave == 0) {
+        const uint64_t agg = tile_offsets<NL>(s_cnt);
+        if (lane < NL)
+            __hip_atomic_store(status + tile * NL + lane, kFlagAggregate | parity | agg, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t g = tile >> 6, k = tile & 63;
+        uint64_t loc[NL], grp[NL];
+        bool ok = sum_published<NL>(status + (tile - k) * NL, k, parity, loc, err);
+        if (ok && (k == 63 || tile == num_tiles - 1) && lane < NL) {
+            uint64_t mine = 0;
+#pragma unroll
+            for (int l = 0; l < NL; ++l) if (lane == l) mine = loc[l];
+            __hip_atomic_store(gstatus + g * NL + lane, kFlagAggregate | parity | (mine + agg), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (ok) ok = sum_published<NL>(gstatus, g, parity, grp, err);
+        // every group total is in, so every tile has read the run number
+        if (tile == num_tiles - 1 && lane == 0)
+            __hip_atomic_store(run_ctr, run + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane < NL) {
+            uint64_t mine = 0;
+#pragma unroll
+            for (int l = 0; l < NL; ++l) if (lane == l) mine = ok ? loc[l] + grp[l] : 0;
+            s_base[lane] = (int64_t)mine;
+            if (tile == tv.d.tile_start) list_off[(int64_t)tv.img_id * NL + lane] = (int64_t)mine;
+            if (tile == num_tiles - 1) list_off[(int64_t)num_images * NL + lane] = (int64_t)(mine + agg);
+        }
+    }
+    __syncthreads();
+    emit_points<N>(tv, s_cnt, s_base, points, capacity);
+}
+
+// Three passes, for plans with more tiles than the chip holds at once (no
+// workgroup ever waits on another): count each tile's entries per list,
+// scan the counts in tile order, then classify again and write.
+template <int N, int CONS, typename T>
+__global__ void __launch_bounds__(kPrecomputeThreads)
+tile_count_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
+                  const int64_t* __restrict__ tile_start, int32_t num_images, int32_t* __restrict__ counts) {
+    constexpr int NL = TileValues<N>::NL;
+    __shared__ int32_t s_cnt[kVertsPerThread][kPrecomputeThreads / 64][NL];
+    const int64_t tile = blockIdx.x;
+    TileValues<N> tv;
+    tile_values<N, CONS, T>(pixels, descs, tile_start, num_images, tile, tv, s_cnt);
+    __syncthreads();
+    if ((threadIdx.x >> 6) == 0) {
+        const uint64_t agg = tile_offsets<NL>(s_cnt);
+        if (threadIdx.x < NL) counts[tile * NL + threadIdx.x] = (int32_t)agg;
+    }
+}
+
+// Exclusive prefix of the tile counts of every list in tile order (64-bit),
+// in three coalesced launches over blocks of kScanTiles tiles: block sums,
+// one workgroup scanning the block sums, and per-block scans that add the
+// block's base, write the prefixes and the list offsets of the images whose
+// first tile lies in the block.
+constexpr int kScanTiles = 1024;
+
+// Inclusive scan over a 1024-thread workgroup of one value per thread and
+// channel (wave shuffles, then the 16 wave totals); returns the total.
+template <int NL>
+__device__ __forceinline__ void block_scan_channels(int64_t (&v)[NL], int64_t (&total)[NL],
+                                                    int64_t (*s_w)[NL]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t o = __shfl_up(v[l], off, 64);
+            if (lane >= off) v[l] += o;
+        }
+        if (lane == 63) s_w[wave][l] = v[l];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        int64_t before = 0, all = 0;
+        for (int w = 0; w < 16; ++w) {
+            const int64_t x = s_w[w][l];
+            if (w < wave) before += x;
+            all += x;
+        }
+        v[l] += before;
+        total[l] = all;
+    }
+    __syncthreads();
+}
+
+template <int NL>
+__global__ void __launch_bounds__(1024)
+tile_block_sum_kernel(const int32_t* __restrict__ counts, int64_t num_tiles, int64_t* __restrict__ blk) {
+    __shared__ int64_t s_w[16][NL];
+    const int64_t t = (int64_t)blockIdx.x * kScanTiles + threadIdx.x;
+    int64_t v[NL], tot[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) v[l] = t < num_tiles ? counts[t * NL + l] : 0;
+    block_scan_channels<NL>(v, tot, s_w);
+    if (threadIdx.x < NL) {
+        int64_t mine = 0;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) if ((int)threadIdx.x == l) mine = tot[l];
+        blk[(int64_t)blockIdx.x * NL + threadIdx.x] = mine;
+    }
+}
+
+// One workgroup: exclusive scan of the block sums, in place; the grand totals
+// close the list offsets.
+template <int NL>
+__global__ void __launch_bounds__(1024)
+tile_block_scan_kernel(int64_t* __restrict__ blk, int64_t nblk, int32_t num_images, int64_t* __restrict__ list_off) {
+    __shared__ int64_t s_w[16][NL];
+    int64_t carry[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) carry[l] = 0;
+    for (int64_t base = 0; base < nblk; base += 1024) {
+        const int64_t b = base + threadIdx.x;
+        int64_t v[NL], x[NL], tot[NL];
+#pragma unroll
+        for (int l = 0; l < NL; ++l) x[l] = v[l] = b < nblk ? blk[b * NL + l] : 0;
+        block_scan_channels<NL>(v, tot, s_w);
+        if (b < nblk)
+#pragma unroll
+            for (int l = 0; l < NL; ++l) blk[b * NL + l] = carry[l] + v[l] - x[l];
+#pragma unroll
+        for (int l = 0; l < NL; ++l) carry[l] += tot[l];
+    }
+    if (threadIdx.x < NL) {
+        int64_t mine = 0;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) if ((int)threadIdx.x == l) mine = carry[l];
+        list_off[(int64_t)num_images * NL + threadIdx.x] = mine;
+    }
+}
+
+template <int NL>
+__global__ void __launch_bounds__(1024)
+tile_block_apply_kernel(const int32_t* __restrict__ counts, int64_t num_tiles, const int64_t* __restrict__ blk,
+                        const int64_t* __restrict__ tile_start, int32_t num_images, int64_t* __restrict__ prefix,
+                        int64_t* __restrict__ list_off) {
+    __shared__ int64_t s_w[16][NL];
+    __shared__ int64_t s_pref[kScanTiles][NL];
+    const int64_t t0 = (int64_t)blockIdx.x * kScanTiles;
+    const int64_t t = t0 + threadIdx.x;
+    int64_t v[NL], x[NL], tot[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) x[l] = v[l] = t < num_tiles ? counts[t * NL + l] : 0;
+    block_scan_channels<NL>(v, tot, s_w);
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        const int64_t p = blk[(int64_t)blockIdx.x * NL + l] + v[l] - x[l];
+        s_pref[threadIdx.x][l] = p;
+        if (t < num_tiles) prefix[t * NL + l] = p;
+    }
+    __syncthreads();
+    // images whose first tile lies in this block: the first one by binary
+    // search, then consecutive images
+    int lo = 0, hi = num_images;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_start[mid] < t0) lo = mid + 1; else hi = mid;
+    }
+    for (int i = lo + (int)threadIdx.x; i < num_images; i += 1024) {
+        const int64_t ts = tile_start[i];
+        if (ts >= t0 + kScanTiles) break;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) list_off[(int64_t)i * NL + l] = s_pref[ts - t0][l];
+    }
+}
+
+template <int N, int CONS, typename T>
+__global__ void __launch_bounds__(kPrecomputeThreads)
+tile_write_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
+                  const int64_t* __restrict__ tile_start, int32_t num_images, const int64_t* __restrict__ prefix,
+                  Point* __restrict__ points, int64_t capacity) {
+    constexpr int NL = TileValues<N>::NL;
+    __shared__ int32_t s_cnt[kVertsPerThread][kPrecomputeThreads / 64][NL];
+    __shared__ int64_t s_base[NL];
+    const int64_t tile = blockIdx.x;
+    TileValues<N> tv;
+    tile_values<N, CONS, T>(pixels, descs, tile_start, num_images, tile, tv, s_cnt);
+    if (threadIdx.x < NL) s_base[threadIdx.x] = prefix[tile * NL + threadIdx.x];
+    __syncthreads();
+    if ((threadIdx.x >> 6) == 0) tile_offsets<NL>(s_cnt);
+    __syncthreads();
+    emit_points<N>(tv, s_cnt, s_base, points, capacity);
+}
+
 template <int N, int CONS, typename T>
 hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream) {
     const PlanLayout& L = p.lay;
+    const int NL = num_lists(N);
     uint32_t* err = (uint32_t*)(p.ws + L.err);
-    uint64_t* ticket = (uint64_t*)(p.ws + L.err + 8);
+    uint64_t* run_ctr = (uint64_t*)(p.ws + L.err + 8);
     uint64_t* status = (uint64_t*)(p.ws + L.status);
-    uint64_t* gstatus = status + L.num_tiles * num_lists(N);   // group totals of the two-level scan
-    const int64_t nstatus = (L.num_tiles + (L.num_tiles + 63) / 64) * num_lists(N);
+    uint64_t* gstatus = status + L.num_tiles * NL;   // [ceil(tiles / 64)][NL] group totals
+    const int64_t nstatus = (L.num_tiles + (L.num_tiles + 63) / 64) * NL;
+    const bool single = L.num_tiles <= p.precompute_grid;
     hipError_t e = hipSuccess;
-    if (first) {
+    if (first && single) {
         int rblocks = (int)std::min<int64_t>((nstatus + 255) / 256 + 1, 4096);
-        hipLaunchKernelGGL(reset_kernel, dim3(rblocks), dim3(256), 0, stream, err, ticket, status, nstatus);
+        hipLaunchKernelGGL(reset_kernel, dim3(rblocks), dim3(256), 0, stream, err, run_ctr, status, nstatus);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     e = stage_mark(ECT_STAGE_PRECOMPUTE, false, stream);
     if (e != hipSuccess) return e;
-    if (p.precompute_resident < 0) {
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, classify_compact<N, CONS, T>, kPrecomputeThreads,
-                                                         0) != hipSuccess)
-            per_cu = 0;
-        // the two-level scan covers 64 groups of 64 tiles
-        p.precompute_resident = ((int64_t)per_cu * p.num_cus >= L.num_tiles && L.num_tiles <= 64 * 64) ? 1 : 0;
+    const T* px = (const T*)p.pixels;
+    const ImageDesc* desc = (const ImageDesc*)(p.ws + L.desc);
+    const int64_t* ts = (const int64_t*)(p.ws + L.tile_start);
+    int64_t* lo = (int64_t*)(p.ws + L.list_off);
+    Point* pts = (Point*)(p.ws + L.points);
+    if (single) {
+        hipLaunchKernelGGL((classify_compact<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads), 0,
+                           stream, px, desc, ts, p.num_images, L.num_tiles, err, run_ctr, status, gstatus, lo, pts,
+                           L.capacity);
+    } else {
+        // the status region holds the counts (int32), the prefixes (int64) and
+        // the block sums (int64)
+        int32_t* counts = (int32_t*)status;
+        int64_t* prefix = (int64_t*)(p.ws + L.status) + (L.num_tiles * NL + 1) / 2;
+        int64_t* blk = prefix + L.num_tiles * NL;
+        const int64_t nblk = (L.num_tiles + kScanTiles - 1) / kScanTiles;
+        if (first) {
+            // first use of the error word by this plan
+            hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, stream, err, run_ctr, status, (int64_t)0);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL((tile_count_kernel<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads), 0,
+                           stream, px, desc, ts, p.num_images, counts);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        constexpr int NLc = TileValues<N>::NL;
+        hipLaunchKernelGGL(tile_block_sum_kernel<NLc>, dim3((unsigned)nblk), dim3(1024), 0, stream, counts,
+                           L.num_tiles, blk);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(tile_block_scan_kernel<NLc>, dim3(1), dim3(1024), 0, stream, blk, nblk, p.num_images, lo);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(tile_block_apply_kernel<NLc>, dim3((unsigned)nblk), dim3(1024), 0, stream, counts,
+                           L.num_tiles, blk, ts, p.num_images, prefix, lo);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((tile_write_kernel<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads), 0,
+                           stream, px, desc, ts, p.num_images, prefix, pts, L.capacity);
     }
-    hipLaunchKernelGGL((classify_compact<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads),
-                       0, stream, (const T*)p.pixels, (const ImageDesc*)(p.ws + L.desc),
-                       (const int64_t*)(p.ws + L.tile_start), p.num_images, L.num_tiles, err, ticket, status, gstatus,
-                       (int64_t*)(p.ws + L.list_off), (Point*)(p.ws + L.points), L.capacity,
-                       (int)p.precompute_resident);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return stage_mark(ECT_STAGE_PRECOMPUTE, true, stream);
+}
+
+template <int N, int CONS, typename T>
+int64_t slots_typed() {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, classify_compact<N, CONS, T>, kPrecomputeThreads, 0) !=
+        hipSuccess)
+        return 0;
+    return per_cu;
 }
 
 template <int N, int CONS>
@@ -520,6 +647,23 @@ hipError_t launch_dtype(const Plan& p, bool first, hipStream_t s) {
 }
 
 }  // namespace
+
+int64_t precompute_slots_per_cu(int ndim, int construction, int dtype) {
+    auto pick = [&](auto n, auto c) -> int64_t {
+        constexpr int N = decltype(n)::value, C = decltype(c)::value;
+        switch (dtype) {
+            case ECT_U8: return slots_typed<N, C, uint8_t>();
+            case ECT_I16: return slots_typed<N, C, int16_t>();
+            default: return slots_typed<N, C, int32_t>();
+        }
+    };
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    using P = std::integral_constant<int, ECT_PRIMAL>;
+    using Du = std::integral_constant<int, ECT_DUAL>;
+    if (ndim == 2) return construction == ECT_PRIMAL ? pick(I2{}, P{}) : pick(I2{}, Du{});
+    return construction == ECT_PRIMAL ? pick(I3{}, P{}) : pick(I3{}, Du{});
+}
 
 hipError_t launch_precompute(const Plan& p, bool first, hipStream_t stream) {
     if (p.ndim == 2)
