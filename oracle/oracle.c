@@ -621,3 +621,89 @@ void oracle_ji0_array(long long n, const double* z, double* out) {
     for (long long i = 0; i < n; ++i) out[i] = ji0_eval(&tb, z[i]);
     free(tb.cum);
 }
+
+/* Radon transform R(xi_d, t_j) = chi of the slice {<xi_d, .> = t_j} (Sec. 2.2),
+ * for every direction d and threshold j (int32 out[d][j]).  Written out from
+ * the cells: a cell whose vertices all project to t lies in the slice and
+ * contributes (-1)^dim phi (every vertex does at its projection, and so does a
+ * cell of positive dimension when xi is not generic); a cell of dimension >= 1
+ * with min < t < max over its vertices' projections is cut through its
+ * relative interior, the cut has one dimension less, and it contributes
+ * (-1)^(dim-1) phi.  (At t = min or t = max of a cell with min < max the slice
+ * meets only a proper face, which is a cell of its own.)  Thresholds must be
+ * non-decreasing; the open-interval contributions go through a difference
+ * array over threshold indices. */
+int oracle_radon(int n, const int32_t* dims, const int32_t* px, int construction,
+                 const double* origin, const double* spacing,
+                 int ndirs, const double* dirs, int M, const double* thr, int32_t* out) {
+    ogrid g;
+    if (grid_init(&g, n, dims, construction, origin, spacing) || M < 1) return 1;
+    for (int j = 1; j < M; ++j) if (!(thr[j] >= thr[j - 1])) return 2;
+    cellset cs;
+    if (cellset_build(&g, px, construction, 0, &cs)) return 3;
+    double* x = vertex_coords(&g);
+    if (!x) { cellset_free(&cs); return 3; }
+    int err = 0;
+#pragma omp parallel
+    {
+        double* u = (double*)malloc(sizeof(double) * g.nvert);
+        long long* diff = (long long*)malloc(sizeof(long long) * (M + 1));
+        long long* point = (long long*)malloc(sizeof(long long) * M);
+        if (!u || !diff || !point) {
+#pragma omp atomic write
+            err = 3;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (int d = 0; d < ndirs; ++d) {
+                const double* xi = dirs + (long long)d * n;
+                for (long long v = 0; v < g.nvert; ++v) u[v] = project(n, xi, x + v * MAXD);
+                memset(diff, 0, sizeof(long long) * (M + 1));
+                memset(point, 0, sizeof(long long) * M);
+                for (long long i = 0; i < cs.count; ++i) {
+                    double lo = u[cs.verts[i * 8]], hi = lo;
+                    for (int q = 1; q < cs.nv[i]; ++q) {
+                        const double w = u[cs.verts[i * 8 + q]];
+                        if (w < lo) lo = w;
+                        if (w > hi) hi = w;
+                    }
+                    if (lo == hi) {   /* the whole cell lies in the slice at t = lo */
+                        const long long c = (cs.dim[i] & 1) ? -(long long)cs.value[i] : (long long)cs.value[i];
+                        for (int j = first_threshold_at_or_above(thr, M, lo); j < M && thr[j] == lo; ++j)
+                            point[j] += c;
+                        continue;
+                    }
+                    /* thresholds with lo < t < hi: indices [j0, j1) */
+                    int j0 = first_threshold_at_or_above(thr, M, lo);
+                    while (j0 < M && thr[j0] == lo) ++j0;
+                    const int j1 = first_threshold_at_or_above(thr, M, hi);
+                    if (j0 >= j1) continue;
+                    const long long s = (cs.dim[i] & 1) ? (long long)cs.value[i] : -(long long)cs.value[i];
+                    diff[j0] += s;
+                    diff[j1] -= s;
+                }
+                long long run = 0;
+                for (int j = 0; j < M; ++j) {
+                    run += diff[j];
+                    out[(long long)d * M + j] = (int32_t)(run + point[j]);
+                }
+            }
+        }
+        free(u); free(diff); free(point);
+    }
+    free(x);
+    cellset_free(&cs);
+    return err;
+}
+
+/* Canonical FP64 projections <xi, x_v> of every vertex (the expression the
+ * ECT is defined with), in linear vertex order. */
+int oracle_vertex_projections(int n, const int32_t* dims, int construction, const double* origin,
+                              const double* spacing, const double* xi, double* out) {
+    ogrid g;
+    if (grid_init(&g, n, dims, construction, origin, spacing)) return 1;
+    double* x = vertex_coords(&g);
+    if (!x) return 3;
+    for (long long v = 0; v < g.nvert; ++v) out[v] = project(n, xi, x + v * MAXD);
+    free(x);
+    return 0;
+}

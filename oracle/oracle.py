@@ -167,6 +167,108 @@ def ect(img, dirs, thresholds, construction=PRIMAL, origin=None, spacing=None) -
     return out
 
 
+def radon(img, dirs, thresholds, construction=PRIMAL, origin=None, spacing=None) -> np.ndarray:
+    """R(xi, t) = chi of the slice {<xi,.> = t} from the cells (Sec. 2.2), int32 [dirs][thresholds]."""
+    img = np.asarray(img)
+    n = img.ndim
+    dims, dp = _i32(_dims(img))
+    px, pp = _i32(img)
+    dirs, dirp = _f64(np.asarray(dirs, dtype=np.float64).reshape(-1, n))
+    thr, tp = _f64(thresholds)
+    org, op = _f64(origin)
+    spc, sp = _f64(spacing)
+    out = np.zeros((dirs.shape[0], thr.shape[0]), dtype=np.int32)
+    rc = lib().oracle_radon(n, dp, pp, construction, op, sp, dirs.shape[0], dirp, thr.shape[0], tp,
+                            out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    if rc:
+        raise ValueError(f"oracle_radon failed ({rc})")
+    return out
+
+
+def vertex_projections(img, xi, construction=PRIMAL, origin=None, spacing=None) -> np.ndarray:
+    """Canonical FP64 projections of every vertex on xi, in linear vertex order."""
+    img = np.asarray(img)
+    n = img.ndim
+    dims, dp = _i32(_dims(img))
+    xi, xp = _f64(np.asarray(xi, dtype=np.float64).reshape(n))
+    org, op = _f64(origin)
+    spc, sp = _f64(spacing)
+    nv = int(np.prod(vertex_shape(img, construction)))
+    out = np.zeros(nv, dtype=np.float64)
+    rc = lib().oracle_vertex_projections(n, dp, construction, op, sp, xp,
+                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc:
+        raise ValueError(f"oracle_vertex_projections failed ({rc})")
+    return out
+
+
+def _sign_index(xi):
+    return sum(1 << a for a in range(len(xi)) if not (xi[a] >= 0.0))
+
+
+def _sorted_jumps(u, vals):
+    """Distinct values of u in ascending order and the sum of vals at each."""
+    order = np.argsort(u, kind="stable")
+    us, vs = u[order], vals[order].astype(np.int64)
+    if us.size == 0:
+        return us, vs
+    head = np.ones(us.size, dtype=bool)
+    head[1:] = us[1:] != us[:-1]
+    starts = np.nonzero(head)[0]
+    return us[starts], np.add.reduceat(vs, starts)
+
+
+def ect_exact(img, xi, construction=PRIMAL, origin=None, spacing=None):
+    """Exact ECT(xi, .) as (T, E) (Sec. 4.3): T = [-inf] + the sorted distinct projections of the
+    classical critical points of eps(xi), E = [0] + the cumulative sums of their critical values
+    (equal projections merged), so that ECT(xi, t) = E[i] for the largest T[i] <= t."""
+    xi = np.asarray(xi, dtype=np.float64)
+    lw, _ = critical_values(img, construction)
+    D = lw[:, _sign_index(xi)]
+    nz = np.nonzero(D)[0]
+    u = vertex_projections(img, xi, construction, origin, spacing)[nz]
+    t, v = _sorted_jumps(u, D[nz])
+    return np.concatenate([[-np.inf], t]), np.concatenate([[0], np.cumsum(v)]).astype(np.int64)
+
+
+def radon_exact(img, xi, construction=PRIMAL, origin=None, spacing=None):
+    """Exact R(xi, .) as (T, E', Tc, Ec) (Sec. 4.3) with the sign the definition gives:
+    R = sum over classical points of Delta^- 1_{u} - sum over ordinary points of D 1_(u, inf).
+    T, E': [-inf] + sorted distinct ordinary projections and the cumulative sums of -D;
+    Tc: sorted distinct classical projections; Ec[i] = E'[i0] + the classical values at Tc[i],
+    with i0 the largest index such that T[i0] < Tc[i] (the open interval excludes u itself)."""
+    xi = np.asarray(xi, dtype=np.float64)
+    lw, od = critical_values(img, construction)
+    e = _sign_index(xi)
+    u_all = vertex_projections(img, xi, construction, origin, spacing)
+    Do = od[:, e]
+    nzo = np.nonzero(Do)[0]
+    to, vo = _sorted_jumps(u_all[nzo], -Do[nzo])
+    T = np.concatenate([[-np.inf], to])
+    Ep = np.concatenate([[0], np.cumsum(vo)]).astype(np.int64)
+    Dc = lw[:, e]
+    nzc = np.nonzero(Dc)[0]
+    tc, vc = _sorted_jumps(u_all[nzc], Dc[nzc])
+    i0 = np.searchsorted(T, tc, side="left") - 1
+    Ec = Ep[i0] + vc
+    return T, Ep, tc, Ec.astype(np.int64)
+
+
+def eval_ect_exact(T, E, t):
+    """ECT(xi, t) = E[i] for the largest i with T[i] <= t (binary search)."""
+    return E[np.searchsorted(T, np.asarray(t, dtype=np.float64), side="right") - 1]
+
+
+def eval_radon_exact(T, Ep, Tc, Ec, t):
+    """R(xi, t): Ec at a classical projection, else E'[i] for the largest i with T[i] < t."""
+    t = np.atleast_1d(np.asarray(t, dtype=np.float64))
+    out = Ep[np.searchsorted(T, t, side="left") - 1].copy()
+    k = np.searchsorted(Tc, t, side="left")
+    hit = (k < Tc.size) & (Tc[np.minimum(k, max(Tc.size - 1, 0))] == t) if Tc.size else np.zeros(t.size, bool)
+    out[hit] = Ec[k[hit]]
+    return out
+
+
 def hybrid(img, xi, kernel, s=1.0, construction=PRIMAL, origin=None, spacing=None,
            with_shift=False):
     """HT at each xi.  Fourier returns complex; Laplace with_shift returns (HT*exp(-m), m)."""

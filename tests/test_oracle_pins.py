@@ -472,3 +472,88 @@ def test_lemma31_laplace_large_phases_cancellation():
         # Sum2 bound: a relative 1e-12 of the critical-point terms plus a doubled-precision
         # residue (~2^-106) of the O(1) cell terms that cancel at non-critical vertices
         assert abs(out[q] - ref) <= 1e-12 * scale + 1e-28, (q, out[q], ref, scale)
+
+
+# ----------------------------------------------------------------------------
+# Exact representations (Sec. 4.3) and the Radon transform (Sec. 2.2)
+# ----------------------------------------------------------------------------
+
+def test_example_ect_exact_pairs():
+    """(T, E) of the example at xi = (2,2): jumps at the printed T, values E (merging the two points
+    that share -2/3)."""
+    d, img = _example()
+    o, h = _paper_coords(img)
+    rep = d["ect_exact_representation"]
+    T, E = O.ect_exact(img, np.array(d["xi"]), O.DUAL, o, h)
+    assert T[0] == -np.inf and E.tolist() == rep["E"]
+    assert np.allclose(T[1:], rep["T_printed"], atol=rep["print_precision"])
+
+
+def test_example_radon_exact_ordinary_jumps():
+    """The ordinary jumps of the example's Radon transform sit where the paper prints them; the
+    values carry the sign the definition gives (the negated E' of the printed example), and the
+    point values at the classical projections agree with the slice Euler characteristic."""
+    d, img = _example()
+    o, h = _paper_coords(img)
+    xi = np.array(d["xi"])
+    T, Ep, Tc, Ec = O.radon_exact(img, xi, O.DUAL, o, h)
+    assert np.allclose(T[1:], [-2.0 / 3.0, 2.0 / 3.0, 4.0 / 3.0], atol=1e-12)
+    assert Ep.tolist() == [0, 2, 1, 0]
+    assert np.allclose(Tc, [-2.0, -2.0 / 3.0, 0.0], atol=1e-12)
+    assert Ec.tolist() == O.radon(img, xi[None], Tc, O.DUAL, o, h)[0].tolist()
+
+
+def _tie_thresholds(img, xi, construction, origin=None, spacing=None, extra=0, rng=None):
+    u = O.vertex_projections(img, xi, construction, origin, spacing)
+    t = np.unique(u)
+    if extra:
+        t = np.concatenate([t, rng.uniform(t.min() - 1, t.max() + 1, extra)])
+    mids = (t[1:] + t[:-1]) / 2 if t.size > 1 else t
+    return np.sort(np.concatenate([t, mids]))
+
+
+@pytest.mark.parametrize("construction", [O.PRIMAL, O.DUAL])
+def test_radon_identity_with_ect_at_every_tie(construction):
+    """R(xi,t) = ECT(xi,t) + ECT(-xi,-t) - chi holds at every t, ties included (a vertex at t is in
+    both closed sublevel sets; a cell with min < t < max is in neither)."""
+    rng = np.random.default_rng(71)
+    for shape in [(5, 6), (4, 3, 5)]:
+        img = W.random_image(rng, shape, 4)
+        chi = O.euler_characteristic(img, construction)
+        n = img.ndim
+        dirs = [rng.standard_normal(n), np.eye(n)[0], -np.eye(n)[n - 1], np.round(rng.standard_normal(n) * 2) / 2]
+        for xi in dirs:
+            t = _tie_thresholds(img, xi, construction, extra=7, rng=rng)
+            r = O.radon(img, xi[None], t, construction)[0].astype(np.int64)
+            e1 = O.ect(img, xi[None], t, construction)[0].astype(np.int64)
+            e2 = O.ect(img, -xi[None], -t[::-1], construction)[0][::-1].astype(np.int64)
+            assert np.array_equal(r, e1 + e2 - chi), (shape, xi)
+
+
+def test_radon_closed_square_and_reflection():
+    """One pixel of value 3 (primal): the slice of the closed square has chi 1 on [min, max], 0 off
+    it; R(-xi, -t) = R(xi, t)."""
+    img = np.array([[3]], dtype=np.int32)
+    xi = np.array([0.7, -1.3])
+    corners = [np.dot(xi, [a, b]) for a in (-0.5, 0.5) for b in (-0.5, 0.5)]
+    lo, hi = min(corners), max(corners)
+    t = np.array([lo - 1, lo, (lo + hi) / 2, hi, hi + 0.25])
+    assert O.radon(img, xi[None], t)[0].tolist() == [0, 3, 3, 3, 0]
+    assert O.radon(img, -xi[None], -t[::-1])[0].tolist() == [0, 3, 3, 3, 0][::-1]
+
+
+@pytest.mark.parametrize("construction", [O.PRIMAL, O.DUAL])
+def test_exact_representations_evaluate_to_the_transforms(construction):
+    """(T, E) evaluated by binary search equals the ECT of the cells, and (T, E', Tc, Ec) equals the
+    Radon transform of the cells, at every tie and between them."""
+    rng = np.random.default_rng(72)
+    for shape in [(6, 7), (3, 4, 4)]:
+        img = W.random_image(rng, shape, 5)
+        n = img.ndim
+        for xi in [rng.standard_normal(n), np.eye(n)[1] * -1.0, np.full(n, 0.5)]:
+            t = _tie_thresholds(img, xi, construction, extra=5, rng=rng)
+            T, E = O.ect_exact(img, xi, construction)
+            assert np.array_equal(O.eval_ect_exact(T, E, t), O.ect(img, xi[None], t, construction)[0])
+            rep = O.radon_exact(img, xi, construction)
+            assert np.array_equal(O.eval_radon_exact(*rep, t), O.radon(img, xi[None], t, construction)[0])
+            assert np.all(np.diff(T) > 0) and np.all(np.diff(rep[2]) > 0)
