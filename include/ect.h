@@ -163,6 +163,18 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
                     int32_t thresholds_per_image, int32_t* out, void* ws, size_t* ws_bytes,
                     hipStream_t stream);
 
+/* radon_eval -- the Radon transform R(xi, t_j) = chi of the slice {<xi,.> = t_j}
+ * (Sec. 2.2) at every direction of `dirs` and every threshold, from the
+ * critical points (Lemma 3.1, with the sign the definition gives):
+ *   R(xi, t) = sum over classical points of Delta^-(eps,x) [<xi,x> = t]
+ *            - sum over ordinary points of D(eps,x) [<xi,x> < t],
+ * with the canonical FP64 projection, so the integer result equals the slice
+ * Euler characteristic of the cells exactly, ties included.  Arguments,
+ * layout, workspace and errors as ect_eval. */
+ect_status radon_eval(ect_plan plan, ect_query_set dirs, const double* thresholds, int32_t M,
+                      int32_t thresholds_per_image, int32_t* out, void* ws, size_t* ws_bytes,
+                      hipStream_t stream);
+
 /* hybrid_eval -- HT(xi) = integral kappa_s(t) R(xi,t) dt (Sec. 2.2), evaluated
  * as the sum over ordinary critical points of Delta^ord(eps,x) kbar_s(<xi,x>)
  * (Lemma 3.1 with the sign that the definition gives).

@@ -448,11 +448,13 @@ def critical_values_literal(img, construction=PRIMAL, generic=None):
 
 
 def radon_from_ect(img, xi, t, construction=PRIMAL, origin=None, spacing=None):
-    """R(xi,t) = ECT(xi,t) + ECT(-xi,-t) - chi (valid when t is not a vertex projection).
+    """R(xi,t) = ECT(xi,t) + ECT(-xi,-t) - chi, at every t (ties included).
 
     {xi = t} = {xi <= t} minus the open set {xi < t}; the open sublevel set of xi
     at t is the complement of the closed sublevel set of -xi at -t, and chi is
-    additive over this partition of the cells' relative interiors.
+    additive over this partition of the cells' relative interiors.  The canonical
+    projection on -xi is exactly the negated projection on xi, so a vertex at t
+    lies in both closed sublevel sets.
     """
     xi = np.asarray(xi, float)
     e1 = ect(img, xi[None], np.array([t]), construction, origin, spacing)[0, 0]

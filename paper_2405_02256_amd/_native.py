@@ -64,6 +64,7 @@ def lib():
     L.ect_precompute.argtypes = [P(ImageBatch), c_vp, P(ctypes.c_size_t), c_vp, P(c_vp)]
     L.ect_plan_rerun.argtypes = [c_vp, c_vp]
     L.ect_eval.argtypes = [c_vp, QuerySet, c_vp, c_i32, c_i32, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
+    L.radon_eval.argtypes = [c_vp, QuerySet, c_vp, c_i32, c_i32, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
     L.hybrid_eval.argtypes = [c_vp, c_i32, c_f64, c_i32, QuerySet, c_vp, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
     L.hybrid_eval_multi.argtypes = [c_vp, c_u32, c_f64, c_i32, QuerySet, c_vp, c_vp, c_vp, c_vp, c_vp,
                                     P(ctypes.c_size_t), c_vp]
@@ -75,7 +76,7 @@ def lib():
     L.ect_plan_destroy.argtypes = [c_vp]
     L.ect_plan_set_tuning.argtypes = [c_vp, c_i64, c_i64, c_i32, c_i32]
     L.ect_set_stage_events.argtypes = [c_i32, c_vp, c_vp]
-    for name in ("ect_precompute", "ect_plan_rerun", "ect_eval", "hybrid_eval", "hybrid_eval_multi",
+    for name in ("ect_precompute", "ect_plan_rerun", "ect_eval", "radon_eval", "hybrid_eval", "hybrid_eval_multi",
                  "hybrid_eval_backward",
                  "ect_plan_counts", "ect_plan_export", "ect_plan_check", "ect_plan_destroy", "ect_plan_set_tuning",
                  "ect_set_stage_events"):
@@ -112,6 +113,11 @@ def ect_plan_rerun(plan: int, stream: int) -> int:
 def ect_eval(plan, dirs: QuerySet, thresholds, M, per_image, out, ws, ws_bytes: ctypes.c_size_t, stream) -> int:
     return lib().ect_eval(c_vp(plan), dirs, c_vp(thresholds), int(M), int(per_image), c_vp(out), ws,
                           ctypes.byref(ws_bytes), c_vp(stream))
+
+
+def radon_eval(plan, dirs: QuerySet, thresholds, M, per_image, out, ws, ws_bytes: ctypes.c_size_t, stream) -> int:
+    return lib().radon_eval(c_vp(plan), dirs, c_vp(thresholds), int(M), int(per_image), c_vp(out), ws,
+                            ctypes.byref(ws_bytes), c_vp(stream))
 
 
 def hybrid_eval(plan, kernel, s, precision, xi: QuerySet, out, log_scale, ws, ws_bytes: ctypes.c_size_t,

@@ -174,6 +174,14 @@ class Plan:
     # -- evaluation ---------------------------------------------------------
     def ect(self, dirs, thresholds: torch.Tensor, offsets=None, out=None, stream=None, slot: str = "main") -> torch.Tensor:
         """int32 [rows][M]: ECT at every direction and threshold (thresholds [M] or [num_images][M])."""
+        return self._thresholds(N.ect_eval, "ect_eval", dirs, thresholds, offsets, out, stream, slot)
+
+    def radon(self, dirs, thresholds: torch.Tensor, offsets=None, out=None, stream=None,
+              slot: str = "main") -> torch.Tensor:
+        """int32 [rows][M]: Radon transform (slice Euler characteristic) at every direction and threshold."""
+        return self._thresholds(N.radon_eval, "radon_eval", dirs, thresholds, offsets, out, stream, slot)
+
+    def _thresholds(self, fn, name, dirs, thresholds, offsets, out, stream, slot):
         q = dirs if isinstance(dirs, QuerySet) else QuerySet(dirs, offsets)
         q.validate(self.num_images, self.ndim)
         thr = thresholds.to(device=self.device, dtype=torch.float64).contiguous()
@@ -186,11 +194,11 @@ class Plan:
             out = torch.empty((rows, M), dtype=torch.int32, device=self.device)
         st = _stream(stream)
         need = ctypes.c_size_t(0)
-        N.check(N.ect_eval(self.handle, q.c(), _dptr(thr), M, per_image, _dptr(out), None, need, st), "ect_eval(size)")
+        N.check(fn(self.handle, q.c(), _dptr(thr), M, per_image, _dptr(out), None, need, st), name + "(size)")
         ws = self._ws(need.value, slot)
         have = ctypes.c_size_t(ws.numel())
-        N.check(N.ect_eval(self.handle, q.c(), _dptr(thr), M, per_image, _dptr(out),
-                           ctypes.c_void_p(_dptr(ws)), have, st), "ect_eval")
+        N.check(fn(self.handle, q.c(), _dptr(thr), M, per_image, _dptr(out), ctypes.c_void_p(_dptr(ws)), have, st),
+                name)
         return out
 
     def hybrid(self, xi, kernel: str = "fourier", s: float = 1.0, precision: str = "fp32", offsets=None,

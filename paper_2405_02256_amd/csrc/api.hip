@@ -264,8 +264,9 @@ ect_status ect_plan_rerun(ect_plan plan, hipStream_t stream) {
     return from_hip(launch_precompute(*plan, false, stream));
 }
 
-ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds, int32_t M,
-                    int32_t thresholds_per_image, int32_t* out, void* ws, size_t* ws_bytes, hipStream_t stream) {
+static ect_status threshold_eval(ect_plan plan, ect_query_set dirs, const double* thresholds, int32_t M,
+                                 int32_t thresholds_per_image, int32_t* out, void* ws, size_t* ws_bytes,
+                                 hipStream_t stream, bool radon) {
     if (!plan || !ws_bytes) return ECT_E_INVALID;
     if (!valid_query_set(dirs, plan->num_images) || !thresholds || !out) return ECT_E_INVALID;
     if (M < 1) return ECT_E_INVALID;
@@ -279,7 +280,8 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
                  : (dirs.offsets == nullptr ? kEctMaxDirs
                                             : (int)std::min<int64_t>(kEctMaxDirs, std::max<int64_t>(1, nrows / 1024)));
     const int64_t lds_budget = 60 * 1024;
-    td = (int)std::min<int64_t>(td, (lds_budget - 8 * (int64_t)M) / (4 * (int64_t)M));
+    const int64_t arrays = radon ? 2 : 1;   // histograms (+ Radon point values) per direction
+    td = (int)std::min<int64_t>(td, (lds_budget - 8 * (int64_t)M) / (4 * arrays * (int64_t)M));
     td = std::max(1, std::min(td, kEctMaxDirs));
     // shared sets go straight to the evaluation kernel (no bucketing); long
     // lists are split into chunks so that enough workgroups share each group
@@ -292,7 +294,7 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
         const int64_t groups = (int64_t)p.num_images * ((dirs.count + td - 1) / td);
         const double avg = mean_list(p, 0, num_classical(p.ndim));
         const int64_t want = (2 * (int64_t)std::max(p.num_cus, 1) + groups - 1) / std::max<int64_t>(groups, 1);
-        chunks = p.tune_ect_chunks > 0 ? p.tune_ect_chunks
+        chunks = radon ? 1 : p.tune_ect_chunks > 0 ? p.tune_ect_chunks
                                        : std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)(avg / 16384.0)));
         if (chunks > 1) L.total = sizeof(int32_t) * (size_t)(groups * chunks * td * (int64_t)M);
     } else {
@@ -341,9 +343,19 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
         a.dirs_per_group = td;
         a.chunks = chunks;
         a.part = chunks > 1 ? (int32_t*)w : nullptr;
-        e = launch_ect(p.ndim, a, L.grid, direct_groups, stream);
+        e = launch_ect(p.ndim, a, L.grid, direct_groups, radon, stream);
     }
     return from_hip(e);
+}
+
+ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds, int32_t M,
+                    int32_t thresholds_per_image, int32_t* out, void* ws, size_t* ws_bytes, hipStream_t stream) {
+    return threshold_eval(plan, dirs, thresholds, M, thresholds_per_image, out, ws, ws_bytes, stream, false);
+}
+
+ect_status radon_eval(ect_plan plan, ect_query_set dirs, const double* thresholds, int32_t M,
+                      int32_t thresholds_per_image, int32_t* out, void* ws, size_t* ws_bytes, hipStream_t stream) {
+    return threshold_eval(plan, dirs, thresholds, M, thresholds_per_image, out, ws, ws_bytes, stream, true);
 }
 
 static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t precision, ect_query_set xi,

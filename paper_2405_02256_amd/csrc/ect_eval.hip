@@ -10,6 +10,14 @@
 // is the ECT row (the vectorization of Sec. 4.3 and Appendix A, at arbitrary
 // non-decreasing thresholds).
 //
+// The Radon transform at thresholds uses the same kernels (RADON = true): by
+// Lemma 3.1 with the sign the definition gives, R(xi, t) = sum over classical
+// points of Delta^-(eps, x) [<xi,x> = t] - sum over ordinary points of
+// D(eps, x) [<xi,x> < t], so the classical list feeds a per-threshold point
+// array (no prefix sum) and the ordinary list of the orthant pair (negated for
+// the mirrored half) a histogram binned at the first threshold above the
+// projection, whose prefix sum is added.
+//
 // Shared query sets (one direction set for every image) are evaluated without
 // a bucketing pass (ect_direct_kernel); ragged sets are bucketed by sign vector
 // first (ect_kernel).
@@ -25,7 +33,8 @@ namespace {
 
 // Stage the thresholds of image img in LDS and clear the histograms; returns
 // nonzero (in every thread) when they are not non-decreasing or not finite.
-__device__ __forceinline__ int stage_thresholds(const EctArgs& a, int64_t img, double* s_thr, int32_t* s_hist) {
+__device__ __forceinline__ int stage_thresholds(const EctArgs& a, int64_t img, double* s_thr, int32_t* s_hist,
+                                                int hist_arrays = 1) {
     const int M = a.M;
     const double* thr = a.thresholds + (a.thr_per_image ? img * M : 0);
     int bad = 0;
@@ -35,16 +44,22 @@ __device__ __forceinline__ int stage_thresholds(const EctArgs& a, int64_t img, d
         if (j > 0 && !(v >= thr[j - 1])) bad = 1;
         if (!isfinite(v)) bad = 1;
     }
-    for (int j = threadIdx.x; j < a.dirs_per_group * M; j += kEctThreads) s_hist[j] = 0;
+    for (int j = threadIdx.x; j < hist_arrays * a.dirs_per_group * M; j += kEctThreads) s_hist[j] = 0;
     return __syncthreads_or(bad);
 }
 
-// Stream points [p0, p1) of one list and add each point's critical value into
-// the histogram of every direction dd with use[dd].
-template <int N>
+// Binning of a projection u against the non-decreasing thresholds:
+//   kBinClosed  the first j with t_j >= u ({xi <= t} contains the point);
+//   kBinOpen    the first j with t_j > u (the open ray (u, inf));
+//   kBinPoint   every j with t_j == u (the point u itself).
+constexpr int kBinClosed = 0, kBinOpen = 1, kBinPoint = 2;
+
+// Stream points [p0, p1) of one list and add sign * (critical value) into the
+// histogram of every direction dd with use[dd].
+template <int N, int MODE>
 __device__ __forceinline__ void accumulate_list(const Point* __restrict__ pts, int64_t p0, int64_t p1,
                                                 const double (&xi)[kEctMaxDirs][N], const bool (&use)[kEctMaxDirs],
-                                                const double* s_thr, int M, int32_t* s_hist) {
+                                                const double* s_thr, int M, int32_t* s_hist, int32_t sign = 1) {
     const double t0 = s_thr[0], t1 = s_thr[M - 1];
     const double inv = (M > 1 && t1 > t0) ? (double)(M - 1) / (t1 - t0) : 0.0;
     // U points per thread are loaded before any is processed, so that their
@@ -60,7 +75,7 @@ __device__ __forceinline__ void accumulate_list(const Point* __restrict__ pts, i
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (p + (int64_t)u * kEctThreads >= p1) break;
-            const int32_t val = (int32_t)pt[u].val;
+            const int32_t val = sign * (int32_t)pt[u].val;
 #pragma unroll
             for (int dd = 0; dd < kEctMaxDirs; ++dd) {
                 if (!use[dd]) continue;
@@ -68,9 +83,17 @@ __device__ __forceinline__ void accumulate_list(const Point* __restrict__ pts, i
                 double g = ceil((uu - t0) * inv);
                 g = fmin(fmax(g, 0.0), (double)M);
                 int j = (int)g;
+                // first j with t_j >= u
                 while (j > 0 && s_thr[j - 1] >= uu) --j;
                 while (j < M && s_thr[j] < uu) ++j;
-                if (j < M) atomicAdd(&s_hist[dd * M + j], val);
+                if constexpr (MODE == kBinClosed) {
+                    if (j < M) atomicAdd(&s_hist[dd * M + j], val);
+                } else if constexpr (MODE == kBinOpen) {
+                    while (j < M && s_thr[j] == uu) ++j;
+                    if (j < M) atomicAdd(&s_hist[dd * M + j], val);
+                } else {
+                    for (; j < M && s_thr[j] == uu; ++j) atomicAdd(&s_hist[dd * M + j], val);
+                }
             }
         }
     }
@@ -79,7 +102,7 @@ __device__ __forceinline__ void accumulate_list(const Point* __restrict__ pts, i
 // Inclusive prefix sum of each histogram into its output row (zeros for an
 // invalid direction); one wave per direction.
 __device__ __forceinline__ void write_rows(const EctArgs& a, int nd, const int64_t* s_row, const int* s_valid,
-                                           const int32_t* s_hist) {
+                                           const int32_t* s_hist, const int32_t* s_point = nullptr) {
     const int M = a.M;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int W = kEctThreads / 64;
@@ -98,10 +121,31 @@ __device__ __forceinline__ void write_rows(const EctArgs& a, int nd, const int64
                 int32_t o = __shfl_up(v, off, 64);
                 if (lane >= off) v += o;
             }
-            if (j < M) out[j] = carry + v;
+            if (j < M) out[j] = carry + v + (s_point ? s_point[dd * M + j] : 0);
             carry += __shfl(v, 63, 64);
         }
     }
+}
+
+// Radon transform: the classical list of eps at the thresholds it hits, the
+// ordinary list of eps's orthant pair (negated when eps is the mirrored half)
+// on the open rays.
+template <int N>
+__device__ __forceinline__ void accumulate_radon(const EctArgs& a, int64_t img, int e, int64_t chunk, int64_t chunks,
+                                                 const double (&xi)[kEctMaxDirs][N], const bool (&use)[kEctMaxDirs],
+                                                 const double* s_thr, int32_t* s_hist, int32_t* s_point) {
+    constexpr int full = (1 << N) - 1;
+    const int M = a.M;
+    const int64_t c0 = a.list_off[img * a.NL + e], c1 = a.list_off[(img + 1) * a.NL + e];
+    const int64_t cl = c1 - c0;
+    accumulate_list<N, kBinPoint>(a.points + (int64_t)e * a.capacity, c0 + cl * chunk / chunks,
+                                  c0 + cl * (chunk + 1) / chunks, xi, use, s_thr, M, s_point);
+    const bool mirrored = (e >> (N - 1)) & 1;
+    const int l = (1 << N) + (mirrored ? (e ^ full) : e);
+    const int64_t o0 = a.list_off[img * a.NL + l], o1 = a.list_off[(img + 1) * a.NL + l];
+    const int64_t ol = o1 - o0;
+    accumulate_list<N, kBinOpen>(a.points + (int64_t)l * a.capacity, o0 + ol * chunk / chunks,
+                                 o0 + ol * (chunk + 1) / chunks, xi, use, s_thr, M, s_hist, mirrored ? 1 : -1);
 }
 
 __device__ __forceinline__ void zero_rows(const EctArgs& a, int nd, const int64_t* s_row) {
@@ -111,7 +155,7 @@ __device__ __forceinline__ void zero_rows(const EctArgs& a, int nd, const int64_
 
 // Bucketed sets (ragged query sets): one workgroup per group of up to
 // dirs_per_group directions of one (image, sign vector) bucket.
-template <int N>
+template <int N, bool RADON>
 __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
     extern __shared__ __align__(16) char smem[];
     constexpr int TD = kEctMaxDirs;
@@ -161,7 +205,8 @@ __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
         s_row[tid] = row;
         s_valid[tid] = ok;
     }
-    if (stage_thresholds(a, img, s_thr, s_hist)) {
+    int32_t* s_point = s_hist + (int64_t)a.dirs_per_group * M;   // Radon point values
+    if (stage_thresholds(a, img, s_thr, s_hist, RADON ? 2 : 1)) {
         if (tid == 0) raise_error(a.err, ECT_DEVERR_THRESHOLDS);
         zero_rows(a, nd, s_row);
         return;
@@ -174,10 +219,14 @@ __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
 #pragma unroll
         for (int c = 0; c < N; ++c) xi[dd][c] = s_xi[dd][c];
     }
-    const int64_t p0 = a.list_off[img * a.NL + b], p1 = a.list_off[(img + 1) * a.NL + b];
-    accumulate_list<N>(a.points + (int64_t)b * a.capacity, p0, p1, xi, use, s_thr, M, s_hist);
+    if constexpr (RADON) {
+        accumulate_radon<N>(a, img, b, 0, 1, xi, use, s_thr, s_hist, s_point);
+    } else {
+        const int64_t p0 = a.list_off[img * a.NL + b], p1 = a.list_off[(img + 1) * a.NL + b];
+        accumulate_list<N, kBinClosed>(a.points + (int64_t)b * a.capacity, p0, p1, xi, use, s_thr, M, s_hist);
+    }
     __syncthreads();
-    write_rows(a, nd, s_row, s_valid, s_hist);
+    write_rows(a, nd, s_row, s_valid, s_hist, RADON ? s_point : nullptr);
 }
 
 // Shared query sets: no bucketing pass.  Workgroup (image, g, c) takes rows
@@ -191,7 +240,7 @@ __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
 // ect_chunk_sum_kernel adds (integers, so the order cannot matter) before the
 // prefix sum.  A non-finite direction gets a zero row and raises
 // ECT_DEVERR_NONFINITE, as in the bucketed path.
-template <int N>
+template <int N, bool RADON>
 __global__ void __launch_bounds__(kEctThreads) ect_direct_kernel(EctArgs a, int64_t groups) {
     extern __shared__ __align__(16) char smem[];
     constexpr int TD = kEctMaxDirs;
@@ -241,7 +290,8 @@ __global__ void __launch_bounds__(kEctThreads) ect_direct_kernel(EctArgs a, int6
         const int k = tid - 64, b = k & ((1 << N) - 1), hi = k >> N;
         s_loff[hi][b] = a.list_off[(img + hi) * a.NL + b];
     }
-    const int bad = stage_thresholds(a, img, s_thr, s_hist);
+    int32_t* s_point = s_hist + (int64_t)a.dirs_per_group * M;   // Radon point values
+    const int bad = stage_thresholds(a, img, s_thr, s_hist, RADON ? 2 : 1);
     if (bad) {
         if (tid == 0 && c == 0) raise_error(a.err, ECT_DEVERR_THRESHOLDS);
     } else {
@@ -268,16 +318,20 @@ __global__ void __launch_bounds__(kEctThreads) ect_direct_kernel(EctArgs a, int6
                 use[dd] = pending[dd] && sgn[dd] == b;
                 if (use[dd]) pending[dd] = false;
             }
-            const int64_t p0 = s_loff[0][b], p1 = s_loff[1][b];
-            const int64_t len = p1 - p0;
-            accumulate_list<N>(a.points + (int64_t)b * a.capacity, p0 + len * c / chunks,
-                               p0 + len * (c + 1) / chunks, xi, use, s_thr, M, s_hist);
+            if constexpr (RADON) {
+                accumulate_radon<N>(a, img, b, c, chunks, xi, use, s_thr, s_hist, s_point);
+            } else {
+                const int64_t p0 = s_loff[0][b], p1 = s_loff[1][b];
+                const int64_t len = p1 - p0;
+                accumulate_list<N, kBinClosed>(a.points + (int64_t)b * a.capacity, p0 + len * c / chunks,
+                                               p0 + len * (c + 1) / chunks, xi, use, s_thr, M, s_hist);
+            }
         }
     }
     __syncthreads();
     if (chunks == 1) {
         if (bad) zero_rows(a, nd, s_row);
-        else write_rows(a, nd, s_row, s_valid, s_hist);
+        else write_rows(a, nd, s_row, s_valid, s_hist, RADON ? s_point : nullptr);
         return;
     }
     // chunk histograms (zeros for invalid directions or bad thresholds)
@@ -315,32 +369,37 @@ __global__ void __launch_bounds__(64) ect_chunk_sum_kernel(EctArgs a, int64_t gr
     }
 }
 
-}  // namespace
-
-hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, int64_t direct_groups, hipStream_t stream) {
-    if (grid <= 0) return hipSuccess;
-    size_t shmem = sizeof(double) * a.M + sizeof(int32_t) * a.dirs_per_group * a.M;
-    hipError_t e = stage_mark(ECT_STAGE_ECT, false, stream);
-    if (e != hipSuccess) return e;
+template <int N, bool RADON>
+hipError_t launch_ect_typed(const EctArgs& a, int64_t grid, int64_t direct_groups, size_t shmem, hipStream_t stream) {
     if (direct_groups > 0) {
-        if (ndim == 2)
-            hipLaunchKernelGGL(ect_direct_kernel<2>, dim3((unsigned)grid), dim3(kEctThreads), shmem, stream, a,
-                               direct_groups);
-        else
-            hipLaunchKernelGGL(ect_direct_kernel<3>, dim3((unsigned)grid), dim3(kEctThreads), shmem, stream, a,
-                               direct_groups);
+        hipLaunchKernelGGL((ect_direct_kernel<N, RADON>), dim3((unsigned)grid), dim3(kEctThreads), shmem, stream, a,
+                           direct_groups);
         if (a.chunks > 1) {
-            e = hipGetLastError();
+            hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             const int64_t rows = (grid / a.chunks) * a.dirs_per_group;
             hipLaunchKernelGGL(ect_chunk_sum_kernel, dim3((unsigned)rows), dim3(64), 0, stream, a, direct_groups);
         }
-    } else if (ndim == 2) {
-        hipLaunchKernelGGL(ect_kernel<2>, dim3((unsigned)grid), dim3(kEctThreads), shmem, stream, a);
     } else {
-        hipLaunchKernelGGL(ect_kernel<3>, dim3((unsigned)grid), dim3(kEctThreads), shmem, stream, a);
+        hipLaunchKernelGGL((ect_kernel<N, RADON>), dim3((unsigned)grid), dim3(kEctThreads), shmem, stream, a);
     }
-    e = hipGetLastError();
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, int64_t direct_groups, bool radon,
+                      hipStream_t stream) {
+    if (grid <= 0) return hipSuccess;
+    const size_t shmem = sizeof(double) * a.M + (radon ? 2 : 1) * sizeof(int32_t) * a.dirs_per_group * a.M;
+    hipError_t e = stage_mark(ECT_STAGE_ECT, false, stream);
+    if (e != hipSuccess) return e;
+    if (ndim == 2)
+        e = radon ? launch_ect_typed<2, true>(a, grid, direct_groups, shmem, stream)
+                  : launch_ect_typed<2, false>(a, grid, direct_groups, shmem, stream);
+    else
+        e = radon ? launch_ect_typed<3, true>(a, grid, direct_groups, shmem, stream)
+                  : launch_ect_typed<3, false>(a, grid, direct_groups, shmem, stream);
     if (e != hipSuccess) return e;
     return stage_mark(ECT_STAGE_ECT, true, stream);
 }

@@ -66,7 +66,9 @@ struct EctArgs {
 // direct_groups > 0: shared query set, num_images * direct_groups * a.chunks
 // workgroups of ect_direct_kernel (no bucketing), then, with a.chunks > 1, the
 // in-order sum of the chunk histograms; else the bucketed kernel.
-hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, int64_t direct_groups, hipStream_t stream);
+// radon: the Radon transform at the thresholds instead of the ECT (same grid).
+hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, int64_t direct_groups, bool radon,
+                      hipStream_t stream);
 
 constexpr int kJi0SmallCoeffs = 10;   // FP32-path small-argument Ji0 polynomial
 

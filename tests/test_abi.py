@@ -41,7 +41,7 @@ def test_library_exports_every_declared_symbol(N):
     missing = [n for n in declared_functions() if n not in exported]
     assert not missing, missing
     # nothing but the C ABI is exported
-    extra = [n for n in exported if not (n.startswith("ect_") or n.startswith("hybrid_eval"))]
+    extra = sorted(exported - set(declared_functions()))
     assert not extra, extra
 
 
@@ -84,6 +84,7 @@ def test_eval_calls_reject_null_plan(N):
     q = N.QuerySet(0x1000, None, 4)
     need = ctypes.c_size_t(0)
     assert N.ect_eval(None, q, 0x2000, 4, 0, 0x3000, None, need, 0) == N.ECT_E_INVALID
+    assert N.radon_eval(None, q, 0x2000, 4, 0, 0x3000, None, need, 0) == N.ECT_E_INVALID
     assert N.hybrid_eval(None, 0, 1.0, 0, q, 0x3000, 0, None, need, 0) == N.ECT_E_INVALID
     assert N.hybrid_eval_backward(None, 0, 1.0, 0, q, 1, 2, 3, 0, None, need, 0) == N.ECT_E_INVALID
     assert N.ect_plan_destroy(None) == N.ECT_E_INVALID
