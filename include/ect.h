@@ -88,6 +88,7 @@ typedef enum { ECT_FP32 = 0, ECT_FP64 = 1 } ect_precision;
 #define ECT_DEVERR_LOOKBACK      0x8u  /* ordered compaction gave up waiting (never expected) */
 #define ECT_DEVERR_OVERFLOW      0x10u /* a Laplace output overflowed without a log-scale output */
 #define ECT_DEVERR_CAPACITY      0x20u /* hybrid work list larger than its workspace */
+#define ECT_DEVERR_LAYOUT        0x40u /* exact representation: a row's offsets leave no room for it */
 
 /* A batch of images.  Every image of a batch has the same ndim, dtype and
  * construction; sizes may differ (ragged batch). */
@@ -174,6 +175,62 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
 ect_status radon_eval(ect_plan plan, ect_query_set dirs, const double* thresholds, int32_t M,
                       int32_t thresholds_per_image, int32_t* out, void* ws, size_t* ws_bytes,
                       hipStream_t stream);
+
+/* Exact representations along each direction (Sec. 4.3).
+ *   ECT_EXACT_ECT    (T, E): T[0] = -inf, then the distinct projections of the
+ *                    classical points of eps(xi) in increasing order; E[i] =
+ *                    ECT(xi, t) for T[i] <= t < T[i+1] (running sums of the
+ *                    critical values, equal projections merged).
+ *   ECT_EXACT_RADON  (T, E', Tc, Ec): T[0] = -inf, then the distinct
+ *                    projections of the ordinary points of the orthant pair,
+ *                    E'[i] = R(xi, t) for T[i] < t < T[i+1] away from Tc
+ *                    (running sums of -D(eps,x)); Tc the distinct classical
+ *                    projections, Ec[k] = R(xi, Tc[k]) = E'[largest i with
+ *                    T[i] < Tc[k]] + the classical values at Tc[k].
+ * Projections use the canonical FP64 expression, so every entry is exact. */
+typedef enum { ECT_EXACT_ECT = 0, ECT_EXACT_RADON = 1 } ect_exact_kind;
+
+/* ect_exact_layout -- entries each query row needs and their offsets:
+ * row_off[r] = first entry of row r, row_off[rows] = total (the capacity the
+ * caller allocates for T and E).  ECT: classical points + 1 per row; Radon:
+ * ordinary points + 1 + classical points (an upper bound: merged projections
+ * leave the rest of a row unused); a non-finite direction: 1.
+ *   row_off         DEVICE int64 [rows + 1], written
+ *   ws, ws_bytes    DEVICE workspace (ws == NULL: size query)
+ * Reads the list sizes on the device, so it follows ect_plan_rerun. */
+ect_status ect_exact_layout(ect_plan plan, ect_query_set dirs, int32_t kind, int64_t* row_off, void* ws,
+                            size_t* ws_bytes, hipStream_t stream);
+
+/* ect_exact -- the exact representation of every query row (sort by
+ * projection, merge of equal projections, running sums; Sec. 4.3).
+ *   row_off         DEVICE int64 [rows + 1] from ect_exact_layout on the same
+ *                   plan contents and query set
+ *   capacity        entries of T and E (>= row_off[rows], < 2^32)
+ *   T, E            DEVICE double / int32 [capacity]: row r writes entries
+ *                   from row_off[r]: ECT: (T, E) of length len[r]; Radon:
+ *                   (T, E') of length len[2r], then (Tc, Ec) of length
+ *                   len[2r+1].  Entries past those are left unspecified.
+ *   len             DEVICE int64 [rows] (ECT) or [rows][2] (Radon)
+ *   ws, ws_bytes    DEVICE workspace (ws == NULL: size query; depends on
+ *                   kind, rows and capacity)
+ * A row whose offsets leave it less room than ect_exact_layout gives, or
+ * reach past capacity, gets length 0 and raises ECT_DEVERR_LAYOUT; a
+ * non-finite direction gets T = [-inf], E = [0] (Radon: no Tc) and raises
+ * ECT_DEVERR_NONFINITE. */
+ect_status ect_exact(ect_plan plan, ect_query_set dirs, int32_t kind, const int64_t* row_off, int64_t capacity,
+                     double* T, int32_t* E, int64_t* len, void* ws, size_t* ws_bytes, hipStream_t stream);
+
+/* ect_exact_eval -- evaluation of exact representations at thresholds by
+ * binary search (Sec. 4.3): ECT: E[largest i with T[i] <= t]; Radon: Ec[k]
+ * where Tc[k] == t, else E'[largest i with T[i] < t].  Any thresholds (no
+ * order needed); t = NaN, or a row of length 0, gives 0.
+ *   rows, row_off, T, E, len, capacity   as written by ect_exact
+ *   thresholds      DEVICE double [M] (thresholds_per_row == 0) or [rows][M]
+ *   out             DEVICE int32 [rows][M]
+ * A row whose entries would reach past capacity gives zeros. */
+ect_status ect_exact_eval(int32_t kind, int64_t rows, const int64_t* row_off, const double* T, const int32_t* E,
+                          const int64_t* len, int64_t capacity, const double* thresholds, int32_t M,
+                          int32_t thresholds_per_row, int32_t* out, hipStream_t stream);
 
 /* hybrid_eval -- HT(xi) = integral kappa_s(t) R(xi,t) dt (Sec. 2.2), evaluated
  * as the sum over ordinary critical points of Delta^ord(eps,x) kbar_s(<xi,x>)

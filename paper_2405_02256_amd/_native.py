@@ -27,6 +27,8 @@ DEVERR_NONFINITE = 0x4
 DEVERR_LOOKBACK = 0x8
 DEVERR_OVERFLOW = 0x10
 DEVERR_CAPACITY = 0x20
+DEVERR_LAYOUT = 0x40
+EXACT_ECT, EXACT_RADON = 0, 1
 BWD_REUSE_PREPARED = 0x1
 
 
@@ -76,8 +78,11 @@ def lib():
     L.ect_plan_destroy.argtypes = [c_vp]
     L.ect_plan_set_tuning.argtypes = [c_vp, c_i64, c_i64, c_i32, c_i32]
     L.ect_set_stage_events.argtypes = [c_i32, c_vp, c_vp]
+    L.ect_exact_layout.argtypes = [c_vp, QuerySet, c_i32, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
+    L.ect_exact.argtypes = [c_vp, QuerySet, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
+    L.ect_exact_eval.argtypes = [c_i32, c_i64, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_i32, c_i32, c_vp, c_vp]
     for name in ("ect_precompute", "ect_plan_rerun", "ect_eval", "radon_eval", "hybrid_eval", "hybrid_eval_multi",
-                 "hybrid_eval_backward",
+                 "hybrid_eval_backward", "ect_exact_layout", "ect_exact", "ect_exact_eval",
                  "ect_plan_counts", "ect_plan_export", "ect_plan_check", "ect_plan_destroy", "ect_plan_set_tuning",
                  "ect_set_stage_events"):
         getattr(L, name).restype = c_i32
@@ -118,6 +123,22 @@ def ect_eval(plan, dirs: QuerySet, thresholds, M, per_image, out, ws, ws_bytes: 
 def radon_eval(plan, dirs: QuerySet, thresholds, M, per_image, out, ws, ws_bytes: ctypes.c_size_t, stream) -> int:
     return lib().radon_eval(c_vp(plan), dirs, c_vp(thresholds), int(M), int(per_image), c_vp(out), ws,
                             ctypes.byref(ws_bytes), c_vp(stream))
+
+
+def ect_exact_layout(plan, dirs: QuerySet, kind, row_off, ws, ws_bytes: ctypes.c_size_t, stream) -> int:
+    return lib().ect_exact_layout(c_vp(plan), dirs, int(kind), c_vp(row_off), ws, ctypes.byref(ws_bytes),
+                                  c_vp(stream))
+
+
+def ect_exact(plan, dirs: QuerySet, kind, row_off, capacity, T, E, length, ws, ws_bytes: ctypes.c_size_t,
+              stream) -> int:
+    return lib().ect_exact(c_vp(plan), dirs, int(kind), c_vp(row_off), int(capacity), c_vp(T), c_vp(E),
+                           c_vp(length), ws, ctypes.byref(ws_bytes), c_vp(stream))
+
+
+def ect_exact_eval(kind, rows, row_off, T, E, length, capacity, thresholds, M, per_row, out, stream) -> int:
+    return lib().ect_exact_eval(int(kind), int(rows), c_vp(row_off), c_vp(T), c_vp(E), c_vp(length),
+                                int(capacity), c_vp(thresholds), int(M), int(per_row), c_vp(out), c_vp(stream))
 
 
 def hybrid_eval(plan, kernel, s, precision, xi: QuerySet, out, log_scale, ws, ws_bytes: ctypes.c_size_t,

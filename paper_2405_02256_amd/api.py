@@ -201,6 +201,38 @@ class Plan:
                 name)
         return out
 
+    def exact(self, dirs, kind: str = "ect", offsets=None, stream=None, slot: str = "main") -> "ExactRepresentation":
+        """Exact representation of every query row (ect_exact_layout, then ect_exact): kind "ect" gives
+        (T, E), "radon" gives (T, E', Tc, Ec).  Reads the total size back to the host once."""
+        kinds = {"ect": N.EXACT_ECT, "radon": N.EXACT_RADON}
+        if kind not in kinds:
+            raise ValueError(f"kind must be one of {sorted(kinds)}")
+        k = kinds[kind]
+        q = dirs if isinstance(dirs, QuerySet) else QuerySet(dirs, offsets)
+        q.validate(self.num_images, self.ndim)
+        rows = q.rows(self.num_images)
+        st = _stream(stream)
+        row_off = torch.empty(rows + 1, dtype=torch.int64, device=self.device)
+        need = ctypes.c_size_t(0)
+        N.check(N.ect_exact_layout(self.handle, q.c(), k, _dptr(row_off), None, need, st), "ect_exact_layout(size)")
+        ws = self._ws(need.value, slot)
+        have = ctypes.c_size_t(ws.numel())
+        N.check(N.ect_exact_layout(self.handle, q.c(), k, _dptr(row_off), ctypes.c_void_p(_dptr(ws)), have, st),
+                "ect_exact_layout")
+        with torch.cuda.stream(stream) if stream is not None else _nullctx():
+            capacity = int(row_off[rows].item())
+        T = torch.empty(max(capacity, 1), dtype=torch.float64, device=self.device)
+        E = torch.empty(max(capacity, 1), dtype=torch.int32, device=self.device)
+        length = torch.empty((rows, 2) if k == N.EXACT_RADON else (rows,), dtype=torch.int64, device=self.device)
+        need = ctypes.c_size_t(0)
+        N.check(N.ect_exact(self.handle, q.c(), k, _dptr(row_off), capacity, _dptr(T), _dptr(E), _dptr(length),
+                            None, need, st), "ect_exact(size)")
+        ws = self._ws(need.value, slot)
+        have = ctypes.c_size_t(ws.numel())
+        N.check(N.ect_exact(self.handle, q.c(), k, _dptr(row_off), capacity, _dptr(T), _dptr(E), _dptr(length),
+                            ctypes.c_void_p(_dptr(ws)), have, st), "ect_exact")
+        return ExactRepresentation(k, row_off, T, E, length, capacity)
+
     def hybrid(self, xi, kernel: str = "fourier", s: float = 1.0, precision: str = "fp32", offsets=None,
                log_scale: bool = False, out=None, stream=None, log_scale_out=None, slot: str = "main"):
         """float64 [rows] (Fourier: [rows][2]); with log_scale (Laplace) returns (out, log_scale)."""
@@ -278,6 +310,52 @@ class Plan:
                                        N.BWD_REUSE_PREPARED if reuse_prepared else 0),
                 "hybrid_eval_backward")
         return gxi, gs
+
+
+class _nullctx:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        return False
+
+
+class ExactRepresentation:
+    """Device arrays written by ect_exact: row r starts at row_off[r]; ECT rows hold (T, E) of length
+    length[r], Radon rows (T, E') of length length[r, 0] followed by (Tc, Ec) of length length[r, 1]."""
+
+    def __init__(self, kind: int, row_off, T, E, length, capacity: int):
+        self.kind, self.row_off, self.T, self.E, self.length, self.capacity = kind, row_off, T, E, length, capacity
+        self.rows = row_off.shape[0] - 1
+
+    def to_host(self):
+        """Per-row numpy arrays: [(T, E)] or [(T, E', Tc, Ec)]."""
+        off = self.row_off.cpu().numpy()
+        T, E, L = self.T.cpu().numpy(), self.E.cpu().numpy(), self.length.cpu().numpy()
+        out = []
+        for r in range(self.rows):
+            b = int(off[r])
+            if self.kind == N.EXACT_ECT:
+                n = int(L[r])
+                out.append((T[b:b + n], E[b:b + n]))
+            else:
+                no, nc = int(L[r, 0]), int(L[r, 1])
+                out.append((T[b:b + no], E[b:b + no], T[b + no:b + no + nc], E[b + no:b + no + nc]))
+        return out
+
+    def eval(self, thresholds: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+        """int32 [rows][M] by binary search (ect_exact_eval); thresholds [M] or [rows][M], any order."""
+        thr = thresholds.to(device=self.T.device, dtype=torch.float64).contiguous()
+        per_row = 1 if thr.dim() == 2 else 0
+        if thr.dim() not in (1, 2) or (per_row and thr.shape[0] != self.rows):
+            raise ValueError("thresholds must be [M] or [rows][M]")
+        M = thr.shape[-1]
+        if out is None:
+            out = torch.empty((self.rows, M), dtype=torch.int32, device=self.T.device)
+        N.check(N.ect_exact_eval(self.kind, self.rows, _dptr(self.row_off), _dptr(self.T), _dptr(self.E),
+                                 _dptr(self.length), self.capacity, _dptr(thr), M, per_row, _dptr(out),
+                                 _stream(stream)), "ect_exact_eval")
+        return out
 
 
 class HybridTransform(torch.autograd.Function):

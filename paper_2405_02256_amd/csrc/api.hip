@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "eval_internal.h"
+#include "exact_internal.h"
 
 using namespace ect;
 
@@ -356,6 +357,109 @@ ect_status ect_eval(ect_plan plan, ect_query_set dirs, const double* thresholds,
 ect_status radon_eval(ect_plan plan, ect_query_set dirs, const double* thresholds, int32_t M,
                       int32_t thresholds_per_image, int32_t* out, void* ws, size_t* ws_bytes, hipStream_t stream) {
     return threshold_eval(plan, dirs, thresholds, M, thresholds_per_image, out, ws, ws_bytes, stream, true);
+}
+
+// Arguments of the exact stage common to the layout and the build.
+static ExactArgs exact_args(const Plan& p, const ect_query_set& dirs, int32_t kind) {
+    ExactArgs a{};
+    a.points = (const Point*)(p.ws + p.lay.points);
+    a.list_off = (const int64_t*)(p.ws + p.lay.list_off);
+    a.list_capacity = p.lay.capacity;
+    a.num_images = p.num_images;
+    a.NL = num_lists(p.ndim);
+    a.vecs = dirs.vecs;
+    a.offsets = dirs.offsets;
+    a.count = dirs.count;
+    a.rows = query_rows(dirs, p.num_images);
+    a.kind = kind;
+    a.err = (uint32_t*)(p.ws + p.lay.err);
+    return a;
+}
+
+ect_status ect_exact_layout(ect_plan plan, ect_query_set dirs, int32_t kind, int64_t* row_off, void* ws,
+                            size_t* ws_bytes, hipStream_t stream) {
+    if (!plan || !ws_bytes || !row_off) return ECT_E_INVALID;
+    if (kind != ECT_EXACT_ECT && kind != ECT_EXACT_RADON) return ECT_E_INVALID;
+    if (!valid_query_set(dirs, plan->num_images)) return ECT_E_INVALID;
+    const Plan& p = *plan;
+    const int64_t rows = query_rows(dirs, p.num_images);
+    const size_t scan = exact_layout_scan_bytes(rows);
+    if (scan == 0) return ECT_E_DEVICE;
+    const size_t need_off = 0;
+    const size_t scan_off = align_up(sizeof(int64_t) * (size_t)(rows + 1), kAlign);
+    const size_t total = scan_off + align_up(scan, kAlign);
+    if (!ws) {
+        *ws_bytes = total;
+        return ECT_OK;
+    }
+    if (*ws_bytes < total) return ECT_E_NOMEM;
+    if ((uintptr_t)ws % kAlign) return ECT_E_INVALID;
+    ExactArgs a = exact_args(p, dirs, kind);
+    a.row_off_out = row_off;
+    char* w = (char*)ws;
+    return from_hip(launch_exact_layout(p.ndim, a, (int64_t*)(w + need_off), w + scan_off, scan, stream));
+}
+
+ect_status ect_exact(ect_plan plan, ect_query_set dirs, int32_t kind, const int64_t* row_off, int64_t capacity,
+                     double* T, int32_t* E, int64_t* len, void* ws, size_t* ws_bytes, hipStream_t stream) {
+    if (!plan || !ws_bytes || !row_off) return ECT_E_INVALID;
+    if (kind != ECT_EXACT_ECT && kind != ECT_EXACT_RADON) return ECT_E_INVALID;
+    if (!valid_query_set(dirs, plan->num_images)) return ECT_E_INVALID;
+    if (capacity < 0) return ECT_E_INVALID;
+    if (capacity >= ((int64_t)1 << 32)) return ECT_E_UNSUPPORTED;
+    const Plan& p = *plan;
+    const int64_t rows = query_rows(dirs, p.num_images);
+    if (2 * rows >= ((int64_t)1 << 32)) return ECT_E_UNSUPPORTED;
+    if (rows > 0 && (!T || !E || !len)) return ECT_E_INVALID;
+    const int64_t segs = exact_segments(kind, rows);
+    const size_t sort = exact_sort_bytes(kind, rows, capacity);
+    if (sort == 0) return ECT_E_DEVICE;
+    const size_t cap = (size_t)std::max<int64_t>(capacity, 1);
+    size_t o = 0;
+    const size_t o_rows = o; o = align_up(o + sizeof(ExactRow) * (size_t)std::max<int64_t>(rows, 1), kAlign);
+    const size_t o_sb = o; o = align_up(o + sizeof(uint32_t) * (size_t)std::max<int64_t>(segs, 1), kAlign);
+    const size_t o_se = o; o = align_up(o + sizeof(uint32_t) * (size_t)std::max<int64_t>(segs, 1), kAlign);
+    const size_t o_ki = o; o = align_up(o + sizeof(uint64_t) * cap, kAlign);
+    const size_t o_ko = o; o = align_up(o + sizeof(uint64_t) * cap, kAlign);
+    const size_t o_vi = o; o = align_up(o + sizeof(int32_t) * cap, kAlign);
+    const size_t o_vo = o; o = align_up(o + sizeof(int32_t) * cap, kAlign);
+    const size_t o_cum = o; o = align_up(o + (kind == ECT_EXACT_RADON ? sizeof(int32_t) * cap : 0), kAlign);
+    const size_t o_tmp = o; o = align_up(o + sort, kAlign);
+    if (!ws) {
+        *ws_bytes = o;
+        return ECT_OK;
+    }
+    if (*ws_bytes < o) return ECT_E_NOMEM;
+    if ((uintptr_t)ws % kAlign) return ECT_E_INVALID;
+    if (rows == 0) return ECT_OK;
+    char* w = (char*)ws;
+    ExactArgs a = exact_args(p, dirs, kind);
+    a.row_off = row_off;
+    a.capacity = capacity;
+    a.rowrec = (ExactRow*)(w + o_rows);
+    a.seg_begin = (uint32_t*)(w + o_sb);
+    a.seg_end = (uint32_t*)(w + o_se);
+    a.keys_in = (uint64_t*)(w + o_ki);
+    a.keys_out = (uint64_t*)(w + o_ko);
+    a.vals_in = (int32_t*)(w + o_vi);
+    a.vals_out = (int32_t*)(w + o_vo);
+    a.cum = kind == ECT_EXACT_RADON ? (int32_t*)(w + o_cum) : nullptr;
+    a.T = T;
+    a.E = E;
+    a.len = len;
+    return from_hip(launch_exact(p.ndim, a, w + o_tmp, sort, stream));
+}
+
+ect_status ect_exact_eval(int32_t kind, int64_t rows, const int64_t* row_off, const double* T, const int32_t* E,
+                          const int64_t* len, int64_t capacity, const double* thresholds, int32_t M,
+                          int32_t thresholds_per_row, int32_t* out, hipStream_t stream) {
+    if (kind != ECT_EXACT_ECT && kind != ECT_EXACT_RADON) return ECT_E_INVALID;
+    if (rows < 0 || M < 1 || capacity < 0) return ECT_E_INVALID;
+    if (rows == 0) return ECT_OK;
+    if (!row_off || !T || !E || !len || !thresholds || !out) return ECT_E_INVALID;
+    if (rows * (int64_t)((M + 255) / 256) >= ((int64_t)1 << 31)) return ECT_E_UNSUPPORTED;
+    return from_hip(launch_exact_eval(kind, rows, row_off, T, E, len, capacity, thresholds, M,
+                                      thresholds_per_row ? 1 : 0, out, stream));
 }
 
 static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t precision, ect_query_set xi,

@@ -87,8 +87,28 @@ def test_eval_calls_reject_null_plan(N):
     assert N.radon_eval(None, q, 0x2000, 4, 0, 0x3000, None, need, 0) == N.ECT_E_INVALID
     assert N.hybrid_eval(None, 0, 1.0, 0, q, 0x3000, 0, None, need, 0) == N.ECT_E_INVALID
     assert N.hybrid_eval_backward(None, 0, 1.0, 0, q, 1, 2, 3, 0, None, need, 0) == N.ECT_E_INVALID
+    assert N.ect_exact_layout(None, q, 0, 0x4000, None, need, 0) == N.ECT_E_INVALID
+    assert N.ect_exact(None, q, 0, 0x4000, 16, 0x5000, 0x6000, 0x7000, None, need, 0) == N.ECT_E_INVALID
     assert N.ect_plan_destroy(None) == N.ECT_E_INVALID
     assert N.ect_plan_rerun(None, 0) == N.ECT_E_INVALID
+
+
+def test_exact_eval_validation(N):
+    """Host checks of ect_exact_eval (no plan involved): bad kind, sizes and null pointers are
+    rejected before any launch; zero rows is a no-op."""
+    args = dict(rows=3, row_off=0x1000, T=0x2000, E=0x3000, length=0x4000, capacity=64, thresholds=0x5000, M=4,
+                per_row=0, out=0x6000, stream=0)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return N.ect_exact_eval(a.pop("kind", 0), **a)
+
+    assert call(kind=2) == N.ECT_E_INVALID
+    assert call(M=0) == N.ECT_E_INVALID
+    assert call(rows=-1) == N.ECT_E_INVALID
+    assert call(capacity=-1) == N.ECT_E_INVALID
+    assert call(T=0) == N.ECT_E_INVALID
+    assert call(rows=0, T=0, E=0) == N.ECT_OK
 
 
 def test_tuning_validation(N):
