@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path comparison")
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="scale of the oracle sample")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-image batched comparison")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the Radon transform and exact-representation measurements")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule knobs")
     ap.add_argument("--concurrent", action="store_true", help="run the ECT branch on a side stream")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -62,6 +64,62 @@ def source_digest(paths):
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def measure_next(plan, w, dirs, thr, n, cls_counts, ord_counts, steps):
+    """Radon transform at the step's thresholds (kernel time from the library's
+    stage events) and the exact representations of the step's directions
+    (whole-call time: every kernel of the build, sort included; then their
+    binary-search evaluation at the thresholds)."""
+    import numpy as np
+    import torch
+
+    from paper_2405_02256_amd import _native as N
+    from paper_2405_02256_amd import hipevents, roofline
+
+    sgn = lambda d: int(d[0] < 0) + 2 * int(d[1] < 0)
+    pair = lambda e: e ^ 3 if e >= 2 else e
+    c_pts = float(sum(cls_counts[0][sgn(d)] for d in w.ect_dirs))
+    o_pts = float(sum(ord_counts[pair(sgn(d))] for d in w.ect_dirs))
+    out = {}
+    rad = plan.radon(dirs, thr)
+    ev = [(hipevents.Event(), hipevents.Event()) for _ in range(steps)]
+    for a, b in ev:
+        N.check(N.ect_set_stage_events(N.STAGE_ECT, a.handle, b.handle), "stage events")
+        plan.radon(dirs, thr, out=rad)
+    torch.cuda.synchronize()
+    N.ect_set_stage_events(N.STAGE_ECT, None, None)
+    ms = float(np.mean([a.elapsed_ms(b) for a, b in ev]))
+    roof = roofline.alu_roofline("radon", n, c_pts + o_pts, ms * 1e-3)
+    out["radon_thresholds"] = {"kernel_ms": ms, "dirs_per_s": len(w.ect_dirs) / (ms * 1e-3),
+                               "points_streamed": c_pts + o_pts, "roofline": roof}
+    for kind, pts in (("ect", c_pts), ("radon", c_pts + o_pts)):
+        rep = plan.exact(dirs, kind)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        plan.exact(dirs, kind, reuse=rep)
+        e0.record()
+        for _ in range(steps):
+            plan.exact(dirs, kind, reuse=rep)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_b = e0.elapsed_time(e1) / steps
+        ln = rep.length.cpu().numpy()
+        entries = float(ln.sum())
+        nbytes = 32.0 * pts + 12.0 * entries
+        o = torch.empty((rep.rows, thr.shape[0]), dtype=torch.int32, device=thr.device)
+        rep.eval(thr, out=o)
+        e0.record()
+        for _ in range(steps):
+            rep.eval(thr, out=o)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_e = e0.elapsed_time(e1) / steps
+        out[f"{kind}_exact"] = {"build_ms": ms_b, "rows": rep.rows, "points": pts, "entries": entries,
+                                "rows_per_s": rep.rows / (ms_b * 1e-3),
+                                "roofline": roofline.hbm_roofline(nbytes, ms_b * 1e-3),
+                                "eval_ms": ms_e, "eval_values_per_s": rep.rows * thr.shape[0] / (ms_e * 1e-3)}
+    return out
 
 
 def main():
@@ -210,6 +268,13 @@ def main():
         except (OSError, ValueError):
             pass
 
+    # ---- Radon transform at the thresholds and the exact representations, same field ----
+    next_rows = None
+    if not args.no_next:
+        log("Radon transform and exact representations")
+        next_rows = measure_next(plan, w, dirs, thr, n, cls_counts, counts, args.steps)
+        log("next rows: " + json.dumps(next_rows))
+
     # ---- FP64 path on the same step, for the FP32-vs-FP64 comparison ----
     fp64 = None
     if not args.no_fp64:
@@ -346,6 +411,7 @@ def main():
         "fp64_path_ms_per_step": None if fp64 is None else fp64 * 1e3,
         "fp32_vs_fp64_speedup": None if fp64 is None else fp64 / sec,
         "batched_vs_per_image": batch,
+        "radon_and_exact": next_rows,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

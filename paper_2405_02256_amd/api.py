@@ -201,9 +201,12 @@ class Plan:
                 name)
         return out
 
-    def exact(self, dirs, kind: str = "ect", offsets=None, stream=None, slot: str = "main") -> "ExactRepresentation":
+    def exact(self, dirs, kind: str = "ect", offsets=None, stream=None, slot: str = "main",
+              reuse: "ExactRepresentation | None" = None) -> "ExactRepresentation":
         """Exact representation of every query row (ect_exact_layout, then ect_exact): kind "ect" gives
-        (T, E), "radon" gives (T, E', Tc, Ec).  Reads the total size back to the host once."""
+        (T, E), "radon" gives (T, E', Tc, Ec).  Reads the total size back to the host once.  With
+        `reuse` (a representation of the same kind, plan contents and query set) its layout and arrays
+        are rebuilt in place: no layout call, no host read-back."""
         kinds = {"ect": N.EXACT_ECT, "radon": N.EXACT_RADON}
         if kind not in kinds:
             raise ValueError(f"kind must be one of {sorted(kinds)}")
@@ -212,6 +215,17 @@ class Plan:
         q.validate(self.num_images, self.ndim)
         rows = q.rows(self.num_images)
         st = _stream(stream)
+        if reuse is not None:
+            if reuse.kind != k or reuse.rows != rows:
+                raise ValueError("reuse needs a representation of the same kind and number of rows")
+            need = ctypes.c_size_t(0)
+            args = (self.handle, q.c(), k, _dptr(reuse.row_off), reuse.capacity, _dptr(reuse.T), _dptr(reuse.E),
+                    _dptr(reuse.length))
+            N.check(N.ect_exact(*args, None, need, st), "ect_exact(size)")
+            ws = self._ws(need.value, slot)
+            have = ctypes.c_size_t(ws.numel())
+            N.check(N.ect_exact(*args, ctypes.c_void_p(_dptr(ws)), have, st), "ect_exact")
+            return reuse
         row_off = torch.empty(rows + 1, dtype=torch.int64, device=self.device)
         need = ctypes.c_size_t(0)
         N.check(N.ect_exact_layout(self.handle, q.c(), k, _dptr(row_off), None, need, st), "ect_exact_layout(size)")

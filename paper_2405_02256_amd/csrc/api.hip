@@ -409,22 +409,16 @@ ect_status ect_exact(ect_plan plan, ect_query_set dirs, int32_t kind, const int6
     if (capacity >= ((int64_t)1 << 32)) return ECT_E_UNSUPPORTED;
     const Plan& p = *plan;
     const int64_t rows = query_rows(dirs, p.num_images);
-    if (2 * rows >= ((int64_t)1 << 32)) return ECT_E_UNSUPPORTED;
+    if (rows >= ((int64_t)1 << 30)) return ECT_E_UNSUPPORTED;
     if (rows > 0 && (!T || !E || !len)) return ECT_E_INVALID;
-    const int64_t segs = exact_segments(kind, rows);
-    const size_t sort = exact_sort_bytes(kind, rows, capacity);
-    if (sort == 0) return ECT_E_DEVICE;
     const size_t cap = (size_t)std::max<int64_t>(capacity, 1);
     size_t o = 0;
-    const size_t o_rows = o; o = align_up(o + sizeof(ExactRow) * (size_t)std::max<int64_t>(rows, 1), kAlign);
-    const size_t o_sb = o; o = align_up(o + sizeof(uint32_t) * (size_t)std::max<int64_t>(segs, 1), kAlign);
-    const size_t o_se = o; o = align_up(o + sizeof(uint32_t) * (size_t)std::max<int64_t>(segs, 1), kAlign);
-    const size_t o_ki = o; o = align_up(o + sizeof(uint64_t) * cap, kAlign);
-    const size_t o_ko = o; o = align_up(o + sizeof(uint64_t) * cap, kAlign);
-    const size_t o_vi = o; o = align_up(o + sizeof(int32_t) * cap, kAlign);
-    const size_t o_vo = o; o = align_up(o + sizeof(int32_t) * cap, kAlign);
+    const size_t o_ka = o; o = align_up(o + sizeof(uint64_t) * cap, kAlign);
+    const size_t o_kb = o; o = align_up(o + sizeof(uint64_t) * cap, kAlign);
+    const size_t o_va = o; o = align_up(o + sizeof(int32_t) * cap, kAlign);
+    const size_t o_vb = o; o = align_up(o + sizeof(int32_t) * cap, kAlign);
     const size_t o_cum = o; o = align_up(o + (kind == ECT_EXACT_RADON ? sizeof(int32_t) * cap : 0), kAlign);
-    const size_t o_tmp = o; o = align_up(o + sort, kAlign);
+    const size_t o_ct = o; o = align_up(o + (kind == ECT_EXACT_RADON ? sizeof(double) * cap : 0), kAlign);
     if (!ws) {
         *ws_bytes = o;
         return ECT_OK;
@@ -436,18 +430,16 @@ ect_status ect_exact(ect_plan plan, ect_query_set dirs, int32_t kind, const int6
     ExactArgs a = exact_args(p, dirs, kind);
     a.row_off = row_off;
     a.capacity = capacity;
-    a.rowrec = (ExactRow*)(w + o_rows);
-    a.seg_begin = (uint32_t*)(w + o_sb);
-    a.seg_end = (uint32_t*)(w + o_se);
-    a.keys_in = (uint64_t*)(w + o_ki);
-    a.keys_out = (uint64_t*)(w + o_ko);
-    a.vals_in = (int32_t*)(w + o_vi);
-    a.vals_out = (int32_t*)(w + o_vo);
+    a.keys_a = (uint64_t*)(w + o_ka);
+    a.keys_b = (uint64_t*)(w + o_kb);
+    a.vals_a = (int32_t*)(w + o_va);
+    a.vals_b = (int32_t*)(w + o_vb);
     a.cum = kind == ECT_EXACT_RADON ? (int32_t*)(w + o_cum) : nullptr;
+    a.ct = kind == ECT_EXACT_RADON ? (double*)(w + o_ct) : nullptr;
     a.T = T;
     a.E = E;
     a.len = len;
-    return from_hip(launch_exact(p.ndim, a, w + o_tmp, sort, stream));
+    return from_hip(launch_exact(p.ndim, a, stream));
 }
 
 ect_status ect_exact_eval(int32_t kind, int64_t rows, const int64_t* row_off, const double* T, const int32_t* E,

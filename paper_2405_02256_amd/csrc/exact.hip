@@ -12,14 +12,18 @@
 // projections; the distinct classical projections Tc carry
 // Ec = E'[largest T[i] < Tc] + the classical values at Tc.
 //
-// Steps: rows (per query row: image, sign vector, list bounds, check of the
-// caller's row offsets) -> project (one thread per slot: canonical FP64
-// projection turned into an order-preserving 64-bit key) -> segmented radix
-// sort of (key, value) per list segment -> finalize (one workgroup per row:
-// merge equal keys with a block scan of head flags and values) -> for Radon,
-// the classical values get E' from a binary search in the row's T.
+// One workgroup builds one row in one launch: it reads the row's list (or
+// lists), turns each canonical FP64 projection into an order-preserving
+// 64-bit key, sorts (key, value) pairs with a block radix sort in LDS, merges
+// equal keys with a block scan of head flags and values and writes the
+// distinct entries.  A list longer than one LDS tile (4096 points) is sorted
+// tile by tile into the workspace and the sorted tiles are merged pairwise
+// there by the same workgroup (merge path), before the same merge of equal
+// keys.  For Radon, each classical entry then takes E' from a binary search
+// in the row's T.  Global memory written by the workgroup is read back by it
+// only after a workgroup barrier.
+#include <rocprim/block/block_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
-#include <rocprim/device/device_segmented_radix_sort.hpp>
 
 #include "exact_internal.h"
 
@@ -28,11 +32,14 @@ namespace ect {
 namespace {
 
 constexpr int kRowThreads = 256;
-constexpr int kFinThreads = 256;
-constexpr int kFinItems = 4;            // consecutive sorted entries per thread per step
+constexpr int kFinThreads = 512;         // the row-building workgroup
+constexpr int kFinItems = 4;            // consecutive sorted entries per thread per step (long lists)
 constexpr int kFinStep = kFinThreads * kFinItems;
-constexpr int kSlotThreads = 256;
+constexpr int kTileItems = 8;           // keys per thread of the largest LDS sort
+constexpr int kTile = kFinThreads * kTileItems;
+constexpr int kMergeItems = 8;          // outputs per thread per step of a pairwise merge
 constexpr int kEvalThreads = 256;
+constexpr int kFixThreads = 256;
 constexpr uint64_t kTopBit = 0x8000000000000000ull;
 
 // Order-preserving key of a finite or infinite FP64 value (-0 taken as +0):
@@ -103,74 +110,6 @@ __global__ void __launch_bounds__(kRowThreads) exact_need_kernel(ExactArgs a, in
     }
     ExactRow ri;
     need[r] = row_info<N>(a, r, ri);
-}
-
-// Row records and sort segments; a row whose offsets do not leave room for
-// its entries (or leave the output) is marked unusable and gets empty
-// segments.
-template <int N>
-__global__ void __launch_bounds__(kRowThreads) exact_rows_kernel(ExactArgs a) {
-    const int64_t r = (int64_t)blockIdx.x * kRowThreads + threadIdx.x;
-    if (r >= a.rows) return;
-    ExactRow ri;
-    const int64_t need = row_info<N>(a, r, ri);
-    const int64_t b = a.row_off[r], e = a.row_off[r + 1];
-    ri.base = b;
-    if (!(b >= 0 && e <= a.capacity && e - b >= need)) {
-        ri.valid = -1;
-        raise_error(a.err, ECT_DEVERR_LAYOUT);
-    } else if (!ri.valid) {
-        raise_error(a.err, ECT_DEVERR_NONFINITE);
-    }
-    a.rowrec[r] = ri;
-    const bool use = ri.valid == 1;
-    const uint32_t ub = use ? (uint32_t)b : 0u;
-    if (a.kind == ECT_EXACT_ECT) {
-        a.seg_begin[r] = ub;
-        a.seg_end[r] = use ? ub + (uint32_t)ri.nc : 0u;
-    } else {
-        a.seg_begin[2 * r] = ub;
-        a.seg_end[2 * r] = use ? ub + (uint32_t)ri.no : 0u;
-        const uint32_t cb = use ? ub + (uint32_t)ri.no + 1u : 0u;
-        a.seg_begin[2 * r + 1] = cb;
-        a.seg_end[2 * r + 1] = use ? cb + (uint32_t)ri.nc : 0u;
-    }
-}
-
-// One thread per output slot: the row owning the slot (the last row whose
-// offset is <= slot), then the list point the slot stands for.
-template <int N>
-__global__ void __launch_bounds__(kSlotThreads) exact_project_kernel(ExactArgs a) {
-    const int64_t s = (int64_t)blockIdx.x * kSlotThreads + threadIdx.x;
-    if (s >= a.capacity || a.rows == 0) return;
-    int64_t lo = 0, hi = a.rows - 1;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (a.row_off[mid] <= s) lo = mid; else hi = mid - 1;
-    }
-    const ExactRow& ri = a.rowrec[lo];
-    if (ri.valid != 1) return;
-    const int64_t k = s - ri.base;
-    if (k < 0) return;
-    int64_t p;
-    int32_t sign = 1;
-    if (a.kind == ECT_EXACT_ECT) {
-        if (k >= ri.nc) return;
-        p = ri.pc + k;
-    } else if (k < ri.no) {
-        p = ri.po + k;
-        sign = ri.sign_o;
-    } else if (k > ri.no && k - ri.no - 1 < ri.nc) {
-        p = ri.pc + (k - ri.no - 1);
-    } else {
-        return;
-    }
-    const Point pt = a.points[p];
-    double xi[N];
-#pragma unroll
-    for (int c = 0; c < N; ++c) xi[c] = ri.xi[c];
-    a.keys_in[s] = order_key(project<N>(xi, pt.x));
-    a.vals_in[s] = sign * (int32_t)pt.val;
 }
 
 // Exclusive block scan of (count, sum) pairs over kFinThreads threads; also
@@ -261,17 +200,280 @@ __device__ int64_t merge_segment(const uint64_t* __restrict__ keys, const int32_
     return distinct;
 }
 
-// One workgroup per row.  ECT: T = [-inf, distinct classical projections],
-// E = [0, running sums].  Radon: the same from the ordinary segment, then the
-// distinct classical projections right after with their running classical
-// sums in `cum` (turned into Ec by exact_radon_fix_kernel).
-__global__ void __launch_bounds__(kFinThreads) exact_finalize_kernel(ExactArgs a) {
-    __shared__ int32_t s_wave[kFinThreads / 64][2];
-    const int64_t r = blockIdx.x;
-    const ExactRow ri = a.rowrec[r];
+
+// A direction passed by value (kept in registers across calls).
+template <int N>
+struct Dir {
+    double v[N];
+};
+
+// Tiles are sorted on 32-bit keys carrying the point's staging index: first
+// on the FP32 rounding of the projection (monotone, so the result is ordered
+// up to projections that round to the same float); only when that leaves two
+// neighbours out of FP64 order is the tile sorted exactly, by the low then
+// (stably) the high half of the 64-bit key.  The keys and values themselves
+// stay in LDS and are read through the sorted indices.
+template <int I>
+using BlockSort = rocprim::block_radix_sort<uint32_t, kFinThreads, I, uint32_t>;
+
+union SortStorage {
+    typename BlockSort<1>::storage_type s1;
+    typename BlockSort<2>::storage_type s2;
+    typename BlockSort<4>::storage_type s4;
+    typename BlockSort<kTileItems>::storage_type s8;
+};
+
+struct RowShared {
+    SortStorage sort;
+    uint64_t key[kTile];           // staged keys and values of the tile, by load index
+    int32_t val[kTile];
+    uint64_t first[kFinThreads];   // first / last key of each thread after a sort
+    uint64_t last[kFinThreads];
+    int32_t wave[kFinThreads / 64][2];
+    ExactRow ri;
+};
+
+template <int I>
+__device__ __forceinline__ typename BlockSort<I>::storage_type& sort_storage(RowShared& sh) {
+    if constexpr (I == 1) return sh.sort.s1;
+    else if constexpr (I == 2) return sh.sort.s2;
+    else if constexpr (I == 4) return sh.sort.s4;
+    else return sh.sort.s8;
+}
+
+// Order-preserving key of an FP32 value (-0 taken as +0).
+__device__ __forceinline__ uint32_t order_key32(float f) {
+    const uint32_t b = (uint32_t)__float_as_int(f + 0.0f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// Stage points [0, n) (n <= I * threads) of one list and sort them: thread t
+// receives the staging indices of ranks t*I .. t*I+I-1 (ranks past n:
+// padding).
+template <int N, int I>
+__device__ __forceinline__ void sort_tile(const Point* __restrict__ pts, int64_t n, int32_t sign, Dir<N> xi,
+                                          uint32_t (&idx)[I], RowShared& sh) {
+    uint32_t key32[I];
+#pragma unroll
+    for (int u = 0; u < I; ++u) {
+        const int j = u * kFinThreads + threadIdx.x;
+        key32[u] = 0xFFFFFFFFu;
+        idx[u] = (uint32_t)j;
+        if (j < n) {
+            const Point pt = pts[j];
+            const double p = project<N>(xi.v, pt.x);
+            sh.key[j] = order_key(p);
+            sh.val[j] = sign * (int32_t)pt.val;
+            key32[u] = order_key32((float)p);
+        }
+    }
+    BlockSort<I>().sort(key32, idx, sort_storage<I>(sh));
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)t * I;
+    int bad = 0;
+    uint64_t prev = 0;
+#pragma unroll
+    for (int u = 0; u < I; ++u) {
+        const uint64_t k = i0 + u < n ? sh.key[idx[u]] : ~0ull;
+        if (u == 0) sh.first[t] = k;
+        else if (k < prev) bad = 1;
+        prev = k;
+    }
+    __syncthreads();
+    if (t + 1 < kFinThreads && sh.first[t + 1] < prev) bad = 1;
+    if (__syncthreads_or(bad)) {
+        // exact order: low halves, then high halves (the sort is stable)
+#pragma unroll
+        for (int u = 0; u < I; ++u) key32[u] = i0 + u < n ? (uint32_t)sh.key[idx[u]] : 0xFFFFFFFFu;
+        BlockSort<I>().sort(key32, idx, sort_storage<I>(sh));
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < I; ++u) key32[u] = i0 + u < n ? (uint32_t)(sh.key[idx[u]] >> 32) : 0xFFFFFFFFu;
+        BlockSort<I>().sort(key32, idx, sort_storage<I>(sh));
+        __syncthreads();
+    }
+}
+
+// Distinct entries of a sorted tile (staging indices in registers, blocked),
+// as merge_segment does for a sorted list in memory.
+template <int I>
+__device__ __forceinline__ int64_t merge_tile(const uint32_t (&idx)[I], int64_t n, double* out_T, int32_t* out_E,
+                                              RowShared& sh) {
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)t * I;
+    sh.first[t] = i0 < n ? sh.key[idx[0]] : ~0ull;
+    sh.last[t] = i0 + I - 1 < n ? sh.key[idx[I - 1]] : ~0ull;
+    __syncthreads();
+    const uint64_t before = t > 0 ? sh.last[t - 1] : 0;
+    const uint64_t after = t + 1 < kFinThreads ? sh.first[t + 1] : 0;
+    int32_t heads = 0, sum = 0;
+    uint64_t prev = before;
+#pragma unroll
+    for (int u = 0; u < I; ++u) {
+        if (i0 + u < n) {
+            const uint64_t k = sh.key[idx[u]];
+            heads += (i0 + u == 0 || k != prev) ? 1 : 0;
+            sum += sh.val[idx[u]];
+            prev = k;
+        }
+    }
+    int32_t h_ex, s_ex, h_tot, s_tot;
+    block_scan2(heads, sum, h_ex, s_ex, h_tot, s_tot, sh.wave);
+    int32_t h = h_ex, c = s_ex;
+    prev = before;
+#pragma unroll
+    for (int u = 0; u < I; ++u) {
+        const int64_t i = i0 + u;
+        if (i >= n) break;
+        const uint64_t k = sh.key[idx[u]];
+        h += (i == 0 || k != prev) ? 1 : 0;
+        c += sh.val[idx[u]];
+        const uint64_t nk = u + 1 < I ? (i + 1 < n ? sh.key[idx[u + 1]] : ~0ull) : after;
+        if (i + 1 == n || nk != k) {
+            out_T[h - 1] = key_value(k);
+            out_E[h - 1] = c;
+        }
+        prev = k;
+    }
+    __syncthreads();   // staging and first/last are reused by the next tile
+    return h_tot;
+}
+
+// Merge sorted runs A [0, la) and B [0, lb) into D (ties: A first); every
+// thread of the workgroup takes kMergeItems consecutive outputs per step,
+// found by a merge-path search.
+__device__ __forceinline__ void merge_runs(const uint64_t* __restrict__ ka, const int32_t* __restrict__ va, int64_t la,
+                                           const uint64_t* __restrict__ kb, const int32_t* __restrict__ vb, int64_t lb,
+                                           uint64_t* __restrict__ kd, int32_t* __restrict__ vd) {
+    const int64_t L = la + lb;
+    for (int64_t d0 = 0; d0 < L; d0 += (int64_t)kFinThreads * kMergeItems) {
+        const int64_t d = d0 + (int64_t)threadIdx.x * kMergeItems;
+        if (d >= L) continue;
+        int64_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (ka[mid] <= kb[d - 1 - mid]) lo = mid + 1; else hi = mid;
+        }
+        int64_t i = lo, j = d - lo;
+        const int64_t end = d + kMergeItems < L ? d + kMergeItems : L;
+        for (int64_t o = d; o < end; ++o) {
+            if (j >= lb || (i < la && ka[i] <= kb[j])) {
+                kd[o] = ka[i];
+                vd[o] = va[i];
+                ++i;
+            } else {
+                kd[o] = kb[j];
+                vd[o] = vb[j];
+                ++j;
+            }
+        }
+    }
+}
+
+// Sort one tile of a long list and store it, in order, at ka/va.
+template <int N, int I>
+__device__ __noinline__ void store_tile(const Point* pts, int64_t m, int32_t sign, Dir<N> xi,
+                                        uint64_t* ka, int32_t* va, RowShared& sh) {
+    uint32_t idx[I];
+    sort_tile<N, I>(pts, m, sign, xi, idx, sh);
+#pragma unroll
+    for (int u = 0; u < I; ++u) {
+        const int64_t i = (int64_t)threadIdx.x * I + u;
+        if (i < m) {
+            ka[i] = sh.key[idx[u]];
+            va[i] = sh.val[idx[u]];
+        }
+    }
+    __syncthreads();
+}
+
+// A list longer than one tile: sorted tiles into workspace A, pairwise merges
+// between A and B, then the merge of equal keys from memory.
+template <int N>
+__device__ __noinline__ int64_t build_long(const Point* pts, int64_t n, int32_t sign, Dir<N> xi, uint64_t* ka,
+                                           int32_t* va, uint64_t* kb, int32_t* vb, double* out_T, int32_t* out_E,
+                                           RowShared& sh) {
+    for (int64_t c0 = 0; c0 < n; c0 += kTile) {
+        const int64_t m = n - c0 < kTile ? n - c0 : kTile;
+        if (m <= kFinThreads) store_tile<N, 1>(pts + c0, m, sign, xi, ka + c0, va + c0, sh);
+        else if (m <= 4 * kFinThreads) store_tile<N, 4>(pts + c0, m, sign, xi, ka + c0, va + c0, sh);
+        else store_tile<N, kTileItems>(pts + c0, m, sign, xi, ka + c0, va + c0, sh);
+    }
+    for (int64_t width = kTile; width < n; width *= 2) {
+        for (int64_t lo = 0; lo < n; lo += 2 * width) {
+            const int64_t la = n - lo < width ? n - lo : width;
+            const int64_t rest = n - lo - la;
+            const int64_t lb = rest < width ? rest : width;
+            merge_runs(ka + lo, va + lo, la, ka + lo + la, va + lo + la, lb, kb + lo, vb + lo);
+        }
+        __syncthreads();
+        uint64_t* tk = ka; ka = kb; kb = tk;
+        int32_t* tv = va; va = vb; vb = tv;
+    }
+    return merge_segment(ka, va, 0, n, out_T, out_E, sh.wave);
+}
+
+// Distinct entries of one list (n points at pts), values times sign.
+template <int N, int I>
+__device__ __noinline__ int64_t build_tile(const Point* pts, int64_t n, int32_t sign, Dir<N> xi,
+                                           double* out_T, int32_t* out_E, RowShared& sh) {
+    uint32_t idx[I];
+    sort_tile<N, I>(pts, n, sign, xi, idx, sh);
+    return merge_tile<I>(idx, n, out_T, out_E, sh);
+}
+
+template <int N>
+__device__ int64_t build_segment(const ExactArgs& a, const Point* pts, int64_t n, int32_t sign, Dir<N> xi,
+                                 int64_t w0, double* out_T, int32_t* out_E, RowShared& sh) {
+    if (n <= 0) return 0;
+    if (n <= kFinThreads) return build_tile<N, 1>(pts, n, sign, xi, out_T, out_E, sh);
+    if (n <= 2 * kFinThreads) return build_tile<N, 2>(pts, n, sign, xi, out_T, out_E, sh);
+    if (n <= 4 * kFinThreads) return build_tile<N, 4>(pts, n, sign, xi, out_T, out_E, sh);
+    if (n <= kTile) return build_tile<N, kTileItems>(pts, n, sign, xi, out_T, out_E, sh);
+    return build_long<N>(pts, n, sign, xi, a.keys_a + w0, a.vals_a + w0, a.keys_b + w0, a.vals_b + w0, out_T, out_E,
+                         sh);
+}
+
+// Row record of row r (thread 0 of the workgroup), with the check of the
+// caller's offsets: a row that needs more room than its offsets give, or
+// reaches past the capacity, is marked -1.
+template <int N>
+__device__ __forceinline__ void load_row(const ExactArgs& a, int64_t r, bool report, RowShared& sh) {
+    if (threadIdx.x == 0) {
+        ExactRow ri;
+        const int64_t need = row_info<N>(a, r, ri);
+        const int64_t b = a.row_off[r], e = a.row_off[r + 1];
+        ri.base = b;
+        if (!(b >= 0 && e <= a.capacity && e - b >= need)) {
+            ri.valid = -1;
+            if (report) raise_error(a.err, ECT_DEVERR_LAYOUT);
+        } else if (!ri.valid && report) {
+            raise_error(a.err, ECT_DEVERR_NONFINITE);
+        }
+        sh.ri = ri;
+    }
+    __syncthreads();
+}
+
+// Workgroup (r, part): part 0 builds the ECT row from the classical list, or
+// the (T, E') part of a Radon row from the ordinary list (values -D); part 1
+// (Radon only) builds the distinct classical projections and their running
+// sums into the workspace (ct, cum at the row's classical slots), which
+// exact_radon_kernel moves behind (T, E') as Ec = E'[last T < Tc] + own
+// values.  A row marked -1 gets length 0 and raises ECT_DEVERR_LAYOUT.
+// Four waves per SIMD (two workgroups per compute unit) measured faster than
+// the register allocation without the bound, despite a few spilled registers.
+template <int N>
+__global__ void __launch_bounds__(kFinThreads, 4) exact_kernel(ExactArgs a) {
+    __shared__ RowShared sh;
     const bool radon = a.kind == ECT_EXACT_RADON;
+    const int64_t r = radon ? blockIdx.x >> 1 : blockIdx.x;
+    const int part = radon ? (int)(blockIdx.x & 1) : 0;
+    load_row<N>(a, r, part == 0, sh);
+    const ExactRow ri = sh.ri;
     if (ri.valid < 0) {
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == 0 && part == 0) {
             if (radon) {
                 a.len[2 * r] = 0;
                 a.len[2 * r + 1] = 0;
@@ -282,49 +484,62 @@ __global__ void __launch_bounds__(kFinThreads) exact_finalize_kernel(ExactArgs a
         return;
     }
     const int64_t base = ri.base;
-    if (threadIdx.x == 0) {
-        a.T[base] = -HUGE_VAL;
-        a.E[base] = 0;
-    }
-    const int64_t n1 = radon ? ri.no : ri.nc;
-    int64_t d1 = 0;
-    if (ri.valid == 1) d1 = merge_segment(a.keys_out, a.vals_out, base, base + n1, a.T + base + 1, a.E + base + 1, s_wave);
-    const int64_t len1 = d1 + 1;
-    if (!radon) {
-        if (threadIdx.x == 0) a.len[r] = len1;
-        return;
-    }
-    int64_t d2 = 0;
-    if (ri.valid == 1) {
-        const int64_t cb = base + ri.no + 1;
-        d2 = merge_segment(a.keys_out, a.vals_out, cb, cb + ri.nc, a.T + base + len1, a.cum + base + len1, s_wave);
-    }
-    if (threadIdx.x == 0) {
-        a.len[2 * r] = len1;
-        a.len[2 * r + 1] = d2;
+    Dir<N> xi;
+#pragma unroll
+    for (int c = 0; c < N; ++c) xi.v[c] = ri.xi[c];
+    if (part == 0) {
+        if (threadIdx.x == 0) {
+            a.T[base] = -HUGE_VAL;
+            a.E[base] = 0;
+        }
+        int64_t d = 0;
+        if (ri.valid == 1) {
+            if (radon) d = build_segment<N>(a, a.points + ri.po, ri.no, ri.sign_o, xi, base, a.T + base + 1,
+                                            a.E + base + 1, sh);
+            else d = build_segment<N>(a, a.points + ri.pc, ri.nc, 1, xi, base, a.T + base + 1, a.E + base + 1, sh);
+        }
+        if (threadIdx.x == 0) a.len[radon ? 2 * r : r] = d + 1;
+    } else {
+        const int64_t w0 = base + ri.no + 1;
+        int64_t d = 0;
+        if (ri.valid == 1) d = build_segment<N>(a, a.points + ri.pc, ri.nc, 1, xi, w0, a.ct + w0, a.cum + w0, sh);
+        if (threadIdx.x == 0) a.len[2 * r + 1] = d;
     }
 }
 
-// Radon point values: Ec[k] = E'[largest i with T[i] < Tc[k]] + the classical
-// values at Tc[k] (difference of consecutive running sums).
-__global__ void __launch_bounds__(kFinThreads) exact_radon_fix_kernel(ExactArgs a) {
+// Radon rows: the distinct classical projections move right behind (T, E')
+// with Ec[k] = E'[largest i with T[i] < Tc[k]] + the classical values at
+// Tc[k] (difference of consecutive running sums).
+template <int N>
+__global__ void __launch_bounds__(kFixThreads) exact_radon_kernel(ExactArgs a) {
+    __shared__ ExactRow s_ri;
     const int64_t r = blockIdx.x;
-    const ExactRow ri = a.rowrec[r];
+    if (threadIdx.x == 0) {
+        ExactRow ri;
+        const int64_t need = row_info<N>(a, r, ri);
+        const int64_t b = a.row_off[r], e = a.row_off[r + 1];
+        ri.base = b;
+        if (!(b >= 0 && e <= a.capacity && e - b >= need)) ri.valid = -1;
+        s_ri = ri;
+    }
+    __syncthreads();
+    const ExactRow ri = s_ri;
     if (ri.valid != 1) return;
     const int64_t base = ri.base;
     const int64_t lo_n = a.len[2 * r], nc = a.len[2 * r + 1];
+    const int64_t w0 = base + ri.no + 1;
     const double* T = a.T + base;
     const int32_t* Ep = a.E + base;
     const int64_t cb = base + lo_n;
-    for (int64_t k = threadIdx.x; k < nc; k += kFinThreads) {
-        const double tc = a.T[cb + k];
-        const int32_t own = a.cum[cb + k] - (k > 0 ? a.cum[cb + k - 1] : 0);
-        // T[0] = -inf < tc: find the last index with T[i] < tc
-        int64_t lo = 0, hi = lo_n - 1;
+    for (int64_t k = threadIdx.x; k < nc; k += kFixThreads) {
+        const double tc = a.ct[w0 + k];
+        const int32_t own = a.cum[w0 + k] - (k > 0 ? a.cum[w0 + k - 1] : 0);
+        int64_t lo = 0, hi = lo_n - 1;   // last index with T[i] < tc (T[0] = -inf)
         while (lo < hi) {
             const int64_t mid = (lo + hi + 1) >> 1;
             if (T[mid] < tc) lo = mid; else hi = mid - 1;
         }
+        a.T[cb + k] = tc;
         a.E[cb + k] = Ep[lo] + own;
     }
 }
@@ -374,19 +589,11 @@ __global__ void __launch_bounds__(kEvalThreads) exact_eval_kernel(int32_t kind, 
     out[r * M + j] = res;
 }
 
-// The size queries and the launches go through these two calls, so that both
-// instantiate the same rocPRIM templates.
+// The size query and the launch go through this call, so that both
+// instantiate the same rocPRIM template.
 hipError_t scan_call(void* tmp, size_t& bytes, const int64_t* in, int64_t* out, int64_t rows, hipStream_t stream) {
     return rocprim::exclusive_scan(tmp, bytes, in, out, (int64_t)0, (size_t)(rows + 1), rocprim::plus<int64_t>(),
                                    stream);
-}
-
-hipError_t sort_call(void* tmp, size_t& bytes, const ExactArgs& a, int64_t capacity, int64_t segments,
-                     hipStream_t stream) {
-    return rocprim::segmented_radix_sort_pairs(tmp, bytes, (const uint64_t*)a.keys_in, a.keys_out,
-                                               (const int32_t*)a.vals_in, a.vals_out, (unsigned)capacity,
-                                               (unsigned)segments, (const uint32_t*)a.seg_begin,
-                                               (const uint32_t*)a.seg_end, 0, 64, stream);
 }
 
 template <int N>
@@ -396,42 +603,11 @@ hipError_t launch_need(const ExactArgs& a, int64_t* need, hipStream_t stream) {
     return hipGetLastError();
 }
 
-template <int N>
-hipError_t launch_exact_typed(const ExactArgs& a, void* sort_tmp, size_t sort_bytes, hipStream_t stream) {
-    if (a.rows == 0) return hipSuccess;
-    const int64_t rb = (a.rows + kRowThreads - 1) / kRowThreads;
-    hipLaunchKernelGGL((exact_rows_kernel<N>), dim3((unsigned)rb), dim3(kRowThreads), 0, stream, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (a.capacity > 0) {
-        const int64_t sb = (a.capacity + kSlotThreads - 1) / kSlotThreads;
-        hipLaunchKernelGGL((exact_project_kernel<N>), dim3((unsigned)sb), dim3(kSlotThreads), 0, stream, a);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        size_t bytes = sort_bytes;
-        e = sort_call(sort_tmp, bytes, a, a.capacity, exact_segments(a.kind, a.rows), stream);
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(exact_finalize_kernel, dim3((unsigned)a.rows), dim3(kFinThreads), 0, stream, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (a.kind == ECT_EXACT_RADON) {
-        hipLaunchKernelGGL(exact_radon_fix_kernel, dim3((unsigned)a.rows), dim3(kFinThreads), 0, stream, a);
-        e = hipGetLastError();
-    }
-    return e;
-}
-
 }  // namespace
 
 size_t exact_layout_scan_bytes(int64_t rows) {
     size_t bytes = 0;
     return scan_call(nullptr, bytes, nullptr, nullptr, rows, (hipStream_t)0) == hipSuccess ? bytes : 0;
-}
-
-size_t exact_sort_bytes(int32_t kind, int64_t rows, int64_t capacity) {
-    size_t bytes = 0;
-    ExactArgs a{};
-    return sort_call(nullptr, bytes, a, capacity, exact_segments(kind, rows), (hipStream_t)0) == hipSuccess ? bytes
-                                                                                                           : 0;
 }
 
 hipError_t launch_exact_layout(int ndim, const ExactArgs& a, int64_t* need, void* scan_tmp, size_t scan_bytes,
@@ -442,9 +618,21 @@ hipError_t launch_exact_layout(int ndim, const ExactArgs& a, int64_t* need, void
     return scan_call(scan_tmp, bytes, need, a.row_off_out, a.rows, stream);
 }
 
-hipError_t launch_exact(int ndim, const ExactArgs& a, void* sort_tmp, size_t sort_bytes, hipStream_t stream) {
-    return ndim == 2 ? launch_exact_typed<2>(a, sort_tmp, sort_bytes, stream)
-                     : launch_exact_typed<3>(a, sort_tmp, sort_bytes, stream);
+hipError_t launch_exact(int ndim, const ExactArgs& a, hipStream_t stream) {
+    if (a.rows == 0) return hipSuccess;
+    const bool radon = a.kind == ECT_EXACT_RADON;
+    const unsigned grid = (unsigned)(radon ? 2 * a.rows : a.rows);
+    if (ndim == 2)
+        hipLaunchKernelGGL((exact_kernel<2>), dim3(grid), dim3(kFinThreads), 0, stream, a);
+    else
+        hipLaunchKernelGGL((exact_kernel<3>), dim3(grid), dim3(kFinThreads), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !radon) return e;
+    if (ndim == 2)
+        hipLaunchKernelGGL((exact_radon_kernel<2>), dim3((unsigned)a.rows), dim3(kFixThreads), 0, stream, a);
+    else
+        hipLaunchKernelGGL((exact_radon_kernel<3>), dim3((unsigned)a.rows), dim3(kFixThreads), 0, stream, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_exact_eval(int32_t kind, int64_t rows, const int64_t* row_off, const double* T, const int32_t* E,

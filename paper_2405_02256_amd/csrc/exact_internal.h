@@ -30,31 +30,25 @@ struct ExactArgs {
     const int64_t* row_off;   // [rows + 1]
     int64_t* row_off_out;     // layout: written
     int64_t capacity;         // output entries
-    ExactRow* rowrec;
-    uint32_t* seg_begin;
-    uint32_t* seg_end;
-    uint64_t* keys_in;
-    uint64_t* keys_out;
-    int32_t* vals_in;
-    int32_t* vals_out;
-    int32_t* cum;             // Radon: running classical sums at the distinct projections
+    uint64_t* keys_a;         // [capacity] x 2: sorted tiles and merge passes of lists longer than one tile
+    uint64_t* keys_b;
+    int32_t* vals_a;
+    int32_t* vals_b;
+    double* ct;               // Radon [capacity]: distinct classical projections, at the row's classical slots
+    int32_t* cum;             // Radon [capacity]: their running classical sums
     double* T;
     int32_t* E;
     int64_t* len;
 };
 
-__host__ __device__ inline int64_t exact_segments(int32_t kind, int64_t rows) {
-    return kind == ECT_EXACT_ECT ? rows : 2 * rows;
-}
-
-// Workspace of the row-offset scan (layout call) and of the segmented sort.
+// Workspace of the row-offset scan (layout call).
 size_t exact_layout_scan_bytes(int64_t rows);
-size_t exact_sort_bytes(int32_t kind, int64_t rows, int64_t capacity);
 
 // Entries per row, exclusive scan into a.row_off_out ([rows + 1]).
 hipError_t launch_exact_layout(int ndim, const ExactArgs& a, int64_t* need, void* scan_tmp, size_t scan_bytes,
                                hipStream_t stream);
-hipError_t launch_exact(int ndim, const ExactArgs& a, void* sort_tmp, size_t sort_bytes, hipStream_t stream);
+// One workgroup per row (exact_kernel).
+hipError_t launch_exact(int ndim, const ExactArgs& a, hipStream_t stream);
 hipError_t launch_exact_eval(int32_t kind, int64_t rows, const int64_t* row_off, const double* T, const int32_t* E,
                              const int64_t* len, int64_t capacity, const double* thr, int32_t M, int32_t per_row,
                              int32_t* out, hipStream_t stream);

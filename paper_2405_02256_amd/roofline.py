@@ -25,8 +25,12 @@ fused pass; then per kernel:
             cotangent combine 3, n fmas                               -> 17 + n
   ECT       projection 2n-1, bin guess 6 (sub, mul, ceil, max, min, cvt),
             fix-up compares 2, LDS add 1                              -> 2n + 8
+  Radon     as ECT plus one equality compare (the point or open-ray
+            bin), over classical and ordinary points                  -> 2n + 9
 Precompute is bounded by HBM: bytes = pixels read once + 32 B per list entry
-written + list offsets.
+written + list offsets.  The exact representations are priced against HBM with
+the bytes the operation cannot avoid: 32 B per critical point read and 12 B
+per output entry (T and E) written.
 """
 from __future__ import annotations
 
@@ -39,6 +43,8 @@ def slots_per_pair(kind: str, n: int, small_fraction: float = 1.0) -> float:
     """kind: 'fourier', 'laplace', 'bessel', '+'-joined fused kernels, 'fourier_bwd' or 'ect'."""
     if kind == "ect":
         return 2 * n + 8
+    if kind == "radon":
+        return 2 * n + 9
     if kind == "fourier_bwd":
         return (2 * n - 1) + 17 + n
     per = {"fourier": 16.0, "laplace": 12.0,
