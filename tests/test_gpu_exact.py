@@ -186,3 +186,31 @@ def test_exact_rejects_offsets_without_room(api):
         assert np.array_equal(Tt[o[r]:o[r] + L[r]].cpu().numpy(), To)
         assert np.array_equal(Et[o[r]:o[r] + L[r]].cpu().numpy(), Eo)
     assert plan.check() & N.DEVERR_LAYOUT
+
+
+def test_exact_near_ties_in_fp32_and_long_lists(api):
+    """Directions whose projections differ below FP32 resolution (the tiles
+    fall back to the exact 64-bit order) and lists of 16k-26k points (several
+    sorted tiles merged in the workspace, an odd number of runs included)."""
+    rng = np.random.default_rng(905)
+    img = W.random_image(rng, (200, 200), 8)
+    dirs = np.array([[1.0, 1e-13], [1e-13, -1.0], [0.5, 0.5 + 1e-12], [-0.7, 0.3], [1.0, 0.0]])
+    plan = api.Plan(T(img))
+    for kind in ("ect", "radon"):
+        rep = plan.exact(T(dirs), kind)
+        check_rows(rep, [img] * len(dirs), dirs)
+    small = W.random_image(rng, (40, 37), 5)
+    plan2 = api.Plan(T(small))
+    d2 = np.array([[1.0, 3e-14], [2e-15, 1.0], [-1.0, -1e-12]])
+    for kind in ("ect", "radon"):
+        check_rows(plan2.exact(T(d2), kind), [small] * len(d2), d2)
+
+
+def test_exact_representation_is_strictly_increasing_grf512(api):
+    w = W.grf_512(2, n_xi=8)
+    plan = api.Plan(T(w.images[0]))
+    for kind in ("ect", "radon"):
+        for row in plan.exact(T(w.ect_dirs), kind).to_host():
+            assert np.all(np.diff(row[0]) > 0)
+            if kind == "radon":
+                assert np.all(np.diff(row[2]) > 0)
