@@ -52,7 +52,8 @@
 #include <omp.h>
 #endif
 
-#define MAXD 3
+#define MAXD 4
+#define MAXV (1 << MAXD)   /* vertices of a cell, at most */
 
 enum { OR_PRIMAL = 0, OR_DUAL = 1 };
 enum { OR_FOURIER = 0, OR_LAPLACE = 1, OR_BESSEL = 2 };
@@ -114,6 +115,16 @@ static long long vertex_index(const ogrid* g, const int k[MAXD]) {
     return idx;
 }
 
+/* Next point of the box lo..hi (every axis, in steps of `step`, axis 0
+ * fastest); returns 0 after the last one. */
+static int box_next(int* q, const int* lo, const int* hi, int step) {
+    for (int a = 0; a < MAXD; ++a) {
+        if (q[a] + step <= hi[a]) { q[a] += step; return 1; }
+        q[a] = lo[a];
+    }
+    return 0;
+}
+
 /* Value of one cell.  Primal: min over coface top cells (all-odd coordinates
  * within one step of c and inside the grid).  Dual: min over its vertices. */
 static int32_t cell_value(const ogrid* g, const int c[MAXD], const int32_t* px, int construction) {
@@ -132,15 +143,14 @@ static int32_t cell_value(const ogrid* g, const int c[MAXD], const int32_t* px, 
     int32_t best = 0;
     int have = 0;
     int q[MAXD];
-    for (q[2] = lo[2]; q[2] <= hi[2]; q[2] += 2)
-        for (q[1] = lo[1]; q[1] <= hi[1]; q[1] += 2)
-            for (q[0] = lo[0]; q[0] <= hi[0]; q[0] += 2) {
-                int p[MAXD];
-                for (int a = 0; a < MAXD; ++a)
-                    p[a] = construction == OR_PRIMAL ? (q[a] - 1) / 2 : q[a] / 2;
-                int32_t v = px[pixel_index(g, p)];
-                if (!have || v < best) { best = v; have = 1; }
-            }
+    for (int a = 0; a < MAXD; ++a) q[a] = lo[a];
+    do {
+        int p[MAXD];
+        for (int a = 0; a < MAXD; ++a)
+            p[a] = construction == OR_PRIMAL ? (q[a] - 1) / 2 : q[a] / 2;
+        int32_t v = px[pixel_index(g, p)];
+        if (!have || v < best) { best = v; have = 1; }
+    } while (box_next(q, lo, hi, 2));
     return best;
 }
 
@@ -176,7 +186,7 @@ typedef struct {
     int32_t* value;      /* phi */
     int8_t* dim;
     int8_t* nv;          /* number of vertices (2^dim) */
-    long long* verts;    /* [count][8] vertex indices */
+    long long* verts;    /* [count][MAXV] vertex indices */
     long long* vidx;     /* unused slots = -1 */
 } cellset;
 
@@ -198,7 +208,7 @@ static int cellset_build(const ogrid* g, const int32_t* px, int construction, in
     cs->value = (int32_t*)malloc(sizeof(int32_t) * (cap ? cap : 1));
     cs->dim = (int8_t*)malloc(cap ? cap : 1);
     cs->nv = (int8_t*)malloc(cap ? cap : 1);
-    cs->verts = (long long*)malloc(sizeof(long long) * 8 * (cap ? cap : 1));
+    cs->verts = (long long*)malloc(sizeof(long long) * MAXV * (cap ? cap : 1));
     if (!cs->value || !cs->dim || !cs->nv || !cs->verts) { cellset_free(cs); return 1; }
     long long m = 0;
     for (long long id = 0; id < g->ncell; ++id) {
@@ -217,13 +227,12 @@ static int cellset_build(const ogrid* g, const int32_t* px, int construction, in
         }
         int nv = 0;
         int q[MAXD];
-        for (q[2] = lo[2]; q[2] <= hi[2]; q[2] += 2)
-            for (q[1] = lo[1]; q[1] <= hi[1]; q[1] += 2)
-                for (q[0] = lo[0]; q[0] <= hi[0]; q[0] += 2) {
-                    int k[MAXD];
-                    for (int a = 0; a < MAXD; ++a) k[a] = q[a] / 2;
-                    cs->verts[m * 8 + nv++] = vertex_index(g, k);
-                }
+        for (int a = 0; a < MAXD; ++a) q[a] = lo[a];
+        do {
+            int k[MAXD];
+            for (int a = 0; a < MAXD; ++a) k[a] = q[a] / 2;
+            cs->verts[m * MAXV + nv++] = vertex_index(g, k);
+        } while (box_next(q, lo, hi, 2));
         cs->nv[m] = (int8_t)nv;
         ++m;
     }
@@ -288,9 +297,9 @@ int oracle_ect(int n, const int32_t* dims, const int32_t* px, int construction,
                 for (long long v = 0; v < g.nvert; ++v) u[v] = project(n, xi, x + v * MAXD);
                 memset(hist, 0, sizeof(long long) * (M + 1));
                 for (long long i = 0; i < cs.count; ++i) {
-                    double top = u[cs.verts[i * 8]];
+                    double top = u[cs.verts[i * MAXV]];
                     for (int q = 1; q < cs.nv[i]; ++q) {
-                        double w = u[cs.verts[i * 8 + q]];
+                        double w = u[cs.verts[i * MAXV + q]];
                         if (w > top) top = w;
                     }
                     long long contrib = (cs.dim[i] & 1) ? -(long long)cs.value[i] : (long long)cs.value[i];
@@ -409,7 +418,7 @@ int oracle_hybrid(int n, const int32_t* dims, const int32_t* px, int constructio
     /* vertices touched by contributing cells */
     unsigned char* used = (unsigned char*)calloc(g.nvert ? g.nvert : 1, 1);
     for (long long i = 0; i < cs.count; ++i)
-        for (int q = 0; q < cs.nv[i]; ++q) used[cs.verts[i * 8 + q]] = 1;
+        for (int q = 0; q < cs.nv[i]; ++q) used[cs.verts[i * MAXV + q]] = 1;
     int err = 0;
 #pragma omp parallel
     {
@@ -442,9 +451,9 @@ int oracle_hybrid(int n, const int32_t* dims, const int32_t* px, int constructio
                 }
                 csum ar = {0.0, 0.0}, ai = {0.0, 0.0};
                 for (long long i = 0; i < cs.count; ++i) {
-                    long long top = cs.verts[i * 8], bot = top;
+                    long long top = cs.verts[i * MAXV], bot = top;
                     for (int q = 1; q < cs.nv[i]; ++q) {
-                        long long w = cs.verts[i * 8 + q];
+                        long long w = cs.verts[i * MAXV + q];
                         if (u[w] > u[top]) top = w;
                         if (u[w] < u[bot]) bot = w;
                     }
@@ -484,7 +493,7 @@ int oracle_hybrid_grad(int n, const int32_t* dims, const int32_t* px, int constr
     if (!x) { cellset_free(&cs); return 3; }
     unsigned char* used = (unsigned char*)calloc(g.nvert ? g.nvert : 1, 1);
     for (long long i = 0; i < cs.count; ++i)
-        for (int q = 0; q < cs.nv[i]; ++q) used[cs.verts[i * 8 + q]] = 1;
+        for (int q = 0; q < cs.nv[i]; ++q) used[cs.verts[i * MAXV + q]] = 1;
     double* gs_part = (double*)calloc(nq > 0 ? nq : 1, sizeof(double));
     int err = 0;
 #pragma omp parallel
@@ -517,12 +526,13 @@ int oracle_hybrid_grad(int n, const int32_t* dims, const int32_t* px, int constr
                         kp[v] = gr * j0(z);
                     }
                 }
-                csum acc[MAXD] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+                csum acc[MAXD];
+                for (int a = 0; a < MAXD; ++a) acc[a].hi = acc[a].lo = 0.0;
                 csum du = {0.0, 0.0}, y = {0.0, 0.0};
                 for (long long i = 0; i < cs.count; ++i) {
-                    long long top = cs.verts[i * 8], bot = top;
+                    long long top = cs.verts[i * MAXV], bot = top;
                     for (int q = 1; q < cs.nv[i]; ++q) {
-                        long long w = cs.verts[i * 8 + q];
+                        long long w = cs.verts[i * MAXV + q];
                         if (u[w] > u[top]) top = w;
                         if (u[w] < u[bot]) bot = w;
                     }
@@ -567,31 +577,32 @@ int oracle_critical_values(int n, const int32_t* dims, const int32_t* px, int co
     const int ne = 1 << n;
 #pragma omp parallel for schedule(static)
     for (long long v = 0; v < g.nvert; ++v) {
-        int k[MAXD] = {0, 0, 0};
+        int k[MAXD] = {0};
         long long r = v;
         for (int a = 0; a < n; ++a) { k[a] = (int)(r % g.V[a]); r /= g.V[a]; }
+        /* the star of the vertex: offsets in {-1, 0, 1} along the image's axes */
+        int olo[MAXD], ohi[MAXD];
+        for (int a = 0; a < MAXD; ++a) { olo[a] = a < n ? -1 : 0; ohi[a] = a < n ? 1 : 0; }
         for (int e = 0; e < ne; ++e) {
             long long lw = 0, up = 0;
             int off[MAXD];
-            for (off[2] = -1; off[2] <= 1; ++off[2])
-                for (off[1] = -1; off[1] <= 1; ++off[1])
-                    for (off[0] = -1; off[0] <= 1; ++off[0]) {
-                        int c[MAXD] = {0, 0, 0};
-                        int inside = 1, is_low = 1, is_up = 1;
-                        for (int a = 0; a < MAXD; ++a) {
-                            if (a >= n) { if (off[a] != 0) inside = 0; continue; }
-                            c[a] = 2 * k[a] + off[a];
-                            if (c[a] < 0 || c[a] > 2 * g.N[a]) inside = 0;
-                            int eps = (e >> a) & 1 ? -1 : 1;
-                            if (off[a] != 0 && off[a] != -eps) is_low = 0;
-                            if (off[a] != 0 && off[a] != eps) is_up = 0;
-                        }
-                        if (!inside || (!is_low && !is_up)) continue;
-                        long long val = cell_value(&g, c, px, construction);
-                        if (cell_dim(&g, c) & 1) val = -val;
-                        if (is_low) lw += val;
-                        if (is_up) up += val;
-                    }
+            for (int a = 0; a < MAXD; ++a) off[a] = olo[a];
+            do {
+                int c[MAXD] = {0};
+                int inside = 1, is_low = 1, is_up = 1;
+                for (int a = 0; a < n; ++a) {
+                    c[a] = 2 * k[a] + off[a];
+                    if (c[a] < 0 || c[a] > 2 * g.N[a]) inside = 0;
+                    int eps = (e >> a) & 1 ? -1 : 1;
+                    if (off[a] != 0 && off[a] != -eps) is_low = 0;
+                    if (off[a] != 0 && off[a] != eps) is_up = 0;
+                }
+                if (!inside || (!is_low && !is_up)) continue;
+                long long val = cell_value(&g, c, px, construction);
+                if (cell_dim(&g, c) & 1) val = -val;
+                if (is_low) lw += val;
+                if (is_up) up += val;
+            } while (box_next(off, olo, ohi, 1));
             lower[v * ne + e] = (int32_t)lw;
             ordinary[v * ne + e] = (int32_t)(up - lw);
         }
@@ -660,9 +671,9 @@ int oracle_radon(int n, const int32_t* dims, const int32_t* px, int construction
                 memset(diff, 0, sizeof(long long) * (M + 1));
                 memset(point, 0, sizeof(long long) * M);
                 for (long long i = 0; i < cs.count; ++i) {
-                    double lo = u[cs.verts[i * 8]], hi = lo;
+                    double lo = u[cs.verts[i * MAXV]], hi = lo;
                     for (int q = 1; q < cs.nv[i]; ++q) {
-                        const double w = u[cs.verts[i * 8 + q]];
+                        const double w = u[cs.verts[i * MAXV + q]];
                         if (w < lo) lo = w;
                         if (w > hi) hi = w;
                     }

@@ -24,6 +24,9 @@ Functions and the definitions they follow:
                            vector is attained at the vertex), tiny inputs.
 * ``ji0``                  integral_0^z J0(t) dt by Gauss-Legendre panels.
 
+Images have 1 to 4 axes (n-dimensional arrays, Sec. 4.1; all 2^n sign vectors,
+Sec. 4.2).
+
 Status: every function is pinned by the CPU tests in ``tests/test_oracle_*.py``
 against closed forms, the worked example of Appendix A, invariants and brute
 force on tiny inputs.
@@ -406,10 +409,15 @@ def ect_literal(img, dirs, thresholds, construction=PRIMAL, origin=None, spacing
     cells = [(dim, val, verts) for _, dim, val, verts in _cells_literal(img, construction) if val != 0]
     out = np.zeros((len(dirs), len(thresholds)), dtype=np.int64)
     for d, xi in enumerate(dirs):
+        proj = {}   # each vertex projected once per direction
+        for _, _, verts in cells:
+            for v in verts:
+                if v not in proj:
+                    proj[v] = _project(xi, _vertex_x(v, origin, spacing))
         for j, t in enumerate(thresholds):
             tot = 0
             for dim, val, verts in cells:
-                if all(_project(xi, _vertex_x(v, origin, spacing)) <= t for v in verts):
+                if all(proj[v] <= t for v in verts):
                     tot += (-1) ** dim * val
             out[d, j] = tot
     return out
@@ -423,7 +431,7 @@ def critical_values_literal(img, construction=PRIMAL, generic=None):
     """
     img = np.asarray(img)
     n = img.ndim
-    base = np.array([1.0, np.sqrt(2.0), np.sqrt(3.0)])[:n] if generic is None else np.asarray(generic)
+    base = np.array([1.0, np.sqrt(2.0), np.sqrt(3.0), np.sqrt(5.0)])[:n] if generic is None else np.asarray(generic)
     cells = list(_cells_literal(img, construction))
     vshape = vertex_shape(img, construction)
     V = list(reversed(vshape))
