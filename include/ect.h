@@ -93,7 +93,7 @@ typedef enum { ECT_FP32 = 0, ECT_FP64 = 1 } ect_precision;
 /* A batch of images.  Every image of a batch has the same ndim, dtype and
  * construction; sizes may differ (ragged batch). */
 typedef struct {
-    int32_t ndim;                  /* 2 or 3 */
+    int32_t ndim;                  /* 2, 3 or 4 (n-dimensional arrays, Sec. 4.1) */
     int32_t num_images;            /* >= 1 */
     const int32_t* dims;           /* HOST [num_images][ndim]: pixels along axis a (>= 1; dual needs >= 1) */
     const int64_t* pixel_offsets;  /* HOST [num_images]: element offset of image i in `pixels` */

@@ -77,8 +77,8 @@ class Plan:
         if dt not in _DTYPES or not images[0].is_cuda:
             raise ValueError("images must be CUDA uint8/int16/int32 tensors")
         ndim = images[0].dim()
-        if ndim not in (2, 3) or any(im.dim() != ndim or im.dtype != dt or im.device != dev for im in images):
-            raise ValueError("every image must have the same ndim (2 or 3), dtype and device")
+        if ndim not in (2, 3, 4) or any(im.dim() != ndim or im.dtype != dt or im.device != dev for im in images):
+            raise ValueError("every image must have the same ndim (2, 3 or 4), dtype and device")
         self.ndim = ndim
         self.construction = int(construction)
         self.tuning = (0, 2048, 0, 0)

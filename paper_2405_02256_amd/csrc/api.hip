@@ -44,7 +44,7 @@ void layout_common(const Plan& p, const ect_query_set& q, int B, EvalLayout* L, 
     L->groups = groups;
     L->entries = (int64_t)p.num_images * B;
     size_t o = *off;
-    L->recs = o; o = align_up(o + sizeof(QRec) * (size_t)B * std::max<int64_t>(q.count, 1), kAlign);
+    L->recs = o; o = align_up(o + qrec_bytes(p.ndim) * (size_t)B * std::max<int64_t>(q.count, 1), kAlign);
     L->bcnt = o; o = align_up(o + sizeof(int32_t) * groups * B, kAlign);
     L->item_off = o; o = align_up(o + sizeof(int64_t) * (L->entries + 1), kAlign);
     L->tile_off = o; o = align_up(o + sizeof(int64_t) * (L->entries + 1), kAlign);
@@ -145,7 +145,7 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
                           ect_plan* out) {
     if (!batch || !ws_bytes) return ECT_E_INVALID;
     const int n = batch->ndim;
-    if (n != 2 && n != 3) return ECT_E_INVALID;
+    if (n < 2 || n > kMaxDim) return ECT_E_INVALID;
     if (batch->num_images < 1 || !batch->dims || !batch->pixel_offsets || !batch->pixels) return ECT_E_INVALID;
     if (batch->dtype < ECT_U8 || batch->dtype > ECT_I32) return ECT_E_INVALID;
     if (batch->construction != ECT_PRIMAL && batch->construction != ECT_DUAL) return ECT_E_INVALID;
@@ -161,7 +161,7 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
         if (batch->pixel_offsets[i] < 0) return ECT_E_INVALID;
         d.pixel_offset = batch->pixel_offsets[i];
         int64_t nv = 1;
-        for (int a = 0; a < 3; ++a) {
+        for (int a = 0; a < kMaxDim; ++a) {
             if (a < n) {
                 const int32_t dim = batch->dims[(int64_t)i * n + a];
                 if (dim < 1 || dim > (1 << 20)) return ECT_E_INVALID;
@@ -201,7 +201,7 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
     // tile counts (int32) and their prefixes (int64).  The size does not
     // depend on the device.
     L.status = o; o = align_up(o + sizeof(uint64_t) * (2 * tiles + (tiles + 63) / 64 + 1) * NL, kAlign);
-    L.points = o; o = align_up(o + sizeof(Point) * verts * NL, kAlign);
+    L.points = o; o = align_up(o + point_bytes(n) * verts * NL, kAlign);
     L.total = o;
     L.num_tiles = tiles;
     L.capacity = verts;
@@ -318,13 +318,13 @@ static ect_status threshold_eval(ect_plan plan, ect_query_set dirs, const double
         L.grid = direct_groups * p.num_images * chunks;
     } else {
         if (plan->last_prep.ws == ws) plan->last_prep.valid = false;
-        e = launch_prepare(p.ndim, dirs, p.num_images, false, err, (QRec*)(w + L.recs), (int32_t*)(w + L.bcnt),
+        e = launch_prepare(p.ndim, dirs, p.num_images, false, err, (void*)(w + L.recs), (int32_t*)(w + L.bcnt),
                            (const int64_t*)(p.ws + p.lay.list_off), 0, NL, td, 0, 0, (int64_t*)(w + L.item_off),
                            (int64_t*)(w + L.tile_off), (int64_t*)(w + L.params), stream);
     }
     if (e == hipSuccess) {
         EctArgs a{};
-        a.points = (const Point*)(p.ws + p.lay.points);
+        a.points = (const void*)(p.ws + p.lay.points);
         a.list_off = (const int64_t*)(p.ws + p.lay.list_off);
         a.desc = (const ImageDesc*)(p.ws + p.lay.desc);
         a.capacity = p.lay.capacity;
@@ -337,7 +337,7 @@ static ect_status threshold_eval(ect_plan plan, ect_query_set dirs, const double
         a.M = M;
         a.thr_per_image = thresholds_per_image ? 1 : 0;
         a.out = out;
-        a.recs = direct ? nullptr : (const QRec*)(w + L.recs);
+        a.recs = direct ? nullptr : (const void*)(w + L.recs);
         a.bcnt = direct ? nullptr : (const int32_t*)(w + L.bcnt);
         a.item_off = direct ? nullptr : (const int64_t*)(w + L.item_off);
         a.err = err;
@@ -362,7 +362,7 @@ ect_status radon_eval(ect_plan plan, ect_query_set dirs, const double* threshold
 // Arguments of the exact stage common to the layout and the build.
 static ExactArgs exact_args(const Plan& p, const ect_query_set& dirs, int32_t kind) {
     ExactArgs a{};
-    a.points = (const Point*)(p.ws + p.lay.points);
+    a.points = (const void*)(p.ws + p.lay.points);
     a.list_off = (const int64_t*)(p.ws + p.lay.list_off);
     a.list_capacity = p.lay.capacity;
     a.num_images = p.num_images;
@@ -492,7 +492,7 @@ static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t 
     const bool shared = xi.offsets == nullptr;
     hipError_t e = hipSuccess;
     if (!reuse) {
-        e = launch_prepare(p.ndim, xi, p.num_images, true, err, (QRec*)(w + L.recs), (int32_t*)(w + L.bcnt),
+        e = launch_prepare(p.ndim, xi, p.num_images, true, err, (void*)(w + L.recs), (int32_t*)(w + L.bcnt),
                            (const int64_t*)(p.ws + p.lay.list_off), num_classical(p.ndim), NL, kHybridTile, chunk,
                            L.capacity, (int64_t*)(w + L.item_off), (int64_t*)(w + L.tile_off),
                            (int64_t*)(w + L.params), stream);
@@ -508,7 +508,7 @@ static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t 
         lp.valid = true;
     }
     HybridArgs a{};
-    a.points = (const Point*)(p.ws + p.lay.points);
+    a.points = (const void*)(p.ws + p.lay.points);
     a.list_off = (const int64_t*)(p.ws + p.lay.list_off);
     a.desc = (const ImageDesc*)(p.ws + p.lay.desc);
     a.capacity = p.lay.capacity;
@@ -525,7 +525,7 @@ static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t 
     a.log_scale = log_scale;
     a.fwd_out = fwd_out;
     a.grad_out = grad_out;
-    a.recs = (const QRec*)(w + L.recs);
+    a.recs = (const void*)(w + L.recs);
     a.bcnt = (const int32_t*)(w + L.bcnt);
     a.item_off = (const int64_t*)(w + L.item_off);
     a.tile_off = (const int64_t*)(w + L.tile_off);
@@ -606,21 +606,26 @@ ect_status ect_plan_export(ect_plan plan, int32_t image, int32_t kind, int32_t l
     *count = cnt;
     const int64_t take = std::min(cnt, capacity);
     if (take <= 0) return ECT_OK;
-    std::vector<Point> buf;
+    const size_t pb = point_bytes(n);
+    std::vector<char> buf;
     try {
-        buf.resize(take);
+        buf.resize(pb * take);
     } catch (...) {
         return ECT_E_NOMEM;
     }
-    e = hipMemcpyAsync(buf.data(), p.ws + p.lay.points + sizeof(Point) * ((int64_t)l * p.lay.capacity + off[0]),
-                       sizeof(Point) * take, hipMemcpyDeviceToHost, stream);
+    e = hipMemcpyAsync(buf.data(), p.ws + p.lay.points + pb * ((int64_t)l * p.lay.capacity + off[0]), pb * take,
+                       hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return ECT_E_DEVICE;
     const ImageDesc& d = p.h_desc[image];
     for (int64_t k = 0; k < take; ++k) {
+        // every record starts with its coordinates, the value follows the n-th
+        // (three-axis records for n <= 3)
+        const double* rec = (const double*)(buf.data() + pb * k);
+        const int nx = n == 4 ? 4 : 3;
         for (int a = 0; a < n; ++a)
-            coords[k * n + a] = (int32_t)std::lrint((buf[k].x[a] - d.origin[a]) / d.spacing[a]);
-        values[k] = (int32_t)buf[k].val;
+            coords[k * n + a] = (int32_t)std::lrint((rec[a] - d.origin[a]) / d.spacing[a]);
+        values[k] = (int32_t)rec[nx];
     }
     return ECT_OK;
 }

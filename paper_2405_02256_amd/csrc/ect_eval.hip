@@ -57,7 +57,7 @@ constexpr int kBinClosed = 0, kBinOpen = 1, kBinPoint = 2;
 // Stream points [p0, p1) of one list and add sign * (critical value) into the
 // histogram of every direction dd with use[dd].
 template <int N, int MODE>
-__device__ __forceinline__ void accumulate_list(const Point* __restrict__ pts, int64_t p0, int64_t p1,
+__device__ __forceinline__ void accumulate_list(const PointT<N>* __restrict__ pts, int64_t p0, int64_t p1,
                                                 const double (&xi)[kEctMaxDirs][N], const bool (&use)[kEctMaxDirs],
                                                 const double* s_thr, int M, int32_t* s_hist, int32_t sign = 1) {
     const double t0 = s_thr[0], t1 = s_thr[M - 1];
@@ -66,7 +66,7 @@ __device__ __forceinline__ void accumulate_list(const Point* __restrict__ pts, i
     // memory latencies overlap
     constexpr int U = 4;
     for (int64_t p = p0 + threadIdx.x; p < p1; p += (int64_t)kEctThreads * U) {
-        Point pt[U];
+        PointT<N> pt[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t pp = p + (int64_t)u * kEctThreads;
@@ -138,13 +138,13 @@ __device__ __forceinline__ void accumulate_radon(const EctArgs& a, int64_t img, 
     const int M = a.M;
     const int64_t c0 = a.list_off[img * a.NL + e], c1 = a.list_off[(img + 1) * a.NL + e];
     const int64_t cl = c1 - c0;
-    accumulate_list<N, kBinPoint>(a.points + (int64_t)e * a.capacity, c0 + cl * chunk / chunks,
+    accumulate_list<N, kBinPoint>(list_points<N>(a.points, a.capacity, e), c0 + cl * chunk / chunks,
                                   c0 + cl * (chunk + 1) / chunks, xi, use, s_thr, M, s_point);
     const bool mirrored = (e >> (N - 1)) & 1;
     const int l = (1 << N) + (mirrored ? (e ^ full) : e);
     const int64_t o0 = a.list_off[img * a.NL + l], o1 = a.list_off[(img + 1) * a.NL + l];
     const int64_t ol = o1 - o0;
-    accumulate_list<N, kBinOpen>(a.points + (int64_t)l * a.capacity, o0 + ol * chunk / chunks,
+    accumulate_list<N, kBinOpen>(list_points<N>(a.points, a.capacity, l), o0 + ol * chunk / chunks,
                                  o0 + ol * (chunk + 1) / chunks, xi, use, s_thr, M, s_hist, mirrored ? 1 : -1);
 }
 
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
     const int M = a.M;
     double* s_thr = (double*)smem;
     int32_t* s_hist = (int32_t*)(smem + sizeof(double) * M);
-    __shared__ double s_xi[TD][3];
+    __shared__ double s_xi[TD][kMaxDim];
     __shared__ int64_t s_row[TD];
     __shared__ int s_valid[TD];
 
@@ -192,11 +192,11 @@ __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
         int ok = 0;
         int64_t row = -1;
         if (tid < nd) {
-            const QRec r = a.recs[bucket_start(a.offsets, a.count, img, B, b) + q0 + tid];
+            const QRecT<N> r = ((const QRecT<N>*)a.recs)[bucket_start(a.offsets, a.count, img, B, b) + q0 + tid];
             row = row_base + (r.code >> 1);               // output row
             ok = 1;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
+            for (int c = 0; c < N; ++c) {
                 const double v = r.v[c];
                 s_xi[tid][c] = v;
                 ok &= isfinite(v) ? 1 : 0;
@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
         accumulate_radon<N>(a, img, b, 0, 1, xi, use, s_thr, s_hist, s_point);
     } else {
         const int64_t p0 = a.list_off[img * a.NL + b], p1 = a.list_off[(img + 1) * a.NL + b];
-        accumulate_list<N, kBinClosed>(a.points + (int64_t)b * a.capacity, p0, p1, xi, use, s_thr, M, s_hist);
+        accumulate_list<N, kBinClosed>(list_points<N>(a.points, a.capacity, b), p0, p1, xi, use, s_thr, M, s_hist);
     }
     __syncthreads();
     write_rows(a, nd, s_row, s_valid, s_hist, RADON ? s_point : nullptr);
@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(kEctThreads) ect_direct_kernel(EctArgs a, int6
     const int M = a.M;
     double* s_thr = (double*)smem;
     int32_t* s_hist = (int32_t*)(smem + sizeof(double) * M);
-    __shared__ double s_xi[TD][3];
+    __shared__ double s_xi[TD][kMaxDim];
     __shared__ int64_t s_row[TD];
     __shared__ int s_valid[TD];
     __shared__ int s_sign[TD];
@@ -268,7 +268,7 @@ __global__ void __launch_bounds__(kEctThreads) ect_direct_kernel(EctArgs a, int6
         if (tid < nd) {
             const int64_t q = q0 + tid;
             row = img * a.count + q;
-            double v[3] = {0.0, 0.0, 0.0};
+            double v[kMaxDim] = {};
             ok = 1;
 #pragma unroll
             for (int cc = 0; cc < N; ++cc) {
@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(kEctThreads) ect_direct_kernel(EctArgs a, int6
                 ok &= isfinite(v[cc]) ? 1 : 0;
             }
 #pragma unroll
-            for (int cc = 0; cc < 3; ++cc) s_xi[tid][cc] = v[cc];
+            for (int cc = 0; cc < kMaxDim; ++cc) s_xi[tid][cc] = v[cc];
             sg = sign_index<N>(v);
             if (!ok && c == 0) raise_error(a.err, ECT_DEVERR_NONFINITE);
         }
@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(kEctThreads) ect_direct_kernel(EctArgs a, int6
             } else {
                 const int64_t p0 = s_loff[0][b], p1 = s_loff[1][b];
                 const int64_t len = p1 - p0;
-                accumulate_list<N, kBinClosed>(a.points + (int64_t)b * a.capacity, p0 + len * c / chunks,
+                accumulate_list<N, kBinClosed>(list_points<N>(a.points, a.capacity, b), p0 + len * c / chunks,
                                                p0 + len * (c + 1) / chunks, xi, use, s_thr, M, s_hist);
             }
         }
@@ -397,9 +397,12 @@ hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, int64_t direct_g
     if (ndim == 2)
         e = radon ? launch_ect_typed<2, true>(a, grid, direct_groups, shmem, stream)
                   : launch_ect_typed<2, false>(a, grid, direct_groups, shmem, stream);
-    else
+    else if (ndim == 3)
         e = radon ? launch_ect_typed<3, true>(a, grid, direct_groups, shmem, stream)
                   : launch_ect_typed<3, false>(a, grid, direct_groups, shmem, stream);
+    else
+        e = radon ? launch_ect_typed<4, true>(a, grid, direct_groups, shmem, stream)
+                  : launch_ect_typed<4, false>(a, grid, direct_groups, shmem, stream);
     if (e != hipSuccess) return e;
     return stage_mark(ECT_STAGE_ECT, true, stream);
 }

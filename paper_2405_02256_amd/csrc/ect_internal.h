@@ -8,11 +8,11 @@
 
 namespace ect {
 
-constexpr int kMaxDim = 3;
+constexpr int kMaxDim = 4;
 constexpr int kPrecomputeThreads = 256;              // threads per precompute workgroup
 constexpr int kVertsPerThread = 4;                   // vertices per thread per tile
 constexpr int kTileVerts = kPrecomputeThreads * kVertsPerThread;
-constexpr int kMaxLists = 12;                        // 2^n classical + 2^(n-1) ordinary, n = 3
+constexpr int kMaxLists = 24;                        // 2^n classical + 2^(n-1) ordinary, n = 4
 
 __host__ __device__ constexpr int num_classical(int n) { return 1 << n; }
 __host__ __device__ constexpr int num_ordinary(int n) { return 1 << (n - 1); }
@@ -20,24 +20,41 @@ __host__ __device__ constexpr int num_lists(int n) { return num_classical(n) + n
 
 // One critical point as the evaluation kernels read it: canonical FP64
 // vertex coordinates (x_a = fma(h_a, k_a, o_a); unused axes 0) and its
-// critical value.  32 bytes, so a wave reads one point with one scalar load.
+// critical value.  32 bytes for images of up to three axes, so a wave reads
+// one point with one scalar load; four-axis images use 48-byte records.
 struct alignas(32) Point {
     double x[3];
     double val;
 };
+struct alignas(16) Point4 {
+    double x[4];
+    double val;
+    double pad;
+};
+template <int N> struct PointSel { using type = Point; };
+template <> struct PointSel<4> { using type = Point4; };
+template <int N> using PointT = typename PointSel<N>::type;
+
+inline size_t point_bytes(int ndim) { return ndim == 4 ? sizeof(Point4) : sizeof(Point); }
+
+// The points of list l (lists are regions of `capacity` records).
+template <int N>
+__host__ __device__ __forceinline__ const PointT<N>* list_points(const void* base, int64_t capacity, int64_t l) {
+    return (const PointT<N>*)base + l * capacity;
+}
 
 // Per-image constants, uploaded once per plan.
 struct alignas(16) ImageDesc {
     int64_t pixel_offset;   // element offset of the image in the pixel buffer
     int64_t nvert;          // number of vertices
     int64_t tile_start;     // first precompute tile of this image
-    int32_t dims[3];        // pixels per axis (1 for unused axes)
-    int32_t N[3];           // top cells per axis
-    int32_t V[3];           // vertices per axis (N + 1)
+    int32_t dims[kMaxDim];  // pixels per axis (1 for unused axes)
+    int32_t N[kMaxDim];     // top cells per axis
+    int32_t V[kMaxDim];     // vertices per axis (N + 1)
     int32_t pad;
-    double origin[3];
-    double spacing[3];
-    double lo[3], hi[3];    // vertex coordinate range per axis (lo <= hi)
+    double origin[kMaxDim];
+    double spacing[kMaxDim];
+    double lo[kMaxDim], hi[kMaxDim];   // vertex coordinate range per axis (lo <= hi)
 };
 
 // Layout of the precompute workspace (byte offsets from its base).
@@ -47,7 +64,7 @@ struct PlanLayout {
     size_t tile_start;      // int64[num_images + 1]
     size_t list_off;        // int64[(num_images + 1) * NL]: start of image i in list l
     size_t status;          // uint64 ordered-compaction status words: tiles, group totals, carries (x NL)
-    size_t points;          // Point[NL * capacity]
+    size_t points;          // PointT<n>[NL * capacity]
     size_t total;
     int64_t num_tiles;
     int64_t capacity;       // entries per list region (= total vertices)

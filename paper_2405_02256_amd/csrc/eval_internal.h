@@ -15,6 +15,16 @@ struct alignas(32) QRec {
     double v[3];
     int64_t code;
 };
+struct alignas(16) QRec4 {
+    double v[4];
+    int64_t code;
+    int64_t pad;
+};
+template <int N> struct QRecSel { using type = QRec; };
+template <> struct QRecSel<4> { using type = QRec4; };
+template <int N> using QRecT = typename QRecSel<N>::type;
+
+inline size_t qrec_bytes(int ndim) { return ndim == 4 ? sizeof(QRec4) : sizeof(QRec); }
 constexpr int kEctThreads = 256;      // ECT workgroup: points stream across its lanes
 constexpr int kEctMaxDirs = 8;        // directions per ECT workgroup
 constexpr int kEctMaxThresholds = 4096;
@@ -29,7 +39,7 @@ constexpr int kSmallMaxEntries = 4096;     // (image, bucket) entries counted in
 // Bucket the queries by sign vector and build the work list (one launch for
 // small sets; fill + bucket + work list otherwise).
 hipError_t launch_prepare(int ndim, const ect_query_set& qs, int num_images, bool hybrid, uint32_t* err,
-                          QRec* recs, int32_t* bcnt, const int64_t* list_off, int list_base, int NL, int qtile,
+                          void* recs, int32_t* bcnt, const int64_t* list_off, int list_base, int NL, int qtile,
                           int64_t chunk, int64_t capacity, int64_t* item_off, int64_t* tile_off, int64_t* params,
                           hipStream_t stream);
 
@@ -41,7 +51,7 @@ __device__ __forceinline__ int64_t bucket_start(const int64_t* offsets, int64_t 
 }
 
 struct EctArgs {
-    const Point* points;
+    const void* points;       // PointT<n> records
     const int64_t* list_off;
     const ImageDesc* desc;
     int64_t capacity;
@@ -54,7 +64,7 @@ struct EctArgs {
     int M;
     int thr_per_image;
     int32_t* out;
-    const QRec* recs;
+    const void* recs;         // QRecT<n> records
     const int32_t* bcnt;
     const int64_t* item_off;
     uint32_t* err;
@@ -73,7 +83,7 @@ hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, int64_t direct_g
 constexpr int kJi0SmallCoeffs = 10;   // FP32-path small-argument Ji0 polynomial
 
 struct HybridArgs {
-    const Point* points;
+    const void* points;       // PointT<n> records
     const int64_t* list_off;
     const ImageDesc* desc;
     int64_t capacity;
@@ -92,7 +102,7 @@ struct HybridArgs {
     const double* grad_out;   // backward
     double* grad_xi;          // backward: [rows][n] (ragged) or per-image partial [images][count][n]
     double* grad_s_part;      // backward: per-row contribution to d/ds
-    const QRec* recs;
+    const void* recs;         // QRecT<n> records
     const int32_t* bcnt;
     const int64_t* item_off;
     const int64_t* tile_off;

@@ -76,7 +76,7 @@ __device__ __forceinline__ int64_t row_info(const ExactArgs& a, int64_t r, Exact
     const double* v = a.vecs + (a.offsets ? r : r % a.count) * N;
     int ok = 1;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < kMaxDim; ++c) {
         const double x = c < N ? v[c] : 0.0;
         ri.xi[c] = x;
         ok &= isfinite(x) ? 1 : 0;
@@ -251,7 +251,7 @@ __device__ __forceinline__ uint32_t order_key32(float f) {
 // receives the staging indices of ranks t*I .. t*I+I-1 (ranks past n:
 // padding).
 template <int N, int I>
-__device__ __forceinline__ void sort_tile(const Point* __restrict__ pts, int64_t n, int32_t sign, Dir<N> xi,
+__device__ __forceinline__ void sort_tile(const PointT<N>* __restrict__ pts, int64_t n, int32_t sign, Dir<N> xi,
                                           uint32_t (&idx)[I], RowShared& sh) {
     uint32_t key32[I];
 #pragma unroll
@@ -260,7 +260,7 @@ __device__ __forceinline__ void sort_tile(const Point* __restrict__ pts, int64_t
         key32[u] = 0xFFFFFFFFu;
         idx[u] = (uint32_t)j;
         if (j < n) {
-            const Point pt = pts[j];
+            const PointT<N> pt = pts[j];
             const double p = project<N>(xi.v, pt.x);
             sh.key[j] = order_key(p);
             sh.val[j] = sign * (int32_t)pt.val;
@@ -373,7 +373,7 @@ __device__ __forceinline__ void merge_runs(const uint64_t* __restrict__ ka, cons
 
 // Sort one tile of a long list and store it, in order, at ka/va.
 template <int N, int I>
-__device__ __noinline__ void store_tile(const Point* pts, int64_t m, int32_t sign, Dir<N> xi,
+__device__ __noinline__ void store_tile(const PointT<N>* pts, int64_t m, int32_t sign, Dir<N> xi,
                                         uint64_t* ka, int32_t* va, RowShared& sh) {
     uint32_t idx[I];
     sort_tile<N, I>(pts, m, sign, xi, idx, sh);
@@ -391,7 +391,7 @@ __device__ __noinline__ void store_tile(const Point* pts, int64_t m, int32_t sig
 // A list longer than one tile: sorted tiles into workspace A, pairwise merges
 // between A and B, then the merge of equal keys from memory.
 template <int N>
-__device__ __noinline__ int64_t build_long(const Point* pts, int64_t n, int32_t sign, Dir<N> xi, uint64_t* ka,
+__device__ __noinline__ int64_t build_long(const PointT<N>* pts, int64_t n, int32_t sign, Dir<N> xi, uint64_t* ka,
                                            int32_t* va, uint64_t* kb, int32_t* vb, double* out_T, int32_t* out_E,
                                            RowShared& sh) {
     for (int64_t c0 = 0; c0 < n; c0 += kTile) {
@@ -416,7 +416,7 @@ __device__ __noinline__ int64_t build_long(const Point* pts, int64_t n, int32_t 
 
 // Distinct entries of one list (n points at pts), values times sign.
 template <int N, int I>
-__device__ __noinline__ int64_t build_tile(const Point* pts, int64_t n, int32_t sign, Dir<N> xi,
+__device__ __noinline__ int64_t build_tile(const PointT<N>* pts, int64_t n, int32_t sign, Dir<N> xi,
                                            double* out_T, int32_t* out_E, RowShared& sh) {
     uint32_t idx[I];
     sort_tile<N, I>(pts, n, sign, xi, idx, sh);
@@ -424,7 +424,7 @@ __device__ __noinline__ int64_t build_tile(const Point* pts, int64_t n, int32_t 
 }
 
 template <int N>
-__device__ int64_t build_segment(const ExactArgs& a, const Point* pts, int64_t n, int32_t sign, Dir<N> xi,
+__device__ int64_t build_segment(const ExactArgs& a, const PointT<N>* pts, int64_t n, int32_t sign, Dir<N> xi,
                                  int64_t w0, double* out_T, int32_t* out_E, RowShared& sh) {
     if (n <= 0) return 0;
     if (n <= kFinThreads) return build_tile<N, 1>(pts, n, sign, xi, out_T, out_E, sh);
@@ -487,6 +487,7 @@ __global__ void __launch_bounds__(kFinThreads, 4) exact_kernel(ExactArgs a) {
     Dir<N> xi;
 #pragma unroll
     for (int c = 0; c < N; ++c) xi.v[c] = ri.xi[c];
+    const PointT<N>* pts = (const PointT<N>*)a.points;
     if (part == 0) {
         if (threadIdx.x == 0) {
             a.T[base] = -HUGE_VAL;
@@ -494,15 +495,15 @@ __global__ void __launch_bounds__(kFinThreads, 4) exact_kernel(ExactArgs a) {
         }
         int64_t d = 0;
         if (ri.valid == 1) {
-            if (radon) d = build_segment<N>(a, a.points + ri.po, ri.no, ri.sign_o, xi, base, a.T + base + 1,
+            if (radon) d = build_segment<N>(a, pts + ri.po, ri.no, ri.sign_o, xi, base, a.T + base + 1,
                                             a.E + base + 1, sh);
-            else d = build_segment<N>(a, a.points + ri.pc, ri.nc, 1, xi, base, a.T + base + 1, a.E + base + 1, sh);
+            else d = build_segment<N>(a, pts + ri.pc, ri.nc, 1, xi, base, a.T + base + 1, a.E + base + 1, sh);
         }
         if (threadIdx.x == 0) a.len[radon ? 2 * r : r] = d + 1;
     } else {
         const int64_t w0 = base + ri.no + 1;
         int64_t d = 0;
-        if (ri.valid == 1) d = build_segment<N>(a, a.points + ri.pc, ri.nc, 1, xi, w0, a.ct + w0, a.cum + w0, sh);
+        if (ri.valid == 1) d = build_segment<N>(a, pts + ri.pc, ri.nc, 1, xi, w0, a.ct + w0, a.cum + w0, sh);
         if (threadIdx.x == 0) a.len[2 * r + 1] = d;
     }
 }
@@ -612,7 +613,9 @@ size_t exact_layout_scan_bytes(int64_t rows) {
 
 hipError_t launch_exact_layout(int ndim, const ExactArgs& a, int64_t* need, void* scan_tmp, size_t scan_bytes,
                                hipStream_t stream) {
-    hipError_t e = ndim == 2 ? launch_need<2>(a, need, stream) : launch_need<3>(a, need, stream);
+    hipError_t e = ndim == 2   ? launch_need<2>(a, need, stream)
+                   : ndim == 3 ? launch_need<3>(a, need, stream)
+                               : launch_need<4>(a, need, stream);
     if (e != hipSuccess) return e;
     size_t bytes = scan_bytes;
     return scan_call(scan_tmp, bytes, need, a.row_off_out, a.rows, stream);
@@ -624,14 +627,18 @@ hipError_t launch_exact(int ndim, const ExactArgs& a, hipStream_t stream) {
     const unsigned grid = (unsigned)(radon ? 2 * a.rows : a.rows);
     if (ndim == 2)
         hipLaunchKernelGGL((exact_kernel<2>), dim3(grid), dim3(kFinThreads), 0, stream, a);
-    else
+    else if (ndim == 3)
         hipLaunchKernelGGL((exact_kernel<3>), dim3(grid), dim3(kFinThreads), 0, stream, a);
+    else
+        hipLaunchKernelGGL((exact_kernel<4>), dim3(grid), dim3(kFinThreads), 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !radon) return e;
     if (ndim == 2)
         hipLaunchKernelGGL((exact_radon_kernel<2>), dim3((unsigned)a.rows), dim3(kFixThreads), 0, stream, a);
-    else
+    else if (ndim == 3)
         hipLaunchKernelGGL((exact_radon_kernel<3>), dim3((unsigned)a.rows), dim3(kFixThreads), 0, stream, a);
+    else
+        hipLaunchKernelGGL((exact_radon_kernel<4>), dim3((unsigned)a.rows), dim3(kFixThreads), 0, stream, a);
     return hipGetLastError();
 }
 

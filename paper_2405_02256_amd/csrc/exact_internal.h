@@ -7,7 +7,7 @@ namespace ect {
 
 // What the exact stage records about one query row.
 struct alignas(8) ExactRow {
-    double xi[3];
+    double xi[kMaxDim];
     int64_t base;     // first output entry of the row
     int64_t pc, po;   // first classical / ordinary point (index into the point array)
     int64_t nc, no;   // their counts (no: Radon only)
@@ -16,7 +16,7 @@ struct alignas(8) ExactRow {
 };
 
 struct ExactArgs {
-    const Point* points;
+    const void* points;       // PointT<n> records
     const int64_t* list_off;
     int64_t list_capacity;    // entries per list region of the point array
     int num_images;

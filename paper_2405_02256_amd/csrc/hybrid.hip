@@ -134,7 +134,7 @@ constexpr int kSlotF = 0, kSlotL = 2, kSlotB = 3;
 // Contribution of one point.  Forward: per requested kernel, sum of D kbar(s u)
 // (without the 1/s); backward (one kernel): acc[a] = sum of D x_a g(kappa).
 template <int N, int MASK, int PREC, bool BWD>
-__device__ __forceinline__ void accumulate_point(const Point& pt, const Query<N>& q, double* acc,
+__device__ __forceinline__ void accumulate_point(const PointT<N>& pt, const Query<N>& q, double* acc,
                                                  const double* ji0c) {
     double u = q.xi[0] * pt.x[0];
 #pragma unroll
@@ -203,7 +203,7 @@ __device__ __forceinline__ void setup_query(const HybridArgs& a, int64_t img, in
     q.gr = q.gi = 0.0;
     const double s = a.s;
     if (active) {
-        const QRec r = a.recs[bucket_start(a.offsets, a.count, img, P, b) + qi];
+        const QRecT<N> r = ((const QRecT<N>*)a.recs)[bucket_start(a.offsets, a.count, img, P, b) + qi];
         row = row_base + (r.code >> 1);
         q.sigma = (r.code & 1) ? -1.0 : 1.0;
 #pragma unroll
@@ -305,7 +305,7 @@ __device__ __forceinline__ int64_t partial_index(int64_t item, int slot, int q) 
 template <int N, int MASK, int PREC, bool BWD>
 __global__ void __launch_bounds__(kHybridThreads) hybrid_kernel(HybridArgs a) {
     constexpr int P = 1 << (N - 1);
-    __shared__ Point s_pts[kHybridStage];
+    __shared__ PointT<N> s_pts[kHybridStage];
     __shared__ double s_acc[kHybridSplit - 1][kAccSlots][kHybridTile];
     const int tid = threadIdx.x;
     const int lane = tid & (kHybridTile - 1);
@@ -325,7 +325,7 @@ __global__ void __launch_bounds__(kHybridThreads) hybrid_kernel(HybridArgs a) {
     const int64_t qn = a.bcnt[a.offsets == nullptr ? b : e];
     const int64_t qi = t * kHybridTile + lane;
     const bool active = qi < qn;
-    const Point* __restrict__ pts = a.points + (int64_t)l * a.capacity;
+    const PointT<N>* __restrict__ pts = list_points<N>(a.points, a.capacity, l);
     const int64_t c0 = p0 + c * C, c1 = min(p1, c0 + C);
 
     Query<N> q;
@@ -522,15 +522,17 @@ hipError_t launch_hybrid(int ndim, unsigned mask, int precision, bool backward, 
     if (grid > 0) {
         e = stage_mark(stage, false, stream);
         if (e != hipSuccess) return e;
-        e = ndim == 2 ? launch_dispatch<2>(mask, precision, backward, a, grid, false, stream)
-                      : launch_dispatch<3>(mask, precision, backward, a, grid, false, stream);
+        e = ndim == 2   ? launch_dispatch<2>(mask, precision, backward, a, grid, false, stream)
+            : ndim == 3 ? launch_dispatch<3>(mask, precision, backward, a, grid, false, stream)
+                        : launch_dispatch<4>(mask, precision, backward, a, grid, false, stream);
         if (e != hipSuccess) return e;
         e = stage_mark(stage, true, stream);
         if (e != hipSuccess) return e;
     }
     if (tiles > 0)
-        e = ndim == 2 ? launch_dispatch<2>(mask, precision, backward, a, tiles, true, stream)
-                      : launch_dispatch<3>(mask, precision, backward, a, tiles, true, stream);
+        e = ndim == 2   ? launch_dispatch<2>(mask, precision, backward, a, tiles, true, stream)
+            : ndim == 3 ? launch_dispatch<3>(mask, precision, backward, a, tiles, true, stream)
+                        : launch_dispatch<4>(mask, precision, backward, a, tiles, true, stream);
     return e;
 }
 
@@ -542,8 +544,11 @@ hipError_t launch_grad_reduce(int ndim, const double* part, int num_images, int6
     if (ndim == 2)
         hipLaunchKernelGGL(grad_reduce_kernel<2>, dim3(blocks), dim3(256), 0, stream, part, num_images, count,
                            shared ? 1 : 0, grad_xi, gs_part, rows, grad_s);
-    else
+    else if (ndim == 3)
         hipLaunchKernelGGL(grad_reduce_kernel<3>, dim3(blocks), dim3(256), 0, stream, part, num_images, count,
+                           shared ? 1 : 0, grad_xi, gs_part, rows, grad_s);
+    else
+        hipLaunchKernelGGL(grad_reduce_kernel<4>, dim3(blocks), dim3(256), 0, stream, part, num_images, count,
                            shared ? 1 : 0, grad_xi, gs_part, rows, grad_s);
     return hipGetLastError();
 }

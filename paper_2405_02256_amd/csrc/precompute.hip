@@ -55,7 +55,11 @@ __device__ __forceinline__ uint32_t udiv(uint32_t v, uint32_t d, double inv_d, u
 }
 
 template <int N>
-__host__ __device__ constexpr int pow3() { return N == 1 ? 3 : (N == 2 ? 9 : 27); }
+__host__ __device__ constexpr int pow3() {
+    int p = 1;
+    for (int a = 0; a < N; ++a) p *= 3;
+    return p;
+}
 
 // Star cell index: sigma_a in {-1, 0, +1} -> digit sigma_a + 1 in base 3.
 template <int N>
@@ -249,7 +253,7 @@ struct TileValues {
     ImageDesc d;
     int img_id;
     int32_t vals[kVertsPerThread][NL];
-    int kk[kVertsPerThread][3];
+    int kk[kVertsPerThread][kMaxDim];
 };
 
 template <int N, int CONS, typename T>
@@ -273,6 +277,7 @@ __device__ __forceinline__ void tile_values(const T* __restrict__ pixels, const 
     const int64_t vbase = (tile - d.tile_start) * kTileVerts;
     const double inv0 = 1.0 / (double)d.V[0];
     const double inv1 = 1.0 / (double)d.V[1];
+    const double inv2 = 1.0 / (double)d.V[2];
     bool valid[J];
     // every round's pixel loads are issued before any vertex is classified
     int32_t nb[J][nb_count<N, CONS>()];
@@ -280,12 +285,25 @@ __device__ __forceinline__ void tile_values(const T* __restrict__ pixels, const 
     for (int j = 0; j < J; ++j) {
         int64_t v = vbase + j * kPrecomputeThreads + tid;
         valid[j] = v < d.nvert;
-        uint32_t r0, r1;
-        uint32_t q0 = udiv((uint32_t)(valid[j] ? v : 0), (uint32_t)d.V[0], inv0, &r0);
-        uint32_t q1 = N == 3 ? udiv(q0, (uint32_t)d.V[1], inv1, &r1) : 0u;
+        // linear vertex index -> coordinates (axis 0 fastest); the last axis
+        // takes the final quotient
+        uint32_t r0, r1 = 0, r2 = 0;
+        const uint32_t q0 = udiv((uint32_t)(valid[j] ? v : 0), (uint32_t)d.V[0], inv0, &r0);
+        const uint32_t q1 = N >= 3 ? udiv(q0, (uint32_t)d.V[1], inv1, &r1) : 0u;
+        const uint32_t q2 = N >= 4 ? udiv(q1, (uint32_t)d.V[2], inv2, &r2) : 0u;
+#pragma unroll
+        for (int a = 0; a < kMaxDim; ++a) tv.kk[j][a] = 0;
         tv.kk[j][0] = (int)r0;
-        tv.kk[j][1] = N == 3 ? (int)r1 : (int)q0;
-        tv.kk[j][2] = N == 3 ? (int)q1 : 0;
+        if constexpr (N == 2) {
+            tv.kk[j][1] = (int)q0;
+        } else if constexpr (N == 3) {
+            tv.kk[j][1] = (int)r1;
+            tv.kk[j][2] = (int)q1;
+        } else {
+            tv.kk[j][1] = (int)r1;
+            tv.kk[j][2] = (int)r2;
+            tv.kk[j][3] = (int)q2;
+        }
         load_neighbourhood<N, CONS, T>(img, d, tv.kk[j], nb[j]);
     }
 #pragma unroll
@@ -327,14 +345,16 @@ __device__ __forceinline__ uint64_t tile_offsets(int32_t (*s_cnt)[kPrecomputeThr
 template <int N>
 __device__ __forceinline__ void emit_points(const TileValues<N>& tv,
                                             int32_t (*s_cnt)[kPrecomputeThreads / 64][TileValues<N>::NL],
-                                            const int64_t* s_base, Point* __restrict__ points, int64_t capacity) {
+                                            const int64_t* s_base, PointT<N>* __restrict__ points,
+                                            int64_t capacity) {
     constexpr int NL = TileValues<N>::NL;
+    constexpr int NX = sizeof(PointT<N>::x) / sizeof(double);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < kVertsPerThread; ++j) {
-        Point pt;
+        PointT<N> pt{};
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < NX; ++a)
             pt.x[a] = a < N ? __fma_rn(tv.d.spacing[a], (double)tv.kk[j][a], tv.d.origin[a]) : 0.0;
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
@@ -361,7 +381,7 @@ __global__ void __launch_bounds__(kPrecomputeThreads)
 classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
                  const int64_t* __restrict__ tile_start, int32_t num_images, int64_t num_tiles,
                  uint32_t* __restrict__ err, uint64_t* __restrict__ run_ctr, uint64_t* __restrict__ status,
-                 uint64_t* __restrict__ gstatus, int64_t* __restrict__ list_off, Point* __restrict__ points,
+                 uint64_t* __restrict__ gstatus, int64_t* __restrict__ list_off, PointT<N>* __restrict__ points,
                  int64_t capacity) {
     constexpr int NL = TileValues<N>::NL;
     constexpr int W = kPrecomputeThreads / 64;
@@ -464,20 +484,30 @@ __device__ __forceinline__ void block_scan_channels(int64_t (&v)[NL], int64_t (&
     __syncthreads();
 }
 
+// The lists are scanned in groups of at most kScanGroup channels, which keeps
+// the per-thread values in registers and the staged prefixes within LDS.
+constexpr int kScanGroup = 12;
+
+template <int NL>
+__host__ __device__ constexpr int scan_group() { return NL < kScanGroup ? NL : kScanGroup; }
+
 template <int NL>
 __global__ void __launch_bounds__(1024)
 tile_block_sum_kernel(const int32_t* __restrict__ counts, int64_t num_tiles, int64_t* __restrict__ blk) {
-    __shared__ int64_t s_w[16][NL];
+    constexpr int G = scan_group<NL>();
+    __shared__ int64_t s_w[16][G];
     const int64_t t = (int64_t)blockIdx.x * kScanTiles + threadIdx.x;
-    int64_t v[NL], tot[NL];
+    for (int l0 = 0; l0 < NL; l0 += G) {
+        int64_t v[G], tot[G];
 #pragma unroll
-    for (int l = 0; l < NL; ++l) v[l] = t < num_tiles ? counts[t * NL + l] : 0;
-    block_scan_channels<NL>(v, tot, s_w);
-    if (threadIdx.x < NL) {
-        int64_t mine = 0;
+        for (int l = 0; l < G; ++l) v[l] = (t < num_tiles && l0 + l < NL) ? counts[t * NL + l0 + l] : 0;
+        block_scan_channels<G>(v, tot, s_w);
+        if ((int)threadIdx.x < G && l0 + (int)threadIdx.x < NL) {
+            int64_t mine = 0;
 #pragma unroll
-        for (int l = 0; l < NL; ++l) if ((int)threadIdx.x == l) mine = tot[l];
-        blk[(int64_t)blockIdx.x * NL + threadIdx.x] = mine;
+            for (int l = 0; l < G; ++l) if ((int)threadIdx.x == l) mine = tot[l];
+            blk[(int64_t)blockIdx.x * NL + l0 + threadIdx.x] = mine;
+        }
     }
 }
 
@@ -486,27 +516,31 @@ tile_block_sum_kernel(const int32_t* __restrict__ counts, int64_t num_tiles, int
 template <int NL>
 __global__ void __launch_bounds__(1024)
 tile_block_scan_kernel(int64_t* __restrict__ blk, int64_t nblk, int32_t num_images, int64_t* __restrict__ list_off) {
-    __shared__ int64_t s_w[16][NL];
-    int64_t carry[NL];
+    constexpr int G = scan_group<NL>();
+    __shared__ int64_t s_w[16][G];
+    for (int l0 = 0; l0 < NL; l0 += G) {
+        int64_t carry[G];
 #pragma unroll
-    for (int l = 0; l < NL; ++l) carry[l] = 0;
-    for (int64_t base = 0; base < nblk; base += 1024) {
-        const int64_t b = base + threadIdx.x;
-        int64_t v[NL], x[NL], tot[NL];
+        for (int l = 0; l < G; ++l) carry[l] = 0;
+        for (int64_t base = 0; base < nblk; base += 1024) {
+            const int64_t b = base + threadIdx.x;
+            int64_t v[G], x[G], tot[G];
 #pragma unroll
-        for (int l = 0; l < NL; ++l) x[l] = v[l] = b < nblk ? blk[b * NL + l] : 0;
-        block_scan_channels<NL>(v, tot, s_w);
-        if (b < nblk)
+            for (int l = 0; l < G; ++l) x[l] = v[l] = (b < nblk && l0 + l < NL) ? blk[b * NL + l0 + l] : 0;
+            block_scan_channels<G>(v, tot, s_w);
+            if (b < nblk)
 #pragma unroll
-            for (int l = 0; l < NL; ++l) blk[b * NL + l] = carry[l] + v[l] - x[l];
+                for (int l = 0; l < G; ++l)
+                    if (l0 + l < NL) blk[b * NL + l0 + l] = carry[l] + v[l] - x[l];
 #pragma unroll
-        for (int l = 0; l < NL; ++l) carry[l] += tot[l];
-    }
-    if (threadIdx.x < NL) {
-        int64_t mine = 0;
+            for (int l = 0; l < G; ++l) carry[l] += tot[l];
+        }
+        if ((int)threadIdx.x < G && l0 + (int)threadIdx.x < NL) {
+            int64_t mine = 0;
 #pragma unroll
-        for (int l = 0; l < NL; ++l) if ((int)threadIdx.x == l) mine = carry[l];
-        list_off[(int64_t)num_images * NL + threadIdx.x] = mine;
+            for (int l = 0; l < G; ++l) if ((int)threadIdx.x == l) mine = carry[l];
+            list_off[(int64_t)num_images * NL + l0 + threadIdx.x] = mine;
+        }
     }
 }
 
@@ -515,21 +549,11 @@ __global__ void __launch_bounds__(1024)
 tile_block_apply_kernel(const int32_t* __restrict__ counts, int64_t num_tiles, const int64_t* __restrict__ blk,
                         const int64_t* __restrict__ tile_start, int32_t num_images, int64_t* __restrict__ prefix,
                         int64_t* __restrict__ list_off) {
-    __shared__ int64_t s_w[16][NL];
-    __shared__ int64_t s_pref[kScanTiles][NL];
+    constexpr int G = scan_group<NL>();
+    __shared__ int64_t s_w[16][G];
+    __shared__ int64_t s_pref[kScanTiles][G];
     const int64_t t0 = (int64_t)blockIdx.x * kScanTiles;
     const int64_t t = t0 + threadIdx.x;
-    int64_t v[NL], x[NL], tot[NL];
-#pragma unroll
-    for (int l = 0; l < NL; ++l) x[l] = v[l] = t < num_tiles ? counts[t * NL + l] : 0;
-    block_scan_channels<NL>(v, tot, s_w);
-#pragma unroll
-    for (int l = 0; l < NL; ++l) {
-        const int64_t p = blk[(int64_t)blockIdx.x * NL + l] + v[l] - x[l];
-        s_pref[threadIdx.x][l] = p;
-        if (t < num_tiles) prefix[t * NL + l] = p;
-    }
-    __syncthreads();
     // images whose first tile lies in this block: the first one by binary
     // search, then consecutive images
     int lo = 0, hi = num_images;
@@ -537,11 +561,27 @@ tile_block_apply_kernel(const int32_t* __restrict__ counts, int64_t num_tiles, c
         const int mid = (lo + hi) >> 1;
         if (tile_start[mid] < t0) lo = mid + 1; else hi = mid;
     }
-    for (int i = lo + (int)threadIdx.x; i < num_images; i += 1024) {
-        const int64_t ts = tile_start[i];
-        if (ts >= t0 + kScanTiles) break;
+    for (int l0 = 0; l0 < NL; l0 += G) {
+        int64_t v[G], x[G], tot[G];
 #pragma unroll
-        for (int l = 0; l < NL; ++l) list_off[(int64_t)i * NL + l] = s_pref[ts - t0][l];
+        for (int l = 0; l < G; ++l) x[l] = v[l] = (t < num_tiles && l0 + l < NL) ? counts[t * NL + l0 + l] : 0;
+        block_scan_channels<G>(v, tot, s_w);
+#pragma unroll
+        for (int l = 0; l < G; ++l) {
+            if (l0 + l >= NL) continue;
+            const int64_t p = blk[(int64_t)blockIdx.x * NL + l0 + l] + v[l] - x[l];
+            s_pref[threadIdx.x][l] = p;
+            if (t < num_tiles) prefix[t * NL + l0 + l] = p;
+        }
+        __syncthreads();
+        for (int i = lo + (int)threadIdx.x; i < num_images; i += 1024) {
+            const int64_t ts = tile_start[i];
+            if (ts >= t0 + kScanTiles) break;
+#pragma unroll
+            for (int l = 0; l < G; ++l)
+                if (l0 + l < NL) list_off[(int64_t)i * NL + l0 + l] = s_pref[ts - t0][l];
+        }
+        __syncthreads();
     }
 }
 
@@ -549,7 +589,7 @@ template <int N, int CONS, typename T>
 __global__ void __launch_bounds__(kPrecomputeThreads)
 tile_write_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
                   const int64_t* __restrict__ tile_start, int32_t num_images, const int64_t* __restrict__ prefix,
-                  Point* __restrict__ points, int64_t capacity) {
+                  PointT<N>* __restrict__ points, int64_t capacity) {
     constexpr int NL = TileValues<N>::NL;
     __shared__ int32_t s_cnt[kVertsPerThread][kPrecomputeThreads / 64][NL];
     __shared__ int64_t s_base[NL];
@@ -586,7 +626,7 @@ hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream) {
     const ImageDesc* desc = (const ImageDesc*)(p.ws + L.desc);
     const int64_t* ts = (const int64_t*)(p.ws + L.tile_start);
     int64_t* lo = (int64_t*)(p.ws + L.list_off);
-    Point* pts = (Point*)(p.ws + L.points);
+    PointT<N>* pts = (PointT<N>*)(p.ws + L.points);
     if (single) {
         hipLaunchKernelGGL((classify_compact<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads), 0,
                            stream, px, desc, ts, p.num_images, L.num_tiles, err, run_ctr, status, gstatus, lo, pts,
@@ -659,18 +699,23 @@ int64_t precompute_slots_per_cu(int ndim, int construction, int dtype) {
     };
     using I2 = std::integral_constant<int, 2>;
     using I3 = std::integral_constant<int, 3>;
+    using I4 = std::integral_constant<int, 4>;
     using P = std::integral_constant<int, ECT_PRIMAL>;
     using Du = std::integral_constant<int, ECT_DUAL>;
     if (ndim == 2) return construction == ECT_PRIMAL ? pick(I2{}, P{}) : pick(I2{}, Du{});
-    return construction == ECT_PRIMAL ? pick(I3{}, P{}) : pick(I3{}, Du{});
+    if (ndim == 3) return construction == ECT_PRIMAL ? pick(I3{}, P{}) : pick(I3{}, Du{});
+    return construction == ECT_PRIMAL ? pick(I4{}, P{}) : pick(I4{}, Du{});
 }
 
 hipError_t launch_precompute(const Plan& p, bool first, hipStream_t stream) {
     if (p.ndim == 2)
         return p.construction == ECT_PRIMAL ? launch_dtype<2, ECT_PRIMAL>(p, first, stream)
                                             : launch_dtype<2, ECT_DUAL>(p, first, stream);
-    return p.construction == ECT_PRIMAL ? launch_dtype<3, ECT_PRIMAL>(p, first, stream)
-                                        : launch_dtype<3, ECT_DUAL>(p, first, stream);
+    if (p.ndim == 3)
+        return p.construction == ECT_PRIMAL ? launch_dtype<3, ECT_PRIMAL>(p, first, stream)
+                                            : launch_dtype<3, ECT_DUAL>(p, first, stream);
+    return p.construction == ECT_PRIMAL ? launch_dtype<4, ECT_PRIMAL>(p, first, stream)
+                                        : launch_dtype<4, ECT_DUAL>(p, first, stream);
 }
 
 }  // namespace ect

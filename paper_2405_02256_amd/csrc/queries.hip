@@ -49,13 +49,14 @@ __device__ __forceinline__ int aggregated_add(Ctr* counters, int key, bool valid
 // [r0, r0 + q) of the set belong to it): returns the (image, bucket) entry.
 template <int N>
 __device__ __forceinline__ int64_t classify_vec(const double (&v)[N], int64_t r, int img, int64_t r0, int64_t q,
-                                                int mode_hybrid, uint32_t* __restrict__ err, QRec* rec,
+                                                int mode_hybrid, uint32_t* __restrict__ err, QRecT<N>* rec,
                                                 int64_t* slot_base) {
     const int B = mode_hybrid ? (1 << (N - 1)) : (1 << N);
     const int full = (1 << N) - 1;
+    constexpr int NV = sizeof(QRecT<N>::v) / sizeof(double);
     bool fin = true;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < NV; ++a) {
         rec->v[a] = a < N ? v[a < N ? a : 0] : 0.0;
         fin = fin && isfinite(rec->v[a]);
     }
@@ -83,7 +84,7 @@ __device__ __forceinline__ int image_of(const O* off, int num_images, int64_t r)
 template <int N>
 __device__ __forceinline__ int64_t classify_query(const double* __restrict__ vecs, const int64_t* __restrict__ offsets,
                                                   int64_t r, int64_t rows, int num_images, int mode_hybrid,
-                                                  uint32_t* __restrict__ err, QRec* rec, int64_t* slot_base) {
+                                                  uint32_t* __restrict__ err, QRecT<N>* rec, int64_t* slot_base) {
     int img = 0;
     int64_t r0 = 0, q = rows;
     if (offsets) {
@@ -100,11 +101,11 @@ __device__ __forceinline__ int64_t classify_query(const double* __restrict__ vec
 template <int N>
 __global__ void __launch_bounds__(kBucketThreads)
 bucket_kernel(const double* __restrict__ vecs, const int64_t* __restrict__ offsets, int64_t rows,
-              int num_images, int mode_hybrid, uint32_t* __restrict__ err, QRec* __restrict__ recs,
+              int num_images, int mode_hybrid, uint32_t* __restrict__ err, QRecT<N>* __restrict__ recs,
               int32_t* __restrict__ bcnt) {
     const int64_t r = (int64_t)blockIdx.x * kBucketThreads + threadIdx.x;
     const bool valid = r < rows;
-    QRec rec;
+    QRecT<N> rec;
     int64_t sbase = 0, ent = 0;
     if (valid) ent = classify_query<N>(vecs, offsets, r, rows, num_images, mode_hybrid, err, &rec, &sbase);
     const int slot = aggregated_add(bcnt, (int)ent, valid);
@@ -303,14 +304,14 @@ constexpr int64_t kSharedMaxRows = 65536;
 template <int N>
 __global__ void __launch_bounds__(1024)
 prepare_shared_kernel(const double* __restrict__ vecs, int64_t rows, int num_images, int mode_hybrid,
-                      uint32_t* __restrict__ err, QRec* __restrict__ recs, int32_t* __restrict__ bcnt,
+                      uint32_t* __restrict__ err, QRecT<N>* __restrict__ recs, int32_t* __restrict__ bcnt,
                       const int64_t* __restrict__ list_off, int list_base, int NL, int qtile, int64_t chunk0,
                       int64_t capacity, int64_t* __restrict__ item_off, int64_t* __restrict__ tile_off,
                       int64_t* __restrict__ params) {
     constexpr int W = 16;
     constexpr int U = 4;   // batches whose loads are in flight together
-    __shared__ int32_t s_wc[W][8];
-    __shared__ int32_t s_tot[8];
+    __shared__ int32_t s_wc[W][1 << kMaxDim];
+    __shared__ int32_t s_tot[1 << kMaxDim];
     const int B = mode_hybrid ? (1 << (N - 1)) : (1 << N);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -340,7 +341,7 @@ prepare_shared_kernel(const double* __restrict__ vecs, int64_t rows, int num_ima
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t r = rb + 64 * u + lane;
-            QRec rec;
+            QRecT<N> rec;
             int64_t sb;
             const int key = r < w1 ? (int)classify_vec<N>(v[u], r, 0, 0, rows, mode_hybrid, err, &rec, &sb) : -1;
             for (int c = 0; c < B; ++c) {
@@ -368,7 +369,7 @@ prepare_shared_kernel(const double* __restrict__ vecs, int64_t rows, int num_ima
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t r = rb + 64 * u + lane;
-            QRec rec;
+            QRecT<N> rec;
             int64_t sb = 0;
             const int key = r < w1 ? (int)classify_vec<N>(v[u], r, 0, 0, rows, mode_hybrid, nullptr, &rec, &sb) : -1;
             int slot = 0;
@@ -403,7 +404,7 @@ constexpr int kSmallMaxOffsets = kSmallMaxEntries / 2 + 1;   // ragged: images <
 template <int N>
 __global__ void __launch_bounds__(1024)
 prepare_small_kernel(const double* __restrict__ vecs, const int64_t* __restrict__ offsets, int64_t rows,
-                     int num_images, int mode_hybrid, uint32_t* __restrict__ err, QRec* __restrict__ recs,
+                     int num_images, int mode_hybrid, uint32_t* __restrict__ err, QRecT<N>* __restrict__ recs,
                      int32_t* __restrict__ bcnt, const int64_t* __restrict__ list_off, int list_base, int NL,
                      int qtile, int64_t chunk0, int64_t capacity, int64_t* __restrict__ item_off,
                      int64_t* __restrict__ tile_off, int64_t* __restrict__ params) {
@@ -443,7 +444,7 @@ prepare_small_kernel(const double* __restrict__ vecs, const int64_t* __restrict_
         for (int j = 0; j < kPrepRows; ++j) {
             const int64_t r = base + (int64_t)j * 1024 + tid;
             const bool valid = r < rows;
-            QRec rec;
+            QRecT<N> rec;
             int64_t sbase = 0, ent = 0;
             if (valid) {
                 int img = 0;
@@ -465,36 +466,26 @@ prepare_small_kernel(const double* __restrict__ vecs, const int64_t* __restrict_
                    stage_np ? s_np : nullptr, qtile, chunk0, capacity, err, item_off, tile_off, params);
 }
 
-}  // namespace
-
-hipError_t launch_prepare(int ndim, const ect_query_set& qs, int num_images, bool hybrid, uint32_t* err,
-                          QRec* recs, int32_t* bcnt, const int64_t* list_off, int list_base, int NL, int qtile,
-                          int64_t chunk, int64_t capacity, int64_t* item_off, int64_t* tile_off, int64_t* params,
-                          hipStream_t stream) {
-    const int B = hybrid ? (1 << (ndim - 1)) : (1 << ndim);
+template <int N>
+hipError_t launch_prepare_typed(const ect_query_set& qs, int num_images, bool hybrid, uint32_t* err, void* recs_v,
+                                int32_t* bcnt, const int64_t* list_off, int list_base, int NL, int qtile,
+                                int64_t chunk, int64_t capacity, int64_t* item_off, int64_t* tile_off,
+                                int64_t* params, hipStream_t stream) {
+    QRecT<N>* recs = (QRecT<N>*)recs_v;
+    const int B = hybrid ? (1 << (N - 1)) : (1 << N);
     const int64_t rows = qs.count;  // shared: the set itself; ragged: all rows
     const int groups = qs.offsets ? num_images : 1;
     const bool shared = qs.offsets == nullptr;
     if (shared && rows <= kSharedMaxRows) {
-        if (ndim == 2)
-            hipLaunchKernelGGL(prepare_shared_kernel<2>, dim3(1), dim3(1024), 0, stream, qs.vecs, rows, num_images,
-                               hybrid ? 1 : 0, err, recs, bcnt, list_off, list_base, NL, qtile, chunk, capacity,
-                               item_off, tile_off, params);
-        else
-            hipLaunchKernelGGL(prepare_shared_kernel<3>, dim3(1), dim3(1024), 0, stream, qs.vecs, rows, num_images,
-                               hybrid ? 1 : 0, err, recs, bcnt, list_off, list_base, NL, qtile, chunk, capacity,
-                               item_off, tile_off, params);
+        hipLaunchKernelGGL(prepare_shared_kernel<N>, dim3(1), dim3(1024), 0, stream, qs.vecs, rows, num_images,
+                           hybrid ? 1 : 0, err, recs, bcnt, list_off, list_base, NL, qtile, chunk, capacity,
+                           item_off, tile_off, params);
         return hipGetLastError();
     }
     if (rows <= kSmallMaxRows && (int64_t)groups * B <= kSmallMaxEntries) {
-        if (ndim == 2)
-            hipLaunchKernelGGL(prepare_small_kernel<2>, dim3(1), dim3(1024), 0, stream, qs.vecs, qs.offsets, rows,
-                               num_images, hybrid ? 1 : 0, err, recs, bcnt, list_off, list_base, NL, qtile, chunk,
-                               capacity, item_off, tile_off, params);
-        else
-            hipLaunchKernelGGL(prepare_small_kernel<3>, dim3(1), dim3(1024), 0, stream, qs.vecs, qs.offsets, rows,
-                               num_images, hybrid ? 1 : 0, err, recs, bcnt, list_off, list_base, NL, qtile, chunk,
-                               capacity, item_off, tile_off, params);
+        hipLaunchKernelGGL(prepare_small_kernel<N>, dim3(1), dim3(1024), 0, stream, qs.vecs, qs.offsets, rows,
+                           num_images, hybrid ? 1 : 0, err, recs, bcnt, list_off, list_base, NL, qtile, chunk,
+                           capacity, item_off, tile_off, params);
         return hipGetLastError();
     }
     hipError_t e = launch_fill_u32((uint32_t*)bcnt, (int64_t)groups * B, 0u, stream);
@@ -502,18 +493,30 @@ hipError_t launch_prepare(int ndim, const ect_query_set& qs, int num_images, boo
     if (rows > 0) {
         const unsigned blocks = (unsigned)((rows + kBucketThreads - 1) / kBucketThreads);
         const int ni = qs.offsets ? num_images : 1;
-        if (ndim == 2)
-            hipLaunchKernelGGL(bucket_kernel<2>, dim3(blocks), dim3(kBucketThreads), 0, stream, qs.vecs, qs.offsets,
-                               rows, ni, hybrid ? 1 : 0, err, recs, bcnt);
-        else
-            hipLaunchKernelGGL(bucket_kernel<3>, dim3(blocks), dim3(kBucketThreads), 0, stream, qs.vecs, qs.offsets,
-                               rows, ni, hybrid ? 1 : 0, err, recs, bcnt);
+        hipLaunchKernelGGL(bucket_kernel<N>, dim3(blocks), dim3(kBucketThreads), 0, stream, qs.vecs, qs.offsets,
+                           rows, ni, hybrid ? 1 : 0, err, recs, bcnt);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(worklist_kernel, dim3(1), dim3(1024), 0, stream, num_images, B, list_base, NL,
                        shared ? 1 : 0, bcnt, list_off, qtile, chunk, capacity, err, item_off, tile_off, params);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_prepare(int ndim, const ect_query_set& qs, int num_images, bool hybrid, uint32_t* err,
+                          void* recs, int32_t* bcnt, const int64_t* list_off, int list_base, int NL, int qtile,
+                          int64_t chunk, int64_t capacity, int64_t* item_off, int64_t* tile_off, int64_t* params,
+                          hipStream_t stream) {
+    if (ndim == 2)
+        return launch_prepare_typed<2>(qs, num_images, hybrid, err, recs, bcnt, list_off, list_base, NL, qtile, chunk,
+                                       capacity, item_off, tile_off, params, stream);
+    if (ndim == 3)
+        return launch_prepare_typed<3>(qs, num_images, hybrid, err, recs, bcnt, list_off, list_base, NL, qtile, chunk,
+                                       capacity, item_off, tile_off, params, stream);
+    return launch_prepare_typed<4>(qs, num_images, hybrid, err, recs, bcnt, list_off, list_base, NL, qtile, chunk,
+                                   capacity, item_off, tile_off, params, stream);
 }
 
 }  // namespace ect

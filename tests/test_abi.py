@@ -69,7 +69,11 @@ def test_precompute_size_query_and_validation(N):
     b2, keep2 = _batch(N, dims=((40, 50),))
     need2 = ctypes.c_size_t(0)
     assert N.ect_precompute(b2, None, need2, 0)[0] == N.ECT_OK and need2.value > need.value
-    for kw in (dict(ndim=4, dims=((2, 2, 2, 2),)), dict(ndim=1, dims=((3,),)), dict(dims=((0, 5),)),
+    # four axes are accepted (16 classical + 8 ordinary lists of 48-byte records)
+    b4, keep4 = _batch(N, ndim=4, dims=((3, 4, 2, 5),))
+    need4 = ctypes.c_size_t(0)
+    assert N.ect_precompute(b4, None, need4, 0)[0] == N.ECT_OK and need4.value > 24 * 48 * (4 * 5 * 3 * 6)
+    for kw in (dict(ndim=5, dims=((2, 2, 2, 2, 2),)), dict(ndim=1, dims=((3,),)), dict(dims=((0, 5),)),
                dict(dtype=7), dict(cons=3), dict(pixels=0)):
         bb, k = _batch(N, **kw)
         assert N.ect_precompute(bb, None, ctypes.c_size_t(0), 0)[0] == N.ECT_E_INVALID, kw
