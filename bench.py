@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-image batched comparison")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the Radon transform and exact-representation measurements")
+    ap.add_argument("--no-4d", action="store_true", help="skip the four-axis workload")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule knobs")
     ap.add_argument("--concurrent", action="store_true", help="run the ECT branch on a side stream")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -120,6 +121,89 @@ def measure_next(plan, w, dirs, thr, n, cls_counts, ord_counts, steps):
                                 "roofline": roofline.hbm_roofline(nbytes, ms_b * 1e-3),
                                 "eval_ms": ms_e, "eval_values_per_s": rep.rows * thr.shape[0] / (ms_e * 1e-3)}
     return out
+
+
+def measure_4d(steps):
+    """The four-axis workload (24^4 quantised field, primal): every stage of the
+    step on it, kernel times from the library's stage events, the hybrid
+    evaluation rate and the fused kernel's ALU roofline, and the exact (T, E)
+    build of its 512 directions."""
+    import numpy as np
+    import torch
+
+    from paper_2405_02256_amd import _native as N
+    from paper_2405_02256_amd import api, hipevents, roofline
+    from paper_2405_02256_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    w = W.hypervolume_24()
+    img = w.images[0]
+    plan = api.Plan(torch.from_numpy(img).to(dev))
+    dirs = torch.from_numpy(w.ect_dirs).to(dev)
+    thr = torch.from_numpy(w.ect_thresholds).to(dev)
+    xi = torch.from_numpy(w.hybrid_xi).to(dev)
+    kern = ("fourier", "laplace", "bessel")
+    g = torch.from_numpy(np.random.default_rng(7).standard_normal((len(w.hybrid_xi), 2))).to(dev)
+    eo = torch.empty((len(w.ect_dirs), thr.shape[0]), dtype=torch.int32, device=dev)
+    outs = plan.hybrid_multi(xi, kern, 1.0, "fp32")
+    gx = torch.empty((len(w.hybrid_xi), 4), dtype=torch.float64, device=dev)
+    gs = torch.empty((), dtype=torch.float64, device=dev)
+
+    def step():
+        plan.rerun()
+        plan.ect(dirs, thr, out=eo)
+        plan.hybrid_multi(xi, kern, 1.0, "fp32", outs=outs)
+        plan.hybrid_backward(xi, outs["fourier"], g, "fourier", 1.0, "fp32", grad_xi=gx, grad_s=gs)
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    names = ["precompute", "ect", "hybrid_fused", "hybrid_bwd_fourier"]
+    evs = {nm: [(hipevents.Event(), hipevents.Event()) for _ in range(steps)] for nm in names}
+    for i in range(steps):
+        for stg, nm in enumerate(names):
+            N.check(N.ect_set_stage_events(stg, evs[nm][i][0].handle, evs[nm][i][1].handle), "stage events")
+        step()
+    torch.cuda.synchronize()
+    for stg in range(4):
+        N.ect_set_stage_events(stg, None, None)
+    ms = {nm: float(np.mean([a.elapsed_ms(b) for a, b in evs[nm]])) for nm in names}
+    if plan.check() != 0:
+        raise RuntimeError("device error flags set on the four-axis workload")
+    cls_counts, ord_counts = plan.counts()
+    e = sum(((w.hybrid_xi[:, a] < 0) * (1 << a) for a in range(4)))
+    pair = np.where(e >= 8, e ^ 15, e)
+    pairs = float(ord_counts[0][pair].sum())
+    ed = sum(((w.ect_dirs[:, a] < 0) * (1 << a) for a in range(4)))
+    ect_pairs = float(cls_counts[0][ed].sum())
+    # share of Bessel (query, point) pairs on the small-argument branch, on 256 sampled xi
+    rng = np.random.default_rng(11)
+    sel = rng.choice(len(w.hybrid_xi), 256, replace=False)
+    lists = [plan.export(0, 1, b)[0].astype(np.float64) - (np.array(img.shape[::-1]) / 2.0) for b in range(8)]
+    small = tot = 0.0
+    for q in sel:
+        z = np.abs(lists[pair[q]] @ w.hybrid_xi[q])
+        small += float((z < 8.0).sum())
+        tot += float(z.size)
+    small_frac = small / max(tot, 1.0)
+    roof = roofline.alu_roofline("+".join(kern), 4, pairs, ms["hybrid_fused"] * 1e-3, small_frac)
+    rep = plan.exact(dirs, "ect")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    plan.exact(dirs, "ect", reuse=rep)
+    e0.record()
+    for _ in range(steps):
+        plan.exact(dirs, "ect", reuse=rep)
+    e1.record()
+    torch.cuda.synchronize()
+    return {"workload": "hypervolume_24: 24^4 smoothed noise quantised into 8 levels, primal; ECT 512 dirs "
+                        "(uniform on S^3) x 256 thresholds; Euler-Fourier/Laplace/Bessel at 4096 xi, "
+                        "|xi|~U[0.01,1]; Fourier backward",
+            "stage_kernel_ms": ms, "hybrid_pairs_per_kernel": pairs,
+            "hybrid_evals_per_s": pairs * (len(kern) + 1) / (sum(ms.values()) * 1e-3),
+            "ect_dirs_per_s": len(w.ect_dirs) / (ms["ect"] * 1e-3), "ect_pairs": ect_pairs,
+            "bessel_small_branch_fraction": small_frac, "hybrid_fused_roofline": roof,
+            "ect_roofline": roofline.alu_roofline("ect", 4, ect_pairs, ms["ect"] * 1e-3),
+            "exact_ect_build_ms": e0.elapsed_time(e1) / steps}
 
 
 def main():
@@ -275,6 +359,13 @@ def main():
         next_rows = measure_next(plan, w, dirs, thr, n, cls_counts, counts, args.steps)
         log("next rows: " + json.dumps(next_rows))
 
+    # ---- four-axis workload ----
+    four = None
+    if not args.no_4d:
+        log("four-axis workload")
+        four = measure_4d(args.steps)
+        log("four axes: " + json.dumps(four))
+
     # ---- FP64 path on the same step, for the FP32-vs-FP64 comparison ----
     fp64 = None
     if not args.no_fp64:
@@ -412,6 +503,7 @@ def main():
         "fp32_vs_fp64_speedup": None if fp64 is None else fp64 / sec,
         "batched_vs_per_image": batch,
         "radon_and_exact": next_rows,
+        "four_axes": four,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

@@ -184,7 +184,7 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
         d.nvert = nv;
         d.tile_start = tiles;
         tstart[i] = tiles;
-        tiles += (nv + kTileVerts - 1) / kTileVerts;
+        tiles += (nv + tile_verts(n) - 1) / tile_verts(n);
         verts += nv;
         maxv = std::max(maxv, nv);
     }
@@ -286,8 +286,8 @@ static ect_status threshold_eval(ect_plan plan, ect_query_set dirs, const double
     td = std::max(1, std::min(td, kEctMaxDirs));
     // shared sets go straight to the evaluation kernel (no bucketing); long
     // lists are split into chunks so that enough workgroups share each group
-    // of directions (about two per compute unit, at least 16384 points each:
-    // below that a workgroup's fixed cost outweighs streaming its list)
+    // of directions (about two per compute unit, at least 4096 points each:
+    // below that a workgroup's fixed cost outweighs streaming its part)
     const bool direct = dirs.offsets == nullptr;
     EvalLayout L{};
     int64_t chunks = 1;
@@ -296,7 +296,7 @@ static ect_status threshold_eval(ect_plan plan, ect_query_set dirs, const double
         const double avg = mean_list(p, 0, num_classical(p.ndim));
         const int64_t want = (2 * (int64_t)std::max(p.num_cus, 1) + groups - 1) / std::max<int64_t>(groups, 1);
         chunks = radon ? 1 : p.tune_ect_chunks > 0 ? p.tune_ect_chunks
-                                       : std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)(avg / 16384.0)));
+                                       : std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)(avg / 4096.0)));
         if (chunks > 1) L.total = sizeof(int32_t) * (size_t)(groups * chunks * td * (int64_t)M);
     } else {
         layout_ect(p, dirs, td, &L);

@@ -10,8 +10,11 @@ namespace ect {
 
 constexpr int kMaxDim = 4;
 constexpr int kPrecomputeThreads = 256;              // threads per precompute workgroup
-constexpr int kVertsPerThread = 4;                   // vertices per thread per tile
-constexpr int kTileVerts = kPrecomputeThreads * kVertsPerThread;
+// Vertices per thread per precompute tile: four for n <= 3 (their loads in
+// flight together); one for n = 4, whose 81-cell stars and 24 lists fill the
+// registers on their own.
+__host__ __device__ constexpr int verts_per_thread(int n) { return n == 4 ? 1 : 4; }
+__host__ __device__ constexpr int tile_verts(int n) { return kPrecomputeThreads * verts_per_thread(n); }
 constexpr int kMaxLists = 24;                        // 2^n classical + 2^(n-1) ordinary, n = 4
 
 __host__ __device__ constexpr int num_classical(int n) { return 1 << n; }

@@ -249,11 +249,11 @@ __device__ __forceinline__ bool sum_published(const uint64_t* words, int64_t cou
 // s_cnt.
 template <int N>
 struct TileValues {
-    static constexpr int NC = 1 << N, NO = 1 << (N - 1), NL = NC + NO;
+    static constexpr int NC = 1 << N, NO = 1 << (N - 1), NL = NC + NO, J = verts_per_thread(N);
     ImageDesc d;
     int img_id;
-    int32_t vals[kVertsPerThread][NL];
-    int kk[kVertsPerThread][kMaxDim];
+    int32_t vals[J][NL];
+    int kk[J][kMaxDim];
 };
 
 template <int N, int CONS, typename T>
@@ -262,7 +262,7 @@ __device__ __forceinline__ void tile_values(const T* __restrict__ pixels, const 
                                             int64_t tile, TileValues<N>& tv,
                                             int32_t (*s_cnt)[kPrecomputeThreads / 64][TileValues<N>::NL]) {
     constexpr int NC = TileValues<N>::NC, NO = TileValues<N>::NO, NL = TileValues<N>::NL;
-    constexpr int J = kVertsPerThread;
+    constexpr int J = TileValues<N>::J;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // image owning this tile: last i with tile_start[i] <= tile
     int lo = 0, hi = num_images - 1;
@@ -274,7 +274,7 @@ __device__ __forceinline__ void tile_values(const T* __restrict__ pixels, const 
     tv.img_id = lo;
     const ImageDesc& d = tv.d;
     const T* __restrict__ img = pixels + d.pixel_offset;
-    const int64_t vbase = (tile - d.tile_start) * kTileVerts;
+    const int64_t vbase = (tile - d.tile_start) * tile_verts(N);
     const double inv0 = 1.0 / (double)d.V[0];
     const double inv1 = 1.0 / (double)d.V[1];
     const double inv2 = 1.0 / (double)d.V[2];
@@ -324,13 +324,13 @@ __device__ __forceinline__ void tile_values(const T* __restrict__ pixels, const 
 
 // Wave 0, lane l < NL: turn list l's counts into exclusive offsets inside the
 // tile and return the tile's total for list l (0 elsewhere).
-template <int NL>
+template <int NL, int J>
 __device__ __forceinline__ uint64_t tile_offsets(int32_t (*s_cnt)[kPrecomputeThreads / 64][NL]) {
     const int lane = threadIdx.x & 63;
     if (lane >= NL) return 0;
     int32_t cnt = 0;
 #pragma unroll
-    for (int j = 0; j < kVertsPerThread; ++j)
+    for (int j = 0; j < J; ++j)
 #pragma unroll
         for (int w = 0; w < kPrecomputeThreads / 64; ++w) {
             int32_t c = s_cnt[j][w][lane];
@@ -351,7 +351,7 @@ __device__ __forceinline__ void emit_points(const TileValues<N>& tv,
     constexpr int NX = sizeof(PointT<N>::x) / sizeof(double);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int j = 0; j < kVertsPerThread; ++j) {
+    for (int j = 0; j < TileValues<N>::J; ++j) {
         PointT<N> pt{};
 #pragma unroll
         for (int a = 0; a < NX; ++a)
@@ -386,7 +386,7 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
     constexpr int NL = TileValues<N>::NL;
     constexpr int W = kPrecomputeThreads / 64;
     __shared__ uint64_t s_run;
-    __shared__ int32_t s_cnt[kVertsPerThread][W][NL];   // per (round, wave, list) counts, then offsets
+    __shared__ int32_t s_cnt[TileValues<N>::J][W][NL];   // per (round, wave, list) counts, then offsets
     __shared__ int64_t s_base[NL];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t tile = blockIdx.x;
@@ -397,7 +397,7 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
     const uint64_t run = s_run;
     const uint64_t parity = (run & 1ull) ? kParityBit : 0ull;
     if (wave == 0) {
-        const uint64_t agg = tile_offsets<NL>(s_cnt);
+        const uint64_t agg = tile_offsets<NL, TileValues<N>::J>(s_cnt);
         if (lane < NL)
             __hip_atomic_store(status + tile * NL + lane, kFlagAggregate | parity | agg, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
@@ -436,13 +436,13 @@ __global__ void __launch_bounds__(kPrecomputeThreads)
 tile_count_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
                   const int64_t* __restrict__ tile_start, int32_t num_images, int32_t* __restrict__ counts) {
     constexpr int NL = TileValues<N>::NL;
-    __shared__ int32_t s_cnt[kVertsPerThread][kPrecomputeThreads / 64][NL];
+    __shared__ int32_t s_cnt[TileValues<N>::J][kPrecomputeThreads / 64][NL];
     const int64_t tile = blockIdx.x;
     TileValues<N> tv;
     tile_values<N, CONS, T>(pixels, descs, tile_start, num_images, tile, tv, s_cnt);
     __syncthreads();
     if ((threadIdx.x >> 6) == 0) {
-        const uint64_t agg = tile_offsets<NL>(s_cnt);
+        const uint64_t agg = tile_offsets<NL, TileValues<N>::J>(s_cnt);
         if (threadIdx.x < NL) counts[tile * NL + threadIdx.x] = (int32_t)agg;
     }
 }
@@ -484,9 +484,10 @@ __device__ __forceinline__ void block_scan_channels(int64_t (&v)[NL], int64_t (&
     __syncthreads();
 }
 
-// The lists are scanned in groups of at most kScanGroup channels, which keeps
-// the per-thread values in registers and the staged prefixes within LDS.
-constexpr int kScanGroup = 12;
+// The lists are scanned a few channels at a time: with every channel in one
+// pass the 64-bit per-thread values of a 1024-thread workgroup spill to
+// scratch memory, which made these launches hundreds of microseconds long.
+constexpr int kScanGroup = 2;
 
 template <int NL>
 __host__ __device__ constexpr int scan_group() { return NL < kScanGroup ? NL : kScanGroup; }
@@ -591,14 +592,14 @@ tile_write_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ de
                   const int64_t* __restrict__ tile_start, int32_t num_images, const int64_t* __restrict__ prefix,
                   PointT<N>* __restrict__ points, int64_t capacity) {
     constexpr int NL = TileValues<N>::NL;
-    __shared__ int32_t s_cnt[kVertsPerThread][kPrecomputeThreads / 64][NL];
+    __shared__ int32_t s_cnt[TileValues<N>::J][kPrecomputeThreads / 64][NL];
     __shared__ int64_t s_base[NL];
     const int64_t tile = blockIdx.x;
     TileValues<N> tv;
     tile_values<N, CONS, T>(pixels, descs, tile_start, num_images, tile, tv, s_cnt);
     if (threadIdx.x < NL) s_base[threadIdx.x] = prefix[tile * NL + threadIdx.x];
     __syncthreads();
-    if ((threadIdx.x >> 6) == 0) tile_offsets<NL>(s_cnt);
+    if ((threadIdx.x >> 6) == 0) tile_offsets<NL, TileValues<N>::J>(s_cnt);
     __syncthreads();
     emit_points<N>(tv, s_cnt, s_base, points, capacity);
 }

@@ -70,11 +70,16 @@ def binary_field(rng: np.random.Generator, shape, sigma: float) -> np.ndarray:
     return (f > np.median(f)).astype(np.uint8)
 
 
-def quantised_volume(rng: np.random.Generator, side: int, sigma: float, levels: int = 8) -> np.ndarray:
-    """Smoothed noise volume; each voxel holds the number of level cuts below it (0..levels-1)."""
-    f = gaussian_field(rng, (side, side, side), sigma)
+def quantised_field(rng: np.random.Generator, shape, sigma: float, levels: int = 8) -> np.ndarray:
+    """Smoothed noise of any shape; each element holds the number of level cuts below it (0..levels-1)."""
+    f = gaussian_field(rng, shape, sigma)
     cuts = np.quantile(f, np.arange(1, levels) / levels)
     return np.searchsorted(cuts, f, side="right").astype(np.uint8)
+
+
+def quantised_volume(rng: np.random.Generator, side: int, sigma: float, levels: int = 8) -> np.ndarray:
+    """Smoothed noise volume; each voxel holds the number of level cuts below it (0..levels-1)."""
+    return quantised_field(rng, (side, side, side), sigma, levels)
 
 
 # --------------------------------------------------------------------------
@@ -119,8 +124,9 @@ def polar_vectors(rng: np.random.Generator, count: int, rmin: float, rmax: float
     return np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
 
 
-def sphere_vectors(rng: np.random.Generator, count: int, rmin: float, rmax: float) -> np.ndarray:
-    g = rng.standard_normal((count, 3))
+def sphere_vectors(rng: np.random.Generator, count: int, rmin: float, rmax: float, dim: int = 3) -> np.ndarray:
+    """Vectors with a uniform direction on the unit sphere of R^dim and norm ~ U[rmin, rmax]."""
+    g = rng.standard_normal((count, dim))
     g /= np.linalg.norm(g, axis=1, keepdims=True)
     r = rng.uniform(rmin, rmax, count)
     return g * r[:, None]
@@ -201,6 +207,21 @@ def volume_128(seed: int = 3, side: int = 128, n_dirs: int = 2048, n_xi: int = 1
     return Workload(f"volume_{side}", 3, [vol], origin=np.zeros((1, 3)),
                     ect_dirs=fibonacci_dirs(n_dirs), ect_thresholds=even_thresholds(R, 256),
                     hybrid_xi=xi, hybrid_kernels=("fourier", "laplace"),
+                    meta={"R": R, "seed": seed, "sigma": sigma})
+
+
+def hypervolume_24(seed: int = 6, side: int = 24, n_dirs: int = 512, n_xi: int = 4096,
+                   sigma: float = 2.0) -> Workload:
+    """A four-axis field (n-dimensional arrays): side^4 smoothed noise quantised into 8 levels,
+    primal construction, centred; ECT at 512 uniform directions of S^3 x 256 thresholds; the
+    three hybrid kernels at 4096 xi with |xi| ~ U[0.01, 1]."""
+    rng = np.random.default_rng(seed)
+    vol = quantised_field(rng, (side,) * 4, sigma)
+    R = float(side)   # half the diagonal of the centred box [-side/2, side/2]^4
+    dirs = sphere_vectors(rng, n_dirs, 1.0, 1.0, dim=4)
+    xi = sphere_vectors(rng, n_xi, 0.01, 1.0, dim=4)
+    return Workload(f"hypervolume_{side}", 4, [vol], ect_dirs=dirs, ect_thresholds=even_thresholds(R, 256),
+                    hybrid_xi=xi, hybrid_kernels=("fourier", "laplace", "bessel"),
                     meta={"R": R, "seed": seed, "sigma": sigma})
 
 
