@@ -220,6 +220,7 @@ union SortStorage {
     typename BlockSort<1>::storage_type s1;
     typename BlockSort<2>::storage_type s2;
     typename BlockSort<4>::storage_type s4;
+    typename BlockSort<6>::storage_type s6;
     typename BlockSort<kTileItems>::storage_type s8;
 };
 
@@ -238,6 +239,7 @@ __device__ __forceinline__ typename BlockSort<I>::storage_type& sort_storage(Row
     if constexpr (I == 1) return sh.sort.s1;
     else if constexpr (I == 2) return sh.sort.s2;
     else if constexpr (I == 4) return sh.sort.s4;
+    else if constexpr (I == 6) return sh.sort.s6;
     else return sh.sort.s8;
 }
 
@@ -430,6 +432,7 @@ __device__ int64_t build_segment(const ExactArgs& a, const PointT<N>* pts, int64
     if (n <= kFinThreads) return build_tile<N, 1>(pts, n, sign, xi, out_T, out_E, sh);
     if (n <= 2 * kFinThreads) return build_tile<N, 2>(pts, n, sign, xi, out_T, out_E, sh);
     if (n <= 4 * kFinThreads) return build_tile<N, 4>(pts, n, sign, xi, out_T, out_E, sh);
+    if (n <= 6 * kFinThreads) return build_tile<N, 6>(pts, n, sign, xi, out_T, out_E, sh);
     if (n <= kTile) return build_tile<N, kTileItems>(pts, n, sign, xi, out_T, out_E, sh);
     return build_long<N>(pts, n, sign, xi, a.keys_a + w0, a.vals_a + w0, a.keys_b + w0, a.vals_b + w0, out_T, out_E,
                          sh);

@@ -301,6 +301,38 @@ worklist_kernel(int num_images, int B, int list_base, int NL, int shared_queries
 constexpr int kPrepRows = 8;   // query rows in flight per thread (ragged small sets)
 constexpr int64_t kSharedMaxRows = 65536;
 
+// Hybrid queries are ordered inside their orthant-pair bucket by a sub-bin:
+// the octave of |xi| (major), then the angle of (xi_0, xi_1) modulo pi in 32
+// bins (of a monotone stand-in for the angle).  The 64 queries of a tile then project each point to nearby
+// values, so the lanes of a wave mostly fall on the same side of the Bessel
+// kernel's |z| < 8 branch (on a 512^2 field with 4096 random xi, waves that
+// need both branches drop from 95% to about 23% of the (wave, point) pairs).
+// Every query's sum is independent of its tile and lane, so the order inside a
+// sub-bin (LDS atomics) does not change any output bit.
+constexpr int kSubBands = 16, kSubAngles = 32, kSubBins = kSubBands * kSubAngles;
+
+template <int N>
+__device__ __forceinline__ int sub_bin(const double* v) {
+    double r2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < N; ++a) r2 = fma(v[a], v[a], r2);
+    // floor(log2 |xi|^2) from the exponent field; octaves of |xi| from 2^-12
+    const int ex = (int)((__double_as_longlong(r2) >> 52) & 0x7ff) - 1023;
+    const int lb = ex + 24 < 0 ? 0 : (ex + 24) >> 1;
+    const int band = !(r2 > 0.0) ? 0 : (lb >= kSubBands ? kSubBands - 1 : lb);
+    // angle of (xi_0, xi_1) modulo pi as a monotone "diamond" angle in [0, 2)
+    float x = (float)v[0], y = (float)v[1];
+    if (y < 0.0f || (y == 0.0f && x < 0.0f)) {
+        x = -x;
+        y = -y;
+    }
+    const float d = fabsf(x) + y;
+    const float t = d > 0.0f ? (x >= 0.0f ? y / d : 2.0f - y / d) : 0.0f;
+    const float f = t * (0.5f * kSubAngles);
+    const int ab = f >= 0.0f && f < (float)kSubAngles ? (int)f : (f >= (float)kSubAngles ? kSubAngles - 1 : 0);
+    return band * kSubAngles + ab;
+}
+
 template <int N>
 __global__ void __launch_bounds__(1024)
 prepare_shared_kernel(const double* __restrict__ vecs, int64_t rows, int num_images, int mode_hybrid,
@@ -312,6 +344,8 @@ prepare_shared_kernel(const double* __restrict__ vecs, int64_t rows, int num_ima
     constexpr int U = 4;   // batches whose loads are in flight together
     __shared__ int32_t s_wc[W][1 << kMaxDim];
     __shared__ int32_t s_tot[1 << kMaxDim];
+    __shared__ int32_t s_start[1 << kMaxDim];
+    __shared__ int32_t s_bin[(1 << (kMaxDim - 1)) * kSubBins];   // hybrid: counts, then slots
     const int B = mode_hybrid ? (1 << (N - 1)) : (1 << N);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -333,6 +367,123 @@ prepare_shared_kernel(const double* __restrict__ vecs, int64_t rows, int num_ima
                 v[u][a] = r < w1 ? vecs[r * N + a] : 0.0;
             }
     };
+    if (mode_hybrid) {
+        // counting sort by (bucket, sub-bin): counts, exclusive scan, slots.
+        // When every wave's block is one batch (up to 16 * 64 * U rows), the
+        // records and bins stay in registers between the two phases.
+        const int nbins = B * kSubBins;
+        const bool one = per <= 64 * U;
+        for (int i = tid; i < nbins; i += 1024) s_bin[i] = 0;
+        QRecT<N> keep[U];
+        int64_t keep_sb[U];
+        int keep_bin[U];
+        if (one) {
+            double v[U][N];
+            load(w0, v);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t r = w0 + 64 * u + lane;
+                keep_bin[u] = -1;
+                keep_sb[u] = 0;
+                if (r < w1) {
+                    const int key = (int)classify_vec<N>(v[u], r, 0, 0, rows, mode_hybrid, err, &keep[u], &keep_sb[u]);
+                    keep_bin[u] = key * kSubBins + sub_bin<N>(keep[u].v);
+                }
+            }
+        }
+        __syncthreads();
+        if (one) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (keep_bin[u] >= 0) atomicAdd(&s_bin[keep_bin[u]], 1);
+        } else {
+            for (int64_t rb = w0; rb < w1; rb += 64 * U) {
+                double v[U][N];
+                load(rb, v);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t r = rb + 64 * u + lane;
+                    if (r >= w1) continue;
+                    QRecT<N> rec;
+                    int64_t sb;
+                    const int key = (int)classify_vec<N>(v[u], r, 0, 0, rows, mode_hybrid, err, &rec, &sb);
+                    atomicAdd(&s_bin[key * kSubBins + sub_bin<N>(rec.v)], 1);
+                }
+            }
+        }
+        __syncthreads();
+        const int bpt = (nbins + 1023) / 1024;   // bins per thread
+        int32_t loc = 0;
+        for (int j = 0; j < bpt; ++j) {
+            const int i = tid * bpt + j;
+            if (i < nbins) loc += s_bin[i];
+        }
+        int32_t inc = loc;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t o = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += o;
+        }
+        if (lane == 63) s_wc[wave][0] = inc;
+        __syncthreads();
+        int32_t run = inc - loc, total = 0;
+        for (int w = 0; w < W; ++w) {
+            if (w < wave) run += s_wc[w][0];
+            total += s_wc[w][0];
+        }
+        for (int j = 0; j < bpt; ++j) {
+            const int i = tid * bpt + j;
+            if (i < nbins) {
+                const int32_t c = s_bin[i];
+                s_bin[i] = run;
+                run += c;
+            }
+        }
+        __syncthreads();
+        if (tid < B) {
+            const int32_t start = s_bin[tid * kSubBins];
+            const int32_t end = tid + 1 < B ? s_bin[(tid + 1) * kSubBins] : total;
+            s_start[tid] = start;
+            s_tot[tid] = end - start;
+            bcnt[tid] = end - start;
+        }
+        __syncthreads();
+        if (one) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (keep_bin[u] < 0) continue;
+                const int pos = atomicAdd(&s_bin[keep_bin[u]], 1) - s_start[keep_bin[u] / kSubBins];
+                recs[keep_sb[u] + pos] = keep[u];
+            }
+        } else {
+            for (int64_t rb = w0; rb < w1; rb += 64 * U) {
+                double v[U][N];
+                load(rb, v);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t r = rb + 64 * u + lane;
+                    if (r >= w1) continue;
+                    QRecT<N> rec;
+                    int64_t sb = 0;
+                    const int key = (int)classify_vec<N>(v[u], r, 0, 0, rows, mode_hybrid, nullptr, &rec, &sb);
+                    const int pos = atomicAdd(&s_bin[key * kSubBins + sub_bin<N>(rec.v)], 1) - s_start[key];
+                    recs[sb + pos] = rec;
+                }
+            }
+        }
+        // the work list needs only the bucket totals: no barrier, so the
+        // record stores drain while it is built
+        if (EW <= 64) {
+            if (wave == 0)
+                worklist_wave(EW, lane < EW ? s_tot[lane % B] : 0, np_lane, qtile, chunk0, capacity, err, item_off,
+                              tile_off, params);
+        } else {
+            build_worklist(num_images, B, list_base, NL, 1, s_tot, list_off, nullptr, qtile, chunk0, capacity, err,
+                           item_off, tile_off, params);
+        }
+        return;
+    }
+    // ECT buckets: stable partition (row order kept inside a bucket)
     // pass 1: per-wave bucket counts
     int32_t cnt = 0;   // lane b < B: count of bucket b in this wave's block
     for (int64_t rb = w0; rb < w1; rb += 64 * U) {
