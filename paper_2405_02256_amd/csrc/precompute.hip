@@ -455,60 +455,59 @@ tile_count_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ de
 constexpr int kScanTiles = 1024;
 
 // Inclusive scan over a 1024-thread workgroup of one value per thread and
-// channel (wave shuffles, then the 16 wave totals); returns the total.
+// channel (wave shuffles; one thread per channel scans the 16 wave totals in
+// LDS); the channel totals go to s_tot.  A block covers kScanTiles tiles of
+// at most tile_verts(n) <= 1024 entries per list, so in-block values fit in
+// 32 bits and every channel goes in one pass; callers add 64-bit bases.
 template <int NL>
-__device__ __forceinline__ void block_scan_channels(int64_t (&v)[NL], int64_t (&total)[NL],
-                                                    int64_t (*s_w)[NL]) {
+__device__ __forceinline__ void block_scan_channels(int32_t (&v)[NL], int32_t (*s_w)[NL], int32_t* s_tot) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int l = 0; l < NL; ++l) {
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            const int64_t o = __shfl_up(v[l], off, 64);
+            const int32_t o = __shfl_up(v[l], off, 64);
             if (lane >= off) v[l] += o;
         }
         if (lane == 63) s_w[wave][l] = v[l];
     }
     __syncthreads();
-#pragma unroll
-    for (int l = 0; l < NL; ++l) {
-        int64_t before = 0, all = 0;
+    // thread l: exclusive prefix of the 16 wave totals of channel l, in place
+    if ((int)threadIdx.x < NL) {
+        int32_t run = 0;
         for (int w = 0; w < 16; ++w) {
-            const int64_t x = s_w[w][l];
-            if (w < wave) before += x;
-            all += x;
+            const int32_t c = s_w[w][threadIdx.x];
+            s_w[w][threadIdx.x] = run;
+            run += c;
         }
-        v[l] += before;
-        total[l] = all;
+        s_tot[threadIdx.x] = run;
     }
     __syncthreads();
+#pragma unroll
+    for (int l = 0; l < NL; ++l) v[l] += s_w[wave][l];
 }
 
-// The lists are scanned a few channels at a time: with every channel in one
-// pass the 64-bit per-thread values of a 1024-thread workgroup spill to
-// scratch memory, which made these launches hundreds of microseconds long.
-constexpr int kScanGroup = 2;
-
-template <int NL>
-__host__ __device__ constexpr int scan_group() { return NL < kScanGroup ? NL : kScanGroup; }
-
+// Per-block sums of the tile counts (a reduction per list).
 template <int NL>
 __global__ void __launch_bounds__(1024)
 tile_block_sum_kernel(const int32_t* __restrict__ counts, int64_t num_tiles, int64_t* __restrict__ blk) {
-    constexpr int G = scan_group<NL>();
-    __shared__ int64_t s_w[16][G];
+    __shared__ int32_t s_w[16][NL];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t t = (int64_t)blockIdx.x * kScanTiles + threadIdx.x;
-    for (int l0 = 0; l0 < NL; l0 += G) {
-        int64_t v[G], tot[G];
+    int32_t v[NL];
 #pragma unroll
-        for (int l = 0; l < G; ++l) v[l] = (t < num_tiles && l0 + l < NL) ? counts[t * NL + l0 + l] : 0;
-        block_scan_channels<G>(v, tot, s_w);
-        if ((int)threadIdx.x < G && l0 + (int)threadIdx.x < NL) {
-            int64_t mine = 0;
+    for (int l = 0; l < NL; ++l) v[l] = t < num_tiles ? counts[t * NL + l] : 0;
 #pragma unroll
-            for (int l = 0; l < G; ++l) if ((int)threadIdx.x == l) mine = tot[l];
-            blk[(int64_t)blockIdx.x * NL + l0 + threadIdx.x] = mine;
-        }
+    for (int l = 0; l < NL; ++l) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[l] += __shfl_xor(v[l], off, 64);
+        if (lane == 0) s_w[wave][l] = v[l];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NL) {
+        int64_t sum = 0;
+        for (int w = 0; w < 16; ++w) sum += s_w[w][threadIdx.x];
+        blk[(int64_t)blockIdx.x * NL + threadIdx.x] = sum;
     }
 }
 
@@ -517,72 +516,55 @@ tile_block_sum_kernel(const int32_t* __restrict__ counts, int64_t num_tiles, int
 template <int NL>
 __global__ void __launch_bounds__(1024)
 tile_block_scan_kernel(int64_t* __restrict__ blk, int64_t nblk, int32_t num_images, int64_t* __restrict__ list_off) {
-    constexpr int G = scan_group<NL>();
-    __shared__ int64_t s_w[16][G];
-    for (int l0 = 0; l0 < NL; l0 += G) {
-        int64_t carry[G];
+    __shared__ int32_t s_w[16][NL];
+    __shared__ int32_t s_tot[NL];
+    __shared__ int64_t s_carry[NL];
+    if ((int)threadIdx.x < NL) s_carry[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nblk; base += 1024) {
+        const int64_t b = base + threadIdx.x;
+        int32_t v[NL], x[NL];
 #pragma unroll
-        for (int l = 0; l < G; ++l) carry[l] = 0;
-        for (int64_t base = 0; base < nblk; base += 1024) {
-            const int64_t b = base + threadIdx.x;
-            int64_t v[G], x[G], tot[G];
+        for (int l = 0; l < NL; ++l) x[l] = v[l] = b < nblk ? (int32_t)blk[b * NL + l] : 0;
+        block_scan_channels<NL>(v, s_w, s_tot);
+        if (b < nblk)
 #pragma unroll
-            for (int l = 0; l < G; ++l) x[l] = v[l] = (b < nblk && l0 + l < NL) ? blk[b * NL + l0 + l] : 0;
-            block_scan_channels<G>(v, tot, s_w);
-            if (b < nblk)
-#pragma unroll
-                for (int l = 0; l < G; ++l)
-                    if (l0 + l < NL) blk[b * NL + l0 + l] = carry[l] + v[l] - x[l];
-#pragma unroll
-            for (int l = 0; l < G; ++l) carry[l] += tot[l];
-        }
-        if ((int)threadIdx.x < G && l0 + (int)threadIdx.x < NL) {
-            int64_t mine = 0;
-#pragma unroll
-            for (int l = 0; l < G; ++l) if ((int)threadIdx.x == l) mine = carry[l];
-            list_off[(int64_t)num_images * NL + l0 + threadIdx.x] = mine;
-        }
+            for (int l = 0; l < NL; ++l) blk[b * NL + l] = s_carry[l] + (int64_t)(v[l] - x[l]);
+        __syncthreads();
+        if ((int)threadIdx.x < NL) s_carry[threadIdx.x] += s_tot[threadIdx.x];
+        __syncthreads();
     }
+    if ((int)threadIdx.x < NL) list_off[(int64_t)num_images * NL + threadIdx.x] = s_carry[threadIdx.x];
 }
 
+// Per-block scans plus the block's base: the tile prefixes, and the list
+// offsets of every image whose first tile is one of the block's tiles.
 template <int NL>
 __global__ void __launch_bounds__(1024)
 tile_block_apply_kernel(const int32_t* __restrict__ counts, int64_t num_tiles, const int64_t* __restrict__ blk,
                         const int64_t* __restrict__ tile_start, int32_t num_images, int64_t* __restrict__ prefix,
                         int64_t* __restrict__ list_off) {
-    constexpr int G = scan_group<NL>();
-    __shared__ int64_t s_w[16][G];
-    __shared__ int64_t s_pref[kScanTiles][G];
-    const int64_t t0 = (int64_t)blockIdx.x * kScanTiles;
-    const int64_t t = t0 + threadIdx.x;
-    // images whose first tile lies in this block: the first one by binary
-    // search, then consecutive images
+    __shared__ int32_t s_w[16][NL];
+    __shared__ int32_t s_tot[NL];
+    const int64_t t = (int64_t)blockIdx.x * kScanTiles + threadIdx.x;
+    int32_t v[NL], x[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) x[l] = v[l] = t < num_tiles ? counts[t * NL + l] : 0;
+    // the image (if any) whose first tile is t; tile starts strictly increase
     int lo = 0, hi = num_images;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (tile_start[mid] < t0) lo = mid + 1; else hi = mid;
+        if (tile_start[mid] < t) lo = mid + 1; else hi = mid;
     }
-    for (int l0 = 0; l0 < NL; l0 += G) {
-        int64_t v[G], x[G], tot[G];
+    const bool first = t < num_tiles && lo < num_images && tile_start[lo] == t;
+    block_scan_channels<NL>(v, s_w, s_tot);
+    if (t < num_tiles) {
 #pragma unroll
-        for (int l = 0; l < G; ++l) x[l] = v[l] = (t < num_tiles && l0 + l < NL) ? counts[t * NL + l0 + l] : 0;
-        block_scan_channels<G>(v, tot, s_w);
-#pragma unroll
-        for (int l = 0; l < G; ++l) {
-            if (l0 + l >= NL) continue;
-            const int64_t p = blk[(int64_t)blockIdx.x * NL + l0 + l] + v[l] - x[l];
-            s_pref[threadIdx.x][l] = p;
-            if (t < num_tiles) prefix[t * NL + l0 + l] = p;
+        for (int l = 0; l < NL; ++l) {
+            const int64_t p = blk[(int64_t)blockIdx.x * NL + l] + (int64_t)(v[l] - x[l]);
+            prefix[t * NL + l] = p;
+            if (first) list_off[(int64_t)lo * NL + l] = p;
         }
-        __syncthreads();
-        for (int i = lo + (int)threadIdx.x; i < num_images; i += 1024) {
-            const int64_t ts = tile_start[i];
-            if (ts >= t0 + kScanTiles) break;
-#pragma unroll
-            for (int l = 0; l < G; ++l)
-                if (l0 + l < NL) list_off[(int64_t)i * NL + l0 + l] = s_pref[ts - t0][l];
-        }
-        __syncthreads();
     }
 }
 
