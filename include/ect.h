@@ -235,7 +235,11 @@ ect_status ect_exact_eval(int32_t kind, int64_t rows, const int64_t* row_off, co
 /* hybrid_eval -- HT(xi) = integral kappa_s(t) R(xi,t) dt (Sec. 2.2), evaluated
  * as the sum over ordinary critical points of Delta^ord(eps,x) kbar_s(<xi,x>)
  * (Lemma 3.1 with the sign that the definition gives).
- *   kernel, s       ect_kernel and scale (s finite; s != 0)
+ *   kernel, s       ect_kernel and scale (s finite).  s = 0 is the limit of
+ *                   the scaled kernels: kappa_0 = kappa(0) = 1 for all three,
+ *                   so HT_0(xi) = integral of R(xi, t) dt = sum over ordinary
+ *                   points of Delta^ord <xi, x> (Fourier: that real part and
+ *                   imaginary part 0; Laplace log_scale 0)
  *   precision       ect_precision
  *   xi              query set (DEVICE vectors)
  *   out             DEVICE double [rows] (Laplace, Bessel) or [rows][2]
@@ -264,7 +268,8 @@ ect_status hybrid_eval_multi(ect_plan plan, uint32_t kernel_mask, double s, int3
 /* hybrid_eval_backward -- vector-Jacobian product of hybrid_eval (without
  * log_scale) with respect to xi and to the scale s.  With kappa the kernel,
  * dHT/dxi_a = sum Delta^ord x_a kappa(s <xi,x>) and
- * dHT/ds = (1/s) [sum Delta^ord <xi,x> kappa(s <xi,x>) - HT].
+ * dHT/ds = (1/s) [sum Delta^ord <xi,x> kappa(s <xi,x>) - HT].  s must be
+ * nonzero (s = 0 returns ECT_E_UNSUPPORTED).
  *   out         DEVICE: the forward output of the same call (needed for d/ds)
  *   grad_out    DEVICE, layout of out
  *   grad_xi     DEVICE double [rows][ndim] for a ragged set; for a shared set

@@ -410,7 +410,7 @@ int oracle_hybrid(int n, const int32_t* dims, const int32_t* px, int constructio
                   double* out, double* shift) {
     ogrid g;
     if (grid_init(&g, n, dims, construction, origin, spacing)) return 1;
-    if (!(s == s) || (s == 0.0)) return 1;
+    if (!(s == s)) return 1;
     cellset cs;
     if (cellset_build(&g, px, construction, 1, &cs)) return 3;
     double* x = vertex_coords(&g);
@@ -441,11 +441,13 @@ int oracle_hybrid(int n, const int32_t* dims, const int32_t* px, int constructio
                     double e = -s * u[v];
                     if (!have_m || e > m) { m = e; have_m = 1; }
                 }
-                if (kernel != OR_LAPLACE || !shift) m = 0.0;
+                if (kernel != OR_LAPLACE || !shift || s == 0.0) m = 0.0;
                 for (long long v = 0; v < g.nvert; ++v) {
                     if (!used[v]) continue;
                     double z = s * u[v];
-                    if (kernel == OR_FOURIER) { kr[v] = sin(z) / s; ki[v] = cos(z) / s; }
+                    /* s = 0: kappa_0 is the constant kappa(0) = 1 for every kernel, with primitive t */
+                    if (s == 0.0) { kr[v] = u[v]; ki[v] = 0.0; }
+                    else if (kernel == OR_FOURIER) { kr[v] = sin(z) / s; ki[v] = cos(z) / s; }
                     else if (kernel == OR_LAPLACE) { kr[v] = -exp(-z - m) / s; ki[v] = 0.0; }
                     else { kr[v] = ji0_eval(&tb, z) / s; ki[v] = 0.0; }
                 }

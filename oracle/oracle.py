@@ -494,6 +494,9 @@ def hybrid_integral(img, xi, kernel, s=1.0, construction=PRIMAL, origin=None, sp
 
 
 def _kbar(kernel, s):
+    if s == 0:
+        # kappa_0 is the constant kappa(0) = 1 for every kernel; its primitive is t
+        return (lambda t: t + 0j) if kernel == "fourier" else (lambda t: t)
     if kernel == "fourier":
         return lambda t: (np.sin(s * t) + 1j * np.cos(s * t)) / s
     if kernel == "laplace":

@@ -463,7 +463,8 @@ static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t 
     if (mask == 0 || mask > 7) return ECT_E_INVALID;
     if (backward && (mask & (mask - 1))) return ECT_E_INVALID;
     if (precision != ECT_FP32 && precision != ECT_FP64) return ECT_E_INVALID;
-    if (!std::isfinite(s) || s == 0.0) return ECT_E_INVALID;
+    if (!std::isfinite(s)) return ECT_E_INVALID;
+    if (s == 0.0 && backward) return ECT_E_UNSUPPORTED;   // forward only at the constant-kernel limit
     if (!valid_query_set(xi, plan->num_images)) return ECT_E_INVALID;
     if (!backward) {
         if (((mask & 1) && !out_f) || ((mask & 2) && !out_l) || ((mask & 4) && !out_b)) return ECT_E_INVALID;
@@ -532,7 +533,10 @@ static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t 
     a.params = (const int64_t*)(w + L.params);
     a.partials = (double*)(w + L.partials);
     a.err = err;
-    if (!backward) return from_hip(launch_hybrid(p.ndim, mask, precision, false, a, L.grid, L.tiles, stream));
+    // s = 0: every requested output is the constant-kernel limit sum D <xi, x>
+    if (!backward)
+        return from_hip(launch_hybrid(p.ndim, s == 0.0 ? kHybridLinear : mask, precision, false, a, L.grid, L.tiles,
+                                      stream));
     double* gpart = (double*)(w + L.gpart);
     a.grad_xi = shared ? gpart : grad_xi;
     a.grad_s_part = (double*)(w + L.gspart);

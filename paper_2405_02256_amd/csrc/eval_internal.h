@@ -112,8 +112,14 @@ struct HybridArgs {
     double ji0c[kJi0SmallCoeffs];   // filled at launch (kernel arguments live in scalar registers)
 };
 
+// Mask of the s = 0 pass: HT_0 = sum over ordinary points of D <xi, x> (the
+// constant kernel kappa(0) = 1 with primitive t), written to every output
+// pointer that is set (Fourier: real part, imaginary part 0).
+constexpr unsigned kHybridLinear = 8;
+
 // Main kernel (grid work items) then, for multi-chunk tiles, the in-order
-// reduction (tiles work groups).  mask: bit k = ect_kernel k (backward: one bit).
+// reduction (tiles work groups).  mask: bit k = ect_kernel k (backward: one
+// bit), or kHybridLinear.
 hipError_t launch_hybrid(int ndim, unsigned mask, int precision, bool backward, const HybridArgs& a,
                          int64_t grid, int64_t tiles, hipStream_t stream);
 hipError_t launch_grad_reduce(int ndim, const double* part, int num_images, int64_t count, bool shared,

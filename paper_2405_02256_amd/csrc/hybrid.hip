@@ -127,7 +127,7 @@ struct Query {
     double sigma;     // +1, or -1 when the query's list is the pair's mirror
 };
 
-constexpr int kF = 1 << ECT_FOURIER, kL = 1 << ECT_LAPLACE, kB = 1 << ECT_BESSEL;
+constexpr int kF = 1 << ECT_FOURIER, kL = 1 << ECT_LAPLACE, kB = 1 << ECT_BESSEL, kLin = (int)kHybridLinear;
 // accumulator slots: Fourier 0-1, Laplace 2, Bessel 3; backward: 0..n-1
 constexpr int kSlotF = 0, kSlotL = 2, kSlotB = 3;
 
@@ -139,6 +139,7 @@ __device__ __forceinline__ void accumulate_point(const PointT<N>& pt, const Quer
     double u = q.xi[0] * pt.x[0];
 #pragma unroll
     for (int a = 1; a < N; ++a) u = fma(q.xi[a], pt.x[a], u);
+    if constexpr (MASK == kLin) acc[0] = fma(pt.val, u, acc[0]);
     if constexpr ((MASK & kF) != 0) {
         const double ph = u * q.cF;
         double sn, cs;
@@ -188,6 +189,7 @@ __device__ __forceinline__ void accumulate_point(const PointT<N>& pt, const Quer
 template <int MASK, bool BWD, int N>
 __host__ __device__ constexpr bool slot_used(int k) {
     if (BWD) return k < N;
+    if (MASK == kLin) return k == 0;
     return ((MASK & kF) && (k == 0 || k == 1)) || ((MASK & kL) && k == 2) || ((MASK & kB) && k == 3);
 }
 
@@ -240,7 +242,18 @@ __device__ __forceinline__ void setup_query(const HybridArgs& a, int64_t img, in
 template <int N, int MASK, int PREC, bool BWD>
 __device__ __forceinline__ void finalize(const HybridArgs& a, const Query<N>& q, int64_t row, const double* acc) {
     const double s = a.s;
-    if constexpr (!BWD) {
+    if constexpr (MASK == kLin) {
+        const double v = q.sigma * acc[0];
+        if (a.out_f) {
+            a.out_f[row * 2] = v;
+            a.out_f[row * 2 + 1] = 0.0;
+        }
+        if (a.out_l) {
+            a.out_l[row] = v;
+            if (a.log_scale) a.log_scale[row] = 0.0;
+        }
+        if (a.out_b) a.out_b[row] = v;
+    } else if constexpr (!BWD) {
         if constexpr ((MASK & kF) != 0) {
             a.out_f[row * 2] = q.sigma * acc[kSlotF] / s;
             a.out_f[row * 2 + 1] = q.sigma * acc[kSlotF + 1] / s;
@@ -509,6 +522,7 @@ hipError_t launch_dispatch(unsigned mask, int precision, bool backward, const Hy
         case 4: return launch_mask<N, 4, false>(precision, a, grid, reduce, stream);
         case 5: return launch_mask<N, 5, false>(precision, a, grid, reduce, stream);
         case 6: return launch_mask<N, 6, false>(precision, a, grid, reduce, stream);
+        case kLin: return launch_mask<N, kLin, false>(ECT_FP64, a, grid, reduce, stream);
         default: return launch_mask<N, 7, false>(precision, a, grid, reduce, stream);
     }
 }

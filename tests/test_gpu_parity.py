@@ -479,3 +479,65 @@ def test_autograd_function_matches_finite_differences(api):
             assert abs(fd - float(xi.grad[q, a])) <= 1e-2 * max(1.0, abs(fd))
     fds = (loss(xi0, 1.0 + h) - loss(xi0, 1.0 - h)) / (2 * h)
     assert abs(fds - float(s.grad)) <= 1e-2 * max(1.0, abs(fds))
+
+
+@pytest.mark.parametrize("construction", [O.PRIMAL, O.DUAL])
+def test_hybrid_zero_scale_limit(api, construction):
+    """s = 0: every kernel gives the constant-kernel limit sum D <xi, x> (Fourier: real part, imaginary
+    0), alone and in the fused pass, on shared and ragged sets; the backward refuses s = 0."""
+    from paper_2405_02256_amd import _native as N
+    rng = np.random.default_rng(1201)
+    imgs = [W.random_image(rng, (23, 19), 4), W.random_image(rng, (7, 9, 6), 3)]
+    for img in imgs:
+        n = img.ndim
+        xi = rng.standard_normal((70, n))
+        plan = api.Plan(T(img), construction=construction)
+        ref = O.hybrid(img, xi, "laplace", 0.0, construction)
+        _, od = O.critical_values(img, construction)
+        x = _vertex_coords_np(img, construction)
+        S1 = np.array([np.abs(od[:, _sidx(q)] * (x @ q)).sum() for q in xi])
+        for kernel in ("fourier", "laplace", "bessel"):
+            for precision in ("fp32", "fp64"):
+                y = plan.hybrid(T(xi), kernel, 0.0, precision).cpu().numpy()
+                if kernel == "fourier":
+                    assert (y[:, 1] == 0).all()
+                    y = y[:, 0]
+                assert (np.abs(y - ref) <= 1e-11 * np.maximum(S1, 1.0)).all(), (kernel, precision)
+        outs = plan.hybrid_multi(T(xi), ("fourier", "laplace", "bessel"), 0.0, "fp32")
+        assert np.array_equal(outs["fourier"].cpu().numpy()[:, 0], outs["laplace"].cpu().numpy())
+        assert np.array_equal(outs["bessel"].cpu().numpy(), outs["laplace"].cpu().numpy())
+        y = plan.hybrid(T(xi), "laplace", 0.0, "fp64")
+        with pytest.raises(N.EctError):
+            plan.hybrid_backward(T(xi), y, T(np.ones(70)), "laplace", 0.0, "fp64")
+
+
+def _vertex_coords_np(img, construction):
+    V = list(reversed(O.vertex_shape(img, construction)))
+    o = O.default_origin(img, construction)
+    ks = np.array(list(np.ndindex(*reversed(V))))[:, ::-1]
+    return ks + o[None, :]
+
+
+def _sidx(xi):
+    return sum(1 << a for a in range(len(xi)) if not (xi[a] >= 0))
+
+
+@pytest.mark.parametrize("kernel", ["fourier", "bessel"])
+def test_hybrid_rows_do_not_depend_on_their_tile(api, kernel):
+    """Queries are reordered inside their buckets (sub-bins of |xi| and angle, LDS atomics): a permuted
+    query set gives the permuted outputs bit for bit, in both precisions and for the backward."""
+    rng = np.random.default_rng(1202)
+    img = W.binary_field(rng, (96, 80), 3.0)
+    plan = api.Plan(T(img))
+    xi = W.polar_vectors(rng, 700, 0.01, 1.0, axis_gap=0.02)
+    perm = rng.permutation(len(xi))
+    for precision in ("fp32", "fp64"):
+        y = plan.hybrid(T(xi), kernel, 1.0, precision).cpu().numpy()
+        yp = plan.hybrid(T(xi[perm]), kernel, 1.0, precision).cpu().numpy()
+        assert np.array_equal(yp, y[perm]), precision
+    y = plan.hybrid(T(xi), kernel, 1.0, "fp32")
+    g = rng.standard_normal(tuple(y.shape))
+    gx, _ = plan.hybrid_backward(T(xi), y, T(g), kernel, 1.0, "fp32")
+    yp = plan.hybrid(T(xi[perm]), kernel, 1.0, "fp32")
+    gxp, _ = plan.hybrid_backward(T(xi[perm]), yp, T(g[perm]), kernel, 1.0, "fp32")
+    assert np.array_equal(gxp.cpu().numpy(), gx.cpu().numpy()[perm])

@@ -557,3 +557,27 @@ def test_exact_representations_evaluate_to_the_transforms(construction):
             rep = O.radon_exact(img, xi, construction)
             assert np.array_equal(O.eval_radon_exact(*rep, t), O.radon(img, xi[None], t, construction)[0])
             assert np.all(np.diff(T) > 0) and np.all(np.diff(rep[2]) > 0)
+
+
+# ----------------------------------------------------------------------------
+# s = 0: the constant kernel kappa_0 = kappa(0) = 1 (primitive t)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kernel", ["fourier", "laplace", "bessel"])
+def test_hybrid_at_zero_scale(kernel):
+    """HT_0(xi) = integral of R(xi, t) dt: a closed box gives M - m, the literal integral agrees on a
+    random image, and HT_s tends to it as s -> 0 (the limit of Lemma 3.1's sum, as sum D = 0)."""
+    rng = np.random.default_rng(49)
+    box = np.ones((4, 6), np.uint8)
+    xi = rng.standard_normal((3, 2)) * 0.5
+    got = O.hybrid(box, xi, kernel, 0.0)
+    for q in range(3):
+        M, m = _box_extremes(box, O.PRIMAL, xi[q])
+        assert abs(got[q] - (M - m)) < 1e-12
+    img = W.random_image(rng, (4, 3), 3)
+    x = rng.standard_normal(2) * 0.7
+    a = O.hybrid(img, x[None], kernel, 0.0)[0]
+    assert abs(a - O.hybrid_integral(img, x, kernel, 0.0)) < 1e-11
+    assert abs(O.hybrid(img, x[None], kernel, 1e-7)[0] - a) < 1e-5 * max(1.0, abs(a))
+    if kernel == "fourier":
+        assert a.imag == 0.0
