@@ -12,12 +12,14 @@
 // the record code (code = 2 * row + negated).
 //
 // Bucket b of image i owns the record slots [B*r0_i + b*Q_i, B*r0_i + (b+1)*Q_i)
-// (r0_i = first query row of the image, Q_i = its number of queries).  Small
-// shared sets are partitioned stably (row order kept inside a bucket) by one
-// workgroup with a counting scan; other sets find their slots with one atomic
-// increment per bucket and wave, so the order inside a bucket is not fixed.
-// No result depends on that order: every query is evaluated independently and
-// in a fixed order over the points.
+// (r0_i = first query row of the image, Q_i = its number of queries).  Shared
+// hybrid sets of up to 65536 rows are counting-sorted by one workgroup into
+// sub-bins of |xi| and angle inside each bucket (see prepare_shared_kernel);
+// other sets find their slots with one atomic increment per bucket and wave.
+// No result depends on the order inside a bucket: every query is evaluated
+// independently, with the same chunks, in a fixed order over the points.
+// (Shared ECT sets are not bucketed at all: ect_direct_kernel reads them in
+// place.)
 #include "eval_internal.h"
 
 namespace ect {
@@ -289,26 +291,21 @@ worklist_kernel(int num_images, int B, int list_base, int NL, int shared_queries
                    err, item_off, tile_off, params);
 }
 
-// Small shared sets (<= kSharedMaxRows rows): one 1024-thread workgroup.
-// Wave w takes a contiguous block of rows and walks it 64 rows at a time
-// (lane l takes the l-th row of a batch, so loads and stores coalesce).
-// Pass 1 counts the block's rows per bucket with ballots; an exclusive prefix
-// of the per-wave counts in LDS gives each wave its first slot in every
-// bucket; pass 2 re-reads the rows and writes each record at that base plus
-// its rank among the block's earlier rows of the bucket (ballot popcounts), so
-// the partition is stable (row order kept inside a bucket).  A work list of
-// at most 64 entries is then built by one wave.
+// Shared hybrid query sets of at most kSharedMaxRows rows: one 1024-thread
+// workgroup.  Wave w takes a contiguous block of rows and walks it 64 rows at
+// a time (lane l takes the l-th row of a batch, so loads coalesce).  Queries
+// are counting-sorted by (orthant pair, sub-bin): LDS counters, an exclusive
+// scan of them, then each record goes to its bin's next slot.  The sub-bin is
+// the octave of |xi| (major), then the angle of (xi_0, xi_1) modulo pi in 32
+// bins (of a monotone stand-in for the angle).  The 64 queries of a tile then
+// project each point to nearby values, so the lanes of a wave mostly fall on
+// the same side of the Bessel kernel's |z| < 8 branch (on a 512^2 field with
+// 4096 random xi, waves that need both branches drop from 95% to about 23% of
+// the (wave, point) pairs).  Every query's sum is independent of its tile and
+// lane, so the order inside a sub-bin (LDS atomics) changes no output bit.  A
+// work list of at most 64 entries is then built by one wave.
 constexpr int kPrepRows = 8;   // query rows in flight per thread (ragged small sets)
 constexpr int64_t kSharedMaxRows = 65536;
-
-// Hybrid queries are ordered inside their orthant-pair bucket by a sub-bin:
-// the octave of |xi| (major), then the angle of (xi_0, xi_1) modulo pi in 32
-// bins (of a monotone stand-in for the angle).  The 64 queries of a tile then project each point to nearby
-// values, so the lanes of a wave mostly fall on the same side of the Bessel
-// kernel's |z| < 8 branch (on a 512^2 field with 4096 random xi, waves that
-// need both branches drop from 95% to about 23% of the (wave, point) pairs).
-// Every query's sum is independent of its tile and lane, so the order inside a
-// sub-bin (LDS atomics) does not change any output bit.
 constexpr int kSubBands = 16, kSubAngles = 32, kSubBins = kSubBands * kSubAngles;
 
 template <int N>
@@ -335,20 +332,19 @@ __device__ __forceinline__ int sub_bin(const double* v) {
 
 template <int N>
 __global__ void __launch_bounds__(1024)
-prepare_shared_kernel(const double* __restrict__ vecs, int64_t rows, int num_images, int mode_hybrid,
+prepare_shared_kernel(const double* __restrict__ vecs, int64_t rows, int num_images,
                       uint32_t* __restrict__ err, QRecT<N>* __restrict__ recs, int32_t* __restrict__ bcnt,
                       const int64_t* __restrict__ list_off, int list_base, int NL, int qtile, int64_t chunk0,
                       int64_t capacity, int64_t* __restrict__ item_off, int64_t* __restrict__ tile_off,
                       int64_t* __restrict__ params) {
     constexpr int W = 16;
     constexpr int U = 4;   // batches whose loads are in flight together
-    __shared__ int32_t s_wc[W][1 << kMaxDim];
+    __shared__ int32_t s_wc[W];
     __shared__ int32_t s_tot[1 << kMaxDim];
     __shared__ int32_t s_start[1 << kMaxDim];
-    __shared__ int32_t s_bin[(1 << (kMaxDim - 1)) * kSubBins];   // hybrid: counts, then slots
-    const int B = mode_hybrid ? (1 << (N - 1)) : (1 << N);
+    __shared__ int32_t s_bin[(1 << (kMaxDim - 1)) * kSubBins];   // counts, then slots
+    const int B = 1 << (N - 1);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint64_t lt = (1ull << lane) - 1ull;
     const int64_t EW = (int64_t)num_images * B;
     // list sizes of a small work list, requested first
     int64_t np_lane = 0;
@@ -367,7 +363,7 @@ prepare_shared_kernel(const double* __restrict__ vecs, int64_t rows, int num_ima
                 v[u][a] = r < w1 ? vecs[r * N + a] : 0.0;
             }
     };
-    if (mode_hybrid) {
+    {
         // counting sort by (bucket, sub-bin): counts, exclusive scan, slots.
         // When every wave's block is one batch (up to 16 * 64 * U rows), the
         // records and bins stay in registers between the two phases.
@@ -386,7 +382,7 @@ prepare_shared_kernel(const double* __restrict__ vecs, int64_t rows, int num_ima
                 keep_bin[u] = -1;
                 keep_sb[u] = 0;
                 if (r < w1) {
-                    const int key = (int)classify_vec<N>(v[u], r, 0, 0, rows, mode_hybrid, err, &keep[u], &keep_sb[u]);
+                    const int key = (int)classify_vec<N>(v[u], r, 0, 0, rows, 1, err, &keep[u], &keep_sb[u]);
                     keep_bin[u] = key * kSubBins + sub_bin<N>(keep[u].v);
                 }
             }
@@ -406,7 +402,7 @@ prepare_shared_kernel(const double* __restrict__ vecs, int64_t rows, int num_ima
                     if (r >= w1) continue;
                     QRecT<N> rec;
                     int64_t sb;
-                    const int key = (int)classify_vec<N>(v[u], r, 0, 0, rows, mode_hybrid, err, &rec, &sb);
+                    const int key = (int)classify_vec<N>(v[u], r, 0, 0, rows, 1, err, &rec, &sb);
                     atomicAdd(&s_bin[key * kSubBins + sub_bin<N>(rec.v)], 1);
                 }
             }
@@ -424,12 +420,12 @@ prepare_shared_kernel(const double* __restrict__ vecs, int64_t rows, int num_ima
             const int32_t o = __shfl_up(inc, off, 64);
             if (lane >= off) inc += o;
         }
-        if (lane == 63) s_wc[wave][0] = inc;
+        if (lane == 63) s_wc[wave] = inc;
         __syncthreads();
         int32_t run = inc - loc, total = 0;
         for (int w = 0; w < W; ++w) {
-            if (w < wave) run += s_wc[w][0];
-            total += s_wc[w][0];
+            if (w < wave) run += s_wc[w];
+            total += s_wc[w];
         }
         for (int j = 0; j < bpt; ++j) {
             const int i = tid * bpt + j;
@@ -465,7 +461,7 @@ prepare_shared_kernel(const double* __restrict__ vecs, int64_t rows, int num_ima
                     if (r >= w1) continue;
                     QRecT<N> rec;
                     int64_t sb = 0;
-                    const int key = (int)classify_vec<N>(v[u], r, 0, 0, rows, mode_hybrid, nullptr, &rec, &sb);
+                    const int key = (int)classify_vec<N>(v[u], r, 0, 0, rows, 1, nullptr, &rec, &sb);
                     const int pos = atomicAdd(&s_bin[key * kSubBins + sub_bin<N>(rec.v)], 1) - s_start[key];
                     recs[sb + pos] = rec;
                 }
@@ -481,66 +477,6 @@ prepare_shared_kernel(const double* __restrict__ vecs, int64_t rows, int num_ima
             build_worklist(num_images, B, list_base, NL, 1, s_tot, list_off, nullptr, qtile, chunk0, capacity, err,
                            item_off, tile_off, params);
         }
-        return;
-    }
-    // ECT buckets: stable partition (row order kept inside a bucket)
-    // pass 1: per-wave bucket counts
-    int32_t cnt = 0;   // lane b < B: count of bucket b in this wave's block
-    for (int64_t rb = w0; rb < w1; rb += 64 * U) {
-        double v[U][N];
-        load(rb, v);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t r = rb + 64 * u + lane;
-            QRecT<N> rec;
-            int64_t sb;
-            const int key = r < w1 ? (int)classify_vec<N>(v[u], r, 0, 0, rows, mode_hybrid, err, &rec, &sb) : -1;
-            for (int c = 0; c < B; ++c) {
-                const int n = (int)__popcll(__ballot(key == c));
-                if (lane == c) cnt += n;
-            }
-        }
-    }
-    if (lane < B) s_wc[wave][lane] = cnt;
-    __syncthreads();
-    // exclusive prefix over waves: base of this wave in each bucket (lane b)
-    int32_t base = 0;
-    if (lane < B) {
-        for (int w = 0; w < wave; ++w) base += s_wc[w][lane];
-        if (wave == W - 1) {
-            const int32_t tot = base + s_wc[W - 1][lane];
-            s_tot[lane] = tot;
-            bcnt[lane] = tot;
-        }
-    }
-    // pass 2: records at base + rank, in row order inside each bucket
-    for (int64_t rb = w0; rb < w1; rb += 64 * U) {
-        double v[U][N];
-        load(rb, v);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t r = rb + 64 * u + lane;
-            QRecT<N> rec;
-            int64_t sb = 0;
-            const int key = r < w1 ? (int)classify_vec<N>(v[u], r, 0, 0, rows, mode_hybrid, nullptr, &rec, &sb) : -1;
-            int slot = 0;
-            for (int c = 0; c < B; ++c) {
-                const uint64_t m = __ballot(key == c);
-                const int bc = __shfl(base, c, 64);
-                if (key == c) slot = bc + (int)__popcll(m & lt);
-                if (lane == c) base += (int)__popcll(m);
-            }
-            if (key >= 0) recs[sb + slot] = rec;
-        }
-    }
-    __syncthreads();
-    if (EW <= 64) {
-        if (wave == 0)
-            worklist_wave(EW, lane < EW ? s_tot[lane % B] : 0, np_lane, qtile, chunk0, capacity, err, item_off,
-                          tile_off, params);
-    } else {
-        build_worklist(num_images, B, list_base, NL, 1, s_tot, list_off, nullptr, qtile, chunk0, capacity, err,
-                       item_off, tile_off, params);
     }
 }
 
@@ -627,10 +563,10 @@ hipError_t launch_prepare_typed(const ect_query_set& qs, int num_images, bool hy
     const int64_t rows = qs.count;  // shared: the set itself; ragged: all rows
     const int groups = qs.offsets ? num_images : 1;
     const bool shared = qs.offsets == nullptr;
-    if (shared && rows <= kSharedMaxRows) {
+    if (shared && hybrid && rows <= kSharedMaxRows) {
         hipLaunchKernelGGL(prepare_shared_kernel<N>, dim3(1), dim3(1024), 0, stream, qs.vecs, rows, num_images,
-                           hybrid ? 1 : 0, err, recs, bcnt, list_off, list_base, NL, qtile, chunk, capacity,
-                           item_off, tile_off, params);
+                           err, recs, bcnt, list_off, list_base, NL, qtile, chunk, capacity, item_off, tile_off,
+                           params);
         return hipGetLastError();
     }
     if (rows <= kSmallMaxRows && (int64_t)groups * B <= kSmallMaxEntries) {
