@@ -242,6 +242,7 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
         return ECT_E_DEVICE;
     }
     p->precompute_grid = std::min<int64_t>(per_cu * p->num_cus, 64 * 64);
+    if (n == 2) p->precompute_grid_flat = precompute_slots_per_cu(n, batch->construction, batch->dtype, true) * p->num_cus;
 
     e = hipMemcpyAsync(p->ws + L.desc, desc.data(), sizeof(ImageDesc) * ni, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)

@@ -83,6 +83,7 @@ struct ect_plan_s {
     int32_t construction = 0;
     int32_t num_cus = 0;                    // compute units of the plan's device
     int64_t precompute_grid = 1;            // tiles the single-pass compaction handles (all resident)
+    int64_t precompute_grid_flat = 0;       // the same for its one-level variant (n = 2, small plans)
     const void* pixels = nullptr;
     char* ws = nullptr;
     ect::PlanLayout lay{};
@@ -151,7 +152,8 @@ inline hipError_t stage_mark(int stage, bool after, hipStream_t s) {
 // first: also clear the plan's error word, ticket counter and look-back words
 // (plan creation); re-runs launch the classification kernel alone.
 hipError_t launch_precompute(const Plan& p, bool first, hipStream_t stream);
-// Compaction workgroups one compute unit holds at once (0 if unknown).
-int64_t precompute_slots_per_cu(int ndim, int construction, int dtype);
+// Compaction workgroups one compute unit holds at once (0 if unknown); flat:
+// the one-level look-back variant.
+int64_t precompute_slots_per_cu(int ndim, int construction, int dtype, bool flat = false);
 
 }  // namespace ect

@@ -322,6 +322,57 @@ __device__ __forceinline__ void tile_values(const T* __restrict__ pixels, const 
     }
 }
 
+// Flat variant for plans of at most kFlatTiles tiles: the sum over every
+// predecessor's word directly (up to kFlatChunks * 64 of them, all loads of a
+// poll in flight together), which saves the group-total round trip of the
+// two-level scan.
+constexpr int kFlatChunks = 5;
+constexpr int64_t kFlatTiles = kFlatChunks * 64 + 1;
+
+template <int NL>
+__device__ __forceinline__ bool sum_published_flat(const uint64_t* words, int64_t count, uint64_t parity,
+                                                   uint64_t* sums, uint32_t* err) {
+    const int lane = threadIdx.x & 63;
+    for (int spins = 0;; ++spins) {
+        uint64_t wv[kFlatChunks][NL];
+#pragma unroll
+        for (int c = 0; c < kFlatChunks; ++c)
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                const int64_t i = (int64_t)c * 64 + lane;
+                wv[c][l] = i < count ? __hip_atomic_load(words + i * NL + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                     : (kFlagAggregate | parity);
+            }
+        bool ready = true;
+#pragma unroll
+        for (int c = 0; c < kFlatChunks; ++c)
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                const bool ok = (wv[c][l] & kParityBit) == parity && (wv[c][l] & kFlagMask) != 0;
+                ready = ready && __ballot(!ok) == 0;
+            }
+        if (ready) {
+#pragma unroll
+            for (int l = 0; l < NL; ++l) {
+                uint64_t v = 0;
+#pragma unroll
+                for (int c = 0; c < kFlatChunks; ++c)
+                    v += ((int64_t)c * 64 + lane < count) ? (wv[c][l] & kValueMask) : 0ull;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                sums[l] = v;
+            }
+            return true;
+        }
+        if (spins > kLookbackSpinLimit) {
+            if (lane == 0) raise_error(err, ECT_DEVERR_LOOKBACK);
+            return false;
+        }
+        const int naps = spins < 16 ? spins + 1 : 16;
+        for (int i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(2);
+    }
+}
+
 // Wave 0, lane l < NL: turn list l's counts into exclusive offsets inside the
 // tile and return the tile's total for list l (0 elsewhere).
 template <int NL, int J>
@@ -376,7 +427,7 @@ __device__ __forceinline__ void emit_points(const TileValues<N>& tv,
 // publishes the group total, and the totals of the preceding groups complete
 // the prefix (level 2).  Every word a tile waits on belongs to a running or
 // finished workgroup, so the waits end.
-template <int N, int CONS, typename T>
+template <int N, int CONS, typename T, bool FLAT>
 __global__ void __launch_bounds__(kPrecomputeThreads)
 classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
                  const int64_t* __restrict__ tile_start, int32_t num_images, int64_t num_tiles,
@@ -403,7 +454,16 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
                                __HIP_MEMORY_SCOPE_AGENT);
         const int64_t g = tile >> 6, k = tile & 63;
         uint64_t loc[NL], grp[NL];
-        bool ok = sum_published<NL>(status + (tile - k) * NL, k, parity, loc, err);
+        bool ok;
+        if constexpr (FLAT) {
+            // one level: every predecessor's word
+            ok = sum_published_flat<NL>(status, tile, parity, loc, err);
+#pragma unroll
+            for (int l = 0; l < NL; ++l) grp[l] = 0;
+            if (tile == num_tiles - 1 && lane == 0)
+                __hip_atomic_store(run_ctr, run + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+        ok = sum_published<NL>(status + (tile - k) * NL, k, parity, loc, err);
         if (ok && (k == 63 || tile == num_tiles - 1) && lane < NL) {
             uint64_t mine = 0;
 #pragma unroll
@@ -415,6 +475,7 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
         // every group total is in, so every tile has read the run number
         if (tile == num_tiles - 1 && lane == 0)
             __hip_atomic_store(run_ctr, run + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         if (lane < NL) {
             uint64_t mine = 0;
 #pragma unroll
@@ -611,9 +672,14 @@ hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream) {
     int64_t* lo = (int64_t*)(p.ws + L.list_off);
     PointT<N>* pts = (PointT<N>*)(p.ws + L.points);
     if (single) {
-        hipLaunchKernelGGL((classify_compact<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads), 0,
-                           stream, px, desc, ts, p.num_images, L.num_tiles, err, run_ctr, status, gstatus, lo, pts,
-                           L.capacity);
+        if (N == 2 && L.num_tiles <= kFlatTiles && L.num_tiles <= p.precompute_grid_flat)
+            hipLaunchKernelGGL((classify_compact<N, CONS, T, true>), dim3((unsigned)L.num_tiles),
+                               dim3(kPrecomputeThreads), 0, stream, px, desc, ts, p.num_images, L.num_tiles, err,
+                               run_ctr, status, gstatus, lo, pts, L.capacity);
+        else
+            hipLaunchKernelGGL((classify_compact<N, CONS, T, false>), dim3((unsigned)L.num_tiles),
+                               dim3(kPrecomputeThreads), 0, stream, px, desc, ts, p.num_images, L.num_tiles, err,
+                               run_ctr, status, gstatus, lo, pts, L.capacity);
     } else {
         // the status region holds the counts (int32), the prefixes (int64) and
         // the block sums (int64)
@@ -652,9 +718,12 @@ hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream) {
 }
 
 template <int N, int CONS, typename T>
-int64_t slots_typed() {
+int64_t slots_typed(bool flat) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, classify_compact<N, CONS, T>, kPrecomputeThreads, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
+                                                     flat ? classify_compact<N, CONS, T, true>
+                                                          : classify_compact<N, CONS, T, false>,
+                                                     kPrecomputeThreads, 0) !=
         hipSuccess)
         return 0;
     return per_cu;
@@ -671,13 +740,13 @@ hipError_t launch_dtype(const Plan& p, bool first, hipStream_t s) {
 
 }  // namespace
 
-int64_t precompute_slots_per_cu(int ndim, int construction, int dtype) {
+int64_t precompute_slots_per_cu(int ndim, int construction, int dtype, bool flat) {
     auto pick = [&](auto n, auto c) -> int64_t {
         constexpr int N = decltype(n)::value, C = decltype(c)::value;
         switch (dtype) {
-            case ECT_U8: return slots_typed<N, C, uint8_t>();
-            case ECT_I16: return slots_typed<N, C, int16_t>();
-            default: return slots_typed<N, C, int32_t>();
+            case ECT_U8: return slots_typed<N, C, uint8_t>(flat);
+            case ECT_I16: return slots_typed<N, C, int16_t>(flat);
+            default: return slots_typed<N, C, int32_t>(flat);
         }
     };
     using I2 = std::integral_constant<int, 2>;
