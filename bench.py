@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-4d", action="store_true", help="skip the four-axis workload")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule knobs")
     ap.add_argument("--concurrent", action="store_true", help="run the ECT branch on a side stream")
+    ap.add_argument("--separate-ect", action="store_true",
+                    help="launch the ECT before the hybrid pass instead of inside its launch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (counter calibration) and exit")
     return ap.parse_args()
@@ -248,7 +250,8 @@ def main():
     log("building plan")
     plan = api.Plan(img_t)
     step = pipeline.Step(plan, dirs, thr, xi, kernels=KERNELS, s=1.0, precision="fp32",
-                         backward_kernel="fourier", grad_out=g_t, fused=True, concurrent=args.concurrent)
+                         backward_kernel="fourier", grad_out=g_t, fused=True, concurrent=args.concurrent,
+                         combined=not args.separate_ect)
 
     # work per step: sum over xi of the ordinary list length of its orthant pair
     n = 2
@@ -305,7 +308,9 @@ def main():
 
     # ---- live per-stage kernel timing (library-recorded HIP events) ----
     st = int(torch.cuda.current_stream().cuda_stream)
-    names = ["precompute", "ect", "hybrid_fused", "hybrid_bwd_fourier"]
+    # the step's own launches (the ECT inside the hybrid launch unless
+    # --separate-ect), and the ECT and hybrid passes launched alone for reference
+    names = ["precompute", "ect_hybrid_fused", "ect", "hybrid_fused", "hybrid_bwd_fourier"]
     evs = {nm: [(hipevents.Event(), hipevents.Event()) for _ in range(args.steps)] for nm in names}
 
     def arm(stage, pair_):
@@ -314,6 +319,9 @@ def main():
     for i in range(args.steps):
         arm(N.STAGE_PRECOMPUTE, evs["precompute"][i])
         plan.rerun()
+        arm(N.STAGE_HYBRID, evs["ect_hybrid_fused"][i])
+        plan.ect_hybrid_multi(step.ect_q, step.ect_thr, step.hy_q, KERNELS, 1.0, "fp32", ect_out=step.ect_out,
+                              outs=step.hy_out)
         arm(N.STAGE_ECT, evs["ect"][i])
         plan.ect(step.ect_q, step.ect_thr, out=step.ect_out)
         arm(N.STAGE_HYBRID, evs["hybrid_fused"][i])
@@ -326,9 +334,14 @@ def main():
         N.ect_set_stage_events(stg, None, None)
     stage_ms = {nm: float(np.mean([a.elapsed_ms(b) for a, b in evs[nm]])) for nm in names}
     log("stage kernel ms: " + ", ".join(f"{k}={v:.4f}" for k, v in stage_ms.items()))
-    dom = max(stage_ms, key=stage_ms.get)
+    in_step = (["precompute", "ect_hybrid_fused", "hybrid_bwd_fourier"] if step.combined
+               else ["precompute", "ect", "hybrid_fused", "hybrid_bwd_fourier"])
+    dom = max(in_step, key=stage_ms.get)
     dsec = stage_ms[dom] * 1e-3
-    if dom == "precompute":
+    if dom == "ect_hybrid_fused":
+        roof = roofline.alu_roofline_parts([("ect", n, ect_pairs, 1.0),
+                                            ("+".join(KERNELS), n, per_kernel_pairs, small_frac)], dsec)
+    elif dom == "precompute":
         nbytes = img.size + 32.0 * float(cls_counts.sum() + counts.sum()) + 8 * 2 * 6
         roof = roofline.hbm_roofline(nbytes, dsec)
     elif dom == "ect":

@@ -111,7 +111,7 @@ typedef struct {
  * offsets[i] .. offsets[i+1]-1 and `count` is the total number of rows
  * (offsets[num_images]). */
 typedef struct {
-    const double* vecs;            /* DEVICE [rows][ndim] */
+    const double* vecs;            /* DEVICE [rows][ndim]; may be NULL when count is 0 */
     const int64_t* offsets;        /* DEVICE [num_images+1], non-decreasing, or NULL */
     int64_t count;
 } ect_query_set;
@@ -264,6 +264,25 @@ ect_status hybrid_eval(ect_plan plan, int32_t kernel, double s, int32_t precisio
 ect_status hybrid_eval_multi(ect_plan plan, uint32_t kernel_mask, double s, int32_t precision,
                              ect_query_set xi, double* out_fourier, double* out_laplace, double* out_bessel,
                              double* log_scale_laplace, void* ws, size_t* ws_bytes, hipStream_t stream);
+
+/* ect_hybrid_eval_multi -- ect_eval(plan, dirs, thresholds, M,
+ * thresholds_per_image, ect_out) and hybrid_eval_multi(plan, kernel_mask, s,
+ * precision, xi, out_fourier, out_laplace, out_bessel, log_scale_laplace) in
+ * one call with one workspace; every argument means what it means there, and
+ * the outputs equal those of the two separate calls bit for bit.  For a
+ * shared direction set with at most two directions per ECT workgroup and
+ * small threshold arrays (M (8 + 4 d) <= 4096 bytes of LDS, d the directions
+ * per workgroup) and s != 0, the ECT workgroups run in the same launch as
+ * the hybrid work items, so the short ECT work fills the hybrid pass's idle
+ * compute units instead of running before it; otherwise the two run one
+ * after the other.  The hybrid part's buckets and work list sit at the start
+ * of ws, so a following hybrid_eval_backward with the same ws and
+ * ECT_BWD_REUSE_PREPARED reuses them.  Errors: those of either call. */
+ect_status ect_hybrid_eval_multi(ect_plan plan, ect_query_set dirs, const double* thresholds, int32_t M,
+                                 int32_t thresholds_per_image, int32_t* ect_out, uint32_t kernel_mask, double s,
+                                 int32_t precision, ect_query_set xi, double* out_fourier, double* out_laplace,
+                                 double* out_bessel, double* log_scale_laplace, void* ws, size_t* ws_bytes,
+                                 hipStream_t stream);
 
 /* hybrid_eval_backward -- vector-Jacobian product of hybrid_eval (without
  * log_scale) with respect to xi and to the scale s.  With kappa the kernel,

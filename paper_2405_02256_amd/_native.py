@@ -70,6 +70,8 @@ def lib():
     L.hybrid_eval.argtypes = [c_vp, c_i32, c_f64, c_i32, QuerySet, c_vp, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
     L.hybrid_eval_multi.argtypes = [c_vp, c_u32, c_f64, c_i32, QuerySet, c_vp, c_vp, c_vp, c_vp, c_vp,
                                     P(ctypes.c_size_t), c_vp]
+    L.ect_hybrid_eval_multi.argtypes = [c_vp, QuerySet, c_vp, c_i32, c_i32, c_vp, c_u32, c_f64, c_i32, QuerySet,
+                                        c_vp, c_vp, c_vp, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
     L.hybrid_eval_backward.argtypes = [c_vp, c_i32, c_f64, c_i32, QuerySet, c_vp, c_vp, c_vp, c_vp, c_u32,
                                        c_vp, P(ctypes.c_size_t), c_vp]
     L.ect_plan_counts.argtypes = [c_vp, P(c_i64), P(c_i64)]
@@ -82,7 +84,7 @@ def lib():
     L.ect_exact.argtypes = [c_vp, QuerySet, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
     L.ect_exact_eval.argtypes = [c_i32, c_i64, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_i32, c_i32, c_vp, c_vp]
     for name in ("ect_precompute", "ect_plan_rerun", "ect_eval", "radon_eval", "hybrid_eval", "hybrid_eval_multi",
-                 "hybrid_eval_backward", "ect_exact_layout", "ect_exact", "ect_exact_eval",
+                 "ect_hybrid_eval_multi", "hybrid_eval_backward", "ect_exact_layout", "ect_exact", "ect_exact_eval",
                  "ect_plan_counts", "ect_plan_export", "ect_plan_check", "ect_plan_destroy", "ect_plan_set_tuning",
                  "ect_set_stage_events"):
         getattr(L, name).restype = c_i32
@@ -153,6 +155,15 @@ def hybrid_eval_multi(plan, mask, s, precision, xi: QuerySet, out_f, out_l, out_
                                    c_vp(out_f) if out_f else None, c_vp(out_l) if out_l else None,
                                    c_vp(out_b) if out_b else None, c_vp(log_scale) if log_scale else None, ws,
                                    ctypes.byref(ws_bytes), c_vp(stream))
+
+
+def ect_hybrid_eval_multi(plan, dirs: QuerySet, thresholds, M, per_image, ect_out, mask, s, precision,
+                          xi: QuerySet, out_f, out_l, out_b, log_scale, ws, ws_bytes: ctypes.c_size_t, stream) -> int:
+    return lib().ect_hybrid_eval_multi(c_vp(plan), dirs, c_vp(thresholds), int(M), int(per_image), c_vp(ect_out),
+                                       int(mask), float(s), int(precision), xi,
+                                       c_vp(out_f) if out_f else None, c_vp(out_l) if out_l else None,
+                                       c_vp(out_b) if out_b else None, c_vp(log_scale) if log_scale else None, ws,
+                                       ctypes.byref(ws_bytes), c_vp(stream))
 
 
 def hybrid_eval_backward(plan, kernel, s, precision, xi: QuerySet, out, grad_out, grad_xi, grad_s, ws,

@@ -294,6 +294,41 @@ class Plan:
                                     _dptr(log_scale_out), ctypes.c_void_p(_dptr(ws)), have, st), "hybrid_eval_multi")
         return {k: outs[k] for k in kernels}
 
+    def ect_hybrid_multi(self, dirs, thresholds: torch.Tensor, xi, kernels=("fourier", "laplace", "bessel"),
+                         s: float = 1.0, precision: str = "fp32", dir_offsets=None, xi_offsets=None, ect_out=None,
+                         outs=None, log_scale_out=None, stream=None, slot: str = "main"):
+        """(ect, {kernel: output}): ect() and hybrid_multi() in one call (ect_hybrid_eval_multi); a shared
+        direction set with small threshold arrays runs both in one launch.  Outputs equal the separate calls'."""
+        qd = dirs if isinstance(dirs, QuerySet) else QuerySet(dirs, dir_offsets)
+        qd.validate(self.num_images, self.ndim)
+        qx = xi if isinstance(xi, QuerySet) else QuerySet(xi, xi_offsets)
+        qx.validate(self.num_images, self.ndim)
+        thr = thresholds.to(device=self.device, dtype=torch.float64).contiguous()
+        per_image = 1 if thr.dim() == 2 else 0
+        if thr.dim() not in (1, 2) or (per_image and thr.shape[0] != self.num_images):
+            raise ValueError("thresholds must be [M] or [num_images][M]")
+        M = thr.shape[-1]
+        if ect_out is None:
+            ect_out = torch.empty((qd.rows(self.num_images), M), dtype=torch.int32, device=self.device)
+        rows = qx.rows(self.num_images)
+        outs = dict(outs or {})
+        mask = 0
+        for k in kernels:
+            mask |= 1 << N.KERNELS[k]
+            if k not in outs:
+                outs[k] = torch.empty((rows, 2) if k == "fourier" else (rows,), dtype=torch.float64,
+                                      device=self.device)
+        st = _stream(stream)
+        ptrs = [_dptr(outs.get(k)) for k in ("fourier", "laplace", "bessel")]
+        head = (self.handle, qd.c(), _dptr(thr), M, per_image, _dptr(ect_out), mask, s, N.PRECISIONS[precision],
+                qx.c(), *ptrs, _dptr(log_scale_out))
+        need = ctypes.c_size_t(0)
+        N.check(N.ect_hybrid_eval_multi(*head, None, need, st), "ect_hybrid_eval_multi(size)")
+        ws = self._ws(need.value, slot)
+        have = ctypes.c_size_t(ws.numel())
+        N.check(N.ect_hybrid_eval_multi(*head, ctypes.c_void_p(_dptr(ws)), have, st), "ect_hybrid_eval_multi")
+        return ect_out, {k: outs[k] for k in kernels}
+
     def hybrid_backward(self, xi, out: torch.Tensor, grad_out: torch.Tensor, kernel: str = "fourier", s: float = 1.0,
                         precision: str = "fp32", offsets=None, stream=None, grad_xi=None, grad_s=None,
                         slot: str = "main", reuse_prepared: bool = False):

@@ -27,7 +27,7 @@ struct EvalLayout {
 };
 
 bool valid_query_set(const ect_query_set& q, int num_images) {
-    if (!q.vecs || q.count < 0) return false;
+    if (q.count < 0 || (!q.vecs && q.count > 0)) return false;
     (void)num_images;
     return true;
 }
@@ -266,19 +266,27 @@ ect_status ect_plan_rerun(ect_plan plan, hipStream_t stream) {
     return from_hip(launch_precompute(*plan, false, stream));
 }
 
-static ect_status threshold_eval(ect_plan plan, ect_query_set dirs, const double* thresholds, int32_t M,
-                                 int32_t thresholds_per_image, int32_t* out, void* ws, size_t* ws_bytes,
-                                 hipStream_t stream, bool radon) {
-    if (!plan || !ws_bytes) return ECT_E_INVALID;
-    if (!valid_query_set(dirs, plan->num_images) || !thresholds || !out) return ECT_E_INVALID;
+// How a threshold evaluation runs: directions per workgroup, list chunks, and
+// whether a shared set goes straight to the direct kernel.
+struct ThresholdSetup {
+    int td;
+    int64_t chunks;
+    bool direct;
+    int64_t direct_groups;
+    EvalLayout L;
+};
+
+static ect_status threshold_setup(const Plan& p, const ect_query_set& dirs, const double* thresholds, int32_t M,
+                                  const int32_t* out, bool radon, ThresholdSetup* S) {
+    if (!valid_query_set(dirs, p.num_images) || !thresholds) return ECT_E_INVALID;
+    if (!out && query_rows(dirs, p.num_images) > 0) return ECT_E_INVALID;
     if (M < 1) return ECT_E_INVALID;
     if (M > kEctMaxThresholds) return ECT_E_UNSUPPORTED;
-    const Plan& p = *plan;
     // directions per workgroup: enough workgroups to fill the chip first, then
     // more directions per streamed point
-    const int64_t nrows = query_rows(dirs, plan->num_images);
-    int td = plan->tune_ect_dirs_per_group > 0
-                 ? plan->tune_ect_dirs_per_group
+    const int64_t nrows = query_rows(dirs, p.num_images);
+    int td = p.tune_ect_dirs_per_group > 0
+                 ? p.tune_ect_dirs_per_group
                  : (dirs.offsets == nullptr ? kEctMaxDirs
                                             : (int)std::min<int64_t>(kEctMaxDirs, std::max<int64_t>(1, nrows / 1024)));
     const int64_t lds_budget = 60 * 1024;
@@ -289,63 +297,78 @@ static ect_status threshold_eval(ect_plan plan, ect_query_set dirs, const double
     // lists are split into chunks so that enough workgroups share each group
     // of directions (about two per compute unit, at least 4096 points each:
     // below that a workgroup's fixed cost outweighs streaming its part)
-    const bool direct = dirs.offsets == nullptr;
-    EvalLayout L{};
-    int64_t chunks = 1;
-    if (direct) {
-        const int64_t groups = (int64_t)p.num_images * ((dirs.count + td - 1) / td);
+    S->td = td;
+    S->direct = dirs.offsets == nullptr;
+    S->chunks = 1;
+    S->direct_groups = 0;
+    S->L = EvalLayout{};
+    if (S->direct) {
+        S->direct_groups = (dirs.count + td - 1) / td;
+        const int64_t groups = (int64_t)p.num_images * S->direct_groups;
         const double avg = mean_list(p, 0, num_classical(p.ndim));
         const int64_t want = (2 * (int64_t)std::max(p.num_cus, 1) + groups - 1) / std::max<int64_t>(groups, 1);
-        chunks = radon ? 1 : p.tune_ect_chunks > 0 ? p.tune_ect_chunks
-                                       : std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)(avg / 4096.0)));
-        if (chunks > 1) L.total = sizeof(int32_t) * (size_t)(groups * chunks * td * (int64_t)M);
+        S->chunks = radon ? 1 : p.tune_ect_chunks > 0 ? p.tune_ect_chunks
+                                          : std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)(avg / 4096.0)));
+        if (S->chunks > 1) S->L.total = sizeof(int32_t) * (size_t)(groups * S->chunks * td * (int64_t)M);
+        S->L.grid = groups * S->chunks;
     } else {
-        layout_ect(p, dirs, td, &L);
+        layout_ect(p, dirs, td, &S->L);
     }
+    return ECT_OK;
+}
+
+static EctArgs threshold_args(const Plan& p, const ect_query_set& dirs, const double* thresholds, int32_t M,
+                              int32_t thresholds_per_image, int32_t* out, char* w, const ThresholdSetup& S) {
+    EctArgs a{};
+    a.points = (const void*)(p.ws + p.lay.points);
+    a.list_off = (const int64_t*)(p.ws + p.lay.list_off);
+    a.desc = (const ImageDesc*)(p.ws + p.lay.desc);
+    a.capacity = p.lay.capacity;
+    a.num_images = p.num_images;
+    a.NL = num_lists(p.ndim);
+    a.vecs = dirs.vecs;
+    a.offsets = dirs.offsets;
+    a.count = dirs.count;
+    a.thresholds = thresholds;
+    a.M = M;
+    a.thr_per_image = thresholds_per_image ? 1 : 0;
+    a.out = out;
+    a.recs = S.direct ? nullptr : (const void*)(w + S.L.recs);
+    a.bcnt = S.direct ? nullptr : (const int32_t*)(w + S.L.bcnt);
+    a.item_off = S.direct ? nullptr : (const int64_t*)(w + S.L.item_off);
+    a.err = (uint32_t*)(p.ws + p.lay.err);
+    a.dirs_per_group = S.td;
+    a.chunks = S.chunks;
+    a.part = S.chunks > 1 ? (int32_t*)w : nullptr;
+    return a;
+}
+
+static ect_status threshold_eval(ect_plan plan, ect_query_set dirs, const double* thresholds, int32_t M,
+                                 int32_t thresholds_per_image, int32_t* out, void* ws, size_t* ws_bytes,
+                                 hipStream_t stream, bool radon) {
+    if (!plan || !ws_bytes) return ECT_E_INVALID;
+    const Plan& p = *plan;
+    ThresholdSetup S;
+    const ect_status st = threshold_setup(p, dirs, thresholds, M, out, radon, &S);
+    if (st != ECT_OK) return st;
     if (!ws) {
-        *ws_bytes = L.total;
+        *ws_bytes = S.L.total;
         return ECT_OK;
     }
-    if (*ws_bytes < L.total) return ECT_E_NOMEM;
-    const int64_t rows = query_rows(dirs, p.num_images);
-    if (rows == 0) return ECT_OK;
+    if (*ws_bytes < S.L.total) return ECT_E_NOMEM;
+    if (query_rows(dirs, p.num_images) == 0) return ECT_OK;
     char* w = (char*)ws;
-    const int NL = num_lists(p.ndim);
-    uint32_t* err = (uint32_t*)(p.ws + p.lay.err);
     hipError_t e = hipSuccess;
-    int64_t direct_groups = 0;
-    if (direct) {
-        direct_groups = (dirs.count + td - 1) / td;
-        L.grid = direct_groups * p.num_images * chunks;
-    } else {
+    if (!S.direct) {
         if (plan->last_prep.ws == ws) plan->last_prep.valid = false;
-        e = launch_prepare(p.ndim, dirs, p.num_images, false, err, (void*)(w + L.recs), (int32_t*)(w + L.bcnt),
-                           (const int64_t*)(p.ws + p.lay.list_off), 0, NL, td, 0, 0, (int64_t*)(w + L.item_off),
-                           (int64_t*)(w + L.tile_off), (int64_t*)(w + L.params), stream);
+        e = launch_prepare(p.ndim, dirs, p.num_images, false, (uint32_t*)(p.ws + p.lay.err), (void*)(w + S.L.recs),
+                           (int32_t*)(w + S.L.bcnt), (const int64_t*)(p.ws + p.lay.list_off), 0, num_lists(p.ndim),
+                           S.td, 0, 0, (int64_t*)(w + S.L.item_off), (int64_t*)(w + S.L.tile_off),
+                           (int64_t*)(w + S.L.params), stream);
     }
     if (e == hipSuccess) {
-        EctArgs a{};
-        a.points = (const void*)(p.ws + p.lay.points);
-        a.list_off = (const int64_t*)(p.ws + p.lay.list_off);
-        a.desc = (const ImageDesc*)(p.ws + p.lay.desc);
-        a.capacity = p.lay.capacity;
-        a.num_images = p.num_images;
-        a.NL = NL;
-        a.vecs = dirs.vecs;
-        a.offsets = dirs.offsets;
-        a.count = dirs.count;
-        a.thresholds = thresholds;
-        a.M = M;
-        a.thr_per_image = thresholds_per_image ? 1 : 0;
-        a.out = out;
-        a.recs = direct ? nullptr : (const void*)(w + L.recs);
-        a.bcnt = direct ? nullptr : (const int32_t*)(w + L.bcnt);
-        a.item_off = direct ? nullptr : (const int64_t*)(w + L.item_off);
-        a.err = err;
-        a.dirs_per_group = td;
-        a.chunks = chunks;
-        a.part = chunks > 1 ? (int32_t*)w : nullptr;
-        e = launch_ect(p.ndim, a, L.grid, direct_groups, radon, stream);
+        const EctArgs a = threshold_args(p, dirs, thresholds, M, thresholds_per_image, out, w, S);
+        e = launch_ect(p.ndim, a, S.L.grid, S.direct_groups, radon, stream);
     }
     return from_hip(e);
 }
@@ -459,7 +482,7 @@ static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t 
                                 double* out_f, double* out_l, double* out_b, double* log_scale,
                                 const double* fwd_out, const double* grad_out, double* grad_xi, double* grad_s,
                                 void* ws, size_t* ws_bytes, hipStream_t stream, bool backward,
-                                bool reuse = false) {
+                                bool reuse = false, const EctArgs* combo = nullptr, int64_t combo_groups = 0) {
     if (!plan || !ws_bytes) return ECT_E_INVALID;
     if (mask == 0 || mask > 7) return ECT_E_INVALID;
     if (backward && (mask & (mask - 1))) return ECT_E_INVALID;
@@ -467,10 +490,12 @@ static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t 
     if (!std::isfinite(s)) return ECT_E_INVALID;
     if (s == 0.0 && backward) return ECT_E_UNSUPPORTED;   // forward only at the constant-kernel limit
     if (!valid_query_set(xi, plan->num_images)) return ECT_E_INVALID;
+    const bool empty = query_rows(xi, plan->num_images) == 0;   // outputs of no rows may be NULL
     if (!backward) {
-        if (((mask & 1) && !out_f) || ((mask & 2) && !out_l) || ((mask & 4) && !out_b)) return ECT_E_INVALID;
+        if (!empty && (((mask & 1) && !out_f) || ((mask & 2) && !out_l) || ((mask & 4) && !out_b)))
+            return ECT_E_INVALID;
         if (log_scale && !(mask & 2)) return ECT_E_INVALID;
-    } else if (!fwd_out || !grad_out || !grad_xi) {
+    } else if (!empty && (!fwd_out || !grad_out || !grad_xi)) {
         return ECT_E_INVALID;
     }
     const Plan& p = *plan;
@@ -487,7 +512,11 @@ static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t 
                    lp.count == xi.count && lp.epoch == plan->lists_epoch))
         return ECT_E_INVALID;
     const int64_t rows = query_rows(xi, p.num_images);
-    if (rows == 0) return ECT_OK;
+    if (rows == 0) {
+        // a sum over no rows: d/ds is 0 (a fill kernel, so the call can be captured)
+        if (backward && grad_s) return from_hip(launch_fill_u32((uint32_t*)grad_s, 2, 0u, stream));
+        return ECT_OK;
+    }
     char* w = (char*)ws;
     const int NL = num_lists(p.ndim);
     uint32_t* err = (uint32_t*)(p.ws + p.lay.err);
@@ -535,6 +564,15 @@ static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t 
     a.partials = (double*)(w + L.partials);
     a.err = err;
     // s = 0: every requested output is the constant-kernel limit sum D <xi, x>
+    if (!backward && combo) {
+        // the shared-set ECT workgroups run in the launch of the hybrid work
+        // items; then the ECT chunk sums and the hybrid reduction
+        const int64_t ect_blocks = combo_groups * p.num_images * combo->chunks;
+        e = launch_ect_hybrid(p.ndim, mask, precision, a, *combo, L.grid, ect_blocks, combo_groups, stream);
+        if (e == hipSuccess) e = launch_ect_chunk_sum(*combo, ect_blocks, combo_groups, stream);
+        if (e == hipSuccess) e = launch_hybrid(p.ndim, mask, precision, false, a, 0, L.tiles, stream);
+        return from_hip(e);
+    }
     if (!backward)
         return from_hip(launch_hybrid(p.ndim, s == 0.0 ? kHybridLinear : mask, precision, false, a, L.grid, L.tiles,
                                       stream));
@@ -563,6 +601,48 @@ ect_status hybrid_eval_multi(ect_plan plan, uint32_t kernel_mask, double s, int3
                              void* ws, size_t* ws_bytes, hipStream_t stream) {
     return hybrid_common(plan, kernel_mask, s, precision, xi, out_fourier, out_laplace, out_bessel,
                          log_scale_laplace, nullptr, nullptr, nullptr, nullptr, ws, ws_bytes, stream, false);
+}
+
+ect_status ect_hybrid_eval_multi(ect_plan plan, ect_query_set dirs, const double* thresholds, int32_t M,
+                                 int32_t thresholds_per_image, int32_t* ect_out, uint32_t kernel_mask, double s,
+                                 int32_t precision, ect_query_set xi, double* out_fourier, double* out_laplace,
+                                 double* out_bessel, double* log_scale_laplace, void* ws, size_t* ws_bytes,
+                                 hipStream_t stream) {
+    if (!plan || !ws_bytes) return ECT_E_INVALID;
+    const Plan& p = *plan;
+    ThresholdSetup S;
+    ect_status st = threshold_setup(p, dirs, thresholds, M, ect_out, false, &S);
+    if (st != ECT_OK) return st;
+    // the hybrid part (its validation and size) at the start of the workspace,
+    // so that a backward call given the same workspace can reuse its buckets
+    size_t hyb = 0;
+    st = hybrid_common(plan, kernel_mask, s, precision, xi, out_fourier, out_laplace, out_bessel, log_scale_laplace,
+                       nullptr, nullptr, nullptr, nullptr, nullptr, &hyb, stream, false);
+    if (st != ECT_OK) return st;
+    const size_t ect_off = align_up(hyb, kAlign);
+    const size_t total = ect_off + S.L.total;
+    if (!ws) {
+        *ws_bytes = total;
+        return ECT_OK;
+    }
+    if (*ws_bytes < total) return ECT_E_NOMEM;
+    char* w = (char*)ws;
+    // one launch for a shared direction set whose thresholds and histograms
+    // fit kComboEctLds bytes of LDS (every workgroup of the launch reserves
+    // them, the hybrid ones included, so more would cost them occupancy)
+    const size_t ect_lds = (sizeof(double) + sizeof(int32_t) * (size_t)S.td) * (size_t)M;
+    const bool one_launch = S.direct && S.td <= kComboEctDirs && ect_lds <= kComboEctLds && s != 0.0 &&
+                            query_rows(dirs, p.num_images) > 0 && query_rows(xi, p.num_images) > 0;
+    if (!one_launch) {
+        size_t eb = S.L.total;
+        st = threshold_eval(plan, dirs, thresholds, M, thresholds_per_image, ect_out, w + ect_off, &eb, stream, false);
+        if (st != ECT_OK) return st;
+        return hybrid_common(plan, kernel_mask, s, precision, xi, out_fourier, out_laplace, out_bessel,
+                             log_scale_laplace, nullptr, nullptr, nullptr, nullptr, ws, &hyb, stream, false);
+    }
+    const EctArgs ea = threshold_args(p, dirs, thresholds, M, thresholds_per_image, ect_out, w + ect_off, S);
+    return hybrid_common(plan, kernel_mask, s, precision, xi, out_fourier, out_laplace, out_bessel, log_scale_laplace,
+                         nullptr, nullptr, nullptr, nullptr, ws, &hyb, stream, false, false, &ea, S.direct_groups);
 }
 
 ect_status hybrid_eval_backward(ect_plan plan, int32_t kernel, double s, int32_t precision, ect_query_set xi,

@@ -27,6 +27,8 @@ template <int N> using QRecT = typename QRecSel<N>::type;
 inline size_t qrec_bytes(int ndim) { return ndim == 4 ? sizeof(QRec4) : sizeof(QRec); }
 constexpr int kEctThreads = 256;      // ECT workgroup: points stream across its lanes
 constexpr int kEctMaxDirs = 8;        // directions per ECT workgroup
+constexpr int kComboEctDirs = 2;      // at most this many in the combined ECT + hybrid launch
+constexpr size_t kComboEctLds = 4096; // and at most this much dynamic LDS (thresholds + histograms)
 constexpr int kEctMaxThresholds = 4096;
 constexpr int kHybridThreads = 256;  // four waves share one staged chunk of points
 constexpr int kHybridSplit = 4;      // the waves split the chunk's points between them ...
@@ -126,5 +128,13 @@ hipError_t launch_grad_reduce(int ndim, const double* part, int num_images, int6
                               double* grad_xi, const double* gs_part, int64_t rows, double* grad_s,
                               hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream);
+
+// The shared-set ECT (ect_blocks = groups * chunks direct workgroups) and a
+// forward hybrid pass (grid work items) in one launch; the chunk sums of the
+// ECT (e.chunks > 1) and the hybrid reduction are launched separately.
+hipError_t launch_ect_hybrid(int ndim, unsigned mask, int precision, const HybridArgs& h, const EctArgs& e,
+                             int64_t grid, int64_t ect_blocks, int64_t ect_groups, hipStream_t stream);
+// ect_chunk_sum_kernel after a chunked shared-set ECT of `grid` workgroups.
+hipError_t launch_ect_chunk_sum(const EctArgs& e, int64_t grid, int64_t groups, hipStream_t stream);
 
 }  // namespace ect

@@ -24,6 +24,7 @@
 // which a second kernel adds in chunk order, so results are bitwise
 // reproducible (a kernel boundary is the cheap synchronisation point between
 // the chip's non-coherent L2 slices).
+#include "ect_body.h"
 #include "eval_internal.h"
 #include "ji0_coeffs.h"
 
@@ -316,14 +317,13 @@ __device__ __forceinline__ int64_t partial_index(int64_t item, int slot, int q) 
 // partial sums, which hybrid_reduce adds in chunk order after the kernel; a
 // single-chunk tile writes its outputs here.
 template <int N, int MASK, int PREC, bool BWD>
-__global__ void __launch_bounds__(kHybridThreads) hybrid_kernel(HybridArgs a) {
+__device__ __forceinline__ void hybrid_block(const HybridArgs& a, int64_t item) {
     constexpr int P = 1 << (N - 1);
     __shared__ PointT<N> s_pts[kHybridStage];
     __shared__ double s_acc[kHybridSplit - 1][kAccSlots][kHybridTile];
     const int tid = threadIdx.x;
     const int lane = tid & (kHybridTile - 1);
     const int wave = tid / kHybridTile;
-    const int64_t item = blockIdx.x;
     if (item >= a.params[0]) return;
     const int64_t C = a.params[2];
     const int64_t e = find_entry(a.item_off, (int64_t)a.num_images * P, item);
@@ -375,6 +375,29 @@ __global__ void __launch_bounds__(kHybridThreads) hybrid_kernel(HybridArgs a) {
         return;
     }
     if (active) finalize<N, MASK, PREC, BWD>(a, q, row, acc);
+}
+
+template <int N, int MASK, int PREC, bool BWD>
+__global__ void __launch_bounds__(kHybridThreads) hybrid_kernel(HybridArgs a) {
+    hybrid_block<N, MASK, PREC, BWD>(a, blockIdx.x);
+}
+
+// The shared-set ECT and a forward hybrid pass in one launch: the first
+// ect_blocks workgroups evaluate the ECT (ect_direct_block), the others are the
+// hybrid work items.  The two read different lists and write different
+// outputs; in one launch the short ECT workgroups run beside the long hybrid
+// ones instead of before them.
+static_assert(kEctThreads == kHybridThreads, "the combined launch runs both bodies with one workgroup size");
+
+template <int N, int MASK, int PREC>
+__global__ void __launch_bounds__(kHybridThreads) ect_hybrid_kernel(HybridArgs h, EctArgs e, int64_t ect_blocks,
+                                                                    int64_t ect_groups) {
+    const int64_t b = blockIdx.x;
+    if (b < ect_blocks) {
+        ect_direct_block<N, false, kComboEctDirs>(e, ect_groups, b);
+        return;
+    }
+    hybrid_block<N, MASK, PREC, false>(h, b - ect_blocks);
 }
 
 // One workgroup of four waves per query tile: add the partial sums of a
@@ -565,6 +588,49 @@ hipError_t launch_grad_reduce(int ndim, const double* part, int num_images, int6
         hipLaunchKernelGGL(grad_reduce_kernel<4>, dim3(blocks), dim3(256), 0, stream, part, num_images, count,
                            shared ? 1 : 0, grad_xi, gs_part, rows, grad_s);
     return hipGetLastError();
+}
+
+namespace {
+
+template <int N, int MASK>
+hipError_t launch_ect_hybrid_mask(int precision, const HybridArgs& h0, const EctArgs& e, int64_t grid,
+                                  int64_t ect_blocks, int64_t ect_groups, size_t shmem, hipStream_t stream) {
+    HybridArgs h = h0;
+    for (int k = 0; k < kJi0SmallCoeffs; ++k) h.ji0c[k] = JI0_F32_SMALL[k];
+    const dim3 g((unsigned)(grid + ect_blocks)), blk(kHybridThreads);
+    if (precision == ECT_FP32)
+        hipLaunchKernelGGL((ect_hybrid_kernel<N, MASK, ECT_FP32>), g, blk, shmem, stream, h, e, ect_blocks, ect_groups);
+    else
+        hipLaunchKernelGGL((ect_hybrid_kernel<N, MASK, ECT_FP64>), g, blk, shmem, stream, h, e, ect_blocks, ect_groups);
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_ect_hybrid_n(unsigned mask, int precision, const HybridArgs& h, const EctArgs& e, int64_t grid,
+                               int64_t ect_blocks, int64_t ect_groups, size_t shmem, hipStream_t stream) {
+    switch (mask) {
+        case 1: return launch_ect_hybrid_mask<N, 1>(precision, h, e, grid, ect_blocks, ect_groups, shmem, stream);
+        case 2: return launch_ect_hybrid_mask<N, 2>(precision, h, e, grid, ect_blocks, ect_groups, shmem, stream);
+        case 3: return launch_ect_hybrid_mask<N, 3>(precision, h, e, grid, ect_blocks, ect_groups, shmem, stream);
+        case 4: return launch_ect_hybrid_mask<N, 4>(precision, h, e, grid, ect_blocks, ect_groups, shmem, stream);
+        case 5: return launch_ect_hybrid_mask<N, 5>(precision, h, e, grid, ect_blocks, ect_groups, shmem, stream);
+        case 6: return launch_ect_hybrid_mask<N, 6>(precision, h, e, grid, ect_blocks, ect_groups, shmem, stream);
+        default: return launch_ect_hybrid_mask<N, 7>(precision, h, e, grid, ect_blocks, ect_groups, shmem, stream);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_ect_hybrid(int ndim, unsigned mask, int precision, const HybridArgs& h, const EctArgs& e,
+                             int64_t grid, int64_t ect_blocks, int64_t ect_groups, hipStream_t stream) {
+    const size_t shmem = sizeof(double) * e.M + sizeof(int32_t) * e.dirs_per_group * e.M;
+    hipError_t err = stage_mark(ECT_STAGE_HYBRID, false, stream);
+    if (err != hipSuccess) return err;
+    if (ndim == 2) err = launch_ect_hybrid_n<2>(mask, precision, h, e, grid, ect_blocks, ect_groups, shmem, stream);
+    else if (ndim == 3) err = launch_ect_hybrid_n<3>(mask, precision, h, e, grid, ect_blocks, ect_groups, shmem, stream);
+    else err = launch_ect_hybrid_n<4>(mask, precision, h, e, grid, ect_blocks, ect_groups, shmem, stream);
+    if (err != hipSuccess) return err;
+    return stage_mark(ECT_STAGE_HYBRID, true, stream);
 }
 
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t stream) {

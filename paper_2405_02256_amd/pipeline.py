@@ -9,11 +9,15 @@ optionally, one backward pass -- without allocating, copying or
 synchronising.  ``capture()`` records that sequence once into a HIP graph
 (through torch.cuda.CUDAGraph) so that a replay costs one launch.
 
-The ECT and the hybrid transforms only read the precomputed lists, so with
-``concurrent=True`` the ECT branch runs on a side stream (its own workspace)
-between an event after the precompute and a join before the step ends; its
-small, latency-bound kernels then overlap the hybrid chain instead of
-adding to it.  In a captured graph the fork and join become graph edges.
+The ECT and the hybrid transforms only read the precomputed lists.  By
+default (``combined=True``) the step evaluates both with one call
+(ect_hybrid_eval_multi), which for a shared direction set puts the ECT
+workgroups into the launch of the fused hybrid pass: the short, latency-bound
+ECT work then fills compute units beside the long hybrid work items instead of
+running before them.  With ``concurrent=True`` the ECT branch instead runs on
+a side stream (its own workspace) between an event after the precompute and a
+join before the step ends; in a captured graph the fork and join become graph
+edges.
 """
 from __future__ import annotations
 
@@ -27,7 +31,7 @@ class Step:
                  s: float = 1.0, precision: str = "fp32", ect_offsets=None, hybrid_offsets=None,
                  backward_kernel: str | None = None, grad_out: torch.Tensor | None = None,
                  log_scale_laplace: bool = False, rerun_precompute: bool = True, fused: bool = True,
-                 concurrent: bool = False, reuse_prepared: bool = True):
+                 concurrent: bool = False, reuse_prepared: bool = True, combined: bool = True):
         self.plan = plan
         self.reuse_prepared = reuse_prepared
         dev = plan.device
@@ -63,6 +67,8 @@ class Step:
             self.grad_s = torch.empty((), dtype=torch.float64, device=dev)
         self.graph = None
         self.concurrent = concurrent and self.ect_q is not None and self.hy_q is not None
+        self.combined = (combined and not self.concurrent and self.ect_q is not None and self.hy_q is not None
+                         and fused)
         if self.concurrent:
             self.side = torch.cuda.Stream(device=dev)
             self._fork = torch.cuda.Event()
@@ -73,25 +79,14 @@ class Step:
         main = stream if stream is not None else torch.cuda.current_stream()
         if self.rerun_precompute:
             p.rerun(main)
-        if self.ect_q is not None:
-            if self.concurrent:
-                self._fork.record(main)
-                self.side.wait_event(self._fork)
-                p.ect(self.ect_q, self.ect_thr, out=self.ect_out, stream=self.side, slot="ect")
-                self._join.record(self.side)
-            else:
-                p.ect(self.ect_q, self.ect_thr, out=self.ect_out, stream=main)
-        stream = main
-        if self.fused and len(self.kernels) > 1:
-            p.hybrid_multi(self.hy_q, self.kernels, self.s, self.precision, outs=self.hy_out,
-                           log_scale_out=self.hy_ls.get("laplace"), stream=stream)
+        if self.combined:
+            p.ect_hybrid_multi(self.ect_q, self.ect_thr, self.hy_q, self.kernels, self.s, self.precision,
+                               ect_out=self.ect_out, outs=self.hy_out, log_scale_out=self.hy_ls.get("laplace"),
+                               stream=main)
         else:
-            for k in self.kernels:
-                if k in self.hy_ls:
-                    p.hybrid(self.hy_q, k, self.s, self.precision, out=self.hy_out[k],
-                             log_scale_out=self.hy_ls[k], stream=stream)
-                else:
-                    p.hybrid(self.hy_q, k, self.s, self.precision, out=self.hy_out[k], stream=stream)
+            self._ect(main)
+            self._hybrid(main)
+        stream = main
         if self.backward_kernel is not None:
             # the forward calls just bucketed this query set into the same workspace
             p.hybrid_backward(self.hy_q, self.hy_out[self.backward_kernel], self.grad_out, self.backward_kernel,
@@ -99,6 +94,31 @@ class Step:
                               reuse_prepared=self.reuse_prepared)
         if self.concurrent:
             main.wait_event(self._join)
+
+    def _ect(self, main) -> None:
+        p = self.plan
+        if self.ect_q is None:
+            return
+        if self.concurrent:
+            self._fork.record(main)
+            self.side.wait_event(self._fork)
+            p.ect(self.ect_q, self.ect_thr, out=self.ect_out, stream=self.side, slot="ect")
+            self._join.record(self.side)
+        else:
+            p.ect(self.ect_q, self.ect_thr, out=self.ect_out, stream=main)
+
+    def _hybrid(self, stream) -> None:
+        p = self.plan
+        if self.fused and len(self.kernels) > 1:
+            p.hybrid_multi(self.hy_q, self.kernels, self.s, self.precision, outs=self.hy_out,
+                           log_scale_out=self.hy_ls.get("laplace"), stream=stream)
+            return
+        for k in self.kernels:
+            if k in self.hy_ls:
+                p.hybrid(self.hy_q, k, self.s, self.precision, out=self.hy_out[k], log_scale_out=self.hy_ls[k],
+                         stream=stream)
+            else:
+                p.hybrid(self.hy_q, k, self.s, self.precision, out=self.hy_out[k], stream=stream)
 
     def autotune(self, cache=None, use_cache: bool = True, reps: int = 10):
         """Pick the plan's schedule knobs for this step's queries (before capture())."""

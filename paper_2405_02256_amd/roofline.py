@@ -62,6 +62,14 @@ def alu_roofline(kind: str, n: int, pairs: float, seconds: float, small_fraction
             "frac": achieved / VALU_PEAK_TFLOPS}
 
 
+def alu_roofline_parts(parts, seconds: float) -> dict:
+    """One launch doing several kinds of work: parts = [(kind, n, pairs, small_fraction), ...]."""
+    flop = sum(2.0 * slots_per_pair(k, n, sf) * pairs for k, n, pairs, sf in parts)
+    achieved = flop / seconds / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / VALU_PEAK_TFLOPS}
+
+
 def hbm_roofline(nbytes: float, seconds: float) -> dict:
     achieved = nbytes / seconds / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
