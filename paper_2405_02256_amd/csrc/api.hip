@@ -359,8 +359,8 @@ static ect_status threshold_eval(ect_plan plan, ect_query_set dirs, const double
     if (query_rows(dirs, p.num_images) == 0) return ECT_OK;
     char* w = (char*)ws;
     hipError_t e = hipSuccess;
+    if (plan->last_prep.ws == ws) plan->last_prep.valid = false;   // buckets or chunk sums overwrite it
     if (!S.direct) {
-        if (plan->last_prep.ws == ws) plan->last_prep.valid = false;
         e = launch_prepare(p.ndim, dirs, p.num_images, false, (uint32_t*)(p.ws + p.lay.err), (void*)(w + S.L.recs),
                            (int32_t*)(w + S.L.bcnt), (const int64_t*)(p.ws + p.lay.list_off), 0, num_lists(p.ndim),
                            S.td, 0, 0, (int64_t*)(w + S.L.item_off), (int64_t*)(w + S.L.tile_off),
@@ -418,6 +418,7 @@ ect_status ect_exact_layout(ect_plan plan, ect_query_set dirs, int32_t kind, int
     }
     if (*ws_bytes < total) return ECT_E_NOMEM;
     if ((uintptr_t)ws % kAlign) return ECT_E_INVALID;
+    if (plan->last_prep.ws == ws) plan->last_prep.valid = false;
     ExactArgs a = exact_args(p, dirs, kind);
     a.row_off_out = row_off;
     char* w = (char*)ws;
@@ -449,6 +450,7 @@ ect_status ect_exact(ect_plan plan, ect_query_set dirs, int32_t kind, const int6
     }
     if (*ws_bytes < o) return ECT_E_NOMEM;
     if ((uintptr_t)ws % kAlign) return ECT_E_INVALID;
+    if (plan->last_prep.ws == ws) plan->last_prep.valid = false;
     if (rows == 0) return ECT_OK;
     char* w = (char*)ws;
     ExactArgs a = exact_args(p, dirs, kind);

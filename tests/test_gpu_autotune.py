@@ -188,4 +188,12 @@ def test_backward_reuses_forward_buckets(api, small):
     plan.hybrid(q, "fourier", 1.0, "fp32", slot="other")
     with pytest.raises(N.EctError):
         plan.hybrid_backward(q, y, g, "fourier", 1.0, "fp32", reuse_prepared=True)
+    # any other call that writes the same workspace ends the reuse
+    for other_call in (lambda: plan.ect(T(dirs), T(thr)), lambda: plan.exact(T(dirs), "ect"),
+                       lambda: plan.exact(T(dirs), "radon")):
+        plan.hybrid(q, "fourier", 1.0, "fp32")
+        plan.hybrid_backward(q, y, g, "fourier", 1.0, "fp32", reuse_prepared=True)
+        other_call()
+        with pytest.raises(N.EctError):
+            plan.hybrid_backward(q, y, g, "fourier", 1.0, "fp32", reuse_prepared=True)
     torch.cuda.synchronize()
