@@ -9,7 +9,11 @@ chunked partial sums):
   fill the 256 compute units but cost more partial sums, long ones the reverse;
 * the number of directions one ECT workgroup evaluates per streamed point and,
   for shared direction sets, the number of parts each list is split into so
-  that several workgroups share one group of directions.
+  that several workgroups share one group of directions.  When the ECT runs
+  inside the hybrid launch (ect_hybrid_eval_multi) these are swept again on
+  that combined call: there the ECT work is hidden beside the hybrid work
+  items and list parts only add a chunk-sum launch, so the best setting
+  differs from the one for a separate ECT launch.
 
 The tuner times each candidate on the device with events around a few
 repetitions of the real calls, keeps the fastest and stores it in a JSON cache
@@ -139,7 +143,8 @@ def time_call(fn, reps: int = 10, warmup: int = 2, trials: int = 3) -> float:
 
 def tune(plan, ect_dirs=None, ect_thresholds=None, hybrid_xi=None, kernels=("fourier",), s=1.0,
          precision="fp32", ect_offsets=None, hybrid_offsets=None, backward_kernel=None, grad_out=None,
-         cache: Cache | None = None, use_cache=True, reps=10, timer=None, dev_key: str | None = None) -> Tuning:
+         cache: Cache | None = None, use_cache=True, reps=10, timer=None, dev_key: str | None = None,
+         combined: bool = False) -> Tuning:
     """Sweep the knobs for this plan's ECT and hybrid calls, apply the fastest
     to the plan and return it (from the cache when the workload was seen)."""
     import torch
@@ -151,7 +156,10 @@ def tune(plan, ect_dirs=None, ect_thresholds=None, hybrid_xi=None, kernels=("fou
     e_rows = eq.rows(plan.num_images) if eq is not None else 0
     h_rows = hq.rows(plan.num_images) if hq is not None else 0
     M = int(ect_thresholds.shape[-1]) if ect_thresholds is not None else 0
+    combined = bool(combined and e_rows > 0 and h_rows > 0)
     sig = signature(plan, e_rows, M, h_rows, tuple(kernels) if hq is not None else (), precision, backward_kernel)
+    if combined:
+        sig += "|one-launch"
     dev = dev_key or device_key()
     if use_cache:
         hit = cache.get(dev, sig)
@@ -198,6 +206,24 @@ def tune(plan, ect_dirs=None, ect_thresholds=None, hybrid_xi=None, kernels=("fou
             hy_t[items] = timer(run, reps)
         best.hybrid_target_items = pick(hy_t)
         timings["hybrid"] = {str(k): v for k, v in hy_t.items()}
+    if combined:
+        co_t = {}
+        for td, ch in ECT_CANDIDATES:
+            plan.set_tuning(0, best.hybrid_target_items, td, ch)
+            eo, ho = plan.ect_hybrid_multi(eq, ect_thresholds, hq, kernels, s, precision)
+            fwd = ho.get(backward_kernel) if backward_kernel else None
+            if fwd is not None and grad_out is None:
+                grad_out = torch.ones_like(fwd)
+            gxi = torch.empty((hq.vecs.shape[0], plan.ndim), dtype=torch.float64, device=plan.device)
+            gs = torch.empty((), dtype=torch.float64, device=plan.device)
+
+            def run(eo=eo, ho=ho, fwd=fwd):
+                plan.ect_hybrid_multi(eq, ect_thresholds, hq, kernels, s, precision, ect_out=eo, outs=ho)
+                if fwd is not None:
+                    plan.hybrid_backward(hq, fwd, grad_out, backward_kernel, s, precision, grad_xi=gxi, grad_s=gs)
+            co_t[(td, ch)] = timer(run, reps)
+        best.ect_dirs_per_group, best.ect_chunks = pick(co_t)
+        timings["ect_hybrid"] = {f"{k[0]}/{k[1]}": v for k, v in co_t.items()}
     best.timings = timings
     plan.set_tuning(*best.as_args())
     if use_cache:
