@@ -353,7 +353,17 @@ __device__ __forceinline__ void hybrid_block(const HybridArgs& a, int64_t item) 
         __syncthreads();
         // wave-uniform loop bounds (scalar counter)
         const int k0 = __builtin_amdgcn_readfirstlane(wave);
-        for (int k = k0; k < cnt; k += kHybridSplit) accumulate_point<N, MASK, PREC, BWD>(s_pts[k], q, acc, a.ji0c);
+        if constexpr (BWD && PREC == ECT_FP32) {
+            // one kernel's short chain per point: two points per iteration give
+            // the wave independent work between the dependent steps (the sums
+            // still take the points in order)
+#pragma unroll 2
+            for (int k = k0; k < cnt; k += kHybridSplit)
+                accumulate_point<N, MASK, PREC, BWD>(s_pts[k], q, acc, a.ji0c);
+        } else {
+            for (int k = k0; k < cnt; k += kHybridSplit)
+                accumulate_point<N, MASK, PREC, BWD>(s_pts[k], q, acc, a.ji0c);
+        }
     }
     if (wave > 0) {
 #pragma unroll
