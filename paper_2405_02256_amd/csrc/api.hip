@@ -273,6 +273,7 @@ struct ThresholdSetup {
     int64_t chunks;
     bool direct;
     int64_t direct_groups;
+    int threads;
     EvalLayout L;
 };
 
@@ -298,6 +299,8 @@ static ect_status threshold_setup(const Plan& p, const ect_query_set& dirs, cons
     // of directions (about two per compute unit, at least 4096 points each:
     // below that a workgroup's fixed cost outweighs streaming its part)
     S->td = td;
+    // short lists: one-wave workgroups (more blocks in flight per compute unit)
+    S->threads = mean_list(p, 0, num_classical(p.ndim)) <= kEctSmallList ? 64 : kEctThreads;
     S->direct = dirs.offsets == nullptr;
     S->chunks = 1;
     S->direct_groups = 0;
@@ -340,6 +343,7 @@ static EctArgs threshold_args(const Plan& p, const ect_query_set& dirs, const do
     a.dirs_per_group = S.td;
     a.chunks = S.chunks;
     a.part = S.chunks > 1 ? (int32_t*)w : nullptr;
+    a.threads = S.threads;
     return a;
 }
 

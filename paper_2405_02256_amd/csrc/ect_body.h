@@ -2,7 +2,10 @@
 // threshold kernels (ect_eval.hip) and the combined ECT + hybrid launch
 // (hybrid.hip) share: threshold staging, list streaming into LDS histograms,
 // the prefix-sum write-out, and the shared-set direct evaluation of one
-// workgroup's block.
+// workgroup's block.  Everything strides by the launch's workgroup size, a
+// multiple of 64 up to kEctThreads: short lists are evaluated by one-wave
+// workgroups, so that four times as many (image, directions) blocks are in
+// flight to cover their memory latency.
 #pragma once
 
 #include "eval_internal.h"
@@ -19,13 +22,14 @@ __device__ __forceinline__ int stage_thresholds(const EctArgs& a, int64_t img, d
     const int M = a.M;
     const double* thr = a.thresholds + (a.thr_per_image ? img * M : 0);
     int bad = 0;
-    for (int j = threadIdx.x; j < M; j += kEctThreads) {
+    const int nt = (int)blockDim.x;
+    for (int j = threadIdx.x; j < M; j += nt) {
         const double v = thr[j];
         s_thr[j] = v;
         if (j > 0 && !(v >= thr[j - 1])) bad = 1;
         if (!isfinite(v)) bad = 1;
     }
-    for (int j = threadIdx.x; j < hist_arrays * a.dirs_per_group * M; j += kEctThreads) s_hist[j] = 0;
+    for (int j = threadIdx.x; j < hist_arrays * a.dirs_per_group * M; j += nt) s_hist[j] = 0;
     return __syncthreads_or(bad);
 }
 
@@ -46,16 +50,17 @@ __device__ __forceinline__ void accumulate_list(const PointT<N>* __restrict__ pt
     // U points per thread are loaded before any is processed, so that their
     // memory latencies overlap
     constexpr int U = 4;
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += (int64_t)kEctThreads * U) {
+    const int64_t nt = blockDim.x;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += nt * U) {
         PointT<N> pt[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t pp = p + (int64_t)u * kEctThreads;
+            const int64_t pp = p + (int64_t)u * nt;
             if (pp < p1) pt[u] = pts[pp];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (p + (int64_t)u * kEctThreads >= p1) break;
+            if (p + (int64_t)u * nt >= p1) break;
             const int32_t val = sign * (int32_t)pt[u].val;
 #pragma unroll
             for (int dd = 0; dd < TD; ++dd) {
@@ -86,7 +91,7 @@ __device__ __forceinline__ void write_rows(const EctArgs& a, int nd, const int64
                                            const int32_t* s_hist, const int32_t* s_point = nullptr) {
     const int M = a.M;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    constexpr int W = kEctThreads / 64;
+    const int W = (int)blockDim.x / 64;
     for (int dd = wave; dd < nd; dd += W) {
         int32_t* out = a.out + s_row[dd] * M;
         if (!s_valid[dd]) {
@@ -131,7 +136,7 @@ __device__ __forceinline__ void accumulate_radon(const EctArgs& a, int64_t img, 
 
 __device__ __forceinline__ void zero_rows(const EctArgs& a, int nd, const int64_t* s_row) {
     for (int dd = 0; dd < nd; ++dd)
-        for (int j = threadIdx.x; j < a.M; j += kEctThreads) a.out[s_row[dd] * a.M + j] = 0;
+        for (int j = threadIdx.x; j < a.M; j += (int)blockDim.x) a.out[s_row[dd] * a.M + j] = 0;
 }
 
 // Shared query sets: no bucketing pass.  Workgroup (image, g, c) takes rows
@@ -190,9 +195,11 @@ __device__ __forceinline__ void ect_direct_block(const EctArgs& a, int64_t group
         s_sign[tid] = sg;
     }
     // every classical list's bounds are requested now, with the directions and
-    // thresholds, instead of after the barrier
-    if (tid >= 64 && tid < 64 + (2 << N)) {
-        const int k = tid - 64, b = k & ((1 << N) - 1), hi = k >> N;
+    // thresholds, instead of after the barrier (by the second wave, or by the
+    // only one)
+    const int kl = blockDim.x > 64 ? tid - 64 : tid;
+    if (kl >= 0 && kl < (2 << N)) {
+        const int k = kl, b = k & ((1 << N) - 1), hi = k >> N;
         s_loff[hi][b] = a.list_off[(img + hi) * a.NL + b];
     }
     int32_t* s_point = s_hist + (int64_t)a.dirs_per_group * M;   // Radon point values
@@ -241,7 +248,7 @@ __device__ __forceinline__ void ect_direct_block(const EctArgs& a, int64_t group
     }
     // chunk histograms (zeros for invalid directions or bad thresholds)
     int32_t* part = a.part + (rest * chunks + c) * (int64_t)TDg * M;
-    for (int j = tid; j < nd * M; j += kEctThreads) part[j] = s_hist[j];
+    for (int j = tid; j < nd * M; j += (int)blockDim.x) part[j] = s_hist[j];
 }
 
 }  // namespace

@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(64) ect_chunk_sum_kernel(EctArgs a, int64_t gr
 template <int N, bool RADON>
 hipError_t launch_ect_typed(const EctArgs& a, int64_t grid, int64_t direct_groups, size_t shmem, hipStream_t stream) {
     if (direct_groups > 0) {
-        hipLaunchKernelGGL((ect_direct_kernel<N, RADON>), dim3((unsigned)grid), dim3(kEctThreads), shmem, stream, a,
+        hipLaunchKernelGGL((ect_direct_kernel<N, RADON>), dim3((unsigned)grid), dim3(a.threads), shmem, stream, a,
                            direct_groups);
         if (a.chunks > 1) {
             hipError_t e = hipGetLastError();
@@ -156,7 +156,7 @@ hipError_t launch_ect_typed(const EctArgs& a, int64_t grid, int64_t direct_group
             hipLaunchKernelGGL(ect_chunk_sum_kernel, dim3((unsigned)rows), dim3(64), 0, stream, a, direct_groups);
         }
     } else {
-        hipLaunchKernelGGL((ect_kernel<N, RADON>), dim3((unsigned)grid), dim3(kEctThreads), shmem, stream, a);
+        hipLaunchKernelGGL((ect_kernel<N, RADON>), dim3((unsigned)grid), dim3(a.threads), shmem, stream, a);
     }
     return hipGetLastError();
 }
@@ -173,6 +173,7 @@ hipError_t launch_ect_chunk_sum(const EctArgs& a, int64_t grid, int64_t groups, 
 hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, int64_t direct_groups, bool radon,
                       hipStream_t stream) {
     if (grid <= 0) return hipSuccess;
+    if (a.threads != 64 && a.threads != kEctThreads) return hipErrorInvalidValue;
     const size_t shmem = sizeof(double) * a.M + (radon ? 2 : 1) * sizeof(int32_t) * a.dirs_per_group * a.M;
     hipError_t e = stage_mark(ECT_STAGE_ECT, false, stream);
     if (e != hipSuccess) return e;

@@ -73,7 +73,11 @@ struct EctArgs {
     int dirs_per_group;
     int64_t chunks;           // shared sets: point chunks per direction group (1: no split)
     int32_t* part;            // shared sets with chunks > 1: per-chunk histograms
+    int threads;              // workgroup size of the threshold kernels: 64 or kEctThreads
 };
+
+// Mean classical list length up to which one-wave workgroups evaluate the ECT.
+constexpr double kEctSmallList = 2048.0;
 
 // direct_groups > 0: shared query set, num_images * direct_groups * a.chunks
 // workgroups of ect_direct_kernel (no bucketing), then, with a.chunks > 1, the

@@ -633,6 +633,10 @@ hipError_t launch_ect_hybrid_n(unsigned mask, int precision, const HybridArgs& h
 
 hipError_t launch_ect_hybrid(int ndim, unsigned mask, int precision, const HybridArgs& h, const EctArgs& e,
                              int64_t grid, int64_t ect_blocks, int64_t ect_groups, hipStream_t stream) {
+    // the ECT block keeps at most kComboEctDirs directions; the constant-kernel
+    // limit has no combined instantiation (the caller makes two launches)
+    if (e.dirs_per_group < 1 || e.dirs_per_group > kComboEctDirs || mask < 1 || mask > 7 || e.chunks < 1)
+        return hipErrorInvalidValue;
     const size_t shmem = sizeof(double) * e.M + sizeof(int32_t) * e.dirs_per_group * e.M;
     hipError_t err = stage_mark(ECT_STAGE_HYBRID, false, stream);
     if (err != hipSuccess) return err;
