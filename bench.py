@@ -479,6 +479,20 @@ def main():
         e_idx = (ex4[..., 0] < 0) * 1 + (ex4[..., 1] < 0) * 2
         pr = np.where(e_idx >= 2, e_idx ^ 3, e_idx)
         pairs4 = float(np.take_along_axis(o4, pr, axis=1).sum())
+        # the batch's precompute alone (count / scan / write launches, library stage events), priced
+        # against HBM with the bytes it cannot avoid: every pixel read once, 32 B per list entry
+        # written, the list offsets
+        pe = [(hipevents.Event(), hipevents.Event()) for _ in range(reps)]
+        for i in range(reps):
+            N.check(N.ect_set_stage_events(N.STAGE_PRECOMPUTE, pe[i][0].handle, pe[i][1].handle), "stage events")
+            plan4.rerun()
+        torch.cuda.synchronize()
+        N.ect_set_stage_events(N.STAGE_PRECOMPUTE, None, None)
+        pre_ms = float(np.mean([a.elapsed_ms(b) for a, b in pe]))
+        px_bytes = float(sum(im.size * im.itemsize for im in w4.images))
+        entries4 = float(c4.sum() + o4.sum())
+        pre_bytes = px_bytes + 32.0 * entries4 + 8.0 * (len(imgs4) + 1) * (c4.shape[1] + o4.shape[1])
+        vertices4 = float(sum((im.shape[0] + 1) * (im.shape[1] + 1) for im in w4.images))
         batch = {"workload": "batch_4096: 4096 binary GRF images, sides U{28,64,128,256}, sigma U[2,8]; "
                              "ECT 128 dirs x 128 per-image thresholds; Euler-Laplace at 512 xi per image",
                  "batched_fp32_graph_ms": t_batched * 1e3, "per_image_fp64_loop_ms": t_loop * 1e3,
@@ -486,7 +500,10 @@ def main():
                  "hybrid_evals_per_s_batched": pairs4 / t_batched,
                  "ect_dirs_per_s_batched": len(imgs4) * len(w4.ect_dirs) / t_batched,
                  "ect_identical": bool(np.array_equal(e32, e64)),
-                 "fp32_vs_fp64_normwise": float(np.abs(y32 - y64).max() / np.abs(y64).max())}
+                 "fp32_vs_fp64_normwise": float(np.abs(y32 - y64).max() / np.abs(y64).max()),
+                 "precompute_ms": pre_ms, "precompute_vertices": vertices4, "precompute_list_entries": entries4,
+                 "precompute_hbm_roofline": roofline.hbm_roofline(pre_bytes, pre_ms * 1e-3),
+                 "precompute_vertices_per_s": vertices4 / (pre_ms * 1e-3)}
         log(f"batched {t_batched * 1e3:.3f} ms vs per-image FP64 loop {t_loop * 1e3:.1f} ms")
 
     res = {

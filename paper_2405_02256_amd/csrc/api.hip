@@ -202,6 +202,15 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
     // depend on the device.
     L.status = o; o = align_up(o + sizeof(uint64_t) * (2 * tiles + (tiles + 63) / 64 + 1) * NL, kAlign);
     L.points = o; o = align_up(o + point_bytes(n) * verts * NL, kAlign);
+    // plans beyond the single pass's largest grid (64 groups of 64 tiles, on
+    // any device) run three passes; with 8- or 16-bit pixels the count pass
+    // leaves its entries packed in per-tile slots, so the last pass only
+    // places them instead of classifying every vertex again
+    const int64_t packed_bytes = (int64_t)sizeof(uint32_t) * tiles * NL * tile_verts(n);
+    L.packed = o;
+    L.packed_bytes = (tiles > 64 * 64 && batch->dtype != ECT_I32 && packed_bytes <= kPackedMaxBytes)
+                         ? (size_t)packed_bytes : 0;
+    o = align_up(o + L.packed_bytes, kAlign);
     L.total = o;
     L.num_tiles = tiles;
     L.capacity = verts;

@@ -10,6 +10,12 @@ namespace ect {
 
 constexpr int kMaxDim = 4;
 constexpr int kPrecomputeThreads = 256;              // threads per precompute workgroup
+// Packed list entry of a three-pass plan: critical value << kPackShift | vertex
+// index in its tile (< 1024).  8- and 16-bit pixels bound |value| by
+// 2 * 2^n * 32767 < 2^21, so the value keeps its sign in the upper 22 bits.
+constexpr int kPackShift = 10;
+constexpr uint32_t kPackLocalMask = (1u << kPackShift) - 1u;
+constexpr int64_t kPackedMaxBytes = (int64_t)8 << 30;   // larger plans classify again instead
 // Vertices per thread per precompute tile: four for n <= 3 (their loads in
 // flight together); one for n = 4, whose 81-cell stars and 24 lists fill the
 // registers on their own.
@@ -68,6 +74,8 @@ struct PlanLayout {
     size_t list_off;        // int64[(num_images + 1) * NL]: start of image i in list l
     size_t status;          // uint64 ordered-compaction status words: tiles, group totals, carries (x NL)
     size_t points;          // PointT<n>[NL * capacity]
+    size_t packed;          // uint32[num_tiles * NL * tile_verts]: three-pass plans of 8/16-bit pixels
+    size_t packed_bytes;    // 0: no packed region (the write pass classifies again)
     size_t total;
     int64_t num_tiles;
     int64_t capacity;       // entries per list region (= total vertices)

@@ -495,16 +495,118 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
 template <int N, int CONS, typename T>
 __global__ void __launch_bounds__(kPrecomputeThreads)
 tile_count_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
-                  const int64_t* __restrict__ tile_start, int32_t num_images, int32_t* __restrict__ counts) {
+                  const int64_t* __restrict__ tile_start, int32_t num_images, int32_t* __restrict__ counts,
+                  uint32_t* __restrict__ packed) {
     constexpr int NL = TileValues<N>::NL;
-    __shared__ int32_t s_cnt[TileValues<N>::J][kPrecomputeThreads / 64][NL];
+    constexpr int J = TileValues<N>::J;
+    __shared__ int32_t s_cnt[J][kPrecomputeThreads / 64][NL];
     const int64_t tile = blockIdx.x;
     TileValues<N> tv;
     tile_values<N, CONS, T>(pixels, descs, tile_start, num_images, tile, tv, s_cnt);
     __syncthreads();
-    if ((threadIdx.x >> 6) == 0) {
-        const uint64_t agg = tile_offsets<NL, TileValues<N>::J>(s_cnt);
-        if (threadIdx.x < NL) counts[tile * NL + threadIdx.x] = (int32_t)agg;
+    constexpr int W = kPrecomputeThreads / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (wave == 0 && lane < NL) {
+        int32_t tot = 0;
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+#pragma unroll
+            for (int w = 0; w < W; ++w) tot += s_cnt[j][w][lane];
+        counts[tile * NL + lane] = tot;
+    }
+    if (!packed) return;
+    // the tile's entries in vertex order inside its own slots, packed as
+    // value << kPackShift | vertex index in the tile (tile_copy_kernel
+    // places them once the offsets are known).  Each wave finds where its
+    // rounds start itself: lane j * NL + l sums list l's counts of the rounds
+    // and waves before (j, wave).
+    static_assert(J * NL <= 64, "one lane per (round, list)");
+    int32_t start = 0;
+    if (lane < J * NL) {
+        const int jj = lane / NL, l = lane % NL;
+        for (int j = 0; j < J; ++j)
+            for (int w = 0; w < W; ++w)
+                if (j < jj || (j == jj && w < wave)) start += s_cnt[j][w][l];
+    }
+    uint32_t* __restrict__ slots = packed + tile * NL * (int64_t)tile_verts(N);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const uint32_t local = (uint32_t)(j * kPrecomputeThreads + threadIdx.x);
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const bool nz = tv.vals[j][l] != 0;
+            const uint64_t b = __ballot(nz);
+            const int32_t st = __shfl(start, j * NL + l, 64);
+            if (nz) {
+                const int pos = st + __popcll(b & ((1ull << lane) - 1ull));
+                slots[l * tile_verts(N) + pos] = ((uint32_t)tv.vals[j][l] << kPackShift) | local;
+            }
+        }
+    }
+}
+
+// Three-pass plans with packed entries: place tile t's entries (list l's
+// count from tile_count_kernel, in vertex order) at the list's prefix.  The
+// tile's counts and prefixes are read once; its entries of all lists are then
+// one flat range, one thread per entry, with the vertex coordinates decoded
+// from the index.
+template <int N>
+__global__ void __launch_bounds__(kPrecomputeThreads)
+tile_copy_kernel(const ImageDesc* __restrict__ descs, const int64_t* __restrict__ tile_start, int32_t num_images,
+                 const int32_t* __restrict__ counts, const int64_t* __restrict__ prefix,
+                 const uint32_t* __restrict__ packed, PointT<N>* __restrict__ points, int64_t capacity) {
+    constexpr int NL = TileValues<N>::NL;
+    constexpr int NX = sizeof(PointT<N>::x) / sizeof(double);
+    __shared__ int32_t s_start[NL + 1];
+    __shared__ int64_t s_base[NL];
+    const int64_t tile = blockIdx.x;
+    if (threadIdx.x < NL) {
+        s_start[threadIdx.x + 1] = counts[tile * NL + threadIdx.x];
+        s_base[threadIdx.x] = prefix[tile * NL + threadIdx.x];
+    }
+    int lo = 0, hi = num_images - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile_start[mid] <= tile) lo = mid; else hi = mid - 1;
+    }
+    const ImageDesc d = descs[lo];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_start[0] = 0;
+        for (int l = 0; l < NL; ++l) s_start[l + 1] += s_start[l];
+    }
+    __syncthreads();
+    const int total = s_start[NL];
+    const int64_t vbase = (tile - d.tile_start) * tile_verts(N);
+    const double inv0 = 1.0 / (double)d.V[0], inv1 = 1.0 / (double)d.V[1], inv2 = 1.0 / (double)d.V[2];
+    const uint32_t* __restrict__ slots = packed + tile * NL * (int64_t)tile_verts(N);
+    for (int i = threadIdx.x; i < total; i += kPrecomputeThreads) {
+        int l = 0;
+#pragma unroll
+        for (int m = 1; m < NL; ++m) l += i >= s_start[m] ? 1 : 0;
+        const int pos = i - s_start[l];
+        const uint32_t w = slots[l * tile_verts(N) + pos];
+        const uint32_t v = (uint32_t)(vbase + (w & kPackLocalMask));
+        uint32_t r0, r1 = 0, r2 = 0;
+        const uint32_t q0 = udiv(v, (uint32_t)d.V[0], inv0, &r0);
+        const uint32_t q1 = N >= 3 ? udiv(q0, (uint32_t)d.V[1], inv1, &r1) : 0u;
+        const uint32_t q2 = N >= 4 ? udiv(q1, (uint32_t)d.V[2], inv2, &r2) : 0u;
+        int k[kMaxDim] = {(int)r0, 0, 0, 0};
+        if constexpr (N == 2) {
+            k[1] = (int)q0;
+        } else if constexpr (N == 3) {
+            k[1] = (int)r1;
+            k[2] = (int)q1;
+        } else {
+            k[1] = (int)r1;
+            k[2] = (int)r2;
+            k[3] = (int)q2;
+        }
+        PointT<N> pt{};
+#pragma unroll
+        for (int a = 0; a < NX; ++a) pt.x[a] = a < N ? __fma_rn(d.spacing[a], (double)k[a], d.origin[a]) : 0.0;
+        pt.val = (double)((int32_t)w >> kPackShift);
+        points[(int64_t)l * capacity + s_base[l] + pos] = pt;
     }
 }
 
@@ -693,8 +795,10 @@ hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream) {
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
+        // packed entries (small pixel types only: their values fit the packed field)
+        uint32_t* packed = (L.packed_bytes > 0 && sizeof(T) < 4) ? (uint32_t*)(p.ws + L.packed) : nullptr;
         hipLaunchKernelGGL((tile_count_kernel<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads), 0,
-                           stream, px, desc, ts, p.num_images, counts);
+                           stream, px, desc, ts, p.num_images, counts, packed);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         constexpr int NLc = TileValues<N>::NL;
@@ -709,8 +813,12 @@ hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream) {
                            L.num_tiles, blk, ts, p.num_images, prefix, lo);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((tile_write_kernel<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads), 0,
-                           stream, px, desc, ts, p.num_images, prefix, pts, L.capacity);
+        if (packed)
+            hipLaunchKernelGGL((tile_copy_kernel<N>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads), 0,
+                               stream, desc, ts, p.num_images, counts, prefix, packed, pts, L.capacity);
+        else
+            hipLaunchKernelGGL((tile_write_kernel<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads),
+                               0, stream, px, desc, ts, p.num_images, prefix, pts, L.capacity);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
