@@ -91,8 +91,9 @@ def measure_next(plan, w, dirs, thr, n, cls_counts, ord_counts, steps):
     saved = getattr(plan, "tuning", None)
     base = saved if saved is not None else (0, 2048, 0, 0)
     best = None
-    for td in (1, 2, 4, 8):
-        plan.set_tuning(base[0], base[1], td, base[3])
+    from paper_2405_02256_amd import autotune as AT
+    for td, ch in AT.ECT_CANDIDATES:
+        plan.set_tuning(base[0], base[1], td, ch)
         ev = [(hipevents.Event(), hipevents.Event()) for _ in range(steps)]
         for a, b in ev:
             N.check(N.ect_set_stage_events(N.STAGE_ECT, a.handle, b.handle), "stage events")
@@ -101,12 +102,12 @@ def measure_next(plan, w, dirs, thr, n, cls_counts, ord_counts, steps):
         N.ect_set_stage_events(N.STAGE_ECT, None, None)
         t = float(np.mean([a.elapsed_ms(b) for a, b in ev]))
         if best is None or t < best[0]:
-            best = (t, td)
+            best = (t, td, ch)
     plan.set_tuning(*base)
-    ms, td_best = best
+    ms, td_best, ch_best = best
     roof = roofline.alu_roofline("radon", n, c_pts + o_pts, ms * 1e-3)
     out["radon_thresholds"] = {"kernel_ms": ms, "dirs_per_s": len(w.ect_dirs) / (ms * 1e-3),
-                               "points_streamed": c_pts + o_pts, "dirs_per_workgroup": td_best, "roofline": roof}
+                               "points_streamed": c_pts + o_pts, "dirs_per_workgroup": td_best, "list_parts": ch_best or "auto", "roofline": roof}
     for kind, pts in (("ect", c_pts), ("radon", c_pts + o_pts)):
         rep = plan.exact(dirs, kind)
         torch.cuda.synchronize()

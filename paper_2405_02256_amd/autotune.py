@@ -33,7 +33,7 @@ from . import _native as N
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2405_02256_amd", "tuning.json")
 # (directions per workgroup, list parts; 0 = automatic)
-ECT_CANDIDATES = ((1, 1), (2, 1), (4, 1), (8, 1), (1, 0), (2, 0), (4, 0), (8, 0))
+ECT_CANDIDATES = ((1, 1), (2, 1), (4, 1), (8, 1), (1, 0), (2, 0), (4, 0), (8, 0), (1, 2), (1, 4), (2, 2), (2, 4))
 HYBRID_ITEM_CANDIDATES = (512, 1024, 2048, 4096, 8192, 16384)
 
 

@@ -319,9 +319,9 @@ static ect_status threshold_setup(const Plan& p, const ect_query_set& dirs, cons
         const int64_t groups = (int64_t)p.num_images * S->direct_groups;
         const double avg = mean_list(p, 0, num_classical(p.ndim));
         const int64_t want = (2 * (int64_t)std::max(p.num_cus, 1) + groups - 1) / std::max<int64_t>(groups, 1);
-        S->chunks = radon ? 1 : p.tune_ect_chunks > 0 ? p.tune_ect_chunks
+        S->chunks = p.tune_ect_chunks > 0 ? p.tune_ect_chunks
                                           : std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)(avg / 4096.0)));
-        if (S->chunks > 1) S->L.total = sizeof(int32_t) * (size_t)(groups * S->chunks * td * (int64_t)M);
+        if (S->chunks > 1) S->L.total = sizeof(int32_t) * (size_t)(groups * S->chunks * td * (int64_t)M * arrays);
         S->L.grid = groups * S->chunks;
     } else {
         layout_ect(p, dirs, td, &S->L);

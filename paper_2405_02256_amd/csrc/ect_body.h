@@ -146,9 +146,9 @@ __device__ __forceinline__ void zero_rows(const EctArgs& a, int nd, const int64_
 // of that list once for the directions that have it.  Splitting the lists
 // lets many workgroups share one group of directions, so each streamed point
 // serves up to eight directions while the chip stays full.  One chunk writes
-// the ECT rows itself; several write their histograms, which
-// ect_chunk_sum_kernel adds (integers, so the order cannot matter) before the
-// prefix sum.  A non-finite direction gets a zero row and raises
+// the rows itself; several write their histograms (and, for the Radon
+// transform, their point values), which ect_chunk_sum_kernel adds (integers,
+// so the order cannot matter) before the prefix sum.  A non-finite direction gets a zero row and raises
 // ECT_DEVERR_NONFINITE, as in the bucketed path.  TD bounds dirs_per_group
 // (the caller checks it); a smaller bound keeps fewer directions in registers.
 template <int N, bool RADON, int TD = kEctMaxDirs>
@@ -246,9 +246,11 @@ __device__ __forceinline__ void ect_direct_block(const EctArgs& a, int64_t group
         else write_rows(a, nd, s_row, s_valid, s_hist, RADON ? s_point : nullptr);
         return;
     }
-    // chunk histograms (zeros for invalid directions or bad thresholds)
-    int32_t* part = a.part + (rest * chunks + c) * (int64_t)TDg * M;
-    for (int j = tid; j < nd * M; j += (int)blockDim.x) part[j] = s_hist[j];
+    // chunk histograms, and for the Radon transform the chunk's point values
+    // after them (zeros for invalid directions or bad thresholds)
+    constexpr int arrays = RADON ? 2 : 1;
+    int32_t* part = a.part + (rest * chunks + c) * (int64_t)arrays * TDg * M;
+    for (int j = tid; j < arrays * TDg * M; j += (int)blockDim.x) part[j] = s_hist[j];
 }
 
 }  // namespace

@@ -115,8 +115,9 @@ __global__ void __launch_bounds__(kEctThreads) ect_direct_kernel(EctArgs a, int6
 }
 
 // Sum of the chunk histograms of one direction (one wave per output row) and
-// the inclusive prefix over thresholds.
-__global__ void __launch_bounds__(64) ect_chunk_sum_kernel(EctArgs a, int64_t groups) {
+// the inclusive prefix over thresholds; for the Radon transform (arrays = 2)
+// plus the sum of the chunks' point values.
+__global__ void __launch_bounds__(64) ect_chunk_sum_kernel(EctArgs a, int64_t groups, int arrays) {
     const int lane = threadIdx.x;
     const int TDg = a.dirs_per_group;
     const int M = a.M;
@@ -127,19 +128,23 @@ __global__ void __launch_bounds__(64) ect_chunk_sum_kernel(EctArgs a, int64_t gr
     if (q >= a.count) return;
     const int64_t img = rest / groups;
     int32_t* out = a.out + (img * a.count + q) * M;
-    const int32_t* part = a.part + rest * chunks * (int64_t)TDg * M + dd * M;
+    const int64_t stride = (int64_t)arrays * TDg * M;   // one chunk's arrays
+    const int32_t* part = a.part + rest * chunks * stride + dd * M;
     int32_t carry = 0;
     for (int jb = 0; jb < M; jb += 64) {
         const int j = jb + lane;
-        int32_t v = 0;
+        int32_t v = 0, pv = 0;
         if (j < M)
-            for (int64_t c = 0; c < chunks; ++c) v += part[c * TDg * M + j];
+            for (int64_t c = 0; c < chunks; ++c) {
+                v += part[c * stride + j];
+                if (arrays == 2) pv += part[c * stride + (int64_t)TDg * M + j];
+            }
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
             const int32_t o = __shfl_up(v, off, 64);
             if (lane >= off) v += o;
         }
-        if (j < M) out[j] = carry + v;
+        if (j < M) out[j] = carry + v + pv;
         carry += __shfl(v, 63, 64);
     }
 }
@@ -153,7 +158,8 @@ hipError_t launch_ect_typed(const EctArgs& a, int64_t grid, int64_t direct_group
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             const int64_t rows = (grid / a.chunks) * a.dirs_per_group;
-            hipLaunchKernelGGL(ect_chunk_sum_kernel, dim3((unsigned)rows), dim3(64), 0, stream, a, direct_groups);
+            hipLaunchKernelGGL(ect_chunk_sum_kernel, dim3((unsigned)rows), dim3(64), 0, stream, a, direct_groups,
+                               RADON ? 2 : 1);
         }
     } else {
         hipLaunchKernelGGL((ect_kernel<N, RADON>), dim3((unsigned)grid), dim3(a.threads), shmem, stream, a);
@@ -166,7 +172,7 @@ hipError_t launch_ect_typed(const EctArgs& a, int64_t grid, int64_t direct_group
 hipError_t launch_ect_chunk_sum(const EctArgs& a, int64_t grid, int64_t groups, hipStream_t stream) {
     if (a.chunks <= 1 || grid <= 0) return hipSuccess;
     const int64_t rows = (grid / a.chunks) * a.dirs_per_group;
-    hipLaunchKernelGGL(ect_chunk_sum_kernel, dim3((unsigned)rows), dim3(64), 0, stream, a, groups);
+    hipLaunchKernelGGL(ect_chunk_sum_kernel, dim3((unsigned)rows), dim3(64), 0, stream, a, groups, 1);
     return hipGetLastError();
 }
 

@@ -52,6 +52,8 @@ def test_any_tuning_keeps_parity(api, small, chunk, items, td, ech):
     plan = api.Plan(T(img))
     plan.set_tuning(chunk, items, td, ech)
     assert np.array_equal(plan.ect(T(dirs), T(thr)).cpu().numpy(), O.ect(img, dirs, thr))
+    # the Radon transform splits its lists the same way (chunk histograms and point values)
+    assert np.array_equal(plan.radon(T(dirs), T(thr)).cpu().numpy(), O.radon(img, dirs, thr))
     outs = plan.hybrid_multi(T(xi), ("fourier", "laplace", "bessel"), 1.0, "fp32")
     for k in ("fourier", "laplace", "bessel"):
         y = outs[k].cpu().numpy()
