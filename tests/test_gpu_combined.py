@@ -166,3 +166,23 @@ def test_step_combined_graph_matches_separate_step(api):
         got = [b.ect_out.cpu().numpy()] + [b.hy_out[k].cpu().numpy() for k in KERNELS] + [b.grad_xi.cpu().numpy()]
         for x, y in zip(got, ref):
             assert np.array_equal(x, y)
+
+
+def test_one_launch_with_laplace_log_scale(api):
+    """The Laplace output split into a shifted value and its log scale, through the combined call."""
+    rng = np.random.default_rng(1107)
+    img = W.random_image(rng, (50, 41), 6)
+    plan = api.Plan(T(img))
+    plan.set_tuning(ect_dirs_per_group=1)
+    dirs, thr = T(W.circle_dirs(20)), T(np.linspace(-40, 40, 80))
+    xi = T(rng.standard_normal((120, 2)) * 3.0)
+    ls_sep = torch.empty(120, dtype=torch.float64, device="cuda:0")
+    ls_one = torch.empty(120, dtype=torch.float64, device="cuda:0")
+    sep = plan.hybrid_multi(xi, ("laplace", "bessel"), 2.0, "fp32", log_scale_out=ls_sep)
+    e_one, one = plan.ect_hybrid_multi(dirs, thr, xi, ("laplace", "bessel"), 2.0, "fp32", log_scale_out=ls_one)
+    for k in ("laplace", "bessel"):
+        assert torch.equal(one[k], sep[k]), k
+    assert torch.equal(ls_one, ls_sep)
+    assert np.array_equal(e_one.cpu().numpy(), O.ect(img, W.circle_dirs(20), np.linspace(-40, 40, 80)))
+    assert plan.check() == 0
+
