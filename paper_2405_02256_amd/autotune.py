@@ -123,7 +123,7 @@ def pick(timings: dict):
     return best
 
 
-def time_call(fn, reps: int = 10, warmup: int = 2, trials: int = 3) -> float:
+def time_call(fn, reps: int = 10, warmup: int = 2, trials: int = 5) -> float:
     """Median over trials of the mean device time (ms) of fn() on the current stream."""
     import torch
     for _ in range(warmup):

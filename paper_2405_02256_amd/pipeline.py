@@ -120,7 +120,7 @@ class Step:
             else:
                 p.hybrid(self.hy_q, k, self.s, self.precision, out=self.hy_out[k], stream=stream)
 
-    def autotune(self, cache=None, use_cache: bool = True, reps: int = 10):
+    def autotune(self, cache=None, use_cache: bool = True, reps: int = 20):
         """Pick the plan's schedule knobs for this step's queries (before capture())."""
         from . import autotune as AT
         return AT.tune(self.plan, self.ect_q, self.ect_thr, self.hy_q, self.kernels, self.s, self.precision,
