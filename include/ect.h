@@ -284,6 +284,20 @@ ect_status ect_hybrid_eval_multi(ect_plan plan, ect_query_set dirs, const double
                                  double* out_bessel, double* log_scale_laplace, void* ws, size_t* ws_bytes,
                                  hipStream_t stream);
 
+/* ect_plan_rerun_prepare -- ect_plan_rerun, and in the same launch the
+ * bucketing and work list that the next hybrid evaluation (hybrid_eval,
+ * hybrid_eval_multi or ect_hybrid_eval_multi, forward) of the shared query set
+ * xi with workspace ws would write first; that call then skips them.  The
+ * query workgroup runs beside the compaction's tiles instead of after them.
+ * Used for two-axis, single-image plans whose compaction runs in one pass with
+ * room for one more workgroup, and for 1 .. 65536 query rows; otherwise this
+ * is ect_plan_rerun and the evaluation buckets the set itself.  ws_bytes: the
+ * size hybrid_eval needs for xi (ws == NULL: size query).  The set must not
+ * change until that evaluation is enqueued; any call in between that writes
+ * ws, re-runs or retunes the plan cancels the skip.  xi.offsets must be NULL
+ * (ECT_E_INVALID otherwise). */
+ect_status ect_plan_rerun_prepare(ect_plan plan, ect_query_set xi, void* ws, size_t* ws_bytes, hipStream_t stream);
+
 /* hybrid_eval_backward -- vector-Jacobian product of hybrid_eval (without
  * log_scale) with respect to xi and to the scale s.  With kappa the kernel,
  * dHT/dxi_a = sum Delta^ord x_a kappa(s <xi,x>) and

@@ -65,6 +65,7 @@ def lib():
     L.ect_status_string.argtypes = [c_i32]
     L.ect_precompute.argtypes = [P(ImageBatch), c_vp, P(ctypes.c_size_t), c_vp, P(c_vp)]
     L.ect_plan_rerun.argtypes = [c_vp, c_vp]
+    L.ect_plan_rerun_prepare.argtypes = [c_vp, QuerySet, c_vp, P(ctypes.c_size_t), c_vp]
     L.ect_eval.argtypes = [c_vp, QuerySet, c_vp, c_i32, c_i32, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
     L.radon_eval.argtypes = [c_vp, QuerySet, c_vp, c_i32, c_i32, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
     L.hybrid_eval.argtypes = [c_vp, c_i32, c_f64, c_i32, QuerySet, c_vp, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
@@ -83,7 +84,7 @@ def lib():
     L.ect_exact_layout.argtypes = [c_vp, QuerySet, c_i32, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
     L.ect_exact.argtypes = [c_vp, QuerySet, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
     L.ect_exact_eval.argtypes = [c_i32, c_i64, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_i32, c_i32, c_vp, c_vp]
-    for name in ("ect_precompute", "ect_plan_rerun", "ect_eval", "radon_eval", "hybrid_eval", "hybrid_eval_multi",
+    for name in ("ect_precompute", "ect_plan_rerun", "ect_plan_rerun_prepare", "ect_eval", "radon_eval", "hybrid_eval", "hybrid_eval_multi",
                  "ect_hybrid_eval_multi", "hybrid_eval_backward", "ect_exact_layout", "ect_exact", "ect_exact_eval",
                  "ect_plan_counts", "ect_plan_export", "ect_plan_check", "ect_plan_destroy", "ect_plan_set_tuning",
                  "ect_set_stage_events"):
@@ -155,6 +156,10 @@ def hybrid_eval_multi(plan, mask, s, precision, xi: QuerySet, out_f, out_l, out_
                                    c_vp(out_f) if out_f else None, c_vp(out_l) if out_l else None,
                                    c_vp(out_b) if out_b else None, c_vp(log_scale) if log_scale else None, ws,
                                    ctypes.byref(ws_bytes), c_vp(stream))
+
+
+def ect_plan_rerun_prepare(plan, xi: QuerySet, ws, ws_bytes: ctypes.c_size_t, stream) -> int:
+    return lib().ect_plan_rerun_prepare(c_vp(plan), xi, ws, ctypes.byref(ws_bytes), c_vp(stream))
 
 
 def ect_hybrid_eval_multi(plan, dirs: QuerySet, thresholds, M, per_image, ect_out, mask, s, precision,

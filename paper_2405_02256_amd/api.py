@@ -134,6 +134,21 @@ class Plan:
             ws = self._eval_ws[slot] = _workspace(nbytes, self.device)
         return ws
 
+    def rerun_prepare(self, xi, stream=None, slot: str = "main") -> None:
+        """rerun(), bucketing the shared query set xi in the same launch for the next forward hybrid call
+        on this workspace slot (ect_plan_rerun_prepare); plans it does not apply to are just re-run."""
+        q = xi if isinstance(xi, QuerySet) else QuerySet(xi)
+        q.validate(self.num_images, self.ndim)
+        if q.offsets is not None:
+            raise ValueError("rerun_prepare takes a shared query set")
+        st = _stream(stream)
+        need = ctypes.c_size_t(0)
+        N.check(N.ect_plan_rerun_prepare(self.handle, q.c(), None, need, st), "ect_plan_rerun_prepare(size)")
+        ws = self._ws(need.value, slot)
+        have = ctypes.c_size_t(ws.numel())
+        N.check(N.ect_plan_rerun_prepare(self.handle, q.c(), ctypes.c_void_p(_dptr(ws)), have, st),
+                "ect_plan_rerun_prepare")
+
     def set_tuning(self, hybrid_chunk: int = 0, hybrid_target_items: int = 2048, ect_dirs_per_group: int = 0,
                    ect_chunks: int = 0):
         """Schedule knobs (0 = automatic): hybrid point chunk, hybrid work items,

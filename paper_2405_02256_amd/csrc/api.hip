@@ -19,6 +19,7 @@ StageEvents g_stage_events[4];
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int64_t kAheadMaxRows = 65536;   // query rows one workgroup buckets inside the compaction launch
 constexpr int kAccSlotsHost = 4;  // doubles per query in a partial record
 
 struct EvalLayout {
@@ -272,7 +273,53 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
 ect_status ect_plan_rerun(ect_plan plan, hipStream_t stream) {
     if (!plan) return ECT_E_INVALID;
     ++plan->lists_epoch;
+    plan->last_prep.ahead = false;
     return from_hip(launch_precompute(*plan, false, stream));
+}
+
+ect_status ect_plan_rerun_prepare(ect_plan plan, ect_query_set xi, void* ws, size_t* ws_bytes, hipStream_t stream) {
+    if (!plan || !ws_bytes) return ECT_E_INVALID;
+    if (!valid_query_set(xi, plan->num_images) || xi.offsets) return ECT_E_INVALID;
+    Plan& p = *plan;
+    EvalLayout L{};
+    int64_t chunk = 0;
+    layout_hybrid(p, xi, false, &L, &chunk);
+    if (!ws) {
+        *ws_bytes = L.total;
+        return ECT_OK;
+    }
+    if (*ws_bytes < L.total) return ECT_E_NOMEM;
+    const int64_t rows = query_rows(xi, p.num_images);
+    ++p.lists_epoch;
+    auto& lp = p.last_prep;
+    lp.ahead = false;
+    if (rows == 0 || rows > kAheadMaxRows || !precompute_takes_queries(p))
+        return from_hip(launch_precompute(p, false, stream));   // the evaluation buckets the set itself
+    char* w = (char*)ws;
+    QueryPrep qp;
+    qp.vecs = xi.vecs;
+    qp.rows = rows;
+    qp.recs = (void*)(w + L.recs);
+    qp.bcnt = (int32_t*)(w + L.bcnt);
+    qp.qtile = kHybridTile;
+    qp.chunk0 = chunk;
+    qp.capacity = L.capacity;
+    qp.item_off = (int64_t*)(w + L.item_off);
+    qp.tile_off = (int64_t*)(w + L.tile_off);
+    qp.params = (int64_t*)(w + L.params);
+    const hipError_t e = launch_precompute(p, false, stream, &qp);
+    if (e != hipSuccess) {
+        lp.valid = false;
+        return ECT_E_DEVICE;
+    }
+    lp.ws = ws;
+    lp.vecs = xi.vecs;
+    lp.offsets = nullptr;
+    lp.count = xi.count;
+    lp.epoch = p.lists_epoch;
+    lp.valid = true;
+    lp.ahead = true;
+    return ECT_OK;
 }
 
 // How a threshold evaluation runs: directions per workgroup, list chunks, and
@@ -537,7 +584,12 @@ static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t 
     uint32_t* err = (uint32_t*)(p.ws + p.lay.err);
     const bool shared = xi.offsets == nullptr;
     hipError_t e = hipSuccess;
-    if (!reuse) {
+    // buckets and work list written ahead by ect_plan_rerun_prepare for this
+    // workspace and query set, since the last change of the lists
+    const bool ahead = !backward && !reuse && lp.ahead && lp.valid && lp.ws == ws && lp.vecs == xi.vecs &&
+                       lp.offsets == xi.offsets && lp.count == xi.count && lp.epoch == plan->lists_epoch;
+    lp.ahead = false;
+    if (!reuse && !ahead) {
         e = launch_prepare(p.ndim, xi, p.num_images, true, err, (void*)(w + L.recs), (int32_t*)(w + L.bcnt),
                            (const int64_t*)(p.ws + p.lay.list_off), num_classical(p.ndim), NL, kHybridTile, chunk,
                            L.capacity, (int64_t*)(w + L.item_off), (int64_t*)(w + L.tile_off),

@@ -110,6 +110,7 @@ struct ect_plan_s {
         int64_t count = 0;
         uint64_t epoch = 0;
         bool valid = false;
+        bool ahead = false;   // written by ect_plan_rerun_prepare, not used by an evaluation yet
     } last_prep;
     int64_t tune_hybrid_chunk = 0;          // 0: automatic
     int64_t tune_hybrid_target_items = 2048;
@@ -159,7 +160,25 @@ inline hipError_t stage_mark(int stage, bool after, hipStream_t s) {
 // Kernel launch helpers (host side, defined in the .hip files).
 // first: also clear the plan's error word, ticket counter and look-back words
 // (plan creation); re-runs launch the classification kernel alone.
-hipError_t launch_precompute(const Plan& p, bool first, hipStream_t stream);
+// A shared hybrid query set bucketed inside the compaction launch (two-axis,
+// single-image plans of the one-level look-back): one extra workgroup sorts
+// the queries (records, pair counts) and publishes the pair counts in one
+// word; the last tile builds the work list from them and the list totals.
+struct QueryPrep {
+    const double* vecs = nullptr;   // null: no queries
+    int64_t rows = 0;
+    void* recs = nullptr;
+    int32_t* bcnt = nullptr;
+    int qtile = 0;
+    int64_t chunk0 = 0, capacity = 0;
+    int64_t* item_off = nullptr;
+    int64_t* tile_off = nullptr;
+    int64_t* params = nullptr;
+};
+
+hipError_t launch_precompute(const Plan& p, bool first, hipStream_t stream, const QueryPrep* prep = nullptr);
+// Whether launch_precompute can take a QueryPrep for this plan.
+bool precompute_takes_queries(const Plan& p);
 // Compaction workgroups one compute unit holds at once (0 if unknown); flat:
 // the one-level look-back variant.
 int64_t precompute_slots_per_cu(int ndim, int construction, int dtype, bool flat = false);

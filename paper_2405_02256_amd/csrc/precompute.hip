@@ -26,7 +26,7 @@
 // sorted by linear vertex index, and identically on every run.
 #include <type_traits>
 
-#include "ect_internal.h"
+#include "query_body.h"
 
 namespace ect {
 
@@ -421,6 +421,45 @@ __device__ __forceinline__ void emit_points(const TileValues<N>& tv,
     }
 }
 
+// Last tile of a compaction launch that buckets a shared hybrid query set
+// (wave 0): wait for the query workgroup's pair counts (a bounded wait), take
+// the sizes of the two ordinary lists from the totals (predecessors' sums
+// plus this tile's counts, lane l holding list l's), build the work list and
+// consume the word so that a later launch without queries cannot see it.
+template <int NL>
+__device__ __forceinline__ void prep_worklist(const QueryPrep& prep, uint64_t* prep_word, bool ok,
+                                              const uint64_t (&loc)[NL], uint64_t agg, uint32_t* err) {
+    const int lane = threadIdx.x & 63;
+    uint64_t w = 0;
+    for (int spins = 0;; ++spins) {
+        w = __hip_atomic_load(prep_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (w & kFlagAggregate) break;
+        if (spins > kLookbackSpinLimit) {
+            if (lane == 0) raise_error(err, ECT_DEVERR_LOOKBACK);
+            ok = false;
+            break;
+        }
+        const int naps = spins < 16 ? spins + 1 : 16;
+        for (int i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(2);
+    }
+    uint64_t tot = 0;
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+        if (lane == l) tot = loc[l] + agg;
+    constexpr int kOrd0 = 4;   // the ordinary lists follow the four classical ones
+    const int64_t np = (int64_t)__shfl(tot, kOrd0 + (lane & 1), 64);
+    const int64_t q = lane == 0 ? (int64_t)(w & 0xFFFFFFull) : (lane == 1 ? (int64_t)((w >> 24) & 0xFFFFFFull) : 0);
+    if (ok) {
+        worklist_wave(2, q, np, prep.qtile, prep.chunk0, prep.capacity, err, prep.item_off, prep.tile_off,
+                      prep.params);
+    } else if (lane == 0) {
+        prep.params[0] = 0;
+        prep.params[1] = 0;
+        prep.params[2] = prep.chunk0;
+    }
+    if (lane == 0) __hip_atomic_store(prep_word, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Single pass, for plans whose tiles all fit on the chip at once (one
 // workgroup per tile, all resident): wave 0 of a tile sums the aggregates of
 // its predecessors in its group of 64 (level 1), the group's last tile
@@ -433,14 +472,33 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
                  const int64_t* __restrict__ tile_start, int32_t num_images, int64_t num_tiles,
                  uint32_t* __restrict__ err, uint64_t* __restrict__ run_ctr, uint64_t* __restrict__ status,
                  uint64_t* __restrict__ gstatus, int64_t* __restrict__ list_off, PointT<N>* __restrict__ points,
-                 int64_t capacity) {
+                 int64_t capacity, QueryPrep prep, uint64_t* __restrict__ prep_word) {
     constexpr int NL = TileValues<N>::NL;
     constexpr int W = kPrecomputeThreads / 64;
     __shared__ uint64_t s_run;
+    // with queries, workgroup 0 sorts them (dispatched first, so that it runs
+    // beside the tiles from the start) and the tiles follow
+    const bool with_prep = FLAT && N == 2 && prep.vecs != nullptr;
+    constexpr int64_t kPrepGroups = 1;
+    if constexpr (FLAT && N == 2) {
+        // the query workgroup: sort the shared hybrid queries and publish the
+        // pair counts in one word (it waits on nothing, so the tiles' waits
+        // still end)
+        if (with_prep && blockIdx.x == 0) {
+            __shared__ int32_t s_pbin[2 * kSubBins];
+            __shared__ int32_t s_pw[kPrecomputeThreads / 64], s_ptot[2], s_pstart[2];
+            sort_shared_queries<2>(prep.vecs, prep.rows, err, (QRecT<2>*)prep.recs, prep.bcnt, s_pbin, s_pw, s_ptot,
+                                   s_pstart);
+            if (threadIdx.x == 0)
+                __hip_atomic_store(prep_word, kFlagAggregate | (uint64_t)s_ptot[0] | ((uint64_t)s_ptot[1] << 24),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+    }
     __shared__ int32_t s_cnt[TileValues<N>::J][W][NL];   // per (round, wave, list) counts, then offsets
     __shared__ int64_t s_base[NL];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = (int64_t)blockIdx.x - (with_prep ? kPrepGroups : 0);
     if (tid == 0) s_run = __hip_atomic_load(run_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     TileValues<N> tv;
     tile_values<N, CONS, T>(pixels, descs, tile_start, num_images, tile, tv, s_cnt);
@@ -460,6 +518,10 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
             ok = sum_published_flat<NL>(status, tile, parity, loc, err);
 #pragma unroll
             for (int l = 0; l < NL; ++l) grp[l] = 0;
+            if constexpr (N == 2) {
+                if (prep.vecs && tile == num_tiles - 1)
+                    prep_worklist(prep, prep_word, ok, loc, agg, err);
+            }
             if (tile == num_tiles - 1 && lane == 0)
                 __hip_atomic_store(run_ctr, run + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
@@ -750,14 +812,18 @@ tile_write_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ de
 }
 
 template <int N, int CONS, typename T>
-hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream) {
+hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream, const QueryPrep* prep) {
     const PlanLayout& L = p.lay;
     const int NL = num_lists(N);
     uint32_t* err = (uint32_t*)(p.ws + L.err);
     uint64_t* run_ctr = (uint64_t*)(p.ws + L.err + 8);
     uint64_t* status = (uint64_t*)(p.ws + L.status);
     uint64_t* gstatus = status + L.num_tiles * NL;   // [ceil(tiles / 64)][NL] group totals
-    const int64_t nstatus = (L.num_tiles + (L.num_tiles + 63) / 64) * NL;
+    // tile words, group totals, and one row whose first word carries the
+    // query workgroup's pair counts
+    const int64_t nstatus = (L.num_tiles + (L.num_tiles + 63) / 64 + 1) * NL;
+    uint64_t* prep_word = status + (L.num_tiles + (L.num_tiles + 63) / 64) * NL;
+    const QueryPrep qp = prep ? *prep : QueryPrep{};
     const bool single = L.num_tiles <= p.precompute_grid;
     hipError_t e = hipSuccess;
     if (first && single) {
@@ -774,14 +840,17 @@ hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream) {
     int64_t* lo = (int64_t*)(p.ws + L.list_off);
     PointT<N>* pts = (PointT<N>*)(p.ws + L.points);
     if (single) {
-        if (N == 2 && L.num_tiles <= kFlatTiles && L.num_tiles <= p.precompute_grid_flat)
-            hipLaunchKernelGGL((classify_compact<N, CONS, T, true>), dim3((unsigned)L.num_tiles),
-                               dim3(kPrecomputeThreads), 0, stream, px, desc, ts, p.num_images, L.num_tiles, err,
-                               run_ctr, status, gstatus, lo, pts, L.capacity);
-        else
+        if (N == 2 && L.num_tiles <= kFlatTiles && L.num_tiles <= p.precompute_grid_flat) {
+            // one more workgroup when it buckets the queries (the caller checked that it fits)
+            const int64_t grid = L.num_tiles + (qp.vecs ? 1 : 0);
+            hipLaunchKernelGGL((classify_compact<N, CONS, T, true>), dim3((unsigned)grid), dim3(kPrecomputeThreads),
+                               0, stream, px, desc, ts, p.num_images, L.num_tiles, err, run_ctr, status, gstatus, lo,
+                               pts, L.capacity, qp, prep_word);
+        } else {
             hipLaunchKernelGGL((classify_compact<N, CONS, T, false>), dim3((unsigned)L.num_tiles),
                                dim3(kPrecomputeThreads), 0, stream, px, desc, ts, p.num_images, L.num_tiles, err,
-                               run_ctr, status, gstatus, lo, pts, L.capacity);
+                               run_ctr, status, gstatus, lo, pts, L.capacity, QueryPrep{}, prep_word);
+        }
     } else {
         // the status region holds the counts (int32), the prefixes (int64) and
         // the block sums (int64)
@@ -838,11 +907,11 @@ int64_t slots_typed(bool flat) {
 }
 
 template <int N, int CONS>
-hipError_t launch_dtype(const Plan& p, bool first, hipStream_t s) {
+hipError_t launch_dtype(const Plan& p, bool first, hipStream_t s, const QueryPrep* prep) {
     switch (p.dtype) {
-        case ECT_U8: return launch_typed<N, CONS, uint8_t>(p, first, s);
-        case ECT_I16: return launch_typed<N, CONS, int16_t>(p, first, s);
-        default: return launch_typed<N, CONS, int32_t>(p, first, s);
+        case ECT_U8: return launch_typed<N, CONS, uint8_t>(p, first, s, prep);
+        case ECT_I16: return launch_typed<N, CONS, int16_t>(p, first, s, prep);
+        default: return launch_typed<N, CONS, int32_t>(p, first, s, prep);
     }
 }
 
@@ -867,15 +936,23 @@ int64_t precompute_slots_per_cu(int ndim, int construction, int dtype, bool flat
     return construction == ECT_PRIMAL ? pick(I4{}, P{}) : pick(I4{}, Du{});
 }
 
-hipError_t launch_precompute(const Plan& p, bool first, hipStream_t stream) {
+bool precompute_takes_queries(const Plan& p) {
+    const PlanLayout& L = p.lay;
+    // the tiles and the query workgroup all resident at once
+    return p.ndim == 2 && p.num_images == 1 && L.num_tiles <= p.precompute_grid &&
+           L.num_tiles + 1 <= kFlatTiles && L.num_tiles + 1 <= p.precompute_grid_flat;
+}
+
+hipError_t launch_precompute(const Plan& p, bool first, hipStream_t stream, const QueryPrep* prep) {
+    if (prep && prep->vecs && !precompute_takes_queries(p)) return hipErrorInvalidValue;
     if (p.ndim == 2)
-        return p.construction == ECT_PRIMAL ? launch_dtype<2, ECT_PRIMAL>(p, first, stream)
-                                            : launch_dtype<2, ECT_DUAL>(p, first, stream);
+        return p.construction == ECT_PRIMAL ? launch_dtype<2, ECT_PRIMAL>(p, first, stream, prep)
+                                            : launch_dtype<2, ECT_DUAL>(p, first, stream, prep);
     if (p.ndim == 3)
-        return p.construction == ECT_PRIMAL ? launch_dtype<3, ECT_PRIMAL>(p, first, stream)
-                                            : launch_dtype<3, ECT_DUAL>(p, first, stream);
-    return p.construction == ECT_PRIMAL ? launch_dtype<4, ECT_PRIMAL>(p, first, stream)
-                                        : launch_dtype<4, ECT_DUAL>(p, first, stream);
+        return p.construction == ECT_PRIMAL ? launch_dtype<3, ECT_PRIMAL>(p, first, stream, prep)
+                                            : launch_dtype<3, ECT_DUAL>(p, first, stream, prep);
+    return p.construction == ECT_PRIMAL ? launch_dtype<4, ECT_PRIMAL>(p, first, stream, prep)
+                                        : launch_dtype<4, ECT_DUAL>(p, first, stream, prep);
 }
 
 }  // namespace ect

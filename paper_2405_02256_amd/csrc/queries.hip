@@ -20,7 +20,7 @@
 // independently, with the same chunks, in a fixed order over the points.
 // (Shared ECT sets are not bucketed at all: ect_direct_kernel reads them in
 // place.)
-#include "eval_internal.h"
+#include "query_body.h"
 
 namespace ect {
 
@@ -45,30 +45,6 @@ __device__ __forceinline__ int aggregated_add(Ctr* counters, int key, bool valid
         pending &= ~m;
     }
     return slot;
-}
-
-// Bucket key and record of query row r with vector v in image img (rows
-// [r0, r0 + q) of the set belong to it): returns the (image, bucket) entry.
-template <int N>
-__device__ __forceinline__ int64_t classify_vec(const double (&v)[N], int64_t r, int img, int64_t r0, int64_t q,
-                                                int mode_hybrid, uint32_t* __restrict__ err, QRecT<N>* rec,
-                                                int64_t* slot_base) {
-    const int B = mode_hybrid ? (1 << (N - 1)) : (1 << N);
-    const int full = (1 << N) - 1;
-    constexpr int NV = sizeof(QRecT<N>::v) / sizeof(double);
-    bool fin = true;
-#pragma unroll
-    for (int a = 0; a < NV; ++a) {
-        rec->v[a] = a < N ? v[a < N ? a : 0] : 0.0;
-        fin = fin && isfinite(rec->v[a]);
-    }
-    if (!fin && err) raise_error(err, ECT_DEVERR_NONFINITE);
-    int e = sign_index<N>(rec->v);
-    int neg = 0;
-    if (mode_hybrid && ((e >> (N - 1)) & 1)) { e ^= full; neg = 1; }
-    rec->code = 2 * (r - r0) + neg;
-    *slot_base = B * r0 + e * q;
-    return (int64_t)img * B + e;
 }
 
 // Image of row r: the last image whose first row is <= r (offsets in global
@@ -226,61 +202,6 @@ __device__ void build_worklist(int num_images, int B, int list_base, int NL, int
     }
 }
 
-// Work list of at most 64 entries by one wave, lane = entry (no barrier):
-// q = the entry's query count, np = its list size.  Same items, prefixes,
-// chunk doubling and outputs as build_worklist.
-__device__ void worklist_wave(int64_t E, int64_t q, int64_t np, int qtile, int64_t chunk0, int64_t capacity,
-                              uint32_t* __restrict__ err, int64_t* __restrict__ item_off,
-                              int64_t* __restrict__ tile_off, int64_t* __restrict__ params) {
-    const int lane = threadIdx.x & 63;
-    const bool valid = lane < E;
-    const int64_t t = valid ? (q + qtile - 1) / qtile : 0;
-    auto items_for = [&](int64_t chunk) {
-        int64_t ch = chunk > 0 ? (np + chunk - 1) / chunk : 1;
-        if (ch < 1) ch = 1;  // an empty list still gets one item per tile, which writes zeros
-        return t * ch;
-    };
-    int64_t chunk = chunk0;
-    if (chunk > 0 && capacity > 0) {
-        for (int attempt = 0;; ++attempt) {
-            int64_t total = items_for(chunk);
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) total += __shfl_xor(total, off, 64);
-            if (total <= capacity) break;
-            chunk *= 2;
-            if (attempt == 39) {
-                if (lane == 0) {
-                    raise_error(err, ECT_DEVERR_CAPACITY);
-                    params[0] = 0;
-                    params[1] = 0;
-                    params[2] = chunk;
-                    item_off[E] = 0;
-                    tile_off[E] = 0;
-                }
-                return;
-            }
-        }
-    }
-    int64_t it = items_for(chunk), tl = t, ii = it, ti = tl;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int64_t a = __shfl_up(ii, off, 64), b = __shfl_up(ti, off, 64);
-        if (lane >= off) { ii += a; ti += b; }
-    }
-    if (valid) {
-        item_off[lane] = ii - it;
-        tile_off[lane] = ti - tl;
-    }
-    const int64_t tot_i = __shfl(ii, 63, 64), tot_t = __shfl(ti, 63, 64);
-    if (lane == 0) {
-        item_off[E] = tot_i;
-        tile_off[E] = tot_t;
-        params[0] = tot_i;
-        params[1] = tot_t;
-        params[2] = chunk;
-    }
-}
-
 __global__ void __launch_bounds__(1024)
 worklist_kernel(int num_images, int B, int list_base, int NL, int shared_queries,
                 const int32_t* __restrict__ bcnt, const int64_t* __restrict__ list_off,
@@ -306,30 +227,6 @@ worklist_kernel(int num_images, int B, int list_base, int NL, int shared_queries
 // work list of at most 64 entries is then built by one wave.
 constexpr int kPrepRows = 8;   // query rows in flight per thread (ragged small sets)
 constexpr int64_t kSharedMaxRows = 65536;
-constexpr int kSubBands = 16, kSubAngles = 32, kSubBins = kSubBands * kSubAngles;
-
-template <int N>
-__device__ __forceinline__ int sub_bin(const double* v) {
-    double r2 = 0.0;
-#pragma unroll
-    for (int a = 0; a < N; ++a) r2 = fma(v[a], v[a], r2);
-    // floor(log2 |xi|^2) from the exponent field; octaves of |xi| from 2^-12
-    const int ex = (int)((__double_as_longlong(r2) >> 52) & 0x7ff) - 1023;
-    const int lb = ex + 24 < 0 ? 0 : (ex + 24) >> 1;
-    const int band = !(r2 > 0.0) ? 0 : (lb >= kSubBands ? kSubBands - 1 : lb);
-    // angle of (xi_0, xi_1) modulo pi as a monotone "diamond" angle in [0, 2)
-    float x = (float)v[0], y = (float)v[1];
-    if (y < 0.0f || (y == 0.0f && x < 0.0f)) {
-        x = -x;
-        y = -y;
-    }
-    const float d = fabsf(x) + y;
-    const float t = d > 0.0f ? (x >= 0.0f ? y / d : 2.0f - y / d) : 0.0f;
-    const float f = t * (0.5f * kSubAngles);
-    const int ab = f >= 0.0f && f < (float)kSubAngles ? (int)f : (f >= (float)kSubAngles ? kSubAngles - 1 : 0);
-    return band * kSubAngles + ab;
-}
-
 template <int N>
 __global__ void __launch_bounds__(1024)
 prepare_shared_kernel(const double* __restrict__ vecs, int64_t rows, int num_images,

@@ -78,7 +78,11 @@ class Step:
         p = self.plan
         main = stream if stream is not None else torch.cuda.current_stream()
         if self.rerun_precompute:
-            p.rerun(main)
+            if self.combined and self.hy_q.offsets is None:
+                # the shared query set is bucketed in the compaction launch
+                p.rerun_prepare(self.hy_q, main)
+            else:
+                p.rerun(main)
         if self.combined:
             p.ect_hybrid_multi(self.ect_q, self.ect_thr, self.hy_q, self.kernels, self.s, self.precision,
                                ect_out=self.ect_out, outs=self.hy_out, log_scale_out=self.hy_ls.get("laplace"),

@@ -95,6 +95,7 @@ def test_eval_calls_reject_null_plan(N):
     assert N.ect_exact(None, q, 0, 0x4000, 16, 0x5000, 0x6000, 0x7000, None, need, 0) == N.ECT_E_INVALID
     assert N.ect_hybrid_eval_multi(None, q, 0x2000, 4, 0, 0x3000, 1, 1.0, 0, q, 0x4000, 0, 0, 0, None, need,
                                    0) == N.ECT_E_INVALID
+    assert N.ect_plan_rerun_prepare(None, q, None, need, 0) == N.ECT_E_INVALID
     assert N.ect_plan_destroy(None) == N.ECT_E_INVALID
     assert N.ect_plan_rerun(None, 0) == N.ECT_E_INVALID
 

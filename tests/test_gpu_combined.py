@@ -186,3 +186,69 @@ def test_one_launch_with_laplace_log_scale(api):
     assert np.array_equal(e_one.cpu().numpy(), O.ect(img, W.circle_dirs(20), np.linspace(-40, 40, 80)))
     assert plan.check() == 0
 
+
+
+def test_rerun_prepare_buckets_the_queries_in_the_compaction_launch(api):
+    """ect_plan_rerun_prepare: the next forward call skips its bucketing and gives the same outputs as
+    after a plain re-run, also when the image changed in place (new list sizes: the work list is built
+    from this launch's totals); calls in between that write the workspace or re-run cancel the skip."""
+    rng = np.random.default_rng(1108)
+    a = W.binary_field(rng, (150, 170), 3.0).astype(np.uint8)
+    b = W.binary_field(rng, (150, 170), 6.0).astype(np.uint8)
+    buf = T(a)
+    plan = api.Plan(buf)
+    plan.set_tuning(ect_dirs_per_group=1)
+    dirs, thr = T(W.circle_dirs(30)), T(np.linspace(-120, 120, 96))
+    xi = api.QuerySet(T(rng.standard_normal((700, 2)) * 0.5))
+    for img in (a, b, a):
+        buf.copy_(T(img))
+        plan.rerun()
+        e_ref, h_ref = plan.ect_hybrid_multi(dirs, thr, xi, KERNELS)
+        e_ref, h_ref = e_ref.cpu().numpy(), {k: v.cpu().numpy() for k, v in h_ref.items()}
+        plan.rerun_prepare(xi)
+        e, h = plan.ect_hybrid_multi(dirs, thr, xi, KERNELS)
+        assert np.array_equal(e.cpu().numpy(), e_ref)
+        for k in KERNELS:
+            assert np.array_equal(h[k].cpu().numpy(), h_ref[k]), k
+        assert np.array_equal(e_ref, O.ect(img, W.circle_dirs(30), np.linspace(-120, 120, 96)))
+        # the separate forward call consumes the buckets as well
+        plan.rerun_prepare(xi)
+        hm = plan.hybrid_multi(xi, KERNELS)
+        for k in KERNELS:
+            assert np.array_equal(hm[k].cpu().numpy(), h_ref[k]), k
+        # an ECT call on the same workspace in between: the evaluation buckets again
+        plan.rerun_prepare(xi)
+        plan.ect(dirs, thr)
+        hm = plan.hybrid_multi(xi, KERNELS)
+        for k in KERNELS:
+            assert np.array_equal(hm[k].cpu().numpy(), h_ref[k]), k
+    # the backward pass reuses what the skipped forward call found in the workspace
+    plan.rerun_prepare(xi)
+    y = plan.hybrid_multi(xi, KERNELS)["fourier"]
+    g = T(rng.standard_normal((700, 2)))
+    got = [t.cpu().numpy() for t in plan.hybrid_backward(xi, y, g, "fourier", 1.0, "fp32", reuse_prepared=True)]
+    ref = [t.cpu().numpy() for t in plan.hybrid_backward(xi, y, g, "fourier", 1.0, "fp32")]
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    assert plan.check() == 0
+
+
+def test_rerun_prepare_on_plans_it_does_not_apply_to(api):
+    """Three axes and batches of several images: a plain re-run, the evaluation buckets the set itself."""
+    rng = np.random.default_rng(1109)
+    vol = W.random_image(rng, (12, 10, 9), 4)
+    p3 = api.Plan(T(vol))
+    xi3 = api.QuerySet(T(rng.standard_normal((90, 3)) * 0.4))
+    ref = {k: v.cpu().numpy() for k, v in p3.hybrid_multi(xi3, KERNELS).items()}
+    p3.rerun_prepare(xi3)
+    for k, v in p3.hybrid_multi(xi3, KERNELS).items():
+        assert np.array_equal(v.cpu().numpy(), ref[k]), k
+    imgs = [W.random_image(rng, (30, 20), 4), W.random_image(rng, (25, 25), 3)]
+    p2 = api.Plan([T(im) for im in imgs])
+    xi2 = api.QuerySet(T(rng.standard_normal((80, 2)) * 0.4))
+    ref = {k: v.cpu().numpy() for k, v in p2.hybrid_multi(xi2, KERNELS).items()}
+    p2.rerun_prepare(xi2)
+    for k, v in p2.hybrid_multi(xi2, KERNELS).items():
+        assert np.array_equal(v.cpu().numpy(), ref[k]), k
+    with pytest.raises(ValueError):
+        p2.rerun_prepare(api.QuerySet(T(rng.standard_normal((4, 2))), T(np.array([0, 2, 4], np.int64))))
+    assert p3.check() == 0 and p2.check() == 0
