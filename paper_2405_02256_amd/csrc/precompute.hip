@@ -422,14 +422,14 @@ __device__ __forceinline__ void emit_points(const TileValues<N>& tv,
 }
 
 // Last tile of a compaction launch that buckets a shared hybrid query set
-// (wave 0): wait for the query workgroup's pair counts (a bounded wait), take
-// the sizes of the two ordinary lists from the totals (predecessors' sums
-// plus this tile's counts, lane l holding list l's), build the work list and
+// (wave 0, after its points): wait for the query workgroup's pair counts (a
+// bounded wait), build the work list from them and the two ordinary lists'
+// sizes (np, lane b holding pair b's; negative if the look-back failed) and
 // consume the word so that a later launch without queries cannot see it.
-template <int NL>
-__device__ __forceinline__ void prep_worklist(const QueryPrep& prep, uint64_t* prep_word, bool ok,
-                                              const uint64_t (&loc)[NL], uint64_t agg, uint32_t* err) {
+__device__ __forceinline__ void prep_worklist(const QueryPrep& prep, uint64_t* prep_word, int64_t np,
+                                              uint32_t* err) {
     const int lane = threadIdx.x & 63;
+    bool ok = __ballot(lane < 2 && np < 0) == 0;
     uint64_t w = 0;
     for (int spins = 0;; ++spins) {
         w = __hip_atomic_load(prep_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -442,12 +442,6 @@ __device__ __forceinline__ void prep_worklist(const QueryPrep& prep, uint64_t* p
         const int naps = spins < 16 ? spins + 1 : 16;
         for (int i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(2);
     }
-    uint64_t tot = 0;
-#pragma unroll
-    for (int l = 0; l < NL; ++l)
-        if (lane == l) tot = loc[l] + agg;
-    constexpr int kOrd0 = 4;   // the ordinary lists follow the four classical ones
-    const int64_t np = (int64_t)__shfl(tot, kOrd0 + (lane & 1), 64);
     const int64_t q = lane == 0 ? (int64_t)(w & 0xFFFFFFull) : (lane == 1 ? (int64_t)((w >> 24) & 0xFFFFFFull) : 0);
     if (ok) {
         worklist_wave(2, q, np, prep.qtile, prep.chunk0, prep.capacity, err, prep.item_off, prep.tile_off,
@@ -497,6 +491,7 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
     }
     __shared__ int32_t s_cnt[TileValues<N>::J][W][NL];   // per (round, wave, list) counts, then offsets
     __shared__ int64_t s_base[NL];
+    __shared__ int64_t s_total[NL];   // last tile: list totals (-1: look-back failed)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t tile = (int64_t)blockIdx.x - (with_prep ? kPrepGroups : 0);
     if (tid == 0) s_run = __hip_atomic_load(run_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -518,10 +513,6 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
             ok = sum_published_flat<NL>(status, tile, parity, loc, err);
 #pragma unroll
             for (int l = 0; l < NL; ++l) grp[l] = 0;
-            if constexpr (N == 2) {
-                if (prep.vecs && tile == num_tiles - 1)
-                    prep_worklist(prep, prep_word, ok, loc, agg, err);
-            }
             if (tile == num_tiles - 1 && lane == 0)
                 __hip_atomic_store(run_ctr, run + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
@@ -544,11 +535,20 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
             for (int l = 0; l < NL; ++l) if (lane == l) mine = ok ? loc[l] + grp[l] : 0;
             s_base[lane] = (int64_t)mine;
             if (tile == tv.d.tile_start) list_off[(int64_t)tv.img_id * NL + lane] = (int64_t)mine;
-            if (tile == num_tiles - 1) list_off[(int64_t)num_images * NL + lane] = (int64_t)(mine + agg);
+            if (tile == num_tiles - 1) {
+                list_off[(int64_t)num_images * NL + lane] = (int64_t)(mine + agg);
+                s_total[lane] = ok ? (int64_t)(mine + agg) : -1;
+            }
         }
     }
     __syncthreads();
     emit_points<N>(tv, s_cnt, s_base, points, capacity);
+    // the last tile builds the queries' work list after writing its own
+    // points, so that its stores drain while it waits for the query workgroup
+    if constexpr (FLAT && N == 2) {
+        if (with_prep && tile == num_tiles - 1 && wave == 0)
+            prep_worklist(prep, prep_word, s_total[4 + (lane & 1)], err);
+    }
 }
 
 // Three passes, for plans with more tiles than the chip holds at once (no
