@@ -370,6 +370,11 @@ static ect_status threshold_setup(const Plan& p, const ect_query_set& dirs, cons
                                           : std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)(avg / 4096.0)));
         if (S->chunks > 1) S->L.total = sizeof(int32_t) * (size_t)(groups * S->chunks * td * (int64_t)M * arrays);
         S->L.grid = groups * S->chunks;
+        // fewer than two workgroups per compute unit: twice the waves in each,
+        // so that more of the list's loads are in flight, without the extra
+        // launch that splitting the list into parts would need to add them up
+        if (S->threads == kEctThreads && S->L.grid < 2 * (int64_t)std::max(p.num_cus, 1))
+            S->threads = kEctWideThreads;
     } else {
         layout_ect(p, dirs, td, &S->L);
     }

@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
 // Shared query sets: one workgroup per (image, group of directions, part of
 // the list); see ect_direct_block.
 template <int N, bool RADON>
-__global__ void __launch_bounds__(kEctThreads) ect_direct_kernel(EctArgs a, int64_t groups) {
+__global__ void __launch_bounds__(kEctWideThreads) ect_direct_kernel(EctArgs a, int64_t groups) {
     ect_direct_block<N, RADON>(a, groups, blockIdx.x);
 }
 
@@ -179,7 +179,8 @@ hipError_t launch_ect_chunk_sum(const EctArgs& a, int64_t grid, int64_t groups, 
 hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, int64_t direct_groups, bool radon,
                       hipStream_t stream) {
     if (grid <= 0) return hipSuccess;
-    if (a.threads != 64 && a.threads != kEctThreads) return hipErrorInvalidValue;
+    if (a.threads != 64 && a.threads != kEctThreads && !(a.threads == kEctWideThreads && direct_groups > 0))
+        return hipErrorInvalidValue;
     const size_t shmem = sizeof(double) * a.M + (radon ? 2 : 1) * sizeof(int32_t) * a.dirs_per_group * a.M;
     hipError_t e = stage_mark(ECT_STAGE_ECT, false, stream);
     if (e != hipSuccess) return e;

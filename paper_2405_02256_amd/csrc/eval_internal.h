@@ -26,6 +26,7 @@ template <int N> using QRecT = typename QRecSel<N>::type;
 
 inline size_t qrec_bytes(int ndim) { return ndim == 4 ? sizeof(QRec4) : sizeof(QRec); }
 constexpr int kEctThreads = 256;      // ECT workgroup: points stream across its lanes
+constexpr int kEctWideThreads = 512;  // shared-set ECT workgroup when the launch has few of them
 constexpr int kEctMaxDirs = 8;        // directions per ECT workgroup
 constexpr int kComboEctDirs = 2;      // at most this many in the combined ECT + hybrid launch
 constexpr size_t kComboEctLds = 4096; // and at most this much dynamic LDS (thresholds + histograms)
@@ -73,7 +74,8 @@ struct EctArgs {
     int dirs_per_group;
     int64_t chunks;           // shared sets: point chunks per direction group (1: no split)
     int32_t* part;            // shared sets with chunks > 1: per-chunk histograms
-    int threads;              // workgroup size of the threshold kernels: 64 or kEctThreads
+    int threads;              // workgroup size of the threshold kernels: 64, kEctThreads, or
+                              // kEctWideThreads (shared sets only)
 };
 
 // Mean classical list length up to which one-wave workgroups evaluate the ECT.
