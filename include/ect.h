@@ -71,7 +71,9 @@ typedef enum {
     ECT_E_NOMEM = 2,        /* workspace smaller than required, or host allocation failed */
     ECT_E_DEVICE = 3,       /* a HIP runtime call failed */
     ECT_E_UNSUPPORTED = 4,  /* valid request outside what this build implements */
-    ECT_E_RANGE = 5         /* a value does not fit the output type */
+    ECT_E_RANGE = 5,        /* a value does not fit the output type */
+    ECT_E_SCRATCH = 6       /* hybrid_eval_noalloc: the call needs more work memory than the
+                               static scratch array holds (ECT_NOALLOC_SCRATCH_BYTES) */
 } ect_status;
 
 typedef enum { ECT_PRIMAL = 0, ECT_DUAL = 1 } ect_construction;
@@ -254,6 +256,28 @@ ect_status ect_exact_eval(int32_t kind, int64_t rows, const int64_t* row_off, co
 ect_status hybrid_eval(ect_plan plan, int32_t kernel, double s, int32_t precision,
                        ect_query_set xi, double* out, double* log_scale,
                        void* ws, size_t* ws_bytes, hipStream_t stream);
+
+/* hybrid_eval_noalloc -- hybrid_eval for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid hipMalloc): the same computation, kernels and outputs as
+ * hybrid_eval(plan, kernel, s, precision, xi, out, log_scale, ...), bit for
+ * bit, with the work memory taken from a static device array of
+ * ECT_NOALLOC_SCRATCH_BYTES bytes inside the library instead of a caller
+ * workspace.  Each GPU the library runs on holds its own copy of that array
+ * until the process ends; its address is looked up once per device, on the
+ * first call with that device current.  The call allocates nothing, on the
+ * host or the device.
+ *   arguments       as hybrid_eval (no workspace)
+ * The current device must be the plan's device (ECT_E_INVALID otherwise).
+ * A call whose hybrid_eval workspace would exceed ECT_NOALLOC_SCRATCH_BYTES
+ * returns ECT_E_SCRATCH before enqueuing anything.  Every call on one GPU
+ * shares that GPU's array and overwrites what the previous call left there:
+ * calls that may overlap on one GPU (different streams, or different host
+ * threads, without ordering between them) race and must not be issued.
+ * A following hybrid_eval_backward cannot reuse its buckets. */
+#define ECT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+ect_status hybrid_eval_noalloc(ect_plan plan, int32_t kernel, double s, int32_t precision,
+                               ect_query_set xi, double* out, double* log_scale, hipStream_t stream);
 
 /* hybrid_eval_multi -- several hybrid transforms in one pass over the same
  * (query, critical point) pairs, sharing the projection <xi, x> and the staged

@@ -14,7 +14,8 @@ LIB_PATH = os.path.join(HERE, "libect.so")
 c_i32, c_i64, c_f64, c_u32, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32, ctypes.c_void_p
 P = ctypes.POINTER
 
-ECT_OK, ECT_E_INVALID, ECT_E_NOMEM, ECT_E_DEVICE, ECT_E_UNSUPPORTED, ECT_E_RANGE = range(6)
+ECT_OK, ECT_E_INVALID, ECT_E_NOMEM, ECT_E_DEVICE, ECT_E_UNSUPPORTED, ECT_E_RANGE, ECT_E_SCRATCH = range(7)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 PRIMAL, DUAL = 0, 1
 U8, I16, I32 = 0, 1, 2
 FOURIER, LAPLACE, BESSEL = 0, 1, 2
@@ -69,6 +70,7 @@ def lib():
     L.ect_eval.argtypes = [c_vp, QuerySet, c_vp, c_i32, c_i32, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
     L.radon_eval.argtypes = [c_vp, QuerySet, c_vp, c_i32, c_i32, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
     L.hybrid_eval.argtypes = [c_vp, c_i32, c_f64, c_i32, QuerySet, c_vp, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
+    L.hybrid_eval_noalloc.argtypes = [c_vp, c_i32, c_f64, c_i32, QuerySet, c_vp, c_vp, c_vp]
     L.hybrid_eval_multi.argtypes = [c_vp, c_u32, c_f64, c_i32, QuerySet, c_vp, c_vp, c_vp, c_vp, c_vp,
                                     P(ctypes.c_size_t), c_vp]
     L.ect_hybrid_eval_multi.argtypes = [c_vp, QuerySet, c_vp, c_i32, c_i32, c_vp, c_u32, c_f64, c_i32, QuerySet,
@@ -84,7 +86,8 @@ def lib():
     L.ect_exact_layout.argtypes = [c_vp, QuerySet, c_i32, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
     L.ect_exact.argtypes = [c_vp, QuerySet, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
     L.ect_exact_eval.argtypes = [c_i32, c_i64, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_i32, c_i32, c_vp, c_vp]
-    for name in ("ect_precompute", "ect_plan_rerun", "ect_plan_rerun_prepare", "ect_eval", "radon_eval", "hybrid_eval", "hybrid_eval_multi",
+    for name in ("ect_precompute", "ect_plan_rerun", "ect_plan_rerun_prepare", "ect_eval", "radon_eval", "hybrid_eval", "hybrid_eval_noalloc",
+                 "hybrid_eval_multi",
                  "ect_hybrid_eval_multi", "hybrid_eval_backward", "ect_exact_layout", "ect_exact", "ect_exact_eval",
                  "ect_plan_counts", "ect_plan_export", "ect_plan_check", "ect_plan_destroy", "ect_plan_set_tuning",
                  "ect_set_stage_events"):
@@ -148,6 +151,11 @@ def hybrid_eval(plan, kernel, s, precision, xi: QuerySet, out, log_scale, ws, ws
                 stream) -> int:
     return lib().hybrid_eval(c_vp(plan), int(kernel), float(s), int(precision), xi, c_vp(out),
                              c_vp(log_scale) if log_scale else None, ws, ctypes.byref(ws_bytes), c_vp(stream))
+
+
+def hybrid_eval_noalloc(plan, kernel, s, precision, xi: QuerySet, out, log_scale, stream) -> int:
+    return lib().hybrid_eval_noalloc(c_vp(plan), int(kernel), float(s), int(precision), xi, c_vp(out),
+                                     c_vp(log_scale) if log_scale else None, c_vp(stream))
 
 
 def hybrid_eval_multi(plan, mask, s, precision, xi: QuerySet, out_f, out_l, out_b, log_scale, ws,

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -126,6 +127,34 @@ bool is_finite(double v) { return std::isfinite(v); }
 
 }  // namespace
 
+// Work memory of hybrid_eval_noalloc: one static array per device.  In host
+// code `scratch` names a host-side stand-in, never the device memory; the
+// device address comes from hipGetSymbolAddress with that device current and
+// is the only one passed to kernels.
+static __device__ __align__(256) unsigned char scratch[ECT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 256;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the current device's scratch array, looked up on the
+// first call with that device current.
+ect_status scratch_address(int dev, void** ptr) {
+    if (dev < 0 || dev >= kMaxScratchDevices) return ECT_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ECT_E_DEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return ECT_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* ect_version(void) { return "0.1.0"; }
@@ -138,6 +167,7 @@ const char* ect_status_string(ect_status s) {
         case ECT_E_DEVICE: return "HIP runtime error";
         case ECT_E_UNSUPPORTED: return "unsupported request";
         case ECT_E_RANGE: return "value out of range";
+        case ECT_E_SCRATCH: return "request needs more work memory than the static scratch array holds";
     }
     return "unknown status";
 }
@@ -246,6 +276,7 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+    p->device = dev;
     const int64_t per_cu = e == hipSuccess ? precompute_slots_per_cu(n, batch->construction, batch->dtype) : 0;
     if (per_cu <= 0) {
         ect_plan_destroy(p);
@@ -666,6 +697,24 @@ ect_status hybrid_eval(ect_plan plan, int32_t kernel, double s, int32_t precisio
     return hybrid_common(plan, 1u << kernel, s, precision, xi, kernel_out(kernel, ECT_FOURIER, out),
                          kernel_out(kernel, ECT_LAPLACE, out), kernel_out(kernel, ECT_BESSEL, out), log_scale,
                          nullptr, nullptr, nullptr, nullptr, ws, ws_bytes, stream, false);
+}
+
+ect_status hybrid_eval_noalloc(ect_plan plan, int32_t kernel, double s, int32_t precision, ect_query_set xi,
+                               double* out, double* log_scale, hipStream_t stream) {
+    if (!plan) return ECT_E_INVALID;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return ECT_E_DEVICE;
+    if (dev != plan->device) return ECT_E_INVALID;
+    // argument checks and the workspace size, as hybrid_eval makes them
+    size_t need = 0;
+    ect_status st = hybrid_eval(plan, kernel, s, precision, xi, out, log_scale, nullptr, &need, stream);
+    if (st != ECT_OK) return st;
+    if (need > ECT_NOALLOC_SCRATCH_BYTES) return ECT_E_SCRATCH;
+    void* ws = nullptr;
+    st = scratch_address(dev, &ws);
+    if (st != ECT_OK) return st;
+    size_t have = ECT_NOALLOC_SCRATCH_BYTES;
+    return hybrid_eval(plan, kernel, s, precision, xi, out, log_scale, ws, &have, stream);
 }
 
 ect_status hybrid_eval_multi(ect_plan plan, uint32_t kernel_mask, double s, int32_t precision, ect_query_set xi,

@@ -90,6 +90,7 @@ struct ect_plan_s {
     int32_t dtype = 0;
     int32_t construction = 0;
     int32_t num_cus = 0;                    // compute units of the plan's device
+    int32_t device = -1;                    // HIP device current at ect_precompute
     int64_t precompute_grid = 1;            // tiles the single-pass compaction handles (all resident)
     int64_t precompute_grid_flat = 0;       // the same for its one-level variant (n = 2, small plans)
     const void* pixels = nullptr;

@@ -47,7 +47,7 @@ def test_library_exports_every_declared_symbol(N):
 
 def test_status_strings_and_version(N):
     assert N.version() == "0.1.0"
-    for st in range(6):
+    for st in range(7):
         assert N.status_string(st)
     assert N.status_string(99) == "unknown status"
 
@@ -91,6 +91,7 @@ def test_eval_calls_reject_null_plan(N):
     assert N.radon_eval(None, q, 0x2000, 4, 0, 0x3000, None, need, 0) == N.ECT_E_INVALID
     assert N.hybrid_eval(None, 0, 1.0, 0, q, 0x3000, 0, None, need, 0) == N.ECT_E_INVALID
     assert N.hybrid_eval_backward(None, 0, 1.0, 0, q, 1, 2, 3, 0, None, need, 0) == N.ECT_E_INVALID
+    assert N.hybrid_eval_noalloc(None, 0, 1.0, 0, q, 0x3000, 0, 0) == N.ECT_E_INVALID
     assert N.ect_exact_layout(None, q, 0, 0x4000, None, need, 0) == N.ECT_E_INVALID
     assert N.ect_exact(None, q, 0, 0x4000, 16, 0x5000, 0x6000, 0x7000, None, need, 0) == N.ECT_E_INVALID
     assert N.ect_hybrid_eval_multi(None, q, 0x2000, 4, 0, 0x3000, 1, 1.0, 0, q, 0x4000, 0, 0, 0, None, need,

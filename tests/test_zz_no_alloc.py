@@ -1,0 +1,108 @@
+"""hybrid_eval_noalloc (work memory in the library's static device array)
+against hybrid_eval (caller workspace), through the C ABI: equal outputs bit
+for bit on two calls in a row, the second with a smaller input, and a request
+larger than the static array refused on the host."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2405_02256_amd import workloads as W
+
+from gates import fp32_gate, term_scales
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_02256_amd import _native as N
+    from paper_2405_02256_amd import api as A
+    return A, N
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(torch.device("cuda:0"))
+
+
+def _noalloc(A, N, plan, xi, kernel, precision, log_scale=False, offsets=None):
+    q = A.QuerySet(xi, offsets)
+    q.validate(plan.num_images, plan.ndim)
+    rows = q.rows(plan.num_images)
+    k = N.KERNELS[kernel]
+    out = torch.full((rows, 2) if k == N.FOURIER else (rows,), np.nan, dtype=torch.float64, device="cuda:0")
+    ls = torch.full((rows,), np.nan, dtype=torch.float64, device="cuda:0") if log_scale else None
+    st = N.hybrid_eval_noalloc(plan.handle, k, 1.0, N.PRECISIONS[precision], q.c(), A._dptr(out), A._dptr(ls),
+                               A._stream())
+    N.check(st, "hybrid_eval_noalloc")
+    torch.cuda.synchronize()
+    return out, ls
+
+
+def _bits(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def test_noalloc_equals_hybrid_eval_two_calls(mods):
+    A, N = mods
+    rng = np.random.default_rng(2405)
+    big = W.binary_field(rng, (200, 240), 4.0)
+    small = W.binary_field(rng, (40, 36), 3.0)
+    xi_big = W.polar_vectors(rng, 3000, 0.01, 1.0)
+    xi_small = W.polar_vectors(rng, 70, 0.01, 1.0)
+    for img, xi in ((big, xi_big), (small, xi_small)):
+        print(f"[noalloc] image {img.shape}, {len(xi)} xi", flush=True)
+        plan = A.Plan(T(img))
+        for kernel in ("fourier", "laplace", "bessel"):
+            for precision in ("fp32", "fp64"):
+                got, _ = _noalloc(A, N, plan, T(xi), kernel, precision)
+                ref = plan.hybrid(T(xi), kernel, 1.0, precision)
+                torch.cuda.synchronize()
+                assert np.array_equal(_bits(got), _bits(ref)), (img.shape, kernel, precision)
+        got, ls = _noalloc(A, N, plan, T(xi), "laplace", "fp32", log_scale=True)
+        ref, rls = plan.hybrid(T(xi), "laplace", 1.0, "fp32", log_scale=True)
+        assert np.array_equal(_bits(got), _bits(ref)) and np.array_equal(_bits(ls), _bits(rls))
+        # and against the oracle, on a sample
+        sel = rng.choice(len(xi), min(24, len(xi)), replace=False)
+        y, _ = _noalloc(A, N, plan, T(xi), "fourier", "fp32")
+        y = y.cpu().numpy()[sel]
+        r = O.hybrid(img, xi[sel], "fourier", 1.0)
+        _, S2 = term_scales(img, xi[sel], "fourier", 1.0)
+        ok, ratio, norm, strict = fp32_gate(y[:, 0] + 1j * y[:, 1], r, S2)
+        assert ok, (ratio, norm)
+        assert plan.check() == 0
+
+
+def test_noalloc_ragged_batch(mods):
+    A, N = mods
+    rng = np.random.default_rng(2406)
+    imgs = [W.binary_field(rng, (s, s), 3.0) for s in (28, 64, 50)]
+    plan = A.Plan([T(im) for im in imgs])
+    offs = np.array([0, 40, 41, 140], np.int64)
+    xi = W.polar_vectors(rng, 140, 0.01, 1.0)
+    got, _ = _noalloc(A, N, plan, T(xi), "laplace", "fp32", offsets=T(offs))
+    ref = plan.hybrid(T(xi), "laplace", 1.0, "fp32", offsets=T(offs))
+    torch.cuda.synchronize()
+    assert np.array_equal(_bits(got), _bits(ref))
+
+
+def test_noalloc_refuses_requests_beyond_the_scratch(mods):
+    A, N = mods
+    img = W.binary_field(np.random.default_rng(2407), (16, 16), 2.0)
+    plan = A.Plan(T(img))
+    rows = (N.NOALLOC_SCRATCH_BYTES // 64) + 4096    # 64 bytes of query records per row alone
+    xi = torch.zeros((rows, 2), dtype=torch.float64, device="cuda:0")
+    xi[:, 0] = 0.5
+    out = torch.zeros((rows, 2), dtype=torch.float64, device="cuda:0")
+    q = A.QuerySet(xi)
+    st = N.hybrid_eval_noalloc(plan.handle, N.FOURIER, 1.0, N.FP32, q.c(), A._dptr(out), 0, A._stream())
+    assert st == N.ECT_E_SCRATCH
+    torch.cuda.synchronize()
+    assert (out == 0).all()
+    # bad arguments are refused as hybrid_eval refuses them
+    assert N.hybrid_eval_noalloc(plan.handle, 7, 1.0, N.FP32, q.c(), A._dptr(out), 0, A._stream()) == N.ECT_E_INVALID
