@@ -247,11 +247,14 @@ ect_status ect_exact_eval(int32_t kind, int64_t rows, const int64_t* row_off, co
  *   out             DEVICE double [rows] (Laplace, Bessel) or [rows][2]
  *                   (Fourier: real, imaginary)
  *   log_scale       DEVICE double [rows] or NULL.  Laplace only: when given,
- *                   out holds HT * exp(-log_scale) with log_scale an upper
- *                   bound of max(-s <xi,x>) over the image's vertices, so
- *                   that no term overflows; when NULL out holds HT and an
- *                   overflow sets ECT_DEVERR_OVERFLOW.  Other kernels: must
- *                   be NULL.
+ *                   out holds HT * exp(-log_scale), where log_scale = m2 ln 2
+ *                   for an integer m2 that follows the largest exponent
+ *                   -s <xi,x> over the query's ordinary points (within
+ *                   [max - 256 ln 2, max + ln 2)), so that no term overflows
+ *                   and the largest never underflows, wherever the object
+ *                   sits in its frame; when NULL out holds HT, scaled back
+ *                   exactly by 2^m2, and an HT beyond the FP64 range sets
+ *                   ECT_DEVERR_OVERFLOW.  Other kernels: must be NULL.
  * Deterministic: repeated calls give bitwise identical outputs. */
 ect_status hybrid_eval(ect_plan plan, int32_t kernel, double s, int32_t precision,
                        ect_query_set xi, double* out, double* log_scale,

@@ -21,7 +21,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int64_t kAheadMaxRows = 65536;   // query rows one workgroup buckets inside the compaction launch
-constexpr int kAccSlotsHost = 4;  // doubles per query in a partial record
+constexpr int kAccSlotsHost = 5;  // doubles per query in a partial record (sums and the Laplace shift)
 
 struct EvalLayout {
     size_t recs, bcnt, item_off, tile_off, params, partials, gpart, gspart, total;

@@ -34,7 +34,27 @@ namespace {
 
 constexpr double kInv2Pi = 0.15915494309189535;
 constexpr double kLog2E = 1.4426950408889634;
-constexpr int kAccSlots = 4;      // doubles per lane in a partial record
+constexpr double kLn2 = 0.6931471805599453;
+constexpr int kAccSlots = 5;      // doubles per lane in a partial record (slot 4: Laplace shift)
+constexpr int kSlotShift = 4;
+
+// Laplace terms exp(-s u) are summed relative to 2^m2 (an integer shift per
+// query): term = exp(-s u - m2 ln 2).  The shift follows the running maximum
+// of the exponents lazily: it starts at the first point of the item's chunk,
+// and a term more than 2^kShiftSlack above it moves it up to that term (the
+// sums so far are scaled by an exact power of two).  So no term overflows,
+// the largest term of the list is at least 1/2, and partial sums with
+// different shifts combine exactly.
+constexpr double kShiftSlack = 256.0;   // log2 units
+constexpr double kShiftClamp = 1.0e9;   // keeps shifts finite (NaN and huge exponents)
+
+// x * 2^e for an integer-valued e <= 0 or > 0, saturating (|e| beyond the
+// FP64 exponent range gives 0 or inf as the product would).
+__device__ __forceinline__ double scale2(double x, double e) {
+    return ldexp(x, (int)fmin(fmax(e, -4096.0), 4096.0));
+}
+
+__device__ __forceinline__ double clamp_shift(double m) { return fmin(fmax(m, -kShiftClamp), kShiftClamp); }
 
 template <int D, typename T>
 __device__ __forceinline__ T horner(const double (&c)[D], T x) {
@@ -122,7 +142,8 @@ template <int N>
 struct Query {
     double xi[N];     // direction
     double cF;        // Fourier: revolutions per unit of <xi,x>, s / (2 pi)
-    double cL, mL;    // Laplace: exponent = cL <xi,x> - mL (FP32: log2 units)
+    double cL, mL;    // Laplace: exponent = cL <xi,x> - mL (FP32: log2 units, mL = m2; FP64: mL = m2 ln 2)
+    double m2;        // Laplace: current shift, an integer in log2 units
     double cB;        // Bessel: z = s <xi,x>
     double gr, gi;    // backward: output cotangent
     double sigma;     // +1, or -1 when the query's list is the pair's mirror
@@ -134,8 +155,42 @@ constexpr int kSlotF = 0, kSlotL = 2, kSlotB = 3;
 
 // Contribution of one point.  Forward: per requested kernel, sum of D kbar(s u)
 // (without the 1/s); backward (one kernel): acc[a] = sum of D x_a g(kappa).
+// Whether accumulator slot k holds a Laplace sum (scaled by 2^-m2).
+template <int MASK, bool BWD, int N>
+__host__ __device__ constexpr bool lap_slot(int k) {
+    if (BWD) return MASK == kL && k < N;
+    return (MASK & kL) && k == kSlotL;
+}
+
+// Shift of the Laplace exponent in the kernel's units.
+template <int PREC>
+__device__ __forceinline__ double shift_units(double m2) { return PREC == ECT_FP32 ? m2 : m2 * kLn2; }
+
+// Move the Laplace shift up to exponent `ex` (kernel units, ex > 0 relative
+// to the current shift): the sums so far are scaled by an exact power of two.
 template <int N, int MASK, int PREC, bool BWD>
-__device__ __forceinline__ void accumulate_point(const PointT<N>& pt, const Query<N>& q, double* acc,
+__device__ __forceinline__ void raise_shift(Query<N>& q, double* acc, double ex) {
+    const double d = ceil(PREC == ECT_FP32 ? ex : ex * kLog2E);
+    q.m2 = clamp_shift(q.m2 + d);
+    q.mL = shift_units<PREC>(q.m2);
+#pragma unroll
+    for (int k = 0; k < kAccSlots; ++k)
+        if (lap_slot<MASK, BWD, N>(k)) acc[k] = scale2(acc[k], -d);
+}
+
+// Start the Laplace shift of a work item at its chunk's first point.
+template <int N, int PREC>
+__device__ __forceinline__ void init_shift(Query<N>& q, const PointT<N>& pt) {
+    double u = q.xi[0] * pt.x[0];
+#pragma unroll
+    for (int a = 1; a < N; ++a) u = fma(q.xi[a], pt.x[a], u);
+    const double c2 = PREC == ECT_FP32 ? q.cL : q.cL * kLog2E;   // log2 units
+    q.m2 = clamp_shift(ceil(u * c2));
+    q.mL = shift_units<PREC>(q.m2);
+}
+
+template <int N, int MASK, int PREC, bool BWD>
+__device__ __forceinline__ void accumulate_point(const PointT<N>& pt, Query<N>& q, double* acc,
                                                  const double* ji0c) {
     double u = q.xi[0] * pt.x[0];
 #pragma unroll
@@ -163,7 +218,17 @@ __device__ __forceinline__ void accumulate_point(const PointT<N>& pt, const Quer
         }
     }
     if constexpr ((MASK & kL) != 0) {
-        const double ex = fma(u, q.cL, -q.mL);   // <= 0
+        constexpr double slack = PREC == ECT_FP32 ? kShiftSlack : kShiftSlack * kLn2;
+        double ex = fma(u, q.cL, -q.mL);
+        // one compare per pair; the wave branches only when some lane's shift
+        // must move (rarely: at most once per factor 2^256 of its terms)
+        const uint64_t over = __builtin_amdgcn_ballot_w64(ex > slack);
+        if (over != 0) {
+            if ((over >> __lane_id()) & 1) {
+                raise_shift<N, MASK, PREC, BWD>(q, acc, ex);
+                ex = fma(u, q.cL, -q.mL);
+            }
+        }
         const double term = (PREC == ECT_FP32) ? exp2_split(ex) : exp(ex);
         if constexpr (!BWD) {
             acc[kSlotL] = fma(pt.val, term, acc[kSlotL]);
@@ -189,9 +254,27 @@ __device__ __forceinline__ void accumulate_point(const PointT<N>& pt, const Quer
 
 template <int MASK, bool BWD, int N>
 __host__ __device__ constexpr bool slot_used(int k) {
+    if (k == kSlotShift) return BWD ? MASK == kL : (MASK & kL) != 0 && MASK != kLin;
     if (BWD) return k < N;
     if (MASK == kLin) return k == 0;
     return ((MASK & kF) && (k == 0 || k == 1)) || ((MASK & kL) && k == 2) || ((MASK & kB) && k == 3);
+}
+
+// Add the sums of another part (its own Laplace shift m2o) into acc (shift
+// q.m2): both are brought to the larger shift by exact powers of two.
+template <int N, int MASK, int PREC, bool BWD>
+__device__ __forceinline__ void add_part(Query<N>& q, double* acc, const double* other, double m2o) {
+    if constexpr (slot_used<MASK, BWD, N>(kSlotShift)) {
+        const double m = fmax(q.m2, m2o);
+#pragma unroll
+        for (int k = 0; k < kAccSlots; ++k)
+            if (lap_slot<MASK, BWD, N>(k)) acc[k] = scale2(acc[k], q.m2 - m) + scale2(other[k], m2o - m);
+        q.m2 = m;
+        q.mL = shift_units<PREC>(m);
+    }
+#pragma unroll
+    for (int k = 0; k < kAccSlots; ++k)
+        if (slot_used<MASK, BWD, N>(k) && k != kSlotShift && !lap_slot<MASK, BWD, N>(k)) acc[k] += other[k];
 }
 
 // Per-query set-up shared by the evaluation and reduction kernels.
@@ -219,14 +302,7 @@ __device__ __forceinline__ void setup_query(const HybridArgs& a, int64_t img, in
     q.cB = s;
     q.cL = (PREC == ECT_FP32) ? -s * kLog2E : -s;
     q.mL = 0.0;
-    if constexpr ((MASK & kL) != 0) {
-        // m = max over the image's vertex box of -s <xi, x> (an upper bound of every exponent)
-        const ImageDesc& dsc = a.desc[img];
-        double m = 0.0;
-#pragma unroll
-        for (int k = 0; k < N; ++k) m += fmax(-s * q.xi[k] * dsc.lo[k], -s * q.xi[k] * dsc.hi[k]);
-        q.mL = active ? ((PREC == ECT_FP32) ? m * kLog2E : m) : 0.0;
-    }
+    q.m2 = 0.0;
     if constexpr (BWD) {
         if (active) {
             if (MASK == kF) {
@@ -260,27 +336,25 @@ __device__ __forceinline__ void finalize(const HybridArgs& a, const Query<N>& q,
             a.out_f[row * 2 + 1] = q.sigma * acc[kSlotF + 1] / s;
         }
         if constexpr ((MASK & kL) != 0) {
-            const double mnat = (PREC == ECT_FP32) ? q.mL / kLog2E : q.mL;
             const double shifted = -q.sigma * acc[kSlotL] / s;
             if (a.log_scale) {
                 a.out_l[row] = shifted;
-                a.log_scale[row] = mnat;
+                a.log_scale[row] = q.m2 * kLn2;
             } else {
-                const double v = shifted * exp(mnat);
+                const double v = scale2(shifted, q.m2);   // exact; inf only when HT itself overflows
                 if (!isfinite(v)) raise_error(a.err, ECT_DEVERR_OVERFLOW);
                 a.out_l[row] = v;
             }
         }
         if constexpr ((MASK & kB) != 0) a.out_b[row] = q.sigma * acc[kSlotB] / s;
     } else {
-        // G_a = sigma * sum D x_a (weighted kappa); Laplace sums carry exp(-m)
+        // G_a = sigma * sum D x_a (weighted kappa); Laplace sums carry 2^-m2
         double scale = q.sigma;
-        if constexpr (MASK == kL) scale *= q.gr * exp((PREC == ECT_FP32) ? q.mL / kLog2E : q.mL);
-        if constexpr (MASK == kB) scale *= q.gr;
+        if constexpr (MASK == kL || MASK == kB) scale *= q.gr;
         double dots = 0.0;
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            const double G = scale * acc[k];
+            const double G = (MASK == kL) ? scale2(scale * acc[k], q.m2) : scale * acc[k];
             a.grad_xi[row * N + k] = G;
             dots = fma(q.xi[k], G, dots);
         }
@@ -344,8 +418,11 @@ __device__ __forceinline__ void hybrid_block(const HybridArgs& a, int64_t item) 
     Query<N> q;
     int64_t row;
     setup_query<N, MASK, PREC, BWD>(a, img, b, qi, active, q, row);
+    if constexpr (slot_used<MASK, BWD, N>(kSlotShift)) {
+        if (c0 < c1) init_shift<N, PREC>(q, pts[c0]);
+    }
 
-    double acc[kAccSlots] = {0.0, 0.0, 0.0, 0.0};
+    double acc[kAccSlots] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t base = c0; base < c1; base += kHybridStage) {
         const int cnt = (int)min<int64_t>(kHybridStage, c1 - base);
         __syncthreads();
@@ -365,6 +442,7 @@ __device__ __forceinline__ void hybrid_block(const HybridArgs& a, int64_t item) 
                 accumulate_point<N, MASK, PREC, BWD>(s_pts[k], q, acc, a.ji0c);
         }
     }
+    acc[kSlotShift] = q.m2;
     if (wave > 0) {
 #pragma unroll
         for (int k = 0; k < kAccSlots; ++k)
@@ -373,10 +451,13 @@ __device__ __forceinline__ void hybrid_block(const HybridArgs& a, int64_t item) 
     __syncthreads();
     if (wave > 0) return;
 #pragma unroll
-    for (int w = 0; w < kHybridSplit - 1; ++w)
+    for (int w = 0; w < kHybridSplit - 1; ++w) {
+        double other[kAccSlots];
 #pragma unroll
-        for (int k = 0; k < kAccSlots; ++k)
-            if (slot_used<MASK, BWD, N>(k)) acc[k] += s_acc[w][k][lane];
+        for (int k = 0; k < kAccSlots; ++k) other[k] = slot_used<MASK, BWD, N>(k) ? s_acc[w][k][lane] : 0.0;
+        add_part<N, MASK, PREC, BWD>(q, acc, other, other[kSlotShift]);
+    }
+    acc[kSlotShift] = q.m2;
 
     if (chunks > 1) {
 #pragma unroll
@@ -444,7 +525,9 @@ __global__ void __launch_bounds__(kHybridThreads) hybrid_reduce_kernel(HybridArg
     const int64_t first = a.item_off[e] + t * chunks;
     const int64_t per = (chunks + kHybridSplit - 1) / kHybridSplit;
     const int64_t lo = min<int64_t>(chunks, wave * per), hi = min<int64_t>(chunks, lo + per);
-    double acc[kAccSlots] = {0.0, 0.0, 0.0, 0.0};
+    // running Laplace shift of this wave's chunks (below every real shift until the first)
+    q.m2 = -kShiftClamp;
+    double acc[kAccSlots] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int64_t cc = lo; cc < hi; cc += kReduceBatch) {
         double v[kReduceBatch][kAccSlots];
 #pragma unroll
@@ -452,12 +535,12 @@ __global__ void __launch_bounds__(kHybridThreads) hybrid_reduce_kernel(HybridArg
 #pragma unroll
             for (int k = 0; k < kAccSlots; ++k)
                 v[j][k] = (slot_used<MASK, BWD, N>(k) && cc + j < hi)
-                              ? a.partials[partial_index(first + cc + j, k, lane)] : 0.0;
+                              ? a.partials[partial_index(first + cc + j, k, lane)]
+                              : (k == kSlotShift ? -kShiftClamp : 0.0);
 #pragma unroll
-        for (int j = 0; j < kReduceBatch; ++j)
-#pragma unroll
-            for (int k = 0; k < kAccSlots; ++k) acc[k] += v[j][k];
+        for (int j = 0; j < kReduceBatch; ++j) add_part<N, MASK, PREC, BWD>(q, acc, v[j], v[j][kSlotShift]);
     }
+    acc[kSlotShift] = q.m2;
     if (wave > 0) {
 #pragma unroll
         for (int k = 0; k < kAccSlots; ++k)
@@ -466,10 +549,12 @@ __global__ void __launch_bounds__(kHybridThreads) hybrid_reduce_kernel(HybridArg
     __syncthreads();
     if (wave > 0 || !active) return;
 #pragma unroll
-    for (int w = 0; w < kHybridSplit - 1; ++w)
+    for (int w = 0; w < kHybridSplit - 1; ++w) {
+        double other[kAccSlots];
 #pragma unroll
-        for (int k = 0; k < kAccSlots; ++k)
-            if (slot_used<MASK, BWD, N>(k)) acc[k] += s_acc[w][k][lane];
+        for (int k = 0; k < kAccSlots; ++k) other[k] = slot_used<MASK, BWD, N>(k) ? s_acc[w][k][lane] : 0.0;
+        add_part<N, MASK, PREC, BWD>(q, acc, other, other[kSlotShift]);
+    }
     finalize<N, MASK, PREC, BWD>(a, q, row, acc);
 }
 

@@ -13,6 +13,15 @@ when the errors are independent); in addition the normwise error
 max|y - y_ref| / max|y_ref| must stay below 1e-5.  The FP64 gate is
 |y - y_ref| <= 1e-11 * S1 with S1 = sum_x |D(x) kbar_s(<xi,x>)|.
 
+Laplace values reach e^(+-900) on the large-phase workloads, so they are
+gated in shifted form: both sides are brought to the oracle's shift m_ref
+(HT e^-m_ref) and S2 is taken over the shifted terms.
+
+Gradients use the same gate per query AND per component: for dHT/dxi_a the
+terms are D x_a kappa(s u) paired with the cotangent, so a wrong small
+component cannot hide under a large one; the d/ds contribution propagates
+the component scales and the forward output's scale through its formula.
+
 S1 and S2 come from the oracle's own critical values, never from the GPU.
 """
 from __future__ import annotations
@@ -35,30 +44,109 @@ def _vertex_coords(shape_np, construction, origin=None, spacing=None):
     return ks * h + o
 
 
+def _rss(t):
+    """Root sum of squares without overflow (terms scaled by their largest)."""
+    t = np.abs(np.asarray(t, float))
+    if t.size == 0:
+        return 0.0
+    m = t.max()
+    if m == 0.0 or not np.isfinite(m):
+        return float(m)
+    return float(m * np.sqrt(((t / m) ** 2).sum()))
+
+
+class _Lists:
+    """The oracle's ordinary lists (D, coordinates) per sign vector, built once per image."""
+
+    def __init__(self, img, construction, origin, spacing):
+        self.n = img.ndim
+        _, self.od = O.critical_values(img, construction)
+        self.x = _vertex_coords(img.shape, construction, origin, spacing)
+        self.cache = {}
+
+    def __call__(self, xi_q):
+        e = sum(1 << a for a in range(self.n) if not (xi_q[a] >= 0))
+        if e not in self.cache:
+            D = self.od[:, e]
+            nz = np.nonzero(D)[0]
+            self.cache[e] = (D[nz].astype(float), self.x[nz])
+        return self.cache[e]
+
+
+def _bessel_envelope(z):
+    """|J0(z)| <= min(1, sqrt(2 / (pi |z|))): the size of J0 that an FP32
+    evaluation's absolute error scales with."""
+    az = np.abs(z)
+    return np.minimum(1.0, np.sqrt(2.0 / (np.pi * np.maximum(az, 1e-300))))
+
+
+def _forward_terms(kernel, D, z, s, m=0.0):
+    if kernel == "fourier":
+        return np.abs(D) / abs(s) * np.ones_like(z)
+    if kernel == "laplace":
+        return np.abs(D) * np.exp(-z - m) / abs(s)
+    return np.abs(D * O.ji0_array(z)) / abs(s)
+
+
 def term_scales(img, xi, kernel, s, construction=O.PRIMAL, origin=None, spacing=None, shift=None):
-    """(S1, S2) per query from the oracle's ordinary critical values."""
+    """(S1, S2) per query from the oracle's ordinary critical values.
+
+    Laplace with shift m: the terms of HT * exp(-m), i.e. the scale of the
+    oracle's shifted output."""
     img = np.asarray(img)
     xi = np.asarray(xi, float).reshape(-1, img.ndim)
-    _, od = O.critical_values(img, construction)
-    x = _vertex_coords(img.shape, construction, origin, spacing)
+    lists = _Lists(img, construction, origin, spacing)
     S1 = np.zeros(len(xi))
     S2 = np.zeros(len(xi))
     for q in range(len(xi)):
-        e = sum(1 << a for a in range(img.ndim) if not (xi[q, a] >= 0))
-        D = od[:, e]
-        nz = np.nonzero(D)[0]
-        u = x[nz] @ xi[q]
-        z = s * u
-        if kernel == "fourier":
-            t = np.abs(D[nz]) / abs(s) * np.ones_like(z)
-        elif kernel == "laplace":
-            m = 0.0 if shift is None else shift[q]
-            t = np.abs(D[nz]) * np.exp(-z - m) / abs(s)
-        else:
-            t = np.abs(D[nz] * O.ji0_array(z)) / abs(s)
+        D, xs = lists(xi[q])
+        z = s * (xs @ xi[q])
+        t = _forward_terms(kernel, D, z, s, 0.0 if shift is None else shift[q])
         S1[q] = t.sum()
-        S2[q] = np.sqrt((t * t).sum())
+        S2[q] = _rss(t)
     return S1, S2
+
+
+def grad_scales(img, xi, kernel, s, gout, construction=O.PRIMAL, origin=None, spacing=None):
+    """Error scales of the backward pass at each query, from the oracle's critical values.
+
+    Returns (S2x [q][n], S1x [q][n], S2s [q], S1s [q]): per component a the
+    root sum of squares (and sum) of the terms |D x_a kappa(s u) g| of
+    dHT/dxi_a paired with the cotangent g, and for the d/ds contribution of
+    the query (sum_a xi_a G_a - <g, HT>) / s the same scales propagated
+    through that expression (the forward output's own term scale included)."""
+    img = np.asarray(img)
+    n = img.ndim
+    xi = np.asarray(xi, float).reshape(-1, n)
+    g = np.asarray(gout)
+    if kernel == "fourier":
+        g = g.reshape(len(xi), 2)
+        gm = np.abs(g[:, 0]) + np.abs(g[:, 1])
+    else:
+        gm = np.abs(g.reshape(len(xi)))
+    lists = _Lists(img, construction, origin, spacing)
+    S2x = np.zeros((len(xi), n))
+    S1x = np.zeros((len(xi), n))
+    S2s = np.zeros(len(xi))
+    S1s = np.zeros(len(xi))
+    for q in range(len(xi)):
+        D, xs = lists(xi[q])
+        z = s * (xs @ xi[q])
+        if kernel == "fourier":
+            k = np.ones_like(z)
+        elif kernel == "laplace":
+            k = np.exp(-z)
+        else:
+            k = _bessel_envelope(z)
+        base = np.abs(D) * k * gm[q]
+        for a in range(n):
+            t = base * np.abs(xs[:, a])
+            S2x[q, a] = _rss(t)
+            S1x[q, a] = t.sum()
+        fwd = _forward_terms(kernel, D, z, s) * gm[q]
+        S2s[q] = (np.abs(xi[q]) @ S2x[q] + _rss(fwd)) / abs(s)
+        S1s[q] = (np.abs(xi[q]) @ S1x[q] + fwd.sum()) / abs(s)
+    return S2x, S1x, S2s, S1s
 
 
 def fp32_gate(y, ref, S2, normwise=True):
@@ -69,7 +157,7 @@ def fp32_gate(y, ref, S2, normwise=True):
     y = np.asarray(y)
     ref = np.asarray(ref)
     err = np.abs(y - ref)
-    tol = 1e-5 * np.abs(ref) + 8 * 2.0 ** -24 * S2
+    tol = 1e-5 * np.abs(ref) + 8 * 2.0 ** -24 * np.asarray(S2)
     ratio = float((err / np.maximum(tol, 1e-300)).max()) if err.size else 0.0
     norm = float(err.max() / max(np.abs(ref).max(), 1e-300)) if err.size else 0.0
     strict = float((err / np.maximum(np.abs(ref), 1e-300)).max()) if err.size else 0.0
@@ -78,6 +166,23 @@ def fp32_gate(y, ref, S2, normwise=True):
 
 def fp64_gate(y, ref, S1):
     err = np.abs(np.asarray(y) - np.asarray(ref))
-    tol = 1e-11 * np.maximum(S1, 1e-300)
+    tol = 1e-11 * np.maximum(np.asarray(S1), 1e-300)
     ratio = float((err / tol).max()) if err.size else 0.0
     return ratio <= 1.0, ratio
+
+
+def combine_rss(*scales):
+    """Scales of sums over independent parts (e.g. images sharing a query set)."""
+    return np.sqrt(sum(np.asarray(a, float) ** 2 for a in scales))
+
+
+def laplace_shifted(img, xi, s, construction=O.PRIMAL, origin=None, spacing=None):
+    """(HT e^-m_ref, m_ref, S2 of the shifted terms) from the oracle."""
+    ref, m = O.hybrid(img, xi, "laplace", s, construction, origin=origin, spacing=spacing, with_shift=True)
+    _, S2 = term_scales(img, xi, "laplace", s, construction, origin, spacing, shift=m)
+    return ref, m, S2
+
+
+def grad_gate(g, ref, S2, normwise=True):
+    """fp32_gate applied to every (query, component) of a gradient."""
+    return fp32_gate(np.asarray(g).ravel(), np.asarray(ref).ravel(), np.asarray(S2).ravel(), normwise)

@@ -9,7 +9,7 @@ import pytest
 from oracle import oracle as O
 from paper_2405_02256_amd import workloads as W
 
-from gates import fp32_gate, term_scales
+from gates import fp32_gate, grad_gate, grad_scales, term_scales
 
 pytestmark = pytest.mark.gpu
 
@@ -67,8 +67,11 @@ def test_any_tuning_keeps_parity(api, small, chunk, items, td, ech):
     g = np.random.default_rng(8).standard_normal((len(xi), 2))
     gxi, gs = plan.hybrid_backward(T(xi), y, T(g), "fourier", 1.0, "fp32")
     ref_xi, ref_s = O.hybrid_grad(img, xi, "fourier", 1.0, g[:, 0] + 1j * g[:, 1])
-    assert np.abs(gxi.cpu().numpy() - ref_xi).max() <= 1e-5 * np.abs(ref_xi).max()
-    assert abs(float(gs.cpu()) - ref_s) <= 1e-5 * max(abs(ref_s), np.abs(ref_xi).max())
+    S2x, _, S2s, _ = grad_scales(img, xi, "fourier", 1.0, g)
+    ok, ratio, norm, _ = grad_gate(gxi.cpu().numpy(), ref_xi, S2x)
+    assert ok, (ratio, norm)
+    ok, ratio, _, _ = fp32_gate([float(gs.cpu())], [ref_s], [np.sqrt((S2s ** 2).sum())], normwise=False)
+    assert ok, ratio
     assert plan.check() == 0
 
 

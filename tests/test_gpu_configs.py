@@ -1,13 +1,15 @@
 """GPU parity at the workloads' full sizes, in the launch configuration the
-benchmark uses; the oracle checks sampled outputs (all lists are compared in
-full for the volume)."""
+benchmark uses.  The oracle evaluates the transforms' definitions over every
+cell, so on the 128^3 volume (17M cells) it checks 128 of the 2048 ECT
+directions and 512 of the 16384 hybrid vectors; every list of the volume and
+of the sampled batch images is compared entry by entry."""
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_2405_02256_amd import workloads as W
 
-from gates import fp32_gate, term_scales
+from gates import combine_rss, fp32_gate, grad_gate, grad_scales, laplace_shifted, term_scales
 
 pytestmark = pytest.mark.gpu
 
@@ -30,12 +32,24 @@ def _cplx(y):
     return y[:, 0] + 1j * y[:, 1]
 
 
-def test_volume_128_full(api):
+@pytest.fixture(scope="module")
+def volume(api):
+    """The 128^3 volume's GPU outputs as the benchmark computes them: ECT at all 2048 directions and
+    Fourier + Laplace (log-scale) at all 16384 xi in one fused FP32 pass."""
     w = W.volume_128(3)
     vol = w.images[0]
     org = np.zeros(3)
     plan = api.Plan(T(vol), origin=org)
-    # every list, entry by entry
+    ect = plan.ect(T(w.ect_dirs), T(w.ect_thresholds)).cpu().numpy()
+    ls = torch.empty(len(w.hybrid_xi), dtype=torch.float64, device="cuda:0")
+    outs = plan.hybrid_multi(T(w.hybrid_xi), ("fourier", "laplace"), 1.0, "fp32", log_scale_out=ls)
+    assert plan.check() == 0
+    return w, plan, ect, _cplx(outs["fourier"].cpu().numpy()), outs["laplace"].cpu().numpy(), ls.cpu().numpy()
+
+
+def test_volume_128_lists(volume):
+    w, plan, _, _, _, _ = volume
+    vol = w.images[0]
     lw, od = O.critical_values(vol, O.PRIMAL)
     V = 129
     for e in range(8):
@@ -48,25 +62,38 @@ def test_volume_128_full(api):
         nz = np.nonzero(od[:, e])[0]
         lin = coords[:, 0] + V * (coords[:, 1] + V * coords[:, 2])
         assert np.array_equal(lin, nz) and np.array_equal(vals, od[nz, e]), e
-    # ECT: all 2048 directions on the GPU, 8 of them checked
-    ect = plan.ect(T(w.ect_dirs), T(w.ect_thresholds)).cpu().numpy()
-    sel = np.linspace(0, 2047, 8).astype(int)
-    assert np.array_equal(ect[sel], O.ect(vol, w.ect_dirs[sel], w.ect_thresholds, origin=org))
-    # hybrid: all 16384 xi, Fourier and Laplace (log-scale) in one fused pass
-    ls = torch.empty(len(w.hybrid_xi), dtype=torch.float64, device="cuda:0")
-    outs = plan.hybrid_multi(T(w.hybrid_xi), ("fourier", "laplace"), 1.0, "fp32", log_scale_out=ls)
-    f = _cplx(outs["fourier"].cpu().numpy())
-    lo, lsv = outs["laplace"].cpu().numpy(), ls.cpu().numpy()
-    qs = np.random.default_rng(3).choice(len(w.hybrid_xi), 10, replace=False)
-    ref_f = O.hybrid(vol, w.hybrid_xi[qs], "fourier", 1.0, origin=org)
-    _, S2 = term_scales(vol, w.hybrid_xi[qs], "fourier", 1.0, origin=org)
-    ok, ratio, norm, strict = fp32_gate(f[qs], ref_f, S2)
-    assert ok, ("fourier", ratio, norm)
-    ref_l, m = O.hybrid(vol, w.hybrid_xi[qs], "laplace", 1.0, origin=org, with_shift=True)
-    _, S2 = term_scales(vol, w.hybrid_xi[qs], "laplace", 1.0, origin=org, shift=m)
-    ok, ratio, norm, strict = fp32_gate(lo[qs] * np.exp(lsv[qs] - m), ref_l, S2)
-    assert ok, ("laplace", ratio, norm)
-    assert plan.check() == 0
+
+
+def test_volume_128_ect_128_directions(volume):
+    w, _, ect, _, _, _ = volume
+    sel = np.linspace(0, 2047, 128).astype(int)
+    assert np.array_equal(ect[sel], O.ect(w.images[0], w.ect_dirs[sel], w.ect_thresholds, origin=np.zeros(3)))
+
+
+def _volume_queries(w):
+    return np.sort(np.random.default_rng(3).choice(len(w.hybrid_xi), 512, replace=False))
+
+
+def test_volume_128_fourier_512_xi(volume):
+    w, _, _, f, _, _ = volume
+    qs = _volume_queries(w)
+    org = np.zeros(3)
+    ref = O.hybrid(w.images[0], w.hybrid_xi[qs], "fourier", 1.0, origin=org)
+    _, S2 = term_scales(w.images[0], w.hybrid_xi[qs], "fourier", 1.0, origin=org)
+    ok, ratio, norm, strict = fp32_gate(f[qs], ref, S2)
+    print(f"[volume fourier] max gate ratio {ratio:.3g}, normwise {norm:.3g}, strict {strict:.3g}")
+    assert ok, (ratio, norm, strict)
+
+
+def test_volume_128_laplace_512_xi(volume):
+    """Phases reach ~900: HT is returned as (HT e^-log_scale, log_scale) and gated in shifted form."""
+    w, _, _, _, lo, lsv = volume
+    qs = _volume_queries(w)
+    ref, m, S2 = laplace_shifted(w.images[0], w.hybrid_xi[qs], 1.0, origin=np.zeros(3))
+    assert m.max() > 700.0    # the range that overflows FP64 unshifted
+    ok, ratio, norm, strict = fp32_gate(lo[qs] * np.exp(lsv[qs] - m), ref, S2)
+    print(f"[volume laplace] max gate ratio {ratio:.3g}, normwise {norm:.3g}, strict {strict:.3g}")
+    assert ok, (ratio, norm, strict)
 
 
 def test_batch_4096_full(api):
@@ -80,6 +107,13 @@ def test_batch_4096_full(api):
         lw, od = O.critical_values(imgs[i], O.PRIMAL)
         assert c[i].tolist() == [int(np.count_nonzero(lw[:, e])) for e in range(4)]
         assert o[i].tolist() == [int(np.count_nonzero(od[:, e])) for e in range(2)]
+        V = imgs[i].shape[1] + 1
+        for kind, vals_all, L in ((0, lw, 4), (1, od, 2)):
+            for e in range(L):
+                coords, vals = plan.export(int(i), kind, e)
+                nz = np.nonzero(vals_all[:, e])[0]
+                assert np.array_equal(coords[:, 0] + V * coords[:, 1], nz), (i, kind, e)
+                assert np.array_equal(vals, vals_all[nz, e]), (i, kind, e)
     thr = w.ect_thresholds
     ect = plan.ect(T(w.ect_dirs), T(thr)).cpu().numpy().reshape(len(imgs), len(w.ect_dirs), -1)
     for i in sample:
@@ -100,6 +134,8 @@ def test_batch_4096_full(api):
 
 
 def test_diff_256_forward_backward(api):
+    """FP32 forward at sampled (image, xi), and the backward of the seeded loss sum(W * outputs)
+    summed over all 256 images at sampled xi, per query and component."""
     w = W.diff_256(5)
     imgs = w.images
     plan = api.Plan([T(im) for im in imgs])
@@ -116,20 +152,59 @@ def test_diff_256_forward_backward(api):
             _, S2 = term_scales(imgs[i], w.hybrid_xi[qs], kernel, 1.0)
             ok, ratio, norm, strict = fp32_gate(y[i, qs], ref, S2)
             assert ok, (kernel, i, ratio, norm)
-        # backward of the seeded loss sum(W * outputs) at the shared xi, summed over the 256 images
         wts = w.meta["loss_weights"] if kernel == "fourier" else w.meta["loss_weights"][..., 0]
         g = T(wts.reshape(len(imgs) * nq, -1) if kernel == "fourier" else wts.reshape(-1))
         yd = plan.hybrid(xi, kernel, 1.0, "fp32")
         gxi, gs = plan.hybrid_backward(xi, yd, g, kernel, 1.0, "fp32")
         gxi = gxi.cpu().numpy()
-        qs = rng.choice(nq, 6, replace=False)
+        qs = rng.choice(nq, 8, replace=False)
         ref = np.zeros((len(qs), 2))
+        S2x = []
         for i, im in enumerate(imgs):
-            gi = wts[i, qs] if kernel == "fourier" else wts[i, qs]
-            a, _ = O.hybrid_grad(im, w.hybrid_xi[qs], kernel, 1.0, gi)
+            a, _ = O.hybrid_grad(im, w.hybrid_xi[qs], kernel, 1.0, wts[i, qs])
             ref += a
-        err = np.abs(gxi[qs] - ref).max() / np.abs(ref).max()
-        assert err < 1e-5, (kernel, err)
+            S2x.append(grad_scales(im, w.hybrid_xi[qs], kernel, 1.0, wts[i, qs])[0])
+        ok, ratio, norm, strict = grad_gate(gxi[qs], ref, combine_rss(*S2x))
+        print(f"[diff_256 {kernel} grad] max gate ratio {ratio:.3g}, normwise {norm:.3g}")
+        assert ok, (kernel, ratio, norm, strict)
+
+
+@pytest.mark.parametrize("kernel", ["fourier", "laplace"])
+def test_diff_256_grad_s_against_oracle(api, kernel):
+    """d/ds of the loss at the workload's shape against the oracle: the loss weights are kept on 32
+    sampled (image, xi) pairs and zero elsewhere (rows with a zero cotangent contribute exactly 0),
+    so the oracle evaluates only those pairs; grad_xi of the sampled xi is checked with it."""
+    w = W.diff_256(5)
+    imgs = w.images
+    plan = api.Plan([T(im) for im in imgs])
+    nq = len(w.hybrid_xi)
+    rng = np.random.default_rng(55)
+    pick_i = rng.choice(len(imgs), 32, replace=False)
+    pick_q = rng.choice(nq, 32, replace=False)
+    full = w.meta["loss_weights"] if kernel == "fourier" else w.meta["loss_weights"][..., :1]
+    wts = np.zeros_like(full)
+    wts[pick_i, pick_q] = full[pick_i, pick_q]
+    g = T(wts.reshape(len(imgs) * nq, -1) if kernel == "fourier" else wts.reshape(-1))
+    xi = T(w.hybrid_xi)
+    y = plan.hybrid(xi, kernel, 1.0, "fp32")
+    gxi, gs = plan.hybrid_backward(xi, y, g, kernel, 1.0, "fp32")
+    gxi, gs = gxi.cpu().numpy(), float(gs.cpu())
+    rgs = 0.0
+    rgx = np.zeros((32, 2))
+    S2s, S2x = [], []
+    for k, (i, q) in enumerate(zip(pick_i, pick_q)):
+        gq = wts[i, q:q + 1] if kernel == "fourier" else wts[i, q:q + 1, 0]
+        a, b = O.hybrid_grad(imgs[i], w.hybrid_xi[q:q + 1], kernel, 1.0, gq)
+        rgs += b
+        rgx[k] = a[0]
+        sx, _, ss, _ = grad_scales(imgs[i], w.hybrid_xi[q:q + 1], kernel, 1.0, gq)
+        S2s.append(ss[0])
+        S2x.append(sx[0])
+    ok, ratio, _, _ = fp32_gate([gs], [rgs], [np.sqrt(np.sum(np.square(S2s)))], normwise=False)
+    print(f"[diff_256 {kernel} grad_s] {gs:.12g} vs {rgs:.12g}, gate ratio {ratio:.3g}")
+    assert ok, (gs, rgs, ratio)
+    ok, ratio, norm, strict = grad_gate(gxi[pick_q], rgx, np.array(S2x))
+    assert ok, (ratio, norm, strict)
 
 
 def test_diff_256_finite_differences_fp64(api):

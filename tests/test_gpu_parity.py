@@ -10,7 +10,7 @@ import pytest
 from oracle import oracle as O
 from paper_2405_02256_amd import workloads as W
 
-from gates import fp32_gate, fp64_gate, term_scales
+from gates import combine_rss, fp32_gate, fp64_gate, grad_gate, grad_scales, laplace_shifted, term_scales
 
 pytestmark = pytest.mark.gpu
 
@@ -241,12 +241,12 @@ def test_ect_ragged_batch_per_image_thresholds_and_dirs(api):
 
 
 def test_ect_grf512_full_config(api):
+    """All 360 x 256 ECT values of the 512 x 512 field, element by element."""
     w = W.grf_512(2, n_xi=8)
     img = w.images[0]
     plan = api.Plan(T(img))
     got = plan.ect(T(w.ect_dirs), T(w.ect_thresholds)).cpu().numpy()
-    sel = np.arange(0, 360, 9)
-    assert np.array_equal(got[sel], O.ect(img, w.ect_dirs[sel], w.ect_thresholds))
+    assert np.array_equal(got, O.ect(img, w.ect_dirs, w.ect_thresholds))
 
 
 def test_ect_large_threshold_count(api):
@@ -295,17 +295,57 @@ def test_hybrid_small_binary(api, kernel, precision):
         assert ok, ratio
 
 
-@pytest.mark.parametrize("kernel", ["fourier", "laplace", "bessel"])
-def test_hybrid_grf512_sampled(api, kernel):
+@pytest.fixture(scope="module")
+def grf512_step(api):
+    """The 512 x 512 field's step as the benchmark launches it: ECT and the fused Fourier + Laplace +
+    Bessel pass in one call (ECT workgroups inside the hybrid launch), FP32."""
     w = W.grf_512(2)
     img = w.images[0]
     plan = api.Plan(T(img))
-    y = _cplx(plan.hybrid(T(w.hybrid_xi), kernel, 1.0, "fp32").cpu().numpy(), kernel)
-    sel = np.random.default_rng(9).choice(len(w.hybrid_xi), 48, replace=False)
-    ref = O.hybrid(img, w.hybrid_xi[sel], kernel, 1.0, with_shift=False)
-    S1, S2 = term_scales(img, w.hybrid_xi[sel], kernel, 1.0)
-    ok, ratio, norm, strict = fp32_gate(y[sel], ref, S2)
+    plan.set_tuning(0, 2048, 2, 1)
+    ect, outs = plan.ect_hybrid_multi(T(w.ect_dirs), T(w.ect_thresholds), T(w.hybrid_xi),
+                                      ("fourier", "laplace", "bessel"), 1.0, "fp32")
+    assert plan.check() == 0
+    return w, plan, ect.cpu().numpy(), {k: v.cpu().numpy() for k, v in outs.items()}
+
+
+def test_grf512_step_ect_full(grf512_step):
+    w, _, ect, _ = grf512_step
+    assert np.array_equal(ect, O.ect(w.images[0], w.ect_dirs, w.ect_thresholds))
+
+
+@pytest.mark.parametrize("kernel", ["fourier", "laplace", "bessel"])
+def test_grf512_step_hybrid_full(grf512_step, kernel):
+    """All 4096 xi of every kernel against the oracle, per query (Laplace in shifted form)."""
+    w, _, _, outs = grf512_step
+    img, xi = w.images[0], w.hybrid_xi
+    y = _cplx(outs[kernel], kernel)
+    if kernel == "laplace":
+        ref, m, S2 = laplace_shifted(img, xi, 1.0)
+        y = y * np.exp(-m)
+    else:
+        ref = O.hybrid(img, xi, kernel, 1.0)
+        _, S2 = term_scales(img, xi, kernel, 1.0)
+    ok, ratio, norm, strict = fp32_gate(y, ref, S2)
+    print(f"[grf512 {kernel}] max gate ratio {ratio:.3g}, normwise {norm:.3g}, strict {strict:.3g}")
     assert ok, (ratio, norm, strict)
+
+
+def test_grf512_step_backward_full(grf512_step):
+    """The step's Fourier backward at all 4096 xi against the oracle gradient, per query and component,
+    and d/ds."""
+    w, plan, _, outs = grf512_step
+    img, xi = w.images[0], w.hybrid_xi
+    g = np.random.default_rng(22).standard_normal((len(xi), 2))
+    gx, gs = plan.hybrid_backward(T(xi), T(outs["fourier"]), T(g), "fourier", 1.0, "fp32")
+    gx, gs = gx.cpu().numpy(), float(gs.cpu())
+    rgx, rgs = O.hybrid_grad(img, xi, "fourier", 1.0, g)
+    S2x, _, S2s, _ = grad_scales(img, xi, "fourier", 1.0, g)
+    ok, ratio, norm, strict = grad_gate(gx, rgx, S2x)
+    print(f"[grf512 grad] max gate ratio {ratio:.3g}, normwise {norm:.3g}")
+    assert ok, (ratio, norm, strict)
+    ok, ratio, _, _ = fp32_gate([gs], [rgs], [np.sqrt((S2s ** 2).sum())], normwise=False)
+    assert ok, (gs, rgs, ratio)
 
 
 @pytest.mark.parametrize("construction", [O.PRIMAL, O.DUAL])
@@ -445,13 +485,27 @@ def test_backward_against_oracle_gradient(api, kernel):
     rows = g.reshape(len(imgs), 40, *g.shape[1:])
     rgx = np.zeros((40, 2))
     rgs = 0.0
+    S2x, S2s = [], []
     for i, im in enumerate(imgs):
         a, b = O.hybrid_grad(im, xi, kernel, 1.0, rows[i])
         rgx += a
         rgs += b
-    err = np.abs(gxi - rgx).max() / max(np.abs(rgx).max(), 1e-300)
-    assert err < 1e-5, err
-    assert abs(gs - rgs) <= 1e-5 * max(abs(rgs), np.abs(rgx).max()), (gs, rgs)
+        sx, _, ss, _ = grad_scales(im, xi, kernel, 1.0, rows[i])
+        S2x.append(sx)
+        S2s.append(ss)
+    ok, ratio, norm, strict = grad_gate(gxi, rgx, combine_rss(*S2x))
+    assert ok, (ratio, norm, strict)
+    ok, ratio, _, _ = fp32_gate([gs], [rgs], [np.sqrt((combine_rss(*S2s) ** 2).sum())], normwise=False)
+    assert ok, (gs, rgs, ratio)
+    # FP64 backward: every component within 1e-11 of its terms' sum
+    y64 = plan.hybrid(T(xi), kernel, 1.0, "fp64")
+    gx64, gs64 = plan.hybrid_backward(T(xi), y64, T(g), kernel, 1.0, "fp64")
+    S1x = sum(grad_scales(im, xi, kernel, 1.0, rows[i])[1] for i, im in enumerate(imgs))
+    S1s = sum(grad_scales(im, xi, kernel, 1.0, rows[i])[3].sum() for i, im in enumerate(imgs))
+    ok, ratio = fp64_gate(gx64.cpu().numpy(), rgx, S1x)
+    assert ok, ratio
+    ok, ratio = fp64_gate([float(gs64.cpu())], [rgs], [S1s])
+    assert ok, ratio
 
 
 def test_autograd_function_matches_finite_differences(api):
@@ -479,6 +533,108 @@ def test_autograd_function_matches_finite_differences(api):
             assert abs(fd - float(xi.grad[q, a])) <= 1e-2 * max(1.0, abs(fd))
     fds = (loss(xi0, 1.0 + h) - loss(xi0, 1.0 - h)) / (2 * h)
     assert abs(fds - float(s.grad)) <= 1e-2 * max(1.0, abs(fds))
+
+
+@pytest.mark.parametrize("kernel", ["fourier", "laplace"])
+def test_autograd_function_fp32_against_oracle_gradient(api, kernel):
+    """The FP32 autograd path (float32 xi, learnable s) against the oracle gradient, per query and
+    component, and against central differences of the oracle forward."""
+    rng = np.random.default_rng(910)
+    imgs = [W.binary_field(rng, (40, 40), 3.0) for _ in range(3)]
+    plan = api.Plan([T(im) for im in imgs])
+    xi0 = W.polar_vectors(rng, 24, 0.05, 0.5, axis_gap=0.05).astype(np.float32)
+    xi = torch.from_numpy(xi0).to(dev()).requires_grad_(True)
+    s = torch.tensor(0.9, dtype=torch.float64, device=dev(), requires_grad=True)
+    y = api.HybridTransform.apply(xi, s, plan, kernel, "fp32")
+    wts = rng.standard_normal(tuple(y.shape))
+    (y * T(wts)).sum().backward()
+    gx, gsv = xi.grad.cpu().numpy().astype(np.float64), float(s.grad.cpu())
+    assert xi.grad.dtype == torch.float32
+    x64 = xi0.astype(np.float64)
+    wr = wts.reshape(len(imgs), 24, *wts.shape[1:])
+    rgx = np.zeros((24, 2))
+    rgs = 0.0
+    S2x, S2s = [], []
+    for i, im in enumerate(imgs):
+        a, b = O.hybrid_grad(im, x64, kernel, 0.9, wr[i])
+        rgx += a
+        rgs += b
+        sx, _, ss, _ = grad_scales(im, x64, kernel, 0.9, wr[i])
+        S2x.append(sx)
+        S2s.append(ss)
+    ok, ratio, norm, strict = grad_gate(gx, rgx, combine_rss(*S2x))   # float32 rounding: within 1e-5 rel
+    assert ok, (ratio, norm, strict)
+    ok, ratio, _, _ = fp32_gate([gsv], [rgs], [np.sqrt((combine_rss(*S2s) ** 2).sum())], normwise=False)
+    assert ok, (gsv, rgs, ratio)
+
+    def loss(xv, sv):
+        tot = 0.0
+        for i, im in enumerate(imgs):
+            r = O.hybrid(im, xv, kernel, sv)
+            r = np.stack([r.real, r.imag], -1) if kernel == "fourier" else r
+            tot += float((r * wr[i]).sum())
+        return tot
+
+    h = 1e-3
+    for q in range(0, 24, 6):
+        for a in range(2):
+            xp, xm = x64.copy(), x64.copy()
+            xp[q, a] += h
+            xm[q, a] -= h
+            fd = (loss(xp, 0.9) - loss(xm, 0.9)) / (2 * h)
+            assert abs(fd - gx[q, a]) <= 1e-2 * max(1.0, abs(fd)), (q, a, fd, gx[q, a])
+    fds = (loss(x64, 0.9 + h) - loss(x64, 0.9 - h)) / (2 * h)
+    assert abs(fds - gsv) <= 1e-2 * max(1.0, abs(fds)), (fds, gsv)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_laplace_off_centre_object_large_xi(api, precision):
+    """An object far from the centre of a 256 x 256 frame at |xi| = 4: every exponent -s<xi,x> of its
+    points lies hundreds of units below the frame's extreme vertex, so the shift must follow the
+    list's own maximum.  With a log-scale output every query is checked in shifted form; without one,
+    queries whose HT is finite are returned unshifted and exactly those that overflow raise the flag.
+    Shared and ragged query sets."""
+    from paper_2405_02256_amd import _native as N
+    rng = np.random.default_rng(1301)
+    img = np.zeros((256, 256), np.uint8)
+    img[216:256, 0:40] = W.binary_field(rng, (40, 40), 3.0)   # the corner of largest axis 1, smallest axis 0
+    img[236:256, 0:20] = 1                  # a solid block at the frame's corner: some HT overflow FP64
+    ang = rng.uniform(0, 2 * np.pi, 96)
+    xi = 4.0 * np.stack([np.cos(ang), np.sin(ang)], -1)
+    xi[:5] = [[4.0, 0.0], [0.0, 4.0], [-4.0, 0.0], [0.0, -4.0], [2.8284271247461903, -2.8284271247461903]]
+    plan = api.Plan(T(img))
+    ref, m, S2 = laplace_shifted(img, xi, 1.0)
+    S1, _ = term_scales(img, xi, "laplace", 1.0, shift=m)
+    offs = np.array([0, len(xi)], np.int64)
+    for ragged in (False, True):
+        kw = dict(offsets=T(offs)) if ragged else {}
+        out, ls = plan.hybrid(T(xi), "laplace", 1.0, precision, log_scale=True, **kw)
+        out, ls = out.cpu().numpy(), ls.cpu().numpy()
+        assert np.isfinite(out).all() and np.isfinite(ls).all()
+        # the shift follows the list: the shifted output is O(1), not 0
+        assert (np.abs(out) > 0).all() or (np.abs(ref) == 0).any()
+        y = out * np.exp(ls - m)
+        if precision == "fp32":
+            ok, ratio, norm, strict = fp32_gate(y, ref, S2)
+            assert ok, (ragged, ratio, norm, strict)
+        else:
+            ok, ratio = fp64_gate(y, ref, S1)
+            assert ok, (ragged, ratio)
+        assert plan.check() == 0
+        # without a log-scale output
+        full = plan.hybrid(T(xi), "laplace", 1.0, precision, **kw).cpu().numpy()
+        flags = plan.check()
+        loght = np.log(np.abs(ref) + 1e-300) + m           # log |HT|
+        finite, over = loght < 705.0, loght > 712.0        # (the few in between may round either way)
+        assert finite.sum() > 80 and over.sum() >= 3
+        yf = full[finite] * np.exp(-m[finite])
+        if precision == "fp32":
+            ok, ratio, _, _ = fp32_gate(yf, ref[finite], S2[finite])
+        else:
+            ok, ratio = fp64_gate(yf, ref[finite], S1[finite])
+        assert ok, (ragged, ratio)
+        assert not np.isfinite(full[over]).any()
+        assert flags & N.DEVERR_OVERFLOW
 
 
 @pytest.mark.parametrize("construction", [O.PRIMAL, O.DUAL])
