@@ -1,4 +1,5 @@
-"""Error gates for floating-point parity against the FP64 oracle.
+"""Error gates for floating-point parity against the FP64 oracle.  TEST INFRASTRUCTURE ONLY
+(used by the tests and by the cpu_baseline leg of bench.py, like the oracle itself).
 
 Hybrid transforms are sums of many terms of both signs that cancel heavily
 (their condition number sum|term| / |sum| reaches 10^4 on binary fields), so
@@ -186,3 +187,19 @@ def laplace_shifted(img, xi, s, construction=O.PRIMAL, origin=None, spacing=None
 def grad_gate(g, ref, S2, normwise=True):
     """fp32_gate applied to every (query, component) of a gradient."""
     return fp32_gate(np.asarray(g).ravel(), np.asarray(ref).ravel(), np.asarray(S2).ravel(), normwise)
+
+
+def g9_stats(y, ref, S2, S1=None) -> dict:
+    """Error statistics of a set of results against the oracle: the worst ratio
+    to the per-query gate (<= 1 passes), the normwise error
+    max|err| / max|ref|, the strict per-query relative error and, with S1,
+    the largest condition number S1 / |ref| of the set."""
+    y = np.asarray(y).ravel()
+    ref = np.asarray(ref).ravel()
+    S2 = np.asarray(S2, float).ravel()
+    ok, ratio, norm, strict = fp32_gate(y, ref, S2)
+    out = {"checked": int(y.size), "max_gate_ratio": ratio, "normwise": norm, "strict_rel_max": strict,
+           "pass": bool(ok)}
+    if S1 is not None:
+        out["cond_max"] = float((np.asarray(S1, float).ravel() / np.maximum(np.abs(ref), 1e-300)).max())
+    return out

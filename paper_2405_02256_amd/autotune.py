@@ -144,9 +144,11 @@ def time_call(fn, reps: int = 10, warmup: int = 2, trials: int = 5) -> float:
 def tune(plan, ect_dirs=None, ect_thresholds=None, hybrid_xi=None, kernels=("fourier",), s=1.0,
          precision="fp32", ect_offsets=None, hybrid_offsets=None, backward_kernel=None, grad_out=None,
          cache: Cache | None = None, use_cache=True, reps=10, timer=None, dev_key: str | None = None,
-         combined: bool = False) -> Tuning:
+         combined: bool = False, log_scale: bool = False) -> Tuning:
     """Sweep the knobs for this plan's ECT and hybrid calls, apply the fastest
-    to the plan and return it (from the cache when the workload was seen)."""
+    to the plan and return it (from the cache when the workload was seen).
+    log_scale: the Laplace output is taken with a log-scale output, as the
+    timed calls then make it (large phases would overflow without one)."""
     import torch
     timer = timer or time_call
     cache = cache or Cache()
@@ -160,6 +162,8 @@ def tune(plan, ect_dirs=None, ect_thresholds=None, hybrid_xi=None, kernels=("fou
     sig = signature(plan, e_rows, M, h_rows, tuple(kernels) if hq is not None else (), precision, backward_kernel)
     if combined:
         sig += "|one-launch"
+    if log_scale:
+        sig += "|log-scale"
     dev = dev_key or device_key()
     if use_cache:
         hit = cache.get(dev, sig)
@@ -181,15 +185,18 @@ def tune(plan, ect_dirs=None, ect_thresholds=None, hybrid_xi=None, kernels=("fou
             ect_t[(td, ch)] = timer(run, reps)
         best.ect_dirs_per_group, best.ect_chunks = pick(ect_t)
         timings["ect"] = {f"{k[0]}/{k[1]}": v for k, v in ect_t.items()}
+    ls = None
+    if hq is not None and h_rows > 0 and log_scale and "laplace" in kernels:
+        ls = torch.empty(h_rows, dtype=torch.float64, device=plan.device)
     if hq is not None and h_rows > 0:
         hy_t = {}
         kernels = tuple(kernels)
         for items in HYBRID_ITEM_CANDIDATES:
             plan.set_tuning(0, items, best.ect_dirs_per_group, best.ect_chunks)
             if len(kernels) > 1:
-                outs = plan.hybrid_multi(hq, kernels, s, precision)
+                outs = plan.hybrid_multi(hq, kernels, s, precision, log_scale_out=ls)
             else:
-                outs = {kernels[0]: plan.hybrid(hq, kernels[0], s, precision)}
+                outs = {kernels[0]: plan.hybrid(hq, kernels[0], s, precision, log_scale_out=ls)}
             fwd = outs.get(backward_kernel) if backward_kernel else None
             if fwd is not None and grad_out is None:
                 grad_out = torch.ones_like(fwd)
@@ -198,9 +205,9 @@ def tune(plan, ect_dirs=None, ect_thresholds=None, hybrid_xi=None, kernels=("fou
 
             def run(outs=outs, fwd=fwd):
                 if len(kernels) > 1:
-                    plan.hybrid_multi(hq, kernels, s, precision, outs=outs)
+                    plan.hybrid_multi(hq, kernels, s, precision, outs=outs, log_scale_out=ls)
                 else:
-                    plan.hybrid(hq, kernels[0], s, precision, out=outs[kernels[0]])
+                    plan.hybrid(hq, kernels[0], s, precision, out=outs[kernels[0]], log_scale_out=ls)
                 if fwd is not None:
                     plan.hybrid_backward(hq, fwd, grad_out, backward_kernel, s, precision, grad_xi=gxi, grad_s=gs)
             hy_t[items] = timer(run, reps)
@@ -210,7 +217,7 @@ def tune(plan, ect_dirs=None, ect_thresholds=None, hybrid_xi=None, kernels=("fou
         co_t = {}
         for td, ch in ECT_CANDIDATES:
             plan.set_tuning(0, best.hybrid_target_items, td, ch)
-            eo, ho = plan.ect_hybrid_multi(eq, ect_thresholds, hq, kernels, s, precision)
+            eo, ho = plan.ect_hybrid_multi(eq, ect_thresholds, hq, kernels, s, precision, log_scale_out=ls)
             fwd = ho.get(backward_kernel) if backward_kernel else None
             if fwd is not None and grad_out is None:
                 grad_out = torch.ones_like(fwd)
@@ -218,7 +225,8 @@ def tune(plan, ect_dirs=None, ect_thresholds=None, hybrid_xi=None, kernels=("fou
             gs = torch.empty((), dtype=torch.float64, device=plan.device)
 
             def run(eo=eo, ho=ho, fwd=fwd):
-                plan.ect_hybrid_multi(eq, ect_thresholds, hq, kernels, s, precision, ect_out=eo, outs=ho)
+                plan.ect_hybrid_multi(eq, ect_thresholds, hq, kernels, s, precision, ect_out=eo, outs=ho,
+                                      log_scale_out=ls)
                 if fwd is not None:
                     plan.hybrid_backward(hq, fwd, grad_out, backward_kernel, s, precision, grad_xi=gxi, grad_s=gs)
             co_t[(td, ch)] = timer(run, reps)

@@ -24,6 +24,7 @@ def hip():
         _hip.hipEventSynchronize.argtypes = [ctypes.c_void_p]
         _hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
         _hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        _hip.hipGetLastError.restype = ctypes.c_int
     return _hip
 
 
@@ -44,6 +45,9 @@ class Event:
     def elapsed_ms(self, later: "Event") -> float:
         ms = ctypes.c_float(0.0)
         if hip().hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(self.handle), ctypes.c_void_p(later.handle)) != 0:
+            # e.g. an event that was never recorded; clear the runtime's last
+            # error so that the next HIP call (torch's included) does not report it
+            hip().hipGetLastError()
             raise RuntimeError("hipEventElapsedTime failed")
         return float(ms.value)
 

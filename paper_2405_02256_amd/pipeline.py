@@ -130,7 +130,8 @@ class Step:
         return AT.tune(self.plan, self.ect_q, self.ect_thr, self.hy_q, self.kernels, self.s, self.precision,
                        backward_kernel=self.backward_kernel,
                        grad_out=self.grad_out if self.backward_kernel is not None else None,
-                       cache=cache, use_cache=use_cache, reps=reps, combined=self.combined)
+                       cache=cache, use_cache=use_cache, reps=reps, combined=self.combined,
+                       log_scale=self.log_scale_laplace)
 
     def capture(self) -> "torch.cuda.CUDAGraph":
         """Record run() into a graph (after one eager run sized every workspace).

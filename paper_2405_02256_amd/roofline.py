@@ -14,8 +14,8 @@ fused pass; then per kernel:
 
   Fourier   phase u*s/(2 pi) 1, reduction to [0,1) 2 (floor, sub), cvt 1,
             sin 4, cos 4, two (cvt + fma) 4                          -> 16
-  Laplace   exponent fma 1, split 2 (floor, sub), cvt 1, exp2 4, cvt 1,
-            cvt-to-int 1, ldexp 1, fma 1                              -> 12
+  Laplace   exponent fma 1, shift test 1, split 2 (floor, sub), cvt 1,
+            exp2 4, cvt 1, cvt-to-int 1, ldexp 1, fma 1               -> 13
   Bessel    |z| < 8: z 1, v 2, degree-9 FP64 Horner 10, scale 1, cvt 2,
             sign 1, fma 1                                             -> 18
             |z| >= 8: z 1, cvt 1, rcp 4, w 2, two degree-5 Horner 12,
@@ -23,12 +23,15 @@ fused pass; then per kernel:
             sign 1, cvt + fma 2                                       -> 45
   Fourier backward: phase and reduction 3, cvt 1, sin 4, cos 4, cvt 2,
             cotangent combine 3, n fmas                               -> 17 + n
+  Laplace backward: the forward term 12 (its fma replaced by a mul),
+            n fmas                                                    -> 12 + n
   ECT       projection 2n-1, bin guess 6 (sub, mul, ceil, max, min, cvt),
             fix-up compares 2, LDS add 1                              -> 2n + 8
   Radon     as ECT plus one equality compare (the point or open-ray
             bin), over classical and ordinary points                  -> 2n + 9
-Precompute is bounded by HBM: bytes = pixels read once + 32 B per list entry
-written + list offsets.  The exact representations are priced against HBM with
+Precompute is bounded by HBM: bytes = pixels read once + each list entry
+written as packed coordinates and value (2n + 2 bytes: uint16 per axis and an
+int16 value) + list offsets.  The exact representations are priced against HBM with
 the bytes the operation cannot avoid: 32 B per critical point read and 12 B
 per output entry (T and E) written.
 """
@@ -40,14 +43,17 @@ VALU_SLOT_RATE = 256 * 64 * 2.4e9  # lane-instruction slots per second
 
 
 def slots_per_pair(kind: str, n: int, small_fraction: float = 1.0) -> float:
-    """kind: 'fourier', 'laplace', 'bessel', '+'-joined fused kernels, 'fourier_bwd' or 'ect'."""
+    """kind: 'fourier', 'laplace', 'bessel', '+'-joined fused kernels, 'fourier_bwd', 'laplace_bwd',
+    'ect' or 'radon'."""
     if kind == "ect":
         return 2 * n + 8
     if kind == "radon":
         return 2 * n + 9
     if kind == "fourier_bwd":
         return (2 * n - 1) + 17 + n
-    per = {"fourier": 16.0, "laplace": 12.0,
+    if kind == "laplace_bwd":
+        return (2 * n - 1) + 12 + n
+    per = {"fourier": 16.0, "laplace": 13.0,
            "bessel": small_fraction * 18.0 + (1.0 - small_fraction) * 45.0}
     parts = kind.split("+")
     if any(p not in per for p in parts):

@@ -9,7 +9,7 @@ import pytest
 from oracle import oracle as O
 from paper_2405_02256_amd import workloads as W
 
-from gates import combine_rss, fp32_gate, grad_gate, grad_scales, laplace_shifted, term_scales
+from oracle.gates import combine_rss, fp32_gate, grad_gate, grad_scales, laplace_shifted, term_scales
 
 pytestmark = pytest.mark.gpu
 

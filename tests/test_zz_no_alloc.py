@@ -10,7 +10,7 @@ import pytest
 from oracle import oracle as O
 from paper_2405_02256_amd import workloads as W
 
-from gates import fp32_gate, term_scales
+from oracle.gates import fp32_gate, term_scales
 
 pytestmark = pytest.mark.gpu
 
