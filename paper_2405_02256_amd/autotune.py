@@ -9,7 +9,9 @@ chunked partial sums):
   fill the 256 compute units but cost more partial sums, long ones the reverse;
 * the number of directions one ECT workgroup evaluates per streamed point and,
   for shared direction sets, the number of parts each list is split into so
-  that several workgroups share one group of directions.  When the ECT runs
+  that several workgroups share one group of directions; the automatic
+  setting (0, 0) also lets many-image batches with short lists take the
+  direction-parallel kernel.  When the ECT runs
   inside the hybrid launch (ect_hybrid_eval_multi) these are swept again on
   that combined call: there the ECT work is hidden beside the hybrid work
   items and list parts only add a chunk-sum launch, so the best setting
@@ -33,7 +35,8 @@ from . import _native as N
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_2405_02256_amd", "tuning.json")
 # (directions per workgroup, list parts; 0 = automatic)
-ECT_CANDIDATES = ((1, 1), (2, 1), (4, 1), (8, 1), (1, 0), (2, 0), (4, 0), (8, 0), (1, 2), (1, 4), (2, 2), (2, 4))
+ECT_CANDIDATES = ((1, 1), (2, 1), (4, 1), (8, 1), (1, 0), (2, 0), (4, 0), (8, 0), (1, 2), (1, 4), (2, 2), (2, 4),
+                  (0, 0))
 HYBRID_ITEM_CANDIDATES = (512, 1024, 2048, 4096, 8192, 16384)
 
 

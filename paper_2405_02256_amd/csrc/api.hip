@@ -227,6 +227,7 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
     L.err = o; o = align_up(o + 16, kAlign);   // uint32 error word, uint32 spare, uint64 run counter
     L.desc = o; o = align_up(o + sizeof(ImageDesc) * ni, kAlign);
     L.tile_start = o; o = align_up(o + sizeof(int64_t) * (ni + 1), kAlign);
+    L.tile_img = o; o = align_up(o + sizeof(int32_t) * tiles, kAlign);
     L.list_off = o; o = align_up(o + sizeof(int64_t) * (int64_t)(ni + 1) * NL, kAlign);
     // single pass: tile aggregates and totals of 64-tile groups; three passes:
     // tile counts (int32) and their prefixes (int64).  The size does not
@@ -285,9 +286,21 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
     p->precompute_grid = std::min<int64_t>(per_cu * p->num_cus, 64 * 64);
     if (n == 2) p->precompute_grid_flat = precompute_slots_per_cu(n, batch->construction, batch->dtype, true) * p->num_cus;
 
+    std::vector<int32_t> timg;
+    try {
+        timg.resize((size_t)tiles);
+    } catch (...) {
+        ect_plan_destroy(p);
+        return ECT_E_NOMEM;
+    }
+    for (int i = 0; i < ni; ++i)
+        for (int64_t t = tstart[i]; t < tstart[i + 1]; ++t) timg[(size_t)t] = i;
     e = hipMemcpyAsync(p->ws + L.desc, desc.data(), sizeof(ImageDesc) * ni, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->ws + L.tile_start, tstart.data(), sizeof(int64_t) * (ni + 1), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->ws + L.tile_img, timg.data(), sizeof(int32_t) * (size_t)tiles, hipMemcpyHostToDevice,
+                           stream);
     if (e == hipSuccess) e = launch_precompute(*p, true, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->h_list_off, p->ws + L.list_off, sizeof(int64_t) * (int64_t)(ni + 1) * NL,
@@ -359,6 +372,7 @@ struct ThresholdSetup {
     int td;
     int64_t chunks;
     bool direct;
+    bool batch;     // ect_batch_kernel after one bucketing of the shared set
     int64_t direct_groups;
     int threads;
     EvalLayout L;
@@ -389,9 +403,23 @@ static ect_status threshold_setup(const Plan& p, const ect_query_set& dirs, cons
     // short lists: one-wave workgroups (more blocks in flight per compute unit)
     S->threads = mean_list(p, 0, num_classical(p.ndim)) <= kEctSmallList ? 64 : kEctThreads;
     S->direct = dirs.offsets == nullptr;
+    S->batch = false;
     S->chunks = 1;
     S->direct_groups = 0;
     S->L = EvalLayout{};
+    // many images with short lists and a shared direction set: lanes own
+    // directions (ect_batch_kernel), after one bucketing of the set; chosen
+    // automatically, or by the autotuner through the automatic setting
+    const int64_t batch_blocks = (int64_t)p.num_images << p.ndim;
+    if (S->direct && !radon && p.tune_ect_dirs_per_group == 0 && p.tune_ect_chunks == 0 &&
+        M <= kBatchMaxThresholds && batch_blocks >= 2 * (int64_t)std::max(p.num_cus, 1) &&
+        mean_list(p, 0, num_classical(p.ndim)) <= kEctSmallList) {
+        S->direct = false;
+        S->batch = true;
+        layout_ect(p, dirs, td, &S->L);
+        S->L.grid = batch_blocks;
+        return ECT_OK;
+    }
     if (S->direct) {
         S->direct_groups = (dirs.count + td - 1) / td;
         const int64_t groups = (int64_t)p.num_images * S->direct_groups;
@@ -457,14 +485,16 @@ static ect_status threshold_eval(ect_plan plan, ect_query_set dirs, const double
     hipError_t e = hipSuccess;
     if (plan->last_prep.ws == ws) plan->last_prep.valid = false;   // buckets or chunk sums overwrite it
     if (!S.direct) {
+        // the batch kernel needs the buckets only, not the bucketed kernel's work list
         e = launch_prepare(p.ndim, dirs, p.num_images, false, (uint32_t*)(p.ws + p.lay.err), (void*)(w + S.L.recs),
                            (int32_t*)(w + S.L.bcnt), (const int64_t*)(p.ws + p.lay.list_off), 0, num_lists(p.ndim),
-                           S.td, 0, 0, (int64_t*)(w + S.L.item_off), (int64_t*)(w + S.L.tile_off),
-                           (int64_t*)(w + S.L.params), stream);
+                           S.td, 0, 0, S.batch ? nullptr : (int64_t*)(w + S.L.item_off),
+                           S.batch ? nullptr : (int64_t*)(w + S.L.tile_off),
+                           S.batch ? nullptr : (int64_t*)(w + S.L.params), stream);
     }
     if (e == hipSuccess) {
         const EctArgs a = threshold_args(p, dirs, thresholds, M, thresholds_per_image, out, w, S);
-        e = launch_ect(p.ndim, a, S.L.grid, S.direct_groups, radon, stream);
+        e = S.batch ? launch_ect_batch(p.ndim, a, stream) : launch_ect(p.ndim, a, S.L.grid, S.direct_groups, radon, stream);
     }
     return from_hip(e);
 }

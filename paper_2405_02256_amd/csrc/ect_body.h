@@ -39,6 +39,19 @@ __device__ __forceinline__ int stage_thresholds(const EctArgs& a, int64_t img, d
 //   kBinPoint   every j with t_j == u (the point u itself).
 constexpr int kBinClosed = 0, kBinOpen = 1, kBinPoint = 2;
 
+// First j with t_j >= u among the M non-decreasing thresholds in LDS (M if
+// none): an arithmetic guess for evenly spaced thresholds (inv = (M - 1) /
+// (t_{M-1} - t_0), or 0), corrected against the stored values, so any
+// non-decreasing array gives the exact bin.
+__device__ __forceinline__ int bin_closed(double uu, const double* s_thr, int M, double t0, double inv) {
+    double g = ceil((uu - t0) * inv);
+    g = fmin(fmax(g, 0.0), (double)M);
+    int j = (int)g;
+    while (j > 0 && s_thr[j - 1] >= uu) --j;
+    while (j < M && s_thr[j] < uu) ++j;
+    return j;
+}
+
 // Stream points [p0, p1) of one list and add sign * (critical value) into the
 // histogram of every direction dd with use[dd].
 template <int N, int MODE, int TD>
@@ -66,12 +79,7 @@ __device__ __forceinline__ void accumulate_list(const PointT<N>* __restrict__ pt
             for (int dd = 0; dd < TD; ++dd) {
                 if (!use[dd]) continue;
                 const double uu = project<N>(xi[dd], pt[u].x);
-                double g = ceil((uu - t0) * inv);
-                g = fmin(fmax(g, 0.0), (double)M);
-                int j = (int)g;
-                // first j with t_j >= u
-                while (j > 0 && s_thr[j - 1] >= uu) --j;
-                while (j < M && s_thr[j] < uu) ++j;
+                int j = bin_closed(uu, s_thr, M, t0, inv);
                 if constexpr (MODE == kBinClosed) {
                     if (j < M) atomicAdd(&s_hist[dd * M + j], val);
                 } else if constexpr (MODE == kBinOpen) {

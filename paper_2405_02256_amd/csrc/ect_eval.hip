@@ -114,6 +114,177 @@ __global__ void __launch_bounds__(kEctWideThreads) ect_direct_kernel(EctArgs a, 
     ect_direct_block<N, RADON>(a, groups, blockIdx.x);
 }
 
+// Shared direction sets over many images with short lists: one workgroup per
+// (image, sign vector b).  The set was bucketed by sign vector once (records
+// in input order within a bucket); the workgroup takes its bucket's
+// directions kBatchDirs at a time and gives each of them 256 / D lanes (D the
+// pass's directions rounded up to a power of two), which split the list
+// between them.  So every lane works even when a list holds a few dozen
+// points, where streaming the list across the lanes for a few directions
+// leaves most of them idle.
+//
+// The list is staged in LDS a stage of 256 points at a time (one coalesced
+// load per thread, the next stage's loads in flight while this one is
+// binned).  A lane bins the canonical projection of each of its points on its
+// direction: the arithmetic guess for evenly spaced thresholds is checked
+// against the two thresholds around it with one LDS read (the thresholds sit
+// between -inf and +inf sentinels), and only a wrong guess searches; the
+// critical value is added into the direction's LDS histogram (integer
+// atomics; rows at an odd stride, so that neighbouring directions' bins fall
+// in different banks).  The histograms are then prefix-summed in place by
+// eight threads per row (a sequential scan of a segment, then a scan of the
+// eight segment totals), and written out row by row with consecutive threads
+// on consecutive thresholds.  Same bins as the other threshold kernels, so the
+// rows are the same integers.
+template <int N>
+__global__ void __launch_bounds__(kBatchThreads) ect_batch_kernel(EctArgs a) {
+    extern __shared__ __align__(16) char smem[];
+    constexpr int B = 1 << N;
+    constexpr int kSeg = kBatchThreads / kBatchDirs;   // threads per histogram row in the scan
+    const int M = a.M;
+    const int MS = M | 1;
+    double* s_tp = (double*)smem;                                          // [M + 2]
+    int32_t* s_hist = (int32_t*)(smem + batch_hist_offset(M));             // [kBatchDirs][MS]
+    __shared__ double s_px[kBatchThreads * N];
+    __shared__ int32_t s_pv[kBatchThreads];
+    __shared__ double s_xi[kBatchDirs][kMaxDim];
+    __shared__ int64_t s_row[kBatchDirs];
+    __shared__ int s_valid[kBatchDirs];
+
+    const int tid = threadIdx.x;
+    const int64_t img = blockIdx.x / B;
+    const int b = (int)(blockIdx.x % B);
+    const int64_t qn = a.bcnt[b];
+    if (qn == 0) return;
+    const QRecT<N>* recs = (const QRecT<N>*)a.recs + (int64_t)b * a.count;
+    const int64_t p0 = a.list_off[img * a.NL + b], p1 = a.list_off[(img + 1) * a.NL + b];
+    const PointT<N>* __restrict__ pts = list_points<N>(a.points, a.capacity, b);
+
+    // the list's first stage of points is requested with the thresholds
+    PointT<N> nxt{};
+    if (p0 + tid < p1) nxt = pts[p0 + tid];
+    const double* thr = a.thresholds + (a.thr_per_image ? img * M : 0);
+    int bad = 0;
+    for (int j = tid; j < M; j += kBatchThreads) {
+        const double v = thr[j];
+        s_tp[j + 1] = v;
+        if (j > 0 && !(v >= thr[j - 1])) bad = 1;
+        if (!isfinite(v)) bad = 1;
+    }
+    if (tid == 0) {
+        s_tp[0] = -INFINITY;
+        s_tp[M + 1] = INFINITY;
+    }
+    bad = __syncthreads_or(bad);
+    if (bad && tid == 0 && b == 0) raise_error(a.err, ECT_DEVERR_THRESHOLDS);
+    const double t0 = s_tp[1], t1 = s_tp[M];
+    const double inv = (M > 1 && t1 > t0) ? (double)(M - 1) / (t1 - t0) : 0.0;
+    const int seg = (M + kSeg - 1) / kSeg;
+    const int rows_per_pass = M <= kBatchThreads ? kBatchThreads / M : 1;
+    const int wrow = M <= kBatchThreads ? tid / M : 0;
+    const int wj = M <= kBatchThreads ? tid - wrow * M : tid;
+
+    for (int64_t q0 = 0; q0 < qn; q0 += kBatchDirs) {
+        const int nd = (int)min<int64_t>(kBatchDirs, qn - q0);
+        if (tid < kBatchDirs) {
+            int ok = 0;
+            int64_t row = -1;
+            if (tid < nd) {
+                const QRecT<N> r = recs[q0 + tid];
+                row = img * a.count + (r.code >> 1);
+                ok = 1;
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    s_xi[tid][c] = r.v[c];
+                    ok &= isfinite(r.v[c]) ? 1 : 0;
+                }
+                if (!ok && img == 0) raise_error(a.err, ECT_DEVERR_NONFINITE);
+            }
+            s_row[tid] = row;
+            s_valid[tid] = ok && !bad;
+        }
+        {
+            int4* h4 = (int4*)s_hist;
+            const int n4 = kBatchDirs * MS / 4;   // kBatchDirs is a multiple of 4
+            for (int j = tid; j < n4; j += kBatchThreads) h4[j] = make_int4(0, 0, 0, 0);
+        }
+        // lanes per direction: D = nd rounded up to a power of two
+        int D = 1;
+        while (D < nd) D <<= 1;
+        const int d = tid & (D - 1);
+        const int lanes = kBatchThreads / D;
+        const int slice = tid / D;
+        __syncthreads();
+        const bool active = d < nd && s_valid[d];
+        double xi[N];
+#pragma unroll
+        for (int c = 0; c < N; ++c) xi[c] = s_xi[d][c];
+        int32_t* hist = s_hist + d * MS;
+        for (int64_t base = p0; base < p1; base += kBatchThreads) {
+            const int cnt = (int)min<int64_t>(kBatchThreads, p1 - base);
+            if (tid < cnt) {
+#pragma unroll
+                for (int c = 0; c < N; ++c) s_px[tid * N + c] = nxt.x[c];
+                s_pv[tid] = (int32_t)nxt.val;
+            }
+            __syncthreads();
+            // next stage, or after the last one the list's start for the next pass
+            const int64_t nb = base + kBatchThreads;
+            const int64_t src = nb < p1 ? nb + tid : (q0 + kBatchDirs < qn ? p0 + tid : p1);
+            if (src < p1) nxt = pts[src];
+            if (active) {
+                for (int k = slice; k < cnt; k += lanes) {
+                    double x[N];
+#pragma unroll
+                    for (int c = 0; c < N; ++c) x[c] = s_px[k * N + c];
+                    const double u = project<N>(xi, x);
+                    double g = ceil((u - t0) * inv);
+                    g = fmin(fmax(g, 0.0), (double)M);
+                    int j = (int)g;                         // candidate: t_{j-1} < u <= t_j
+                    const double lo = s_tp[j], hi = s_tp[j + 1];
+                    if (!((lo < u) & (u <= hi))) {          // a guess off by a threshold or more (rare)
+                        while (j > 0 && s_tp[j] >= u) --j;
+                        while (j < M && s_tp[j + 1] < u) ++j;
+                    }
+                    if (j < M) atomicAdd(&hist[j], s_pv[k]);
+                }
+            }
+            __syncthreads();
+        }
+        // inclusive prefix sums in place: kSeg threads per row, a segment each
+        {
+            const int dd = tid / kSeg, part = tid % kSeg;
+            const int j0 = min(M, part * seg), j1 = min(M, j0 + seg);
+            int32_t* h = s_hist + dd * MS;
+            int32_t run = 0;
+            if (dd < nd)
+                for (int j = j0; j < j1; ++j) {
+                    run += h[j];
+                    h[j] = run;
+                }
+            int32_t off = run;   // inclusive scan of the segment totals within the row's kSeg lanes
+#pragma unroll
+            for (int o = 1; o < kSeg; o <<= 1) {
+                const int32_t v = __shfl_up(off, o, kSeg);
+                if (part >= o) off += v;
+            }
+            off -= run;
+            if (dd < nd && off != 0)
+                for (int j = j0; j < j1; ++j) h[j] += off;
+        }
+        __syncthreads();
+        // rows out: consecutive threads on consecutive thresholds
+        if (wj < M && wrow < rows_per_pass)
+            for (int dd = wrow; dd < nd; dd += rows_per_pass) {
+                int32_t* out = a.out + s_row[dd] * M;
+                const bool ok = s_valid[dd];
+                for (int j = wj; j < M; j += (M <= kBatchThreads ? M : kBatchThreads))
+                    out[j] = ok ? s_hist[dd * MS + j] : 0;
+            }
+        __syncthreads();
+    }
+}
+
 // Sum of the chunk histograms of one direction (one wave per output row) and
 // the inclusive prefix over thresholds; for the Radon transform (arrays = 2)
 // plus the sum of the chunks' point values.
@@ -174,6 +345,23 @@ hipError_t launch_ect_chunk_sum(const EctArgs& a, int64_t grid, int64_t groups, 
     const int64_t rows = (grid / a.chunks) * a.dirs_per_group;
     hipLaunchKernelGGL(ect_chunk_sum_kernel, dim3((unsigned)rows), dim3(64), 0, stream, a, groups, 1);
     return hipGetLastError();
+}
+
+hipError_t launch_ect_batch(int ndim, const EctArgs& a, hipStream_t stream) {
+    const int64_t grid = (int64_t)a.num_images << ndim;
+    if (grid <= 0) return hipSuccess;
+    const size_t shmem = batch_ect_lds(a.M);
+    hipError_t e = stage_mark(ECT_STAGE_ECT, false, stream);
+    if (e != hipSuccess) return e;
+    if (ndim == 2)
+        hipLaunchKernelGGL(ect_batch_kernel<2>, dim3((unsigned)grid), dim3(kBatchThreads), shmem, stream, a);
+    else if (ndim == 3)
+        hipLaunchKernelGGL(ect_batch_kernel<3>, dim3((unsigned)grid), dim3(kBatchThreads), shmem, stream, a);
+    else
+        hipLaunchKernelGGL(ect_batch_kernel<4>, dim3((unsigned)grid), dim3(kBatchThreads), shmem, stream, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return stage_mark(ECT_STAGE_ECT, true, stream);
 }
 
 hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, int64_t direct_groups, bool radon,

@@ -71,6 +71,7 @@ struct PlanLayout {
     size_t err;             // uint32 device error word, uint32 spare, uint64 run counter
     size_t desc;            // ImageDesc[num_images]
     size_t tile_start;      // int64[num_images + 1]
+    size_t tile_img;        // int32[num_tiles]: the image each precompute tile belongs to
     size_t list_off;        // int64[(num_images + 1) * NL]: start of image i in list l
     size_t status;          // uint64 ordered-compaction status words: tiles, group totals, carries (x NL)
     size_t points;          // PointT<n>[NL * capacity]

@@ -40,7 +40,8 @@ constexpr int64_t kSmallMaxRows = 65536;   // query sets bucketed by a single wo
 constexpr int kSmallMaxEntries = 4096;     // (image, bucket) entries counted in LDS there
 
 // Bucket the queries by sign vector and build the work list (one launch for
-// small sets; fill + bucket + work list otherwise).
+// small sets; fill + bucket + work list otherwise).  item_off == nullptr:
+// buckets only (ECT sets, not the hybrid path's shared-set kernel).
 hipError_t launch_prepare(int ndim, const ect_query_set& qs, int num_images, bool hybrid, uint32_t* err,
                           void* recs, int32_t* bcnt, const int64_t* list_off, int list_base, int NL, int qtile,
                           int64_t chunk, int64_t capacity, int64_t* item_off, int64_t* tile_off, int64_t* params,
@@ -80,6 +81,22 @@ struct EctArgs {
 
 // Mean classical list length up to which one-wave workgroups evaluate the ECT.
 constexpr double kEctSmallList = 2048.0;
+
+// Shared direction sets over many images with short lists (ect_batch_kernel):
+// one workgroup per (image, sign vector) after the set was bucketed once.
+constexpr int kBatchThreads = 256;
+constexpr int kBatchDirs = 16;          // directions of a bucket per pass
+constexpr int kBatchMaxThresholds = 256;
+// Dynamic LDS of ect_batch_kernel: the thresholds between two sentinels, then
+// (16-byte aligned) the histograms of one pass, rows at an odd stride.
+__host__ __device__ constexpr size_t batch_hist_offset(int M) {
+    return (sizeof(double) * (size_t)(M + 2) + 15) / 16 * 16;
+}
+__host__ __device__ constexpr size_t batch_ect_lds(int M) {
+    return batch_hist_offset(M) + sizeof(int32_t) * (size_t)kBatchDirs * (size_t)(M | 1);
+}
+// a.recs / a.bcnt hold the shared set bucketed by sign vector (launch_prepare).
+hipError_t launch_ect_batch(int ndim, const EctArgs& a, hipStream_t stream);
 
 // direct_groups > 0: shared query set, num_images * direct_groups * a.chunks
 // workgroups of ect_direct_kernel (no bucketing), then, with a.chunks > 1, the

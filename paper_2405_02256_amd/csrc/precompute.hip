@@ -73,6 +73,10 @@ template <typename T>
 __device__ __forceinline__ int32_t px_load(const T* __restrict__ img, int64_t i) {
     return (int32_t)img[i];
 }
+template <typename T>
+__device__ __forceinline__ int32_t px_load(const T* __restrict__ img, uint32_t i) {
+    return (int32_t)img[i];
+}
 
 // Pixels a vertex's star depends on: primal, the 2^N pixels k_a - 1 + d_a
 // (d in {0,1}^N); dual, the 3^N pixels k + t (t in {-1,0,1}^N).  Coordinates
@@ -193,6 +197,29 @@ __device__ __forceinline__ void vertex_values(const int32_t* p, const ImageDesc&
     for (int e = 0; e < (1 << (N - 1)); ++e) D[e] = L[e ^ full] - L[e];
 }
 
+// Two-axis primal images, the common case, with the shared subexpressions
+// written out: the four pixels around vertex k (a = (k0-1, k1-1), b = (k0,
+// k1-1), c = (k0-1, k1), d = (k0, k1), clamped into the image), the vertex
+// value (min of the four), the four edge values (min of the two pixels on
+// either side) and the four squares, masked where the cell does not exist;
+// then L(eps) = vertex - edge along -eps_0 - edge along -eps_1 + square
+// towards (-eps_0, -eps_1), and D(eps) = L(-eps) - L(eps).
+__device__ __forceinline__ void vertex_values_2p(int32_t a, int32_t b, int32_t c, int32_t d, int k0, int k1, int N0,
+                                                 int N1, int32_t* L, int32_t* D) {
+    const bool hm0 = k0 >= 1, hp0 = k0 <= N0 - 1, hm1 = k1 >= 1, hp1 = k1 <= N1 - 1;
+    const int32_t v = min(min(a, b), min(c, d));
+    const int32_t exm = hm0 ? min(a, c) : 0, exp_ = hp0 ? min(b, d) : 0;   // edges towards -x, +x
+    const int32_t eym = hm1 ? min(a, b) : 0, eyp = hp1 ? min(c, d) : 0;    // edges towards -y, +y
+    const int32_t sa = (hm0 && hm1) ? a : 0, sb = (hp0 && hm1) ? b : 0;
+    const int32_t sc = (hm0 && hp1) ? c : 0, sd = (hp0 && hp1) ? d : 0;
+    L[0] = v - exm - eym + sa;    // eps = (+, +): the cells towards -x, -y
+    L[1] = v - exp_ - eym + sb;   // eps = (-, +)
+    L[2] = v - exm - eyp + sc;    // eps = (+, -)
+    L[3] = v - exp_ - eyp + sd;   // eps = (-, -)
+    D[0] = L[3] - L[0];
+    D[1] = L[2] - L[1];
+}
+
 // Once per plan: clear the error word, the run counter and the status words.
 __global__ void reset_kernel(uint32_t* __restrict__ err, uint64_t* __restrict__ run_ctr, uint64_t* __restrict__ status,
                              int64_t nstatus) {
@@ -258,18 +285,13 @@ struct TileValues {
 
 template <int N, int CONS, typename T>
 __device__ __forceinline__ void tile_values(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
-                                            const int64_t* __restrict__ tile_start, int32_t num_images,
+                                            const int32_t* __restrict__ tile_img, int32_t num_images,
                                             int64_t tile, TileValues<N>& tv,
                                             int32_t (*s_cnt)[kPrecomputeThreads / 64][TileValues<N>::NL]) {
     constexpr int NC = TileValues<N>::NC, NO = TileValues<N>::NO, NL = TileValues<N>::NL;
     constexpr int J = TileValues<N>::J;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // image owning this tile: last i with tile_start[i] <= tile
-    int lo = 0, hi = num_images - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (tile_start[mid] <= tile) lo = mid; else hi = mid - 1;
-    }
+    const int lo = tile_img[tile];   // the image owning this tile
     tv.d = descs[lo];
     tv.img_id = lo;
     const ImageDesc& d = tv.d;
@@ -304,12 +326,26 @@ __device__ __forceinline__ void tile_values(const T* __restrict__ pixels, const 
             tv.kk[j][2] = (int)r2;
             tv.kk[j][3] = (int)q2;
         }
-        load_neighbourhood<N, CONS, T>(img, d, tv.kk[j], nb[j]);
+        if constexpr (N == 2 && CONS == ECT_PRIMAL) {
+            // 32-bit offsets from the image base (images hold fewer than 2^31 pixels)
+            const int k0 = tv.kk[j][0], k1 = tv.kk[j][1];
+            const int c0 = max(k0 - 1, 0), c1 = min(k0, d.dims[0] - 1);
+            const int r0 = max(k1 - 1, 0) * d.dims[0], r1 = min(k1, d.dims[1] - 1) * d.dims[0];
+            nb[j][0] = px_load(img, (uint32_t)(r0 + c0));
+            nb[j][1] = px_load(img, (uint32_t)(r0 + c1));
+            nb[j][2] = px_load(img, (uint32_t)(r1 + c0));
+            nb[j][3] = px_load(img, (uint32_t)(r1 + c1));
+        } else {
+            load_neighbourhood<N, CONS, T>(img, d, tv.kk[j], nb[j]);
+        }
     }
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         int32_t L[NC], D[NO];
-        vertex_values<N, CONS>(nb[j], d, tv.kk[j], L, D);
+        if constexpr (N == 2 && CONS == ECT_PRIMAL)
+            vertex_values_2p(nb[j][0], nb[j][1], nb[j][2], nb[j][3], tv.kk[j][0], tv.kk[j][1], d.N[0], d.N[1], L, D);
+        else
+            vertex_values<N, CONS>(nb[j], d, tv.kk[j], L, D);
 #pragma unroll
         for (int l = 0; l < NC; ++l) tv.vals[j][l] = valid[j] ? L[l] : 0;
 #pragma unroll
@@ -463,7 +499,7 @@ __device__ __forceinline__ void prep_worklist(const QueryPrep& prep, uint64_t* p
 template <int N, int CONS, typename T, bool FLAT>
 __global__ void __launch_bounds__(kPrecomputeThreads)
 classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
-                 const int64_t* __restrict__ tile_start, int32_t num_images, int64_t num_tiles,
+                 const int32_t* __restrict__ tile_img, int32_t num_images, int64_t num_tiles,
                  uint32_t* __restrict__ err, uint64_t* __restrict__ run_ctr, uint64_t* __restrict__ status,
                  uint64_t* __restrict__ gstatus, int64_t* __restrict__ list_off, PointT<N>* __restrict__ points,
                  int64_t capacity, QueryPrep prep, uint64_t* __restrict__ prep_word) {
@@ -496,7 +532,7 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
     const int64_t tile = (int64_t)blockIdx.x - (with_prep ? kPrepGroups : 0);
     if (tid == 0) s_run = __hip_atomic_load(run_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     TileValues<N> tv;
-    tile_values<N, CONS, T>(pixels, descs, tile_start, num_images, tile, tv, s_cnt);
+    tile_values<N, CONS, T>(pixels, descs, tile_img, num_images, tile, tv, s_cnt);
     __syncthreads();
     const uint64_t run = s_run;
     const uint64_t parity = (run & 1ull) ? kParityBit : 0ull;
@@ -557,14 +593,14 @@ classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ des
 template <int N, int CONS, typename T>
 __global__ void __launch_bounds__(kPrecomputeThreads)
 tile_count_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
-                  const int64_t* __restrict__ tile_start, int32_t num_images, int32_t* __restrict__ counts,
+                  const int32_t* __restrict__ tile_img, int32_t num_images, int32_t* __restrict__ counts,
                   uint32_t* __restrict__ packed) {
     constexpr int NL = TileValues<N>::NL;
     constexpr int J = TileValues<N>::J;
     __shared__ int32_t s_cnt[J][kPrecomputeThreads / 64][NL];
     const int64_t tile = blockIdx.x;
     TileValues<N> tv;
-    tile_values<N, CONS, T>(pixels, descs, tile_start, num_images, tile, tv, s_cnt);
+    tile_values<N, CONS, T>(pixels, descs, tile_img, num_images, tile, tv, s_cnt);
     __syncthreads();
     constexpr int W = kPrecomputeThreads / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -607,6 +643,112 @@ tile_count_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ de
     }
 }
 
+// Two-axis primal images, count pass of three-pass plans.  Same counts and
+// packed slots as tile_count_kernel, with the work per vertex cut down: a
+// wave owns 256 consecutive vertices of the tile (lane l, round j: vertex
+// wave * 256 + j * 64 + l), so the wave's entries of a list are contiguous in
+// the tile's order and their positions come from the wave's ballot masks
+// (scalar bit counts) and the earlier waves' totals; the vertex coordinates
+// advance by 64 per round instead of a division per vertex; the cell values
+// have their shared subexpressions written out (vertex_values_2p).
+template <typename T>
+__global__ void __launch_bounds__(kPrecomputeThreads)
+tile_count_2p_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
+                     const int32_t* __restrict__ tile_img, int32_t num_images, int32_t* __restrict__ counts,
+                     uint32_t* __restrict__ packed) {
+    constexpr int NL = 6, J = 4, W = kPrecomputeThreads / 64;
+    static_assert(tile_verts(2) == J * kPrecomputeThreads, "four rounds of 64 vertices per wave");
+    __shared__ int32_t s_tot[W][NL];
+    const int64_t tile = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const ImageDesc& d = descs[tile_img[tile]];
+    const T* __restrict__ img = pixels + d.pixel_offset;
+    const int64_t nvert = d.nvert;
+    const int V0 = d.V[0], N0 = d.N[0], N1 = d.N[1], W0 = d.dims[0], H1 = d.dims[1];
+    const int64_t first = (tile - d.tile_start) * tile_verts(2) + wave * (J * 64);
+    const double invV0 = 1.0 / (double)V0;
+    uint32_t r;
+    const uint32_t q = udiv((uint32_t)(first + lane), (uint32_t)V0, invV0, &r);
+    int k0 = (int)r, k1 = (int)q;
+    uint32_t r64;
+    const int q64 = (int)udiv(64u, (uint32_t)V0, invV0, &r64);
+    int32_t px[J][4];
+    int kk0[J], kk1[J];
+    bool valid[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        valid[j] = first + j * 64 + lane < nvert;
+        kk0[j] = valid[j] ? k0 : 0;
+        kk1[j] = valid[j] ? k1 : 0;
+        const int c0 = max(kk0[j] - 1, 0), c1 = min(kk0[j], W0 - 1);
+        const int r0 = max(kk1[j] - 1, 0) * W0, r1 = min(kk1[j], H1 - 1) * W0;
+        px[j][0] = px_load(img, (uint32_t)(r0 + c0));
+        px[j][1] = px_load(img, (uint32_t)(r0 + c1));
+        px[j][2] = px_load(img, (uint32_t)(r1 + c0));
+        px[j][3] = px_load(img, (uint32_t)(r1 + c1));
+        k0 += (int)r64;
+        k1 += q64;
+        if (k0 >= V0) {
+            k0 -= V0;
+            ++k1;
+        }
+    }
+    int32_t vals[J][NL];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        int32_t L[4], D[2];
+        vertex_values_2p(px[j][0], px[j][1], px[j][2], px[j][3], kk0[j], kk1[j], N0, N1, L, D);
+#pragma unroll
+        for (int l = 0; l < 4; ++l) vals[j][l] = valid[j] ? L[l] : 0;
+#pragma unroll
+        for (int l = 0; l < 2; ++l) vals[j][4 + l] = valid[j] ? D[l] : 0;
+    }
+    // the wave's totals per list
+    int32_t tot[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) tot[l] = 0;
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int l = 0; l < NL; ++l) tot[l] += __popcll(__builtin_amdgcn_ballot_w64(vals[j][l] != 0));
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+        if (lane == l) s_tot[wave][l] = tot[l];
+    __syncthreads();
+    if (wave == 0 && lane < NL) {
+        int32_t t = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) t += s_tot[w][lane];
+        counts[tile * NL + lane] = t;
+    }
+    if (!packed) return;
+    uint32_t* __restrict__ slots = packed + tile * NL * (int64_t)tile_verts(2);
+    const uint64_t below = (1ull << lane) - 1ull;
+    int32_t base[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        int32_t b = 0;
+        for (int w = 0; w < wave; ++w) b += s_tot[w][l];
+        base[l] = __builtin_amdgcn_readfirstlane(b);
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const uint32_t local = (uint32_t)(wave * (J * 64) + j * 64 + lane);
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const bool nz = vals[j][l] != 0;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(nz);
+            if (m != 0) {
+                if (nz) {
+                    const uint32_t pos = (uint32_t)(base[l] + __popcll(m & below));
+                    slots[(uint32_t)(l * tile_verts(2)) + pos] = ((uint32_t)vals[j][l] << kPackShift) | local;
+                }
+                base[l] += __popcll(m);
+            }
+        }
+    }
+}
+
 // Three-pass plans with packed entries: place tile t's entries (list l's
 // count from tile_count_kernel, in vertex order) at the list's prefix.  The
 // tile's counts and prefixes are read once; its entries of all lists are then
@@ -614,7 +756,7 @@ tile_count_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ de
 // from the index.
 template <int N>
 __global__ void __launch_bounds__(kPrecomputeThreads)
-tile_copy_kernel(const ImageDesc* __restrict__ descs, const int64_t* __restrict__ tile_start, int32_t num_images,
+tile_copy_kernel(const ImageDesc* __restrict__ descs, const int32_t* __restrict__ tile_img, int32_t num_images,
                  const int32_t* __restrict__ counts, const int64_t* __restrict__ prefix,
                  const uint32_t* __restrict__ packed, PointT<N>* __restrict__ points, int64_t capacity) {
     constexpr int NL = TileValues<N>::NL;
@@ -626,12 +768,7 @@ tile_copy_kernel(const ImageDesc* __restrict__ descs, const int64_t* __restrict_
         s_start[threadIdx.x + 1] = counts[tile * NL + threadIdx.x];
         s_base[threadIdx.x] = prefix[tile * NL + threadIdx.x];
     }
-    int lo = 0, hi = num_images - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tile_start[mid] <= tile) lo = mid; else hi = mid - 1;
-    }
-    const ImageDesc d = descs[lo];
+    const ImageDesc d = descs[tile_img[tile]];
     __syncthreads();
     if (threadIdx.x == 0) {
         s_start[0] = 0;
@@ -796,14 +933,14 @@ tile_block_apply_kernel(const int32_t* __restrict__ counts, int64_t num_tiles, c
 template <int N, int CONS, typename T>
 __global__ void __launch_bounds__(kPrecomputeThreads)
 tile_write_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
-                  const int64_t* __restrict__ tile_start, int32_t num_images, const int64_t* __restrict__ prefix,
+                  const int32_t* __restrict__ tile_img, int32_t num_images, const int64_t* __restrict__ prefix,
                   PointT<N>* __restrict__ points, int64_t capacity) {
     constexpr int NL = TileValues<N>::NL;
     __shared__ int32_t s_cnt[TileValues<N>::J][kPrecomputeThreads / 64][NL];
     __shared__ int64_t s_base[NL];
     const int64_t tile = blockIdx.x;
     TileValues<N> tv;
-    tile_values<N, CONS, T>(pixels, descs, tile_start, num_images, tile, tv, s_cnt);
+    tile_values<N, CONS, T>(pixels, descs, tile_img, num_images, tile, tv, s_cnt);
     if (threadIdx.x < NL) s_base[threadIdx.x] = prefix[tile * NL + threadIdx.x];
     __syncthreads();
     if ((threadIdx.x >> 6) == 0) tile_offsets<NL, TileValues<N>::J>(s_cnt);
@@ -837,6 +974,7 @@ hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream, const Que
     const T* px = (const T*)p.pixels;
     const ImageDesc* desc = (const ImageDesc*)(p.ws + L.desc);
     const int64_t* ts = (const int64_t*)(p.ws + L.tile_start);
+    const int32_t* ti = (const int32_t*)(p.ws + L.tile_img);
     int64_t* lo = (int64_t*)(p.ws + L.list_off);
     PointT<N>* pts = (PointT<N>*)(p.ws + L.points);
     if (single) {
@@ -844,11 +982,11 @@ hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream, const Que
             // one more workgroup when it buckets the queries (the caller checked that it fits)
             const int64_t grid = L.num_tiles + (qp.vecs ? 1 : 0);
             hipLaunchKernelGGL((classify_compact<N, CONS, T, true>), dim3((unsigned)grid), dim3(kPrecomputeThreads),
-                               0, stream, px, desc, ts, p.num_images, L.num_tiles, err, run_ctr, status, gstatus, lo,
+                               0, stream, px, desc, ti, p.num_images, L.num_tiles, err, run_ctr, status, gstatus, lo,
                                pts, L.capacity, qp, prep_word);
         } else {
             hipLaunchKernelGGL((classify_compact<N, CONS, T, false>), dim3((unsigned)L.num_tiles),
-                               dim3(kPrecomputeThreads), 0, stream, px, desc, ts, p.num_images, L.num_tiles, err,
+                               dim3(kPrecomputeThreads), 0, stream, px, desc, ti, p.num_images, L.num_tiles, err,
                                run_ctr, status, gstatus, lo, pts, L.capacity, QueryPrep{}, prep_word);
         }
     } else {
@@ -866,8 +1004,12 @@ hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream, const Que
         }
         // packed entries (small pixel types only: their values fit the packed field)
         uint32_t* packed = (L.packed_bytes > 0 && sizeof(T) < 4) ? (uint32_t*)(p.ws + L.packed) : nullptr;
-        hipLaunchKernelGGL((tile_count_kernel<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads), 0,
-                           stream, px, desc, ts, p.num_images, counts, packed);
+        if constexpr (N == 2 && CONS == ECT_PRIMAL)
+            hipLaunchKernelGGL((tile_count_2p_kernel<T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads), 0,
+                               stream, px, desc, ti, p.num_images, counts, packed);
+        else
+            hipLaunchKernelGGL((tile_count_kernel<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads),
+                               0, stream, px, desc, ti, p.num_images, counts, packed);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         constexpr int NLc = TileValues<N>::NL;
@@ -884,10 +1026,10 @@ hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream, const Que
         if (e != hipSuccess) return e;
         if (packed)
             hipLaunchKernelGGL((tile_copy_kernel<N>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads), 0,
-                               stream, desc, ts, p.num_images, counts, prefix, packed, pts, L.capacity);
+                               stream, desc, ti, p.num_images, counts, prefix, packed, pts, L.capacity);
         else
             hipLaunchKernelGGL((tile_write_kernel<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads),
-                               0, stream, px, desc, ts, p.num_images, prefix, pts, L.capacity);
+                               0, stream, px, desc, ti, p.num_images, prefix, pts, L.capacity);
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -399,7 +399,7 @@ prepare_small_kernel(const double* __restrict__ vecs, const int64_t* __restrict_
     const int groups = offsets ? num_images : 1;
     const int E = groups * B;
     const int64_t EW = (int64_t)num_images * B;     // work-list entries
-    const bool stage_np = EW <= kSmallMaxEntries;
+    const bool stage_np = EW <= kSmallMaxEntries && item_off != nullptr;
     const int tid = threadIdx.x;
     // the first batch of query rows is requested before anything else
     double v[kPrepRows][N];
@@ -446,6 +446,7 @@ prepare_small_kernel(const double* __restrict__ vecs, const int64_t* __restrict_
     }
     __syncthreads();
     for (int i = tid; i < E; i += 1024) bcnt[i] = s_cnt[i];
+    if (!item_off) return;   // buckets only (the batch ECT kernel needs no work list)
     build_worklist(num_images, B, list_base, NL, offsets == nullptr ? 1 : 0, s_cnt, list_off,
                    stage_np ? s_np : nullptr, qtile, chunk0, capacity, err, item_off, tile_off, params);
 }
@@ -482,6 +483,7 @@ hipError_t launch_prepare_typed(const ect_query_set& qs, int num_images, bool hy
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    if (!item_off) return hipSuccess;   // buckets only
     hipLaunchKernelGGL(worklist_kernel, dim3(1), dim3(1024), 0, stream, num_images, B, list_base, NL,
                        shared ? 1 : 0, bcnt, list_off, qtile, chunk, capacity, err, item_off, tile_off, params);
     return hipGetLastError();
