@@ -91,6 +91,7 @@ typedef enum { ECT_FP32 = 0, ECT_FP64 = 1 } ect_precision;
 #define ECT_DEVERR_OVERFLOW      0x10u /* a Laplace output overflowed without a log-scale output */
 #define ECT_DEVERR_CAPACITY      0x20u /* hybrid work list larger than its workspace */
 #define ECT_DEVERR_LAYOUT        0x40u /* exact representation: a row's offsets leave no room for it */
+#define ECT_DEVERR_SCALE         0x80u /* a device kernel scale (hybrid_eval_multi_s, ...) is 0 or not finite */
 
 /* A batch of images.  Every image of a batch has the same ndim, dtype and
  * construction; sizes may differ (ragged batch). */
@@ -291,6 +292,24 @@ ect_status hybrid_eval_noalloc(ect_plan plan, int32_t kernel, double s, int32_t 
 ect_status hybrid_eval_multi(ect_plan plan, uint32_t kernel_mask, double s, int32_t precision,
                              ect_query_set xi, double* out_fourier, double* out_laplace, double* out_bessel,
                              double* log_scale_laplace, void* ws, size_t* ws_bytes, hipStream_t stream);
+
+/* hybrid_eval_multi_s, hybrid_eval_backward_s -- hybrid_eval_multi and
+ * hybrid_eval_backward with the kernel scale read by the kernels from device
+ * memory: a learnable scale (the kernel's s in kappa(s t)) can then change
+ * between replays of a captured HIP graph without a copy to the host.
+ *   s               DEVICE double scalar, read when the kernels run; it must
+ *                   be finite and nonzero (the constant-kernel limit s = 0 is
+ *                   not available here): otherwise ECT_DEVERR_SCALE is raised
+ *                   and the outputs are not finite
+ * Every other argument, layout and error as in hybrid_eval_multi and
+ * hybrid_eval_backward; the outputs equal theirs at the same value of s bit
+ * for bit. */
+ect_status hybrid_eval_multi_s(ect_plan plan, uint32_t kernel_mask, const double* s, int32_t precision,
+                               ect_query_set xi, double* out_fourier, double* out_laplace, double* out_bessel,
+                               double* log_scale_laplace, void* ws, size_t* ws_bytes, hipStream_t stream);
+ect_status hybrid_eval_backward_s(ect_plan plan, int32_t kernel, const double* s, int32_t precision,
+                                  ect_query_set xi, const double* out, const double* grad_out, double* grad_xi,
+                                  double* grad_s, uint32_t flags, void* ws, size_t* ws_bytes, hipStream_t stream);
 
 /* ect_hybrid_eval_multi -- ect_eval(plan, dirs, thresholds, M,
  * thresholds_per_image, ect_out) and hybrid_eval_multi(plan, kernel_mask, s,

@@ -29,6 +29,7 @@ DEVERR_LOOKBACK = 0x8
 DEVERR_OVERFLOW = 0x10
 DEVERR_CAPACITY = 0x20
 DEVERR_LAYOUT = 0x40
+DEVERR_SCALE = 0x80
 EXACT_ECT, EXACT_RADON = 0, 1
 BWD_REUSE_PREPARED = 0x1
 
@@ -75,6 +76,10 @@ def lib():
                                     P(ctypes.c_size_t), c_vp]
     L.ect_hybrid_eval_multi.argtypes = [c_vp, QuerySet, c_vp, c_i32, c_i32, c_vp, c_u32, c_f64, c_i32, QuerySet,
                                         c_vp, c_vp, c_vp, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
+    L.hybrid_eval_multi_s.argtypes = [c_vp, c_u32, c_vp, c_i32, QuerySet, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                      P(ctypes.c_size_t), c_vp]
+    L.hybrid_eval_backward_s.argtypes = [c_vp, c_i32, c_vp, c_i32, QuerySet, c_vp, c_vp, c_vp, c_vp, c_u32,
+                                         c_vp, P(ctypes.c_size_t), c_vp]
     L.hybrid_eval_backward.argtypes = [c_vp, c_i32, c_f64, c_i32, QuerySet, c_vp, c_vp, c_vp, c_vp, c_u32,
                                        c_vp, P(ctypes.c_size_t), c_vp]
     L.ect_plan_counts.argtypes = [c_vp, P(c_i64), P(c_i64)]
@@ -87,7 +92,7 @@ def lib():
     L.ect_exact.argtypes = [c_vp, QuerySet, c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, P(ctypes.c_size_t), c_vp]
     L.ect_exact_eval.argtypes = [c_i32, c_i64, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_i32, c_i32, c_vp, c_vp]
     for name in ("ect_precompute", "ect_plan_rerun", "ect_plan_rerun_prepare", "ect_eval", "radon_eval", "hybrid_eval", "hybrid_eval_noalloc",
-                 "hybrid_eval_multi",
+                 "hybrid_eval_multi", "hybrid_eval_multi_s", "hybrid_eval_backward_s",
                  "ect_hybrid_eval_multi", "hybrid_eval_backward", "ect_exact_layout", "ect_exact", "ect_exact_eval",
                  "ect_plan_counts", "ect_plan_export", "ect_plan_check", "ect_plan_destroy", "ect_plan_set_tuning",
                  "ect_set_stage_events"):
@@ -164,6 +169,21 @@ def hybrid_eval_multi(plan, mask, s, precision, xi: QuerySet, out_f, out_l, out_
                                    c_vp(out_f) if out_f else None, c_vp(out_l) if out_l else None,
                                    c_vp(out_b) if out_b else None, c_vp(log_scale) if log_scale else None, ws,
                                    ctypes.byref(ws_bytes), c_vp(stream))
+
+
+def hybrid_eval_multi_s(plan, mask, s_ptr, precision, xi: QuerySet, out_f, out_l, out_b, log_scale, ws,
+                        ws_bytes: ctypes.c_size_t, stream) -> int:
+    return lib().hybrid_eval_multi_s(c_vp(plan), int(mask), c_vp(s_ptr), int(precision), xi,
+                                     c_vp(out_f) if out_f else None, c_vp(out_l) if out_l else None,
+                                     c_vp(out_b) if out_b else None, c_vp(log_scale) if log_scale else None, ws,
+                                     ctypes.byref(ws_bytes), c_vp(stream))
+
+
+def hybrid_eval_backward_s(plan, kernel, s_ptr, precision, xi: QuerySet, out, grad_out, grad_xi, grad_s, ws,
+                           ws_bytes: ctypes.c_size_t, stream, flags: int = 0) -> int:
+    return lib().hybrid_eval_backward_s(c_vp(plan), int(kernel), c_vp(s_ptr), int(precision), xi, c_vp(out),
+                                        c_vp(grad_out), c_vp(grad_xi), c_vp(grad_s) if grad_s else None, int(flags),
+                                        ws, ctypes.byref(ws_bytes), c_vp(stream))
 
 
 def ect_plan_rerun_prepare(plan, xi: QuerySet, ws, ws_bytes: ctypes.c_size_t, stream) -> int:

@@ -26,6 +26,16 @@ def _dptr(t) -> int:
     return 0 if t is None else int(t.data_ptr())
 
 
+def _device_scale(s, device):
+    """A device float64 scalar for the *_s entry points (None when s is a Python number)."""
+    if not torch.is_tensor(s):
+        return None
+    t = s.detach()
+    if t.numel() != 1 or t.device != device:
+        raise ValueError("a tensor scale must be one element on the plan's device")
+    return t.reshape(()).to(torch.float64).contiguous()
+
+
 def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
@@ -276,7 +286,18 @@ class Plan:
         ls = log_scale_out if log_scale_out is not None else (
             torch.empty(rows, dtype=torch.float64, device=self.device) if log_scale else None)
         st = _stream(stream)
+        sd = _device_scale(s, self.device)
         need = ctypes.c_size_t(0)
+        if sd is not None:
+            # the kernels read the scale from device memory (no host copy)
+            ptrs = [_dptr(out) if k == kk else 0 for kk in (N.FOURIER, N.LAPLACE, N.BESSEL)]
+            N.check(N.hybrid_eval_multi_s(self.handle, 1 << k, _dptr(sd), N.PRECISIONS[precision], q.c(), *ptrs,
+                                          _dptr(ls), None, need, st), "hybrid_eval_multi_s(size)")
+            ws = self._ws(need.value, slot)
+            have = ctypes.c_size_t(ws.numel())
+            N.check(N.hybrid_eval_multi_s(self.handle, 1 << k, _dptr(sd), N.PRECISIONS[precision], q.c(), *ptrs,
+                                          _dptr(ls), ctypes.c_void_p(_dptr(ws)), have, st), "hybrid_eval_multi_s")
+            return (out, ls) if log_scale else out
         N.check(N.hybrid_eval(self.handle, k, s, N.PRECISIONS[precision], q.c(), _dptr(out), _dptr(ls), None,
                               need, st), "hybrid_eval(size)")
         ws = self._ws(need.value, slot)
@@ -300,13 +321,16 @@ class Plan:
                                       device=self.device)
         st = _stream(stream)
         ptrs = [_dptr(outs.get(k)) for k in ("fourier", "laplace", "bessel")]
+        sd = _device_scale(s, self.device)
+        fn, sv, name = ((N.hybrid_eval_multi_s, _dptr(sd), "hybrid_eval_multi_s") if sd is not None
+                        else (N.hybrid_eval_multi, s, "hybrid_eval_multi"))
         need = ctypes.c_size_t(0)
-        N.check(N.hybrid_eval_multi(self.handle, mask, s, N.PRECISIONS[precision], q.c(), *ptrs,
-                                    _dptr(log_scale_out), None, need, st), "hybrid_eval_multi(size)")
+        N.check(fn(self.handle, mask, sv, N.PRECISIONS[precision], q.c(), *ptrs, _dptr(log_scale_out), None, need,
+                   st), name + "(size)")
         ws = self._ws(need.value, slot)
         have = ctypes.c_size_t(ws.numel())
-        N.check(N.hybrid_eval_multi(self.handle, mask, s, N.PRECISIONS[precision], q.c(), *ptrs,
-                                    _dptr(log_scale_out), ctypes.c_void_p(_dptr(ws)), have, st), "hybrid_eval_multi")
+        N.check(fn(self.handle, mask, sv, N.PRECISIONS[precision], q.c(), *ptrs, _dptr(log_scale_out),
+                   ctypes.c_void_p(_dptr(ws)), have, st), name)
         return {k: outs[k] for k in kernels}
 
     def ect_hybrid_multi(self, dirs, thresholds: torch.Tensor, xi, kernels=("fourier", "laplace", "bessel"),
@@ -364,15 +388,16 @@ class Plan:
         out = out.to(torch.float64).contiguous()
         go = grad_out.to(torch.float64).contiguous()
         st = _stream(stream)
+        sd = _device_scale(s, self.device)
+        fn, sv, name = ((N.hybrid_eval_backward_s, _dptr(sd), "hybrid_eval_backward_s") if sd is not None
+                        else (N.hybrid_eval_backward, s, "hybrid_eval_backward"))
         need = ctypes.c_size_t(0)
-        N.check(N.hybrid_eval_backward(self.handle, k, s, N.PRECISIONS[precision], q.c(), _dptr(out), _dptr(go),
-                                       _dptr(gxi), _dptr(gs), None, need, st), "hybrid_eval_backward(size)")
+        N.check(fn(self.handle, k, sv, N.PRECISIONS[precision], q.c(), _dptr(out), _dptr(go), _dptr(gxi), _dptr(gs),
+                   None, need, st), name + "(size)")
         ws = self._ws(need.value, slot)
         have = ctypes.c_size_t(ws.numel())
-        N.check(N.hybrid_eval_backward(self.handle, k, s, N.PRECISIONS[precision], q.c(), _dptr(out), _dptr(go),
-                                       _dptr(gxi), _dptr(gs), ctypes.c_void_p(_dptr(ws)), have, st,
-                                       N.BWD_REUSE_PREPARED if reuse_prepared else 0),
-                "hybrid_eval_backward")
+        N.check(fn(self.handle, k, sv, N.PRECISIONS[precision], q.c(), _dptr(out), _dptr(go), _dptr(gxi), _dptr(gs),
+                   ctypes.c_void_p(_dptr(ws)), have, st, N.BWD_REUSE_PREPARED if reuse_prepared else 0), name)
         return gxi, gs
 
 
@@ -426,24 +451,30 @@ class HybridTransform(torch.autograd.Function):
     """y = HT_s(xi) for every image of a plan, differentiable in xi and in the scale s.
 
     xi: [count][ndim] shared by every image (float32 or float64; converted to
-    float64 losslessly at the boundary).  s: 0-dim tensor.  Returns float64
-    [num_images*count] (Fourier: [num_images*count][2]); the backward pass
-    calls the library's vector-Jacobian product kernel.
+    float64 losslessly at the boundary).  s: a number, or a one-element tensor
+    on the plan's device, which the kernels read from device memory (no host
+    synchronisation, so a training step with a learnable scale can be
+    captured into a HIP graph).  Returns float64 [num_images*count] (Fourier:
+    [num_images*count][2]); the backward pass calls the library's
+    vector-Jacobian product kernel.
     """
 
     @staticmethod
     def forward(ctx, xi, s, plan: Plan, kernel: str = "fourier", precision: str = "fp32"):
         xi64 = xi.detach().to(torch.float64).contiguous()
-        sval = float(s.detach().item()) if torch.is_tensor(s) else float(s)
-        y = plan.hybrid(xi64, kernel, sval, precision)
-        ctx.plan, ctx.kernel, ctx.precision, ctx.sval = plan, kernel, precision, sval
-        ctx.xi_dtype = xi.dtype
         ctx.s_is_tensor = torch.is_tensor(s)
+        sarg = _device_scale(s, plan.device) if ctx.s_is_tensor else float(s)
+        y = plan.hybrid(xi64, kernel, sarg, precision)
+        ctx.plan, ctx.kernel, ctx.precision, ctx.sarg = plan, kernel, precision, sarg
+        ctx.xi_dtype = xi.dtype
+        ctx.s_dtype = s.dtype if ctx.s_is_tensor else None
+        ctx.s_shape = s.shape if ctx.s_is_tensor else None
         ctx.save_for_backward(xi64, y)
         return y
 
     @staticmethod
     def backward(ctx, gy):
         xi64, y = ctx.saved_tensors
-        gxi, gs = ctx.plan.hybrid_backward(xi64, y, gy.contiguous(), ctx.kernel, ctx.sval, ctx.precision)
-        return gxi.to(ctx.xi_dtype), (gs if ctx.s_is_tensor else None), None, None, None
+        gxi, gs = ctx.plan.hybrid_backward(xi64, y, gy.contiguous(), ctx.kernel, ctx.sarg, ctx.precision)
+        return (gxi.to(ctx.xi_dtype), (gs.to(ctx.s_dtype).reshape(ctx.s_shape) if ctx.s_is_tensor else None), None,
+                None, None)

@@ -610,7 +610,8 @@ static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t 
                                 double* out_f, double* out_l, double* out_b, double* log_scale,
                                 const double* fwd_out, const double* grad_out, double* grad_xi, double* grad_s,
                                 void* ws, size_t* ws_bytes, hipStream_t stream, bool backward,
-                                bool reuse = false, const EctArgs* combo = nullptr, int64_t combo_groups = 0) {
+                                bool reuse = false, const EctArgs* combo = nullptr, int64_t combo_groups = 0,
+                                const double* s_dev = nullptr) {
     if (!plan || !ws_bytes) return ECT_E_INVALID;
     if (mask == 0 || mask > 7) return ECT_E_INVALID;
     if (backward && (mask & (mask - 1))) return ECT_E_INVALID;
@@ -683,6 +684,7 @@ static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t 
     a.offsets = xi.offsets;
     a.count = xi.count;
     a.s = s;
+    a.s_dev = s_dev;
     a.out_f = out_f;
     a.out_l = out_l;
     a.out_b = out_b;
@@ -752,6 +754,27 @@ ect_status hybrid_eval_multi(ect_plan plan, uint32_t kernel_mask, double s, int3
                              void* ws, size_t* ws_bytes, hipStream_t stream) {
     return hybrid_common(plan, kernel_mask, s, precision, xi, out_fourier, out_laplace, out_bessel,
                          log_scale_laplace, nullptr, nullptr, nullptr, nullptr, ws, ws_bytes, stream, false);
+}
+
+ect_status hybrid_eval_multi_s(ect_plan plan, uint32_t kernel_mask, const double* s, int32_t precision,
+                               ect_query_set xi, double* out_fourier, double* out_laplace, double* out_bessel,
+                               double* log_scale_laplace, void* ws, size_t* ws_bytes, hipStream_t stream) {
+    if (!s) return ECT_E_INVALID;
+    // the host sees a nonzero placeholder: the constant-kernel limit is not taken with a device scale
+    return hybrid_common(plan, kernel_mask, 1.0, precision, xi, out_fourier, out_laplace, out_bessel,
+                         log_scale_laplace, nullptr, nullptr, nullptr, nullptr, ws, ws_bytes, stream, false, false,
+                         nullptr, 0, s);
+}
+
+ect_status hybrid_eval_backward_s(ect_plan plan, int32_t kernel, const double* s, int32_t precision,
+                                  ect_query_set xi, const double* out, const double* grad_out, double* grad_xi,
+                                  double* grad_s, uint32_t flags, void* ws, size_t* ws_bytes, hipStream_t stream) {
+    if (!s) return ECT_E_INVALID;
+    if (kernel < ECT_FOURIER || kernel > ECT_BESSEL) return ECT_E_INVALID;
+    if (flags & ~(uint32_t)ECT_BWD_REUSE_PREPARED) return ECT_E_INVALID;
+    return hybrid_common(plan, 1u << kernel, 1.0, precision, xi, nullptr, nullptr, nullptr, nullptr, out, grad_out,
+                         grad_xi, grad_s, ws, ws_bytes, stream, true, (flags & ECT_BWD_REUSE_PREPARED) != 0, nullptr,
+                         0, s);
 }
 
 ect_status ect_hybrid_eval_multi(ect_plan plan, ect_query_set dirs, const double* thresholds, int32_t M,

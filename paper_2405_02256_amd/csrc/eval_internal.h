@@ -119,6 +119,7 @@ struct HybridArgs {
     const int64_t* offsets;
     int64_t count;
     double s;
+    const double* s_dev;      // device scale (read by the kernels instead of s) or null
     double* out_f;            // Fourier [rows][2]
     double* out_l;            // Laplace [rows]
     double* out_b;            // Bessel [rows]

@@ -277,6 +277,16 @@ __device__ __forceinline__ void add_part(Query<N>& q, double* acc, const double*
         if (slot_used<MASK, BWD, N>(k) && k != kSlotShift && !lap_slot<MASK, BWD, N>(k)) acc[k] += other[k];
 }
 
+// The kernel scale: the call's argument, or read from device memory (a
+// learnable scale in a captured graph); a device scale that is zero or not
+// finite raises ECT_DEVERR_SCALE (the outputs are then not finite).
+__device__ __forceinline__ double scale_of(const HybridArgs& a) {
+    if (!a.s_dev) return a.s;
+    const double s = *a.s_dev;
+    if (!(isfinite(s) && s != 0.0) && threadIdx.x == 0) raise_error(a.err, ECT_DEVERR_SCALE);
+    return s;
+}
+
 // Per-query set-up shared by the evaluation and reduction kernels.
 template <int N, int MASK, int PREC, bool BWD>
 __device__ __forceinline__ void setup_query(const HybridArgs& a, int64_t img, int b, int64_t qi, bool active,
@@ -287,7 +297,7 @@ __device__ __forceinline__ void setup_query(const HybridArgs& a, int64_t img, in
     row = 0;
     q.sigma = 1.0;
     q.gr = q.gi = 0.0;
-    const double s = a.s;
+    const double s = scale_of(a);
     if (active) {
         const QRecT<N> r = ((const QRecT<N>*)a.recs)[bucket_start(a.offsets, a.count, img, P, b) + qi];
         row = row_base + (r.code >> 1);
@@ -318,7 +328,7 @@ __device__ __forceinline__ void setup_query(const HybridArgs& a, int64_t img, in
 // Scale the point sums of one query into its outputs.
 template <int N, int MASK, int PREC, bool BWD>
 __device__ __forceinline__ void finalize(const HybridArgs& a, const Query<N>& q, int64_t row, const double* acc) {
-    const double s = a.s;
+    const double s = scale_of(a);
     if constexpr (MASK == kLin) {
         const double v = q.sigma * acc[0];
         if (a.out_f) {

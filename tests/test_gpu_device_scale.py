@@ -1,0 +1,115 @@
+"""The kernel scale read from device memory (hybrid_eval_multi_s,
+hybrid_eval_backward_s): outputs equal those of the host-scale calls bit for
+bit, a bad device scale raises its flag, and a training step with a
+learnable scale (forward, loss, gradients through the autograd Function) is
+captured once as a HIP graph and replayed for several scales, each replay
+equal to the eager step bit for bit."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2405_02256_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2405_02256_amd import _native as N
+    from paper_2405_02256_amd import api as A
+    return A, N
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(torch.device("cuda:0"))
+
+
+def _bits(t):
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_device_scale_equals_host_scale(mods, precision):
+    A, N = mods
+    rng = np.random.default_rng(2601)
+    imgs = [W.binary_field(rng, (60, 52), 3.0) for _ in range(3)]
+    plan = A.Plan([T(im) for im in imgs])
+    xi = T(W.polar_vectors(rng, 300, 0.01, 1.0, axis_gap=0.02))
+    for sval in (1.0, 0.37, -1.2):
+        sdev = torch.tensor(sval, dtype=torch.float64, device="cuda:0")
+        ref = plan.hybrid_multi(xi, ("fourier", "laplace", "bessel"), sval, precision)
+        got = plan.hybrid_multi(xi, ("fourier", "laplace", "bessel"), sdev, precision)
+        for k in ref:
+            assert np.array_equal(_bits(got[k]), _bits(ref[k])), (sval, k)
+        g = T(rng.standard_normal((xi.shape[0] * len(imgs), 2)))
+        for k in ("fourier", "laplace", "bessel"):
+            gk = g if k == "fourier" else g[:, 0].contiguous()
+            ax, as_ = plan.hybrid_backward(xi, ref[k], gk, k, sval, precision)
+            bx, bs = plan.hybrid_backward(xi, got[k], gk, k, sdev, precision)
+            assert np.array_equal(_bits(ax), _bits(bx)) and np.array_equal(_bits(as_), _bits(bs)), (sval, k)
+    assert plan.check() == 0
+    # a zero or non-finite device scale is flagged
+    for bad in (0.0, float("nan")):
+        plan.hybrid_multi(xi, ("laplace",), torch.tensor(bad, dtype=torch.float64, device="cuda:0"), precision)
+        assert plan.check() & N.DEVERR_SCALE
+
+
+def test_learnable_scale_step_in_a_graph(mods):
+    A, N = mods
+    rng = np.random.default_rng(2602)
+    imgs = [W.binary_field(rng, (48, 48), float(sg)) for sg in rng.uniform(2.0, 6.0, size=6)]
+    plan = A.Plan([T(im) for im in imgs])
+    xi0 = W.polar_vectors(rng, 96, 0.01, 0.5, axis_gap=0.02)
+    xi = T(xi0).clone().requires_grad_(True)
+    s = torch.tensor(1.0, dtype=torch.float64, device="cuda:0", requires_grad=True)
+    wts = {k: T(rng.standard_normal((len(imgs) * len(xi0), 2) if k == "fourier" else (len(imgs) * len(xi0),)))
+           for k in ("fourier", "laplace")}
+
+    def step():
+        loss = 0.0
+        ys = []
+        for k in ("fourier", "laplace"):
+            y = A.HybridTransform.apply(xi, s, plan, k, "fp32")
+            ys.append(y)
+            loss = loss + (y * wts[k]).sum()
+        gx, gs = torch.autograd.grad(loss, (xi, s))
+        return ys + [gx, gs]
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(2):
+            step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        captured = step()
+    torch.cuda.synchronize()
+    for sval in (0.8, 1.25, 0.6, 0.8):
+        with torch.no_grad():
+            s.fill_(sval)
+        g.replay()
+        torch.cuda.synchronize()
+        eager = step()
+        torch.cuda.synchronize()
+        for a, b in zip(captured, eager):
+            assert np.array_equal(_bits(a), _bits(b)), sval
+        # the host-scale path at the same value
+        ref = plan.hybrid(xi.detach(), "laplace", sval, "fp32")
+        assert np.array_equal(_bits(captured[1]), _bits(ref)), sval
+    # the replayed gradient in s against the oracle at the last scale (per-image sums)
+    gs_ref = 0.0
+    nq = len(xi0)
+    for k in ("fourier", "laplace"):
+        wk = wts[k].cpu().numpy().reshape(len(imgs), nq, -1)
+        for i, im in enumerate(imgs):
+            gi = wk[i] if k == "fourier" else wk[i, :, 0]
+            gs_ref += O.hybrid_grad(im, xi0, k, 0.8, gi)[1]
+    gs = float(captured[3].cpu())
+    assert abs(gs - gs_ref) <= 1e-5 * abs(gs_ref) + 1e-6, (gs, gs_ref)
+    assert plan.check() == 0
