@@ -644,146 +644,234 @@ tile_count_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ de
 }
 
 // Two-axis primal images, count pass of three-pass plans.  Same counts and
-// packed slots as tile_count_kernel, with the work per vertex cut down: a
-// wave owns 256 consecutive vertices of the tile (lane l, round j: vertex
-// wave * 256 + j * 64 + l), so the wave's entries of a list are contiguous in
-// the tile's order and their positions come from the wave's ballot masks
-// (scalar bit counts) and the earlier waves' totals; the vertex coordinates
-// advance by 64 per round instead of a division per vertex; the cell values
-// have their shared subexpressions written out (vertex_values_2p).
-template <typename T>
-__global__ void __launch_bounds__(kPrecomputeThreads)
-tile_count_2p_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
-                     const int32_t* __restrict__ tile_img, int32_t num_images, int32_t* __restrict__ counts,
-                     uint32_t* __restrict__ packed) {
-    constexpr int NL = 6, J = 4, W = kPrecomputeThreads / 64;
-    static_assert(tile_verts(2) == J * kPrecomputeThreads, "four rounds of 64 vertices per wave");
-    __shared__ int32_t s_tot[W][NL];
-    const int64_t tile = blockIdx.x;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const ImageDesc& d = descs[tile_img[tile]];
-    const T* __restrict__ img = pixels + d.pixel_offset;
-    const int64_t nvert = d.nvert;
-    const int V0 = d.V[0], N0 = d.N[0], N1 = d.N[1], W0 = d.dims[0], H1 = d.dims[1];
-    const int64_t first = (tile - d.tile_start) * tile_verts(2) + wave * (J * 64);
-    const double invV0 = 1.0 / (double)V0;
-    uint32_t r;
-    const uint32_t q = udiv((uint32_t)(first + lane), (uint32_t)V0, invV0, &r);
-    int k0 = (int)r, k1 = (int)q;
-    uint32_t r64;
-    const int q64 = (int)udiv(64u, (uint32_t)V0, invV0, &r64);
-    int32_t px[J][4];
-    int kk0[J], kk1[J];
-    bool valid[J];
+// packed slots as tile_count_kernel, with the work per vertex cut down: one
+// wave per tile, 16 rounds of 64 consecutive vertices (lane l, round j:
+// vertex j * 64 + l of the tile).  The pixel rows the tile touches are
+// staged once into the wave's part of LDS with dword loads (byte loads of
+// four pixels per vertex kept the vector memory pipeline busy for most of
+// the pass), unless they exceed it (very wide images read global memory).
+// The wave's entries of a list are contiguous in the tile's order, so their
+// slots come from the ballot masks (a running scalar count plus the bit count
+// below the lane); they collect in LDS and leave in whole-wave stores (see
+// flush_entries); the vertex coordinates advance by 64 per round instead of
+// a division per vertex; the cell values have their shared subexpressions
+// written out (vertex_values_2p).
+constexpr int kSpanDwords = 512;   // LDS per wave for the staged pixel rows (2 KiB)
+
+// The wave's packed entries of list l collect in LDS (kEntryBuf per list)
+// and go out in whole-wave stores: one store instruction per entry slot kept
+// the texture address unit busy for most of the pass.  flush_entries writes
+// list l's collected entries to slots at its running count.
+constexpr int kEntryBuf = 128;
+
+__device__ __forceinline__ void flush_entries(const uint32_t* buf, uint32_t n, char* __restrict__ slots,
+                                              uint32_t at) {
+    const int lane = threadIdx.x & 63;
+    // entries other lanes of the wave put in LDS
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    for (uint32_t i = (uint32_t)lane; i < n; i += 64u) *(uint32_t*)(slots + (at + i) * 4u) = buf[i];
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
+// The 16 rounds of one tile; STAGED: pixels from the staged rows in LDS
+// (row rr at (rr - rlo) * W0), else from global memory.  base[l]: slots
+// written for list l (scalar), buffered[l]: entries waiting in buf.
+template <typename T, bool STAGED>
+__device__ __forceinline__ void count_rounds_2p(const unsigned char* lds, const T* __restrict__ img, int rlo, int rhi,
+                                                int W0, int V0, int N0, int N1, int nv, int q64, int r64, int k0,
+                                                int k1, char* __restrict__ slots, uint32_t* base, uint32_t* buf) {
+    constexpr int NL = 6, R = tile_verts(2) / 64;
+    const int lane = threadIdx.x & 63;
+    uint32_t buffered[NL];
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-        valid[j] = first + j * 64 + lane < nvert;
-        kk0[j] = valid[j] ? k0 : 0;
-        kk1[j] = valid[j] ? k1 : 0;
-        const int c0 = max(kk0[j] - 1, 0), c1 = min(kk0[j], W0 - 1);
-        const int r0 = max(kk1[j] - 1, 0) * W0, r1 = min(kk1[j], H1 - 1) * W0;
-        px[j][0] = px_load(img, (uint32_t)(r0 + c0));
-        px[j][1] = px_load(img, (uint32_t)(r0 + c1));
-        px[j][2] = px_load(img, (uint32_t)(r1 + c0));
-        px[j][3] = px_load(img, (uint32_t)(r1 + c1));
-        k0 += (int)r64;
+    for (int l = 0; l < NL; ++l) buffered[l] = 0u;
+    auto pix = [&](int rr, int cc) -> int32_t {
+        if constexpr (STAGED) {
+            const uint32_t o = __umul24((uint32_t)(rr - rlo), (uint32_t)W0) + (uint32_t)cc;
+            return (int32_t)((const T*)lds)[o];
+        } else {
+            return px_load(img, (uint32_t)(rr * W0 + cc));
+        }
+    };
+#pragma unroll 2
+    for (int round = 0; round < R; ++round) {
+        const bool valid = round * 64 + lane < nv;
+        // clamped into the image and into the staged rows (lanes past the
+        // last vertex included)
+        const int c0 = max(k0 - 1, 0), c1 = min(k0, W0 - 1);
+        const int r0 = min(max(k1 - 1, 0), rhi), r1 = min(k1, rhi);
+        const int32_t pa = pix(r0, c0), pb = pix(r0, c1), pc = pix(r1, c0), pd = pix(r1, c1);
+        int32_t L[4], D[2];
+        vertex_values_2p(pa, pb, pc, pd, k0, k1, N0, N1, L, D);
+        const int32_t vals[NL] = {L[0], L[1], L[2], L[3], D[0], D[1]};
+        const uint32_t local = (uint32_t)(round * 64 + lane);
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const bool nz = valid && vals[l] != 0;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(nz);
+            if (m != 0) {
+                if (slots) {
+                    if (buffered[l] + 64u > (uint32_t)kEntryBuf) {
+                        flush_entries(buf + l * kEntryBuf, buffered[l], slots, base[l]);
+                        base[l] += buffered[l];
+                        buffered[l] = 0u;
+                    }
+                    if (nz) {
+                        // buffered + number of the wave's entries on lower lanes
+                        const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, buffered[l]));
+                        buf[l * kEntryBuf + pos] = ((uint32_t)vals[l] << kPackShift) | local;
+                    }
+                    buffered[l] += (uint32_t)__builtin_popcountll(m);
+                } else {
+                    base[l] += (uint32_t)__builtin_popcountll(m);
+                }
+            }
+        }
+        k0 += r64;
         k1 += q64;
         if (k0 >= V0) {
             k0 -= V0;
             ++k1;
         }
     }
-    int32_t vals[J][NL];
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        int32_t L[4], D[2];
-        vertex_values_2p(px[j][0], px[j][1], px[j][2], px[j][3], kk0[j], kk1[j], N0, N1, L, D);
-#pragma unroll
-        for (int l = 0; l < 4; ++l) vals[j][l] = valid[j] ? L[l] : 0;
-#pragma unroll
-        for (int l = 0; l < 2; ++l) vals[j][4 + l] = valid[j] ? D[l] : 0;
-    }
-    // the wave's totals per list
-    int32_t tot[NL];
-#pragma unroll
-    for (int l = 0; l < NL; ++l) tot[l] = 0;
-#pragma unroll
-    for (int j = 0; j < J; ++j)
-#pragma unroll
-        for (int l = 0; l < NL; ++l) tot[l] += __popcll(__builtin_amdgcn_ballot_w64(vals[j][l] != 0));
-#pragma unroll
-    for (int l = 0; l < NL; ++l)
-        if (lane == l) s_tot[wave][l] = tot[l];
-    __syncthreads();
-    if (wave == 0 && lane < NL) {
-        int32_t t = 0;
-#pragma unroll
-        for (int w = 0; w < W; ++w) t += s_tot[w][lane];
-        counts[tile * NL + lane] = t;
-    }
-    if (!packed) return;
-    uint32_t* __restrict__ slots = packed + tile * NL * (int64_t)tile_verts(2);
-    const uint64_t below = (1ull << lane) - 1ull;
-    int32_t base[NL];
-#pragma unroll
-    for (int l = 0; l < NL; ++l) {
-        int32_t b = 0;
-        for (int w = 0; w < wave; ++w) b += s_tot[w][l];
-        base[l] = __builtin_amdgcn_readfirstlane(b);
-    }
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const uint32_t local = (uint32_t)(wave * (J * 64) + j * 64 + lane);
+    if (slots) {
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
-            const bool nz = vals[j][l] != 0;
-            const uint64_t m = __builtin_amdgcn_ballot_w64(nz);
-            if (m != 0) {
-                if (nz) {
-                    const uint32_t pos = (uint32_t)(base[l] + __popcll(m & below));
-                    slots[(uint32_t)(l * tile_verts(2)) + pos] = ((uint32_t)vals[j][l] << kPackShift) | local;
-                }
-                base[l] += __popcll(m);
-            }
+            if (buffered[l] != 0u) flush_entries(buf + l * kEntryBuf, buffered[l], slots, base[l]);
+            base[l] += buffered[l];
         }
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kPrecomputeThreads)
+tile_count_2p_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
+                     const int32_t* __restrict__ tile_img, int64_t num_tiles, int32_t* __restrict__ counts,
+                     uint32_t* __restrict__ packed) {
+    constexpr int NL = 6, R = tile_verts(2) / 64;
+    __shared__ uint32_t s_span[kPrecomputeThreads / 64][kSpanDwords];
+    __shared__ uint32_t s_ent[kPrecomputeThreads / 64][NL * kEntryBuf];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t tile = (int64_t)blockIdx.x * (kPrecomputeThreads / 64) + wave;
+    if (tile >= num_tiles) return;
+    const ImageDesc& d = descs[tile_img[tile]];
+    const T* __restrict__ img = pixels + d.pixel_offset;
+    const int V0 = d.V[0], N0 = d.N[0], N1 = d.N[1], W0 = d.dims[0], H1 = d.dims[1];
+    const int64_t first = (tile - d.tile_start) * tile_verts(2);
+    // vertices of the tile that exist (the image's last tile is short)
+    const int nv = (int)min<int64_t>(d.nvert - first, (int64_t)tile_verts(2));
+    const double invV0 = 1.0 / (double)V0;
+    uint32_t r;
+    const uint32_t q = udiv((uint32_t)(first + lane), (uint32_t)V0, invV0, &r);
+    int k0 = (int)r, k1 = (int)q;
+    uint32_t r64;
+    const int q64 = (int)udiv(64u, (uint32_t)V0, invV0, &r64);
+    // pixel rows rlo..rhi hold every pixel of the tile's vertex stars
+    uint32_t rdummy;
+    const int k1f = (int)(first / V0);
+    const int k1l = (int)udiv((uint32_t)(first + nv - 1), (uint32_t)V0, invV0, &rdummy);
+    const int rlo = min(max(k1f - 1, 0), H1 - 1), rhi = min(k1l, H1 - 1);
+    const int64_t span_lo = (int64_t)rlo * W0 * (int64_t)sizeof(T);
+    const int64_t span_hi = ((int64_t)rhi + 1) * W0 * (int64_t)sizeof(T);
+    // dword-aligned start of the span (mis bytes before it); offsets are
+    // relative to the image's first byte
+    const char* __restrict__ ib = (const char*)img;
+    const int mis = (int)(((uintptr_t)ib + (uintptr_t)span_lo) & 3u);
+    const int64_t o0 = span_lo - mis;
+    const int ndw = (int)((span_hi - o0 + 3) >> 2);
+    const bool staged = ndw <= kSpanDwords;
+    unsigned char* s_bytes = (unsigned char*)s_span[wave];
+    if (staged) {
+        // dwords wholly inside the span in one load; the partial first and
+        // last ones byte by byte (nothing outside the image is read)
+        for (int i = lane; i < ndw; i += 64) {
+            const int64_t o = o0 + 4 * (int64_t)i;
+            uint32_t w;
+            if (o >= span_lo && o + 4 <= span_hi) {
+                w = *(const uint32_t*)(ib + o);
+            } else {
+                w = 0u;
+                for (int b = 0; b < 4; ++b)
+                    if (o + b >= span_lo && o + b < span_hi) w |= (uint32_t)(unsigned char)ib[o + b] << (8 * b);
+            }
+            s_span[wave][i] = w;
+        }
+        // the wave's own LDS writes come before its reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // slots of this tile: 32-bit byte offsets from a uniform base; base[l] is
+    // the next free slot of list l (a scalar)
+    char* __restrict__ slots = packed ? (char*)(packed + tile * NL * (int64_t)tile_verts(2)) : nullptr;
+    uint32_t base[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) base[l] = (uint32_t)(l * tile_verts(2));
+    if (staged)
+        count_rounds_2p<T, true>(s_bytes + mis, img, rlo, rhi, W0, V0, N0, N1, nv, q64, (int)r64, k0, k1, slots, base,
+                                 s_ent[wave]);
+    else
+        count_rounds_2p<T, false>(s_bytes, img, rlo, rhi, W0, V0, N0, N1, nv, q64, (int)r64, k0, k1, slots, base,
+                                  s_ent[wave]);
+    int32_t c = 0;
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+        if (lane == l) c = (int32_t)(base[l] - (uint32_t)(l * tile_verts(2)));
+    if (lane < NL) counts[tile * NL + lane] = c;
+}
+
 // Three-pass plans with packed entries: place tile t's entries (list l's
-// count from tile_count_kernel, in vertex order) at the list's prefix.  The
-// tile's counts and prefixes are read once; its entries of all lists are then
-// one flat range, one thread per entry, with the vertex coordinates decoded
-// from the index.
+// count from the count pass, in vertex order) at the list's prefix.  One wave
+// per tile: lanes l < NL read list l's count and prefix, a wave scan turns
+// the counts into the start of each list in the tile's flat range of entries,
+// and the starts and prefixes are broadcast into scalar registers; the range
+// is then placed one entry per lane, with the vertex coordinates decoded from
+// the index.
 template <int N>
 __global__ void __launch_bounds__(kPrecomputeThreads)
-tile_copy_kernel(const ImageDesc* __restrict__ descs, const int32_t* __restrict__ tile_img, int32_t num_images,
+tile_copy_kernel(const ImageDesc* __restrict__ descs, const int32_t* __restrict__ tile_img, int64_t num_tiles,
                  const int32_t* __restrict__ counts, const int64_t* __restrict__ prefix,
                  const uint32_t* __restrict__ packed, PointT<N>* __restrict__ points, int64_t capacity) {
     constexpr int NL = TileValues<N>::NL;
     constexpr int NX = sizeof(PointT<N>::x) / sizeof(double);
-    __shared__ int32_t s_start[NL + 1];
-    __shared__ int64_t s_base[NL];
-    const int64_t tile = blockIdx.x;
-    if (threadIdx.x < NL) {
-        s_start[threadIdx.x + 1] = counts[tile * NL + threadIdx.x];
-        s_base[threadIdx.x] = prefix[tile * NL + threadIdx.x];
+    const int lane = threadIdx.x & 63;
+    const int64_t tile =
+        (int64_t)blockIdx.x * (kPrecomputeThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (tile >= num_tiles) return;
+    const int32_t c = lane < NL ? counts[tile * NL + lane] : 0;
+    const int64_t b = lane < NL ? prefix[tile * NL + lane] : 0;
+    int32_t inc = c;
+#pragma unroll
+    for (int off = 1; off < NL; off <<= 1) {
+        const int32_t t = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += t;
     }
-    const ImageDesc d = descs[tile_img[tile]];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        s_start[0] = 0;
-        for (int l = 0; l < NL; ++l) s_start[l + 1] += s_start[l];
+    int32_t start[NL];
+    int64_t base[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        start[l] = __builtin_amdgcn_readlane(inc - c, l);
+        base[l] = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int32_t)(b >> 32), l) << 32) |
+                            (uint32_t)__builtin_amdgcn_readlane((int32_t)b, l));
     }
-    __syncthreads();
-    const int total = s_start[NL];
+    const int total = __builtin_amdgcn_readlane(inc, NL - 1);
+    const ImageDesc& d = descs[tile_img[tile]];
     const int64_t vbase = (tile - d.tile_start) * tile_verts(N);
     const double inv0 = 1.0 / (double)d.V[0], inv1 = 1.0 / (double)d.V[1], inv2 = 1.0 / (double)d.V[2];
     const uint32_t* __restrict__ slots = packed + tile * NL * (int64_t)tile_verts(N);
-    for (int i = threadIdx.x; i < total; i += kPrecomputeThreads) {
+    for (int i = lane; i < total; i += 64) {
         int l = 0;
+        int32_t st = start[0];
+        int64_t bl = base[0];
 #pragma unroll
-        for (int m = 1; m < NL; ++m) l += i >= s_start[m] ? 1 : 0;
-        const int pos = i - s_start[l];
+        for (int m = 1; m < NL; ++m)
+            if (i >= start[m]) {
+                l = m;
+                st = start[m];
+                bl = base[m];
+            }
+        const int pos = i - st;
         const uint32_t w = slots[l * tile_verts(N) + pos];
         const uint32_t v = (uint32_t)(vbase + (w & kPackLocalMask));
         uint32_t r0, r1 = 0, r2 = 0;
@@ -805,7 +893,7 @@ tile_copy_kernel(const ImageDesc* __restrict__ descs, const int32_t* __restrict_
 #pragma unroll
         for (int a = 0; a < NX; ++a) pt.x[a] = a < N ? __fma_rn(d.spacing[a], (double)k[a], d.origin[a]) : 0.0;
         pt.val = (double)((int32_t)w >> kPackShift);
-        points[(int64_t)l * capacity + s_base[l] + pos] = pt;
+        points[(int64_t)l * capacity + bl + pos] = pt;
     }
 }
 
@@ -1005,8 +1093,9 @@ hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream, const Que
         // packed entries (small pixel types only: their values fit the packed field)
         uint32_t* packed = (L.packed_bytes > 0 && sizeof(T) < 4) ? (uint32_t*)(p.ws + L.packed) : nullptr;
         if constexpr (N == 2 && CONS == ECT_PRIMAL)
-            hipLaunchKernelGGL((tile_count_2p_kernel<T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads), 0,
-                               stream, px, desc, ti, p.num_images, counts, packed);
+            hipLaunchKernelGGL((tile_count_2p_kernel<T>),
+                               dim3((unsigned)((L.num_tiles + kPrecomputeThreads / 64 - 1) / (kPrecomputeThreads / 64))),
+                               dim3(kPrecomputeThreads), 0, stream, px, desc, ti, L.num_tiles, counts, packed);
         else
             hipLaunchKernelGGL((tile_count_kernel<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads),
                                0, stream, px, desc, ti, p.num_images, counts, packed);
@@ -1025,8 +1114,10 @@ hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream, const Que
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         if (packed)
-            hipLaunchKernelGGL((tile_copy_kernel<N>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads), 0,
-                               stream, desc, ti, p.num_images, counts, prefix, packed, pts, L.capacity);
+            hipLaunchKernelGGL((tile_copy_kernel<N>),
+                               dim3((unsigned)((L.num_tiles + kPrecomputeThreads / 64 - 1) / (kPrecomputeThreads / 64))),
+                               dim3(kPrecomputeThreads), 0, stream, desc, ti, L.num_tiles, counts, prefix, packed, pts,
+                               L.capacity);
         else
             hipLaunchKernelGGL((tile_write_kernel<N, CONS, T>), dim3((unsigned)L.num_tiles), dim3(kPrecomputeThreads),
                                0, stream, px, desc, ti, p.num_images, prefix, pts, L.capacity);
