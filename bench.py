@@ -129,7 +129,7 @@ def measure_next(plan, w, dirs, thr, n, cls_counts, ord_counts, steps):
         ms_b = e0.elapsed_time(e1) / steps
         ln = rep.length.cpu().numpy()
         entries = float(ln.sum())
-        nbytes = 32.0 * pts + 12.0 * entries
+        nbytes = 8.0 * pts + 12.0 * entries
         o = torch.empty((rep.rows, thr.shape[0]), dtype=torch.int32, device=thr.device)
         rep.eval(thr, out=o)
         e0.record()

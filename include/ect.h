@@ -137,8 +137,13 @@ typedef struct ect_plan_s* ect_plan;  /* host handle; the critical-point lists l
  *   stream    HIP stream for the work
  *   out       receives the plan handle (only when ws != NULL)
  * Synchronises once at the end to read the list sizes back to the host.
+ * A list entry is 8 bytes: the vertex index packed into 32 bits (axis a takes
+ * ceil(log2 V_a) bits, V_a the largest vertex count along axis a over the
+ * batch) and the critical value.
  * Returns ECT_E_INVALID for a malformed batch, ECT_E_NOMEM when *ws_bytes is
- * too small. */
+ * too small, ECT_E_UNSUPPORTED when an image has 2^31 vertices or more or the
+ * bit fields of the vertex index need more than 32 bits (e.g. beyond
+ * 65535^2 pixels, 2047^3 voxels or 255^4 in the primal construction). */
 ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_bytes,
                           hipStream_t stream, ect_plan* out);
 

@@ -221,6 +221,28 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
     }
     tstart[ni] = tiles;
     if (tiles >= (int64_t)1 << 31) return ECT_E_UNSUPPORTED;
+    // bit fields of the list entries' vertex index: axis a takes enough bits
+    // for the largest vertex count along it over the plan's images
+    {
+        uint32_t shift = 0;
+        uint32_t bits[kMaxDim] = {0, 0, 0, 0};
+        for (int a = 0; a < n; ++a) {
+            int32_t vmax = 1;
+            for (int i = 0; i < ni; ++i) vmax = std::max(vmax, desc[i].V[a]);
+            while (((int64_t)1 << bits[a]) < (int64_t)vmax) ++bits[a];
+        }
+        for (int a = 0; a < n; ++a) shift += bits[a];
+        if (shift > 32) return ECT_E_UNSUPPORTED;
+        shift = 0;
+        for (int i = 0; i < ni; ++i) {
+            uint32_t sh = 0;
+            for (int a = 0; a < kMaxDim; ++a) {
+                desc[i].kshift[a] = a < n ? sh : 0u;
+                desc[i].kmask[a] = a < n ? (uint32_t)(((uint64_t)1 << bits[a]) - 1u) : 0u;
+                if (a < n) sh += bits[a];
+            }
+        }
+    }
 
     PlanLayout L{};
     size_t o = 0;
@@ -233,7 +255,7 @@ ect_status ect_precompute(const ect_image_batch* batch, void* ws, size_t* ws_byt
     // tile counts (int32) and their prefixes (int64).  The size does not
     // depend on the device.
     L.status = o; o = align_up(o + sizeof(uint64_t) * (2 * tiles + (tiles + 63) / 64 + 1) * NL, kAlign);
-    L.points = o; o = align_up(o + point_bytes(n) * verts * NL, kAlign);
+    L.points = o; o = align_up(o + entry_bytes() * verts * NL, kAlign);
     // plans beyond the single pass's largest grid (64 groups of 64 tiles, on
     // any device) run three passes; with 8- or 16-bit pixels the count pass
     // leaves its entries packed in per-tile slots, so the last pass only
@@ -513,6 +535,7 @@ ect_status radon_eval(ect_plan plan, ect_query_set dirs, const double* threshold
 static ExactArgs exact_args(const Plan& p, const ect_query_set& dirs, int32_t kind) {
     ExactArgs a{};
     a.points = (const void*)(p.ws + p.lay.points);
+    a.desc = (const ImageDesc*)(p.ws + p.lay.desc);
     a.list_off = (const int64_t*)(p.ws + p.lay.list_off);
     a.list_capacity = p.lay.capacity;
     a.num_images = p.num_images;
@@ -865,10 +888,10 @@ ect_status ect_plan_export(ect_plan plan, int32_t image, int32_t kind, int32_t l
     *count = cnt;
     const int64_t take = std::min(cnt, capacity);
     if (take <= 0) return ECT_OK;
-    const size_t pb = point_bytes(n);
-    std::vector<char> buf;
+    const size_t pb = entry_bytes();
+    std::vector<ListEntry> buf;
     try {
-        buf.resize(pb * take);
+        buf.resize((size_t)take);
     } catch (...) {
         return ECT_E_NOMEM;
     }
@@ -878,13 +901,8 @@ ect_status ect_plan_export(ect_plan plan, int32_t image, int32_t kind, int32_t l
     if (e != hipSuccess) return ECT_E_DEVICE;
     const ImageDesc& d = p.h_desc[image];
     for (int64_t k = 0; k < take; ++k) {
-        // every record starts with its coordinates, the value follows the n-th
-        // (three-axis records for n <= 3)
-        const double* rec = (const double*)(buf.data() + pb * k);
-        const int nx = n == 4 ? 4 : 3;
-        for (int a = 0; a < n; ++a)
-            coords[k * n + a] = (int32_t)std::lrint((rec[a] - d.origin[a]) / d.spacing[a]);
-        values[k] = (int32_t)rec[nx];
+        for (int a = 0; a < n; ++a) coords[k * n + a] = (int32_t)((buf[(size_t)k].code >> d.kshift[a]) & d.kmask[a]);
+        values[k] = buf[(size_t)k].val;
     }
     return ECT_OK;
 }

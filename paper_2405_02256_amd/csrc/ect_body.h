@@ -55,8 +55,8 @@ __device__ __forceinline__ int bin_closed(double uu, const double* s_thr, int M,
 // Stream points [p0, p1) of one list and add sign * (critical value) into the
 // histogram of every direction dd with use[dd].
 template <int N, int MODE, int TD>
-__device__ __forceinline__ void accumulate_list(const PointT<N>* __restrict__ pts, int64_t p0, int64_t p1,
-                                                const double (&xi)[TD][N], const bool (&use)[TD],
+__device__ __forceinline__ void accumulate_list(const ListEntry* __restrict__ pts, const ImageDesc& d, int64_t p0,
+                                                int64_t p1, const double (&xi)[TD][N], const bool (&use)[TD],
                                                 const double* s_thr, int M, int32_t* s_hist, int32_t sign = 1) {
     const double t0 = s_thr[0], t1 = s_thr[M - 1];
     const double inv = (M > 1 && t1 > t0) ? (double)(M - 1) / (t1 - t0) : 0.0;
@@ -65,12 +65,15 @@ __device__ __forceinline__ void accumulate_list(const PointT<N>* __restrict__ pt
     constexpr int U = 4;
     const int64_t nt = blockDim.x;
     for (int64_t p = p0 + threadIdx.x; p < p1; p += nt * U) {
-        PointT<N> pt[U];
+        ListEntry en[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t pp = p + (int64_t)u * nt;
-            if (pp < p1) pt[u] = pts[pp];
+            if (pp < p1) en[u] = pts[pp];
         }
+        PointT<N> pt[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) pt[u] = decode_entry<N>(en[u], d);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (p + (int64_t)u * nt >= p1) break;
@@ -132,13 +135,13 @@ __device__ __forceinline__ void accumulate_radon(const EctArgs& a, int64_t img, 
     const int M = a.M;
     const int64_t c0 = a.list_off[img * a.NL + e], c1 = a.list_off[(img + 1) * a.NL + e];
     const int64_t cl = c1 - c0;
-    accumulate_list<N, kBinPoint>(list_points<N>(a.points, a.capacity, e), c0 + cl * chunk / chunks,
+    accumulate_list<N, kBinPoint>(list_entries(a.points, a.capacity, e), a.desc[img], c0 + cl * chunk / chunks,
                                   c0 + cl * (chunk + 1) / chunks, xi, use, s_thr, M, s_point);
     const bool mirrored = (e >> (N - 1)) & 1;
     const int l = (1 << N) + (mirrored ? (e ^ full) : e);
     const int64_t o0 = a.list_off[img * a.NL + l], o1 = a.list_off[(img + 1) * a.NL + l];
     const int64_t ol = o1 - o0;
-    accumulate_list<N, kBinOpen>(list_points<N>(a.points, a.capacity, l), o0 + ol * chunk / chunks,
+    accumulate_list<N, kBinOpen>(list_entries(a.points, a.capacity, l), a.desc[img], o0 + ol * chunk / chunks,
                                  o0 + ol * (chunk + 1) / chunks, xi, use, s_thr, M, s_hist, mirrored ? 1 : -1);
 }
 
@@ -243,7 +246,7 @@ __device__ __forceinline__ void ect_direct_block(const EctArgs& a, int64_t group
             } else {
                 const int64_t p0 = s_loff[0][b], p1 = s_loff[1][b];
                 const int64_t len = p1 - p0;
-                accumulate_list<N, kBinClosed>(list_points<N>(a.points, a.capacity, b), p0 + len * c / chunks,
+                accumulate_list<N, kBinClosed>(list_entries(a.points, a.capacity, b), a.desc[img], p0 + len * c / chunks,
                                                p0 + len * (c + 1) / chunks, xi, use, s_thr, M, s_hist);
             }
         }

@@ -101,7 +101,8 @@ __global__ void __launch_bounds__(kEctThreads) ect_kernel(EctArgs a) {
         accumulate_radon<N>(a, img, b, 0, 1, xi, use, s_thr, s_hist, s_point);
     } else {
         const int64_t p0 = a.list_off[img * a.NL + b], p1 = a.list_off[(img + 1) * a.NL + b];
-        accumulate_list<N, kBinClosed>(list_points<N>(a.points, a.capacity, b), p0, p1, xi, use, s_thr, M, s_hist);
+        accumulate_list<N, kBinClosed>(list_entries(a.points, a.capacity, b), a.desc[img], p0, p1, xi, use, s_thr, M,
+                                       s_hist);
     }
     __syncthreads();
     write_rows(a, nd, s_row, s_valid, s_hist, RADON ? s_point : nullptr);
@@ -158,10 +159,11 @@ __global__ void __launch_bounds__(kBatchThreads) ect_batch_kernel(EctArgs a) {
     if (qn == 0) return;
     const QRecT<N>* recs = (const QRecT<N>*)a.recs + (int64_t)b * a.count;
     const int64_t p0 = a.list_off[img * a.NL + b], p1 = a.list_off[(img + 1) * a.NL + b];
-    const PointT<N>* __restrict__ pts = list_points<N>(a.points, a.capacity, b);
+    const ListEntry* __restrict__ pts = list_entries(a.points, a.capacity, b);
+    const ImageDesc& dsc = a.desc[img];
 
     // the list's first stage of points is requested with the thresholds
-    PointT<N> nxt{};
+    ListEntry nxt{0u, 0};
     if (p0 + tid < p1) nxt = pts[p0 + tid];
     const double* thr = a.thresholds + (a.thr_per_image ? img * M : 0);
     int bad = 0;
@@ -223,9 +225,10 @@ __global__ void __launch_bounds__(kBatchThreads) ect_batch_kernel(EctArgs a) {
         for (int64_t base = p0; base < p1; base += kBatchThreads) {
             const int cnt = (int)min<int64_t>(kBatchThreads, p1 - base);
             if (tid < cnt) {
+                const PointT<N> pt = decode_entry<N>(nxt, dsc);
 #pragma unroll
-                for (int c = 0; c < N; ++c) s_px[tid * N + c] = nxt.x[c];
-                s_pv[tid] = (int32_t)nxt.val;
+                for (int c = 0; c < N; ++c) s_px[tid * N + c] = pt.x[c];
+                s_pv[tid] = nxt.val;
             }
             __syncthreads();
             // next stage, or after the last one the list's start for the next pass

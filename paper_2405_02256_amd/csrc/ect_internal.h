@@ -27,10 +27,9 @@ __host__ __device__ constexpr int num_classical(int n) { return 1 << n; }
 __host__ __device__ constexpr int num_ordinary(int n) { return 1 << (n - 1); }
 __host__ __device__ constexpr int num_lists(int n) { return num_classical(n) + num_ordinary(n); }
 
-// One critical point as the evaluation kernels read it: canonical FP64
-// vertex coordinates (x_a = fma(h_a, k_a, o_a); unused axes 0) and its
-// critical value.  32 bytes for images of up to three axes, so a wave reads
-// one point with one scalar load; four-axis images use 48-byte records.
+// One critical point as the evaluation kernels use it (in registers and
+// LDS): canonical FP64 vertex coordinates (x_a = fma(h_a, k_a, o_a); unused
+// axes 0) and its critical value.
 struct alignas(32) Point {
     double x[3];
     double val;
@@ -44,12 +43,21 @@ template <int N> struct PointSel { using type = Point; };
 template <> struct PointSel<4> { using type = Point4; };
 template <int N> using PointT = typename PointSel<N>::type;
 
-inline size_t point_bytes(int ndim) { return ndim == 4 ? sizeof(Point4) : sizeof(Point); }
+// One critical point as the lists store it: the vertex index k packed into
+// one 32-bit word (axis a in the bit field of width kbits[a] at kshift[a],
+// the same fields for every image of a plan) and the critical value.  The
+// coordinates are rebuilt with the canonical fma when a kernel stages the
+// point, so the evaluation sees exactly the FP64 values a full record would
+// hold, from a quarter of the bytes.
+struct alignas(8) ListEntry {
+    uint32_t code;
+    int32_t val;
+};
+inline size_t entry_bytes() { return sizeof(ListEntry); }
 
-// The points of list l (lists are regions of `capacity` records).
-template <int N>
-__host__ __device__ __forceinline__ const PointT<N>* list_points(const void* base, int64_t capacity, int64_t l) {
-    return (const PointT<N>*)base + l * capacity;
+// The entries of list l (lists are regions of `capacity` entries).
+__host__ __device__ __forceinline__ const ListEntry* list_entries(const void* base, int64_t capacity, int64_t l) {
+    return (const ListEntry*)base + l * capacity;
 }
 
 // Per-image constants, uploaded once per plan.
@@ -60,11 +68,33 @@ struct alignas(16) ImageDesc {
     int32_t dims[kMaxDim];  // pixels per axis (1 for unused axes)
     int32_t N[kMaxDim];     // top cells per axis
     int32_t V[kMaxDim];     // vertices per axis (N + 1)
-    int32_t pad;
+    uint32_t kshift[kMaxDim];   // list entries: bit offset of axis a's vertex index
+    uint32_t kmask[kMaxDim];    // and its mask (0 for unused axes)
     double origin[kMaxDim];
     double spacing[kMaxDim];
     double lo[kMaxDim], hi[kMaxDim];   // vertex coordinate range per axis (lo <= hi)
 };
+
+// Packed vertex index of an entry (k_a < 2^kbits[a]).
+__host__ __device__ __forceinline__ uint32_t entry_code(const ImageDesc& d, const int* k, int n) {
+    uint32_t c = 0;
+    for (int a = 0; a < n; ++a) c |= (uint32_t)k[a] << d.kshift[a];
+    return c;
+}
+
+// The point of an entry: vertex index from the bit fields, canonical FP64
+// coordinates (the same fma as everywhere else), value.
+template <int N>
+__device__ __forceinline__ PointT<N> decode_entry(const ListEntry e, const ImageDesc& d) {
+    PointT<N> p{};
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        const uint32_t k = (e.code >> d.kshift[a]) & d.kmask[a];
+        p.x[a] = __fma_rn(d.spacing[a], (double)k, d.origin[a]);
+    }
+    p.val = (double)e.val;
+    return p;
+}
 
 // Layout of the precompute workspace (byte offsets from its base).
 struct PlanLayout {
@@ -74,7 +104,7 @@ struct PlanLayout {
     size_t tile_img;        // int32[num_tiles]: the image each precompute tile belongs to
     size_t list_off;        // int64[(num_images + 1) * NL]: start of image i in list l
     size_t status;          // uint64 ordered-compaction status words: tiles, group totals, carries (x NL)
-    size_t points;          // PointT<n>[NL * capacity]
+    size_t points;          // ListEntry[NL * capacity]
     size_t packed;          // uint32[num_tiles * NL * tile_verts]: three-pass plans of 8/16-bit pixels
     size_t packed_bytes;    // 0: no packed region (the write pass classifies again)
     size_t total;

@@ -55,7 +55,7 @@ __device__ __forceinline__ int64_t bucket_start(const int64_t* offsets, int64_t 
 }
 
 struct EctArgs {
-    const void* points;       // PointT<n> records
+    const void* points;       // ListEntry records
     const int64_t* list_off;
     const ImageDesc* desc;
     int64_t capacity;
@@ -108,7 +108,7 @@ hipError_t launch_ect(int ndim, const EctArgs& a, int64_t grid, int64_t direct_g
 constexpr int kJi0SmallCoeffs = 10;   // FP32-path small-argument Ji0 polynomial
 
 struct HybridArgs {
-    const void* points;       // PointT<n> records
+    const void* points;       // ListEntry records
     const int64_t* list_off;
     const ImageDesc* desc;
     int64_t capacity;

@@ -73,6 +73,7 @@ template <int N>
 __device__ __forceinline__ int64_t row_info(const ExactArgs& a, int64_t r, ExactRow& ri) {
     constexpr int B = 1 << N, full = B - 1;
     const int64_t img = row_image(a, r);
+    ri.img = img;
     const double* v = a.vecs + (a.offsets ? r : r % a.count) * N;
     int ok = 1;
 #pragma unroll
@@ -253,7 +254,7 @@ __device__ __forceinline__ uint32_t order_key32(float f) {
 // receives the staging indices of ranks t*I .. t*I+I-1 (ranks past n:
 // padding).
 template <int N, int I>
-__device__ __forceinline__ void sort_tile(const PointT<N>* __restrict__ pts, int64_t n, int32_t sign, Dir<N> xi,
+__device__ __forceinline__ void sort_tile(const ListEntry* __restrict__ pts, const ImageDesc* dsc, int64_t n, int32_t sign, Dir<N> xi,
                                           uint32_t (&idx)[I], RowShared& sh) {
     uint32_t key32[I];
 #pragma unroll
@@ -262,7 +263,7 @@ __device__ __forceinline__ void sort_tile(const PointT<N>* __restrict__ pts, int
         key32[u] = 0xFFFFFFFFu;
         idx[u] = (uint32_t)j;
         if (j < n) {
-            const PointT<N> pt = pts[j];
+            const PointT<N> pt = decode_entry<N>(pts[j], *dsc);
             const double p = project<N>(xi.v, pt.x);
             sh.key[j] = order_key(p);
             sh.val[j] = sign * (int32_t)pt.val;
@@ -375,10 +376,10 @@ __device__ __forceinline__ void merge_runs(const uint64_t* __restrict__ ka, cons
 
 // Sort one tile of a long list and store it, in order, at ka/va.
 template <int N, int I>
-__device__ __noinline__ void store_tile(const PointT<N>* pts, int64_t m, int32_t sign, Dir<N> xi,
+__device__ __noinline__ void store_tile(const ListEntry* pts, const ImageDesc* dsc, int64_t m, int32_t sign, Dir<N> xi,
                                         uint64_t* ka, int32_t* va, RowShared& sh) {
     uint32_t idx[I];
-    sort_tile<N, I>(pts, m, sign, xi, idx, sh);
+    sort_tile<N, I>(pts, dsc, m, sign, xi, idx, sh);
 #pragma unroll
     for (int u = 0; u < I; ++u) {
         const int64_t i = (int64_t)threadIdx.x * I + u;
@@ -393,14 +394,14 @@ __device__ __noinline__ void store_tile(const PointT<N>* pts, int64_t m, int32_t
 // A list longer than one tile: sorted tiles into workspace A, pairwise merges
 // between A and B, then the merge of equal keys from memory.
 template <int N>
-__device__ __noinline__ int64_t build_long(const PointT<N>* pts, int64_t n, int32_t sign, Dir<N> xi, uint64_t* ka,
+__device__ __noinline__ int64_t build_long(const ListEntry* pts, const ImageDesc* dsc, int64_t n, int32_t sign, Dir<N> xi, uint64_t* ka,
                                            int32_t* va, uint64_t* kb, int32_t* vb, double* out_T, int32_t* out_E,
                                            RowShared& sh) {
     for (int64_t c0 = 0; c0 < n; c0 += kTile) {
         const int64_t m = n - c0 < kTile ? n - c0 : kTile;
-        if (m <= kFinThreads) store_tile<N, 1>(pts + c0, m, sign, xi, ka + c0, va + c0, sh);
-        else if (m <= 4 * kFinThreads) store_tile<N, 4>(pts + c0, m, sign, xi, ka + c0, va + c0, sh);
-        else store_tile<N, kTileItems>(pts + c0, m, sign, xi, ka + c0, va + c0, sh);
+        if (m <= kFinThreads) store_tile<N, 1>(pts + c0, dsc, m, sign, xi, ka + c0, va + c0, sh);
+        else if (m <= 4 * kFinThreads) store_tile<N, 4>(pts + c0, dsc, m, sign, xi, ka + c0, va + c0, sh);
+        else store_tile<N, kTileItems>(pts + c0, dsc, m, sign, xi, ka + c0, va + c0, sh);
     }
     for (int64_t width = kTile; width < n; width *= 2) {
         for (int64_t lo = 0; lo < n; lo += 2 * width) {
@@ -418,23 +419,23 @@ __device__ __noinline__ int64_t build_long(const PointT<N>* pts, int64_t n, int3
 
 // Distinct entries of one list (n points at pts), values times sign.
 template <int N, int I>
-__device__ __noinline__ int64_t build_tile(const PointT<N>* pts, int64_t n, int32_t sign, Dir<N> xi,
+__device__ __noinline__ int64_t build_tile(const ListEntry* pts, const ImageDesc* dsc, int64_t n, int32_t sign, Dir<N> xi,
                                            double* out_T, int32_t* out_E, RowShared& sh) {
     uint32_t idx[I];
-    sort_tile<N, I>(pts, n, sign, xi, idx, sh);
+    sort_tile<N, I>(pts, dsc, n, sign, xi, idx, sh);
     return merge_tile<I>(idx, n, out_T, out_E, sh);
 }
 
 template <int N>
-__device__ int64_t build_segment(const ExactArgs& a, const PointT<N>* pts, int64_t n, int32_t sign, Dir<N> xi,
+__device__ int64_t build_segment(const ExactArgs& a, const ListEntry* pts, const ImageDesc* dsc, int64_t n, int32_t sign, Dir<N> xi,
                                  int64_t w0, double* out_T, int32_t* out_E, RowShared& sh) {
     if (n <= 0) return 0;
-    if (n <= kFinThreads) return build_tile<N, 1>(pts, n, sign, xi, out_T, out_E, sh);
-    if (n <= 2 * kFinThreads) return build_tile<N, 2>(pts, n, sign, xi, out_T, out_E, sh);
-    if (n <= 4 * kFinThreads) return build_tile<N, 4>(pts, n, sign, xi, out_T, out_E, sh);
-    if (n <= 6 * kFinThreads) return build_tile<N, 6>(pts, n, sign, xi, out_T, out_E, sh);
-    if (n <= kTile) return build_tile<N, kTileItems>(pts, n, sign, xi, out_T, out_E, sh);
-    return build_long<N>(pts, n, sign, xi, a.keys_a + w0, a.vals_a + w0, a.keys_b + w0, a.vals_b + w0, out_T, out_E,
+    if (n <= kFinThreads) return build_tile<N, 1>(pts, dsc, n, sign, xi, out_T, out_E, sh);
+    if (n <= 2 * kFinThreads) return build_tile<N, 2>(pts, dsc, n, sign, xi, out_T, out_E, sh);
+    if (n <= 4 * kFinThreads) return build_tile<N, 4>(pts, dsc, n, sign, xi, out_T, out_E, sh);
+    if (n <= 6 * kFinThreads) return build_tile<N, 6>(pts, dsc, n, sign, xi, out_T, out_E, sh);
+    if (n <= kTile) return build_tile<N, kTileItems>(pts, dsc, n, sign, xi, out_T, out_E, sh);
+    return build_long<N>(pts, dsc, n, sign, xi, a.keys_a + w0, a.vals_a + w0, a.keys_b + w0, a.vals_b + w0, out_T, out_E,
                          sh);
 }
 
@@ -490,7 +491,8 @@ __global__ void __launch_bounds__(kFinThreads, 4) exact_kernel(ExactArgs a) {
     Dir<N> xi;
 #pragma unroll
     for (int c = 0; c < N; ++c) xi.v[c] = ri.xi[c];
-    const PointT<N>* pts = (const PointT<N>*)a.points;
+    const ListEntry* pts = (const ListEntry*)a.points;
+    const ImageDesc* dsc = a.desc + ri.img;
     if (part == 0) {
         if (threadIdx.x == 0) {
             a.T[base] = -HUGE_VAL;
@@ -498,15 +500,15 @@ __global__ void __launch_bounds__(kFinThreads, 4) exact_kernel(ExactArgs a) {
         }
         int64_t d = 0;
         if (ri.valid == 1) {
-            if (radon) d = build_segment<N>(a, pts + ri.po, ri.no, ri.sign_o, xi, base, a.T + base + 1,
+            if (radon) d = build_segment<N>(a, pts + ri.po, dsc, ri.no, ri.sign_o, xi, base, a.T + base + 1,
                                             a.E + base + 1, sh);
-            else d = build_segment<N>(a, pts + ri.pc, ri.nc, 1, xi, base, a.T + base + 1, a.E + base + 1, sh);
+            else d = build_segment<N>(a, pts + ri.pc, dsc, ri.nc, 1, xi, base, a.T + base + 1, a.E + base + 1, sh);
         }
         if (threadIdx.x == 0) a.len[radon ? 2 * r : r] = d + 1;
     } else {
         const int64_t w0 = base + ri.no + 1;
         int64_t d = 0;
-        if (ri.valid == 1) d = build_segment<N>(a, pts + ri.pc, ri.nc, 1, xi, w0, a.ct + w0, a.cum + w0, sh);
+        if (ri.valid == 1) d = build_segment<N>(a, pts + ri.pc, dsc, ri.nc, 1, xi, w0, a.ct + w0, a.cum + w0, sh);
         if (threadIdx.x == 0) a.len[2 * r + 1] = d;
     }
 }

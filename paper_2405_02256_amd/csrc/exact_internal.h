@@ -11,12 +11,14 @@ struct alignas(8) ExactRow {
     int64_t base;     // first output entry of the row
     int64_t pc, po;   // first classical / ordinary point (index into the point array)
     int64_t nc, no;   // their counts (no: Radon only)
+    int64_t img;      // the row's image
     int32_t sign_o;   // factor on the stored ordinary values (Radon)
     int32_t valid;    // 1 usable, 0 non-finite direction, -1 offsets leave no room
 };
 
 struct ExactArgs {
-    const void* points;       // PointT<n> records
+    const void* points;       // ListEntry records
+    const ImageDesc* desc;    // per image: the entries' bit fields, origin and spacing
     const int64_t* list_off;
     int64_t list_capacity;    // entries per list region of the point array
     int num_images;

@@ -422,22 +422,27 @@ __device__ __forceinline__ void hybrid_block(const HybridArgs& a, int64_t item) 
     const int64_t qn = a.bcnt[a.offsets == nullptr ? b : e];
     const int64_t qi = t * kHybridTile + lane;
     const bool active = qi < qn;
-    const PointT<N>* __restrict__ pts = list_points<N>(a.points, a.capacity, l);
+    const ListEntry* __restrict__ pts = list_entries(a.points, a.capacity, l);
+    const ImageDesc& d = a.desc[img];
     const int64_t c0 = p0 + c * C, c1 = min(p1, c0 + C);
 
     Query<N> q;
     int64_t row;
     setup_query<N, MASK, PREC, BWD>(a, img, b, qi, active, q, row);
     if constexpr (slot_used<MASK, BWD, N>(kSlotShift)) {
-        if (c0 < c1) init_shift<N, PREC>(q, pts[c0]);
+        if (c0 < c1) init_shift<N, PREC>(q, decode_entry<N>(pts[c0], d));
     }
 
     double acc[kAccSlots] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    // each stage's entries are loaded during the previous stage's work
+    ListEntry nx{0u, 0};
+    if (c0 + tid < c1) nx = pts[c0 + tid];
     for (int64_t base = c0; base < c1; base += kHybridStage) {
         const int cnt = (int)min<int64_t>(kHybridStage, c1 - base);
         __syncthreads();
-        if (tid < cnt) s_pts[tid] = pts[base + tid];
+        if (tid < cnt) s_pts[tid] = decode_entry<N>(nx, d);
         __syncthreads();
+        if (base + kHybridStage + tid < c1) nx = pts[base + kHybridStage + tid];
         // wave-uniform loop bounds (scalar counter)
         const int k0 = __builtin_amdgcn_readfirstlane(wave);
         if constexpr (BWD && PREC == ECT_FP32) {

@@ -432,17 +432,13 @@ __device__ __forceinline__ uint64_t tile_offsets(int32_t (*s_cnt)[kPrecomputeThr
 template <int N>
 __device__ __forceinline__ void emit_points(const TileValues<N>& tv,
                                             int32_t (*s_cnt)[kPrecomputeThreads / 64][TileValues<N>::NL],
-                                            const int64_t* s_base, PointT<N>* __restrict__ points,
+                                            const int64_t* s_base, ListEntry* __restrict__ points,
                                             int64_t capacity) {
     constexpr int NL = TileValues<N>::NL;
-    constexpr int NX = sizeof(PointT<N>::x) / sizeof(double);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < TileValues<N>::J; ++j) {
-        PointT<N> pt{};
-#pragma unroll
-        for (int a = 0; a < NX; ++a)
-            pt.x[a] = a < N ? __fma_rn(tv.d.spacing[a], (double)tv.kk[j][a], tv.d.origin[a]) : 0.0;
+        const uint32_t code = entry_code(tv.d, tv.kk[j], N);
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
             const bool nz = tv.vals[j][l] != 0;
@@ -450,8 +446,7 @@ __device__ __forceinline__ void emit_points(const TileValues<N>& tv,
             if (nz) {
                 const int rank = __popcll(b & ((1ull << lane) - 1ull));
                 const int64_t pos_l = s_base[l] + s_cnt[j][wave][l] + rank;
-                pt.val = (double)tv.vals[j][l];
-                points[(int64_t)l * capacity + pos_l] = pt;
+                points[(int64_t)l * capacity + pos_l] = ListEntry{code, tv.vals[j][l]};
             }
         }
     }
@@ -501,7 +496,7 @@ __global__ void __launch_bounds__(kPrecomputeThreads)
 classify_compact(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
                  const int32_t* __restrict__ tile_img, int32_t num_images, int64_t num_tiles,
                  uint32_t* __restrict__ err, uint64_t* __restrict__ run_ctr, uint64_t* __restrict__ status,
-                 uint64_t* __restrict__ gstatus, int64_t* __restrict__ list_off, PointT<N>* __restrict__ points,
+                 uint64_t* __restrict__ gstatus, int64_t* __restrict__ list_off, ListEntry* __restrict__ points,
                  int64_t capacity, QueryPrep prep, uint64_t* __restrict__ prep_word) {
     constexpr int NL = TileValues<N>::NL;
     constexpr int W = kPrecomputeThreads / 64;
@@ -832,9 +827,8 @@ template <int N>
 __global__ void __launch_bounds__(kPrecomputeThreads)
 tile_copy_kernel(const ImageDesc* __restrict__ descs, const int32_t* __restrict__ tile_img, int64_t num_tiles,
                  const int32_t* __restrict__ counts, const int64_t* __restrict__ prefix,
-                 const uint32_t* __restrict__ packed, PointT<N>* __restrict__ points, int64_t capacity) {
+                 const uint32_t* __restrict__ packed, ListEntry* __restrict__ points, int64_t capacity) {
     constexpr int NL = TileValues<N>::NL;
-    constexpr int NX = sizeof(PointT<N>::x) / sizeof(double);
     const int lane = threadIdx.x & 63;
     const int64_t tile =
         (int64_t)blockIdx.x * (kPrecomputeThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -889,11 +883,7 @@ tile_copy_kernel(const ImageDesc* __restrict__ descs, const int32_t* __restrict_
             k[2] = (int)r2;
             k[3] = (int)q2;
         }
-        PointT<N> pt{};
-#pragma unroll
-        for (int a = 0; a < NX; ++a) pt.x[a] = a < N ? __fma_rn(d.spacing[a], (double)k[a], d.origin[a]) : 0.0;
-        pt.val = (double)((int32_t)w >> kPackShift);
-        points[(int64_t)l * capacity + bl + pos] = pt;
+        points[(int64_t)l * capacity + bl + pos] = ListEntry{entry_code(d, k, N), (int32_t)w >> kPackShift};
     }
 }
 
@@ -1022,7 +1012,7 @@ template <int N, int CONS, typename T>
 __global__ void __launch_bounds__(kPrecomputeThreads)
 tile_write_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__ descs,
                   const int32_t* __restrict__ tile_img, int32_t num_images, const int64_t* __restrict__ prefix,
-                  PointT<N>* __restrict__ points, int64_t capacity) {
+                  ListEntry* __restrict__ points, int64_t capacity) {
     constexpr int NL = TileValues<N>::NL;
     __shared__ int32_t s_cnt[TileValues<N>::J][kPrecomputeThreads / 64][NL];
     __shared__ int64_t s_base[NL];
@@ -1064,7 +1054,7 @@ hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream, const Que
     const int64_t* ts = (const int64_t*)(p.ws + L.tile_start);
     const int32_t* ti = (const int32_t*)(p.ws + L.tile_img);
     int64_t* lo = (int64_t*)(p.ws + L.list_off);
-    PointT<N>* pts = (PointT<N>*)(p.ws + L.points);
+    ListEntry* pts = (ListEntry*)(p.ws + L.points);
     if (single) {
         if (N == 2 && L.num_tiles <= kFlatTiles && L.num_tiles <= p.precompute_grid_flat) {
             // one more workgroup when it buckets the queries (the caller checked that it fits)

@@ -32,8 +32,8 @@ fused pass; then per kernel:
 Precompute is bounded by HBM: bytes = pixels read once + each list entry
 written as packed coordinates and value (2n + 2 bytes: uint16 per axis and an
 int16 value) + list offsets.  The exact representations are priced against HBM with
-the bytes the operation cannot avoid: 32 B per critical point read and 12 B
-per output entry (T and E) written.
+the bytes the operation cannot avoid: 8 B per critical point read (the
+stored list entry) and 12 B per output entry (T and E) written.
 """
 from __future__ import annotations
 

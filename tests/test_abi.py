@@ -69,10 +69,16 @@ def test_precompute_size_query_and_validation(N):
     b2, keep2 = _batch(N, dims=((40, 50),))
     need2 = ctypes.c_size_t(0)
     assert N.ect_precompute(b2, None, need2, 0)[0] == N.ECT_OK and need2.value > need.value
-    # four axes are accepted (16 classical + 8 ordinary lists of 48-byte records)
+    # four axes are accepted (16 classical + 8 ordinary lists of 8-byte entries)
     b4, keep4 = _batch(N, ndim=4, dims=((3, 4, 2, 5),))
     need4 = ctypes.c_size_t(0)
-    assert N.ect_precompute(b4, None, need4, 0)[0] == N.ECT_OK and need4.value > 24 * 48 * (4 * 5 * 3 * 6)
+    assert N.ect_precompute(b4, None, need4, 0)[0] == N.ECT_OK and need4.value > 24 * 8 * (4 * 5 * 3 * 6)
+    # the packed vertex index needs 3 x 11 bits for 1025^3 vertices: refused
+    b5, keep5 = _batch(N, ndim=3, dims=((1024, 1024, 1024),))
+    assert N.ect_precompute(b5, None, ctypes.c_size_t(0), 0)[0] == N.ECT_E_UNSUPPORTED
+    # 1023^3 pixels (1024^3 vertices) fit in 30 bits
+    b6, keep6 = _batch(N, ndim=3, dims=((1023, 1023, 1023),))
+    assert N.ect_precompute(b6, None, ctypes.c_size_t(0), 0)[0] == N.ECT_OK
     for kw in (dict(ndim=5, dims=((2, 2, 2, 2, 2),)), dict(ndim=1, dims=((3,),)), dict(dims=((0, 5),)),
                dict(dtype=7), dict(cons=3), dict(pixels=0)):
         bb, k = _batch(N, **kw)
