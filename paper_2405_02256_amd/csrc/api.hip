@@ -24,7 +24,7 @@ constexpr int64_t kAheadMaxRows = 65536;   // query rows one workgroup buckets i
 constexpr int kAccSlotsHost = 5;  // doubles per query in a partial record (sums and the Laplace shift)
 
 struct EvalLayout {
-    size_t recs, bcnt, item_off, tile_off, params, partials, gpart, gspart, total;
+    size_t recs, bcnt, item_off, tile_off, params, partials, tile_ent, gpart, gspart, total;
     int64_t groups, entries, grid, capacity, tiles;
 };
 
@@ -101,6 +101,7 @@ void layout_hybrid(const Plan& p, const ect_query_set& q, bool backward, EvalLay
     L->grid = tiles * maxch;
     L->capacity = L->grid;
     L->partials = o; o = align_up(o + sizeof(double) * kAccSlotsHost * kHybridTile * std::max<int64_t>(L->capacity, 1), kAlign);
+    L->tile_ent = o; o = align_up(o + sizeof(int32_t) * std::max<int64_t>(tiles, 1), kAlign);
     // gradient partials are reserved for forward calls too, so that one
     // workspace size serves a forward call and the backward call reusing its
     // buckets and work list
@@ -719,6 +720,7 @@ static ect_status hybrid_common(ect_plan plan, unsigned mask, double s, int32_t 
     a.item_off = (const int64_t*)(w + L.item_off);
     a.tile_off = (const int64_t*)(w + L.tile_off);
     a.params = (const int64_t*)(w + L.params);
+    a.tile_ent = (int32_t*)(w + L.tile_ent);
     a.partials = (double*)(w + L.partials);
     a.err = err;
     // s = 0: every requested output is the constant-kernel limit sum D <xi, x>

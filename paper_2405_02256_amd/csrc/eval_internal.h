@@ -134,6 +134,7 @@ struct HybridArgs {
     const int64_t* tile_off;
     const int64_t* params;    // [0] items, [1] tiles, [2] chunk
     double* partials;
+    int32_t* tile_ent;        // per query tile: its work-list entry if split into chunks, else -1
     uint32_t* err;
     double ji0c[kJi0SmallCoeffs];   // filled at launch (kernel arguments live in scalar registers)
 };

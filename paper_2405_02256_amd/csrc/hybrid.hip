@@ -422,6 +422,8 @@ __device__ __forceinline__ void hybrid_block(const HybridArgs& a, int64_t item) 
     const int64_t qn = a.bcnt[a.offsets == nullptr ? b : e];
     const int64_t qi = t * kHybridTile + lane;
     const bool active = qi < qn;
+    // the tile's first chunk tells the reduction which entry the tile belongs to
+    const int64_t tslot = (c == 0 && tid == 0) ? a.tile_off[e] + t : -1;
     const ListEntry* __restrict__ pts = list_entries(a.points, a.capacity, l);
     const ImageDesc& d = a.desc[img];
     const int64_t c0 = p0 + c * C, c1 = min(p1, c0 + C);
@@ -478,8 +480,10 @@ __device__ __forceinline__ void hybrid_block(const HybridArgs& a, int64_t item) 
 #pragma unroll
         for (int k = 0; k < kAccSlots; ++k)
             if (slot_used<MASK, BWD, N>(k)) a.partials[partial_index(item, k, lane)] = acc[k];
+        if (tslot >= 0) a.tile_ent[tslot] = (int32_t)e;
         return;
     }
+    if (tslot >= 0) a.tile_ent[tslot] = -1;
     if (active) finalize<N, MASK, PREC, BWD>(a, q, row, acc);
 }
 
@@ -522,8 +526,11 @@ __global__ void __launch_bounds__(kHybridThreads) hybrid_reduce_kernel(HybridArg
     const int wave = tid / kHybridTile;
     const int64_t tile = blockIdx.x;
     if (tile >= a.params[1]) return;
+    // written by the tile's first chunk in the evaluation launch (-1: one chunk)
+    const int32_t ent = a.tile_ent[tile];
+    if (ent < 0) return;
     const int64_t C = a.params[2];
-    const int64_t e = find_entry(a.tile_off, (int64_t)a.num_images * P, tile);
+    const int64_t e = ent;
     const int64_t img = e / P;
     const int b = (int)(e % P);
     const int64_t t = tile - a.tile_off[e];
