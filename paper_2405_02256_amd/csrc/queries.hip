@@ -126,43 +126,70 @@ __device__ __forceinline__ void block_exclusive_scan2(int64_t& a, int64_t& b, in
 // each split into ceil(points / chunk) point chunks (chunk == 0: no split).
 // Writes the item prefix over entries, the query-tile prefix and the chunk
 // size actually used.  If the item count exceeds `capacity`, the chunk size is
-// doubled until it fits.  Runs on one 1024-thread workgroup.
-__device__ void build_worklist(int num_images, int B, int list_base, int NL, int shared_queries,
+// doubled until it fits.  Runs on one 1024-thread workgroup.  Entry
+// e = j * 1024 + tid is thread tid's j-th (coalesced loads); up to
+// kWorklistRun entries per thread stay in registers, their loads in flight
+// together, and the prefixes of all j come from one joint block scan.
+constexpr int kWorklistRun = 8;
+
+__device__ __forceinline__ void build_worklist(int num_images, int B, int list_base, int NL, int shared_queries,
                                const int32_t* bcnt, const int64_t* __restrict__ list_off,
                                const int32_t* np_lds, int qtile,
                                int64_t chunk0, int64_t capacity, uint32_t* __restrict__ err,
                                int64_t* __restrict__ item_off, int64_t* __restrict__ tile_off,
                                int64_t* __restrict__ params) {
     __shared__ int64_t s_a[17], s_b[17];
-    __shared__ int64_t s_red[16];
+    __shared__ int64_t s_wi[16][kWorklistRun], s_wt[16][kWorklistRun];
+    __shared__ int64_t s_ji[kWorklistRun + 1], s_jt[kWorklistRun + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t E = (int64_t)num_images * B;
-    auto entry = [&](int64_t e, int64_t chunk, int64_t* items, int64_t* tiles) {
+    auto tiles_pts = [&](int64_t e, int64_t* t, int64_t* np) {
         const int64_t i = e / B, b = e % B;
         const int64_t q = bcnt[shared_queries ? b : e];
-        const int64_t t = (q + qtile - 1) / qtile;
-        const int64_t np = np_lds ? (int64_t)np_lds[e]
-                                  : list_off[(i + 1) * NL + list_base + b] - list_off[i * NL + list_base + b];
+        *t = (q + qtile - 1) / qtile;
+        *np = np_lds ? (int64_t)np_lds[e]
+                     : list_off[(i + 1) * NL + list_base + b] - list_off[i * NL + list_base + b];
+    };
+    auto items_of = [](int64_t t, int64_t np, int64_t chunk) {
         int64_t ch = chunk > 0 ? (np + chunk - 1) / chunk : 1;
         if (ch < 1) ch = 1;  // an empty list still gets one item per tile, which writes zeros
-        *items = t * ch;
-        *tiles = t;
+        return t * ch;
     };
+    const int64_t R = (E + 1023) / 1024;
+    const bool in_regs = R <= kWorklistRun;
+    // (tiles and points of an entry, and the item and tile counts of a wave,
+    // fit 32 bits: the launch grid is below 2^32 items)
+    uint32_t rt[kWorklistRun], rn[kWorklistRun];
+    if (in_regs) {
+#pragma unroll
+        for (int j = 0; j < kWorklistRun; ++j) {
+            int64_t t = 0, np = 0;
+            const int64_t e = (int64_t)j * 1024 + tid;
+            if (e < E) tiles_pts(e, &t, &np);
+            rt[j] = (uint32_t)t;
+            rn[j] = (uint32_t)np;
+        }
+    }
     int64_t chunk = chunk0;
     if (chunk > 0 && capacity > 0) {
-        for (int attempt = 0; attempt < 40; ++attempt) {
+        for (int attempt = 0;; ++attempt) {
             int64_t my = 0;
-            for (int64_t e = tid; e < E; e += 1024) {
-                int64_t it, tl;
-                entry(e, chunk, &it, &tl);
-                my += it;
+            if (in_regs) {
+#pragma unroll
+                for (int j = 0; j < kWorklistRun; ++j) my += items_of(rt[j], rn[j], chunk);
+            } else {
+                for (int64_t e = tid; e < E; e += 1024) {
+                    int64_t t, np;
+                    tiles_pts(e, &t, &np);
+                    my += items_of(t, np, chunk);
+                }
             }
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) my += __shfl_xor(my, off, 64);
-            if (lane == 0) s_red[wave] = my;
+            if (lane == 0) s_a[wave] = my;
             __syncthreads();
             int64_t total = 0;
-            for (int w = 0; w < 16; ++w) total += s_red[w];
+            for (int w = 0; w < 16; ++w) total += s_a[w];
             __syncthreads();
             if (total <= capacity) break;
             chunk *= 2;
@@ -180,18 +207,84 @@ __device__ void build_worklist(int num_images, int B, int list_base, int NL, int
         }
     }
     int64_t carry_i = 0, carry_t = 0;
-    for (int64_t base = 0; base < E; base += 1024) {
-        const int64_t e = base + tid;
-        int64_t it = 0, tl = 0;
-        if (e < E) entry(e, chunk, &it, &tl);
-        int64_t tot_i, tot_t;
-        block_exclusive_scan2(it, tl, &tot_i, &tot_t, s_a, s_b);
-        if (e < E) {
-            item_off[e] = carry_i + it;
-            tile_off[e] = carry_t + tl;
+    if (in_regs) {
+        // inclusive wave scans of every j, then the wave totals and the j
+        // totals in LDS: one pass for all rows
+        uint32_t vi[kWorklistRun], si[kWorklistRun], st[kWorklistRun];
+#pragma unroll
+        for (int j = 0; j < kWorklistRun; ++j) {
+            vi[j] = (uint32_t)items_of(rt[j], rn[j], chunk);
+            si[j] = vi[j];
+            st[j] = rt[j];
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t a = __shfl_up(si[j], off, 64), b = __shfl_up(st[j], off, 64);
+                if (lane >= off) {
+                    si[j] += a;
+                    st[j] += b;
+                }
+            }
+            if (lane == 63) {
+                s_wi[wave][j] = (int64_t)si[j];
+                s_wt[wave][j] = (int64_t)st[j];
+            }
         }
-        carry_i += tot_i;
-        carry_t += tot_t;
+        __syncthreads();
+        // thread j < R: exclusive prefix of the 16 wave totals of row j, and the row's total
+        if (tid < kWorklistRun) {
+            int64_t ri = 0, rtt = 0;
+            for (int w = 0; w < 16; ++w) {
+                const int64_t ci = s_wi[w][tid], ct = s_wt[w][tid];
+                s_wi[w][tid] = ri;
+                s_wt[w][tid] = rtt;
+                ri += ci;
+                rtt += ct;
+            }
+            s_ji[tid] = ri;
+            s_jt[tid] = rtt;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int64_t ri = 0, rtt = 0;
+            for (int j = 0; j < kWorklistRun; ++j) {
+                const int64_t ci = s_ji[j], ct = s_jt[j];
+                s_ji[j] = ri;
+                s_jt[j] = rtt;
+                ri += ci;
+                rtt += ct;
+            }
+            s_ji[kWorklistRun] = ri;
+            s_jt[kWorklistRun] = rtt;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kWorklistRun; ++j) {
+            const int64_t e = (int64_t)j * 1024 + tid;
+            if (e < E) {
+                item_off[e] = s_ji[j] + s_wi[wave][j] + (int64_t)(si[j] - vi[j]);
+                tile_off[e] = s_jt[j] + s_wt[wave][j] + (int64_t)(st[j] - rt[j]);
+            }
+        }
+        carry_i = s_ji[kWorklistRun];
+        carry_t = s_jt[kWorklistRun];
+    } else {
+        for (int64_t base = 0; base < E; base += 1024) {
+            const int64_t e = base + tid;
+            int64_t it = 0, tl = 0;
+            if (e < E) {
+                int64_t np;
+                tiles_pts(e, &tl, &np);
+                it = items_of(tl, np, chunk);
+            }
+            int64_t tot_i, tot_t;
+            block_exclusive_scan2(it, tl, &tot_i, &tot_t, s_a, s_b);
+            if (e < E) {
+                item_off[e] = carry_i + it;
+                tile_off[e] = carry_t + tl;
+            }
+            carry_i += tot_i;
+            carry_t += tot_t;
+        }
     }
     if (tid == 0) {
         item_off[E] = carry_i;
