@@ -287,6 +287,54 @@ __device__ __forceinline__ double scale_of(const HybridArgs& a) {
     return s;
 }
 
+// Laplace alone, FP32 forward: the exponent of a pair is <c xi, x> - mL with
+// the direction pre-scaled by the kernel factor c (one fma per axis), and
+// the points of one wave are taken G at a time: when no lane's group needs
+// the shift raised (the common case, one compare per group) the G terms are
+// summed without a branch, else one point after another as accumulate_point
+// does.  The sums take each lane's points in the same order either way.
+template <int N>
+__device__ __forceinline__ double lap_exponent(const PointT<N>& pt, const double (&cx)[N], double mL) {
+    double e = fma(pt.x[0], cx[0], -mL);
+#pragma unroll
+    for (int a = 1; a < N; ++a) e = fma(pt.x[a], cx[a], e);
+    return e;
+}
+
+template <int N>
+__device__ __forceinline__ void lap_point_slow(const PointT<N>& pt, const double (&cx)[N], Query<N>& q, double* acc) {
+    double ex = lap_exponent<N>(pt, cx, q.mL);
+    if (ex > kShiftSlack) {
+        raise_shift<N, kL, ECT_FP32, false>(q, acc, ex);
+        ex = lap_exponent<N>(pt, cx, q.mL);
+    }
+    acc[kSlotL] = fma(pt.val, exp2_split(ex), acc[kSlotL]);
+}
+
+template <int N>
+__device__ __forceinline__ void laplace_stage_f32(const PointT<N>* s_pts, int k0, int cnt, const double (&cx)[N],
+                                                  Query<N>& q, double* acc) {
+    constexpr int G = 4;
+    int k = k0;
+    for (; k + (G - 1) * kHybridSplit < cnt; k += G * kHybridSplit) {
+        double ex[G], v[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const PointT<N>& pt = s_pts[k + g * kHybridSplit];
+            ex[g] = lap_exponent<N>(pt, cx, q.mL);
+            v[g] = pt.val;
+        }
+        const double mx = fmax(fmax(ex[0], ex[1]), fmax(ex[2], ex[3]));
+        if (__builtin_amdgcn_ballot_w64(mx > kShiftSlack) == 0) {
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc[kSlotL] = fma(v[g], exp2_split(ex[g]), acc[kSlotL]);
+        } else {
+            for (int g = 0; g < G; ++g) lap_point_slow<N>(s_pts[k + g * kHybridSplit], cx, q, acc);
+        }
+    }
+    for (; k < cnt; k += kHybridSplit) lap_point_slow<N>(s_pts[k], cx, q, acc);
+}
+
 // Per-query set-up shared by the evaluation and reduction kernels.
 template <int N, int MASK, int PREC, bool BWD>
 __device__ __forceinline__ void setup_query(const HybridArgs& a, int64_t img, int b, int64_t qi, bool active,
@@ -436,6 +484,9 @@ __device__ __forceinline__ void hybrid_block(const HybridArgs& a, int64_t item) 
     }
 
     double acc[kAccSlots] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double cx[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) cx[k] = q.cL * q.xi[k];
     // each stage's entries are loaded during the previous stage's work
     ListEntry nx{0u, 0};
     if (c0 + tid < c1) nx = pts[c0 + tid];
@@ -454,6 +505,8 @@ __device__ __forceinline__ void hybrid_block(const HybridArgs& a, int64_t item) 
 #pragma unroll 2
             for (int k = k0; k < cnt; k += kHybridSplit)
                 accumulate_point<N, MASK, PREC, BWD>(s_pts[k], q, acc, a.ji0c);
+        } else if constexpr (MASK == kL && PREC == ECT_FP32 && !BWD) {
+            laplace_stage_f32<N>(s_pts, k0, cnt, cx, q, acc);
         } else {
             for (int k = k0; k < cnt; k += kHybridSplit)
                 accumulate_point<N, MASK, PREC, BWD>(s_pts[k], q, acc, a.ji0c);
