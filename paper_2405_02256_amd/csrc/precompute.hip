@@ -668,38 +668,45 @@ __device__ __forceinline__ void flush_entries(const uint32_t* buf, uint32_t n, c
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
 
-// The 16 rounds of one tile; STAGED: pixels from the staged rows in LDS
-// (row rr at (rr - rlo) * W0), else from global memory.  base[l]: slots
-// written for list l (scalar), buffered[l]: entries waiting in buf.
+// The values of one vertex per lane (k0, k1; `valid` lanes only) and their
+// entries: per list, the wave's nonzero entries in lane order are appended to
+// the list's LDS buffer (flushed in whole-wave stores when it fills).
 template <typename T, bool STAGED>
-__device__ __forceinline__ void count_rounds_2p(const unsigned char* lds, const T* __restrict__ img, int rlo, int rhi,
-                                                int W0, int V0, int N0, int N1, int nv, int q64, int r64, int k0,
-                                                int k1, char* __restrict__ slots, uint32_t* base, uint32_t* buf) {
-    constexpr int NL = 6, R = tile_verts(2) / 64;
-    const int lane = threadIdx.x & 63;
-    uint32_t buffered[NL];
-#pragma unroll
-    for (int l = 0; l < NL; ++l) buffered[l] = 0u;
-    auto pix = [&](int rr, int cc) -> int32_t {
+struct CountCtx {
+    const unsigned char* lds;
+    const T* __restrict__ img;
+    int rlo, rhi, W0, N0, N1;
+    char* __restrict__ slots;
+    uint32_t* base;
+    uint32_t* buf;
+    uint32_t buffered[6];
+
+    __device__ __forceinline__ int32_t pix(int rr, int cc) const {
         if constexpr (STAGED) {
             const uint32_t o = __umul24((uint32_t)(rr - rlo), (uint32_t)W0) + (uint32_t)cc;
             return (int32_t)((const T*)lds)[o];
         } else {
             return px_load(img, (uint32_t)(rr * W0 + cc));
         }
-    };
-#pragma unroll 2
-    for (int round = 0; round < R; ++round) {
-        const bool valid = round * 64 + lane < nv;
-        // clamped into the image and into the staged rows (lanes past the
-        // last vertex included)
+    }
+
+    // the four pixels of a vertex star, clamped into the image and into the
+    // staged rows (lanes past the last vertex included)
+    __device__ __forceinline__ void pixels(int k0, int k1, int32_t& pa, int32_t& pb, int32_t& pc, int32_t& pd) const {
         const int c0 = max(k0 - 1, 0), c1 = min(k0, W0 - 1);
         const int r0 = min(max(k1 - 1, 0), rhi), r1 = min(k1, rhi);
-        const int32_t pa = pix(r0, c0), pb = pix(r0, c1), pc = pix(r1, c0), pd = pix(r1, c1);
+        pa = pix(r0, c0);
+        pb = pix(r0, c1);
+        pc = pix(r1, c0);
+        pd = pix(r1, c1);
+    }
+
+    __device__ __forceinline__ void classify(int k0, int k1, bool valid, uint32_t local, int32_t pa, int32_t pb,
+                                             int32_t pc, int32_t pd) {
+        constexpr int NL = 6;
         int32_t L[4], D[2];
         vertex_values_2p(pa, pb, pc, pd, k0, k1, N0, N1, L, D);
         const int32_t vals[NL] = {L[0], L[1], L[2], L[3], D[0], D[1]};
-        const uint32_t local = (uint32_t)(round * 64 + lane);
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
             const bool nz = valid && vals[l] != 0;
@@ -723,20 +730,97 @@ __device__ __forceinline__ void count_rounds_2p(const unsigned char* lds, const 
                 }
             }
         }
-        k0 += r64;
-        k1 += q64;
-        if (k0 >= V0) {
-            k0 -= V0;
-            ++k1;
-        }
     }
-    if (slots) {
+
+    __device__ __forceinline__ void finish() {
+        if (slots) {
 #pragma unroll
-        for (int l = 0; l < NL; ++l) {
-            if (buffered[l] != 0u) flush_entries(buf + l * kEntryBuf, buffered[l], slots, base[l]);
-            base[l] += buffered[l];
+            for (int l = 0; l < 6; ++l) {
+                if (buffered[l] != 0u) flush_entries(buf + l * kEntryBuf, buffered[l], slots, base[l]);
+                base[l] += buffered[l];
+            }
         }
     }
+};
+
+// The 16 rounds of one tile; STAGED: pixels from the staged rows in LDS
+// (row rr at (rr - rlo) * W0), else from global memory.  base[l]: slots
+// written for list l (scalar).  With staged rows, a vertex whose four pixels
+// are equal and whose star lies inside the image has only zero values, so a
+// round only tests its vertices and queues the others in LDS (in vertex
+// order); full waves of queued vertices are then classified, which keeps the
+// entries in vertex order and spends the classification on the vertices near
+// the edge of a region or of the image.
+template <typename T, bool STAGED>
+__device__ __forceinline__ void count_rounds_2p(const unsigned char* lds, const T* __restrict__ img, int rlo, int rhi,
+                                                int W0, int V0, int N0, int N1, int nv, int q64, int r64, int k0,
+                                                int k1, int64_t first, char* __restrict__ slots, uint32_t* base,
+                                                uint32_t* buf, uint32_t* queue) {
+    constexpr int R = tile_verts(2) / 64;
+    const int lane = threadIdx.x & 63;
+    CountCtx<T, STAGED> cx{lds, img, rlo, rhi, W0, N0, N1, slots, base, buf, {0u, 0u, 0u, 0u, 0u, 0u}};
+    if constexpr (!STAGED) {
+#pragma unroll 2
+        for (int round = 0; round < R; ++round) {
+            const bool valid = round * 64 + lane < nv;
+            int32_t pa, pb, pc, pd;
+            cx.pixels(k0, k1, pa, pb, pc, pd);
+            cx.classify(k0, k1, valid, (uint32_t)(round * 64 + lane), pa, pb, pc, pd);
+            k0 += r64;
+            k1 += q64;
+            if (k0 >= V0) {
+                k0 -= V0;
+                ++k1;
+            }
+        }
+    } else {
+        // queue entry: k0 (21 bits) | k1 - the tile's first row (11 bits);
+        // lane 0 holds the tile's first vertex
+        const int row0 = __builtin_amdgcn_readfirstlane(k1);
+        uint32_t qn = 0;   // queued vertices (uniform, below 64 between rounds)
+        auto drain = [&](uint32_t n) {
+            // classify queue[0, n) (n <= 64), then move the rest to the front
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            const bool on = (uint32_t)lane < n;
+            const uint32_t e = on ? queue[lane] : 0u;
+            const int qk0 = (int)(e & 0x1FFFFFu), qk1 = row0 + (int)(e >> 21);
+            const uint32_t local = (uint32_t)((int64_t)qk1 * V0 + qk0 - first);
+            int32_t pa, pb, pc, pd;
+            cx.pixels(qk0, qk1, pa, pb, pc, pd);
+            cx.classify(qk0, qk1, on, local, pa, pb, pc, pd);
+            const uint32_t rest = qn - n;
+            const uint32_t t = (uint32_t)lane < rest ? queue[n + lane] : 0u;
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            if ((uint32_t)lane < rest) queue[lane] = t;
+            qn = rest;
+        };
+        for (int round = 0; round < R; ++round) {
+            const bool valid = round * 64 + lane < nv;
+            int32_t pa, pb, pc, pd;
+            cx.pixels(k0, k1, pa, pb, pc, pd);
+            const bool inside = (uint32_t)(k0 - 1) < (uint32_t)(N0 - 1) && (uint32_t)(k1 - 1) < (uint32_t)(N1 - 1);
+            const bool flat = pa == pb && pa == pc && pa == pd;
+            const bool need = valid && !(inside && flat);
+            const uint64_t m = __builtin_amdgcn_ballot_w64(need);
+            if (m != 0) {
+                if (need) {
+                    const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, qn));
+                    queue[pos] = (uint32_t)k0 | ((uint32_t)(k1 - row0) << 21);
+                }
+                qn += (uint32_t)__builtin_popcountll(m);
+                if (qn >= 64u) drain(64u);
+            }
+            k0 += r64;
+            k1 += q64;
+            if (k0 >= V0) {
+                k0 -= V0;
+                ++k1;
+            }
+        }
+        if (qn > 0u) drain(qn);
+    }
+    cx.finish();
 }
 
 template <typename T>
@@ -747,6 +831,7 @@ tile_count_2p_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__
     constexpr int NL = 6, R = tile_verts(2) / 64;
     __shared__ uint32_t s_span[kPrecomputeThreads / 64][kSpanDwords];
     __shared__ uint32_t s_ent[kPrecomputeThreads / 64][NL * kEntryBuf];
+    __shared__ uint32_t s_queue[kPrecomputeThreads / 64][128];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t tile = (int64_t)blockIdx.x * (kPrecomputeThreads / 64) + wave;
     if (tile >= num_tiles) return;
@@ -804,11 +889,11 @@ tile_count_2p_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__
 #pragma unroll
     for (int l = 0; l < NL; ++l) base[l] = (uint32_t)(l * tile_verts(2));
     if (staged)
-        count_rounds_2p<T, true>(s_bytes + mis, img, rlo, rhi, W0, V0, N0, N1, nv, q64, (int)r64, k0, k1, slots, base,
-                                 s_ent[wave]);
+        count_rounds_2p<T, true>(s_bytes + mis, img, rlo, rhi, W0, V0, N0, N1, nv, q64, (int)r64, k0, k1, first,
+                                 slots, base, s_ent[wave], s_queue[wave]);
     else
-        count_rounds_2p<T, false>(s_bytes, img, rlo, rhi, W0, V0, N0, N1, nv, q64, (int)r64, k0, k1, slots, base,
-                                  s_ent[wave]);
+        count_rounds_2p<T, false>(s_bytes, img, rlo, rhi, W0, V0, N0, N1, nv, q64, (int)r64, k0, k1, first, slots,
+                                  base, s_ent[wave], s_queue[wave]);
     int32_t c = 0;
 #pragma unroll
     for (int l = 0; l < NL; ++l)
