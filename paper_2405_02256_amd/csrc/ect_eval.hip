@@ -118,41 +118,44 @@ __global__ void __launch_bounds__(kEctWideThreads) ect_direct_kernel(EctArgs a, 
 // Shared direction sets over many images with short lists: one workgroup per
 // (image, sign vector b).  The set was bucketed by sign vector once (records
 // in input order within a bucket); the workgroup takes its bucket's
-// directions kBatchDirs at a time and gives each of them 256 / D lanes (D the
-// pass's directions rounded up to a power of two), which split the list
-// between them.  So every lane works even when a list holds a few dozen
-// points, where streaming the list across the lanes for a few directions
-// leaves most of them idle.
+// directions kBatchDirs at a time.  The list is streamed a stage of 256
+// points at a time, one point per thread (decoded once, the next stage's
+// entries in flight), and each thread bins its point on every direction of
+// the pass in turn (the point stays in registers, the directions come from
+// LDS).
 //
-// The list is staged in LDS a stage of 256 points at a time (one coalesced
-// load per thread, the next stage's loads in flight while this one is
-// binned).  A lane bins the canonical projection of each of its points on its
-// direction: the arithmetic guess for evenly spaced thresholds is checked
-// against the two thresholds around it with one LDS read (the thresholds sit
-// between -inf and +inf sentinels), and only a wrong guess searches; the
-// critical value is added into the direction's LDS histogram (integer
-// atomics; rows at an odd stride, so that neighbouring directions' bins fall
-// in different banks).  The histograms are then prefix-summed in place by
-// eight threads per row (a sequential scan of a segment, then a scan of the
-// eight segment totals), and written out row by row with consecutive threads
-// on consecutive thresholds.  Same bins as the other threshold kernels, so the
-// rows are the same integers.
+// Binning: the first j with t_j >= u.  The workgroup measures, once, how far
+// its thresholds stray from evenly spaced ones, in bins (tol, plus a margin
+// for the rounding of the position p = (u - t_0)(M - 1)/(t_{M-1} - t_0)).
+// With p clamped to [-1/2, M - 1/2], when p is farther than tol from every
+// integer the bin is ceil(p) exactly (0 below t_0, M above t_{M-1});
+// otherwise (a projection within rounding of a threshold, or uneven
+// thresholds) it is searched among the thresholds in LDS, which sit between
+// -inf and +inf sentinels.  The critical value is added into the direction's
+// LDS histogram (integer atomics; rows of M + 1 bins at an odd stride, bin M
+// unused); a non-finite direction bins as the zero vector (its row is not
+// written).  Thread t takes the pass's directions starting at t mod nd, so
+// the lanes of one atomic spread over the rows.  The histograms are then
+// prefix-summed in place by kSeg threads per row (a sequential scan of a
+// segment, then a scan of the segment totals), and written out row by row
+// with consecutive threads on consecutive thresholds.  Same bins as the other
+// threshold kernels, so the rows are the same integers.
 template <int N>
 __global__ void __launch_bounds__(kBatchThreads) ect_batch_kernel(EctArgs a) {
     extern __shared__ __align__(16) char smem[];
     constexpr int B = 1 << N;
     constexpr int kSeg = kBatchThreads / kBatchDirs;   // threads per histogram row in the scan
+    constexpr int W = kBatchThreads / 64;
     const int M = a.M;
-    const int MS = M | 1;
+    const int MS = batch_row_stride(M);
     double* s_tp = (double*)smem;                                          // [M + 2]
     int32_t* s_hist = (int32_t*)(smem + batch_hist_offset(M));             // [kBatchDirs][MS]
-    __shared__ double s_px[kBatchThreads * N];
-    __shared__ int32_t s_pv[kBatchThreads];
-    __shared__ double s_xi[kBatchDirs][kMaxDim];
+    __shared__ double s_xi[kBatchDirs][N];
     __shared__ int64_t s_row[kBatchDirs];
     __shared__ int s_valid[kBatchDirs];
+    __shared__ double s_dev[W];
 
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t img = blockIdx.x / B;
     const int b = (int)(blockIdx.x % B);
     const int64_t qn = a.bcnt[b];
@@ -181,6 +184,20 @@ __global__ void __launch_bounds__(kBatchThreads) ect_batch_kernel(EctArgs a) {
     if (bad && tid == 0 && b == 0) raise_error(a.err, ECT_DEVERR_THRESHOLDS);
     const double t0 = s_tp[1], t1 = s_tp[M];
     const double inv = (M > 1 && t1 > t0) ? (double)(M - 1) / (t1 - t0) : 0.0;
+    const double t0i = t0 * inv;
+    // largest distance of a threshold's position from its index, in bins
+    double dv = 0.0;
+    for (int j = tid; j < M; j += kBatchThreads) dv = fmax(dv, fabs(fma(s_tp[j + 1], inv, -t0i) - (double)j));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dv = fmax(dv, __shfl_xor(dv, off, 64));
+    if (lane == 0) s_dev[wave] = dv;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < W; ++w) dv = fmax(dv, s_dev[w]);
+    // the position's rounding (fma of |u inv| and |t0 inv|, both below M + |t0 inv| + 1 where it matters)
+    // and the measurement's own; tol >= 0.5 never certifies
+    const double tol = (inv > 0.0 && !bad) ? dv + ((double)M + 4.0 + fabs(t0i)) * 0x1p-48 : 1.0;
+    const double p_hi = (double)M - 0.5;
     const int seg = (M + kSeg - 1) / kSeg;
     const int rows_per_pass = M <= kBatchThreads ? kBatchThreads / M : 1;
     const int wrow = M <= kBatchThreads ? tid / M : 0;
@@ -189,19 +206,27 @@ __global__ void __launch_bounds__(kBatchThreads) ect_batch_kernel(EctArgs a) {
     for (int64_t q0 = 0; q0 < qn; q0 += kBatchDirs) {
         const int nd = (int)min<int64_t>(kBatchDirs, qn - q0);
         if (tid < kBatchDirs) {
+            // a non-finite direction bins as the zero vector (its row is not written)
             int ok = 0;
             int64_t row = -1;
+            double v[N];
+#pragma unroll
+            for (int c = 0; c < N; ++c) v[c] = 0.0;
             if (tid < nd) {
                 const QRecT<N> r = recs[q0 + tid];
                 row = img * a.count + (r.code >> 1);
                 ok = 1;
 #pragma unroll
-                for (int c = 0; c < N; ++c) {
-                    s_xi[tid][c] = r.v[c];
-                    ok &= isfinite(r.v[c]) ? 1 : 0;
+                for (int c = 0; c < N; ++c) ok &= isfinite(r.v[c]) ? 1 : 0;
+                if (ok) {
+#pragma unroll
+                    for (int c = 0; c < N; ++c) v[c] = r.v[c];
+                } else if (img == 0) {
+                    raise_error(a.err, ECT_DEVERR_NONFINITE);
                 }
-                if (!ok && img == 0) raise_error(a.err, ECT_DEVERR_NONFINITE);
             }
+#pragma unroll
+            for (int c = 0; c < N; ++c) s_xi[tid][c] = v[c];
             s_row[tid] = row;
             s_valid[tid] = ok && !bad;
         }
@@ -210,50 +235,39 @@ __global__ void __launch_bounds__(kBatchThreads) ect_batch_kernel(EctArgs a) {
             const int n4 = kBatchDirs * MS / 4;   // kBatchDirs is a multiple of 4
             for (int j = tid; j < n4; j += kBatchThreads) h4[j] = make_int4(0, 0, 0, 0);
         }
-        // lanes per direction: D = nd rounded up to a power of two
-        int D = 1;
-        while (D < nd) D <<= 1;
-        const int d = tid & (D - 1);
-        const int lanes = kBatchThreads / D;
-        const int slice = tid / D;
         __syncthreads();
-        const bool active = d < nd && s_valid[d];
-        double xi[N];
-#pragma unroll
-        for (int c = 0; c < N; ++c) xi[c] = s_xi[d][c];
-        int32_t* hist = s_hist + d * MS;
+        const int dd0 = tid % nd;
         for (int64_t base = p0; base < p1; base += kBatchThreads) {
-            const int cnt = (int)min<int64_t>(kBatchThreads, p1 - base);
-            if (tid < cnt) {
-                const PointT<N> pt = decode_entry<N>(nxt, dsc);
-#pragma unroll
-                for (int c = 0; c < N; ++c) s_px[tid * N + c] = pt.x[c];
-                s_pv[tid] = nxt.val;
-            }
-            __syncthreads();
+            const bool has = base + tid < p1;
+            const PointT<N> pt = decode_entry<N>(nxt, dsc);
+            const int32_t val = nxt.val;
             // next stage, or after the last one the list's start for the next pass
             const int64_t nb = base + kBatchThreads;
             const int64_t src = nb < p1 ? nb + tid : (q0 + kBatchDirs < qn ? p0 + tid : p1);
             if (src < p1) nxt = pts[src];
-            if (active) {
-                for (int k = slice; k < cnt; k += lanes) {
-                    double x[N];
-#pragma unroll
-                    for (int c = 0; c < N; ++c) x[c] = s_px[k * N + c];
-                    const double u = project<N>(xi, x);
-                    double g = ceil((u - t0) * inv);
-                    g = fmin(fmax(g, 0.0), (double)M);
-                    int j = (int)g;                         // candidate: t_{j-1} < u <= t_j
-                    const double lo = s_tp[j], hi = s_tp[j + 1];
-                    if (!((lo < u) & (u <= hi))) {          // a guess off by a threshold or more (rare)
+            if (has) {
+                // thread t starts at direction t mod nd and walks through all nd of
+                // them, so one instruction's atomics spread over the directions'
+                // rows instead of piling onto the few bins of one direction
+                int dd = dd0;
+                for (int step = 0; step < nd; ++step, dd = (dd + 1 == nd) ? 0 : dd + 1) {
+                    const double u = project<N>(s_xi[dd], pt.x);
+                    // position clamped to [-1/2, M - 1/2]: below t_0 or above
+                    // t_{M-1} (by more than tol) the bin is 0 or M and certain
+                    const double p = fmin(fmax(fma(u, inv, -t0i), -0.5), p_hi);
+                    const double g = ceil(p);
+                    const double rr = g - p;
+                    int j = (int)g;
+                    if (!(fmin(rr, 1.0 - rr) > tol)) {
+                        // within rounding of a threshold: search (t_{j-1} < u <= t_j)
                         while (j > 0 && s_tp[j] >= u) --j;
                         while (j < M && s_tp[j + 1] < u) ++j;
                     }
-                    if (j < M) atomicAdd(&hist[j], s_pv[k]);
+                    atomicAdd(&s_hist[dd * MS + j], val);   // bin M: above every threshold, not written
                 }
             }
-            __syncthreads();
         }
+        __syncthreads();
         // inclusive prefix sums in place: kSeg threads per row, a segment each
         {
             const int dd = tid / kSeg, part = tid % kSeg;

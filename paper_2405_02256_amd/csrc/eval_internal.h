@@ -92,8 +92,10 @@ constexpr int kBatchMaxThresholds = 256;
 __host__ __device__ constexpr size_t batch_hist_offset(int M) {
     return (sizeof(double) * (size_t)(M + 2) + 15) / 16 * 16;
 }
+// (a row has M + 1 bins, the last one catching projections above every threshold)
+__host__ __device__ constexpr int batch_row_stride(int M) { return (M + 1) | 1; }
 __host__ __device__ constexpr size_t batch_ect_lds(int M) {
-    return batch_hist_offset(M) + sizeof(int32_t) * (size_t)kBatchDirs * (size_t)(M | 1);
+    return batch_hist_offset(M) + sizeof(int32_t) * (size_t)kBatchDirs * (size_t)batch_row_stride(M);
 }
 // a.recs / a.bcnt hold the shared set bucketed by sign vector (launch_prepare).
 hipError_t launch_ect_batch(int ndim, const EctArgs& a, hipStream_t stream);

@@ -102,3 +102,27 @@ def test_batch_ect_3d_and_4d(mods):
     hv = [W.random_image(rng, tuple(int(v) for v in rng.integers(2, 4, size=4)), 3) for _ in range(40)]
     d4 = rng.standard_normal((24, 4))
     _check(A, N, hv, d4, np.linspace(-5.0, 5.0, 40))
+
+
+def test_batch_ect_ties_uneven_and_offset_thresholds(mods):
+    """Projections that land exactly on thresholds (axis and diagonal directions over half-integer vertex
+    coordinates and thresholds on the half-integer grid), thresholds that are far from evenly spaced, and a
+    coordinate frame far from the origin: every bin is the first threshold at or above the projection."""
+    A, N = mods
+    rng = np.random.default_rng(2504)
+    imgs = [W.binary_field(rng, (18, 15), 2.5) for _ in range(200)]
+    dirs = np.array([[1.0, 0.0], [0.0, 1.0], [1.0, 1.0], [-1.0, 1.0], [1.0, -2.0], [-0.5, -0.5],
+                     [2.0, 1.0], [0.0, -1.0], [-1.0, 0.0], [0.25, 0.75]])
+    _check(A, N, imgs, dirs, np.arange(-20.0, 20.25, 0.5))
+    uneven = np.sort(rng.uniform(-20.0, 20.0, size=90))
+    uneven[40:44] = uneven[40]                            # repeated thresholds
+    _check(A, N, imgs, dirs, uneven)
+    # far from the origin: vertex coordinates near 1e6, thresholds around them
+    org = np.array([1.0e6, -1.0e6])
+    plan = A.Plan([T(im) for im in imgs], origin=np.tile(org, (len(imgs), 1)))
+    thr = T(1.0e6 + np.arange(-20.0, 20.25, 0.5))
+    d = np.array([[1.0, 0.0], [1.0, 1e-9], [1.0, -1e-9], [1.0, 2e-9]])   # x_0 = 1e6 + k_0 against the grid
+    assert _uses_batch_kernel(A, N, plan, d, thr)
+    got = plan.ect(T(d), thr).cpu().numpy().reshape(len(imgs), len(d), -1)
+    for i in range(0, len(imgs), 37):
+        assert np.array_equal(got[i], O.ect(imgs[i], d, thr.cpu().numpy(), origin=org)), i
