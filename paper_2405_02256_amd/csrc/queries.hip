@@ -59,6 +59,16 @@ __device__ __forceinline__ int image_of(const O* off, int num_images, int64_t r)
     return lo;
 }
 
+// The same from global offsets, trying first the image that evenly sized
+// images would give (two independent loads confirm it); the search runs
+// only when the guess is wrong.
+__device__ __forceinline__ int image_of_guess(const int64_t* __restrict__ off, int num_images, int64_t r,
+                                              int64_t rows) {
+    const int g = (int)min<int64_t>((int64_t)num_images - 1, rows > 0 ? r * num_images / rows : 0);
+    if (off[g] <= r && off[g + 1] > r) return g;
+    return image_of(off, num_images, r);
+}
+
 template <int N>
 __device__ __forceinline__ int64_t classify_query(const double* __restrict__ vecs, const int64_t* __restrict__ offsets,
                                                   int64_t r, int64_t rows, int num_images, int mode_hybrid,
@@ -66,7 +76,7 @@ __device__ __forceinline__ int64_t classify_query(const double* __restrict__ vec
     int img = 0;
     int64_t r0 = 0, q = rows;
     if (offsets) {
-        img = image_of(offsets, num_images, r);
+        img = image_of_guess(offsets, num_images, r, rows);
         r0 = offsets[img];
         q = offsets[img + 1] - r0;
     }
