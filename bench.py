@@ -60,6 +60,10 @@ def parse():
                     help="skip the Radon transform and exact-representation measurements")
     ap.add_argument("--no-4d", action="store_true", help="skip the four-axis workload")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule knobs")
+    ap.add_argument("--traffic-json", nargs=5,
+                    metavar=("WORKLOAD", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write profiles/traffic_<WORKLOAD>.json from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE "
+                         "counter files of this build's bench run and of --calibrate-copy (no GPU needed)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (counter calibration) and exit")
     return ap.parse_args()
@@ -317,6 +321,55 @@ def dominant(stage_ms, models):
     roof["kernel"] = name
     roof["kernel_ms"] = stage_ms[name]
     return name, roof
+
+
+# kernels of each bench stage (a stage's launch = one launch of each)
+TRAFFIC_STAGES = {
+    "batch_4096": {"precompute": r"tile_count_2p_kernel|tile_block_\w+_kernel|tile_copy_kernel",
+                   "ect": r"ect_batch_kernel<2>", "hybrid": r"hybrid_kernel<2, 2, 0, false>"},
+    "grf_512": {"precompute": r"classify_compact<2, 0, unsigned char, true>",
+                "ect_hybrid_fused": r"ect_hybrid_kernel<2, 7, 0>", "hybrid_bwd_fourier": r"hybrid_kernel<2, 1, 0, true>",
+                "ect": r"ect_direct_kernel<2, false>", "hybrid_fused": r"hybrid_kernel<2, 7, 0, false>"},
+}
+
+
+def counter_means(path, counter):
+    """Mean value per dispatch of one counter for every kernel of a rocprofv3 counter_collection.csv."""
+    import csv
+    import collections
+    tot, disp = collections.defaultdict(float), collections.defaultdict(set)
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            k = r["Kernel_Name"]
+            tot[k] += float(r["Counter_Value"])
+            disp[k].add(r["Dispatch_Id"])
+    return {k: tot[k] / len(disp[k]) for k in tot}
+
+
+def write_traffic_json(workload, fetch_csv, write_csv, cfetch_csv, cwrite_csv):
+    """HBM bytes per launch of each bench stage: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by
+    what it reads for a plain device copy of known size."""
+    import re
+    nbytes = 256 << 20
+    cf, cw = counter_means(cfetch_csv, "FETCH_SIZE"), counter_means(cwrite_csv, "WRITE_SIZE")
+    f_scale = nbytes / (1024.0 * max(cf.values()))
+    w_scale = nbytes / (1024.0 * max(cw.values()))
+    fetch, write = counter_means(fetch_csv, "FETCH_SIZE"), counter_means(write_csv, "WRITE_SIZE")
+    out = {}
+    for stage, rx in TRAFFIC_STAGES[workload].items():
+        ks = [k for k in fetch if re.search(rx, k)]
+        if ks:
+            out[stage] = sum(1024.0 * (fetch[k] * f_scale + write.get(k, 0.0) * w_scale) for k in ks)
+    csrc = os.path.join(ROOT, "paper_2405_02256_amd", "csrc")
+    doc = {"source_digest": source_digest(sorted(os.path.join(csrc, f) for f in os.listdir(csrc))),
+           "bytes_per_launch": out, "fetch_scale": f_scale, "write_scale": w_scale,
+           "note": "FETCH_SIZE + WRITE_SIZE per launch, scaled by a plain 256 MiB device copy's readings"}
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    with open(path, "w") as f:
+        json.dump(doc, f, indent=1)
+    print(path)
 
 
 def traffic_for(workload, kernel):
@@ -837,6 +890,9 @@ def oracle_leg(rows, batch, grf, vol, diff, small):
 
 def main():
     args = parse()
+    if args.traffic_json:
+        write_traffic_json(*args.traffic_json)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
