@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--only-headline", action="store_true", help="measure the batched workload alone")
     ap.add_argument("--no-next", action="store_true",
                     help="skip the Radon transform and exact-representation measurements")
+    ap.add_argument("--rows", default="grf,volume,diff,small",
+                    help="comma-separated rows measured beside the headline (grf, volume, diff, small); "
+                         "the four-axis row follows --no-4d")
     ap.add_argument("--no-4d", action="store_true", help="skip the four-axis workload")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule knobs")
     ap.add_argument("--traffic-json", nargs=5,
@@ -921,24 +924,30 @@ def main():
     batch_row, roof, w4, gpu4 = bench_batch(args, dev, tuning)
     rows["batch"] = batch_row
     grf = vol = diff = small = None
+    sel = set(r.strip() for r in args.rows.split(",") if r.strip())
     if not args.only_headline:
-        tg = {}
-        rows["grf_512"], wg, gpug, plan_g, (dirs_g, thr_g, cg, og) = bench_grf(args, dev, tg)
-        rows["grf_512"]["tuning"] = tg
-        grf = (wg, gpug)
-        if not args.no_next:
-            log("Radon transform and exact representations (grf_512)")
-            rows["grf_512"]["radon_and_exact"] = measure_next(plan_g, wg, dirs_g, thr_g, 2, cg, og[0], args.steps)
-        del plan_g
-        log("volume_128")
-        rows["volume_128"], wv, gpuv = bench_volume(args, dev)
-        vol = (wv, gpuv)
-        log("diff_256")
-        rows["diff_256"], wd, gpud = bench_diff(args, dev)
-        diff = (wd, gpud)
-        log("small_binary")
-        rows["small_binary"], ws, gpus = bench_small(args, dev)
-        small = (ws, gpus)
+        if "grf" in sel:
+            tg = {}
+            rows["grf_512"], wg, gpug, plan_g, (dirs_g, thr_g, cg, og) = bench_grf(args, dev, tg)
+            rows["grf_512"]["tuning"] = tg
+            grf = (wg, gpug)
+            if not args.no_next:
+                log("Radon transform and exact representations (grf_512)")
+                rows["grf_512"]["radon_and_exact"] = measure_next(plan_g, wg, dirs_g, thr_g, 2, cg, og[0],
+                                                                  args.steps)
+            del plan_g
+        if "volume" in sel:
+            log("volume_128")
+            rows["volume_128"], wv, gpuv = bench_volume(args, dev)
+            vol = (wv, gpuv)
+        if "diff" in sel:
+            log("diff_256")
+            rows["diff_256"], wd, gpud = bench_diff(args, dev)
+            diff = (wd, gpud)
+        if "small" in sel:
+            log("small_binary")
+            rows["small_binary"], ws, gpus = bench_small(args, dev)
+            small = (ws, gpus)
         if not args.no_4d:
             log("four-axis workload")
             rows["four_axes"] = measure_4d(args.steps)

@@ -7,33 +7,35 @@ Expressed as FP32-FMA-equivalent FLOP (2 per lane-instruction) that is the
 peak; packed FP32 is not used (disabled at build time).
 
 Work per (query, critical point) pair is counted in VALU issue slots of the
-minimal arithmetic the method needs on this path, with a quarter-rate
-transcendental (sin, cos, exp2, rcp, rsq) counted as 4 slots.  The projection
-u = <xi, x> costs 2n-1 (one mul, n-1 fmas) and is shared by every kernel of a
-fused pass; then per kernel:
+minimal arithmetic the method needs on this path.  Every instruction takes one
+issue slot; a quarter-rate transcendental (sin, cos, exp2, rcp, rsq) also takes
+one, since its extra cycles run beside the following independent instructions
+(a three-axis Fourier-plus-Laplace pass measured above the issue rate when they
+were priced at four slots).  The projection u = <xi, x> costs 2n-1 (one mul,
+n-1 fmas) and is shared by every kernel of a fused pass; then per kernel:
 
   Fourier   phase u*s/(2 pi) 1, reduction to [0,1) 2 (floor, sub), cvt 1,
-            sin 4, cos 4, two (cvt + fma) 4                          -> 16
+            sin 1, cos 1, two (cvt + fma) 4                          -> 10
   Laplace   exponent fma 1, shift test 1, split 2 (floor, sub), cvt 1,
-            exp2 4, cvt 1, cvt-to-int 1, ldexp 1, fma 1               -> 13
+            exp2 1, cvt 1, cvt-to-int 1, ldexp 1, fma 1               -> 10
   Bessel    |z| < 8: z 1, v 2, degree-9 FP64 Horner 10, scale 1, cvt 2,
             sign 1, fma 1                                             -> 18
-            |z| >= 8: z 1, cvt 1, rcp 4, w 2, two degree-5 Horner 12,
-            phase reduction 4, cvt 1, sin 4, cos 4, rsq 4, combine 5,
-            sign 1, cvt + fma 2                                       -> 45
-  Fourier backward: phase and reduction 3, cvt 1, sin 4, cos 4, cvt 2,
-            cotangent combine 3, n fmas                               -> 17 + n
-  Laplace backward: the forward term 12 (its fma replaced by a mul),
-            n fmas                                                    -> 12 + n
+            |z| >= 8: z 1, cvt 1, rcp 1, w 2, two degree-5 Horner 12,
+            phase reduction 4, cvt 1, sin 1, cos 1, rsq 1, combine 5,
+            sign 1, cvt + fma 2                                       -> 33
+  Fourier backward: phase and reduction 3, cvt 1, sin 1, cos 1, cvt 2,
+            cotangent combine 3, n fmas                               -> 11 + n
+  Laplace backward: the forward term without its shift test and with a
+            mul for its fma 9, n fmas                                 -> 9 + n
   ECT       projection 2n-1, bin guess 6 (sub, mul, ceil, max, min, cvt),
             fix-up compares 2, LDS add 1                              -> 2n + 8
   Radon     as ECT plus one equality compare (the point or open-ray
             bin), over classical and ordinary points                  -> 2n + 9
 Precompute is bounded by HBM: bytes = pixels read once + each list entry
-written as packed coordinates and value (2n + 2 bytes: uint16 per axis and an
-int16 value) + list offsets.  The exact representations are priced against HBM with
-the bytes the operation cannot avoid: 8 B per critical point read (the
-stored list entry) and 12 B per output entry (T and E) written.
+written once (8 B: the packed vertex index and the int32 value) + list
+offsets.  The exact representations are priced against HBM with the bytes the
+operation cannot avoid: 8 B per critical point read (the stored list entry)
+and 12 B per output entry (T and E) written.
 """
 from __future__ import annotations
 
@@ -50,11 +52,11 @@ def slots_per_pair(kind: str, n: int, small_fraction: float = 1.0) -> float:
     if kind == "radon":
         return 2 * n + 9
     if kind == "fourier_bwd":
-        return (2 * n - 1) + 17 + n
+        return (2 * n - 1) + 11 + n
     if kind == "laplace_bwd":
-        return (2 * n - 1) + 12 + n
-    per = {"fourier": 16.0, "laplace": 13.0,
-           "bessel": small_fraction * 18.0 + (1.0 - small_fraction) * 45.0}
+        return (2 * n - 1) + 9 + n
+    per = {"fourier": 10.0, "laplace": 10.0,
+           "bessel": small_fraction * 18.0 + (1.0 - small_fraction) * 33.0}
     parts = kind.split("+")
     if any(p not in per for p in parts):
         raise ValueError(kind)
