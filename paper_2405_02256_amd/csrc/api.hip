@@ -615,7 +615,9 @@ ect_status ect_exact(ect_plan plan, ect_query_set dirs, int32_t kind, const int6
     a.T = T;
     a.E = E;
     a.len = len;
-    return from_hip(launch_exact(p.ndim, a, stream));
+    const int64_t max_len = kind == ECT_EXACT_ECT ? max_list(p, 0, num_classical(p.ndim))
+                                                  : max_list(p, 0, num_lists(p.ndim));
+    return from_hip(launch_exact(p.ndim, a, max_len, stream));
 }
 
 ect_status ect_exact_eval(int32_t kind, int64_t rows, const int64_t* row_off, const double* T, const int32_t* E,

@@ -14,15 +14,21 @@
 //
 // One workgroup builds one row in one launch: it reads the row's list (or
 // lists), turns each canonical FP64 projection into an order-preserving
-// 64-bit key, sorts (key, value) pairs with a block radix sort in LDS, merges
-// equal keys with a block scan of head flags and values and writes the
-// distinct entries.  A list longer than one LDS tile (4096 points) is sorted
-// tile by tile into the workspace and the sorted tiles are merged pairwise
-// there by the same workgroup (merge path), before the same merge of equal
-// keys.  For Radon, each classical entry then takes E' from a binary search
-// in the row's T.  Global memory written by the workgroup is read back by it
-// only after a workgroup barrier.
-#include <rocprim/block/block_radix_sort.hpp>
+// 64-bit key and sorts (key, value) pairs in LDS.  The sort is a bucket sort:
+// the projection range [lo, hi] of the tile is cut into about as many buckets
+// as the tile has points (a monotone map, so bucket order is key order), an
+// LDS histogram and a block scan place every point in its bucket, and a
+// point's place inside its bucket is the number of bucket members with
+// smaller keys.  Tiles whose largest bucket holds more than kBucketMax points
+// (projections clustered far below the range's resolution) are sorted by a
+// bitonic network instead, whose cost does not depend on the data.  A block
+// scan of head flags and values then merges equal keys and writes the
+// distinct entries.  A list longer than one LDS tile is sorted tile by tile
+// into the workspace and the sorted tiles are merged pairwise there by the
+// same workgroup (merge path), before the same merge of equal keys.  For
+// Radon, each classical entry then takes E' from a binary search in the
+// row's T.  Global memory written by the workgroup is read back by it only
+// after a workgroup barrier.
 #include <rocprim/device/device_scan.hpp>
 
 #include "exact_internal.h"
@@ -33,13 +39,14 @@ namespace {
 
 constexpr int kRowThreads = 256;
 constexpr int kFinThreads = 512;         // the row-building workgroup
+constexpr int kFinWaves = kFinThreads / 64;
 constexpr int kFinItems = 4;            // consecutive sorted entries per thread per step (long lists)
 constexpr int kFinStep = kFinThreads * kFinItems;
-constexpr int kTileItems = 8;           // keys per thread of the largest LDS sort
-constexpr int kTile = kFinThreads * kTileItems;
 constexpr int kMergeItems = 8;          // outputs per thread per step of a pairwise merge
+constexpr int kBucketMax = 64;          // largest bucket ranked by comparisons
 constexpr int kEvalThreads = 256;
 constexpr int kFixThreads = 256;
+constexpr int kFixSamples = 4096;       // entries of T a Radon fix-up workgroup stages
 constexpr uint64_t kTopBit = 0x8000000000000000ull;
 
 // Order-preserving key of a finite or infinite FP64 value (-0 taken as +0):
@@ -208,139 +215,324 @@ struct Dir {
     double v[N];
 };
 
-// Tiles are sorted on 32-bit keys carrying the point's staging index: first
-// on the FP32 rounding of the projection (monotone, so the result is ordered
-// up to projections that round to the same float); only when that leaves two
-// neighbours out of FP64 order is the tile sorted exactly, by the low then
-// (stably) the high half of the 64-bit key.  The keys and values themselves
-// stay in LDS and are read through the sorted indices.
-template <int I>
-using BlockSort = rocprim::block_radix_sort<uint32_t, kFinThreads, I, uint32_t>;
-
-union SortStorage {
-    typename BlockSort<1>::storage_type s1;
-    typename BlockSort<2>::storage_type s2;
-    typename BlockSort<4>::storage_type s4;
-    typename BlockSort<6>::storage_type s6;
-    typename BlockSort<kTileItems>::storage_type s8;
+// LDS of one tile of C points (C a power of two, a multiple of the workgroup
+// size): keys and values in sorted order once a sort returns, and the bucket
+// starts (start[b] = first slot of bucket b, start[nb] = points).
+template <int C>
+struct TileLds {
+    uint64_t key[C];
+    int32_t val[C];
+    int32_t start[C + 1];
 };
 
-struct RowShared {
-    SortStorage sort;
-    uint64_t key[kTile];           // staged keys and values of the tile, by load index
-    int32_t val[kTile];
-    uint64_t first[kFinThreads];   // first / last key of each thread after a sort
-    uint64_t last[kFinThreads];
-    int32_t wave[kFinThreads / 64][2];
-    ExactRow ri;
+// Small per-workgroup LDS: the wave totals of the striped scans and the
+// scratch of block_scan2.
+constexpr int kScanSlots = 128;   // rounds x waves of the largest striped scan
+constexpr int kMaxRuns = 64;     // runs of coarse buckets of one long list
+struct RowSmall {
+    int32_t tot[2][kScanSlots];
+    int32_t wave[kFinWaves][2];
+    int32_t run_b[kMaxRuns + 1];  // first coarse bucket and first point of each run
+    int32_t run_s[kMaxRuns + 1];
 };
 
-template <int I>
-__device__ __forceinline__ typename BlockSort<I>::storage_type& sort_storage(RowShared& sh) {
-    if constexpr (I == 1) return sh.sort.s1;
-    else if constexpr (I == 2) return sh.sort.s2;
-    else if constexpr (I == 4) return sh.sort.s4;
-    else if constexpr (I == 6) return sh.sort.s6;
-    else return sh.sort.s8;
+// Inclusive scan over the 64 lanes of a wave with DPP moves (no LDS): shifts
+// by 1, 2, 4 and 8 inside each row of 16 lanes (lanes shifted in from
+// outside the row read 0), then the last lane of row 0 added to row 1 and of
+// row 2 to row 3 (row_bcast:15), then the last lane of row 1 added to rows 2
+// and 3 (row_bcast:31).
+__device__ __forceinline__ int32_t wave_scan(int32_t x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15 -> rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31 -> rows 2, 3
+    return x;
 }
 
-// Order-preserving key of an FP32 value (-0 taken as +0).
-__device__ __forceinline__ uint32_t order_key32(float f) {
-    const uint32_t b = (uint32_t)__float_as_int(f + 0.0f);
-    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-}
-
-// Stage points [0, n) (n <= I * threads) of one list and sort them: thread t
-// receives the staging indices of ranks t*I .. t*I+I-1 (ranks past n:
-// padding).
-template <int N, int I>
-__device__ __forceinline__ void sort_tile(const ListEntry* __restrict__ pts, const ImageDesc* dsc, int64_t n, int32_t sign, Dir<N> xi,
-                                          uint32_t (&idx)[I], RowShared& sh) {
-    uint32_t key32[I];
+// Exclusive scans of two sequences held striped over the workgroup: element
+// u * kFinThreads + t of each is x[u], y[u] of thread t (u < rounds, every
+// LDS access of the callers consecutive across lanes).  On return x[u], y[u]
+// hold the sums of the elements before it and tx, ty the totals.  One
+// barrier between the wave scans and the scan of the wave totals.
+template <int R>
+__device__ __forceinline__ void striped_scan2(int32_t (&x)[R], int32_t (&y)[R], int rounds, int32_t& tx, int32_t& ty,
+                                              RowSmall& sm) {
+    static_assert(R * kFinWaves <= kScanSlots, "scan slots");
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 #pragma unroll
-    for (int u = 0; u < I; ++u) {
-        const int j = u * kFinThreads + threadIdx.x;
-        key32[u] = 0xFFFFFFFFu;
-        idx[u] = (uint32_t)j;
-        if (j < n) {
-            const PointT<N> pt = decode_entry<N>(pts[j], *dsc);
-            const double p = project<N>(xi.v, pt.x);
-            sh.key[j] = order_key(p);
-            sh.val[j] = sign * (int32_t)pt.val;
-            key32[u] = order_key32((float)p);
+    for (int u = 0; u < R; ++u) {
+        if (u < rounds) {
+            const int32_t ix = wave_scan(x[u]), iy = wave_scan(y[u]);
+            if (lane == 63) {
+                sm.tot[0][u * kFinWaves + wave] = ix;
+                sm.tot[1][u * kFinWaves + wave] = iy;
+            }
+            x[u] = ix - x[u];
+            y[u] = iy - y[u];
         }
     }
-    BlockSort<I>().sort(key32, idx, sort_storage<I>(sh));
     __syncthreads();
+    // exclusive prefix of the wave totals in (round, wave) order, 64 at a time
+    const int slots = rounds * kFinWaves;
+    int32_t cx = 0, cy = 0;
+    for (int c0 = 0; c0 < slots; c0 += 64) {
+        const int j = c0 + lane;
+        const int32_t vx = j < slots ? sm.tot[0][j] : 0, vy = j < slots ? sm.tot[1][j] : 0;
+        const int32_t sx = wave_scan(vx) - vx + cx, sy = wave_scan(vy) - vy + cy;
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int idx = u * kFinWaves + wave;   // wave-uniform
+            if (u < rounds && idx >= c0 && idx < c0 + 64) {
+                x[u] += __builtin_amdgcn_readlane(sx, idx - c0);
+                y[u] += __builtin_amdgcn_readlane(sy, idx - c0);
+            }
+        }
+        cx = __builtin_amdgcn_readlane(sx + vx, 63);
+        cy = __builtin_amdgcn_readlane(sy + vy, 63);
+    }
+    tx = cx;
+    ty = cy;
+    __syncthreads();   // tot is reused by the next scan
+}
+
+// Sort the keys of a power-of-two range [0, P) of the tile ascending with a
+// bitonic network (each merge of two sorted halves starts with the step that
+// compares mirrored positions, so every comparator puts the smaller key at
+// the lower index).
+template <int C>
+__device__ __forceinline__ void bitonic_sort(TileLds<C>& tl, int P) {
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int lj = __ffs(j) - 1;
+            for (int q = threadIdx.x; q < (P >> 1); q += kFinThreads) {
+                int lo, hi;
+                if (j == (k >> 1)) {
+                    const int base = (q >> lj) * k, off = q & (j - 1);
+                    lo = base + off;
+                    hi = base + k - 1 - off;
+                } else {
+                    lo = ((q >> lj) << (lj + 1)) + (q & (j - 1));
+                    hi = lo + j;
+                }
+                const uint64_t kl = tl.key[lo], kh = tl.key[hi];
+                if (kh < kl) {
+                    const int32_t vl = tl.val[lo];
+                    tl.key[lo] = kh;
+                    tl.key[hi] = kl;
+                    tl.val[lo] = tl.val[hi];
+                    tl.val[hi] = vl;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Where a tile's points come from: a list (entry decoded, canonical FP64
+// projection turned into its key, value times sign) ...
+template <int N>
+struct ListSource {
+    const ListEntry* pts;
+    const ImageDesc* dsc;
+    int32_t sign;
+    Dir<N> xi;
+    __device__ __forceinline__ void get(int64_t j, uint64_t& k, int32_t& v) const {
+        const PointT<N> pt = decode_entry<N>(pts[j], *dsc);
+        k = order_key(project<N>(xi.v, pt.x));
+        v = sign * (int32_t)pt.val;
+    }
+};
+
+// ... or keys and values already in the workspace.
+struct KeySource {
+    const uint64_t* ka;
+    const int32_t* va;
+    __device__ __forceinline__ void get(int64_t j, uint64_t& k, int32_t& v) const {
+        k = ka[j];
+        v = va[j];
+    }
+};
+
+// Bucket of a key among nb buckets over [lo, lo + nb / scale): floor((p -
+// lo) * scale) clamped to [0, nb - 1], p the key's projection.  Subtraction,
+// multiplication by a non-negative factor, the clamps and the truncation are
+// monotone, so p <= q gives bucket(p) <= bucket(q) whatever lo and scale are
+// (-0 comes back from its key as +0, which changes no bucket).
+__device__ __forceinline__ int32_t bucket_of(uint64_t k, double lo, double scale, int nb) {
+    const double x = (key_value(k) - lo) * scale;
+    return x > 0.0 ? (x < (double)(nb - 1) ? (int32_t)x : nb - 1) : 0;
+}
+
+__device__ __forceinline__ double bucket_scale(double lo, double hi, int nb) {
+    const double s = hi > lo ? (double)nb / (hi - lo) : 0.0;
+    return isfinite(s) ? s : 0.0;
+}
+
+// Stage points [first, first + m) (1 <= m <= C) of a source and sort them:
+// on return tl.key[0, m) holds their keys in ascending order (equal keys in
+// some order) and tl.val the matching values.  [lo, hi]: a range that holds
+// the projections up to rounding (it only balances the buckets).
+template <int C, class Src>
+__device__ __forceinline__ void sort_tile(const Src& src, int64_t first, int m, double lo, double hi, TileLds<C>& tl,
+                                          RowSmall& sm) {
+    constexpr int I = C / kFinThreads;
     const int t = threadIdx.x;
-    const int64_t i0 = (int64_t)t * I;
-    int bad = 0;
-    uint64_t prev = 0;
+    // nb buckets (a power of two, at least one per thread, held striped)
+    int nb = kFinThreads;
+    while (nb < m) nb <<= 1;
+    const int rounds_b = nb / kFinThreads;
+    for (int c = 0; c < rounds_b; ++c) tl.start[c * kFinThreads + t] = 0;
+    if (t == 0) tl.start[nb] = m;
+    uint64_t k[I];
+    int32_t v[I];
 #pragma unroll
     for (int u = 0; u < I; ++u) {
-        const uint64_t k = i0 + u < n ? sh.key[idx[u]] : ~0ull;
-        if (u == 0) sh.first[t] = k;
-        else if (k < prev) bad = 1;
-        prev = k;
+        const int j = u * kFinThreads + t;
+        k[u] = ~0ull;
+        v[u] = 0;
+        if (j < m) src.get(first + j, k[u], v[u]);
+    }
+    const double scale = bucket_scale(lo, hi, nb);
+    __syncthreads();   // bins cleared
+    int32_t bs[I];     // bucket | slot in the bucket << 16
+#pragma unroll
+    for (int u = 0; u < I; ++u) {
+        bs[u] = -1;
+        if (u * kFinThreads + t < m) {
+            const int32_t b = bucket_of(k[u], lo, scale, nb);
+            bs[u] = b | (atomicAdd(&tl.start[b], 1) << 16);
+        }
     }
     __syncthreads();
-    if (t + 1 < kFinThreads && sh.first[t + 1] < prev) bad = 1;
-    if (__syncthreads_or(bad)) {
-        // exact order: low halves, then high halves (the sort is stable)
+    int32_t cnt[I], big[I];
 #pragma unroll
-        for (int u = 0; u < I; ++u) key32[u] = i0 + u < n ? (uint32_t)sh.key[idx[u]] : 0xFFFFFFFFu;
-        BlockSort<I>().sort(key32, idx, sort_storage<I>(sh));
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < I; ++u) key32[u] = i0 + u < n ? (uint32_t)(sh.key[idx[u]] >> 32) : 0xFFFFFFFFu;
-        BlockSort<I>().sort(key32, idx, sort_storage<I>(sh));
-        __syncthreads();
+    for (int c = 0; c < I; ++c) {
+        cnt[c] = c < rounds_b ? tl.start[c * kFinThreads + t] : 0;
+        big[c] = cnt[c] > kBucketMax ? 1 : 0;
     }
+    int32_t total, nbig;
+    striped_scan2<I>(cnt, big, rounds_b, total, nbig, sm);
+    if (nbig > 0) {
+        // clustered projections: the bitonic network on the padded tile
+        int P = 1;
+        while (P < m) P <<= 1;
+#pragma unroll
+        for (int u = 0; u < I; ++u) {
+            const int j = u * kFinThreads + t;
+            if (j < P) {
+                tl.key[j] = k[u];   // ~0 (above every finite key) past m
+                tl.val[j] = v[u];
+            }
+        }
+        __syncthreads();
+        bitonic_sort<C>(tl, P);
+        return;
+    }
+#pragma unroll
+    for (int c = 0; c < I; ++c)
+        if (c < rounds_b) tl.start[c * kFinThreads + t] = cnt[c];
+    __syncthreads();
+    // pos: the slot in bucket order, then the place in key order
+    int32_t pos[I];
+#pragma unroll
+    for (int u = 0; u < I; ++u) {
+        pos[u] = -1;
+        if (bs[u] >= 0) {
+            pos[u] = tl.start[bs[u] & 0xFFFF] + (bs[u] >> 16);
+            tl.key[pos[u]] = k[u];
+        }
+    }
+    __syncthreads();
+    // place inside the bucket: members with a smaller key, or an equal key
+    // in an earlier slot.  Each step reads one member of every bucket of the
+    // thread (the last one again once a bucket is exhausted, so the loads
+    // carry no branch and go out together).
+    int32_t span[I], r[I];   // first member | members << 16 (0 when alone)
+    int32_t longest = 0;
+#pragma unroll
+    for (int u = 0; u < I; ++u) {
+        span[u] = 0;
+        r[u] = 0;
+        if (bs[u] >= 0) {
+            const int b = bs[u] & 0xFFFF;
+            const int q0 = tl.start[b], q1 = tl.start[b + 1];
+            span[u] = q0 | (q1 - q0 > 1 ? (q1 - q0) << 16 : 0);
+            longest = max(longest, (q1 - q0 > 1 ? q1 - q0 : 0));
+        }
+    }
+    for (int o = 0; o < longest; ++o) {
+        uint64_t kq[I];
+#pragma unroll
+        for (int u = 0; u < I; ++u) {
+            const int len = span[u] >> 16;
+            kq[u] = tl.key[(span[u] & 0xFFFF) + (o < len ? o : (len > 0 ? len - 1 : 0))];
+        }
+#pragma unroll
+        for (int u = 0; u < I; ++u) {
+            const int q = (span[u] & 0xFFFF) + o;
+            r[u] += (o < (span[u] >> 16) && (kq[u] < k[u] || (kq[u] == k[u] && q < pos[u]))) ? 1 : 0;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < I; ++u)
+        if (bs[u] >= 0) pos[u] = (span[u] & 0xFFFF) + r[u];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < I; ++u) {
+        if (pos[u] >= 0) {
+            tl.key[pos[u]] = k[u];
+            tl.val[pos[u]] = v[u];
+        }
+    }
+    __syncthreads();
 }
 
-// Distinct entries of a sorted tile (staging indices in registers, blocked),
-// as merge_segment does for a sorted list in memory.
-template <int I>
-__device__ __forceinline__ int64_t merge_tile(const uint32_t (&idx)[I], int64_t n, double* out_T, int32_t* out_E,
-                                              RowShared& sh) {
+// Distinct entries of the sorted tile tl[0, m): out_T[j], out_E[j] for the
+// j-th distinct key, with carry plus the running sum of the values up to its
+// last occurrence; carry grows by the tile's sum.  Elements are taken
+// striped (consecutive across lanes), so a wave's stores land on consecutive
+// entries.
+template <int C>
+__device__ __forceinline__ int64_t merge_tile(TileLds<C>& tl, int m, double* out_T, int32_t* out_E, int32_t& carry,
+                                              RowSmall& sm) {
+    constexpr int I = C / kFinThreads;
     const int t = threadIdx.x;
-    const int64_t i0 = (int64_t)t * I;
-    sh.first[t] = i0 < n ? sh.key[idx[0]] : ~0ull;
-    sh.last[t] = i0 + I - 1 < n ? sh.key[idx[I - 1]] : ~0ull;
-    __syncthreads();
-    const uint64_t before = t > 0 ? sh.last[t - 1] : 0;
-    const uint64_t after = t + 1 < kFinThreads ? sh.first[t + 1] : 0;
-    int32_t heads = 0, sum = 0;
-    uint64_t prev = before;
+    const int rounds = (m + kFinThreads - 1) / kFinThreads;
+    uint64_t k[I];
+    int32_t h[I], c[I], v[I];
+    uint32_t tails = 0;
 #pragma unroll
     for (int u = 0; u < I; ++u) {
-        if (i0 + u < n) {
-            const uint64_t k = sh.key[idx[u]];
-            heads += (i0 + u == 0 || k != prev) ? 1 : 0;
-            sum += sh.val[idx[u]];
-            prev = k;
+        const int i = u * kFinThreads + t;
+        k[u] = 0;
+        h[u] = 0;
+        v[u] = 0;
+        if (i < m) {
+            k[u] = tl.key[i];
+            v[u] = tl.val[i];
+            h[u] = (i == 0 || tl.key[i - 1] != k[u]) ? 1 : 0;
+            if (i + 1 == m || tl.key[i + 1] != k[u]) tails |= 1u << u;
         }
+        c[u] = v[u];
     }
-    int32_t h_ex, s_ex, h_tot, s_tot;
-    block_scan2(heads, sum, h_ex, s_ex, h_tot, s_tot, sh.wave);
-    int32_t h = h_ex, c = s_ex;
-    prev = before;
+    uint32_t heads = 0;
+#pragma unroll
+    for (int u = 0; u < I; ++u) heads |= (uint32_t)h[u] << u;
+    int32_t th, tc;
+    striped_scan2<I>(h, c, rounds, th, tc, sm);
 #pragma unroll
     for (int u = 0; u < I; ++u) {
-        const int64_t i = i0 + u;
-        if (i >= n) break;
-        const uint64_t k = sh.key[idx[u]];
-        h += (i == 0 || k != prev) ? 1 : 0;
-        c += sh.val[idx[u]];
-        const uint64_t nk = u + 1 < I ? (i + 1 < n ? sh.key[idx[u + 1]] : ~0ull) : after;
-        if (i + 1 == n || nk != k) {
-            out_T[h - 1] = key_value(k);
-            out_E[h - 1] = c;
+        if (tails & (1u << u)) {
+            const int32_t j = h[u] + (int32_t)((heads >> u) & 1u) - 1;
+            out_T[j] = key_value(k[u]);
+            out_E[j] = carry + c[u] + v[u];
         }
-        prev = k;
     }
-    __syncthreads();   // staging and first/last are reused by the next tile
-    return h_tot;
+    carry += tc;
+    return th;
 }
 
 // Merge sorted runs A [0, la) and B [0, lb) into D (ties: A first); every
@@ -374,90 +566,157 @@ __device__ __forceinline__ void merge_runs(const uint64_t* __restrict__ ka, cons
     }
 }
 
-// Sort one tile of a long list and store it, in order, at ka/va.
-template <int N, int I>
-__device__ __noinline__ void store_tile(const ListEntry* pts, const ImageDesc* dsc, int64_t m, int32_t sign, Dir<N> xi,
-                                        uint64_t* ka, int32_t* va, RowShared& sh) {
-    uint32_t idx[I];
-    sort_tile<N, I>(pts, dsc, m, sign, xi, idx, sh);
+// Distinct entries of one list (n points at pts, values times sign).  A list
+// of at most C points is sorted and merged in LDS.  A longer one is first
+// distributed over C coarse buckets: a histogram pass, a scan, and a pass
+// that places every key and value at its bucket's slots in workspace A (ka,
+// va).  With no coarse bucket above C/2 points, the first bucket reaching
+// each multiple of C/2 points starts a run of whole buckets of fewer than C
+// points (equal keys share a bucket, so no run splits them); the runs are
+// sorted and merged in LDS one after the other.  Otherwise (projections
+// crowded below the range's resolution, or more than kMaxRuns runs) the
+// general path runs: sorted tiles into A, pairwise merges between A and B,
+// then the merge of equal keys from memory.
+template <int N, int C>
+__device__ __forceinline__ int64_t build_segment(const ListEntry* pts, const ImageDesc* dsc, int64_t n, int32_t sign,
+                                                 Dir<N> xi, uint64_t* ka, int32_t* va, uint64_t* kb, int32_t* vb,
+                                                 double* out_T, int32_t* out_E, TileLds<C>& tl, RowSmall& sm) {
+    constexpr int I = C / kFinThreads;
+    constexpr int H = C / 2;
+    const int t = threadIdx.x;
+    if (n <= 0) return 0;
+    const ListSource<N> src{pts, dsc, sign, xi};
+    // projections of the image's vertex box
+    double lo = 0.0, hi = 0.0;
 #pragma unroll
-    for (int u = 0; u < I; ++u) {
-        const int64_t i = (int64_t)threadIdx.x * I + u;
-        if (i < m) {
-            ka[i] = sh.key[idx[u]];
-            va[i] = sh.val[idx[u]];
+    for (int a = 0; a < N; ++a) {
+        const double e0 = xi.v[a] * dsc->lo[a], e1 = xi.v[a] * dsc->hi[a];
+        lo += fmin(e0, e1);
+        hi += fmax(e0, e1);
+    }
+    int32_t carry = 0;
+    if (n <= C) {
+        sort_tile<C>(src, 0, (int)n, lo, hi, tl, sm);
+        return merge_tile<C>(tl, (int)n, out_T, out_E, carry, sm);
+    }
+    if (n / H < kMaxRuns) {
+        // coarse buckets: counts in tl.start, then cursors in tl.val
+        const double scale = bucket_scale(lo, hi, C);
+#pragma unroll
+        for (int c = 0; c < I; ++c) tl.start[c * kFinThreads + t] = 0;
+        if (t == 0) tl.start[C] = (int32_t)n;
+        __syncthreads();
+        for (int64_t j0 = 0; j0 < n; j0 += C) {   // I loads in flight per thread
+            uint64_t k[I];
+            int32_t v[I];
+#pragma unroll
+            for (int u = 0; u < I; ++u)
+                if (j0 + u * kFinThreads + t < n) src.get(j0 + u * kFinThreads + t, k[u], v[u]);
+#pragma unroll
+            for (int u = 0; u < I; ++u)
+                if (j0 + u * kFinThreads + t < n) atomicAdd(&tl.start[bucket_of(k[u], lo, scale, C)], 1);
+        }
+        __syncthreads();
+        int32_t cnt[I], big[I];
+#pragma unroll
+        for (int c = 0; c < I; ++c) {
+            cnt[c] = tl.start[c * kFinThreads + t];
+            big[c] = cnt[c] > H ? 1 : 0;
+        }
+        int32_t total, nbig;
+        striped_scan2<I>(cnt, big, I, total, nbig, sm);
+        if (nbig == 0) {
+#pragma unroll
+            for (int c = 0; c < I; ++c) {
+                tl.start[c * kFinThreads + t] = cnt[c];
+                tl.val[c * kFinThreads + t] = cnt[c];
+            }
+            if (t == 0) {
+                sm.run_b[0] = 0;
+                sm.run_s[0] = 0;
+            }
+            __syncthreads();
+            // run starts: bucket b begins run k = floor(start[b] / H) when it
+            // is the first to reach k * H points (steps of at most H points
+            // cross each multiple once)
+            for (int b = t + 1; b <= C; b += kFinThreads) {
+                const int32_t sb = tl.start[b], sp = tl.start[b - 1];
+                if (sb / H > sp / H) {
+                    sm.run_b[sb / H] = b;
+                    sm.run_s[sb / H] = sb;
+                }
+            }
+            for (int64_t j0 = 0; j0 < n; j0 += C) {
+                uint64_t k[I];
+                int32_t v[I];
+#pragma unroll
+                for (int u = 0; u < I; ++u)
+                    if (j0 + u * kFinThreads + t < n) src.get(j0 + u * kFinThreads + t, k[u], v[u]);
+#pragma unroll
+                for (int u = 0; u < I; ++u) {
+                    if (j0 + u * kFinThreads + t < n) {
+                        const int32_t q = atomicAdd(&tl.val[bucket_of(k[u], lo, scale, C)], 1);
+                        ka[q] = k[u];
+                        va[q] = v[u];
+                    }
+                }
+            }
+            __syncthreads();
+            const int runs = (int)(n / H) + 1;
+            int64_t d = 0;
+            for (int w = 0; w < runs; ++w) {
+                const int32_t b0 = sm.run_b[w], s0 = sm.run_s[w];
+                const int32_t b1 = w + 1 < runs ? sm.run_b[w + 1] : C;
+                const int32_t s1 = w + 1 < runs ? sm.run_s[w + 1] : (int32_t)n;
+                const int m = s1 - s0;
+                if (m > 0) {
+                    sort_tile<C>(KeySource{ka, va}, s0, m, lo + (double)b0 / scale, lo + (double)b1 / scale, tl, sm);
+                    d += merge_tile<C>(tl, m, out_T + d, out_E + d, carry, sm);
+                }
+            }
+            return d;
         }
     }
-    __syncthreads();
-}
-
-// A list longer than one tile: sorted tiles into workspace A, pairwise merges
-// between A and B, then the merge of equal keys from memory.
-template <int N>
-__device__ __noinline__ int64_t build_long(const ListEntry* pts, const ImageDesc* dsc, int64_t n, int32_t sign, Dir<N> xi, uint64_t* ka,
-                                           int32_t* va, uint64_t* kb, int32_t* vb, double* out_T, int32_t* out_E,
-                                           RowShared& sh) {
-    for (int64_t c0 = 0; c0 < n; c0 += kTile) {
-        const int64_t m = n - c0 < kTile ? n - c0 : kTile;
-        if (m <= kFinThreads) store_tile<N, 1>(pts + c0, dsc, m, sign, xi, ka + c0, va + c0, sh);
-        else if (m <= 4 * kFinThreads) store_tile<N, 4>(pts + c0, dsc, m, sign, xi, ka + c0, va + c0, sh);
-        else store_tile<N, kTileItems>(pts + c0, dsc, m, sign, xi, ka + c0, va + c0, sh);
+    // crowded buckets: sorted tiles and pairwise merges
+    for (int64_t c0 = 0; c0 < n; c0 += C) {
+        const int m = (int)(n - c0 < C ? n - c0 : C);
+        sort_tile<C>(src, c0, m, lo, hi, tl, sm);
+        for (int j = t; j < m; j += kFinThreads) {
+            ka[c0 + j] = tl.key[j];
+            va[c0 + j] = tl.val[j];
+        }
+        __syncthreads();
     }
-    for (int64_t width = kTile; width < n; width *= 2) {
-        for (int64_t lo = 0; lo < n; lo += 2 * width) {
-            const int64_t la = n - lo < width ? n - lo : width;
-            const int64_t rest = n - lo - la;
+    for (int64_t width = C; width < n; width *= 2) {
+        for (int64_t lo2 = 0; lo2 < n; lo2 += 2 * width) {
+            const int64_t la = n - lo2 < width ? n - lo2 : width;
+            const int64_t rest = n - lo2 - la;
             const int64_t lb = rest < width ? rest : width;
-            merge_runs(ka + lo, va + lo, la, ka + lo + la, va + lo + la, lb, kb + lo, vb + lo);
+            merge_runs(ka + lo2, va + lo2, la, ka + lo2 + la, va + lo2 + la, lb, kb + lo2, vb + lo2);
         }
         __syncthreads();
         uint64_t* tk = ka; ka = kb; kb = tk;
         int32_t* tv = va; va = vb; vb = tv;
     }
-    return merge_segment(ka, va, 0, n, out_T, out_E, sh.wave);
+    return merge_segment(ka, va, 0, n, out_T, out_E, sm.wave);
 }
 
-// Distinct entries of one list (n points at pts), values times sign.
-template <int N, int I>
-__device__ __noinline__ int64_t build_tile(const ListEntry* pts, const ImageDesc* dsc, int64_t n, int32_t sign, Dir<N> xi,
-                                           double* out_T, int32_t* out_E, RowShared& sh) {
-    uint32_t idx[I];
-    sort_tile<N, I>(pts, dsc, n, sign, xi, idx, sh);
-    return merge_tile<I>(idx, n, out_T, out_E, sh);
-}
-
-template <int N>
-__device__ int64_t build_segment(const ExactArgs& a, const ListEntry* pts, const ImageDesc* dsc, int64_t n, int32_t sign, Dir<N> xi,
-                                 int64_t w0, double* out_T, int32_t* out_E, RowShared& sh) {
-    if (n <= 0) return 0;
-    if (n <= kFinThreads) return build_tile<N, 1>(pts, dsc, n, sign, xi, out_T, out_E, sh);
-    if (n <= 2 * kFinThreads) return build_tile<N, 2>(pts, dsc, n, sign, xi, out_T, out_E, sh);
-    if (n <= 4 * kFinThreads) return build_tile<N, 4>(pts, dsc, n, sign, xi, out_T, out_E, sh);
-    if (n <= 6 * kFinThreads) return build_tile<N, 6>(pts, dsc, n, sign, xi, out_T, out_E, sh);
-    if (n <= kTile) return build_tile<N, kTileItems>(pts, dsc, n, sign, xi, out_T, out_E, sh);
-    return build_long<N>(pts, dsc, n, sign, xi, a.keys_a + w0, a.vals_a + w0, a.keys_b + w0, a.vals_b + w0, out_T, out_E,
-                         sh);
-}
-
-// Row record of row r (thread 0 of the workgroup), with the check of the
-// caller's offsets: a row that needs more room than its offsets give, or
+// Row record of row r (every thread reads the same words), with the check of
+// the caller's offsets: a row that needs more room than its offsets give, or
 // reaches past the capacity, is marked -1.
 template <int N>
-__device__ __forceinline__ void load_row(const ExactArgs& a, int64_t r, bool report, RowShared& sh) {
-    if (threadIdx.x == 0) {
-        ExactRow ri;
-        const int64_t need = row_info<N>(a, r, ri);
-        const int64_t b = a.row_off[r], e = a.row_off[r + 1];
-        ri.base = b;
-        if (!(b >= 0 && e <= a.capacity && e - b >= need)) {
-            ri.valid = -1;
-            if (report) raise_error(a.err, ECT_DEVERR_LAYOUT);
-        } else if (!ri.valid && report) {
-            raise_error(a.err, ECT_DEVERR_NONFINITE);
-        }
-        sh.ri = ri;
+__device__ __forceinline__ ExactRow load_row(const ExactArgs& a, int64_t r, bool report) {
+    ExactRow ri;
+    const int64_t need = row_info<N>(a, r, ri);
+    const int64_t b = a.row_off[r], e = a.row_off[r + 1];
+    ri.base = b;
+    if (!(b >= 0 && e <= a.capacity && e - b >= need)) {
+        ri.valid = -1;
+        if (report && threadIdx.x == 0) raise_error(a.err, ECT_DEVERR_LAYOUT);
+    } else if (!ri.valid && report && threadIdx.x == 0) {
+        raise_error(a.err, ECT_DEVERR_NONFINITE);
     }
-    __syncthreads();
+    return ri;
 }
 
 // Workgroup (r, part): part 0 builds the ECT row from the classical list, or
@@ -466,16 +725,15 @@ __device__ __forceinline__ void load_row(const ExactArgs& a, int64_t r, bool rep
 // sums into the workspace (ct, cum at the row's classical slots), which
 // exact_radon_kernel moves behind (T, E') as Ec = E'[last T < Tc] + own
 // values.  A row marked -1 gets length 0 and raises ECT_DEVERR_LAYOUT.
-// Four waves per SIMD (two workgroups per compute unit) measured faster than
-// the register allocation without the bound, despite a few spilled registers.
-template <int N>
-__global__ void __launch_bounds__(kFinThreads, 4) exact_kernel(ExactArgs a) {
-    __shared__ RowShared sh;
+// C: points per LDS tile (12 B each plus a bucket word).
+template <int N, int C>
+__global__ void __launch_bounds__(kFinThreads, C >= 8192 ? 2 : 4) exact_kernel(ExactArgs a) {
+    __shared__ TileLds<C> tl;
+    __shared__ RowSmall sm;
     const bool radon = a.kind == ECT_EXACT_RADON;
     const int64_t r = radon ? blockIdx.x >> 1 : blockIdx.x;
     const int part = radon ? (int)(blockIdx.x & 1) : 0;
-    load_row<N>(a, r, part == 0, sh);
-    const ExactRow ri = sh.ri;
+    const ExactRow ri = load_row<N>(a, r, part == 0);
     if (ri.valid < 0) {
         if (threadIdx.x == 0 && part == 0) {
             if (radon) {
@@ -491,62 +749,80 @@ __global__ void __launch_bounds__(kFinThreads, 4) exact_kernel(ExactArgs a) {
     Dir<N> xi;
 #pragma unroll
     for (int c = 0; c < N; ++c) xi.v[c] = ri.xi[c];
-    const ListEntry* pts = (const ListEntry*)a.points;
     const ImageDesc* dsc = a.desc + ri.img;
+    // the row's one list: part 0 writes T, E (the first entry -inf, 0) and
+    // the row length; Radon's part 1 writes the classical part into ct, cum
+    int64_t first, n, w0;
+    int32_t sign;
+    double* oT;
+    int32_t* oE;
     if (part == 0) {
         if (threadIdx.x == 0) {
             a.T[base] = -HUGE_VAL;
             a.E[base] = 0;
         }
-        int64_t d = 0;
-        if (ri.valid == 1) {
-            if (radon) d = build_segment<N>(a, pts + ri.po, dsc, ri.no, ri.sign_o, xi, base, a.T + base + 1,
-                                            a.E + base + 1, sh);
-            else d = build_segment<N>(a, pts + ri.pc, dsc, ri.nc, 1, xi, base, a.T + base + 1, a.E + base + 1, sh);
-        }
-        if (threadIdx.x == 0) a.len[radon ? 2 * r : r] = d + 1;
+        first = radon ? ri.po : ri.pc;
+        n = radon ? ri.no : ri.nc;
+        sign = radon ? ri.sign_o : 1;
+        w0 = base;
+        oT = a.T + base + 1;
+        oE = a.E + base + 1;
     } else {
-        const int64_t w0 = base + ri.no + 1;
-        int64_t d = 0;
-        if (ri.valid == 1) d = build_segment<N>(a, pts + ri.pc, dsc, ri.nc, 1, xi, w0, a.ct + w0, a.cum + w0, sh);
-        if (threadIdx.x == 0) a.len[2 * r + 1] = d;
+        first = ri.pc;
+        n = ri.nc;
+        sign = 1;
+        w0 = base + ri.no + 1;
+        oT = a.ct + w0;
+        oE = a.cum + w0;
+    }
+    int64_t d = 0;
+    if (ri.valid == 1)
+        d = build_segment<N, C>((const ListEntry*)a.points + first, dsc, n, sign, xi, a.keys_a + w0, a.vals_a + w0,
+                                a.keys_b + w0, a.vals_b + w0, oT, oE, tl, sm);
+    if (threadIdx.x == 0) {
+        if (part == 0) a.len[radon ? 2 * r : r] = d + 1;
+        else a.len[2 * r + 1] = d;
     }
 }
 
 // Radon rows: the distinct classical projections move right behind (T, E')
 // with Ec[k] = E'[largest i with T[i] < Tc[k]] + the classical values at
-// Tc[k] (difference of consecutive running sums).
+// Tc[k] (difference of consecutive running sums).  The search runs on every
+// st-th entry of T staged in LDS, then inside one stride of T.
 template <int N>
 __global__ void __launch_bounds__(kFixThreads) exact_radon_kernel(ExactArgs a) {
-    __shared__ ExactRow s_ri;
+    __shared__ double s_t[kFixSamples];
     const int64_t r = blockIdx.x;
-    if (threadIdx.x == 0) {
-        ExactRow ri;
-        const int64_t need = row_info<N>(a, r, ri);
-        const int64_t b = a.row_off[r], e = a.row_off[r + 1];
-        ri.base = b;
-        if (!(b >= 0 && e <= a.capacity && e - b >= need)) ri.valid = -1;
-        s_ri = ri;
-    }
-    __syncthreads();
-    const ExactRow ri = s_ri;
-    if (ri.valid != 1) return;
-    const int64_t base = ri.base;
+    ExactRow ri;
+    const int64_t need = row_info<N>(a, r, ri);
+    const int64_t b = a.row_off[r], e = a.row_off[r + 1];
+    if (!(b >= 0 && e <= a.capacity && e - b >= need) || ri.valid != 1) return;
+    const int64_t base = b;
     const int64_t lo_n = a.len[2 * r], nc = a.len[2 * r + 1];
     const int64_t w0 = base + ri.no + 1;
     const double* T = a.T + base;
     const int32_t* Ep = a.E + base;
     const int64_t cb = base + lo_n;
+    int64_t st = 1;
+    while (st * kFixSamples < lo_n) st <<= 1;
+    const int ns = (int)((lo_n + st - 1) / st);
+    for (int i = threadIdx.x; i < ns; i += kFixThreads) s_t[i] = T[(int64_t)i * st];
+    __syncthreads();
     for (int64_t k = threadIdx.x; k < nc; k += kFixThreads) {
         const double tc = a.ct[w0 + k];
         const int32_t own = a.cum[w0 + k] - (k > 0 ? a.cum[w0 + k - 1] : 0);
-        int64_t lo = 0, hi = lo_n - 1;   // last index with T[i] < tc (T[0] = -inf)
+        int lo = 0, hi = ns - 1;   // last sample below tc (T[0] = -inf)
         while (lo < hi) {
-            const int64_t mid = (lo + hi + 1) >> 1;
-            if (T[mid] < tc) lo = mid; else hi = mid - 1;
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_t[mid] < tc) lo = mid; else hi = mid - 1;
+        }
+        int64_t glo = (int64_t)lo * st, ghi = glo + st < lo_n ? glo + st - 1 : lo_n - 1;
+        while (glo < ghi) {        // last index with T[i] < tc inside the stride
+            const int64_t mid = (glo + ghi + 1) >> 1;
+            if (T[mid] < tc) glo = mid; else ghi = mid - 1;
         }
         a.T[cb + k] = tc;
-        a.E[cb + k] = Ep[lo] + own;
+        a.E[cb + k] = Ep[glo] + own;
     }
 }
 
@@ -609,6 +885,16 @@ hipError_t launch_need(const ExactArgs& a, int64_t* need, hipStream_t stream) {
     return hipGetLastError();
 }
 
+template <int N>
+void launch_rows(const ExactArgs& a, int64_t max_len, unsigned grid, hipStream_t stream) {
+    if (max_len <= 2048)
+        hipLaunchKernelGGL((exact_kernel<N, 2048>), dim3(grid), dim3(kFinThreads), 0, stream, a);
+    else if (max_len <= 4096)
+        hipLaunchKernelGGL((exact_kernel<N, 4096>), dim3(grid), dim3(kFinThreads), 0, stream, a);
+    else
+        hipLaunchKernelGGL((exact_kernel<N, 8192>), dim3(grid), dim3(kFinThreads), 0, stream, a);
+}
+
 }  // namespace
 
 size_t exact_layout_scan_bytes(int64_t rows) {
@@ -626,16 +912,13 @@ hipError_t launch_exact_layout(int ndim, const ExactArgs& a, int64_t* need, void
     return scan_call(scan_tmp, bytes, need, a.row_off_out, a.rows, stream);
 }
 
-hipError_t launch_exact(int ndim, const ExactArgs& a, hipStream_t stream) {
+hipError_t launch_exact(int ndim, const ExactArgs& a, int64_t max_len, hipStream_t stream) {
     if (a.rows == 0) return hipSuccess;
     const bool radon = a.kind == ECT_EXACT_RADON;
     const unsigned grid = (unsigned)(radon ? 2 * a.rows : a.rows);
-    if (ndim == 2)
-        hipLaunchKernelGGL((exact_kernel<2>), dim3(grid), dim3(kFinThreads), 0, stream, a);
-    else if (ndim == 3)
-        hipLaunchKernelGGL((exact_kernel<3>), dim3(grid), dim3(kFinThreads), 0, stream, a);
-    else
-        hipLaunchKernelGGL((exact_kernel<4>), dim3(grid), dim3(kFinThreads), 0, stream, a);
+    if (ndim == 2) launch_rows<2>(a, max_len, grid, stream);
+    else if (ndim == 3) launch_rows<3>(a, max_len, grid, stream);
+    else launch_rows<4>(a, max_len, grid, stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !radon) return e;
     if (ndim == 2)

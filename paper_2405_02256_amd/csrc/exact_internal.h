@@ -49,8 +49,10 @@ size_t exact_layout_scan_bytes(int64_t rows);
 // Entries per row, exclusive scan into a.row_off_out ([rows + 1]).
 hipError_t launch_exact_layout(int ndim, const ExactArgs& a, int64_t* need, void* scan_tmp, size_t scan_bytes,
                                hipStream_t stream);
-// One workgroup per row (exact_kernel).
-hipError_t launch_exact(int ndim, const ExactArgs& a, hipStream_t stream);
+// One workgroup per row (exact_kernel); max_len: the longest list a row may
+// read as far as the host knows (it picks the LDS tile; longer lists take the
+// multi-tile path).
+hipError_t launch_exact(int ndim, const ExactArgs& a, int64_t max_len, hipStream_t stream);
 hipError_t launch_exact_eval(int32_t kind, int64_t rows, const int64_t* row_off, const double* T, const int32_t* E,
                              const int64_t* len, int64_t capacity, const double* thr, int32_t M, int32_t per_row,
                              int32_t* out, hipStream_t stream);

@@ -194,16 +194,24 @@ def test_exact_near_ties_in_fp32_and_long_lists(api):
     sorted tiles merged in the workspace, an odd number of runs included)."""
     rng = np.random.default_rng(905)
     img = W.random_image(rng, (200, 200), 8)
-    dirs = np.array([[1.0, 1e-13], [1e-13, -1.0], [0.5, 0.5 + 1e-12], [-0.7, 0.3], [1.0, 0.0]])
+    dirs = np.array([[1.0, 1e-13], [1e-13, -1.0], [0.5, 0.5 + 1e-12], [-0.7, 0.3], [1.0, 0.0], [0.0, 0.0]])
     plan = api.Plan(T(img))
     for kind in ("ect", "radon"):
         rep = plan.exact(T(dirs), kind)
         check_rows(rep, [img] * len(dirs), dirs)
     small = W.random_image(rng, (40, 37), 5)
     plan2 = api.Plan(T(small))
-    d2 = np.array([[1.0, 3e-14], [2e-15, 1.0], [-1.0, -1e-12]])
+    d2 = np.array([[1.0, 3e-14], [2e-15, 1.0], [-1.0, -1e-12], [0.0, 0.0]])
     for kind in ("ect", "radon"):
         check_rows(plan2.exact(T(d2), kind), [small] * len(d2), d2)
+    # one LDS tile whose projections crowd into few buckets (a narrow image
+    # seen almost along its long axis: about 21 distinct coordinates), next to
+    # directions whose buckets hold a few points each
+    narrow = W.random_image(rng, (300, 20), 3)
+    plan3 = api.Plan(T(narrow))
+    d3 = np.array([[1e-13, 1.0], [-1e-13, -1.0], [1.0, 1e-13], [0.3, -0.8], [0.0, 0.0]])
+    for kind in ("ect", "radon"):
+        check_rows(plan3.exact(T(d3), kind), [narrow] * len(d3), d3)
 
 
 def test_exact_representation_is_strictly_increasing_grf512(api):
