@@ -891,8 +891,10 @@ void launch_rows(const ExactArgs& a, int64_t max_len, unsigned grid, hipStream_t
         hipLaunchKernelGGL((exact_kernel<N, 2048>), dim3(grid), dim3(kFinThreads), 0, stream, a);
     else if (max_len <= 4096)
         hipLaunchKernelGGL((exact_kernel<N, 4096>), dim3(grid), dim3(kFinThreads), 0, stream, a);
-    else
+    else if (max_len <= 8192)
         hipLaunchKernelGGL((exact_kernel<N, 8192>), dim3(grid), dim3(kFinThreads), 0, stream, a);
+    else   // runs of coarse buckets: two 4096-point workgroups per compute unit beat one of 8192
+        hipLaunchKernelGGL((exact_kernel<N, 4096>), dim3(grid), dim3(kFinThreads), 0, stream, a);
 }
 
 }  // namespace

@@ -69,33 +69,40 @@ def test_learnable_scale_step_in_a_graph(mods):
     wts = {k: T(rng.standard_normal((len(imgs) * len(xi0), 2) if k == "fourier" else (len(imgs) * len(xi0),)))
            for k in ("fourier", "laplace")}
 
-    def step():
+    def step(xv, sv):
         loss = 0.0
         ys = []
         for k in ("fourier", "laplace"):
-            y = A.HybridTransform.apply(xi, s, plan, k, "fp32")
+            y = A.HybridTransform.apply(xv, sv, plan, k, "fp32")
             ys.append(y)
             loss = loss + (y * wts[k]).sum()
-        gx, gs = torch.autograd.grad(loss, (xi, s))
+        gx, gs = torch.autograd.grad(loss, (xv, sv))
         return ys + [gx, gs]
+
+    # every stream gets leaves of its own (views of the same storage), so no
+    # autograd accumulator crosses streams
+    def leaves():
+        return xi.detach().requires_grad_(True), s.detach().requires_grad_(True)
 
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
+        xw, sw = leaves()
         for _ in range(2):
-            step()
+            step(xw, sw)
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        captured = step()
+        captured = step(xi, s)
     torch.cuda.synchronize()
+    xe, se = leaves()
     for sval in (0.8, 1.25, 0.6, 0.8):
         with torch.no_grad():
             s.fill_(sval)
         g.replay()
         torch.cuda.synchronize()
-        eager = step()
+        eager = step(xe, se)
         torch.cuda.synchronize()
         for a, b in zip(captured, eager):
             assert np.array_equal(_bits(a), _bits(b)), sval
