@@ -82,6 +82,21 @@ def test_batch_ect_2d_ragged(mods):
     assert flags & N.DEVERR_NONFINITE and flags & N.DEVERR_THRESHOLDS
 
 
+def test_batch_ect_short_and_long_lists(mods):
+    """Lists from a few points to a few thousand (one partial stage of the
+    streamed list, or several), passes of 16 and of 1 to 3 directions."""
+    A, N = mods
+    rng = np.random.default_rng(2504)
+    sides = rng.choice([9, 14, 30, 60, 120, 200], size=144)   # enough images for the batch kernel
+    imgs = [W.binary_field(rng, (int(s), int(s) + 5), 2.5) for s in sides]
+    dirs = rng.standard_normal((70, 2))                  # ~17 directions per sign vector
+    dirs[0] = [1.0, 0.0]
+    M = 64
+    thr = np.stack([W.even_thresholds(float(s), M) for s in sides])
+    _check(A, N, imgs, dirs, thr)
+    _check(A, N, imgs, dirs[:9], thr)                     # one to three directions per sign vector
+
+
 def test_batch_ect_shared_thresholds_one_direction_per_bucket_and_max_m(mods):
     A, N = mods
     rng = np.random.default_rng(2502)
