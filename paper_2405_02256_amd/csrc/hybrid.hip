@@ -134,7 +134,9 @@ __device__ __forceinline__ double exp2_split(double a) {
     const double n = floor(a);
     const float f = (float)(a - n);
     const double e = (double)__builtin_amdgcn_exp2f(f);
-    return ldexp(e, (int)fmax(n, -2000.0));
+    // v_cvt_i32_f64 saturates (NaN gives 0), and ldexp of INT_MIN underflows
+    // to 0, so exponents below the int range need no clamp
+    return ldexp(e, (int)n);
 }
 
 // Per-thread query state.
