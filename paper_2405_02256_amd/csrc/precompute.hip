@@ -902,73 +902,82 @@ tile_count_2p_kernel(const T* __restrict__ pixels, const ImageDesc* __restrict__
 }
 
 // Three-pass plans with packed entries: place tile t's entries (list l's
-// count from the count pass, in vertex order) at the list's prefix.  One wave
-// per tile: lanes l < NL read list l's count and prefix, a wave scan turns
-// the counts into the start of each list in the tile's flat range of entries,
-// and the starts and prefixes are broadcast into scalar registers; the range
-// is then placed one entry per lane, with the vertex coordinates decoded from
-// the index.
+// count from the count pass, in vertex order) at the list's prefix.  A wave
+// takes kCopyTiles consecutive tiles: their counts and list prefixes come in
+// with scalar loads, then the slots of every list's first 64 entries of all
+// its tiles go out as one batch of loads (lane i: entry i), so the tiles'
+// memory round trips overlap; each entry is stored with its vertex
+// coordinates decoded from the index.  Entries past the 64th of a list in a
+// tile (rare) follow in a loop.
+constexpr int kCopyTiles = 2;
+
+template <int N>
+__device__ __forceinline__ ListEntry copy_entry(const ImageDesc& d, int64_t vbase, double inv0, double inv1,
+                                                double inv2, uint32_t w) {
+    const uint32_t v = (uint32_t)(vbase + (w & kPackLocalMask));
+    uint32_t r0, r1 = 0, r2 = 0;
+    const uint32_t q0 = udiv(v, (uint32_t)d.V[0], inv0, &r0);
+    const uint32_t q1 = N >= 3 ? udiv(q0, (uint32_t)d.V[1], inv1, &r1) : 0u;
+    const uint32_t q2 = N >= 4 ? udiv(q1, (uint32_t)d.V[2], inv2, &r2) : 0u;
+    int k[kMaxDim] = {(int)r0, 0, 0, 0};
+    if constexpr (N == 2) {
+        k[1] = (int)q0;
+    } else if constexpr (N == 3) {
+        k[1] = (int)r1;
+        k[2] = (int)q1;
+    } else {
+        k[1] = (int)r1;
+        k[2] = (int)r2;
+        k[3] = (int)q2;
+    }
+    return ListEntry{entry_code(d, k, N), (int32_t)w >> kPackShift};
+}
+
 template <int N>
 __global__ void __launch_bounds__(kPrecomputeThreads)
 tile_copy_kernel(const ImageDesc* __restrict__ descs, const int32_t* __restrict__ tile_img, int64_t num_tiles,
                  const int32_t* __restrict__ counts, const int64_t* __restrict__ prefix,
                  const uint32_t* __restrict__ packed, ListEntry* __restrict__ points, int64_t capacity) {
     constexpr int NL = TileValues<N>::NL;
+    constexpr int TV = tile_verts(N);
     const int lane = threadIdx.x & 63;
-    const int64_t tile =
-        (int64_t)blockIdx.x * (kPrecomputeThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (tile >= num_tiles) return;
-    const int32_t c = lane < NL ? counts[tile * NL + lane] : 0;
-    const int64_t b = lane < NL ? prefix[tile * NL + lane] : 0;
-    int32_t inc = c;
+    const int64_t t0 =
+        ((int64_t)blockIdx.x * (kPrecomputeThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) *
+        kCopyTiles;
+    if (t0 >= num_tiles) return;
+    int32_t cnt[kCopyTiles][NL];
+    int64_t pre[kCopyTiles][NL];
 #pragma unroll
-    for (int off = 1; off < NL; off <<= 1) {
-        const int32_t t = __shfl_up(inc, off, 64);
-        if (lane >= off) inc += t;
-    }
-    int32_t start[NL];
-    int64_t base[NL];
+    for (int j = 0; j < kCopyTiles; ++j) {
+        const bool ok = t0 + j < num_tiles;
 #pragma unroll
-    for (int l = 0; l < NL; ++l) {
-        start[l] = __builtin_amdgcn_readlane(inc - c, l);
-        base[l] = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int32_t)(b >> 32), l) << 32) |
-                            (uint32_t)__builtin_amdgcn_readlane((int32_t)b, l));
-    }
-    const int total = __builtin_amdgcn_readlane(inc, NL - 1);
-    const ImageDesc& d = descs[tile_img[tile]];
-    const int64_t vbase = (tile - d.tile_start) * tile_verts(N);
-    const double inv0 = 1.0 / (double)d.V[0], inv1 = 1.0 / (double)d.V[1], inv2 = 1.0 / (double)d.V[2];
-    const uint32_t* __restrict__ slots = packed + tile * NL * (int64_t)tile_verts(N);
-    for (int i = lane; i < total; i += 64) {
-        int l = 0;
-        int32_t st = start[0];
-        int64_t bl = base[0];
-#pragma unroll
-        for (int m = 1; m < NL; ++m)
-            if (i >= start[m]) {
-                l = m;
-                st = start[m];
-                bl = base[m];
-            }
-        const int pos = i - st;
-        const uint32_t w = slots[l * tile_verts(N) + pos];
-        const uint32_t v = (uint32_t)(vbase + (w & kPackLocalMask));
-        uint32_t r0, r1 = 0, r2 = 0;
-        const uint32_t q0 = udiv(v, (uint32_t)d.V[0], inv0, &r0);
-        const uint32_t q1 = N >= 3 ? udiv(q0, (uint32_t)d.V[1], inv1, &r1) : 0u;
-        const uint32_t q2 = N >= 4 ? udiv(q1, (uint32_t)d.V[2], inv2, &r2) : 0u;
-        int k[kMaxDim] = {(int)r0, 0, 0, 0};
-        if constexpr (N == 2) {
-            k[1] = (int)q0;
-        } else if constexpr (N == 3) {
-            k[1] = (int)r1;
-            k[2] = (int)q1;
-        } else {
-            k[1] = (int)r1;
-            k[2] = (int)r2;
-            k[3] = (int)q2;
+        for (int l = 0; l < NL; ++l) {
+            cnt[j][l] = ok ? counts[(t0 + j) * NL + l] : 0;
+            pre[j][l] = ok ? prefix[(t0 + j) * NL + l] : 0;
         }
-        points[(int64_t)l * capacity + bl + pos] = ListEntry{entry_code(d, k, N), (int32_t)w >> kPackShift};
+    }
+    uint32_t w[kCopyTiles][NL];
+#pragma unroll
+    for (int j = 0; j < kCopyTiles; ++j) {
+        const uint32_t* __restrict__ slots = packed + (t0 + j) * NL * (int64_t)TV;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) w[j][l] = lane < cnt[j][l] ? slots[l * TV + lane] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kCopyTiles; ++j) {
+        const int64_t tile = t0 + j;
+        if (tile >= num_tiles) break;
+        const ImageDesc& d = descs[tile_img[tile]];
+        const int64_t vbase = (tile - d.tile_start) * TV;
+        const double inv0 = 1.0 / (double)d.V[0], inv1 = 1.0 / (double)d.V[1], inv2 = 1.0 / (double)d.V[2];
+        const uint32_t* __restrict__ slots = packed + tile * NL * (int64_t)TV;
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            ListEntry* __restrict__ out = points + (int64_t)l * capacity + pre[j][l];
+            if (lane < cnt[j][l]) out[lane] = copy_entry<N>(d, vbase, inv0, inv1, inv2, w[j][l]);
+            for (int pos = 64 + lane; pos < cnt[j][l]; pos += 64)
+                out[pos] = copy_entry<N>(d, vbase, inv0, inv1, inv2, slots[l * TV + pos]);
+        }
     }
 }
 
@@ -1190,7 +1199,8 @@ hipError_t launch_typed(const Plan& p, bool first, hipStream_t stream, const Que
         if (e != hipSuccess) return e;
         if (packed)
             hipLaunchKernelGGL((tile_copy_kernel<N>),
-                               dim3((unsigned)((L.num_tiles + kPrecomputeThreads / 64 - 1) / (kPrecomputeThreads / 64))),
+                               dim3((unsigned)((L.num_tiles + kCopyTiles * (kPrecomputeThreads / 64) - 1) /
+                                               (kCopyTiles * (kPrecomputeThreads / 64)))),
                                dim3(kPrecomputeThreads), 0, stream, desc, ti, L.num_tiles, counts, prefix, packed, pts,
                                L.capacity);
         else
