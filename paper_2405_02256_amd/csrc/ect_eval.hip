@@ -279,12 +279,15 @@ __global__ void __launch_bounds__(kBatchThreads) ect_batch_kernel(EctArgs a) {
                     run += h[j];
                     h[j] = run;
                 }
-            int32_t off = run;   // inclusive scan of the segment totals within the row's kSeg lanes
-#pragma unroll
-            for (int o = 1; o < kSeg; o <<= 1) {
-                const int32_t v = __shfl_up(off, o, kSeg);
-                if (part >= o) off += v;
-            }
+            // inclusive scan of the segment totals within the row's kSeg = 16
+            // lanes: DPP row shifts (a DPP row is 16 lanes; lanes shifted in
+            // from outside the row read 0)
+            static_assert(kSeg == 16, "one DPP row per histogram row");
+            int32_t off = run;
+            off += __builtin_amdgcn_update_dpp(0, off, 0x111, 0xf, 0xf, false);   // row_shr:1
+            off += __builtin_amdgcn_update_dpp(0, off, 0x112, 0xf, 0xf, false);   // row_shr:2
+            off += __builtin_amdgcn_update_dpp(0, off, 0x114, 0xf, 0xf, false);   // row_shr:4
+            off += __builtin_amdgcn_update_dpp(0, off, 0x118, 0xf, 0xf, false);   // row_shr:8
             off -= run;
             if (dd < nd && off != 0)
                 for (int j = j0; j < j1; ++j) h[j] += off;
