@@ -63,6 +63,8 @@ def parse():
                          "the four-axis row follows --no-4d")
     ap.add_argument("--no-4d", action="store_true", help="skip the four-axis workload")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default schedule knobs")
+    ap.add_argument("--serial-ect", action="store_true",
+                    help="batch step: run the ECT before the Laplace pass on one stream (no side stream)")
     ap.add_argument("--traffic-json", nargs=5,
                     metavar=("WORKLOAD", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write profiles/traffic_<WORKLOAD>.json from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE "
@@ -407,7 +409,10 @@ def bench_batch(args, dev, tuning_out):
     xi = torch.from_numpy(w.hybrid_xi).to(dev)
     nq = len(w.hybrid_xi) // len(imgs)
     offs = torch.arange(len(imgs) + 1, dtype=torch.int64, device=dev) * nq
-    step = pipeline.Step(plan, dirs, thr, xi, kernels=("laplace",), s=1.0, precision="fp32", hybrid_offsets=offs)
+    # the ECT runs on a side stream beside the Laplace pass (its latency-bound
+    # workgroups fill the compute units the ALU-bound pass leaves idle)
+    step = pipeline.Step(plan, dirs, thr, xi, kernels=("laplace",), s=1.0, precision="fp32", hybrid_offsets=offs,
+                         concurrent=not args.serial_ect)
     if not args.no_autotune:
         log("batch_4096: autotuning")
         t = step.autotune()
@@ -427,7 +432,9 @@ def bench_batch(args, dev, tuning_out):
     pairs = float(np.take_along_axis(o, pair_index(sign_index(ex), 2), axis=1).sum())
     ect_pairs = float(c[:, sign_index(w.ect_dirs)].sum())
     stage_ms = stage_kernel_ms(step.run, args.steps)
-    combined = "ect" not in stage_ms
+    # one launch holding both (combined), or the ECT on its side stream inside
+    # the Laplace launch's window (concurrent): the window's work is both
+    combined = "ect" not in stage_ms or (step.concurrent and stage_ms["ect"] <= stage_ms["hybrid"])
     nbytes = precompute_bytes(2, sum(im.size for im in w.images), c.sum() + o.sum(), len(imgs), 6)
     models = {"precompute": lambda s: roofline.hbm_roofline(nbytes, s),
               "ect": lambda s: roofline.alu_roofline("ect", 2, ect_pairs, s),
@@ -436,6 +443,10 @@ def bench_batch(args, dev, tuning_out):
               else (lambda s: roofline.alu_roofline("laplace", 2, pairs, s))}
     dom, roof = dominant(stage_ms, models)
     roof["traffic"] = traffic_for("batch_4096", dom)
+    if combined and dom == "hybrid" and "ect" in stage_ms:
+        roof["window"] = "Laplace launch, batched ECT on a side stream inside it; work of both"
+        te = traffic_for("batch_4096", "ect")
+        roof["traffic"] = roof["traffic"] + te if roof["traffic"] is not None and te is not None else None
     rows_all = {k: models[k](stage_ms[k] * 1e-3) for k in models if k in stage_ms}
     log(f"batch_4096: {sec * 1e3:.4f} ms/step, stages {stage_ms}")
 
@@ -973,6 +984,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": b["workload"], "graph": not args.no_graph,
+                   "ect_stream": "serial" if args.serial_ect else "side stream beside the Laplace pass",
                    "precision": "FP32 kernel values, FP64 phases and accumulation", "tuning": tuning},
         "ect_dirs_per_s": b["ect_dirs_per_s"],
         "batched_vs_per_image": b["batched_vs_per_image"],
