@@ -164,6 +164,45 @@ def test_concurrent_ect_branch_matches_serial_step(api, small):
     assert torch.equal(outs[0][2], outs[1][2])
 
 
+def test_concurrent_batched_ect_beside_ragged_laplace(api):
+    """The step of many images (per-image thresholds, so the batched ECT
+    kernel, and a ragged Laplace set) with the ECT on its own stream and
+    graph branch equals the serial step bitwise, over graph replays."""
+    from paper_2405_02256_amd.pipeline import Step
+    rng = np.random.default_rng(12)
+    sides = rng.choice([12, 24, 40], size=160)
+    imgs = [W.binary_field(rng, (int(s), int(s)), 2.0) for s in sides]
+    dirs = W.circle_dirs(24) + 1e-3
+    thr = np.stack([W.even_thresholds(float(s), 32) for s in sides])
+    nq = 40
+    xi = np.concatenate([W.polar_vectors(rng, nq, 0.01, 1.0) for _ in imgs])
+    offs = T(np.arange(len(imgs) + 1, dtype=np.int64) * nq)
+    outs = []
+    for concurrent in (False, True):
+        plan = api.Plan([T(im) for im in imgs])
+        st = Step(plan, T(dirs), T(thr), T(xi), ("laplace",), precision="fp32", hybrid_offsets=offs,
+                  concurrent=concurrent)
+        assert st.concurrent == concurrent
+        st.run()
+        torch.cuda.synchronize()
+        eager = (st.ect_out.clone(), st.hy_out["laplace"].clone())
+        st.capture()
+        for _ in range(3):
+            st.ect_out.fill_(-7)
+            st.hy_out["laplace"].fill_(0.5)
+            st.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(st.ect_out, eager[0])
+            assert torch.equal(st.hy_out["laplace"], eager[1])
+        assert plan.check() == 0
+        outs.append(eager)
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+    for i in (0, 77, 159):
+        assert np.array_equal(outs[1][0].cpu().numpy().reshape(len(imgs), len(dirs), -1)[i],
+                              O.ect(imgs[i], dirs, thr[i])), i
+
+
 def test_backward_reuses_forward_buckets(api, small):
     """The backward call with the reuse flag gives the same gradients as a
     backward call that buckets again, and is refused when the last
