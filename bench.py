@@ -493,7 +493,9 @@ def bench_batch(args, dev, tuning_out):
            "ms_per_step": sec * 1e3, "hybrid_pairs": pairs, "ect_pairs": ect_pairs,
            "hybrid_evals_per_s": pairs / sec, "ect_dirs_per_s": len(imgs) * len(w.ect_dirs) / sec,
            "stage_kernel_ms": stage_ms,
-           "stage_note": ("the ECT workgroups run inside the hybrid launch" if combined else None),
+           "stage_note": ("the ECT runs on a side stream while the hybrid (Laplace) launch runs; the two stage "
+                          "times overlap" if step.concurrent else
+                          "the ECT workgroups run inside the hybrid launch" if combined else None),
            "rooflines": rows_all, "precompute_vertices": float(sum((im.shape[0] + 1) * (im.shape[1] + 1)
                                                                    for im in w.images)),
            "precompute_list_entries": float(c.sum() + o.sum()), "batched_vs_per_image": fp64}
